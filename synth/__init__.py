@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/bench and the CPU oracle.
+
+This module only draws inputs: Gaussian clouds, pinhole cameras and gaze points.
+It holds none of the renderer's arithmetic (no projection, no colour, no blending),
+so that the oracle and the GPU path can both take their inputs from it without
+sharing any of the method.
+
+The paper renders trained 3DGS scenes (Tanks & Temples, Deep Blending; Sec. 4.1).
+Those are not available, so seeded uniform Gaussian clouds of the same parameter
+layout stand in (Sec. 2.3 describes the representation: position, anisotropic
+scale, rotation, opacity and spherical-harmonic colour per point).
+
+Layout (structure of arrays, float32, as the GPU loads it):
+  mean[3][N], scale[3][N] (already exp(log_scale)), quat[4][N] as (w, x, y, z),
+  opacity[N] (already sigmoid(logit)), sh[16][3][N] (coefficient, channel, point).
+The raw draws (log_scale, logit) are kept too, for the differentiable render.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SH_COEFFS = 16  # degree 3
+
+
+@dataclass
+class Scene:
+    n: int
+    mean: np.ndarray       # f32 [3][N]
+    log_scale: np.ndarray  # f32 [3][N]
+    scale: np.ndarray      # f32 [3][N]
+    quat: np.ndarray       # f32 [4][N] (w, x, y, z), unit norm up to f32 rounding
+    logit: np.ndarray      # f32 [N]
+    opacity: np.ndarray    # f32 [N]
+    sh: np.ndarray         # f32 [16][3][N]
+
+    def subset(self, idx) -> "Scene":
+        idx = np.asarray(idx)
+        return Scene(
+            n=int(idx.size),
+            mean=np.ascontiguousarray(self.mean[:, idx]),
+            log_scale=np.ascontiguousarray(self.log_scale[:, idx]),
+            scale=np.ascontiguousarray(self.scale[:, idx]),
+            quat=np.ascontiguousarray(self.quat[:, idx]),
+            logit=np.ascontiguousarray(self.logit[idx]),
+            opacity=np.ascontiguousarray(self.opacity[idx]),
+            sh=np.ascontiguousarray(self.sh[:, :, idx]),
+        )
+
+
+def make_scene(n: int, half_extent: float, seed: int,
+               log_scale_mean: float = -3.0, log_scale_std: float = 0.5,
+               sh_std: float = 0.3) -> Scene:
+    """Uniform cloud: mean ~ U[-h,h]^3, log-scale ~ N(-3,0.5) per axis, quaternion
+    uniform on S^3 (normal draw then normalised), logit ~ N(0,1), 48 SH
+    coefficients ~ N(0,0.3). Draw order: means, log-scales, quaternions, logits, SH.
+    Values are drawn in float64 and rounded once to float32; the activated
+    scale/opacity are the float64 exp/sigmoid of the drawn values, rounded once."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mean = rng.uniform(-half_extent, half_extent, size=(3, n))
+    log_s = rng.normal(log_scale_mean, log_scale_std, size=(3, n))
+    q = rng.normal(0.0, 1.0, size=(4, n))
+    q = q / np.sqrt((q * q).sum(axis=0, keepdims=True))
+    logit = rng.normal(0.0, 1.0, size=n)
+    sh = rng.normal(0.0, sh_std, size=(SH_COEFFS, 3, n))
+    log_s32 = log_s.astype(np.float32)
+    logit32 = logit.astype(np.float32)
+    return Scene(
+        n=n,
+        mean=mean.astype(np.float32),
+        log_scale=log_s32,
+        scale=np.exp(log_s32.astype(np.float64)).astype(np.float32),
+        quat=q.astype(np.float32),
+        logit=logit32,
+        opacity=(1.0 / (1.0 + np.exp(-logit32.astype(np.float64)))).astype(np.float32),
+        sh=sh.astype(np.float32),
+    )
+
+
+@dataclass
+class Camera:
+    """Pinhole camera, OpenCV axes (x right, y down, z forward).
+    World->camera: p = R @ x + t. Pixel (i, j) is sampled at (i + 0.5, j + 0.5)."""
+    R: np.ndarray          # f64 [3][3]
+    t: np.ndarray          # f64 [3]
+    campos: np.ndarray     # f64 [3], camera centre in world space
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    bg: tuple = (0.0, 0.0, 0.0)
+
+
+def rot_yaw_pitch(yaw_deg: float, pitch_deg: float) -> np.ndarray:
+    """Camera-to-world rotation for a head turned by yaw (about +y) then pitch
+    (about +x): R_c2w = R_y(yaw) @ R_x(pitch)."""
+    a, b = math.radians(yaw_deg), math.radians(pitch_deg)
+    ry = np.array([[math.cos(a), 0.0, math.sin(a)], [0.0, 1.0, 0.0], [-math.sin(a), 0.0, math.cos(a)]])
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, math.cos(b), -math.sin(b)], [0.0, math.sin(b), math.cos(b)]])
+    return ry @ rx
+
+
+def make_camera(width: int, height: int, fov_x_deg: float, position, c2w=None,
+                bg=(0.0, 0.0, 0.0)) -> Camera:
+    """Square-pixel pinhole camera with the horizontal field of view on the width;
+    principal point at the image centre."""
+    c2w = np.eye(3) if c2w is None else np.asarray(c2w, dtype=np.float64)
+    pos = np.asarray(position, dtype=np.float64)
+    R = c2w.T.copy()
+    t = -(R @ pos)
+    f = (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)
+    return Camera(R=R, t=t, campos=pos.copy(), fx=f, fy=f, cx=width / 2.0, cy=height / 2.0,
+                  width=width, height=height, bg=tuple(float(x) for x in bg))
+
+
+def stereo_cameras(head, width, height, fov_x_deg, c2w=None, ipd=0.064):
+    """Two parallel-axis eye cameras at head -/+ ipd/2 along the camera's right axis."""
+    c2w = np.eye(3) if c2w is None else np.asarray(c2w, dtype=np.float64)
+    right = c2w[:, 0]
+    head = np.asarray(head, dtype=np.float64)
+    return [make_camera(width, height, fov_x_deg, head + s * 0.5 * ipd * right, c2w) for s in (-1.0, 1.0)]
+
+
+def gaze_points(seed: int, n: int, cam: Camera, ecc_max_deg: float = 20.0):
+    """n seeded gaze points (pixel coordinates) uniform in eccentricity disc of
+    ecc_max_deg around the optical axis; the first is the image centre."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = [(cam.cx, cam.cy)]
+    while len(pts) < n:
+        ecc = math.radians(ecc_max_deg) * math.sqrt(rng.uniform())
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        tx, ty = math.tan(ecc) * math.cos(ang), math.tan(ecc) * math.sin(ang)
+        pts.append((cam.cx + cam.fx * tx, cam.cy + cam.fy * ty))
+    return pts
+
+
+# ---------------------------------------------------------------------------
+# The workloads, with the sizes of the rendering configurations.
+# ---------------------------------------------------------------------------
+
+def single_view(n=10_000, size=256, seed=1):
+    """Single view, no foveation: n Gaussians in [-1,1]^3, camera at z=-3 looking
+    +z, 60 degree horizontal FOV, size x size, black background."""
+    scene = make_scene(n, 1.0, seed)
+    cam = make_camera(size, size, 60.0, (0.0, 0.0, -3.0))
+    return scene, cam
+
+
+def foveated_stereo(n=1_000_000, width=1832, height=1920, seed=2, half_extent=5.0):
+    """Foveated stereo frame: n Gaussians over [-h,h]^3, head at (0,0,-3) looking
+    +z, eyes 64 mm apart, width x height per eye. Returns scene and two cameras."""
+    scene = make_scene(n, half_extent, seed)
+    cams = stereo_cameras((0.0, 0.0, -3.0), width, height, 60.0)
+    return scene, cams
+
+
+FOVEA_FRACTIONS = (0.15, 0.35)   # fovea and mid radii as fractions of the image width
+PERIPH_KEEP = (3, 10)            # periphery keeps ceil(3/10 of the visible points)
