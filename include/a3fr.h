@@ -1,0 +1,252 @@
+/*
+ * a3fr.h -- C ABI of the MI355X (gfx950) foveated 3D Gaussian Splatting library.
+ *
+ * The library renders a 3D Gaussian Splatting scene the way the paper's
+ * renderer does it (Sec. 2.3: project every 3D Gaussian to a screen ellipse and
+ * find the tiles it touches; sort each tile's ellipses by depth, near to far;
+ * composite each pixel front to back), for several layers of several eyes at
+ * once, reusing the projection of one pass over the scene for every layer
+ * (Sec. 3.5: the projected Gaussians, per-tile subsets and depth-sorted lists
+ * of the first round are buffered and reused by later rounds).  A foveated
+ * frame has a full-resolution foveal layer around the gaze point and coarser
+ * surrounding layers (Sec. 2.2 and Eq. 1, the foveal radius).
+ *
+ * Conventions (every entry point):
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors), owned by the caller, which must keep them alive until the work
+ *    enqueued on the context's stream has finished.  Host pointers are read
+ *    before the call returns.
+ *  - All work is enqueued on the context's HIP stream and is asynchronous,
+ *    except where a call is documented to synchronise.
+ *  - Errors: arguments are checked on the host before anything is enqueued
+ *    and give A3FR_EINVAL (nothing enqueued); a failed device allocation gives
+ *    A3FR_ENOMEM; a HIP runtime error gives A3FR_EDEVICE.  No C++ exception
+ *    crosses this interface.  a3fr_last_error() returns a message for the
+ *    last failure on the context.
+ *  - Images are planar float32, [channel][row][column], row = y (down),
+ *    column = x (right); pixel (x, y) is sampled at its centre (x+0.5, y+0.5).
+ *  - The tile grid is 16 x 16 pixels; a view of W x H pixels has
+ *    ceil(W/16) x ceil(H/16) tiles, row-major.
+ */
+#ifndef A3FR_H
+#define A3FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    A3FR_OK = 0,
+    A3FR_EINVAL = 1,     /* bad argument; nothing was enqueued */
+    A3FR_ENOMEM = 2,     /* device allocation failed */
+    A3FR_ECAPACITY = 3,  /* a size limit of the library was exceeded (see each call) */
+    A3FR_EDEVICE = 4,    /* HIP runtime error */
+    A3FR_ENOTREADY = 5   /* call order violated (e.g. blend before bin_sort) */
+} a3fr_status;
+
+#define A3FR_TILE 16
+#define A3FR_MASK_ALL 0      /* every tile of the view is rendered */
+#define A3FR_MASK_DISC 1     /* tiles whose pixel-centre rectangle is within r_out of the gaze */
+#define A3FR_MASK_ANNULUS 2  /* as DISC with r_out, minus tiles lying wholly within r_in */
+
+typedef struct a3fr_ctx a3fr_ctx;
+
+/* Scene (Sec. 2.3: every point carries a position, an anisotropic scale, a
+ * rotation, an opacity and spherical-harmonic colour).  Structure of arrays,
+ * float32, device pointers, already activated (scale = exp(log-scale),
+ * opacity = sigmoid(logit)).  quat is (w, x, y, z) and is normalised inside
+ * the library.  sh holds (sh_degree+1)^2 coefficients as [coef][channel][n]. */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;        /* 0..3 */
+    int32_t reserved;
+    const float *mean_dev;    /* [3][n] */
+    const float *scale_dev;   /* [3][n] */
+    const float *quat_dev;    /* [4][n] */
+    const float *opacity_dev; /* [n] */
+    const float *sh_dev;      /* [(sh_degree+1)^2][3][n] */
+} a3fr_scene;
+
+/* One rendered layer of one eye: a pinhole camera at this layer's resolution
+ * plus the layer's active-tile mask.  OpenCV axes (x right, y down, z
+ * forward); world->camera p = R x + t.  Views with the same eye index share
+ * their colour (view-dependent spherical harmonics seen from campos) and must
+ * carry the same R, t and campos.  Gaze and radii are in this layer's pixels. */
+typedef struct {
+    double R[9];          /* row-major */
+    double t[3];
+    double campos[3];     /* eye centre, world space (view direction for colour) */
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    int32_t eye;          /* 0 .. 15 */
+    int32_t mask;         /* A3FR_MASK_* */
+    int32_t select;       /* 1: draw only the kept periphery subset (see a3fr_preprocess) */
+    int32_t reserved;
+    double gx, gy;        /* gaze point */
+    double r_in, r_out;   /* mask radii */
+    float bg[3];          /* background colour */
+    int32_t reserved2;
+} a3fr_view;
+
+/* An eye camera at full resolution. */
+typedef struct {
+    double R[9];
+    double t[3];
+    double campos[3];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    float bg[3];
+    int32_t reserved;
+} a3fr_camera;
+
+typedef struct { double x, y; } a3fr_gaze; /* full-resolution pixel coordinates */
+
+/* Layered foveation (Sec. 2.2: foveal region at full resolution, surrounding
+ * regions at progressively lower resolution; Eq. 1 sizes the foveal radius).
+ * Full-resolution pixels within r_fovea of the gaze come from the fovea layer,
+ * those within r_mid from the mid layer (1/scale_mid per axis, bilinear), the
+ * rest from the periphery layer (1/scale_periph per axis, bilinear), which
+ * draws only the ceil(keep_num/keep_den x N_vis) visible Gaussians of largest
+ * opacity x projected area (ties to the lower index). */
+typedef struct {
+    double r_fovea, r_mid;    /* full-resolution pixels, 0 <= r_fovea <= r_mid */
+    int32_t scale_mid;        /* 2 */
+    int32_t scale_periph;     /* 4 */
+    int32_t keep_num, keep_den; /* 3, 10 */
+    double margin;            /* mid-layer bilinear support in mid-layer pixels (2.0) */
+} a3fr_fovea;
+
+/* Counters of the last bin_sort / blend. */
+typedef struct {
+    int64_t n_keys;         /* (tile, depth) keys emitted */
+    int64_t n_kept[16];     /* kept periphery points per selecting view (first 16 views) */
+    int64_t n_tiles;        /* tiles of all views */
+    int64_t n_active_tiles; /* tiles rendered */
+} a3fr_counts;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context bound to a HIP stream (hipStream_t; NULL = default
+ * stream).  The context owns a growable device workspace (allocated with
+ * hipMalloc on first use, freed by a3fr_destroy). */
+a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream);
+void a3fr_destroy(a3fr_ctx *ctx);
+a3fr_status a3fr_set_stream(a3fr_ctx *ctx, void *hip_stream);
+/* Debug option: keep a copy of the keys in emission order for a3fr_inspect
+ * (costs one extra device copy of the keys per a3fr_bin_sort). */
+a3fr_status a3fr_set_debug(a3fr_ctx *ctx, int32_t keep_emission_order);
+/* Blocks until the context's stream is idle; reports deferred device errors. */
+a3fr_status a3fr_sync(a3fr_ctx *ctx);
+const char *a3fr_status_str(a3fr_status s);
+const char *a3fr_last_error(const a3fr_ctx *ctx);
+
+/* ---- the rendering path ---------------------------------------------------*/
+
+/* Projection of every (view, Gaussian) pair (Sec. 2.3, projection stage):
+ * near-plane cull (z <= 0.2), EWA projection of the 3D covariance to a 2D
+ * covariance dilated by 0.3 px^2, the tile rectangle of the footprint box
+ * {d : d' Sigma2D^-1 d <= 11.1}, the number of active tiles it covers, the
+ * float32 depth key and view-dependent SH colour per eye.  The integer
+ * results are computed in float64 in a fixed operation order (bit-exact
+ * against the reference definition).  For views with select = 1 the
+ * periphery subset is chosen here (radix select on opacity x pi x
+ * sqrt(det Sigma2D)).  Then the key counts are prefix-summed.
+ * views: host array of n_views (1..384) views.  keep = keep_num/keep_den
+ * (ignored without selecting views).  The results stay in the context and are
+ * reused by a3fr_bin_sort and a3fr_blend until the next a3fr_preprocess
+ * (Sec. 3.5).  Limits: n < 2^31; every view <= 65535 tiles per axis. */
+a3fr_status a3fr_preprocess(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_view *views, int32_t n_views,
+                            int32_t keep_num, int32_t keep_den);
+
+/* Tile-key duplication and depth sort (Sec. 2.3, sorting stage): one 64-bit
+ * key (global tile id << 32 | float32 depth bits) per (Gaussian, active tile
+ * it touches), value = Gaussian index, emitted in (view, index, row, column)
+ * order and sorted by a stable LSD radix sort, so equal (tile, depth) keys
+ * stay in index order; then each tile's [start, end) run.  Global tile id =
+ * the view's tile offset (views in order) + row x tiles_x + column.
+ * SYNCHRONISES once (reads the key count).  *n_keys_out (host, may be NULL)
+ * receives the key count.  A3FR_ECAPACITY if the count reaches 2^30. */
+a3fr_status a3fr_bin_sort(a3fr_ctx *ctx, int64_t *n_keys_out);
+
+/* Front-to-back blend of every active tile (Sec. 2.3, rasterization stage):
+ * alpha = min(0.99, o exp(-q/2)), q the Mahalanobis distance of the pixel
+ * centre; alpha < 1/255 is skipped; a pixel stops before the Gaussian that
+ * would bring its transmittance below 1e-4; output = colour + T x bg.
+ * rgb_dev: all views' images concatenated in view order, each [3][H][W];
+ * T_dev (may be NULL): final transmittance, [H][W] per view, concatenated;
+ * last_dev (may be NULL): 1 + list position of the last blended Gaussian
+ * (0: none).  Pixels of inactive tiles are not written. */
+a3fr_status a3fr_blend(a3fr_ctx *ctx, float *rgb_dev, float *T_dev, uint32_t *last_dev);
+
+/* Plain full-resolution render (FRR) of n_cams eye cameras: every tile, every
+ * Gaussian.  out_dev: [n_cams][3][H][W].  Synchronises once (a3fr_bin_sort). */
+a3fr_status a3fr_render_full(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_cams,
+                             float *out_dev);
+
+/* Foveated stereo frame: the three layers of each of n_eyes eyes
+ * (a3fr_make_foveated_views) rendered in one preprocess / sort / blend,
+ * then composited to full resolution: out_dev [n_eyes][3][H][W].
+ * Synchronises once (a3fr_bin_sort). */
+a3fr_status a3fr_render_foveated(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams,
+                                 const a3fr_gaze *gaze, int32_t n_eyes, const a3fr_fovea *fovea, float *out_dev);
+
+/* Host helper: the 3 layer views of each eye (eye-major, layer-minor:
+ * fovea disc of radius r_fovea at full resolution; mid annulus at 1/scale_mid
+ * with radii r_fovea/s - margin and r_mid/s + margin; periphery at
+ * 1/scale_periph, every tile, select = 1).  out: host array of 3*n_eyes. */
+a3fr_status a3fr_make_foveated_views(const a3fr_camera *cams, const a3fr_gaze *gaze, int32_t n_eyes,
+                                     const a3fr_fovea *fovea, a3fr_view *out);
+
+/* Composite of one eye's three layers (fovea [3][H][W], mid [3][H/sm][W/sm],
+ * periphery [3][H/sp][W/sp]) into out_dev [3][H][W]: region by the distance
+ * of the pixel centre to the gaze (float64 test), bilinear with
+ * align_corners = false and clamp-to-edge for the coarser layers.  If
+ * periph_full_dev is not NULL it replaces the bilinear periphery (an
+ * already-upsampled [3][H][W] image). */
+a3fr_status a3fr_composite(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze, const a3fr_fovea *fovea,
+                           const float *fovea_dev, const float *mid_dev, const float *periph_dev,
+                           const float *periph_full_dev, float *out_dev);
+
+/* Quality judge: squared error of two [3][H][W] images, both clamped to
+ * [0,1], summed over RGB per region (0 fovea, 1 mid, 2 periphery; by the same
+ * distance test as the composite) in float64, and the pixel count per
+ * region.  sse3 and count3 are host arrays of 3; synchronises.
+ * PSNR = 10 log10(count x 3 / sse). */
+a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze, double r_fovea, double r_mid,
+                            const float *a_dev, const float *b_dev, double *sse3, int64_t *count3);
+
+/* Counters of the last preprocess / bin_sort (host struct). */
+a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
+
+/* ---- inspection of buffered intermediates (tests and tools) -------------- */
+typedef enum {
+    A3FR_BUF_COUNTS = 0,      /* uint32 [n_views][n] active tiles covered (before selection) */
+    A3FR_BUF_DEPTH = 1,       /* uint32 [n_views][n] float32 depth bits (valid where count > 0) */
+    A3FR_BUF_RECT = 2,        /* uint16 [n_views][n][4] x0,x1,y0,y1 tile rectangle (valid where count > 0) */
+    A3FR_BUF_OFFSETS = 3,     /* uint32 [n_views*n + 1] exclusive prefix of the kept counts */
+    A3FR_BUF_KEYS = 4,        /* uint64 [K] keys in emission order (needs a3fr_set_debug) */
+    A3FR_BUF_VALS = 5,        /* uint32 [K] values in emission order (needs a3fr_set_debug) */
+    A3FR_BUF_SORTED_KEYS = 6, /* uint64 [K] */
+    A3FR_BUF_SORTED_VALS = 7, /* uint32 [K] */
+    A3FR_BUF_RANGES = 8,      /* uint32 [n_tiles][2] start, end */
+    A3FR_BUF_ACTIVE = 9,      /* uint8 [n_tiles] active-tile flags */
+    A3FR_BUF_KEEP = 10,       /* uint8 [n_views][n] kept by the periphery subset (selecting views) */
+    A3FR_BUF_RECORDS = 11     /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb */
+} a3fr_buffer;
+
+/* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);
+ * *bytes_out (host) receives its size.  dst_dev may be NULL to query. */
+a3fr_status a3fr_inspect(a3fr_ctx *ctx, a3fr_buffer which, void *dst_dev, int64_t max_bytes, int64_t *bytes_out);
+
+/* Device self-check used by the tests: out_sqrt[i] = sqrt(x[i]) and
+ * out_div[i] = x[i] / y[i] in float64 on the device (the operations the
+ * key path relies on being correctly rounded).  Device pointers, n >= 0. */
+a3fr_status a3fr_fp64_probe(a3fr_ctx *ctx, const double *x_dev, const double *y_dev, double *sqrt_dev,
+                            double *div_dev, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* A3FR_H */

@@ -562,6 +562,48 @@ void or_blend_brute(int64_t n, int32_t nv, const or_view *views, const int64_t *
     free(list);
 }
 
+typedef struct {
+    const uint32_t *list; int64_t len; int32_t v; int64_t n;
+    const double *mu, *cov, *det; const float *opac; const double *col; const double *bg;
+    or_blend_opts op; const int32_t *xs, *ys; double *rgb, *T; int32_t *amb;
+} or_pixels_ctx;
+
+static void or_pixels_body(void *vctx, int64_t j) {
+    or_pixels_ctx *C = (or_pixels_ctx *)vctx;
+    or_pix P;
+    or_blend_pixel(C->xs[j] + 0.5, C->ys[j] + 0.5, C->list, C->len, C->v, C->n, C->mu, C->cov, C->det, C->opac,
+                   C->col, C->bg, &C->op, &P);
+    for (int ch = 0; ch < 3; ++ch) C->rgb[3 * j + ch] = P.rgb[ch];
+    C->T[j] = P.T;
+    C->amb[j] = P.amb;
+}
+
+/* The plain definition for a sample of pixels of view v of a large scene:
+ * every projectable (and, for a selecting view, kept) Gaussian sorted by
+ * (depth bits, index), composited at each requested pixel centre. */
+void or_blend_pixels(int64_t n, int32_t v, const or_view *views, const uint8_t *proj, const uint8_t *keep,
+                     const uint32_t *depth_bits, const double *mu, const double *cov, const double *det,
+                     const float *opac, const double *colour, double eps_alpha, double eps_step, int64_t npx,
+                     const int32_t *xs, const int32_t *ys, double *rgb, double *T, int32_t *amb, int nthreads) {
+    const or_view *vw = &views[v];
+    uint64_t *ord = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = (int64_t)v * n + i;
+        if (!proj[k]) continue;
+        if (vw->select && !(keep && keep[k])) continue;
+        ord[m++] = ((uint64_t)depth_bits[k] << 32) | (uint64_t)i;
+    }
+    qsort(ord, (size_t)m, sizeof(uint64_t), or_u64_cmp);
+    for (int64_t a = 0; a < m; ++a) list[a] = (uint32_t)(ord[a] & 0xffffffffu);
+    or_pixels_ctx C = {list, m, v, n, mu, cov, det, opac, colour + (int64_t)vw->eye * n * 3, vw->bg,
+                       {eps_alpha, eps_step}, xs, ys, rgb, T, amb};
+    or_parallel(npx, or_pixels_body, &C, nthreads);
+    free(ord);
+    free(list);
+}
+
 /* Per-step transmittance of one pixel along its tile list (for the
  * monotonicity invariant): trace[j] = T after entry j (unchanged when skipped),
  * stops where the blend stops. Returns the number of entries written. */

@@ -71,6 +71,7 @@ def lib():
         L.or_blend.argtypes = [I32, P, I32, I32, P, P, P, P, P, P, I64, P, P, P, P, P, D, D,
                                P, P, P, P, P, C.c_int]
         L.or_blend_brute.argtypes = [I64, I32, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.or_blend_pixels.argtypes = [I64, I32, P, P, P, P, P, P, P, P, P, D, D, I64, P, P, P, P, P, C.c_int]
         L.or_pixel_trace.argtypes = [I32, D, D, P, I64, I64, P, P, P, P, P]
         L.or_pixel_trace.restype = I64
         L.or_composite.argtypes = [I32, I32, D, D, D, D, P, P, I32, P, I32, P, P]
@@ -340,6 +341,23 @@ def render_brute(scene, views, keep=None, colours=None, tw=TILE, th=TILE):
         a, b = int(ioff[v]), int(ioff[v + 1])
         imgs.append(dict(rgb=rgb[3 * a:3 * b].reshape(3, vw.height, vw.width), T=T[a:b].reshape(vw.height, vw.width)))
     return imgs
+
+
+def blend_pixels(scene, views, pr, keep, colours, v, xs, ys, eps_alpha=None, eps_step=None, nthreads=None):
+    """Brute-force colours (and T, ambiguity) of sampled pixels (xs, ys) of view v,
+    from the projection arrays of project()."""
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    npx = xs.size
+    rgb, T, amb = np.zeros((npx, 3)), np.zeros(npx), np.zeros(npx, np.int32)
+    vc = _views_c(views)
+    op = np.ascontiguousarray(scene.opacity, np.float32)
+    lib().or_blend_pixels(scene.n, v, vc, _p(pr["proj"]), _p(None if keep is None else np.ascontiguousarray(keep)),
+                          _p(pr["depth_bits"]), _p(pr["mu"]), _p(pr["cov"]), _p(pr["det"]), _p(op),
+                          _p(np.ascontiguousarray(colours)), EPS_ALPHA if eps_alpha is None else eps_alpha,
+                          EPS_STEP if eps_step is None else eps_step, npx, _p(xs), _p(ys), _p(rgb), _p(T), _p(amb),
+                          nthreads or default_threads())
+    return rgb, T, amb
 
 
 def pixel_trace(res, view_index, px, py, tw=TILE, th=TILE, views=None):

@@ -1,0 +1,292 @@
+"""Python binding of liba3fr.so, the gfx950 foveated 3D Gaussian Splatting library.
+
+Argument marshalling only: every step of the rendering path runs in the HIP
+kernels behind the C ABI declared in include/a3fr.h.  PyTorch provides device
+memory (tensors) and the HIP stream.  There is no CPU fallback: if the shared
+library is missing, loading it raises.
+
+Method names follow the C entry points (a3fr_preprocess -> Context.preprocess,
+a3fr_bin_sort -> Context.bin_sort, a3fr_blend -> Context.blend,
+a3fr_render_foveated -> Context.render_foveated, ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liba3fr.so")
+
+A3FR_OK, A3FR_EINVAL, A3FR_ENOMEM, A3FR_ECAPACITY, A3FR_EDEVICE, A3FR_ENOTREADY = range(6)
+MASK_ALL, MASK_DISC, MASK_ANNULUS = 0, 1, 2
+TILE = 16
+
+BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
+           active=9, keep=10, records=11)
+
+_lib = None
+
+
+class A3FRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"a3fr status {status}: {msg}")
+        self.status = status
+
+
+class Scene_(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
+                ("mean_dev", C.c_void_p), ("scale_dev", C.c_void_p), ("quat_dev", C.c_void_p),
+                ("opacity_dev", C.c_void_p), ("sh_dev", C.c_void_p)]
+
+
+class View_(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("campos", C.c_double * 3),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_int32), ("mask", C.c_int32),
+                ("select", C.c_int32), ("reserved", C.c_int32),
+                ("gx", C.c_double), ("gy", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double),
+                ("bg", C.c_float * 3), ("reserved2", C.c_int32)]
+
+
+class Camera_(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("campos", C.c_double * 3),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("bg", C.c_float * 3), ("reserved", C.c_int32)]
+
+
+class Gaze_(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double)]
+
+
+class Fovea_(C.Structure):
+    _fields_ = [("r_fovea", C.c_double), ("r_mid", C.c_double), ("scale_mid", C.c_int32),
+                ("scale_periph", C.c_int32), ("keep_num", C.c_int32), ("keep_den", C.c_int32),
+                ("margin", C.c_double)]
+
+
+class Counts_(C.Structure):
+    _fields_ = [("n_keys", C.c_int64), ("n_kept", C.c_int64 * 16), ("n_tiles", C.c_int64),
+                ("n_active_tiles", C.c_int64)]
+
+
+def lib():
+    """Load liba3fr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2507_04147_amd/build.py "
+                          "(the HIP path has no fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "a3fr_create": [C.POINTER(P), P],
+        "a3fr_set_stream": [P, P],
+        "a3fr_set_debug": [P, I32],
+        "a3fr_sync": [P],
+        "a3fr_preprocess": [P, C.POINTER(Scene_), C.POINTER(View_), I32, I32, I32],
+        "a3fr_bin_sort": [P, C.POINTER(I64)],
+        "a3fr_blend": [P, P, P, P],
+        "a3fr_render_full": [P, C.POINTER(Scene_), C.POINTER(Camera_), I32, P],
+        "a3fr_render_foveated": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32,
+                                 C.POINTER(Fovea_), P],
+        "a3fr_make_foveated_views": [C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Fovea_),
+                                     C.POINTER(View_)],
+        "a3fr_composite": [P, I32, I32, Gaze_, C.POINTER(Fovea_), P, P, P, P, P],
+        "a3fr_region_sse": [P, I32, I32, Gaze_, D, D, P, P, C.POINTER(D), C.POINTER(I64)],
+        "a3fr_get_counts": [P, C.POINTER(Counts_)],
+        "a3fr_inspect": [P, I32, P, I64, C.POINTER(I64)],
+        "a3fr_fp64_probe": [P, P, P, P, P, I64],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.a3fr_destroy.argtypes = [P]
+    L.a3fr_destroy.restype = None
+    L.a3fr_status_str.argtypes = [C.c_int]
+    L.a3fr_status_str.restype = C.c_char_p
+    L.a3fr_last_error.argtypes = [P]
+    L.a3fr_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def _dp(t):
+    """Device pointer of a contiguous torch CUDA tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def camera_struct(cam) -> Camera_:
+    c = Camera_()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float64).reshape(9)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float64).reshape(3)]
+    c.campos[:] = [float(x) for x in np.asarray(cam.campos, np.float64).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.bg[:] = [float(x) for x in cam.bg]
+    return c
+
+
+def view_struct(v) -> View_:
+    """From any object with the a3fr_view fields (e.g. the oracle's View)."""
+    s = View_()
+    s.R[:] = [float(x) for x in np.asarray(v.R, np.float64).reshape(9)]
+    s.t[:] = [float(x) for x in np.asarray(v.t, np.float64).reshape(3)]
+    s.campos[:] = [float(x) for x in np.asarray(v.campos, np.float64).reshape(3)]
+    s.fx, s.fy, s.cx, s.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+    s.width, s.height, s.eye, s.mask, s.select = int(v.width), int(v.height), int(v.eye), int(v.mask), int(v.select)
+    s.gx, s.gy, s.r_in, s.r_out = float(v.gx), float(v.gy), float(v.r_in), float(v.r_out)
+    s.bg[:] = [float(x) for x in v.bg]
+    return s
+
+
+def fovea_struct(r_fovea, r_mid, scale_mid=2, scale_periph=4, keep=(3, 10), margin=2.0) -> Fovea_:
+    f = Fovea_()
+    f.r_fovea, f.r_mid, f.scale_mid, f.scale_periph = float(r_fovea), float(r_mid), int(scale_mid), int(scale_periph)
+    f.keep_num, f.keep_den, f.margin = int(keep[0]), int(keep[1]), float(margin)
+    return f
+
+
+class DeviceScene:
+    """A scene resident in device memory (torch tensors, SoA float32)."""
+
+    def __init__(self, mean, scale, quat, opacity, sh, sh_degree=3):
+        self.mean, self.scale, self.quat, self.opacity, self.sh = mean, scale, quat, opacity, sh
+        self.n = int(opacity.shape[0])
+        self.sh_degree = sh_degree
+
+    @classmethod
+    def from_host(cls, scene, device="cuda", sh_degree=3):
+        import torch
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        nk = (sh_degree + 1) ** 2
+        return cls(f(scene.mean), f(scene.scale), f(scene.quat), f(scene.opacity), f(scene.sh[:nk]), sh_degree)
+
+    def struct(self) -> Scene_:
+        s = Scene_()
+        s.n, s.sh_degree = self.n, self.sh_degree
+        s.mean_dev, s.scale_dev, s.quat_dev = _dp(self.mean), _dp(self.scale), _dp(self.quat)
+        s.opacity_dev, s.sh_dev = _dp(self.opacity), _dp(self.sh)
+        return s
+
+
+class Context:
+    """One a3fr context bound to a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, stream=None):
+        import torch
+        self._L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(self._L.a3fr_create(C.byref(h), C.c_void_p(stream.cuda_stream)), ctx=None)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.a3fr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ctx="self"):
+        if st != A3FR_OK:
+            msg = self._L.a3fr_last_error(self._h).decode() if ctx == "self" and self._h else ""
+            raise A3FRError(st, msg or self._L.a3fr_status_str(st).decode())
+
+    # ---- C entry points ----
+    def set_debug(self, keep_emission_order=True):
+        self._check(self._L.a3fr_set_debug(self._h, int(bool(keep_emission_order))))
+
+    def sync(self):
+        self._check(self._L.a3fr_sync(self._h))
+
+    def preprocess(self, scene: DeviceScene, views, keep=(3, 10)):
+        self._scene = scene  # keep the tensors alive while queued work reads them
+        arr = (View_ * len(views))(*[view_struct(v) if not isinstance(v, View_) else v for v in views])
+        self._views = arr
+        self._check(self._L.a3fr_preprocess(self._h, C.byref(scene.struct()), arr, len(views), int(keep[0]),
+                                            int(keep[1])))
+
+    def bin_sort(self) -> int:
+        k = C.c_int64()
+        self._check(self._L.a3fr_bin_sort(self._h, C.byref(k)))
+        return int(k.value)
+
+    def blend(self, rgb, T=None, last=None):
+        self._check(self._L.a3fr_blend(self._h, _dp(rgb), _dp(T), _dp(last)))
+
+    def render_full(self, scene: DeviceScene, cams, out):
+        self._scene = scene
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        self._check(self._L.a3fr_render_full(self._h, C.byref(scene.struct()), arr, len(cams), _dp(out)))
+
+    def render_foveated(self, scene: DeviceScene, cams, gazes, fovea: Fovea_, out):
+        self._scene = scene
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+        self._check(self._L.a3fr_render_foveated(self._h, C.byref(scene.struct()), arr, gz, len(cams),
+                                                 C.byref(fovea), _dp(out)))
+
+    def composite(self, W, H, gaze, fovea: Fovea_, fov_img, mid_img, per_img, per_full, out):
+        self._check(self._L.a3fr_composite(self._h, W, H, Gaze_(float(gaze[0]), float(gaze[1])), C.byref(fovea),
+                                           _dp(fov_img), _dp(mid_img), _dp(per_img), _dp(per_full), _dp(out)))
+
+    def region_sse(self, W, H, gaze, r_fovea, r_mid, a, b):
+        sse = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        self._check(self._L.a3fr_region_sse(self._h, W, H, Gaze_(float(gaze[0]), float(gaze[1])), float(r_fovea),
+                                            float(r_mid), _dp(a), _dp(b), sse, cnt))
+        return np.array(sse[:]), np.array(cnt[:])
+
+    def get_counts(self):
+        c = Counts_()
+        self._check(self._L.a3fr_get_counts(self._h, C.byref(c)))
+        return dict(n_keys=c.n_keys, n_kept=list(c.n_kept), n_tiles=c.n_tiles, n_active_tiles=c.n_active_tiles)
+
+    def inspect(self, which: str, dtype):
+        """Copy of a buffered intermediate as a device tensor of `dtype`."""
+        import torch
+        nb = C.c_int64()
+        self._check(self._L.a3fr_inspect(self._h, BUF[which], None, 0, C.byref(nb)))
+        esz = torch.tensor([], dtype=dtype).element_size()
+        out = torch.empty(max(1, nb.value // esz), dtype=dtype, device="cuda")
+        self._check(self._L.a3fr_inspect(self._h, BUF[which], _dp(out), out.numel() * esz, C.byref(nb)))
+        return out[: nb.value // esz]
+
+    def fp64_probe(self, x, y):
+        import torch
+        sq, dv = torch.empty_like(x), torch.empty_like(x)
+        self._check(self._L.a3fr_fp64_probe(self._h, _dp(x), _dp(y), _dp(sq), _dp(dv), x.numel()))
+        return sq, dv
+
+
+def make_foveated_views(cams, gazes, fovea: Fovea_):
+    arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+    gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+    out = (View_ * (3 * len(cams)))()
+    st = lib().a3fr_make_foveated_views(arr, gz, len(cams), C.byref(fovea), out)
+    if st != A3FR_OK:
+        raise A3FRError(st, "make_foveated_views")
+    return list(out)
+
+
+EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", "a3fr_sync", "a3fr_status_str",
+            "a3fr_last_error", "a3fr_preprocess", "a3fr_bin_sort", "a3fr_blend", "a3fr_render_full",
+            "a3fr_render_foveated", "a3fr_make_foveated_views", "a3fr_composite", "a3fr_region_sse",
+            "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe"]

@@ -1,0 +1,90 @@
+// Internal declarations of the gfx950 library (kernels + host glue).
+// Not part of the public ABI; shared only between the library's own sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/a3fr.h"
+
+namespace a3fr {
+
+constexpr int kTile = A3FR_TILE;          // 16 x 16 pixel tiles
+constexpr int kWave = 64;                 // CDNA wavefront
+constexpr double kZNear = 0.2;
+constexpr double kDilate = 0.3;           // low-pass dilation of the 2D covariance, px^2
+constexpr double kExtentQ = 11.1;         // footprint box of {d' S^-1 d <= Q}; Q >= 2 ln 255
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr int kMaxViews = 384;
+constexpr int kMaxEyes = 16;
+
+// Blend record of one (view, Gaussian): centre in float64 (so that the
+// tile-relative offset keeps full precision at any image size) and the
+// inverse 2D covariance in LDL^T form scaled for exp2:
+//   log2 G(d) = a2 (dx + k dy)^2 + c2 dy^2,
+//   a2 = -log2(e)/2 * c/det, k = -b/c, c2 = -log2(e)/2 / c,
+// where (a, b, c) is the dilated 2D covariance and det = a c - b^2.
+struct alignas(16) Record {
+    double u, v;
+    float a2, k, c2, o;
+    float r, g, b, pad;
+};
+static_assert(sizeof(Record) == 48, "record layout");
+
+// Device copy of the per-frame view table, plus derived tile-grid data.
+struct DevView {
+    a3fr_view v;
+    int32_t tiles_x, tiles_y;
+    int64_t tile_off;     // first global tile id
+    int64_t img_off;      // first pixel of this view in the concatenated images
+    int64_t mask_off;     // offset of this view's row tables (rows x (tiles_x + 1)) in the mask arrays
+    int32_t sel_slot;     // index among selecting views, -1 if none
+    int32_t pad;
+};
+
+// Per-selecting-view state of the periphery radix select.
+struct SelectState {
+    uint32_t hist[12][256];   // per pass digit histogram of the candidates
+};
+
+// Lookback status word of the onesweep sort: [31:30] flag, [29:0] count.
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1;
+
+// ---- kernels' host launchers (all enqueue on `s`) ----
+void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
+                       const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
+                       hipStream_t s);
+void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
+                       const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
+                       Record *rec, double *score, hipStream_t s);
+void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
+                   const uint32_t *counts, const double *score, int keep_num, int keep_den,
+                   uint32_t *sel_hist /* [nsel][12][256] */, uint8_t *keep, hipStream_t s);
+void launch_scan_counts(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
+                        uint32_t *offsets, uint64_t *block_sums, int64_t nblocks_cap, uint64_t *total,
+                        hipStream_t s);
+void launch_emit(const DevView *views, int nv, int64_t n, const uint32_t *offsets, const uint32_t *depth,
+                 const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
+                 uint64_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s);
+int sort_passes_for_bits(int bits);
+void launch_radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b, int64_t K,
+                       int key_bits, uint32_t *hist /* [8][256] */, uint32_t *status, int64_t status_cap,
+                       uint32_t *counters /* [8] */, bool *result_in_b, hipStream_t s);
+void launch_ranges(const uint64_t *keys, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
+void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
+                  const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
+                  hipStream_t s);
+void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
+                      const float *mid, int sm, const float *periph, int sp, const float *periph_full,
+                      float *out, hipStream_t s);
+void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm, const float *a,
+                       const float *b, double *partial /* [nblk][3] */, unsigned long long *cnt /* [nblk][3] */,
+                       int nblk, hipStream_t s);
+void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace a3fr

@@ -1,0 +1,601 @@
+// Host side of the C ABI (include/a3fr.h): argument checks, the context's
+// growable device workspace, and the order of launches of one frame.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "a3fr_internal.h"
+
+using namespace a3fr;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct a3fr_ctx {
+    hipStream_t stream = nullptr;
+    std::string err;
+    // frame description
+    int nv = 0;
+    int64_t n = 0;
+    int64_t ntiles = 0;
+    int64_t npix = 0;
+    int nsel = 0;
+    int64_t rows_total = 0;
+    int64_t mask_entries = 0;
+    std::vector<DevView> hviews;
+    std::vector<int32_t> hrow_view, hrow_y, hsel_views;
+    // pinned staging for uploads and small readbacks
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t upload_done = nullptr;
+    uint64_t *h_total = nullptr;
+    // device workspace
+    DevBuf views, row_view, row_y, row_prefix, row_list, active;
+    DevBuf counts, depth, rect, rec, score, keep, sel_views, sel;
+    DevBuf offsets, block_sums, total;
+    DevBuf keys_a, keys_b, vals_a, vals_b, big_list, big_count;
+    DevBuf sort_hist, sort_status, sort_counters, ranges;
+    DevBuf layers, sse_part, sse_cnt;
+    DevBuf keys_e, vals_e;     // emission-order copy (debug option)
+    bool keep_emission = false;
+    // state
+    bool preprocessed = false;
+    bool sorted = false;
+    bool sorted_in_b = false;
+    int64_t K = 0;
+};
+
+namespace {
+
+a3fr_status fail(a3fr_ctx *c, a3fr_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHECK(ctx, expr)                                                                    \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), A3FR_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+a3fr_status ensure(a3fr_ctx *c, DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return A3FR_OK;
+    if (b.p) {
+        // the old buffer may still be read by queued work
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        HIPCHECK(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 255) & ~size_t(255);
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(c, A3FR_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    b.cap = want;
+    return A3FR_OK;
+}
+
+template <class T>
+T *P(DevBuf &b) { return reinterpret_cast<T *>(b.p); }
+
+#define TRY(expr)                           \
+    do {                                    \
+        a3fr_status s_ = (expr);            \
+        if (s_ != A3FR_OK) return s_;       \
+    } while (0)
+
+a3fr_status check_launch(a3fr_ctx *c, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, A3FR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return A3FR_OK;
+}
+
+a3fr_status ensure_pinned(a3fr_ctx *c, size_t bytes) {
+    if (c->upload_done) HIPCHECK(c, hipEventSynchronize(c->upload_done));
+    if (c->pinned_cap >= bytes) return A3FR_OK;
+    if (c->pinned) HIPCHECK(c, hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    size_t want = bytes + bytes / 2 + 4096;
+    if (hipHostMalloc(&c->pinned, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->pinned_cap = 0;
+        return fail(c, A3FR_ENOMEM, "hipHostMalloc failed");
+    }
+    c->pinned_cap = want;
+    return A3FR_OK;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+a3fr_status check_scene(a3fr_ctx *c, const a3fr_scene *s) {
+    if (!s) return fail(c, A3FR_EINVAL, "scene is NULL");
+    if (s->n < 0 || s->n >= (int64_t(1) << 31)) return fail(c, A3FR_EINVAL, "scene.n must be in [0, 2^31)");
+    if (s->sh_degree < 0 || s->sh_degree > 3) return fail(c, A3FR_EINVAL, "scene.sh_degree must be 0..3");
+    if (s->n > 0 && (!s->mean_dev || !s->scale_dev || !s->quat_dev || !s->opacity_dev || !s->sh_dev))
+        return fail(c, A3FR_EINVAL, "scene arrays must not be NULL");
+    return A3FR_OK;
+}
+
+a3fr_status check_view(a3fr_ctx *c, const a3fr_view &v, int k) {
+    std::string w = "view " + std::to_string(k) + ": ";
+    if (v.width <= 0 || v.height <= 0) return fail(c, A3FR_EINVAL, w + "width and height must be positive");
+    if ((v.width + kTile - 1) / kTile > 65535 || (v.height + kTile - 1) / kTile > 65535)
+        return fail(c, A3FR_EINVAL, w + "more than 65535 tiles per axis");
+    if ((int64_t)v.width * v.height > (int64_t(1) << 31)) return fail(c, A3FR_EINVAL, w + "image too large");
+    if (v.eye < 0 || v.eye >= kMaxEyes) return fail(c, A3FR_EINVAL, w + "eye must be 0..15");
+    if (v.mask < 0 || v.mask > 2) return fail(c, A3FR_EINVAL, w + "mask must be 0, 1 or 2");
+    if (v.select != 0 && v.select != 1) return fail(c, A3FR_EINVAL, w + "select must be 0 or 1");
+    if (!(v.fx > 0.0) || !(v.fy > 0.0) || !is_fin(v.fx) || !is_fin(v.fy) || !is_fin(v.cx) || !is_fin(v.cy))
+        return fail(c, A3FR_EINVAL, w + "focal lengths must be positive and finite");
+    for (int j = 0; j < 9; ++j) if (!is_fin(v.R[j])) return fail(c, A3FR_EINVAL, w + "R not finite");
+    for (int j = 0; j < 3; ++j)
+        if (!is_fin(v.t[j]) || !is_fin(v.campos[j])) return fail(c, A3FR_EINVAL, w + "t/campos not finite");
+    if (v.mask != A3FR_MASK_ALL && (!is_fin(v.gx) || !is_fin(v.gy) || !is_fin(v.r_out) || !is_fin(v.r_in)))
+        return fail(c, A3FR_EINVAL, w + "gaze and radii must be finite");
+    return A3FR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *a3fr_status_str(a3fr_status s) {
+    switch (s) {
+        case A3FR_OK: return "ok";
+        case A3FR_EINVAL: return "invalid argument";
+        case A3FR_ENOMEM: return "out of device memory";
+        case A3FR_ECAPACITY: return "capacity exceeded";
+        case A3FR_EDEVICE: return "device error";
+        case A3FR_ENOTREADY: return "call order violated";
+    }
+    return "unknown status";
+}
+
+const char *a3fr_last_error(const a3fr_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
+    if (!out) return A3FR_EINVAL;
+    *out = nullptr;
+    a3fr_ctx *c = new (std::nothrow) a3fr_ctx();
+    if (!c) return A3FR_ENOMEM;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return A3FR_EDEVICE;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_total), 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(c->upload_done);
+        delete c;
+        return A3FR_ENOMEM;
+    }
+    *out = c;
+    return A3FR_OK;
+}
+
+void a3fr_destroy(a3fr_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
+                      &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
+                      &c->sel, &c->offsets, &c->block_sums, &c->total, &c->keys_a, &c->keys_b,
+                      &c->vals_a, &c->vals_b, &c->big_list, &c->big_count, &c->sort_hist,
+                      &c->sort_status, &c->sort_counters, &c->ranges, &c->layers, &c->sse_part,
+                      &c->sse_cnt, &c->keys_e, &c->vals_e};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->h_total) (void)hipHostFree(c->h_total);
+    if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    delete c;
+}
+
+a3fr_status a3fr_set_stream(a3fr_ctx *c, void *hip_stream) {
+    if (!c) return A3FR_EINVAL;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_set_debug(a3fr_ctx *c, int32_t keep_emission_order) {
+    if (!c) return A3FR_EINVAL;
+    c->keep_emission = keep_emission_order != 0;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_sync(a3fr_ctx *c) {
+    if (!c) return A3FR_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipGetLastError());
+    if (c->sort_counters.p) {
+        uint32_t flag = 0;
+        HIPCHECK(c, hipMemcpy(&flag, P<uint32_t>(c->sort_counters) + 8, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        if (flag) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
+    }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_view *views, int32_t nv,
+                            int32_t keep_num, int32_t keep_den) {
+    if (!c) return A3FR_EINVAL;
+    TRY(check_scene(c, scene));
+    if (!views || nv < 1 || nv > kMaxViews) return fail(c, A3FR_EINVAL, "n_views must be in [1, 384]");
+    bool any_sel = false;
+    for (int k = 0; k < nv; ++k) {
+        TRY(check_view(c, views[k], k));
+        any_sel |= views[k].select != 0;
+    }
+    if (any_sel && (keep_den <= 0 || keep_num < 0 || keep_num > keep_den))
+        return fail(c, A3FR_EINVAL, "keep fraction must satisfy 0 <= keep_num <= keep_den, keep_den > 0");
+    // views of one eye share pose
+    for (int k = 0; k < nv; ++k)
+        for (int j = 0; j < k; ++j)
+            if (views[j].eye == views[k].eye &&
+                (std::memcmp(views[j].R, views[k].R, sizeof(views[k].R)) != 0 ||
+                 std::memcmp(views[j].t, views[k].t, sizeof(views[k].t)) != 0 ||
+                 std::memcmp(views[j].campos, views[k].campos, sizeof(views[k].campos)) != 0))
+                return fail(c, A3FR_EINVAL, "views with the same eye must share R, t and campos");
+    const int64_t n = scene->n;
+
+    // ---- frame layout
+    c->hviews.resize(nv);
+    c->hrow_view.clear();
+    c->hrow_y.clear();
+    c->hsel_views.clear();
+    int64_t toff = 0, ioff = 0, moff = 0;
+    for (int k = 0; k < nv; ++k) {
+        DevView &d = c->hviews[k];
+        std::memset(&d, 0, sizeof(d));
+        d.v = views[k];
+        d.tiles_x = (views[k].width + kTile - 1) / kTile;
+        d.tiles_y = (views[k].height + kTile - 1) / kTile;
+        d.tile_off = toff;
+        d.img_off = ioff;
+        d.mask_off = views[k].mask == A3FR_MASK_ALL ? -1 : moff;
+        d.sel_slot = views[k].select ? (int32_t)c->hsel_views.size() : -1;
+        if (views[k].select) c->hsel_views.push_back(k);
+        if (views[k].mask != A3FR_MASK_ALL) moff += (int64_t)d.tiles_y * (d.tiles_x + 1);
+        for (int ty = 0; ty < d.tiles_y; ++ty) {
+            c->hrow_view.push_back(k);
+            c->hrow_y.push_back(ty);
+        }
+        toff += (int64_t)d.tiles_x * d.tiles_y;
+        ioff += (int64_t)views[k].width * views[k].height;
+    }
+    if (toff >= (int64_t(1) << 31)) return fail(c, A3FR_ECAPACITY, "more than 2^31 tiles in one frame");
+    c->nv = nv;
+    c->n = n;
+    c->ntiles = toff;
+    c->npix = ioff;
+    c->nsel = (int)c->hsel_views.size();
+    c->rows_total = (int64_t)c->hrow_view.size();
+    c->mask_entries = moff;
+    c->preprocessed = false;
+    c->sorted = false;
+
+    // ---- workspace
+    const int64_t m = (int64_t)nv * n;
+    TRY(ensure(c, c->views, sizeof(DevView) * nv));
+    TRY(ensure(c, c->row_view, sizeof(int32_t) * c->rows_total));
+    TRY(ensure(c, c->row_y, sizeof(int32_t) * c->rows_total));
+    TRY(ensure(c, c->row_prefix, sizeof(uint16_t) * moff));
+    TRY(ensure(c, c->row_list, sizeof(uint16_t) * moff));
+    TRY(ensure(c, c->active, (size_t)toff));
+    TRY(ensure(c, c->counts, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->depth, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->rect, sizeof(uint64_t) * m));
+    TRY(ensure(c, c->rec, sizeof(Record) * m));
+    TRY(ensure(c, c->score, c->nsel ? sizeof(double) * m : 16));
+    TRY(ensure(c, c->keep, c->nsel ? (size_t)m : 16));
+    TRY(ensure(c, c->sel_views, sizeof(int32_t) * (c->nsel + 1)));
+    TRY(ensure(c, c->sel, sizeof(uint32_t) * ((size_t)c->nsel * 12 * 256 + (size_t)c->nsel * 32 + 32)));
+    TRY(ensure(c, c->offsets, sizeof(uint32_t) * (m + 1)));
+    TRY(ensure(c, c->block_sums, sizeof(uint64_t) * ((m + 4095) / 4096 + 1)));
+    TRY(ensure(c, c->total, sizeof(uint64_t)));
+
+    // ---- uploads through pinned staging
+    const size_t bytes_v = sizeof(DevView) * nv, bytes_r = sizeof(int32_t) * c->rows_total,
+                 bytes_s = sizeof(int32_t) * (c->nsel + 1);
+    TRY(ensure_pinned(c, bytes_v + 2 * bytes_r + bytes_s + 64));
+    char *pin = static_cast<char *>(c->pinned);
+    std::memcpy(pin, c->hviews.data(), bytes_v);
+    std::memcpy(pin + bytes_v, c->hrow_view.data(), bytes_r);
+    std::memcpy(pin + bytes_v + bytes_r, c->hrow_y.data(), bytes_r);
+    if (c->nsel) std::memcpy(pin + bytes_v + 2 * bytes_r, c->hsel_views.data(), sizeof(int32_t) * c->nsel);
+    HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, bytes_v, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->row_view.p, pin + bytes_v, bytes_r, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->row_y.p, pin + bytes_v + bytes_r, bytes_r, hipMemcpyHostToDevice, c->stream));
+    if (c->nsel)
+        HIPCHECK(c, hipMemcpyAsync(c->sel_views.p, pin + bytes_v + 2 * bytes_r, sizeof(int32_t) * c->nsel,
+                                   hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipEventRecord(c->upload_done, c->stream));
+
+    // ---- kernels
+    const DevView *dv = P<DevView>(c->views);
+    launch_tile_masks(dv, nv, c->rows_total, P<int32_t>(c->row_view), P<int32_t>(c->row_y),
+                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream);
+    launch_preprocess(*scene, dv, nv, nullptr, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
+                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
+                      c->stream);
+    if (c->nsel)
+        launch_select(dv, nv, P<int32_t>(c->sel_views), c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
+                      keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream);
+    launch_scan_counts(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->offsets),
+                       P<uint64_t>(c->block_sums), (m + 4095) / 4096 + 1, P<uint64_t>(c->total), c->stream);
+    TRY(check_launch(c, "preprocess"));
+    c->preprocessed = true;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "a3fr_bin_sort before a3fr_preprocess");
+    HIPCHECK(c, hipMemcpyAsync(c->h_total, c->total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    const uint64_t K = *c->h_total;
+    if (n_keys_out) *n_keys_out = (int64_t)K;
+    if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
+    const int64_t m = (int64_t)c->nv * c->n;
+    TRY(ensure(c, c->keys_a, sizeof(uint64_t) * K));
+    TRY(ensure(c, c->keys_b, sizeof(uint64_t) * K));
+    TRY(ensure(c, c->vals_a, sizeof(uint32_t) * K));
+    TRY(ensure(c, c->vals_b, sizeof(uint32_t) * K));
+    TRY(ensure(c, c->big_list, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->big_count, sizeof(uint32_t) * 4));
+    int tile_bits = 1;
+    while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
+    const int key_bits = 32 + tile_bits;
+    const int npass = sort_passes_for_bits(key_bits);
+    const int64_t nparts = ((int64_t)K + 4095) / 4096;
+    TRY(ensure(c, c->sort_hist, sizeof(uint32_t) * 8 * 256));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)npass * nparts * 256));
+    if (!c->sort_counters.p) {
+        TRY(ensure(c, c->sort_counters, sizeof(uint32_t) * 16));
+        launch_fill_u32(P<uint32_t>(c->sort_counters), 0u, 16, c->stream);
+    }
+    TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
+    const DevView *dv = P<DevView>(c->views);
+    launch_emit(dv, c->nv, c->n, P<uint32_t>(c->offsets), P<uint32_t>(c->depth), P<uint64_t>(c->rect),
+                P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint64_t>(c->keys_a),
+                P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream);
+    if (c->keep_emission) {
+        TRY(ensure(c, c->keys_e, sizeof(uint64_t) * K));
+        TRY(ensure(c, c->vals_e, sizeof(uint32_t) * K));
+        HIPCHECK(c, hipMemcpyAsync(c->keys_e.p, c->keys_a.p, sizeof(uint64_t) * K, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(c->vals_e.p, c->vals_a.p, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, c->stream));
+    }
+    bool in_b = false;
+    launch_radix_sort(P<uint64_t>(c->keys_a), P<uint32_t>(c->vals_a), P<uint64_t>(c->keys_b), P<uint32_t>(c->vals_b),
+                      (int64_t)K, key_bits, P<uint32_t>(c->sort_hist), P<uint32_t>(c->sort_status),
+                      (int64_t)npass * nparts * 256, P<uint32_t>(c->sort_counters), &in_b, c->stream);
+    c->sorted_in_b = in_b;
+    c->K = (int64_t)K;
+    const uint64_t *sk = in_b ? P<uint64_t>(c->keys_b) : P<uint64_t>(c->keys_a);
+    launch_ranges(sk, (int64_t)K, c->ntiles, P<uint32_t>(c->ranges), c->stream);
+    TRY(check_launch(c, "bin_sort"));
+    c->sorted = true;
+    return A3FR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+const uint64_t *sorted_keys(a3fr_ctx *c) {
+    return c->sorted_in_b ? P<uint64_t>(c->keys_b) : P<uint64_t>(c->keys_a);
+}
+const uint32_t *sorted_vals(a3fr_ctx *c) {
+    return c->sorted_in_b ? P<uint32_t>(c->vals_b) : P<uint32_t>(c->vals_a);
+}
+}  // namespace
+
+extern "C" {
+
+a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend before a3fr_bin_sort");
+    if (!rgb) return fail(c, A3FR_EINVAL, "rgb_dev is NULL");
+    launch_blend(P<DevView>(c->views), c->nv, c->ntiles, P<uint8_t>(c->active), P<uint32_t>(c->ranges),
+                 sorted_vals(c), P<Record>(c->rec), c->n, rgb, T, last, c->stream);
+    return check_launch(c, "blend");
+}
+
+static void view_from_camera(const a3fr_camera &cam, int eye, a3fr_view &v) {
+    std::memset(&v, 0, sizeof(v));
+    std::memcpy(v.R, cam.R, sizeof(v.R));
+    std::memcpy(v.t, cam.t, sizeof(v.t));
+    std::memcpy(v.campos, cam.campos, sizeof(v.campos));
+    v.fx = cam.fx; v.fy = cam.fy; v.cx = cam.cx; v.cy = cam.cy;
+    v.width = cam.width; v.height = cam.height;
+    v.eye = eye;
+    v.mask = A3FR_MASK_ALL;
+    v.select = 0;
+    std::memcpy(v.bg, cam.bg, sizeof(v.bg));
+}
+
+a3fr_status a3fr_render_full(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_cams,
+                             float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (!cams || n_cams < 1 || n_cams > kMaxEyes) return fail(c, A3FR_EINVAL, "n_cams must be in [1, 16]");
+    if (!out) return fail(c, A3FR_EINVAL, "out_dev is NULL");
+    std::vector<a3fr_view> v(n_cams);
+    for (int e = 0; e < n_cams; ++e) view_from_camera(cams[e], e, v[e]);
+    TRY(a3fr_preprocess(c, scene, v.data(), n_cams, 1, 1));
+    TRY(a3fr_bin_sort(c, nullptr));
+    return a3fr_blend(c, out, nullptr, nullptr);
+}
+
+a3fr_status a3fr_make_foveated_views(const a3fr_camera *cams, const a3fr_gaze *gaze, int32_t n_eyes,
+                                     const a3fr_fovea *f, a3fr_view *out) {
+    if (!cams || !gaze || !f || !out || n_eyes < 1 || n_eyes > kMaxEyes) return A3FR_EINVAL;
+    if (f->scale_mid < 1 || f->scale_periph < 1 || !(f->r_fovea >= 0.0) || !(f->r_mid >= f->r_fovea) ||
+        !is_fin(f->r_mid) || !is_fin(f->margin) || f->keep_den <= 0 || f->keep_num < 0 || f->keep_num > f->keep_den)
+        return A3FR_EINVAL;
+    const int scales[3] = {1, f->scale_mid, f->scale_periph};
+    for (int e = 0; e < n_eyes; ++e) {
+        for (int l = 0; l < 3; ++l) {
+            const double s = (double)scales[l];
+            a3fr_view &v = out[3 * e + l];
+            view_from_camera(cams[e], e, v);
+            v.fx = cams[e].fx / s; v.fy = cams[e].fy / s;
+            v.cx = cams[e].cx / s; v.cy = cams[e].cy / s;
+            v.width = cams[e].width / scales[l];
+            v.height = cams[e].height / scales[l];
+            v.gx = gaze[e].x / s; v.gy = gaze[e].y / s;
+            if (l == 0) {
+                v.mask = A3FR_MASK_DISC;
+                v.r_out = f->r_fovea / s;
+            } else if (l == 1) {
+                v.mask = A3FR_MASK_ANNULUS;
+                v.r_in = f->r_fovea / s - f->margin;
+                v.r_out = f->r_mid / s + f->margin;
+            } else {
+                v.select = 1;
+            }
+        }
+    }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_composite(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, const a3fr_fovea *f, const float *fov,
+                           const float *mid, const float *per, const float *per_full, float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (!f || W <= 0 || H <= 0 || !fov || !mid || !out || (!per && !per_full))
+        return fail(c, A3FR_EINVAL, "composite: bad arguments");
+    if (f->scale_mid < 1 || f->scale_periph < 1 || W / f->scale_mid < 1 || H / f->scale_mid < 1 ||
+        W / f->scale_periph < 1 || H / f->scale_periph < 1)
+        return fail(c, A3FR_EINVAL, "composite: layer scales too large for the image");
+    launch_composite(W, H, g.x, g.y, f->r_fovea, f->r_mid, fov, mid, f->scale_mid, per, f->scale_periph, per_full,
+                     out, c->stream);
+    return check_launch(c, "composite");
+}
+
+a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams,
+                                 const a3fr_gaze *gaze, int32_t n_eyes, const a3fr_fovea *f, float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (!cams || !gaze || !f || !out || n_eyes < 1 || n_eyes > kMaxEyes)
+        return fail(c, A3FR_EINVAL, "render_foveated: bad arguments");
+    std::vector<a3fr_view> v(3 * n_eyes);
+    if (a3fr_make_foveated_views(cams, gaze, n_eyes, f, v.data()) != A3FR_OK)
+        return fail(c, A3FR_EINVAL, "render_foveated: bad fovea parameters");
+    TRY(a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den));
+    TRY(a3fr_bin_sort(c, nullptr));
+    TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
+    float *L = P<float>(c->layers);
+    TRY(a3fr_blend(c, L, nullptr, nullptr));
+    for (int e = 0; e < n_eyes; ++e) {
+        const DevView &d0 = c->hviews[3 * e], &d1 = c->hviews[3 * e + 1], &d2 = c->hviews[3 * e + 2];
+        const int W = cams[e].width, H = cams[e].height;
+        TRY(a3fr_composite(c, W, H, gaze[e], f, L + 3 * d0.img_off, L + 3 * d1.img_off, L + 3 * d2.img_off, nullptr,
+                           out + (int64_t)e * 3 * W * H));
+    }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, double rf, double rm, const float *a,
+                            const float *b, double *sse3, int64_t *count3) {
+    if (!c) return A3FR_EINVAL;
+    if (W <= 0 || H <= 0 || !a || !b || !sse3 || !count3) return fail(c, A3FR_EINVAL, "region_sse: bad arguments");
+    const int nblk = 1024;
+    TRY(ensure(c, c->sse_part, sizeof(double) * 3 * nblk));
+    TRY(ensure(c, c->sse_cnt, sizeof(unsigned long long) * 3 * nblk));
+    launch_region_sse(W, H, g.x, g.y, rf, rm, a, b, P<double>(c->sse_part), P<unsigned long long>(c->sse_cnt), nblk,
+                      c->stream);
+    TRY(check_launch(c, "region_sse"));
+    std::vector<double> part(3 * nblk);
+    std::vector<unsigned long long> cnt(3 * nblk);
+    HIPCHECK(c, hipMemcpyAsync(part.data(), c->sse_part.p, sizeof(double) * 3 * nblk, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(cnt.data(), c->sse_cnt.p, sizeof(unsigned long long) * 3 * nblk, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        int64_t k = 0;
+        for (int j = 0; j < nblk; ++j) { s += part[3 * j + r]; k += (int64_t)cnt[3 * j + r]; }
+        sse3[r] = s;
+        count3[r] = k;
+    }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
+    if (!c || !out) return A3FR_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->n_keys = c->K;
+    out->n_tiles = c->ntiles;
+    if (!c->preprocessed) return A3FR_OK;
+    std::vector<uint8_t> act(c->ntiles > 0 ? c->ntiles : 1);
+    HIPCHECK(c, hipMemcpyAsync(act.data(), c->active.p, (size_t)c->ntiles, hipMemcpyDeviceToHost, c->stream));
+    // SelState (bin.hip): {n_vis, k, k_rem, done, mode, npass, pad[2], digit[12]} = 20 words per slot
+    constexpr int kSelWords = 20;
+    std::vector<uint32_t> st((size_t)c->nsel * kSelWords + 1);
+    if (c->nsel)
+        HIPCHECK(c, hipMemcpyAsync(st.data(), P<uint32_t>(c->sel) + (size_t)c->nsel * 12 * 256,
+                                   sizeof(uint32_t) * kSelWords * c->nsel, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (int64_t t = 0; t < c->ntiles; ++t) out->n_active_tiles += act[t];
+    for (int s = 0; s < c->nsel; ++s) {
+        const int v = c->hsel_views[s];
+        if (v < 16) out->n_kept[v] = st[(size_t)kSelWords * s + 1];  // SelState.k
+    }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_bytes, int64_t *bytes_out) {
+    if (!c) return A3FR_EINVAL;
+    const int64_t m = (int64_t)c->nv * c->n;
+    const void *src = nullptr;
+    int64_t bytes = 0;
+    bool need_sort = false;
+    switch (which) {
+        case A3FR_BUF_COUNTS: src = c->counts.p; bytes = 4 * m; break;
+        case A3FR_BUF_DEPTH: src = c->depth.p; bytes = 4 * m; break;
+        case A3FR_BUF_RECT: src = c->rect.p; bytes = 8 * m; break;
+        case A3FR_BUF_OFFSETS: src = c->offsets.p; bytes = 4 * (m + 1); break;
+        case A3FR_BUF_KEYS:
+        case A3FR_BUF_VALS:
+            if (!c->keep_emission) return fail(c, A3FR_ENOTREADY, "emission order kept only with a3fr_set_debug(ctx, 1)");
+            src = which == A3FR_BUF_KEYS ? c->keys_e.p : c->vals_e.p;
+            bytes = (which == A3FR_BUF_KEYS ? 8 : 4) * c->K;
+            need_sort = true;
+            break;
+        case A3FR_BUF_SORTED_KEYS: src = sorted_keys(c); bytes = 8 * c->K; need_sort = true; break;
+        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * c->K; need_sort = true; break;
+        case A3FR_BUF_RANGES: src = c->ranges.p; bytes = 8 * c->ntiles; need_sort = true; break;
+        case A3FR_BUF_ACTIVE: src = c->active.p; bytes = c->ntiles; break;
+        case A3FR_BUF_KEEP: src = c->keep.p; bytes = c->nsel ? m : 0; break;
+        case A3FR_BUF_RECORDS: src = c->rec.p; bytes = (int64_t)sizeof(Record) * m; break;
+        default: return fail(c, A3FR_EINVAL, "unknown buffer");
+    }
+    if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "nothing preprocessed");
+    if (need_sort && !c->sorted) return fail(c, A3FR_ENOTREADY, "keys not sorted yet");
+    if (bytes_out) *bytes_out = bytes;
+    if (!dst || bytes == 0) return A3FR_OK;
+    if (bytes > max_bytes) return fail(c, A3FR_EINVAL, "destination too small");
+    HIPCHECK(c, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, c->stream));
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_fp64_probe(a3fr_ctx *c, const double *x, const double *y, double *sq, double *dv, int64_t n) {
+    if (!c) return A3FR_EINVAL;
+    if (n < 0 || (n > 0 && (!x || !y || !sq || !dv))) return fail(c, A3FR_EINVAL, "fp64_probe: bad arguments");
+    launch_fp64_probe(x, y, sq, dv, n, c->stream);
+    return check_launch(c, "fp64_probe");
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+// Rasterization stage (paper Sec. 2.3: the colour of a pixel is the
+// front-to-back volume-rendering sum over the depth-sorted ellipses of its
+// tile), the foveated composite (Sec. 2.2: full detail at the gaze, coarser
+// around it), and the quality judge.
+//
+// Blend mapping on CDNA (wave64): one wavefront per 16x16 tile, each lane
+// owns four horizontally adjacent pixels of one row (so the row-dependent
+// terms of the quadratic form are computed once per Gaussian per lane).  The
+// tile's depth-sorted list is consumed in batches of 64: each lane gathers one
+// 48-byte record, converts its centre to tile-relative float32 (exact enough
+// at any image size because the record keeps the centre in float64) and puts
+// it in LDS; then every lane walks the batch with broadcast LDS reads.  The
+// wave stops as soon as a ballot finds no live pixel.
+#include "a3fr_internal.h"
+
+namespace a3fr {
+
+constexpr int kBatch = 64;
+
+__global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,
+                                              const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges,
+                                              const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                              int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
+                                              uint32_t *__restrict__ lastout) {
+    const int64_t gt = blockIdx.x;
+    if (!active[gt]) return;
+    // view of this tile: views are ordered by tile offset
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    const DevView &dv = views[lo];
+    const int64_t lt = gt - dv.tile_off;
+    const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
+    const int W = dv.v.width, H = dv.v.height;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int lane = threadIdx.x;
+    const int py = lane >> 2, px0 = (lane & 3) * 4;
+    const float fy = (float)py + 0.5f;
+    float fxq[4];
+    bool alive[4];
+    float T[4], Cr[4], Cg[4], Cb[4];
+    uint32_t last[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fxq[q] = (float)(px0 + q) + 0.5f;
+        alive[q] = (x0 + px0 + q < W) && (y0 + py < H);
+        T[q] = 1.0f; Cr[q] = Cg[q] = Cb[q] = 0.0f; last[q] = 0;
+    }
+    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    const Record *R = rec + (int64_t)lo * n;
+    __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
+    __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
+    const double dx0 = (double)x0, dy0 = (double)y0;
+
+    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+        if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
+        const uint32_t j = b0 + lane;
+        if (j < end) {
+            const Record r = R[vals[j]];
+            s_u[lane] = (float)(r.u - dx0);
+            s_v[lane] = (float)(r.v - dy0);
+            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
+            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
+        }
+        __syncthreads();
+        const uint32_t cnt = (end - b0) < (uint32_t)kBatch ? (end - b0) : (uint32_t)kBatch;
+        for (uint32_t jj = 0; jj < cnt; ++jj) {
+            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+            const float dy = fy - mv;
+            const float kdy = kk * dy;
+            const float cdy = c2 * dy * dy;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float t = (fxq[q] - mu) + kdy;
+                const float e = fmaf(a2, t * t, cdy);
+                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
+                if (alive[q] && al >= kAlphaMin) {
+                    const float Tn = T[q] * (1.0f - al);
+                    if (Tn < kTMin) {
+                        alive[q] = false;
+                    } else {
+                        const float wgt = al * T[q];
+                        Cr[q] = fmaf(wgt, s_r[jj], Cr[q]);
+                        Cg[q] = fmaf(wgt, s_g[jj], Cg[q]);
+                        Cb[q] = fmaf(wgt, s_b[jj], Cb[q]);
+                        T[q] = Tn;
+                        last[q] = b0 - start + jj + 1;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t HW = (int64_t)W * H;
+    float *img = rgb + 3 * dv.img_off;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = x0 + px0 + q, y = y0 + py;
+        if (x < W && y < H) {
+            const int64_t pix = (int64_t)y * W + x;
+            img[pix] = Cr[q] + T[q] * dv.v.bg[0];
+            img[HW + pix] = Cg[q] + T[q] * dv.v.bg[1];
+            img[2 * HW + pix] = Cb[q] + T[q] * dv.v.bg[2];
+            if (Tout) Tout[dv.img_off + pix] = T[q];
+            if (lastout) lastout[dv.img_off + pix] = last[q];
+        }
+    }
+}
+
+void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
+                  const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
+                  hipStream_t s) {
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals, rec, n, rgb,
+                       T, last);
+}
+
+// ------------------------------------------------------------------------
+// composite
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int region_of(int x, int y, double gx, double gy, double rf, double rm) {
+    const double dx = ((double)x + 0.5) - gx, dy = ((double)y + 0.5) - gy;
+    const double r2 = dx * dx + dy * dy;
+    if (r2 <= rf * rf) return 0;
+    if (r2 <= rm * rm) return 1;
+    return 2;
+}
+
+// bilinear, align_corners = false, clamp to edge; sx = (x + 0.5)/s - 0.5
+__device__ __forceinline__ void bilinear_setup(int x, int s, int Wl, int &i0, int &i1, float &w) {
+    float sx = ((float)x + 0.5f) / (float)s - 0.5f;
+    sx = fminf(fmaxf(sx, 0.0f), (float)(Wl - 1));
+    const float f = floorf(sx);
+    i0 = (int)f;
+    i1 = i0 + 1 < Wl ? i0 + 1 : Wl - 1;
+    w = sx - f;
+}
+
+__global__ void k_composite(int W, int H, double gx, double gy, double rf, double rm,
+                            const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
+                            const float *__restrict__ periph, int sp, const float *__restrict__ periph_full,
+                            float *__restrict__ out) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= W) return;
+    const int64_t HW = (int64_t)W * H, pix = (int64_t)y * W + x;
+    const int reg = region_of(x, y, gx, gy, rf, rm);
+    if (reg == 0) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = fovea[ch * HW + pix];
+        return;
+    }
+    if (reg == 2 && periph_full) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = periph_full[ch * HW + pix];
+        return;
+    }
+    const int s = reg == 1 ? sm : sp;
+    const float *src = reg == 1 ? mid : periph;
+    const int Wl = W / s, Hl = H / s;
+    int xa, xb, ya, yb;
+    float wx, wy;
+    bilinear_setup(x, s, Wl, xa, xb, wx);
+    bilinear_setup(y, s, Hl, ya, yb, wy);
+    const int64_t HWl = (int64_t)Wl * Hl;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float *p = src + ch * HWl;
+        const float top = (1.0f - wx) * p[(int64_t)ya * Wl + xa] + wx * p[(int64_t)ya * Wl + xb];
+        const float bot = (1.0f - wx) * p[(int64_t)yb * Wl + xa] + wx * p[(int64_t)yb * Wl + xb];
+        out[ch * HW + pix] = (1.0f - wy) * top + wy * bot;
+    }
+}
+
+void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
+                      const float *mid, int sm, const float *periph, int sp, const float *periph_full,
+                      float *out, hipStream_t s) {
+    if (W <= 0 || H <= 0) return;
+    hipLaunchKernelGGL(k_composite, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, W, H, gx, gy,
+                       rf, rm, fovea, mid, sm, periph, sp, periph_full, out);
+}
+
+// ------------------------------------------------------------------------
+// region squared error (quality judge)
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_region_sse(int W, int H, double gx, double gy, double rf, double rm,
+                                                    const float *__restrict__ a, const float *__restrict__ b,
+                                                    double *partial, unsigned long long *cnt) {
+    const int64_t HW = (int64_t)W * H;
+    double acc[3] = {0.0, 0.0, 0.0};
+    unsigned long long c[3] = {0, 0, 0};
+    for (int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pix < HW;
+         pix += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(pix % W), y = (int)(pix / W);
+        const int reg = region_of(x, y, gx, gy, rf, rm);
+        double s = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const double u = fmin(fmax((double)a[ch * HW + pix], 0.0), 1.0);
+            const double v = fmin(fmax((double)b[ch * HW + pix], 0.0), 1.0);
+            s += (u - v) * (u - v);
+        }
+        acc[0] += reg == 0 ? s : 0.0; acc[1] += reg == 1 ? s : 0.0; acc[2] += reg == 2 ? s : 0.0;
+        c[reg] += 1;
+    }
+    __shared__ double sa[3][256];
+    __shared__ unsigned long long sc[3][256];
+    for (int r = 0; r < 3; ++r) { sa[r][threadIdx.x] = acc[r]; sc[r][threadIdx.x] = c[r]; }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int r = 0; r < 3; ++r) {
+                sa[r][threadIdx.x] += sa[r][threadIdx.x + off];
+                sc[r][threadIdx.x] += sc[r][threadIdx.x + off];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int r = 0; r < 3; ++r) { partial[3 * blockIdx.x + r] = sa[r][0]; cnt[3 * blockIdx.x + r] = sc[r][0]; }
+}
+
+void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm, const float *a, const float *b,
+                       double *partial, unsigned long long *cnt, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_region_sse, dim3((unsigned)nblk), dim3(256), 0, s, W, H, gx, gy, rf, rm, a, b, partial, cnt);
+}
+
+// ------------------------------------------------------------------------
+// float64 self-check
+// ------------------------------------------------------------------------
+__global__ void k_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    sq[i] = sqrt(x[i]);
+    dv[i] = x[i] / y[i];
+}
+
+void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fp64_probe, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, sq, dv, n);
+}
+
+}  // namespace a3fr

@@ -1,0 +1,259 @@
+// Projection stage of 3D Gaussian Splatting (paper Sec. 2.3: every ellipsoid
+// is projected to a screen ellipse and the tiles it intersects are found), run
+// once per frame for every layer of every eye so that later stages reuse it
+// (Sec. 3.5).  One thread per Gaussian: the scene is read once (236 B per
+// Gaussian, coalesced structure-of-arrays loads) and serves all views.
+//
+// The integer outputs (tile rectangle, active-tile count, depth key, periphery
+// score bits) come from a float64 "key path" whose every operation is written
+// out below in a fixed order: explicit fma() for each product-sum, IEEE
+// division and square root, no contraction (the library is compiled with
+// -ffp-contract=off).  The same sequence, evaluated in float64 anywhere,
+// yields the same bits.
+#include "a3fr_internal.h"
+
+namespace a3fr {
+
+// ------------------------------------------------------------------------
+// active-tile masks
+// ------------------------------------------------------------------------
+__device__ __forceinline__ bool tile_active(const a3fr_view &v, int tx, int ty) {
+    if (v.mask == A3FR_MASK_ALL) return true;
+    int xe = (tx + 1) * kTile; if (xe > v.width) xe = v.width;
+    int ye = (ty + 1) * kTile; if (ye > v.height) ye = v.height;
+    double x0 = (double)(tx * kTile) + 0.5, x1 = (double)xe - 0.5;
+    double y0 = (double)(ty * kTile) + 0.5, y1 = (double)ye - 0.5;
+    double ddx = fmax(fmax(x0 - v.gx, v.gx - x1), 0.0);
+    double ddy = fmax(fmax(y0 - v.gy, v.gy - y1), 0.0);
+    double d2 = ddx * ddx + ddy * ddy;
+    if (!(d2 <= v.r_out * v.r_out)) return false;
+    if (v.mask == A3FR_MASK_ANNULUS && v.r_in > 0.0) {
+        double ri2 = v.r_in * v.r_in;
+        double ax = x0 - v.gx, bx = x1 - v.gx, ay = y0 - v.gy, by = y1 - v.gy;
+        bool inside = (ax * ax + ay * ay <= ri2) && (bx * bx + ay * ay <= ri2) &&
+                      (ax * ax + by * by <= ri2) && (bx * bx + by * by <= ri2);
+        if (inside) return false;
+    }
+    return true;
+}
+
+// One thread per tile row of every view: active flags, and for masked views a
+// row prefix count (row_prefix[x] = active tiles in columns < x) and the
+// columns of the row's active tiles in order (row_list).
+__global__ void k_tile_masks(const DevView *views, int64_t rows_total, const int32_t *row_view,
+                             const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_total) return;
+    const DevView &dv = views[row_view[r]];
+    int ty = row_y[r];
+    int TX = dv.tiles_x;
+    uint8_t *act = active + dv.tile_off + (int64_t)ty * TX;
+    if (dv.v.mask == A3FR_MASK_ALL) {
+        for (int tx = 0; tx < TX; ++tx) act[tx] = 1;
+        return;
+    }
+    uint16_t *pre = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
+    uint16_t *lst = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
+    int c = 0;
+    for (int tx = 0; tx < TX; ++tx) {
+        pre[tx] = (uint16_t)c;
+        bool a = tile_active(dv.v, tx, ty);
+        act[tx] = a ? 1 : 0;
+        if (a) lst[c++] = (uint16_t)tx;
+    }
+    pre[TX] = (uint16_t)c;
+}
+
+void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
+                       const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
+                       hipStream_t s) {
+    (void)nv;
+    if (rows_total == 0) return;
+    int blk = 128;
+    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((rows_total + blk - 1) / blk)), dim3(blk), 0, s, views,
+                       rows_total, row_view, row_y, row_prefix, row_list, active);
+}
+
+// ------------------------------------------------------------------------
+// key path
+// ------------------------------------------------------------------------
+struct Cov3 { double s00, s01, s02, s11, s12, s22; };
+
+// Sigma3D = (R(q) S)(R(q) S)^T for the normalised quaternion q = (w,x,y,z).
+__device__ __forceinline__ bool gaussian_cov3(double qw, double qx, double qy, double qz, double s0, double s1,
+                                              double s2, Cov3 &S) {
+    double nq = sqrt(fma(qw, qw, fma(qx, qx, fma(qy, qy, qz * qz))));
+    if (!(nq > 0.0)) return false;
+    double w = qw / nq, x = qx / nq, y = qy / nq, z = qz / nq;
+    double xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    double wx = w * x, wy = w * y, wz = w * z;
+    // rotation of the unit quaternion, row-major, times diag(s) column-wise
+    double m00 = (1.0 - 2.0 * (yy + zz)) * s0, m01 = (2.0 * (xy - wz)) * s1, m02 = (2.0 * (xz + wy)) * s2;
+    double m10 = (2.0 * (xy + wz)) * s0, m11 = (1.0 - 2.0 * (xx + zz)) * s1, m12 = (2.0 * (yz - wx)) * s2;
+    double m20 = (2.0 * (xz - wy)) * s0, m21 = (2.0 * (yz + wx)) * s1, m22 = (1.0 - 2.0 * (xx + yy)) * s2;
+    S.s00 = fma(m00, m00, fma(m01, m01, m02 * m02));
+    S.s01 = fma(m00, m10, fma(m01, m11, m02 * m12));
+    S.s02 = fma(m00, m20, fma(m01, m21, m02 * m22));
+    S.s11 = fma(m10, m10, fma(m11, m11, m12 * m12));
+    S.s12 = fma(m10, m20, fma(m11, m21, m12 * m22));
+    S.s22 = fma(m20, m20, fma(m21, m21, m22 * m22));
+    return true;
+}
+
+// Sigma_view = Rw Sigma3D Rw^T, evaluated as A = Rw Sigma3D, then A Rw^T.
+__device__ __forceinline__ void view_cov(const double *Rw, const Cov3 &S, Cov3 &V) {
+    const double Sm[9] = {S.s00, S.s01, S.s02, S.s01, S.s11, S.s12, S.s02, S.s12, S.s22};
+    double A[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            A[3 * r + c] = fma(Rw[3 * r + 0], Sm[0 * 3 + c], fma(Rw[3 * r + 1], Sm[1 * 3 + c], Rw[3 * r + 2] * Sm[2 * 3 + c]));
+    auto e = [&](int r, int c) {
+        return fma(A[3 * r + 0], Rw[3 * c + 0], fma(A[3 * r + 1], Rw[3 * c + 1], A[3 * r + 2] * Rw[3 * c + 2]));
+    };
+    V.s00 = e(0, 0); V.s01 = e(0, 1); V.s02 = e(0, 2);
+    V.s11 = e(1, 1); V.s12 = e(1, 2); V.s22 = e(2, 2);
+}
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase, m = -l..l)
+// at unit direction (x, y, z); each constant is the closed-form normalisation
+// sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (x sqrt 2 for m != 0) of its polynomial.
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = 0.28209479177387814f;                    // 1/(2 sqrt(pi))
+    const float c1 = 0.4886025119029199f;           // sqrt(3/(4 pi))
+    Y[1] = -c1 * y; Y[2] = c1 * z; Y[3] = -c1 * x;
+    const float c2a = 1.0925484305920792f;          // sqrt(15/pi)/2
+    const float c2b = 0.31539156525252005f;         // sqrt(5/pi)/4
+    const float c2c = 0.5462742152960396f;          // sqrt(15/pi)/4
+    Y[4] = c2a * x * y; Y[5] = -c2a * y * z; Y[6] = c2b * (2.0f * zz - xx - yy);
+    Y[7] = -c2a * x * z; Y[8] = c2c * (xx - yy);
+    const float c3a = 0.5900435899266435f;          // sqrt(35/(2 pi))/4
+    const float c3b = 2.890611442640554f;           // sqrt(105/pi)/2
+    const float c3c = 0.4570457994644658f;          // sqrt(21/(2 pi))/4
+    const float c3d = 0.3731763325901154f;          // sqrt(7/pi)/4
+    const float c3e = 1.445305721320277f;           // sqrt(105/pi)/4
+    Y[9] = -c3a * y * (3.0f * xx - yy);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+    Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+    Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3.0f * yy);
+}
+
+__global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views, int nv,
+                                                    const uint16_t *__restrict__ row_prefix,
+                                                    uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
+                                                    uint64_t *__restrict__ rect, Record *__restrict__ rec,
+                                                    double *__restrict__ score) {
+    const int64_t n = sc.n;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
+    const float op = sc.opacity_dev[i];
+    Cov3 S;
+    bool qok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
+                             sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S);
+    const int nk = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+
+    int cur_eye = -1;
+    double p0 = 0, p1 = 0, p2 = 0;
+    Cov3 V = {0, 0, 0, 0, 0, 0};
+    float col[3] = {0.f, 0.f, 0.f};
+    for (int vi = 0; vi < nv; ++vi) {
+        const DevView &dv = views[vi];
+        const a3fr_view &v = dv.v;
+        const int64_t slot = (int64_t)vi * n + i;
+        if (v.eye != cur_eye) {
+            cur_eye = v.eye;
+            const double *Rw = v.R;
+            p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v.t[0])));
+            p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v.t[1])));
+            p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v.t[2])));
+            if (qok) view_cov(Rw, S, V);
+            // view-dependent colour of this eye, float32
+            float dx = (float)mx - (float)v.campos[0], dy = (float)my - (float)v.campos[1],
+                  dz = (float)mz - (float)v.campos[2];
+            float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            float Y[16];
+            sh_basis(dx * inv, dy * inv, dz * inv, Y);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
+                for (int k = 0; k < nk; ++k) acc = fmaf(Y[k], sc.sh_dev[((int64_t)k * 3 + ch) * n + i], acc);
+                col[ch] = fmaxf(acc, 0.0f);
+            }
+        }
+        uint32_t cnt = 0;
+        if (qok && p2 > kZNear) {
+            const double xz = p0 / p2, yz = p1 / p2;
+            const double limx = (1.3 * (0.5 * (double)v.width)) / v.fx;
+            const double limy = (1.3 * (0.5 * (double)v.height)) / v.fy;
+            const double txc = fmin(fmax(xz, -limx), limx);
+            const double tyc = fmin(fmax(yz, -limy), limy);
+            const double j00 = v.fx / p2, j02 = -(j00 * txc);
+            const double j11 = v.fy / p2, j12 = -(j11 * tyc);
+            const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
+                         B02 = fma(j00, V.s02, j02 * V.s22);
+            const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
+            const double a = fma(B00, j00, B02 * j02) + kDilate;
+            const double b = fma(B01, j11, B02 * j12);
+            const double c = fma(B11, j11, B12 * j12) + kDilate;
+            const double det = fma(a, c, -(b * b));
+            if (det > 0.0) {
+                const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
+                const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
+                const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
+                if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
+                    double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
+                    double fx1 = floor((hix - 0.5) / (double)kTile);
+                    double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
+                    double fy1 = floor((hiy - 0.5) / (double)kTile);
+                    fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
+                    fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
+                    if (fx0 <= fx1 && fy0 <= fy1) {
+                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+                        if (v.mask == A3FR_MASK_ALL) {
+                            cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+                        } else {
+                            const uint16_t *pre = row_prefix + dv.mask_off;
+                            for (int ty = y0; ty <= y1; ++ty) {
+                                const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+                                cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
+                            }
+                        }
+                        const float dz32 = (float)p2;
+                        depth[slot] = __float_as_uint(dz32);
+                        rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
+                                     ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
+                        if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
+                        const double kLog2e = 1.4426950408889634;
+                        Record R;
+                        R.u = u; R.v = w;
+                        R.a2 = (float)(-0.5 * kLog2e * (c / det));
+                        R.k = (float)(-b / c);
+                        R.c2 = (float)(-0.5 * kLog2e / c);
+                        R.o = op;
+                        R.r = col[0]; R.g = col[1]; R.b = col[2]; R.pad = 0.0f;
+                        rec[slot] = R;
+                    }
+                }
+            }
+        }
+        counts[slot] = cnt;
+    }
+}
+
+void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
+                       const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
+                       Record *rec, double *score, hipStream_t s) {
+    (void)eye_first;
+    if (sc.n == 0) return;
+    const int blk = 256;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk)), dim3(blk), 0, s, sc, views, nv,
+                       row_prefix, counts, depth, rect, rec, score);
+}
+
+}  // namespace a3fr
