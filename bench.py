@@ -1,0 +1,225 @@
+#!/usr/bin/env python
+"""Stereo frames/s of the gaze-tracked foveated 3DGS renderer on one MI355X.
+
+Workload: the foveated stereo frame -- 1,000,000 Gaussians drawn uniformly over
+[-5,5]^3 (log-scales N(-3,0.5), random unit quaternions, opacity sigmoid(N(0,1)),
+degree-3 SH coefficients N(0,0.3)), head at (0,0,-3) looking +z, two eyes 64 mm
+apart, 1832 x 1920 per eye, 60 degree horizontal FOV; foveal layer at full
+resolution within 0.15 W of the gaze (image centre), mid layer at 1/2 resolution
+to 0.35 W, periphery at 1/4 resolution over the whole frame drawing the top 30%
+of visible Gaussians by opacity x projected area; composited to full resolution.
+One step = one whole stereo frame through the C ABI (preprocess, periphery
+select, scan, key emission, radix sort, ranges, blend, composite), scene
+resident in HBM, output [2][3][1920][1832] float32 in HBM.
+
+The plain full-resolution render (FRR) of the same frame is timed in the same
+process, and the periphery PSNR of the foveated frame against it is reported.
+A second timed pass with per-stage HIP events gives the roofline of the
+dominant kernel; the FP64 CPU oracle is timed on the host as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stereo frames/s @1M Gaussians, foveated vs full-res on GPU, periphery PSNR≥30dB"
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
+FP32_VECTOR_PEAK_TF = 157.3   # MI355X FP32 vector (packed) peak
+SORT_BYTES_PER_KEY_PASS = 24  # read key (8) + value (4), write key (8) + value (4)
+BLEND_FLOPS_PER_PAIR = 18
+PREPROCESS_READ_PER_GAUSSIAN = 236
+PREPROCESS_WRITE_PER_VISIBLE = 64  # record 48 + depth 4 + rect 8 + count 4
+PREPROCESS_WRITE_COUNT = 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--gaussians", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=2, help="oracle frames timed for the CPU baseline")
+    ap.add_argument("--only", choices=["both", "foveated", "full"], default="both",
+                    help="restrict the timed loops (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the renderer has no multi-GPU path; "
+              "see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_04147_amd as pkg
+    import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    scene, cams = synth.foveated_stereo(n=args.gaussians)
+    W, H = cams[0].width, cams[0].height
+    gaze = [(c.cx, c.cy) for c in cams]
+    rad = (synth.FOVEA_FRACTIONS[0] * W, synth.FOVEA_FRACTIONS[1] * W)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad, keep=synth.PERIPH_KEEP)
+    ctx = pkg.Context()
+    out_f = torch.empty((2, 3, H, W), device="cuda")
+    out_r = torch.empty((2, 3, H, W), device="cuda")
+    log(f"scene ready in {time.time() - t0:.1f}s: {scene.n} Gaussians, {W}x{H} per eye")
+
+    def step_fov():
+        ctx.render_foveated(ds, cams, gaze, fov, out_f)
+
+    def step_frr():
+        ctx.render_full(ds, cams, out_r)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1000.0 / steps
+
+    do_fov = args.only in ("both", "foveated")
+    do_frr = args.only in ("both", "full")
+    for _ in range(args.warmup):
+        if do_fov:
+            step_fov()
+        if do_frr:
+            step_frr()
+    torch.cuda.synchronize()
+    log("warmup done")
+    ms_f = timed(step_fov, args.steps) if do_fov else float("nan")
+    ms_r = timed(step_frr, args.steps) if do_frr else float("nan")
+    log(f"foveated {ms_f:.3f} ms/frame, full-res {ms_r:.3f} ms/frame")
+
+    # quality of the foveated frame against the full-resolution render
+    psnr = []
+    psnr_outer = []
+    if do_fov and do_frr:
+        step_fov()
+        step_frr()
+        for e in range(2):
+            sse, cnt = ctx.region_sse(W, H, gaze[e], rad[0], rad[1], out_f[e], out_r[e])
+            n_out = cnt[1] + cnt[2]
+            mse = (sse[1] + sse[2]) / (3.0 * n_out)
+            psnr.append(math.inf if mse == 0 else 10 * math.log10(1.0 / mse))
+            mo = sse[2] / (3.0 * cnt[2])
+            psnr_outer.append(math.inf if mo == 0 else 10 * math.log10(1.0 / mo))
+
+    # per-stage event timing over a second timed pass (roofline)
+    stages = {}
+    roofline = None
+    counts = {}
+    if do_fov:
+        ctx.set_profiling(True)
+        ms_f_prof = timed(step_fov, args.steps)
+        prof = ctx.get_profile()
+        ctx.set_profiling(False)
+        counts = ctx.get_counts()
+        K = prof["sort_keys"] / max(1, args.steps)
+        n_vis_views = None
+        st = prof["stages"]
+        for name, v in st.items():
+            if v["launches"]:
+                stages[name] = dict(ms_per_frame=v["ms"] / args.steps, launches_per_frame=v["launches"] / args.steps,
+                                    ms_per_launch=v["ms"] / v["launches"])
+        # sort pass: bytes per launch = 24 B x keys
+        sp = st["sort_pass"]
+        if sp["launches"]:
+            per_launch_s = sp["ms"] / sp["launches"] / 1000.0
+            gbs = SORT_BYTES_PER_KEY_PASS * K / per_launch_s / 1e9
+            stages["sort_pass"].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                       bytes_per_launch=SORT_BYTES_PER_KEY_PASS * K)
+        bl = st["blend"]
+        pairs = prof["blend_pairs"] / args.steps
+        if bl["launches"]:
+            per_launch_s = bl["ms"] / bl["launches"] / 1000.0
+            tf = BLEND_FLOPS_PER_PAIR * pairs / per_launch_s / 1e12
+            stages["blend"].update(bound="alu", achieved_TFLOPs=tf, frac=tf / FP32_VECTOR_PEAK_TF,
+                                   pairs_per_launch=pairs)
+        pp = st["preprocess"]
+        if pp["launches"]:
+            cnt = ctx.inspect("counts", torch.int32)
+            nvis = int((cnt != 0).sum().item())
+            bytes_pp = PREPROCESS_READ_PER_GAUSSIAN * scene.n + PREPROCESS_WRITE_COUNT * cnt.numel() + \
+                PREPROCESS_WRITE_PER_VISIBLE * nvis
+            per_launch_s = pp["ms"] / pp["launches"] / 1000.0
+            gbs = bytes_pp / per_launch_s / 1e9
+            stages["preprocess"].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                        bytes_per_launch=bytes_pp)
+        # dominant kernel: the stage with the most time per frame among sort pass / blend / preprocess
+        cand = [s for s in ("sort_pass", "blend", "preprocess") if s in stages]
+        dom = max(cand, key=lambda s: stages[s]["ms_per_frame"])
+        d = stages[dom]
+        if d["bound"] == "hbm":
+            roofline = dict(kernel=dom, bound="hbm", achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=d["frac"], traffic=None, ms_per_launch=d["ms_per_launch"])
+        else:
+            roofline = dict(kernel=dom, bound="alu", achieved=d["achieved_TFLOPs"], peak=FP32_VECTOR_PEAK_TF,
+                            unit="TFLOP/s", frac=d["frac"], traffic=None, ms_per_launch=d["ms_per_launch"])
+        log(f"profiled pass {ms_f_prof:.3f} ms/frame; stages: " +
+            ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
+
+    cpu = None
+    if not args.no_cpu_baseline and do_fov:
+        import oracle
+        times = []
+        for _ in range(max(1, args.cpu_frames)):
+            t = time.perf_counter()
+            oracle.render_foveated(scene, cams, gaze, rad)
+            times.append(time.perf_counter() - t)
+        med = statistics.median(times)
+        cpu = dict(value=1.0 / med, unit="stereo frames/s", cores=oracle.default_threads(), kind="oracle",
+                   sample=f"{len(times)} whole foveated stereo frames of the same workload (FP64 oracle, "
+                          f"median {med:.2f} s/frame, {oracle.default_threads()} threads)")
+        log(f"cpu oracle {med:.2f} s/frame")
+
+    res = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_f if do_fov else None,
+        "unit": "stereo frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_f,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "foveated stereo frame: 1M-Gaussian uniform cloud over [-5,5]^3, 2 eyes x 1832x1920, "
+                        "fovea r=0.15W full res, mid r=0.35W at 1/2, periphery at 1/4 with top-30% subset",
+            "gaussians": scene.n, "width": W, "height": H, "eyes": 2, "gaze": "image centre",
+            "key_path": "f64", "blend": "f32",
+        },
+        "full_res_fps": 1000.0 / ms_r if do_frr else None,
+        "full_res_ms": ms_r,
+        "speedup_vs_full_res": (ms_r / ms_f) if (do_fov and do_frr) else None,
+        "periphery_psnr_db": min(psnr) if psnr else None,
+        "periphery_psnr_db_per_eye": psnr,
+        "outer_psnr_db_per_eye": psnr_outer,
+        "keys_foveated": counts.get("n_keys"),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages": stages,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

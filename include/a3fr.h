@@ -220,6 +220,38 @@ a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze,
 /* Counters of the last preprocess / bin_sort (host struct). */
 a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
 
+/* ---- per-stage timing (HIP events on the context's stream) -------------- */
+typedef enum {
+    A3FR_STAGE_MASKS = 0,      /* active-tile masks */
+    A3FR_STAGE_PREPROCESS = 1, /* projection, colour, counts */
+    A3FR_STAGE_SELECT = 2,     /* periphery radix select */
+    A3FR_STAGE_SCAN = 3,       /* key-count scan */
+    A3FR_STAGE_EMIT = 4,       /* key emission */
+    A3FR_STAGE_SORT_HIST = 5,  /* digit histograms of the radix sort */
+    A3FR_STAGE_SORT_PASS = 6,  /* one onesweep pass (one launch per 8-bit digit) */
+    A3FR_STAGE_RANGES = 7,     /* tile ranges */
+    A3FR_STAGE_BLEND = 8,      /* front-to-back blend */
+    A3FR_STAGE_COMPOSITE = 9,  /* foveated composite */
+    A3FR_STAGE_COUNT = 10
+} a3fr_stage;
+
+typedef struct {
+    int64_t launches[A3FR_STAGE_COUNT]; /* timed intervals per stage */
+    double ms[A3FR_STAGE_COUNT];        /* summed event time per stage */
+    int64_t sort_keys;                  /* keys sorted, summed over the timed bin_sorts */
+    int64_t sort_passes;                /* onesweep passes, summed */
+    int64_t blend_pairs;                /* evaluated (pixel, Gaussian) pairs of the timed blends */
+} a3fr_profile;
+
+/* Turn per-stage event timing on or off (off by default; each timed interval
+ * adds two event records to the stream, and blends also count their evaluated
+ * (pixel, Gaussian) pairs: every list entry a pixel evaluates while it has not
+ * stopped, the stopping one included). */
+a3fr_status a3fr_set_profiling(a3fr_ctx *ctx, int32_t enable);
+/* Synchronises, returns the per-stage totals accumulated since the last call
+ * (or since profiling was enabled) and resets them. */
+a3fr_status a3fr_get_profile(a3fr_ctx *ctx, a3fr_profile *out);
+
 /* ---- inspection of buffered intermediates (tests and tools) -------------- */
 typedef enum {
     A3FR_BUF_COUNTS = 0,      /* uint32 [n_views][n] active tiles covered (before selection) */

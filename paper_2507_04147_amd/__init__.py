@@ -66,6 +66,14 @@ class Fovea_(C.Structure):
                 ("margin", C.c_double)]
 
 
+STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite"]
+
+
+class Profile_(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 10), ("ms", C.c_double * 10), ("sort_keys", C.c_int64),
+                ("sort_passes", C.c_int64), ("blend_pairs", C.c_int64)]
+
+
 class Counts_(C.Structure):
     _fields_ = [("n_keys", C.c_int64), ("n_kept", C.c_int64 * 16), ("n_tiles", C.c_int64),
                 ("n_active_tiles", C.c_int64)]
@@ -99,6 +107,8 @@ def lib():
         "a3fr_get_counts": [P, C.POINTER(Counts_)],
         "a3fr_inspect": [P, I32, P, I64, C.POINTER(I64)],
         "a3fr_fp64_probe": [P, P, P, P, P, I64],
+        "a3fr_set_profiling": [P, I32],
+        "a3fr_get_profile": [P, C.POINTER(Profile_)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -269,6 +279,15 @@ class Context:
         self._check(self._L.a3fr_inspect(self._h, BUF[which], _dp(out), out.numel() * esz, C.byref(nb)))
         return out[: nb.value // esz]
 
+    def set_profiling(self, enable=True):
+        self._check(self._L.a3fr_set_profiling(self._h, int(bool(enable))))
+
+    def get_profile(self):
+        p = Profile_()
+        self._check(self._L.a3fr_get_profile(self._h, C.byref(p)))
+        return dict(stages={STAGES[k]: dict(launches=int(p.launches[k]), ms=float(p.ms[k])) for k in range(10)},
+                    sort_keys=int(p.sort_keys), sort_passes=int(p.sort_passes), blend_pairs=int(p.blend_pairs))
+
     def fp64_probe(self, x, y):
         import torch
         sq, dv = torch.empty_like(x), torch.empty_like(x)
@@ -289,4 +308,4 @@ def make_foveated_views(cams, gazes, fovea: Fovea_):
 EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", "a3fr_sync", "a3fr_status_str",
             "a3fr_last_error", "a3fr_preprocess", "a3fr_bin_sort", "a3fr_blend", "a3fr_render_full",
             "a3fr_render_foveated", "a3fr_make_foveated_views", "a3fr_composite", "a3fr_region_sse",
-            "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe"]
+            "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe", "a3fr_set_profiling", "a3fr_get_profile"]

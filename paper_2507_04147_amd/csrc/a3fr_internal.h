@@ -71,13 +71,14 @@ void launch_emit(const DevView *views, int nv, int64_t n, const uint32_t *offset
                  const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  uint64_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s);
 int sort_passes_for_bits(int bits);
-void launch_radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b, int64_t K,
-                       int key_bits, uint32_t *hist /* [8][256] */, uint32_t *status, int64_t status_cap,
-                       uint32_t *counters /* [8] */, bool *result_in_b, hipStream_t s);
+void launch_sort_hist(const uint64_t *keys, int64_t K, int npass, uint32_t *hist /* [8][256] */, uint32_t *status,
+                      uint32_t *counters /* [16] */, hipStream_t s);
+void launch_sort_pass(const uint64_t *ki, const uint32_t *vi, uint64_t *ko, uint32_t *vo, int64_t K, int p,
+                      const uint32_t *hist, uint32_t *status, uint32_t *counters, hipStream_t s);
 void launch_ranges(const uint64_t *keys, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
 void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                   const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
-                  hipStream_t s);
+                  unsigned long long *pairs /* nullable: count evaluated pairs */, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
                       float *out, hipStream_t s);

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdint>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -49,6 +51,14 @@ struct a3fr_ctx {
     DevBuf layers, sse_part, sse_cnt;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
     bool keep_emission = false;
+    // per-stage event timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (stage, index of the start event)
+    int64_t prof_sort_keys = 0, prof_sort_passes = 0;
+    DevBuf pair_count;          // evaluated blend pairs while profiling
+    bool pairs_armed = false;
     // state
     bool preprocessed = false;
     bool sorted = false;
@@ -122,6 +132,36 @@ a3fr_status ensure_pinned(a3fr_ctx *c, size_t bytes) {
 }
 
 bool is_fin(double x) { return std::isfinite(x); }
+
+// Stage timing: a pair of events around each timed interval.
+a3fr_status stage_begin(a3fr_ctx *c, int stage, size_t *slot) {
+    *slot = SIZE_MAX;
+    if (!c->profiling) return A3FR_OK;
+    while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHECK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    *slot = c->ev_used;
+    c->ev_used += 2;
+    c->ev_marks.emplace_back(stage, *slot);
+    HIPCHECK(c, hipEventRecord(c->ev_pool[*slot], c->stream));
+    return A3FR_OK;
+}
+
+a3fr_status stage_end(a3fr_ctx *c, size_t slot) {
+    if (slot == SIZE_MAX) return A3FR_OK;
+    HIPCHECK(c, hipEventRecord(c->ev_pool[slot + 1], c->stream));
+    return A3FR_OK;
+}
+
+struct StageTimer {
+    a3fr_ctx *c;
+    size_t slot;
+    a3fr_status st;
+    StageTimer(a3fr_ctx *cc, int stage) : c(cc), slot(SIZE_MAX) { st = stage_begin(c, stage, &slot); }
+    ~StageTimer() { (void)stage_end(c, slot); }
+};
 
 a3fr_status check_scene(a3fr_ctx *c, const a3fr_scene *s) {
     if (!s) return fail(c, A3FR_EINVAL, "scene is NULL");
@@ -198,12 +238,13 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->sel, &c->offsets, &c->block_sums, &c->total, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->big_list, &c->big_count, &c->sort_hist,
                       &c->sort_status, &c->sort_counters, &c->ranges, &c->layers, &c->sse_part,
-                      &c->sse_cnt, &c->keys_e, &c->vals_e};
+                      &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->h_total) (void)hipHostFree(c->h_total);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -216,6 +257,40 @@ a3fr_status a3fr_set_stream(a3fr_ctx *c, void *hip_stream) {
 a3fr_status a3fr_set_debug(a3fr_ctx *c, int32_t keep_emission_order) {
     if (!c) return A3FR_EINVAL;
     c->keep_emission = keep_emission_order != 0;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_set_profiling(a3fr_ctx *c, int32_t enable) {
+    if (!c) return A3FR_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->profiling = enable != 0;
+    c->ev_used = 0;
+    c->ev_marks.clear();
+    c->prof_sort_keys = c->prof_sort_passes = 0;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_get_profile(a3fr_ctx *c, a3fr_profile *out) {
+    if (!c || !out) return A3FR_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (auto &m : c->ev_marks) {
+        float ms = 0.0f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
+        out->ms[m.first] += ms;
+        out->launches[m.first] += 1;
+    }
+    out->sort_keys = c->prof_sort_keys;
+    out->sort_passes = c->prof_sort_passes;
+    if (c->pairs_armed) {
+        unsigned long long pc = 0;
+        HIPCHECK(c, hipMemcpy(&pc, c->pair_count.p, sizeof(pc), hipMemcpyDeviceToHost));
+        out->blend_pairs = (int64_t)pc;
+        c->pairs_armed = false;
+    }
+    c->ev_used = 0;
+    c->ev_marks.clear();
+    c->prof_sort_keys = c->prof_sort_passes = 0;
     return A3FR_OK;
 }
 
@@ -328,16 +403,19 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
 
     // ---- kernels
     const DevView *dv = P<DevView>(c->views);
+    { StageTimer t_(c, A3FR_STAGE_MASKS);
     launch_tile_masks(dv, nv, c->rows_total, P<int32_t>(c->row_view), P<int32_t>(c->row_y),
-                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream);
+                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream); }
+    { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, nv, nullptr, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
-                      c->stream);
-    if (c->nsel)
+                      c->stream); }
+    if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
         launch_select(dv, nv, P<int32_t>(c->sel_views), c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
-                      keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream);
+                      keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream); }
+    { StageTimer t_(c, A3FR_STAGE_SCAN);
     launch_scan_counts(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->offsets),
-                       P<uint64_t>(c->block_sums), (m + 4095) / 4096 + 1, P<uint64_t>(c->total), c->stream);
+                       P<uint64_t>(c->block_sums), (m + 4095) / 4096 + 1, P<uint64_t>(c->total), c->stream); }
     TRY(check_launch(c, "preprocess"));
     c->preprocessed = true;
     return A3FR_OK;
@@ -371,23 +449,41 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     }
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
+    { StageTimer t_(c, A3FR_STAGE_EMIT);
     launch_emit(dv, c->nv, c->n, P<uint32_t>(c->offsets), P<uint32_t>(c->depth), P<uint64_t>(c->rect),
                 P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint64_t>(c->keys_a),
-                P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream);
+                P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream); }
     if (c->keep_emission) {
         TRY(ensure(c, c->keys_e, sizeof(uint64_t) * K));
         TRY(ensure(c, c->vals_e, sizeof(uint32_t) * K));
         HIPCHECK(c, hipMemcpyAsync(c->keys_e.p, c->keys_a.p, sizeof(uint64_t) * K, hipMemcpyDeviceToDevice, c->stream));
         HIPCHECK(c, hipMemcpyAsync(c->vals_e.p, c->vals_a.p, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, c->stream));
     }
+    {
+        StageTimer t_(c, A3FR_STAGE_SORT_HIST);
+        launch_sort_hist(P<uint64_t>(c->keys_a), (int64_t)K, npass, P<uint32_t>(c->sort_hist),
+                         P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
+    }
+    uint64_t *ki = P<uint64_t>(c->keys_a), *ko = P<uint64_t>(c->keys_b);
+    uint32_t *vi = P<uint32_t>(c->vals_a), *vo = P<uint32_t>(c->vals_b);
     bool in_b = false;
-    launch_radix_sort(P<uint64_t>(c->keys_a), P<uint32_t>(c->vals_a), P<uint64_t>(c->keys_b), P<uint32_t>(c->vals_b),
-                      (int64_t)K, key_bits, P<uint32_t>(c->sort_hist), P<uint32_t>(c->sort_status),
-                      (int64_t)npass * nparts * 256, P<uint32_t>(c->sort_counters), &in_b, c->stream);
+    if (K > 1) {
+        for (int p = 0; p < npass; ++p) {
+            StageTimer t_(c, A3FR_STAGE_SORT_PASS);
+            launch_sort_pass(ki, vi, ko, vo, (int64_t)K, p, P<uint32_t>(c->sort_hist),
+                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters),
+                             c->stream);
+            std::swap(ki, ko);
+            std::swap(vi, vo);
+            in_b = !in_b;
+        }
+        if (c->profiling) { c->prof_sort_keys += (int64_t)K; c->prof_sort_passes += npass; }
+    }
     c->sorted_in_b = in_b;
     c->K = (int64_t)K;
     const uint64_t *sk = in_b ? P<uint64_t>(c->keys_b) : P<uint64_t>(c->keys_a);
-    launch_ranges(sk, (int64_t)K, c->ntiles, P<uint32_t>(c->ranges), c->stream);
+    { StageTimer t_(c, A3FR_STAGE_RANGES);
+      launch_ranges(sk, (int64_t)K, c->ntiles, P<uint32_t>(c->ranges), c->stream); }
     TRY(check_launch(c, "bin_sort"));
     c->sorted = true;
     return A3FR_OK;
@@ -410,8 +506,18 @@ a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
     if (!c) return A3FR_EINVAL;
     if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend before a3fr_bin_sort");
     if (!rgb) return fail(c, A3FR_EINVAL, "rgb_dev is NULL");
+    unsigned long long *pairs = nullptr;
+    if (c->profiling) {
+        TRY(ensure(c, c->pair_count, 16));
+        pairs = P<unsigned long long>(c->pair_count);
+        if (!c->pairs_armed) {
+            launch_fill_u32(P<uint32_t>(c->pair_count), 0u, 2, c->stream);
+            c->pairs_armed = true;
+        }
+    }
+    StageTimer t_(c, A3FR_STAGE_BLEND);
     launch_blend(P<DevView>(c->views), c->nv, c->ntiles, P<uint8_t>(c->active), P<uint32_t>(c->ranges),
-                 sorted_vals(c), P<Record>(c->rec), c->n, rgb, T, last, c->stream);
+                 sorted_vals(c), P<Record>(c->rec), c->n, rgb, T, last, pairs, c->stream);
     return check_launch(c, "blend");
 }
 
@@ -480,6 +586,7 @@ a3fr_status a3fr_composite(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, const
     if (f->scale_mid < 1 || f->scale_periph < 1 || W / f->scale_mid < 1 || H / f->scale_mid < 1 ||
         W / f->scale_periph < 1 || H / f->scale_periph < 1)
         return fail(c, A3FR_EINVAL, "composite: layer scales too large for the image");
+    StageTimer t_(c, A3FR_STAGE_COMPOSITE);
     launch_composite(W, H, g.x, g.y, f->r_fovea, f->r_mid, fov, mid, f->scale_mid, per, f->scale_periph, per_full,
                      out, c->stream);
     return check_launch(c, "composite");

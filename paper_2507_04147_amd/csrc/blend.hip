@@ -17,11 +17,14 @@ namespace a3fr {
 
 constexpr int kBatch = 64;
 
+// COUNT: also count evaluated (pixel, Gaussian) pairs -- every list entry a
+// pixel evaluates while it is live, the one that stops it included.
+template <bool COUNT>
 __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,
                                               const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
                                               int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
-                                              uint32_t *__restrict__ lastout) {
+                                              uint32_t *__restrict__ lastout, unsigned long long *__restrict__ pairs) {
     const int64_t gt = blockIdx.x;
     if (!active[gt]) return;
     // view of this tile: views are ordered by tile offset
@@ -53,6 +56,7 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
     __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
     __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
     const double dx0 = (double)x0, dy0 = (double)y0;
+    uint32_t npairs = 0;
 
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
@@ -73,6 +77,7 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
             const float cdy = c2 * dy * dy;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                if (COUNT) npairs += alive[q] ? 1u : 0u;
                 const float t = (fxq[q] - mu) + kdy;
                 const float e = fmaf(a2, t * t, cdy);
                 const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
@@ -93,6 +98,11 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
         }
         __syncthreads();
     }
+    if (COUNT) {
+        unsigned long long tot = npairs;
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
+        if (lane == 0) atomicAdd(pairs, tot);
+    }
     const int64_t HW = (int64_t)W * H;
     float *img = rgb + 3 * dv.img_off;
 #pragma unroll
@@ -111,10 +121,14 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
 
 void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                   const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
-                  hipStream_t s) {
+                  unsigned long long *pairs, hipStream_t s) {
     if (ntiles == 0) return;
-    hipLaunchKernelGGL(k_blend, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals, rec, n, rgb,
-                       T, last);
+    if (pairs)
+        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals, rec,
+                           n, rgb, T, last, pairs);
+    else
+        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals,
+                           rec, n, rgb, T, last, pairs);
 }
 
 // ------------------------------------------------------------------------

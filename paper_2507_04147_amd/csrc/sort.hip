@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
             if (flag == 0) {
                 // predecessors always publish; the bound only turns a logic
                 // error into a reported failure instead of a hang
-                if (++spins > (1u << 26)) { atomicOr(counter + kMaxPasses, 1u); break; }
+                if (++spins > (1u << 26)) { atomicOr(counter - (shift / 8) + kMaxPasses, 1u); break; }
                 continue;
             }
             excl += st & kValMask;
@@ -210,33 +210,28 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     }
 }
 
-// Sort K (key, value) pairs on the low key_bits bits of the keys.  The result
-// ends in (keys_a, vals_a) or (keys_b, vals_b) as *result_in_b says.
-// status must hold passes x ceil(K/4096) x 256 words; counters holds passes + 1
-// words (the last is a sticky error flag: look-back gave up waiting).
-void launch_radix_sort(uint64_t *keys_a, uint32_t *vals_a, uint64_t *keys_b, uint32_t *vals_b, int64_t K,
-                       int key_bits, uint32_t *hist, uint32_t *status, int64_t status_cap, uint32_t *counters,
-                       bool *result_in_b, hipStream_t s) {
-    *result_in_b = false;
-    if (K <= 1) return;
-    const int npass = sort_passes_for_bits(key_bits);
+// Digit histograms of all npass passes (and cleared look-back state).
+// status must hold npass x ceil(K/4096) x 256 words; counters holds npass words
+// plus, at index kMaxPasses, a sticky error flag (look-back gave up waiting)
+// that the owner clears once.
+void launch_sort_hist(const uint64_t *keys, int64_t K, int npass, uint32_t *hist, uint32_t *status,
+                      uint32_t *counters, hipStream_t s) {
     const int64_t nparts = (K + kSortPart - 1) / kSortPart;
-    (void)status_cap;
     launch_fill_u32(hist, 0u, (int64_t)npass * kRadix, s);
     launch_fill_u32(status, 0u, (int64_t)npass * nparts * kRadix, s);
-    launch_fill_u32(counters, 0u, npass, s);  // counters[kMaxPasses] (error flag) is cleared by the owner
+    launch_fill_u32(counters, 0u, npass, s);
     int64_t hblocks = (K + 256 * 16 - 1) / (256 * 16);
     if (hblocks > 4096) hblocks = 4096;
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys_a, K, npass, hist);
-    uint64_t *ki = keys_a, *ko = keys_b;
-    uint32_t *vi = vals_a, *vo = vals_b;
-    for (int p = 0; p < npass; ++p) {
-        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, K, 8 * p,
-                           hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, counters + p);
-        uint64_t *tk = ki; ki = ko; ko = tk;
-        uint32_t *tv = vi; vi = vo; vo = tv;
-    }
-    *result_in_b = (npass & 1) != 0;
+    if (K > 0) hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, K, npass, hist);
+}
+
+// One onesweep pass over digit p (bits 8p .. 8p+7): (ki, vi) -> (ko, vo).
+void launch_sort_pass(const uint64_t *ki, const uint32_t *vi, uint64_t *ko, uint32_t *vo, int64_t K, int p,
+                      const uint32_t *hist, uint32_t *status, uint32_t *counters, hipStream_t s) {
+    const int64_t nparts = (K + kSortPart - 1) / kSortPart;
+    if (nparts == 0) return;
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, K, 8 * p,
+                       hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, counters + p);
 }
 
 // ------------------------------------------------------------------------
