@@ -160,12 +160,15 @@ const char *a3fr_last_error(const a3fr_ctx *ctx);
 a3fr_status a3fr_preprocess(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_view *views, int32_t n_views,
                             int32_t keep_num, int32_t keep_den);
 
-/* Tile-key duplication and depth sort (Sec. 2.3, sorting stage): one 64-bit
- * key (global tile id << 32 | float32 depth bits) per (Gaussian, active tile
- * it touches), value = Gaussian index, emitted in (view, index, row, column)
- * order and sorted by a stable LSD radix sort, so equal (tile, depth) keys
- * stay in index order; then each tile's [start, end) run.  Global tile id =
- * the view's tile offset (views in order) + row x tiles_x + column.
+/* Tile-key duplication and depth sort (Sec. 2.3, sorting stage): the result
+ * is, per tile, the list of Gaussians whose footprint box covers it, ordered by
+ * (float32 depth bits, Gaussian index) -- the order of a stable sort of
+ * (global tile id << 32 | depth bits) keys emitted in index order.  It is
+ * built as: visible entries sorted by depth (in a3fr_preprocess), one 32-bit
+ * tile-id key per (entry, active tile) emitted in that order (value =
+ * Gaussian index), a stable LSD radix sort by tile id, then each tile's
+ * [start, end) run.  Global tile id = the view's tile offset (views in order)
+ * + row x tiles_x + column.
  * SYNCHRONISES once (reads the key count).  *n_keys_out (host, may be NULL)
  * receives the key count.  A3FR_ECAPACITY if the count reaches 2^30. */
 a3fr_status a3fr_bin_sort(a3fr_ctx *ctx, int64_t *n_keys_out);
@@ -225,21 +228,22 @@ typedef enum {
     A3FR_STAGE_MASKS = 0,      /* active-tile masks */
     A3FR_STAGE_PREPROCESS = 1, /* projection, colour, counts */
     A3FR_STAGE_SELECT = 2,     /* periphery radix select */
-    A3FR_STAGE_SCAN = 3,       /* key-count scan */
+    A3FR_STAGE_SCAN = 3,       /* compaction of visible entries; key offsets in depth order */
     A3FR_STAGE_EMIT = 4,       /* key emission */
-    A3FR_STAGE_SORT_HIST = 5,  /* digit histograms of the radix sort */
-    A3FR_STAGE_SORT_PASS = 6,  /* one onesweep pass (one launch per 8-bit digit) */
+    A3FR_STAGE_SORT_HIST = 5,  /* digit histograms of the tile-id sort */
+    A3FR_STAGE_SORT_PASS = 6,  /* one onesweep pass of the tile-id sort (one launch per 8-bit digit) */
     A3FR_STAGE_RANGES = 7,     /* tile ranges */
     A3FR_STAGE_BLEND = 8,      /* front-to-back blend */
     A3FR_STAGE_COMPOSITE = 9,  /* foveated composite */
-    A3FR_STAGE_COUNT = 10
+    A3FR_STAGE_DEPTH_SORT = 10,/* radix sort of the visible entries by depth (histograms + 4 passes) */
+    A3FR_STAGE_COUNT = 11
 } a3fr_stage;
 
 typedef struct {
     int64_t launches[A3FR_STAGE_COUNT]; /* timed intervals per stage */
     double ms[A3FR_STAGE_COUNT];        /* summed event time per stage */
-    int64_t sort_keys;                  /* keys sorted, summed over the timed bin_sorts */
-    int64_t sort_passes;                /* onesweep passes, summed */
+    int64_t sort_keys;                  /* keys sorted by tile id, summed over the timed bin_sorts */
+    int64_t sort_passes;                /* onesweep passes of the tile-id sorts, summed */
     int64_t blend_pairs;                /* evaluated (pixel, Gaussian) pairs of the timed blends */
 } a3fr_profile;
 
@@ -257,15 +261,18 @@ typedef enum {
     A3FR_BUF_COUNTS = 0,      /* uint32 [n_views][n] active tiles covered (before selection) */
     A3FR_BUF_DEPTH = 1,       /* uint32 [n_views][n] float32 depth bits (valid where count > 0) */
     A3FR_BUF_RECT = 2,        /* uint16 [n_views][n][4] x0,x1,y0,y1 tile rectangle (valid where count > 0) */
-    A3FR_BUF_OFFSETS = 3,     /* uint32 [n_views*n + 1] exclusive prefix of the kept counts */
-    A3FR_BUF_KEYS = 4,        /* uint64 [K] keys in emission order (needs a3fr_set_debug) */
+    A3FR_BUF_OFFSETS = 3,     /* uint32 [E + 1] exclusive prefix of the key counts of the E visible
+                                 (kept) entries, in depth order (A3FR_BUF_DEPTH_ORDER) */
+    A3FR_BUF_KEYS = 4,        /* uint64 [K] (tile << 32 | depth bits) keys in emission order: entries in
+                                 depth order, tiles row-major (needs a3fr_set_debug) */
     A3FR_BUF_VALS = 5,        /* uint32 [K] values in emission order (needs a3fr_set_debug) */
-    A3FR_BUF_SORTED_KEYS = 6, /* uint64 [K] */
-    A3FR_BUF_SORTED_VALS = 7, /* uint32 [K] */
+    A3FR_BUF_SORTED_KEYS = 6, /* uint64 [K] (tile << 32 | depth bits), sorted */
+    A3FR_BUF_SORTED_VALS = 7, /* uint32 [K] Gaussian indices, sorted */
     A3FR_BUF_RANGES = 8,      /* uint32 [n_tiles][2] start, end */
     A3FR_BUF_ACTIVE = 9,      /* uint8 [n_tiles] active-tile flags */
     A3FR_BUF_KEEP = 10,       /* uint8 [n_views][n] kept by the periphery subset (selecting views) */
-    A3FR_BUF_RECORDS = 11     /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb */
+    A3FR_BUF_RECORDS = 11,    /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb */
+    A3FR_BUF_DEPTH_ORDER = 12 /* uint32 [E] visible (kept) entries view*n + index, sorted by (depth, view, index) */
 } a3fr_buffer;
 
 /* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);

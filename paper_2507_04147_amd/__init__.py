@@ -24,7 +24,7 @@ MASK_ALL, MASK_DISC, MASK_ANNULUS = 0, 1, 2
 TILE = 16
 
 BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
-           active=9, keep=10, records=11)
+           active=9, keep=10, records=11, depth_order=12)
 
 _lib = None
 
@@ -66,11 +66,12 @@ class Fovea_(C.Structure):
                 ("margin", C.c_double)]
 
 
-STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite"]
+STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite",
+          "depth_sort"]
 
 
 class Profile_(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 10), ("ms", C.c_double * 10), ("sort_keys", C.c_int64),
+    _fields_ = [("launches", C.c_int64 * 11), ("ms", C.c_double * 11), ("sort_keys", C.c_int64),
                 ("sort_passes", C.c_int64), ("blend_pairs", C.c_int64)]
 
 
@@ -285,7 +286,7 @@ class Context:
     def get_profile(self):
         p = Profile_()
         self._check(self._L.a3fr_get_profile(self._h, C.byref(p)))
-        return dict(stages={STAGES[k]: dict(launches=int(p.launches[k]), ms=float(p.ms[k])) for k in range(10)},
+        return dict(stages={STAGES[k]: dict(launches=int(p.launches[k]), ms=float(p.ms[k])) for k in range(len(STAGES))},
                     sort_keys=int(p.sort_keys), sort_passes=int(p.sort_passes), blend_pairs=int(p.blend_pairs))
 
     def fp64_probe(self, x, y):

@@ -64,18 +64,23 @@ void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
                    uint32_t *sel_hist /* [nsel][12][256] */, uint8_t *keep, hipStream_t s);
-void launch_scan_counts(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                        uint32_t *offsets, uint64_t *block_sums, int64_t nblocks_cap, uint64_t *total,
-                        hipStream_t s);
-void launch_emit(const DevView *views, int nv, int64_t n, const uint32_t *offsets, const uint32_t *depth,
-                 const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
-                 uint64_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s);
-int sort_passes_for_bits(int bits);
-void launch_sort_hist(const uint64_t *keys, int64_t K, int npass, uint32_t *hist /* [8][256] */, uint32_t *status,
-                      uint32_t *counters /* [16] */, hipStream_t s);
-void launch_sort_pass(const uint64_t *ki, const uint32_t *vi, uint64_t *ko, uint32_t *vo, int64_t K, int p,
-                      const uint32_t *hist, uint32_t *status, uint32_t *counters, hipStream_t s);
-void launch_ranges(const uint64_t *keys, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
+void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
+                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *block_sums,
+                            uint64_t *total, uint32_t *n_ent, hipStream_t s);
+void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
+                        uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s);
+void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
+                 const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
+                 uint32_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s);
+void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
+                        int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s);
+int sort_partitions(int64_t n);
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *hist,
+                         uint32_t *status, uint32_t *ctr, hipStream_t s);
+void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                      int64_t n_max, int p, const uint32_t *hist, uint32_t *status, uint32_t *ctr, uint32_t *err,
+                      hipStream_t s);
+void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
 void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                   const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
                   unsigned long long *pairs /* nullable: count evaluated pairs */, hipStream_t s);

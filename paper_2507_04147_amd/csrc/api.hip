@@ -45,7 +45,8 @@ struct a3fr_ctx {
     // device workspace
     DevBuf views, row_view, row_y, row_prefix, row_list, active;
     DevBuf counts, depth, rect, rec, score, keep, sel_views, sel;
-    DevBuf offsets, block_sums, total;
+    DevBuf offsets, block_sums, scalars;
+    DevBuf ent_a, ent_b, dkey_a, dkey_b;       // visible entries, depth sort
     DevBuf keys_a, keys_b, vals_a, vals_b, big_list, big_count;
     DevBuf sort_hist, sort_status, sort_counters, ranges;
     DevBuf layers, sse_part, sse_cnt;
@@ -103,6 +104,15 @@ a3fr_status ensure(a3fr_ctx *c, DevBuf &b, size_t bytes) {
 
 template <class T>
 T *P(DevBuf &b) { return reinterpret_cast<T *>(b.p); }
+
+// Device scalars of one frame (the scalars buffer, 64 bytes):
+//   u64 [0] entries total, u64 [1] keys total, u32 [4] entries (sort count),
+//   u32 [5] keys (sort count), u32 [6] sticky sort error flag.
+uint64_t *sc_ent_total(DevBuf &b) { return reinterpret_cast<uint64_t *>(b.p); }
+uint64_t *sc_key_total(DevBuf &b) { return reinterpret_cast<uint64_t *>(b.p) + 1; }
+uint32_t *sc_n_ent(DevBuf &b) { return reinterpret_cast<uint32_t *>(b.p) + 4; }
+uint32_t *sc_n_keys(DevBuf &b) { return reinterpret_cast<uint32_t *>(b.p) + 5; }
+uint32_t *sc_err(DevBuf &b) { return reinterpret_cast<uint32_t *>(b.p) + 6; }
 
 #define TRY(expr)                           \
     do {                                    \
@@ -235,7 +245,8 @@ void a3fr_destroy(a3fr_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
                       &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
-                      &c->sel, &c->offsets, &c->block_sums, &c->total, &c->keys_a, &c->keys_b,
+                      &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
+                      &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->big_list, &c->big_count, &c->sort_hist,
                       &c->sort_status, &c->sort_counters, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count};
@@ -298,9 +309,9 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
     if (!c) return A3FR_EINVAL;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     HIPCHECK(c, hipGetLastError());
-    if (c->sort_counters.p) {
+    if (c->scalars.p) {
         uint32_t flag = 0;
-        HIPCHECK(c, hipMemcpy(&flag, P<uint32_t>(c->sort_counters) + 8, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(c, hipMemcpy(&flag, sc_err(c->scalars), sizeof(uint32_t), hipMemcpyDeviceToHost));
         if (flag) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
     }
     return A3FR_OK;
@@ -382,7 +393,17 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     TRY(ensure(c, c->sel, sizeof(uint32_t) * ((size_t)c->nsel * 12 * 256 + (size_t)c->nsel * 32 + 32)));
     TRY(ensure(c, c->offsets, sizeof(uint32_t) * (m + 1)));
     TRY(ensure(c, c->block_sums, sizeof(uint64_t) * ((m + 4095) / 4096 + 1)));
-    TRY(ensure(c, c->total, sizeof(uint64_t)));
+    if (!c->scalars.p) {
+        TRY(ensure(c, c->scalars, 64));
+        launch_fill_u32(P<uint32_t>(c->scalars), 0u, 16, c->stream);
+    }
+    TRY(ensure(c, c->ent_a, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->dkey_a, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->sort_hist, sizeof(uint32_t) * 4 * 256));
+    TRY(ensure(c, c->sort_counters, sizeof(uint32_t) * 8));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * 4 * (size_t)sort_partitions(m) * 256));
 
     // ---- uploads through pinned staging
     const size_t bytes_v = sizeof(DevView) * nv, bytes_r = sizeof(int32_t) * c->rows_total,
@@ -413,9 +434,32 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
         launch_select(dv, nv, P<int32_t>(c->sel_views), c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
                       keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream); }
-    { StageTimer t_(c, A3FR_STAGE_SCAN);
-    launch_scan_counts(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->offsets),
-                       P<uint64_t>(c->block_sums), (m + 4095) / 4096 + 1, P<uint64_t>(c->total), c->stream); }
+    {
+        StageTimer t_(c, A3FR_STAGE_SCAN);
+        launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
+                               P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
+                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), c->stream);
+    }
+    {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
+        StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
+        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, P<uint32_t>(c->sort_hist),
+                            P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
+        uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
+        uint32_t *vi = P<uint32_t>(c->ent_a), *vo = P<uint32_t>(c->ent_b);
+        for (int p = 0; p < 4; ++p) {
+            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, p, P<uint32_t>(c->sort_hist),
+                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), sc_err(c->scalars),
+                             c->stream);
+            std::swap(ki, ko);
+            std::swap(vi, vo);
+        }
+    }
+    {
+        StageTimer t_(c, A3FR_STAGE_SCAN);
+        launch_key_offsets(P<uint32_t>(c->counts), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m,
+                           P<uint32_t>(c->offsets), P<uint64_t>(c->block_sums), sc_key_total(c->scalars),
+                           sc_n_keys(c->scalars), c->stream);
+    }
     TRY(check_launch(c, "preprocess"));
     c->preprocessed = true;
     return A3FR_OK;
@@ -424,54 +468,50 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
 a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (!c) return A3FR_EINVAL;
     if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "a3fr_bin_sort before a3fr_preprocess");
-    HIPCHECK(c, hipMemcpyAsync(c->h_total, c->total.p, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     const uint64_t K = *c->h_total;
     if (n_keys_out) *n_keys_out = (int64_t)K;
     if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
     const int64_t m = (int64_t)c->nv * c->n;
-    TRY(ensure(c, c->keys_a, sizeof(uint64_t) * K));
-    TRY(ensure(c, c->keys_b, sizeof(uint64_t) * K));
+    TRY(ensure(c, c->keys_a, sizeof(uint32_t) * K));
+    TRY(ensure(c, c->keys_b, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_a, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_b, sizeof(uint32_t) * K));
     TRY(ensure(c, c->big_list, sizeof(uint32_t) * m));
     TRY(ensure(c, c->big_count, sizeof(uint32_t) * 4));
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
-    const int key_bits = 32 + tile_bits;
-    const int npass = sort_passes_for_bits(key_bits);
-    const int64_t nparts = ((int64_t)K + 4095) / 4096;
-    TRY(ensure(c, c->sort_hist, sizeof(uint32_t) * 8 * 256));
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)npass * nparts * 256));
-    if (!c->sort_counters.p) {
-        TRY(ensure(c, c->sort_counters, sizeof(uint32_t) * 16));
-        launch_fill_u32(P<uint32_t>(c->sort_counters), 0u, 16, c->stream);
-    }
+    const int npass = (tile_bits + 7) / 8;
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)npass * sort_partitions((int64_t)K) * 256));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
-    { StageTimer t_(c, A3FR_STAGE_EMIT);
-    launch_emit(dv, c->nv, c->n, P<uint32_t>(c->offsets), P<uint32_t>(c->depth), P<uint64_t>(c->rect),
-                P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint64_t>(c->keys_a),
-                P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream); }
+    {
+        StageTimer t_(c, A3FR_STAGE_EMIT);
+        launch_emit(dv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
+                    P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->keys_a),
+                    P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream);
+    }
     if (c->keep_emission) {
-        TRY(ensure(c, c->keys_e, sizeof(uint64_t) * K));
+        TRY(ensure(c, c->keys_e, sizeof(uint32_t) * K));
         TRY(ensure(c, c->vals_e, sizeof(uint32_t) * K));
-        HIPCHECK(c, hipMemcpyAsync(c->keys_e.p, c->keys_a.p, sizeof(uint64_t) * K, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(c->keys_e.p, c->keys_a.p, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, c->stream));
         HIPCHECK(c, hipMemcpyAsync(c->vals_e.p, c->vals_a.p, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, c->stream));
     }
-    {
-        StageTimer t_(c, A3FR_STAGE_SORT_HIST);
-        launch_sort_hist(P<uint64_t>(c->keys_a), (int64_t)K, npass, P<uint32_t>(c->sort_hist),
-                         P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
-    }
-    uint64_t *ki = P<uint64_t>(c->keys_a), *ko = P<uint64_t>(c->keys_b);
+    uint32_t *ki = P<uint32_t>(c->keys_a), *ko = P<uint32_t>(c->keys_b);
     uint32_t *vi = P<uint32_t>(c->vals_a), *vo = P<uint32_t>(c->vals_b);
     bool in_b = false;
     if (K > 1) {
+        {
+            StageTimer t_(c, A3FR_STAGE_SORT_HIST);
+            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, P<uint32_t>(c->sort_hist),
+                                P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
+        }
         for (int p = 0; p < npass; ++p) {
             StageTimer t_(c, A3FR_STAGE_SORT_PASS);
-            launch_sort_pass(ki, vi, ko, vo, (int64_t)K, p, P<uint32_t>(c->sort_hist),
-                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters),
+            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, p, P<uint32_t>(c->sort_hist),
+                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), sc_err(c->scalars),
                              c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
@@ -481,9 +521,11 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     }
     c->sorted_in_b = in_b;
     c->K = (int64_t)K;
-    const uint64_t *sk = in_b ? P<uint64_t>(c->keys_b) : P<uint64_t>(c->keys_a);
-    { StageTimer t_(c, A3FR_STAGE_RANGES);
-      launch_ranges(sk, (int64_t)K, c->ntiles, P<uint32_t>(c->ranges), c->stream); }
+    {
+        StageTimer t_(c, A3FR_STAGE_RANGES);
+        launch_ranges(in_b ? P<uint32_t>(c->keys_b) : P<uint32_t>(c->keys_a), (int64_t)K, c->ntiles,
+                      P<uint32_t>(c->ranges), c->stream);
+    }
     TRY(check_launch(c, "bin_sort"));
     c->sorted = true;
     return A3FR_OK;
@@ -492,8 +534,8 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
 }  // extern "C"
 
 namespace {
-const uint64_t *sorted_keys(a3fr_ctx *c) {
-    return c->sorted_in_b ? P<uint64_t>(c->keys_b) : P<uint64_t>(c->keys_a);
+const uint32_t *sorted_tiles(a3fr_ctx *c) {
+    return c->sorted_in_b ? P<uint32_t>(c->keys_b) : P<uint32_t>(c->keys_a);
 }
 const uint32_t *sorted_vals(a3fr_ctx *c) {
     return c->sorted_in_b ? P<uint32_t>(c->vals_b) : P<uint32_t>(c->vals_a);
@@ -665,35 +707,47 @@ a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
 
 a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_bytes, int64_t *bytes_out) {
     if (!c) return A3FR_EINVAL;
+    if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "nothing preprocessed");
     const int64_t m = (int64_t)c->nv * c->n;
     const void *src = nullptr;
     int64_t bytes = 0;
-    bool need_sort = false;
+    int make64 = 0;  // 1: emission-order keys, 2: sorted keys (rebuilt as tile << 32 | depth)
+    uint32_t n_ent = 0;
+    if (which == A3FR_BUF_OFFSETS || which == A3FR_BUF_DEPTH_ORDER) {
+        HIPCHECK(c, hipMemcpyAsync(&n_ent, sc_n_ent(c->scalars), 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
+    const bool need_sort = which == A3FR_BUF_KEYS || which == A3FR_BUF_VALS || which == A3FR_BUF_SORTED_KEYS ||
+                           which == A3FR_BUF_SORTED_VALS || which == A3FR_BUF_RANGES;
+    if (need_sort && !c->sorted) return fail(c, A3FR_ENOTREADY, "keys not sorted yet");
+    if ((which == A3FR_BUF_KEYS || which == A3FR_BUF_VALS) && !c->keep_emission)
+        return fail(c, A3FR_ENOTREADY, "emission order kept only with a3fr_set_debug(ctx, 1)");
     switch (which) {
         case A3FR_BUF_COUNTS: src = c->counts.p; bytes = 4 * m; break;
         case A3FR_BUF_DEPTH: src = c->depth.p; bytes = 4 * m; break;
         case A3FR_BUF_RECT: src = c->rect.p; bytes = 8 * m; break;
-        case A3FR_BUF_OFFSETS: src = c->offsets.p; bytes = 4 * (m + 1); break;
-        case A3FR_BUF_KEYS:
-        case A3FR_BUF_VALS:
-            if (!c->keep_emission) return fail(c, A3FR_ENOTREADY, "emission order kept only with a3fr_set_debug(ctx, 1)");
-            src = which == A3FR_BUF_KEYS ? c->keys_e.p : c->vals_e.p;
-            bytes = (which == A3FR_BUF_KEYS ? 8 : 4) * c->K;
-            need_sort = true;
-            break;
-        case A3FR_BUF_SORTED_KEYS: src = sorted_keys(c); bytes = 8 * c->K; need_sort = true; break;
-        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * c->K; need_sort = true; break;
-        case A3FR_BUF_RANGES: src = c->ranges.p; bytes = 8 * c->ntiles; need_sort = true; break;
+        case A3FR_BUF_OFFSETS: src = c->offsets.p; bytes = 4 * ((int64_t)n_ent + 1); break;
+        case A3FR_BUF_KEYS: make64 = 1; bytes = 8 * c->K; break;
+        case A3FR_BUF_VALS: src = c->vals_e.p; bytes = 4 * c->K; break;
+        case A3FR_BUF_SORTED_KEYS: make64 = 2; bytes = 8 * c->K; break;
+        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * c->K; break;
+        case A3FR_BUF_RANGES: src = c->ranges.p; bytes = 8 * c->ntiles; break;
         case A3FR_BUF_ACTIVE: src = c->active.p; bytes = c->ntiles; break;
         case A3FR_BUF_KEEP: src = c->keep.p; bytes = c->nsel ? m : 0; break;
         case A3FR_BUF_RECORDS: src = c->rec.p; bytes = (int64_t)sizeof(Record) * m; break;
+        case A3FR_BUF_DEPTH_ORDER: src = c->ent_a.p; bytes = 4 * (int64_t)n_ent; break;
         default: return fail(c, A3FR_EINVAL, "unknown buffer");
     }
-    if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "nothing preprocessed");
-    if (need_sort && !c->sorted) return fail(c, A3FR_ENOTREADY, "keys not sorted yet");
     if (bytes_out) *bytes_out = bytes;
     if (!dst || bytes == 0) return A3FR_OK;
     if (bytes > max_bytes) return fail(c, A3FR_EINVAL, "destination too small");
+    if (make64) {
+        const uint32_t *t = make64 == 1 ? P<uint32_t>(c->keys_e) : sorted_tiles(c);
+        const uint32_t *v = make64 == 1 ? P<uint32_t>(c->vals_e) : sorted_vals(c);
+        launch_make_keys64(P<DevView>(c->views), c->nv, c->n, t, v, c->K, P<uint32_t>(c->depth),
+                           reinterpret_cast<uint64_t *>(dst), c->stream);
+        return check_launch(c, "inspect");
+    }
     HIPCHECK(c, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, c->stream));
     return A3FR_OK;
 }

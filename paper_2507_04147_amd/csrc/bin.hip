@@ -10,9 +10,11 @@
 // chosen bucket is kept whole; later passes exit at once.
 //
 // Keys (paper Sec. 2.3: the tiles each ellipse intersects, then per-tile depth
-// order) are emitted after an exclusive scan of the per-(view, Gaussian) key
-// counts, in (view, Gaussian index, tile row, tile column) order, so that a
-// stable sort on the key leaves equal (tile, depth) keys in index order.
+// order): the visible (view, Gaussian) entries are compacted in (view, index)
+// order, sorted by depth (sort.hip), prefix-summed in that order, and then each
+// entry writes one 32-bit key (its global tile id) per active tile of its
+// rectangle, row by row, with the Gaussian index as value.  A stable sort of
+// these keys by tile id leaves every tile's list in (depth, index) order.
 #include "a3fr_internal.h"
 
 namespace a3fr {
@@ -157,20 +159,37 @@ void launch_select(const DevView *views, int nv, const int32_t *sel_views, int n
 }
 
 // ------------------------------------------------------------------------
-// scan of the kept key counts
+// scans: compaction of the visible entries, then key offsets in depth order
 // ------------------------------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block
 
-__device__ __forceinline__ uint32_t eff_count(const uint32_t *counts, const uint8_t *keep, const DevView *views,
-                                              int64_t n, int64_t e) {
-    const uint32_t c = counts[e];
-    if (c == 0) return 0;
-    const int v = (int)(e / n);
-    if (views[v].v.select && !keep[e]) return 0;
-    return c;
-}
+// Entry e = view * n + index contributes keys iff it is visible in its view and,
+// for a selecting view, kept.
+struct EntryFlags {
+    const uint32_t *counts;
+    const uint8_t *keep;
+    const DevView *views;
+    int64_t n;
+    __device__ __forceinline__ uint32_t operator()(int64_t e, int64_t m) const {
+        if (e >= m) return 0;
+        if (counts[e] == 0) return 0;
+        const int v = (int)(e / n);
+        if (views[v].v.select && !keep[e]) return 0;
+        return 1;
+    }
+};
+
+// Key count of the j-th entry in depth order.
+struct SortedCounts {
+    const uint32_t *counts;
+    const uint32_t *ent;
+    const uint32_t *n_ent;
+    __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
+        return j < (int64_t)*n_ent ? counts[ent[j]] : 0u;
+    }
+};
 
 // wave-level inclusive scan of a 64-bit value (wave64 via shuffles)
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
@@ -201,23 +220,21 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t *total)
     return wpre + inc - x;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const uint32_t *counts, const uint8_t *keep,
-                                                            const DevView *views, int64_t n, int64_t m,
-                                                            uint64_t *block_sums) {
+template <class F>
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(F f, int64_t m, uint64_t *block_sums) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint64_t acc = 0;
 #pragma unroll 4
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t e = base + (int64_t)j * kScanBlock + threadIdx.x;
-        if (e < m) acc += eff_count(counts, keep, views, n, e);
-    }
+    for (int j = 0; j < kScanItems; ++j) acc += f(base + (int64_t)j * kScanBlock + threadIdx.x, m);
     uint64_t tot;
     block_excl_scan(acc, &tot);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t *block_sums, int64_t nb, uint64_t *total) {
-    // one block: exclusive scan of nb block sums in chunks of 1024
+// one block: exclusive scan of nb block sums in chunks of 1024; writes the
+// grand total as u64 and (clamped) u32
+__global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t *block_sums, int64_t nb, uint64_t *total,
+                                                      uint32_t *total32) {
     __shared__ uint64_t wsum[16];
     __shared__ uint64_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -240,22 +257,49 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t *block_sums, int6
         if (threadIdx.x == 0) carry = base + tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) {
+        *total = carry;
+        *total32 = carry > 0xffffffffull ? 0xffffffffu : (uint32_t)carry;
+    }
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_down(const uint32_t *counts, const uint8_t *keep,
-                                                          const DevView *views, int64_t n, int64_t m,
-                                                          const uint64_t *block_pre, const uint64_t *total,
-                                                          uint32_t *offsets) {
-    // thread t owns entries base + t*16 .. base + t*16 + 15 (blocked), so the
-    // running sum inside a thread follows index order
+// Compaction: entry e with flag 1 goes to slot (its exclusive prefix), with
+// its depth bits as sort key.  Thread t owns 16 consecutive entries (blocked),
+// so the running sum inside a thread follows entry order.
+__global__ void __launch_bounds__(kScanBlock) k_compact_down(EntryFlags f, int64_t m, const uint64_t *block_pre,
+                                                             const uint32_t *__restrict__ depth,
+                                                             uint32_t *__restrict__ ent, uint32_t *__restrict__ dkey) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint32_t fl = f(base + j, m);
+        flags |= fl << j;
+        cnt += fl;
+    }
+    uint64_t tot;
+    uint64_t run = block_pre[blockIdx.x] + block_excl_scan(cnt, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if ((flags >> j) & 1u) {
+            const int64_t e = base + j;
+            ent[run] = (uint32_t)e;
+            dkey[run] = depth[e];
+            ++run;
+        }
+    }
+}
+
+// Offsets of the keys of the entries in depth order; offsets[E] = K.
+__global__ void __launch_bounds__(kScanBlock) k_offsets_down(SortedCounts f, int64_t m, const uint64_t *block_pre,
+                                                             const uint64_t *total, uint32_t *offsets) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t E = *f.n_ent;
     uint32_t c[kScanItems];
     uint64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t e = base + j;
-        c[j] = e < m ? eff_count(counts, keep, views, n, e) : 0u;
+        c[j] = f(base + j, m);
         acc += c[j];
     }
     uint64_t tot;
@@ -263,74 +307,73 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_down(const uint32_t *counts
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t e = base + j;
-        if (e < m) offsets[e] = (uint32_t)run;
+        if (e < E) offsets[e] = (uint32_t)run;
         run += c[j];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[m] = (uint32_t)*total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[E] = (uint32_t)*total;
 }
 
-void launch_scan_counts(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                        uint32_t *offsets, uint64_t *block_sums, int64_t nblocks_cap, uint64_t *total,
-                        hipStream_t s) {
+void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
+                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *block_sums,
+                            uint64_t *total, uint32_t *n_ent, hipStream_t s) {
     const int64_t m = (int64_t)nv * n;
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
-    (void)nblocks_cap;
-    if (nb == 0) {
-        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, (int64_t)0, total);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, keep, views, n, m,
-                       block_sums);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, keep, views, n, m,
-                       block_sums, total, offsets);
+    EntryFlags f{counts, keep, views, n};
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<EntryFlags>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total, n_ent);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_compact_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums, depth, ent, dkey);
+}
+
+void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
+                        uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s) {
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    SortedCounts f{counts, ent, n_ent};
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<SortedCounts>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total, total32);
+    hipLaunchKernelGGL(k_offsets_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, block_sums,
+                       total, offsets);
 }
 
 // ------------------------------------------------------------------------
-// key emission
+// key emission (entries in depth order)
 // ------------------------------------------------------------------------
-constexpr uint32_t kBigKeys = 48;  // Gaussians with more keys go to the cooperative path
+constexpr uint32_t kBigKeys = 48;  // entries with more keys go to the cooperative path
 
 __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y0, int &y1) {
     x0 = (int)(r & 0xffff); x1 = (int)((r >> 16) & 0xffff);
     y0 = (int)((r >> 32) & 0xffff); y1 = (int)((r >> 48) & 0xffff);
 }
 
-__device__ __forceinline__ int find_view(const DevView *views, int nv, int64_t n, int64_t e) {
-    (void)views; (void)nv;
-    return (int)(e / n);
-}
-
-__global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views, int nv, int64_t n,
-                                              const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ depth,
-                                              const uint64_t *__restrict__ rect,
+__global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views, int64_t n,
+                                              const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                              const uint32_t *__restrict__ offsets, const uint64_t *__restrict__ rect,
                                               const uint16_t *__restrict__ row_prefix,
-                                              const uint16_t *__restrict__ row_list, uint64_t *__restrict__ keys,
+                                              const uint16_t *__restrict__ row_list, uint32_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals, uint32_t *big_list, uint32_t *big_count) {
-    const int64_t m = (int64_t)nv * n;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const uint32_t off = offsets[e];
-    const uint32_t cnt = offsets[e + 1] - off;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)*n_ent) return;
+    const uint32_t off = offsets[j];
+    const uint32_t cnt = offsets[j + 1] - off;
     if (cnt == 0) return;
     if (cnt > kBigKeys) {
-        big_list[atomicAdd(big_count, 1u)] = (uint32_t)e;
+        big_list[atomicAdd(big_count, 1u)] = (uint32_t)j;
         return;
     }
-    const int v = find_view(views, nv, n, e);
+    const int64_t e = ent[j];
+    const int v = (int)(e / n);
     const DevView &dv = views[v];
     const uint32_t i = (uint32_t)(e - (int64_t)v * n);
-    const uint64_t dbits = depth[e];
     int x0, x1, y0, y1;
     unpack_rect(rect[e], x0, x1, y0, y1);
     const int TX = dv.tiles_x;
+    const uint32_t tbase = (uint32_t)dv.tile_off;
     uint32_t w = off;
     const uint32_t wend = off + cnt;  // never write past this entry's slots
     if (dv.v.mask == A3FR_MASK_ALL) {
         for (int ty = y0; ty <= y1; ++ty)
             for (int tx = x0; tx <= x1 && w < wend; ++tx) {
-                const uint64_t gt = (uint64_t)(dv.tile_off + (int64_t)ty * TX + tx);
-                keys[w] = (gt << 32) | dbits;
+                keys[w] = tbase + (uint32_t)(ty * TX + tx);
                 vals[w] = i;
                 ++w;
             }
@@ -339,8 +382,7 @@ __global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views,
             const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
             const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
             for (int p = rp[x0]; p < rp[x1 + 1] && w < wend; ++p) {
-                const uint64_t gt = (uint64_t)(dv.tile_off + (int64_t)ty * TX + rl[p]);
-                keys[w] = (gt << 32) | dbits;
+                keys[w] = tbase + (uint32_t)(ty * TX + rl[p]);
                 vals[w] = i;
                 ++w;
             }
@@ -348,35 +390,35 @@ __global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views,
     }
 }
 
-// One block per Gaussian with many keys; threads write consecutive keys.
-__global__ void __launch_bounds__(256) k_emit_big(const DevView *__restrict__ views, int nv, int64_t n,
-                                                  const uint32_t *__restrict__ offsets,
-                                                  const uint32_t *__restrict__ depth, const uint64_t *__restrict__ rect,
+// One block per entry with many keys; threads write consecutive keys.
+__global__ void __launch_bounds__(256) k_emit_big(const DevView *__restrict__ views, int64_t n,
+                                                  const uint32_t *__restrict__ ent,
+                                                  const uint32_t *__restrict__ offsets, const uint64_t *__restrict__ rect,
                                                   const uint16_t *__restrict__ row_prefix,
-                                                  const uint16_t *__restrict__ row_list, uint64_t *__restrict__ keys,
+                                                  const uint16_t *__restrict__ row_list, uint32_t *__restrict__ keys,
                                                   uint32_t *__restrict__ vals, const uint32_t *big_list,
                                                   const uint32_t *big_count) {
     const uint32_t nbig = *big_count;
     for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const int64_t e = big_list[b];
-        const int v = find_view(views, nv, n, e);
+        const int64_t j = big_list[b];
+        const int64_t e = ent[j];
+        const int v = (int)(e / n);
         const DevView &dv = views[v];
         const uint32_t i = (uint32_t)(e - (int64_t)v * n);
-        const uint64_t dbits = depth[e];
-        const uint32_t off = offsets[e];
-        const uint32_t cnt_e = offsets[e + 1] - off;
+        const uint32_t off = offsets[j];
+        const uint32_t cnt_e = offsets[j + 1] - off;
         int x0, x1, y0, y1;
         unpack_rect(rect[e], x0, x1, y0, y1);
         const int TX = dv.tiles_x;
+        const uint32_t tbase = (uint32_t)dv.tile_off;
         if (dv.v.mask == A3FR_MASK_ALL) {
             const uint32_t wdt = (uint32_t)(x1 - x0 + 1);
             uint32_t cnt = wdt * (uint32_t)(y1 - y0 + 1);
             if (cnt > cnt_e) cnt = cnt_e;
-            for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-                const int ty = y0 + (int)(j / wdt), tx = x0 + (int)(j % wdt);
-                const uint64_t gt = (uint64_t)(dv.tile_off + (int64_t)ty * TX + tx);
-                keys[off + j] = (gt << 32) | dbits;
-                vals[off + j] = i;
+            for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+                const int ty = y0 + (int)(q / wdt), tx = x0 + (int)(q % wdt);
+                keys[off + q] = tbase + (uint32_t)(ty * TX + tx);
+                vals[off + q] = i;
             }
         } else {
             uint32_t run = off;
@@ -386,10 +428,9 @@ __global__ void __launch_bounds__(256) k_emit_big(const DevView *__restrict__ vi
                 const int p0 = rp[x0];
                 int rc = rp[x1 + 1] - p0;
                 if (run + (uint32_t)rc > off + cnt_e) rc = (int)(off + cnt_e - run);
-                for (int j = threadIdx.x; j < rc; j += blockDim.x) {
-                    const uint64_t gt = (uint64_t)(dv.tile_off + (int64_t)ty * TX + rl[p0 + j]);
-                    keys[run + j] = (gt << 32) | dbits;
-                    vals[run + j] = i;
+                for (int q = threadIdx.x; q < rc; q += blockDim.x) {
+                    keys[run + q] = tbase + (uint32_t)(ty * TX + rl[p0 + q]);
+                    vals[run + q] = i;
                 }
                 run += (uint32_t)rc;
             }
@@ -409,16 +450,40 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
-void launch_emit(const DevView *views, int nv, int64_t n, const uint32_t *offsets, const uint32_t *depth,
-                 const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list, uint64_t *keys,
-                 uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
-    const int64_t m = (int64_t)nv * n;
+void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
+                 const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
+                 uint32_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
     if (m == 0) return;
     launch_fill_u32(big_count, 0u, 1, s);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, views, nv, n, offsets, depth,
-                       rect, row_prefix, row_list, keys, vals, big_list, big_count);
-    hipLaunchKernelGGL(k_emit_big, dim3(2048), dim3(256), 0, s, views, nv, n, offsets, depth, rect, row_prefix,
-                       row_list, keys, vals, big_list, big_count);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, views, n, ent, n_ent, offsets, rect,
+                       row_prefix, row_list, keys, vals, big_list, big_count);
+    hipLaunchKernelGGL(k_emit_big, dim3(2048), dim3(256), 0, s, views, n, ent, offsets, rect, row_prefix, row_list,
+                       keys, vals, big_list, big_count);
+}
+
+// ------------------------------------------------------------------------
+// inspection: 64-bit (tile << 32 | depth bits) keys from tile ids and values
+// ------------------------------------------------------------------------
+__global__ void k_make_keys64(const DevView *__restrict__ views, int nv, int64_t n, const uint32_t *__restrict__ tiles,
+                              const uint32_t *__restrict__ vals, int64_t K, const uint32_t *__restrict__ depth,
+                              uint64_t *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    const uint32_t t = tiles[j];
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= (int64_t)t) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t i = vals[j] < (uint32_t)n ? vals[j] : 0u;
+    out[j] = ((uint64_t)t << 32) | (uint64_t)depth[(int64_t)lo * n + i];
+}
+
+void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
+                        int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s) {
+    if (K == 0) return;
+    hipLaunchKernelGGL(k_make_keys64, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, views, nv, n, tiles, vals, K,
+                       depth, out);
 }
 
 }  // namespace a3fr

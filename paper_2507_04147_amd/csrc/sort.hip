@@ -1,20 +1,28 @@
 // Per-tile depth sort (paper Sec. 2.3: the ellipses of each tile are sorted by
-// depth, near to far) as one stable LSD radix sort of the 64-bit
-// (tile << 32 | depth bits) keys with their Gaussian-index values.
+// depth, near to far).
 //
-// Onesweep structure for gfx950:
-//  * one pass over the keys builds the digit histograms of every 8-bit pass;
-//  * then one kernel per pass.  A block takes the next partition id from an
-//    atomic counter (so it only ever waits on partitions that have already
-//    started), loads 4096 keys wave-striped (lane-consecutive, coalesced), ranks
-//    them stably inside each wave with ballots (8 ballots give the lanes that
-//    share a digit; popcount below the lane gives the rank), publishes its
-//    digit counts, and finds its global digit offsets by decoupled look-back
-//    over the preceding partitions' published counts;
-//  * keys are first scattered into LDS in sorted order and then written out,
-//    so that consecutive threads write consecutive addresses of each digit run.
-// Stability: within a partition the wave-striped processing order (item, lane)
-// equals memory order, and waves / partitions are combined in order.
+// The order required is (tile, depth, Gaussian index).  It is produced in two
+// stable radix sorts of 32-bit keys instead of one sort of 64-bit
+// (tile, depth) keys:
+//   1. the visible (view, Gaussian) entries -- about one per visible Gaussian
+//      and layer, far fewer than keys -- are sorted by their float32 depth bits
+//      (positive floats order like their bit patterns), starting from
+//      (view, index) order so that equal depths stay in index order;
+//   2. the keys, emitted entry by entry in that depth order, are sorted by
+//      tile id alone; stability keeps each tile's keys in (depth, index) order.
+//
+// Both use the same onesweep LSD kernel for gfx950 (8-bit digits):
+//  * one coalesced pass builds the digit histograms of every pass;
+//  * one kernel per digit: a block takes the next partition id from an atomic
+//    counter (so it only waits on partitions that have already started), loads
+//    its keys wave-striped (lane-consecutive, coalesced), ranks them stably
+//    inside each wave with 8 ballots (lanes sharing a digit) and a popcount of
+//    the lower lanes, publishes its per-digit counts, resolves its global
+//    digit offsets by decoupled look-back over the preceding partitions, and
+//    scatters through LDS so that consecutive threads write consecutive
+//    addresses of each digit run.
+// The element count is read from device memory, so a launch may be sized by
+// an upper bound; blocks past the last partition exit at once.
 #include "a3fr_internal.h"
 
 namespace a3fr {
@@ -22,40 +30,30 @@ namespace a3fr {
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortThreads * kSortItems;  // 4096 keys per partition
+constexpr int kSortPart = kSortThreads * kSortItems;  // keys per partition
 constexpr int kRadix = 256;
-constexpr int kMaxPasses = 8;
+constexpr int kMaxPasses = 4;                         // 32-bit keys
 
-int sort_passes_for_bits(int bits) { return (bits + 7) / 8; }
+int sort_partitions(int64_t n) { return (int)((n + kSortPart - 1) / kSortPart); }
 
-__global__ void __launch_bounds__(256) k_sort_hist(const uint64_t *__restrict__ keys, int64_t K, int npass,
-                                                   uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[kMaxPasses][kRadix];
-    for (int j = threadIdx.x; j < kMaxPasses * kRadix; j += blockDim.x) (&h[0][0])[j] = 0;
+// Histograms of the npass low digits of n keys (n read from *n_dev).  Each
+// wave keeps its own LDS histograms; the block adds them to the global ones.
+__global__ void __launch_bounds__(256) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
+                                                   int npass, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kSortWaves][kMaxPasses][kRadix];
+    for (int j = threadIdx.x; j < kSortWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
     __syncthreads();
-    // each thread walks a contiguous run of keys and flushes a digit's count
-    // only when the digit changes (keys of one Gaussian share most digits)
-    const int64_t per_thread = 16;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * per_thread;
-    for (int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * per_thread; b0 < K; b0 += stride) {
-        const int64_t b1 = b0 + per_thread < K ? b0 + per_thread : K;
-        for (int p = 0; p < npass; ++p) {
-            uint32_t cur = 0xffffffffu, run = 0;
-            for (int64_t j = b0; j < b1; ++j) {
-                const uint32_t d = (uint32_t)(keys[j] >> (8 * p)) & 255u;
-                if (d != cur) {
-                    if (run) atomicAdd(&h[p][cur], run);
-                    cur = d;
-                    run = 0;
-                }
-                ++run;
-            }
-            if (run) atomicAdd(&h[p][cur], run);
-        }
+    const int64_t n = *n_dev;
+    const int w = threadIdx.x >> 6;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[j];
+        for (int p = 0; p < npass; ++p) atomicAdd(&h[w][p][(k >> (8 * p)) & 255u], 1u);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < npass * kRadix; j += blockDim.x) {
-        const uint32_t c = (&h[0][0])[j];
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kSortWaves; ++q) c += (&h[q][0][0])[j];
         if (c) atomicAdd(&hist[j], c);
     }
 }
@@ -67,34 +65,39 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__restrict__ kin,
+// One stable pass over digit (key >> shift) & 255.  err: sticky flag set if a
+// look-back wait exceeds its bound (never expected: predecessors always
+// publish; the bound turns a logic error into a report instead of a hang).
+__global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
-                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                           int64_t K, int shift, const uint32_t *__restrict__ ghist,
-                                                           uint32_t *status, uint32_t *counter) {
+                                                           uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                           const uint32_t *n_dev, int shift,
+                                                           const uint32_t *__restrict__ ghist, uint32_t *status,
+                                                           uint32_t *counter, uint32_t *err) {
     __shared__ uint32_t s_part;
     __shared__ uint32_t s_wh[kSortWaves][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_wsum[kSortWaves];
-    __shared__ uint64_t s_k[kSortPart];
+    __shared__ uint32_t s_k[kSortPart];
     __shared__ uint32_t s_v[kSortPart];
 
+    const int64_t K = *n_dev;
+    const int nparts = (int)((K + kSortPart - 1) / kSortPart);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_part = atomicAdd(counter, 1u);
     for (int j = tid; j < kSortWaves * kRadix; j += kSortThreads) (&s_wh[0][0])[j] = 0;
     __syncthreads();
     const uint32_t part = s_part;
+    if ((int)part >= nparts) return;
     const int64_t base = (int64_t)part * kSortPart;
 
-    uint64_t key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t rk[kSortItems];
+    uint32_t key[kSortItems], val[kSortItems], rk[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
         const bool valid = pos < K;
-        key[it] = valid ? kin[pos] : 0ull;
+        key[it] = valid ? kin[pos] : 0u;
         val[it] = valid ? vin[pos] : 0u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -102,7 +105,7 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
         const bool valid = pos < K;
-        const uint32_t d = (uint32_t)(key[it] >> shift) & 255u;
+        const uint32_t d = (key[it] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -118,21 +121,19 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     }
     __syncthreads();
 
-    // per-digit totals and per-wave exclusive offsets (thread = digit)
+    // thread = digit: totals, per-wave exclusive offsets, publication
     const int d = tid;
     uint32_t c[kSortWaves];
     uint32_t tot = 0;
 #pragma unroll
     for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
-    // publish this partition's count of digit d
     st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kFlagInc : kFlagAgg) | tot);
     {
         uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
     }
-    // block-local exclusive scan over digits
-    {
+    {   // block-local exclusive scan over digits
         uint32_t inc = tot;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -146,9 +147,8 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
         for (int q = 0; q < kSortWaves; ++q) if (q < w) pre += s_wsum[q];
         s_lstart[d] = pre + inc - tot;
     }
-    // global base of digit d: digits below it over all keys, then this digit in earlier partitions
     uint32_t gexcl;
-    {
+    {   // keys of smaller digits over the whole input
         const uint32_t g = ghist[d];
         uint32_t inc = g;
 #pragma unroll
@@ -172,9 +172,7 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
             const uint32_t st = ld_status(&status[p * kRadix + d]);
             const uint32_t flag = st >> 30;
             if (flag == 0) {
-                // predecessors always publish; the bound only turns a logic
-                // error into a reported failure instead of a hang
-                if (++spins > (1u << 26)) { atomicOr(counter - (shift / 8) + kMaxPasses, 1u); break; }
+                if (++spins > (1u << 26)) { atomicOr(err, 1u); break; }
                 continue;
             }
             excl += st & kValMask;
@@ -190,7 +188,7 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
         if (pos < K) {
-            const uint32_t dg = (uint32_t)(key[it] >> shift) & 255u;
+            const uint32_t dg = (key[it] >> shift) & 255u;
             const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
             s_k[lp] = key[it];
             s_v[lp] = val[it];
@@ -200,8 +198,8 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     const int64_t rem = K - base;
     const int nvalid = rem < kSortPart ? (int)rem : kSortPart;
     for (int j = tid; j < nvalid; j += kSortThreads) {
-        const uint64_t kk = s_k[j];
-        const uint32_t dg = (uint32_t)(kk >> shift) & 255u;
+        const uint32_t kk = s_k[j];
+        const uint32_t dg = (kk >> shift) & 255u;
         const uint32_t g = s_gbase[dg] + ((uint32_t)j - s_lstart[dg]);
         if ((int64_t)g < K) {
             kout[g] = kk;
@@ -210,46 +208,43 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint64_t *__res
     }
 }
 
-// Digit histograms of all npass passes (and cleared look-back state).
-// status must hold npass x ceil(K/4096) x 256 words; counters holds npass words
-// plus, at index kMaxPasses, a sticky error flag (look-back gave up waiting)
-// that the owner clears once.
-void launch_sort_hist(const uint64_t *keys, int64_t K, int npass, uint32_t *hist, uint32_t *status,
-                      uint32_t *counters, hipStream_t s) {
-    const int64_t nparts = (K + kSortPart - 1) / kSortPart;
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *hist,
+                         uint32_t *status, uint32_t *ctr, hipStream_t s) {
+    const int nparts = sort_partitions(n_max);
     launch_fill_u32(hist, 0u, (int64_t)npass * kRadix, s);
     launch_fill_u32(status, 0u, (int64_t)npass * nparts * kRadix, s);
-    launch_fill_u32(counters, 0u, npass, s);
-    int64_t hblocks = (K + 256 * 16 - 1) / (256 * 16);
-    if (hblocks > 4096) hblocks = 4096;
-    if (K > 0) hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, K, npass, hist);
-}
-
-// One onesweep pass over digit p (bits 8p .. 8p+7): (ki, vi) -> (ko, vo).
-void launch_sort_pass(const uint64_t *ki, const uint32_t *vi, uint64_t *ko, uint32_t *vo, int64_t K, int p,
-                      const uint32_t *hist, uint32_t *status, uint32_t *counters, hipStream_t s) {
-    const int64_t nparts = (K + kSortPart - 1) / kSortPart;
+    launch_fill_u32(ctr, 0u, npass, s);
     if (nparts == 0) return;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, K, 8 * p,
-                       hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, counters + p);
+    int hblocks = (int)((n_max + 256 * 8 - 1) / (256 * 8));
+    if (hblocks > 2048) hblocks = 2048;
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, n_dev, npass, hist);
+}
+
+void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                      int64_t n_max, int p, const uint32_t *hist, uint32_t *status, uint32_t *ctr, uint32_t *err,
+                      hipStream_t s) {
+    const int nparts = sort_partitions(n_max);
+    if (nparts == 0) return;
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev, 8 * p,
+                       hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
 }
 
 // ------------------------------------------------------------------------
-// tile ranges
+// tile ranges from the sorted tile ids
 // ------------------------------------------------------------------------
-__global__ void k_ranges(const uint64_t *__restrict__ keys, int64_t K, int64_t ntiles, uint32_t *__restrict__ ranges) {
+__global__ void k_ranges(const uint32_t *__restrict__ tiles, int64_t K, int64_t ntiles, uint32_t *__restrict__ ranges) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K) return;
-    const uint64_t t = keys[j] >> 32;
+    const uint32_t t = tiles[j];
     if ((int64_t)t >= ntiles) return;
-    if (j == 0 || (keys[j - 1] >> 32) != t) ranges[2 * t] = (uint32_t)j;
-    if (j == K - 1 || (keys[j + 1] >> 32) != t) ranges[2 * t + 1] = (uint32_t)(j + 1);
+    if (j == 0 || tiles[j - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)j;
+    if (j == K - 1 || tiles[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
 }
 
-void launch_ranges(const uint64_t *keys, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s) {
+void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s) {
     launch_fill_u32(ranges, 0u, 2 * ntiles, s);
     if (K == 0) return;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, keys, K, ntiles, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, tiles, K, ntiles, ranges);
 }
 
 }  // namespace a3fr

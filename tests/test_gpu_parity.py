@@ -73,16 +73,40 @@ def compare_stage_outputs(ctx, ref, views, n):
         for v, vw in enumerate(views):
             if vw.select:
                 np.testing.assert_array_equal(keep[v], ref["keep"][v])
+    # visible entries in depth order, their key offsets, and keys in emission order
+    ent, offs, ekeys, evals = expected_emission(ref, views, n)
+    np.testing.assert_array_equal(_u(ctx.inspect("depth_order", torch.int32), np.uint32), ent)
+    np.testing.assert_array_equal(_u(ctx.inspect("offsets", torch.int32), np.uint32), offs)
     keys = _u(ctx.inspect("keys", torch.int64), np.uint64)
     vals = _u(ctx.inspect("vals", torch.int32), np.uint32)
-    np.testing.assert_array_equal(keys, ref["keys"])
-    np.testing.assert_array_equal(vals, ref["vals"])
+    np.testing.assert_array_equal(keys, ekeys)
+    np.testing.assert_array_equal(vals, evals)
     sk = _u(ctx.inspect("sorted_keys", torch.int64), np.uint64)
     sv = _u(ctx.inspect("sorted_vals", torch.int32), np.uint32)
     np.testing.assert_array_equal(sk, ref["sorted_keys"])
     np.testing.assert_array_equal(sv, ref["sorted_vals"])
     rg = _u(ctx.inspect("ranges", torch.int32), np.uint32).reshape(-1, 2)
     np.testing.assert_array_equal(rg.astype(np.int64), ref["ranges"])
+
+
+def expected_emission(ref, views, n):
+    """From the oracle's arrays: the visible (kept) entries sorted by (depth
+    bits, view, index), the exclusive prefix of their key counts, and the
+    oracle's keys regrouped entry by entry in that order (each entry's keys stay
+    row-major, as the oracle emits them)."""
+    sel = np.array([[vw.select] for vw in views], dtype=bool)
+    eff = np.where(sel, ref["count"] * ref["keep"], ref["count"]).astype(np.int64)
+    v_idx, i_idx = np.nonzero(eff > 0)               # (view, index) order
+    order = np.lexsort((i_idx, v_idx, ref["depth_bits"][v_idx, i_idx]))
+    ent = (v_idx * n + i_idx)[order].astype(np.uint32)
+    cnt = eff[v_idx, i_idx]
+    starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])  # group starts in the oracle's emission
+    c_o = cnt[order]
+    offs = np.concatenate([[0], np.cumsum(c_o)]).astype(np.uint32)
+    K = int(offs[-1])
+    gather = np.repeat(starts[order] - offs[:-1].astype(np.int64), c_o) + np.arange(K)
+    assert K == ref["keys"].size
+    return ent, offs, ref["keys"][gather], ref["vals"][gather]
 
 
 def compare_images(views, ref, rgb, T, last, active):
@@ -271,3 +295,132 @@ def test_invalid_arguments_enqueue_nothing(pkg, ctx):
     v.mask = 7
     with pytest.raises(pkg.A3FRError):
         ctx.preprocess(ds, [v])
+
+
+# ---------------------------------------------------------------------------
+# full size: the foveated stereo frame the benchmark times
+# ---------------------------------------------------------------------------
+def test_full_size_foveated_frame(pkg, ctx):
+    """1M Gaussians, 2 x 1832 x 1920, the launch configuration of the
+    benchmark.  Per-entry integer outputs, the kept set and the whole sorted
+    key list are bit-exact against the oracle; layer pixels are checked on a
+    seeded sample against the brute-force definition (every projectable
+    Gaussian sorted by depth), one pixel at a time; the composite against the
+    oracle's composite of the same layers."""
+    scene, cams = synth.foveated_stereo()
+    W, H = cams[0].width, cams[0].height
+    gz = [(c.cx, c.cy) for c in cams]
+    rad = (0.15 * W, 0.35 * W)
+    views = oracle.foveated_views(cams, gz, rad)
+    ds = pkg.DeviceScene.from_host(scene)
+    # the composite exactly as the benchmark renders it
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.set_debug(False)
+    ctx.render_foveated(ds, cams, gz, pkg.fovea_struct(*rad), out)
+    # the same views through the stage calls, keeping the layer images
+    ctx.preprocess(ds, views)
+    K = ctx.bin_sort()
+    npx = sum(v.width * v.height for v in views)
+    rgb = torch.zeros(3 * npx, device="cuda")
+    T = torch.zeros(npx, device="cuda")
+    ctx.blend(rgb, T, None)
+    ctx.sync()
+    ref = oracle.render(scene, views, blend=False)
+    n = scene.n
+    assert K == ref["keys"].size
+    counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(6, n)
+    vis = ref["vis"].astype(bool)
+    np.testing.assert_array_equal(counts, ref["count"].astype(np.uint32) * vis)
+    depth = _u(ctx.inspect("depth", torch.int32), np.uint32).reshape(6, n)
+    np.testing.assert_array_equal(depth[vis], ref["depth_bits"][vis])
+    keep = ctx.inspect("keep", torch.uint8).cpu().numpy().reshape(6, n)
+    np.testing.assert_array_equal(keep[[2, 5]], ref["keep"][[2, 5]])
+    np.testing.assert_array_equal(_u(ctx.inspect("sorted_keys", torch.int64), np.uint64), ref["sorted_keys"])
+    np.testing.assert_array_equal(_u(ctx.inspect("sorted_vals", torch.int32), np.uint32), ref["sorted_vals"])
+    # sampled layer pixels against the brute-force definition
+    col = oracle.colour(scene, [cams[0].campos, cams[1].campos])
+    ioff = oracle.image_offsets(views)
+    rgb_h, T_h = rgb.cpu().numpy(), T.cpu().numpy()
+    rng = np.random.default_rng(123)
+    n_amb = 0
+    for v, vw in enumerate(views):
+        TX = (vw.width + 15) // 16
+        act = ref["active"][ref["aoff"][v]: ref["aoff"][v + 1]].reshape(-1, TX)
+        ys, xs = np.nonzero(np.kron(act, np.ones((16, 16), np.uint8))[: vw.height, : vw.width])
+        pick = rng.choice(ys.size, size=min(150, ys.size), replace=False)
+        px, py = xs[pick], ys[pick]
+        o_rgb, o_T, o_amb = oracle.blend_pixels(scene, views, ref, ref["keep"], col, v, px, py)
+        HW = vw.width * vw.height
+        a = int(ioff[v])
+        g = np.stack([rgb_h[3 * a + ch * HW + py * vw.width + px] for ch in range(3)], 1)
+        err = np.abs(g - o_rgb)
+        ok = o_amb == 0
+        assert err[ok].max(initial=0.0) <= COLOUR_TOL, (v, err[ok].max())
+        assert err[~ok].max(initial=0.0) <= AMB_TOL
+        assert np.abs(T_h[a + py * vw.width + px] - o_T)[ok].max(initial=0.0) <= COLOUR_TOL
+        n_amb += int((~ok).sum())
+    assert n_amb <= 30
+    # composite of the GPU layers: oracle composite (float64) vs the benchmark's output
+    L = [rgb_h[3 * int(ioff[v]): 3 * int(ioff[v + 1])].reshape(3, vw.height, vw.width).astype(np.float64)
+         for v, vw in enumerate(views)]
+    o = out.cpu().numpy()
+    for e in range(2):
+        want = oracle.composite(W, H, gz[e], rad, L[3 * e], L[3 * e + 1], L[3 * e + 2])
+        assert np.abs(o[e] - want).max() <= 2e-6
+
+
+def test_full_size_full_res_frame_sampled(pkg, ctx):
+    """The plain full-resolution stereo render at full size: per-entry outputs
+    bit-exact, sampled pixels against the brute-force definition."""
+    scene, cams = synth.foveated_stereo()
+    views = [oracle.full_view(c, e) for e, c in enumerate(cams)]
+    ds = pkg.DeviceScene.from_host(scene)
+    W, H = cams[0].width, cams[0].height
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.set_debug(False)
+    ctx.render_full(ds, cams, out)
+    ctx.sync()
+    act, aoff = oracle.tile_masks(views)
+    pr = oracle.project(scene, views, active=act, aoff=aoff)
+    counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(2, scene.n)
+    np.testing.assert_array_equal(counts, pr["count"].astype(np.uint32) * pr["vis"])
+    assert ctx.get_counts()["n_keys"] == int(pr["count"].sum())
+    col = oracle.colour(scene, [cams[0].campos, cams[1].campos])
+    rng = np.random.default_rng(321)
+    o = out.cpu().numpy()
+    for e in range(2):
+        px, py = rng.integers(0, W, 200), rng.integers(0, H, 200)
+        o_rgb, o_T, o_amb = oracle.blend_pixels(scene, views, pr, None, col, e, px, py)
+        g = o[e][:, py, px].T
+        ok = o_amb == 0
+        assert np.abs(g - o_rgb)[ok].max() <= COLOUR_TOL
+        assert np.abs(g - o_rgb)[~ok].max(initial=0.0) <= AMB_TOL
+
+
+def test_blend_pair_count_matches_oracle(pkg, ctx):
+    """The evaluated-pair counter behind the blend roofline counts what the
+    oracle counts: per pixel, the list entries evaluated until it stops."""
+    W, H = 232, 240
+    scene, cams = synth.foveated_stereo(n=60_000, width=W, height=H, seed=4)
+    views = oracle.foveated_views(cams, [(c.cx, c.cy) for c in cams], (0.15 * W, 0.35 * W))
+    ref = oracle.render(scene, views)
+    ds = pkg.DeviceScene.from_host(scene)
+    ctx.set_debug(False)
+    ctx.preprocess(ds, views)
+    ctx.bin_sort()
+    npx = sum(v.width * v.height for v in views)
+    rgb = torch.zeros(3 * npx, device="cuda")
+    ctx.set_profiling(True)
+    ctx.blend(rgb)
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    want = 0
+    amb_pairs = 0
+    for v, vw in enumerate(views):
+        TX = (vw.width + 15) // 16
+        act = ref["active"][ref["aoff"][v]: ref["aoff"][v + 1]].reshape(-1, TX)
+        pm = np.kron(act, np.ones((16, 16), np.uint8))[: vw.height, : vw.width].astype(bool)
+        want += int(ref["images"][v]["pairs"][pm].sum())
+        amb_pairs += int(ref["images"][v]["pairs"][pm & ref["images"][v]["amb"].astype(bool)].sum())
+    assert abs(prof["blend_pairs"] - want) <= amb_pairs + 1
+    assert prof["stages"]["blend"]["launches"] == 1
