@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2, help="oracle frames timed for the CPU baseline")
     ap.add_argument("--only", choices=["both", "foveated", "full"], default="both",
                     help="restrict the timed loops (for profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the renderer has no multi-GPU path; "
@@ -67,6 +69,13 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
     t0 = time.time()
     scene, cams = synth.foveated_stereo(n=args.gaussians)
     W, H = cams[0].width, cams[0].height
