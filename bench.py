@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "stereo frames/s @1M Gaussians, foveated vs full-res on GPU, periphery PSNR≥30dB"
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 FP32_VECTOR_PEAK_TF = 157.3   # MI355X FP32 vector (packed) peak
-SORT_BYTES_PER_KEY_PASS = 24  # read key (8) + value (4), write key (8) + value (4)
+SORT_BYTES_PER_KEY_PASS = 16  # tile-id sort: read key (4) + value (4), write key (4) + value (4)
 BLEND_FLOPS_PER_PAIR = 18
 PREPROCESS_READ_PER_GAUSSIAN = 236
 PREPROCESS_WRITE_PER_VISIBLE = 64  # record 48 + depth 4 + rect 8 + count 4

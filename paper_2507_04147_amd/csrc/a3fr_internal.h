@@ -40,13 +40,9 @@ struct DevView {
     int64_t tile_off;     // first global tile id
     int64_t img_off;      // first pixel of this view in the concatenated images
     int64_t mask_off;     // offset of this view's row tables (rows x (tiles_x + 1)) in the mask arrays
+    int64_t cum_off;      // offset of this view's 2D active-tile prefix ((rows + 1) x (tiles_x + 1))
     int32_t sel_slot;     // index among selecting views, -1 if none
     int32_t pad;
-};
-
-// Per-selecting-view state of the periphery radix select.
-struct SelectState {
-    uint32_t hist[12][256];   // per pass digit histogram of the candidates
 };
 
 // Lookback status word of the onesweep sort: [31:30] flag, [29:0] count.
@@ -61,9 +57,12 @@ void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const i
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, hipStream_t s);
+void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
+                         int64_t m, Record *rec, hipStream_t s);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
-                   uint32_t *sel_hist /* [nsel][12][256] */, uint8_t *keep, hipStream_t s);
+                   uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s);
+int64_t select_workspace_words(int nsel, int64_t n);
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
                             const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *block_sums,
                             uint64_t *total, uint32_t *n_ent, hipStream_t s);
@@ -71,15 +70,18 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
                         uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s);
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
-                 uint32_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s);
+                 const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
+                 hipStream_t s);
+void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
+                     hipStream_t s);
 void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
                         int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s);
 int sort_partitions(int64_t n);
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *hist,
-                         uint32_t *status, uint32_t *ctr, hipStream_t s);
+int64_t sort_workspace_words(int64_t n_max, int npass);
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
+                         hipStream_t s);
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int p, const uint32_t *hist, uint32_t *status, uint32_t *ctr, uint32_t *err,
-                      hipStream_t s);
+                      int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
 void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
 void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                   const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,

@@ -35,6 +35,8 @@ struct a3fr_ctx {
     int nsel = 0;
     int64_t rows_total = 0;
     int64_t mask_entries = 0;
+    int64_t cum_entries = 0;
+    int max_tiles_x = 1;
     std::vector<DevView> hviews;
     std::vector<int32_t> hrow_view, hrow_y, hsel_views;
     // pinned staging for uploads and small readbacks
@@ -49,7 +51,7 @@ struct a3fr_ctx {
     DevBuf ent_a, ent_b, dkey_a, dkey_b;       // visible entries, depth sort
     DevBuf keys_a, keys_b, vals_a, vals_b, big_list, big_count;
     DevBuf sort_hist, sort_status, sort_counters, ranges;
-    DevBuf layers, sse_part, sse_cnt;
+    DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
     bool keep_emission = false;
     // per-stage event timing
@@ -249,7 +251,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->big_list, &c->big_count, &c->sort_hist,
                       &c->sort_status, &c->sort_counters, &c->ranges, &c->layers, &c->sse_part,
-                      &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count};
+                      &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -344,7 +346,8 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     c->hrow_view.clear();
     c->hrow_y.clear();
     c->hsel_views.clear();
-    int64_t toff = 0, ioff = 0, moff = 0;
+    int64_t toff = 0, ioff = 0, moff = 0, coff = 0;
+    int max_tx = 1;
     for (int k = 0; k < nv; ++k) {
         DevView &d = c->hviews[k];
         std::memset(&d, 0, sizeof(d));
@@ -354,6 +357,9 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
         d.tile_off = toff;
         d.img_off = ioff;
         d.mask_off = views[k].mask == A3FR_MASK_ALL ? -1 : moff;
+        d.cum_off = views[k].mask == A3FR_MASK_ALL ? -1 : coff;
+        if (views[k].mask != A3FR_MASK_ALL) coff += (int64_t)(d.tiles_y + 1) * (d.tiles_x + 1);
+        if (d.tiles_x > max_tx) max_tx = d.tiles_x;
         d.sel_slot = views[k].select ? (int32_t)c->hsel_views.size() : -1;
         if (views[k].select) c->hsel_views.push_back(k);
         if (views[k].mask != A3FR_MASK_ALL) moff += (int64_t)d.tiles_y * (d.tiles_x + 1);
@@ -372,16 +378,16 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     c->nsel = (int)c->hsel_views.size();
     c->rows_total = (int64_t)c->hrow_view.size();
     c->mask_entries = moff;
+    c->cum_entries = coff;
+    c->max_tiles_x = max_tx;
     c->preprocessed = false;
     c->sorted = false;
 
     // ---- workspace
     const int64_t m = (int64_t)nv * n;
-    TRY(ensure(c, c->views, sizeof(DevView) * nv));
-    TRY(ensure(c, c->row_view, sizeof(int32_t) * c->rows_total));
-    TRY(ensure(c, c->row_y, sizeof(int32_t) * c->rows_total));
     TRY(ensure(c, c->row_prefix, sizeof(uint16_t) * moff));
     TRY(ensure(c, c->row_list, sizeof(uint16_t) * moff));
+    TRY(ensure(c, c->cum, sizeof(uint32_t) * coff));
     TRY(ensure(c, c->active, (size_t)toff));
     TRY(ensure(c, c->counts, sizeof(uint32_t) * m));
     TRY(ensure(c, c->depth, sizeof(uint32_t) * m));
@@ -389,8 +395,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     TRY(ensure(c, c->rec, sizeof(Record) * m));
     TRY(ensure(c, c->score, c->nsel ? sizeof(double) * m : 16));
     TRY(ensure(c, c->keep, c->nsel ? (size_t)m : 16));
-    TRY(ensure(c, c->sel_views, sizeof(int32_t) * (c->nsel + 1)));
-    TRY(ensure(c, c->sel, sizeof(uint32_t) * ((size_t)c->nsel * 12 * 256 + (size_t)c->nsel * 32 + 32)));
+    TRY(ensure(c, c->sel, sizeof(uint32_t) * (size_t)select_workspace_words(c->nsel, n)));
     TRY(ensure(c, c->offsets, sizeof(uint32_t) * (m + 1)));
     TRY(ensure(c, c->block_sums, sizeof(uint64_t) * ((m + 4095) / 4096 + 1)));
     if (!c->scalars.p) {
@@ -401,38 +406,39 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_a, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->sort_hist, sizeof(uint32_t) * 4 * 256));
-    TRY(ensure(c, c->sort_counters, sizeof(uint32_t) * 8));
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * 4 * (size_t)sort_partitions(m) * 256));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4)));
 
-    // ---- uploads through pinned staging
+    // ---- one upload through pinned staging: [views | row views | row ys | selecting views]
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes_v = sizeof(DevView) * nv, bytes_r = sizeof(int32_t) * c->rows_total,
                  bytes_s = sizeof(int32_t) * (c->nsel + 1);
-    TRY(ensure_pinned(c, bytes_v + 2 * bytes_r + bytes_s + 64));
+    const size_t o_rv = al(bytes_v), o_ry = o_rv + al(bytes_r), o_sv = o_ry + al(bytes_r), total = o_sv + al(bytes_s);
+    TRY(ensure(c, c->views, total));
+    TRY(ensure_pinned(c, total));
     char *pin = static_cast<char *>(c->pinned);
     std::memcpy(pin, c->hviews.data(), bytes_v);
-    std::memcpy(pin + bytes_v, c->hrow_view.data(), bytes_r);
-    std::memcpy(pin + bytes_v + bytes_r, c->hrow_y.data(), bytes_r);
-    if (c->nsel) std::memcpy(pin + bytes_v + 2 * bytes_r, c->hsel_views.data(), sizeof(int32_t) * c->nsel);
-    HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, bytes_v, hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(c->row_view.p, pin + bytes_v, bytes_r, hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(c->row_y.p, pin + bytes_v + bytes_r, bytes_r, hipMemcpyHostToDevice, c->stream));
-    if (c->nsel)
-        HIPCHECK(c, hipMemcpyAsync(c->sel_views.p, pin + bytes_v + 2 * bytes_r, sizeof(int32_t) * c->nsel,
-                                   hipMemcpyHostToDevice, c->stream));
+    std::memcpy(pin + o_rv, c->hrow_view.data(), bytes_r);
+    std::memcpy(pin + o_ry, c->hrow_y.data(), bytes_r);
+    if (c->nsel) std::memcpy(pin + o_sv, c->hsel_views.data(), sizeof(int32_t) * c->nsel);
+    HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, total, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->upload_done, c->stream));
+    char *frame = static_cast<char *>(c->views.p);
+    const int32_t *d_row_view = reinterpret_cast<const int32_t *>(frame + o_rv);
+    const int32_t *d_row_y = reinterpret_cast<const int32_t *>(frame + o_ry);
+    const int32_t *d_sel_views = reinterpret_cast<const int32_t *>(frame + o_sv);
 
     // ---- kernels
     const DevView *dv = P<DevView>(c->views);
     { StageTimer t_(c, A3FR_STAGE_MASKS);
-    launch_tile_masks(dv, nv, c->rows_total, P<int32_t>(c->row_view), P<int32_t>(c->row_y),
-                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream); }
+    launch_tile_masks(dv, nv, c->rows_total, d_row_view, d_row_y,
+                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream);
+      if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, nv, nullptr, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
                       c->stream); }
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
-        launch_select(dv, nv, P<int32_t>(c->sel_views), c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
+        launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
                       keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream); }
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
@@ -440,16 +446,19 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                                P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
                                sc_ent_total(c->scalars), sc_n_ent(c->scalars), c->stream);
     }
+    {
+        StageTimer t_(c, A3FR_STAGE_PREPROCESS);
+        launch_entry_colour(*scene, dv, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m, P<Record>(c->rec), c->stream);
+    }
     {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
         StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
-        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, P<uint32_t>(c->sort_hist),
-                            P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
+        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, P<uint32_t>(c->sort_status),
+                            c->stream);
         uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
         uint32_t *vi = P<uint32_t>(c->ent_a), *vo = P<uint32_t>(c->ent_b);
         for (int p = 0; p < 4; ++p) {
-            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, p, P<uint32_t>(c->sort_hist),
-                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), sc_err(c->scalars),
-                             c->stream);
+            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, p, P<uint32_t>(c->sort_status),
+                             sc_err(c->scalars), c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
         }
@@ -479,19 +488,18 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     TRY(ensure(c, c->keys_b, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_a, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_b, sizeof(uint32_t) * K));
-    TRY(ensure(c, c->big_list, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->big_count, sizeof(uint32_t) * 4));
+    TRY(ensure(c, c->chunk_start, sizeof(uint32_t) * ((K + 63) / 64 + 1)));
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
     const int npass = (tile_bits + 7) / 8;
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)npass * sort_partitions((int64_t)K) * 256));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass)));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
     {
         StageTimer t_(c, A3FR_STAGE_EMIT);
         launch_emit(dv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
-                    P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->keys_a),
-                    P<uint32_t>(c->vals_a), P<uint32_t>(c->big_list), P<uint32_t>(c->big_count), c->stream);
+                    P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
+                    P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K, c->stream);
     }
     if (c->keep_emission) {
         TRY(ensure(c, c->keys_e, sizeof(uint32_t) * K));
@@ -505,14 +513,12 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (K > 1) {
         {
             StageTimer t_(c, A3FR_STAGE_SORT_HIST);
-            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, P<uint32_t>(c->sort_hist),
-                                P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), c->stream);
+            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, P<uint32_t>(c->sort_status), c->stream);
         }
         for (int p = 0; p < npass; ++p) {
             StageTimer t_(c, A3FR_STAGE_SORT_PASS);
-            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, p, P<uint32_t>(c->sort_hist),
-                             P<uint32_t>(c->sort_status), P<uint32_t>(c->sort_counters), sc_err(c->scalars),
-                             c->stream);
+            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, npass, p,
+                             P<uint32_t>(c->sort_status), sc_err(c->scalars), c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
             in_b = !in_b;
@@ -690,11 +696,12 @@ a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
     if (!c->preprocessed) return A3FR_OK;
     std::vector<uint8_t> act(c->ntiles > 0 ? c->ntiles : 1);
     HIPCHECK(c, hipMemcpyAsync(act.data(), c->active.p, (size_t)c->ntiles, hipMemcpyDeviceToHost, c->stream));
-    // SelState (bin.hip): {n_vis, k, k_rem, done, mode, npass, pad[2], digit[12]} = 20 words per slot
-    constexpr int kSelWords = 20;
+    // SelState (bin.hip): {n_vis, k, k_rem, mode, b0, b1, ncand, pad} = 8 words per slot, after the
+    // two 4096-bucket histogram levels
+    constexpr int kSelWords = 8;
     std::vector<uint32_t> st((size_t)c->nsel * kSelWords + 1);
     if (c->nsel)
-        HIPCHECK(c, hipMemcpyAsync(st.data(), P<uint32_t>(c->sel) + (size_t)c->nsel * 12 * 256,
+        HIPCHECK(c, hipMemcpyAsync(st.data(), P<uint32_t>(c->sel) + (size_t)c->nsel * 2 * 4096,
                                    sizeof(uint32_t) * kSelWords * c->nsel, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     for (int64_t t = 0; t < c->ntiles; ++t) out->n_active_tiles += act[t];

@@ -22,140 +22,236 @@ namespace a3fr {
 // ------------------------------------------------------------------------
 // periphery select
 // ------------------------------------------------------------------------
+// Selection key of visible Gaussian i: the 96-bit (score bits, ~i) -- score
+// descending, index ascending.  Scores are non-negative doubles, so their bit
+// patterns order like the values and bit 63 is 0.
+//   1. two histogram levels of 12 bits each (score bits 62..51, then 50..39 of
+//      the Gaussians in the chosen level-1 bucket), per block in LDS; after
+//      each, one block per view picks the bucket holding the k-th largest key;
+//   2. every visible Gaussian outside the chosen 24-bit bucket is decided at
+//      once, those inside are listed as candidates (usually a handful);
+//   3. one block per view runs an MSD radix select over the candidates'
+//      remaining 71 key bits (score bits 38..0, ~index) and marks the kept ones.
+constexpr int kSelBits = 12;
+constexpr int kSelBuckets = 1 << kSelBits;
+constexpr int kSelLow = 63 - 2 * kSelBits;      // 39 score bits below the two levels
+constexpr int kSelKeyBits = kSelLow + 32;       // candidate key bits
+constexpr int kSelDigits = (kSelKeyBits + 7) / 8;
+
 struct SelState {
-    uint32_t n_vis, k, k_rem, done;   // done: 0 running, 1 finished
-    uint32_t mode;                    // 0: compare digits, 1: keep all visible, 2: keep none
-    uint32_t npass;                   // digits[0..npass) define the kept prefix
-    uint32_t pad[2];
-    uint32_t digit[12];
+    uint32_t n_vis, k, k_rem, mode;  // mode 0: select, 1: keep all visible, 2: keep none
+    uint32_t b0, b1, ncand, pad;     // chosen level buckets
 };
 
-__device__ __forceinline__ uint32_t sel_digit(double score, uint32_t idx, int pass) {
-    const uint64_t sb = (uint64_t)__double_as_longlong(score);
-    if (pass < 8) return (uint32_t)(sb >> (56 - 8 * pass)) & 255u;
-    return ((~idx) >> (24 - 8 * (pass - 8))) & 255u;
-}
-
-__global__ void k_sel_init(SelState *st, uint32_t *hist, int nsel) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nsel * (int)(sizeof(SelState) / 4)) reinterpret_cast<uint32_t *>(st)[t] = 0;
-    for (int j = t; j < nsel * 12 * 256; j += gridDim.x * blockDim.x) hist[j] = 0;
+__device__ __forceinline__ uint32_t sel_level(uint64_t bits, int level) {
+    return (uint32_t)(bits >> (63 - kSelBits * (level + 1))) & (uint32_t)(kSelBuckets - 1);
 }
 
 __global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, const uint32_t *__restrict__ counts,
-                                                  const double *__restrict__ score, int64_t n, int pass,
+                                                  const double *__restrict__ score, int64_t n, int level,
                                                   const SelState *st, uint32_t *hist) {
     const int slot = blockIdx.y;
-    if (st[slot].done) return;
-    __shared__ uint32_t h[256];
-    __shared__ uint32_t dig[12];
-    h[threadIdx.x] = 0;
-    if (threadIdx.x < 12) dig[threadIdx.x] = st[slot].digit[threadIdx.x];
+    if (level > 0 && st[slot].mode != 0) return;
+    __shared__ uint32_t lh[kSelBuckets];
+    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x) lh[b] = 0;
     __syncthreads();
+    const uint32_t b0 = level > 0 ? st[slot].b0 : 0u;
     const int64_t base = (int64_t)sel_views[slot] * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (counts[base + i] == 0) continue;
-        const double sc = score[base + i];
-        bool match = true;
-        for (int p = 0; p < pass; ++p)
-            if (sel_digit(sc, (uint32_t)i, p) != dig[p]) { match = false; break; }
-        if (match) atomicAdd(&h[sel_digit(sc, (uint32_t)i, pass)], 1u);
+        const uint64_t bits = (uint64_t)__double_as_longlong(score[base + i]);
+        if (level > 0 && sel_level(bits, 0) != b0) continue;
+        atomicAdd(&lh[sel_level(bits, level)], 1u);
     }
     __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&hist[((int64_t)slot * 12 + pass) * 256 + threadIdx.x], h[threadIdx.x]);
+    uint32_t *h = hist + ((int64_t)slot * 2 + level) * kSelBuckets;
+    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x)
+        if (lh[b]) atomicAdd(&h[b], lh[b]);
 }
 
-__global__ void __launch_bounds__(256) k_sel_decide(int pass, int keep_num, int keep_den, SelState *st,
-                                                    const uint32_t *hist) {
-    const int slot = blockIdx.x;
+// One block of 1024 threads per view: thread t owns kSelBuckets/1024
+// consecutive buckets, the highest first; finds the bucket holding the
+// k_rem-th largest key of this level.
+__global__ void __launch_bounds__(1024) k_sel_pick(const uint32_t *hist, int level, int keep_num, int keep_den,
+                                                   SelState *st) {
+    constexpr int kPer = kSelBuckets / 1024;
+    const int slot = blockIdx.x, t = threadIdx.x;
     SelState &S = st[slot];
-    if (S.done) return;
-    const int d = threadIdx.x;
-    __shared__ uint32_t suf[257];
-    const uint32_t h = hist[((int64_t)slot * 12 + pass) * 256 + d];
-    suf[d] = h;
-    if (d == 0) suf[256] = 0;
-    __syncthreads();
-    // inclusive suffix sums suf[d] = sum_{d' >= d} h[d'] (Hillis-Steele over 256)
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t add = (d + off < 256) ? suf[d + off] : 0u;
-        __syncthreads();
-        suf[d] += add;
-        __syncthreads();
+    if (level > 0 && S.mode != 0) return;
+    const uint32_t *h = hist + ((int64_t)slot * 2 + level) * kSelBuckets;
+    const int hi = kSelBuckets - kPer * t;
+    uint32_t loc = 0;
+    for (int b = hi - 1; b >= hi - kPer; --b) loc += h[b];
+    __shared__ uint32_t wsum[16];
+    const int lane = t & 63, w = t >> 6;
+    uint32_t inc = loc;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
     }
-    __shared__ uint32_t s_krem, s_done;
-    if (d == 0) {
-        uint32_t done = 0;
-        if (pass == 0) {
-            const uint32_t nvis = suf[0];
-            const uint64_t k = ((uint64_t)keep_num * nvis + (uint64_t)keep_den - 1) / (uint64_t)keep_den;
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+        if (q < w) pre += wsum[q];
+        tot += wsum[q];
+    }
+    const uint32_t above0 = pre + inc - loc;
+    uint64_t k;
+    if (level == 0) {
+        const uint32_t nvis = tot;
+        k = ((uint64_t)keep_num * nvis + (uint64_t)keep_den - 1) / (uint64_t)keep_den;
+        __syncthreads();
+        if (t == 0) {
             S.n_vis = nvis;
             S.k = (uint32_t)k;
-            S.k_rem = (uint32_t)k;
-            if (k == 0) { S.mode = 2; done = 1; }
-            else if (k >= nvis) { S.mode = 1; done = 1; }
-            if (done) S.done = 1;
+            S.ncand = 0;
+            S.mode = k == 0 ? 2u : (k >= nvis ? 1u : 0u);
         }
-        s_krem = S.k_rem;
-        s_done = done;
+        if (k == 0 || k >= nvis) return;
+    } else {
+        k = S.k_rem;
+        __syncthreads();
     }
-    __syncthreads();
-    if (s_done) return;
-    const uint32_t krem = s_krem;
-    const uint32_t above = suf[d + 1];
-    if (suf[d] >= krem && above < krem) {
-        const uint32_t k2 = krem - above;
-        S.digit[pass] = (uint32_t)d;
-        S.k_rem = k2;
-        S.npass = (uint32_t)pass + 1;
-        if (h == k2 || pass == 11) S.done = 1;
+    if (above0 < k && above0 + loc >= k) {
+        uint32_t above = above0;
+        for (int b = hi - 1; b >= hi - kPer; --b) {
+            const uint32_t c = h[b];
+            if (above + c >= k) {
+                if (level == 0) S.b0 = (uint32_t)b; else S.b1 = (uint32_t)b;
+                S.k_rem = (uint32_t)(k - above);
+                break;
+            }
+            above += c;
+        }
     }
 }
 
-__global__ void __launch_bounds__(256) k_sel_mark(const int32_t *sel_views, const uint32_t *__restrict__ counts,
-                                                  const double *__restrict__ score, int64_t n, const SelState *st,
-                                                  uint8_t *keep) {
+__global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, const uint32_t *__restrict__ counts,
+                                                    const double *__restrict__ score, int64_t n, SelState *st,
+                                                    uint64_t *cand_key, uint32_t *cand_idx, uint8_t *keep) {
     const int slot = blockIdx.y;
-    __shared__ uint32_t dig[12];
-    if (threadIdx.x < 12) dig[threadIdx.x] = st[slot].digit[threadIdx.x];
-    __syncthreads();
-    const uint32_t mode = st[slot].mode, npass = st[slot].npass;
     const int64_t base = (int64_t)sel_views[slot] * n;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t mode = st[slot].mode;
+    const uint32_t top = (st[slot].b0 << kSelBits) | st[slot].b1;  // chosen 24-bit prefix
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
         uint8_t kp = 0;
-        if (counts[base + i] != 0) {
-            if (mode == 1) kp = 1;
-            else if (mode == 0) {
-                const double sc = score[base + i];
-                kp = 1;  // equal through the decided prefix: the bucket is kept whole
-                for (uint32_t p = 0; p < npass; ++p) {
-                    const uint32_t dg = sel_digit(sc, (uint32_t)i, (int)p);
-                    if (dg != dig[p]) { kp = dg > dig[p] ? 1 : 0; break; }
-                }
+        bool cand = false;
+        uint64_t bits = 0;
+        if (i < n && counts[base + i] != 0) {
+            if (mode == 1) {
+                kp = 1;
+            } else if (mode == 0) {
+                bits = (uint64_t)__double_as_longlong(score[base + i]);
+                const uint32_t tb = (uint32_t)(bits >> kSelLow);
+                kp = tb > top ? 1 : 0;
+                cand = tb == top;
             }
         }
-        keep[base + i] = kp;
+        const uint64_t m = __ballot(cand);  // one atomic per wave for its candidates
+        if (m) {
+            uint32_t first = 0;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            if (lane == leader) first = atomicAdd(&st[slot].ncand, (uint32_t)__popcll(m));
+            first = __shfl(first, leader, 64);
+            if (cand) {
+                const uint32_t c = first + (uint32_t)__popcll(m & lt);
+                cand_key[(int64_t)slot * n + c] = bits & ((1ull << kSelLow) - 1);
+                cand_idx[(int64_t)slot * n + c] = (uint32_t)i;
+            }
+        }
+        if (i < n) keep[base + i] = kp;
+    }
+}
+
+// Candidate key (score low bits, ~index) as a 128-bit integer: larger is kept first.
+__device__ __forceinline__ unsigned __int128 sel_ckey(uint64_t lo, uint32_t idx) {
+    return ((unsigned __int128)lo << 32) | (unsigned __int128)(~idx);
+}
+
+__global__ void __launch_bounds__(1024) k_sel_final(const int32_t *sel_views, int64_t n, const SelState *st,
+                                                    const uint64_t *cand_key, const uint32_t *cand_idx,
+                                                    uint8_t *keep) {
+    const int slot = blockIdx.x, t = threadIdx.x;
+    if (st[slot].mode != 0) return;
+    const uint32_t nc = st[slot].ncand;
+    const uint64_t *ck = cand_key + (int64_t)slot * n;
+    const uint32_t *ci = cand_idx + (int64_t)slot * n;
+    const int64_t base = (int64_t)sel_views[slot] * n;
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_krem, s_done, s_np;
+    __shared__ unsigned long long s_pre_hi, s_pre_lo;  // chosen key prefix (digits so far), 128-bit
+    if (t == 0) { s_krem = st[slot].k_rem; s_done = 0; s_np = 0; s_pre_hi = 0; s_pre_lo = 0; }
+    __syncthreads();
+    for (int p = 0; p < kSelDigits; ++p) {
+        const int sh = kSelDigits * 8 - 8 * (p + 1);  // shift of digit p in the zero-padded key
+        if (t < 256) hist[t] = 0;
+        __syncthreads();
+        const unsigned __int128 pre = ((unsigned __int128)s_pre_hi << 64) | s_pre_lo;
+        for (uint32_t c = t; c < nc; c += blockDim.x) {
+            const unsigned __int128 key = sel_ckey(ck[c], ci[c]) << (kSelDigits * 8 - kSelKeyBits);
+            if (p == 0 || (key >> (sh + 8)) == pre) atomicAdd(&hist[(uint32_t)(key >> sh) & 255u], 1u);
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t above = 0;
+            const uint32_t kr = s_krem;
+            for (int d = 255; d >= 0; --d) {
+                const uint32_t c = hist[d];
+                if (above + c >= kr) {
+                    const unsigned __int128 np = (pre << 8) | (unsigned __int128)d;
+                    s_pre_hi = (unsigned long long)(np >> 64);
+                    s_pre_lo = (unsigned long long)np;
+                    s_krem = kr - above;
+                    s_np = (uint32_t)p + 1;
+                    if (c == kr - above) s_done = 1;
+                    break;
+                }
+                above += c;
+            }
+        }
+        __syncthreads();
+        if (s_done) break;
+    }
+    // kept: candidates whose key prefix (s_np digits) is >= the chosen prefix
+    const int sh = kSelDigits * 8 - 8 * (int)s_np;
+    const unsigned __int128 pre = ((unsigned __int128)s_pre_hi << 64) | s_pre_lo;
+    for (uint32_t c = t; c < nc; c += blockDim.x) {
+        const unsigned __int128 key = sel_ckey(ck[c], ci[c]) << (kSelDigits * 8 - kSelKeyBits);
+        keep[base + ci[c]] = (key >> sh) >= pre ? 1 : 0;
     }
 }
 
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
-                   uint32_t *sel_hist, uint8_t *keep, hipStream_t s) {
+                   uint32_t *sel_ws, uint8_t *keep, hipStream_t s) {
     (void)views; (void)nv;
     if (nsel == 0 || n == 0) return;
-    // state lives right after the histograms
-    SelState *st = reinterpret_cast<SelState *>(sel_hist + (int64_t)nsel * 12 * 256);
-    hipLaunchKernelGGL(k_sel_init, dim3(64), dim3(256), 0, s, st, sel_hist, nsel);
+    // workspace: hist [nsel][2][4096] u32 | state [nsel] (8 words) | cand_key [nsel][n] u64 | cand_idx [nsel][n] u32
+    uint32_t *hist = sel_ws;
+    SelState *st = reinterpret_cast<SelState *>(sel_ws + (int64_t)nsel * 2 * kSelBuckets);
+    uint64_t *ck = reinterpret_cast<uint64_t *>(sel_ws + (int64_t)nsel * 2 * kSelBuckets + (int64_t)nsel * 8);
+    uint32_t *ci = reinterpret_cast<uint32_t *>(ck + (int64_t)nsel * n);
+    launch_fill_u32(hist, 0u, (int64_t)nsel * 2 * kSelBuckets, s);
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    for (int pass = 0; pass < 12; ++pass) {
-        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)blocks, (unsigned)nsel), dim3(256), 0, s, sel_views, counts,
-                           score, n, pass, st, sel_hist);
-        hipLaunchKernelGGL(k_sel_decide, dim3((unsigned)nsel), dim3(256), 0, s, pass, keep_num, keep_den, st,
-                           sel_hist);
+    if (blocks > 1024) blocks = 1024;
+    const unsigned hb = (unsigned)(blocks < 256 ? blocks : 256);
+    for (int level = 0; level < 2; ++level) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(hb, (unsigned)nsel), dim3(256), 0, s, sel_views, counts, score, n, level, st,
+                           hist);
+        hipLaunchKernelGGL(k_sel_pick, dim3((unsigned)nsel), dim3(1024), 0, s, hist, level, keep_num, keep_den, st);
     }
-    hipLaunchKernelGGL(k_sel_mark, dim3((unsigned)blocks, (unsigned)nsel), dim3(256), 0, s, sel_views, counts,
-                       score, n, st, keep);
+    hipLaunchKernelGGL(k_sel_gather, dim3((unsigned)blocks, (unsigned)nsel), dim3(256), 0, s, sel_views, counts, score,
+                       n, st, ck, ci, keep);
+    hipLaunchKernelGGL(k_sel_final, dim3((unsigned)nsel), dim3(1024), 0, s, sel_views, n, st, ck, ci, keep);
+}
+
+// words of select workspace (hist, state, candidates) for nsel views of n Gaussians
+int64_t select_workspace_words(int nsel, int64_t n) {
+    return (int64_t)nsel * 2 * kSelBuckets + (int64_t)nsel * 8 + (int64_t)nsel * n * 3 + 4;
 }
 
 // ------------------------------------------------------------------------
@@ -338,28 +434,58 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
 // ------------------------------------------------------------------------
 // key emission (entries in depth order)
 // ------------------------------------------------------------------------
-constexpr uint32_t kBigKeys = 48;  // entries with more keys go to the cooperative path
+// One thread per output key, so every wavefront writes 64 consecutive keys
+// (coalesced) whatever the sizes of the entries.  A first kernel records, for
+// every 64-key chunk, the entry holding its first key; the chunk's keys then
+// belong to at most 64 consecutive entries, whose offsets the wavefront stages
+// in LDS and binary-searches.  Within its entry a key's tile is found
+// directly: column-major division of the rectangle for views with every tile
+// active; for masked views, a binary search over rows of the view's 2D prefix
+// table of active tiles (cum[ty][tx] = active tiles in rows < ty, columns < tx),
+// then the row's list of active columns.
 
 __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y0, int &y1) {
     x0 = (int)(r & 0xffff); x1 = (int)((r >> 16) & 0xffff);
     y0 = (int)((r >> 32) & 0xffff); y1 = (int)((r >> 48) & 0xffff);
 }
 
-__global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views, int64_t n,
-                                              const uint32_t *__restrict__ ent, const uint32_t *n_ent,
-                                              const uint32_t *__restrict__ offsets, const uint64_t *__restrict__ rect,
-                                              const uint16_t *__restrict__ row_prefix,
-                                              const uint16_t *__restrict__ row_list, uint32_t *__restrict__ keys,
-                                              uint32_t *__restrict__ vals, uint32_t *big_list, uint32_t *big_count) {
+__global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
+                                                      uint32_t *__restrict__ chunk_start) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent) return;
-    const uint32_t off = offsets[j];
-    const uint32_t cnt = offsets[j + 1] - off;
-    if (cnt == 0) return;
-    if (cnt > kBigKeys) {
-        big_list[atomicAdd(big_count, 1u)] = (uint32_t)j;
-        return;
+    const uint32_t lo = offsets[j], hi = offsets[j + 1];
+    for (uint32_t c = (lo + 63) >> 6; ((uint64_t)c << 6) < hi; ++c) chunk_start[c] = (uint32_t)j;
+}
+
+__global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, int64_t n,
+                                             const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                             const uint32_t *__restrict__ offsets,
+                                             const uint32_t *__restrict__ chunk_start,
+                                             const uint64_t *__restrict__ rect,
+                                             const uint16_t *__restrict__ row_prefix,
+                                             const uint16_t *__restrict__ row_list, const uint32_t *__restrict__ cum,
+                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t K) {
+    __shared__ uint32_t s_off[65];
+    const int lane = threadIdx.x;
+    const int64_t q0 = (int64_t)blockIdx.x * 64;
+    const int64_t E = *n_ent;
+    const uint32_t j0 = chunk_start[blockIdx.x];
+    {
+        const int64_t jj = (int64_t)j0 + lane;
+        s_off[lane] = offsets[jj < E ? jj : E];
+        if (lane == 0) s_off[64] = offsets[(int64_t)j0 + 64 < E ? (int64_t)j0 + 64 : E];
     }
+    __syncthreads();
+    const int64_t q = q0 + lane;
+    if (q >= K) return;
+    // largest k with s_off[k] <= q (s_off[0] <= q0 <= q < s_off[64] or = K)
+    int lo = 0, hi = 64;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)s_off[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int64_t j = (int64_t)j0 + lo;
+    const uint32_t r = (uint32_t)(q - s_off[lo]);
     const int64_t e = ent[j];
     const int v = (int)(e / n);
     const DevView &dv = views[v];
@@ -367,75 +493,56 @@ __global__ void __launch_bounds__(256) k_emit(const DevView *__restrict__ views,
     int x0, x1, y0, y1;
     unpack_rect(rect[e], x0, x1, y0, y1);
     const int TX = dv.tiles_x;
-    const uint32_t tbase = (uint32_t)dv.tile_off;
-    uint32_t w = off;
-    const uint32_t wend = off + cnt;  // never write past this entry's slots
+    int tx, ty;
     if (dv.v.mask == A3FR_MASK_ALL) {
-        for (int ty = y0; ty <= y1; ++ty)
-            for (int tx = x0; tx <= x1 && w < wend; ++tx) {
-                keys[w] = tbase + (uint32_t)(ty * TX + tx);
-                vals[w] = i;
-                ++w;
-            }
+        const uint32_t w = (uint32_t)(x1 - x0 + 1);
+        ty = y0 + (int)(r / w);
+        tx = x0 + (int)(r % w);
     } else {
-        for (int ty = y0; ty <= y1; ++ty) {
-            const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
-            const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
-            for (int p = rp[x0]; p < rp[x1 + 1] && w < wend; ++p) {
-                keys[w] = tbase + (uint32_t)(ty * TX + rl[p]);
-                vals[w] = i;
-                ++w;
-            }
+        const uint32_t *cm = cum + dv.cum_off;
+        const int stride = TX + 1;
+        // keys of this entry in rows < y: (cm[y][x1+1] - cm[y][x0]) - base
+        const uint32_t base = cm[(int64_t)y0 * stride + x1 + 1] - cm[(int64_t)y0 * stride + x0];
+        int a = y0, b = y1 + 1;  // row ty: largest y in [y0, y1] with count(rows < y) <= r
+        while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            const uint32_t before = cm[(int64_t)mid * stride + x1 + 1] - cm[(int64_t)mid * stride + x0] - base;
+            if (before <= r) a = mid; else b = mid;
         }
+        ty = a;
+        const uint32_t before = cm[(int64_t)ty * stride + x1 + 1] - cm[(int64_t)ty * stride + x0] - base;
+        const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * stride;
+        const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * stride;
+        tx = rl[rp[x0] + (r - before)];
+    }
+    keys[q] = (uint32_t)dv.tile_off + (uint32_t)(ty * TX + tx);
+    vals[q] = i;
+}
+
+// cum[v][ty][tx] for masked views: active tiles in rows < ty and columns < tx.
+// One thread per (view, column), walking the rows.
+__global__ void k_mask_cum(const DevView *__restrict__ views, const uint16_t *__restrict__ row_prefix,
+                           uint32_t *__restrict__ cum) {
+    const DevView &dv = views[blockIdx.y];
+    if (dv.v.mask == A3FR_MASK_ALL) return;
+    const int TX = dv.tiles_x, stride = TX + 1;
+    const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tx > TX) return;
+    uint32_t *cm = cum + dv.cum_off;
+    const uint16_t *rp = row_prefix + dv.mask_off;
+    uint32_t acc = 0;
+    cm[tx] = 0;
+    for (int ty = 0; ty < dv.tiles_y; ++ty) {
+        acc += rp[(int64_t)ty * stride + tx];
+        cm[(int64_t)(ty + 1) * stride + tx] = acc;
     }
 }
 
-// One block per entry with many keys; threads write consecutive keys.
-__global__ void __launch_bounds__(256) k_emit_big(const DevView *__restrict__ views, int64_t n,
-                                                  const uint32_t *__restrict__ ent,
-                                                  const uint32_t *__restrict__ offsets, const uint64_t *__restrict__ rect,
-                                                  const uint16_t *__restrict__ row_prefix,
-                                                  const uint16_t *__restrict__ row_list, uint32_t *__restrict__ keys,
-                                                  uint32_t *__restrict__ vals, const uint32_t *big_list,
-                                                  const uint32_t *big_count) {
-    const uint32_t nbig = *big_count;
-    for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const int64_t j = big_list[b];
-        const int64_t e = ent[j];
-        const int v = (int)(e / n);
-        const DevView &dv = views[v];
-        const uint32_t i = (uint32_t)(e - (int64_t)v * n);
-        const uint32_t off = offsets[j];
-        const uint32_t cnt_e = offsets[j + 1] - off;
-        int x0, x1, y0, y1;
-        unpack_rect(rect[e], x0, x1, y0, y1);
-        const int TX = dv.tiles_x;
-        const uint32_t tbase = (uint32_t)dv.tile_off;
-        if (dv.v.mask == A3FR_MASK_ALL) {
-            const uint32_t wdt = (uint32_t)(x1 - x0 + 1);
-            uint32_t cnt = wdt * (uint32_t)(y1 - y0 + 1);
-            if (cnt > cnt_e) cnt = cnt_e;
-            for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
-                const int ty = y0 + (int)(q / wdt), tx = x0 + (int)(q % wdt);
-                keys[off + q] = tbase + (uint32_t)(ty * TX + tx);
-                vals[off + q] = i;
-            }
-        } else {
-            uint32_t run = off;
-            for (int ty = y0; ty <= y1; ++ty) {
-                const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
-                const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
-                const int p0 = rp[x0];
-                int rc = rp[x1 + 1] - p0;
-                if (run + (uint32_t)rc > off + cnt_e) rc = (int)(off + cnt_e - run);
-                for (int q = threadIdx.x; q < rc; q += blockDim.x) {
-                    keys[run + q] = tbase + (uint32_t)(ty * TX + rl[p0 + q]);
-                    vals[run + q] = i;
-                }
-                run += (uint32_t)rc;
-            }
-        }
-    }
+void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
+                     hipStream_t s) {
+    if (nv == 0) return;
+    hipLaunchKernelGGL(k_mask_cum, dim3((unsigned)((max_tiles_x + 1 + 127) / 128), (unsigned)nv), dim3(128), 0, s,
+                       views, row_prefix, cum);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -452,13 +559,12 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
-                 uint32_t *keys, uint32_t *vals, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
-    if (m == 0) return;
-    launch_fill_u32(big_count, 0u, 1, s);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, views, n, ent, n_ent, offsets, rect,
-                       row_prefix, row_list, keys, vals, big_list, big_count);
-    hipLaunchKernelGGL(k_emit_big, dim3(2048), dim3(256), 0, s, views, n, ent, offsets, rect, row_prefix, row_list,
-                       keys, vals, big_list, big_count);
+                 const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
+                 hipStream_t s) {
+    if (m == 0 || K == 0) return;
+    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((K + 63) / 64)), dim3(64), 0, s, views, n, ent, n_ent, offsets,
+                       chunk_start, rect, row_prefix, row_list, cum, keys, vals, K);
 }
 
 // ------------------------------------------------------------------------

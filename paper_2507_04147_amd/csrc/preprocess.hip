@@ -37,31 +37,40 @@ __device__ __forceinline__ bool tile_active(const a3fr_view &v, int tx, int ty) 
     return true;
 }
 
-// One thread per tile row of every view: active flags, and for masked views a
-// row prefix count (row_prefix[x] = active tiles in columns < x) and the
-// columns of the row's active tiles in order (row_list).
-__global__ void k_tile_masks(const DevView *views, int64_t rows_total, const int32_t *row_view,
-                             const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per tile row of every view: active flags, and for masked views
+// a row prefix count (row_prefix[x] = active tiles in columns < x) and the
+// columns of the row's active tiles in order (row_list), built with ballots.
+__global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_t rows_total, const int32_t *row_view,
+                                                    const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list,
+                                                    uint8_t *active) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (r >= rows_total) return;
     const DevView &dv = views[row_view[r]];
-    int ty = row_y[r];
-    int TX = dv.tiles_x;
+    const int ty = row_y[r];
+    const int TX = dv.tiles_x;
     uint8_t *act = active + dv.tile_off + (int64_t)ty * TX;
     if (dv.v.mask == A3FR_MASK_ALL) {
-        for (int tx = 0; tx < TX; ++tx) act[tx] = 1;
+        for (int tx = lane; tx < TX; tx += 64) act[tx] = 1;
         return;
     }
     uint16_t *pre = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
     uint16_t *lst = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
-    int c = 0;
-    for (int tx = 0; tx < TX; ++tx) {
-        pre[tx] = (uint16_t)c;
-        bool a = tile_active(dv.v, tx, ty);
-        act[tx] = a ? 1 : 0;
-        if (a) lst[c++] = (uint16_t)tx;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t c = 0;
+    for (int tx0 = 0; tx0 < TX; tx0 += 64) {
+        const int tx = tx0 + lane;
+        const bool a = tx < TX && tile_active(dv.v, tx, ty);
+        const uint64_t m = __ballot(a);
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        if (tx < TX) {
+            pre[tx] = (uint16_t)(c + below);
+            act[tx] = a ? 1 : 0;
+            if (a) lst[c + below] = (uint16_t)tx;
+        }
+        c += (uint32_t)__popcll(m);
     }
-    pre[TX] = (uint16_t)c;
+    if (lane == 0) pre[TX] = (uint16_t)c;
 }
 
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
@@ -69,9 +78,8 @@ void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const i
                        hipStream_t s) {
     (void)nv;
     if (rows_total == 0) return;
-    int blk = 128;
-    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((rows_total + blk - 1) / blk)), dim3(blk), 0, s, views,
-                       rows_total, row_view, row_y, row_prefix, row_list, active);
+    hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((rows_total + 3) / 4)), dim3(256), 0, s, views, rows_total,
+                       row_view, row_y, row_prefix, row_list, active);
 }
 
 // ------------------------------------------------------------------------
@@ -143,117 +151,136 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
     Y[15] = -c3a * x * (xx - 3.0f * yy);
 }
 
-__global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views, int nv,
+// One thread per (Gaussian, view): the float64 key path of that view and the
+// blend record (its colour is filled in later, only for the entries that emit
+// keys, by k_entry_colour).
+__global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views,
                                                     const uint16_t *__restrict__ row_prefix,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
                                                     uint64_t *__restrict__ rect, Record *__restrict__ rec,
                                                     double *__restrict__ score) {
     const int64_t n = sc.n;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int vi = blockIdx.y;
     if (i >= n) return;
+    const DevView &dv = views[vi];
+    const a3fr_view &v = dv.v;
+    const int64_t slot = (int64_t)vi * n + i;
     const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
-    const float op = sc.opacity_dev[i];
+    const double *Rw = v.R;
+    const double p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v.t[0])));
+    const double p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v.t[1])));
+    const double p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v.t[2])));
+    uint32_t cnt = 0;
     Cov3 S;
-    bool qok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
-                             sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S);
-    const int nk = (sc.sh_degree + 1) * (sc.sh_degree + 1);
-
-    int cur_eye = -1;
-    double p0 = 0, p1 = 0, p2 = 0;
-    Cov3 V = {0, 0, 0, 0, 0, 0};
-    float col[3] = {0.f, 0.f, 0.f};
-    for (int vi = 0; vi < nv; ++vi) {
-        const DevView &dv = views[vi];
-        const a3fr_view &v = dv.v;
-        const int64_t slot = (int64_t)vi * n + i;
-        if (v.eye != cur_eye) {
-            cur_eye = v.eye;
-            const double *Rw = v.R;
-            p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v.t[0])));
-            p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v.t[1])));
-            p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v.t[2])));
-            if (qok) view_cov(Rw, S, V);
-            // view-dependent colour of this eye, float32
-            float dx = (float)mx - (float)v.campos[0], dy = (float)my - (float)v.campos[1],
-                  dz = (float)mz - (float)v.campos[2];
-            float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-            float Y[16];
-            sh_basis(dx * inv, dy * inv, dz * inv, Y);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float acc = 0.5f;
-                for (int k = 0; k < nk; ++k) acc = fmaf(Y[k], sc.sh_dev[((int64_t)k * 3 + ch) * n + i], acc);
-                col[ch] = fmaxf(acc, 0.0f);
-            }
-        }
-        uint32_t cnt = 0;
-        if (qok && p2 > kZNear) {
-            const double xz = p0 / p2, yz = p1 / p2;
-            const double limx = (1.3 * (0.5 * (double)v.width)) / v.fx;
-            const double limy = (1.3 * (0.5 * (double)v.height)) / v.fy;
-            const double txc = fmin(fmax(xz, -limx), limx);
-            const double tyc = fmin(fmax(yz, -limy), limy);
-            const double j00 = v.fx / p2, j02 = -(j00 * txc);
-            const double j11 = v.fy / p2, j12 = -(j11 * tyc);
-            const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
-                         B02 = fma(j00, V.s02, j02 * V.s22);
-            const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
-            const double a = fma(B00, j00, B02 * j02) + kDilate;
-            const double b = fma(B01, j11, B02 * j12);
-            const double c = fma(B11, j11, B12 * j12) + kDilate;
-            const double det = fma(a, c, -(b * b));
-            if (det > 0.0) {
-                const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
-                const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
-                const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
-                if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
-                    double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
-                    double fx1 = floor((hix - 0.5) / (double)kTile);
-                    double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
-                    double fy1 = floor((hiy - 0.5) / (double)kTile);
-                    fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
-                    fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
-                    if (fx0 <= fx1 && fy0 <= fy1) {
-                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-                        if (v.mask == A3FR_MASK_ALL) {
-                            cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-                        } else {
-                            const uint16_t *pre = row_prefix + dv.mask_off;
-                            for (int ty = y0; ty <= y1; ++ty) {
-                                const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
-                                cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
-                            }
+    if (p2 > kZNear &&
+        gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
+                      sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S)) {
+        Cov3 V;
+        view_cov(Rw, S, V);
+        const double xz = p0 / p2, yz = p1 / p2;
+        const double limx = (1.3 * (0.5 * (double)v.width)) / v.fx;
+        const double limy = (1.3 * (0.5 * (double)v.height)) / v.fy;
+        const double txc = fmin(fmax(xz, -limx), limx);
+        const double tyc = fmin(fmax(yz, -limy), limy);
+        const double j00 = v.fx / p2, j02 = -(j00 * txc);
+        const double j11 = v.fy / p2, j12 = -(j11 * tyc);
+        const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
+                     B02 = fma(j00, V.s02, j02 * V.s22);
+        const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
+        const double a = fma(B00, j00, B02 * j02) + kDilate;
+        const double b = fma(B01, j11, B02 * j12);
+        const double c = fma(B11, j11, B12 * j12) + kDilate;
+        const double det = fma(a, c, -(b * b));
+        if (det > 0.0) {
+            const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
+            const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
+            const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
+            if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
+                double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
+                double fx1 = floor((hix - 0.5) / (double)kTile);
+                double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
+                double fy1 = floor((hiy - 0.5) / (double)kTile);
+                fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
+                fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
+                if (fx0 <= fx1 && fy0 <= fy1) {
+                    const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+                    if (v.mask == A3FR_MASK_ALL) {
+                        cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+                    } else {
+                        const uint16_t *pre = row_prefix + dv.mask_off;
+                        for (int ty = y0; ty <= y1; ++ty) {
+                            const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+                            cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
                         }
-                        const float dz32 = (float)p2;
-                        depth[slot] = __float_as_uint(dz32);
-                        rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
-                                     ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
-                        if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
-                        const double kLog2e = 1.4426950408889634;
-                        Record R;
-                        R.u = u; R.v = w;
-                        R.a2 = (float)(-0.5 * kLog2e * (c / det));
-                        R.k = (float)(-b / c);
-                        R.c2 = (float)(-0.5 * kLog2e / c);
-                        R.o = op;
-                        R.r = col[0]; R.g = col[1]; R.b = col[2]; R.pad = 0.0f;
-                        rec[slot] = R;
                     }
+                    depth[slot] = __float_as_uint((float)p2);
+                    rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
+                                 ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
+                    const float op = sc.opacity_dev[i];
+                    if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
+                    // inverse covariance in LDL^T form, float64 then rounded once
+                    const double kLog2e = 1.4426950408889634;
+                    const double inv_c = 1.0 / c, inv_det = 1.0 / det;
+                    Record R;
+                    R.u = u; R.v = w;
+                    R.a2 = (float)(-0.5 * kLog2e * (c * inv_det));
+                    R.k = (float)(-(b * inv_c));
+                    R.c2 = (float)(-0.5 * kLog2e * inv_c);
+                    R.o = op;
+                    R.r = R.g = R.b = 0.0f;
+                    R.pad = 0.0f;
+                    rec[slot] = R;
                 }
             }
         }
-        counts[slot] = cnt;
     }
+    counts[slot] = cnt;
 }
 
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, hipStream_t s) {
     (void)eye_first;
-    if (sc.n == 0) return;
+    if (sc.n == 0 || nv == 0) return;
     const int blk = 256;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk)), dim3(blk), 0, s, sc, views, nv,
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)nv), dim3(blk), 0, s, sc, views,
                        row_prefix, counts, depth, rect, rec, score);
+}
+
+// View-dependent colour (degree <= 3 real SH, float32) of every entry that
+// emits keys, seen from its view's eye centre, written into its record.
+__global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevView *__restrict__ views,
+                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                                      Record *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)*n_ent) return;
+    const int64_t n = sc.n;
+    const int64_t e = ent[j];
+    const int v = (int)(e / n);
+    const int64_t i = e - (int64_t)v * n;
+    const a3fr_view &vw = views[v].v;
+    const float dx = sc.mean_dev[i] - (float)vw.campos[0], dy = sc.mean_dev[n + i] - (float)vw.campos[1],
+                dz = sc.mean_dev[2 * n + i] - (float)vw.campos[2];
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    float Y[16];
+    sh_basis(dx * inv, dy * inv, dz * inv, Y);
+    const int nk = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+        for (int k = 0; k < nk; ++k) acc = fmaf(Y[k], sc.sh_dev[((int64_t)k * 3 + ch) * n + i], acc);
+        col[ch] = fmaxf(acc, 0.0f);
+    }
+    float *r = &rec[e].r;
+    r[0] = col[0]; r[1] = col[1]; r[2] = col[2];
+}
+
+void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
+                         int64_t m, Record *rec, hipStream_t s) {
+    if (m == 0) return;
+    hipLaunchKernelGGL(k_entry_colour, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, sc, views, ent, n_ent, rec);
 }
 
 }  // namespace a3fr

@@ -208,23 +208,27 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__res
     }
 }
 
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *hist,
-                         uint32_t *status, uint32_t *ctr, hipStream_t s) {
+// ws: one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256]
+// cleared by one fill, then the digit histograms of all passes.
+int64_t sort_workspace_words(int64_t n_max, int npass) {
+    return (int64_t)npass * kRadix + 8 + (int64_t)npass * sort_partitions(n_max) * kRadix;
+}
+
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
+                         hipStream_t s) {
     const int nparts = sort_partitions(n_max);
-    launch_fill_u32(hist, 0u, (int64_t)npass * kRadix, s);
-    launch_fill_u32(status, 0u, (int64_t)npass * nparts * kRadix, s);
-    launch_fill_u32(ctr, 0u, npass, s);
+    launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + 256 * 8 - 1) / (256 * 8));
     if (hblocks > 2048) hblocks = 2048;
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, n_dev, npass, hist);
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, n_dev, npass, ws);
 }
 
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int p, const uint32_t *hist, uint32_t *status, uint32_t *ctr, uint32_t *err,
-                      hipStream_t s) {
+                      int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
     const int nparts = sort_partitions(n_max);
     if (nparts == 0) return;
+    uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix, *status = ctr + 8;
     hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev, 8 * p,
                        hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
 }
