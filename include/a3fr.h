@@ -54,10 +54,13 @@ typedef enum {
 typedef struct a3fr_ctx a3fr_ctx;
 
 /* Scene (Sec. 2.3: every point carries a position, an anisotropic scale, a
- * rotation, an opacity and spherical-harmonic colour).  Structure of arrays,
- * float32, device pointers, already activated (scale = exp(log-scale),
- * opacity = sigmoid(logit)).  quat is (w, x, y, z) and is normalised inside
- * the library.  sh holds (sh_degree+1)^2 coefficients as [coef][channel][n]. */
+ * rotation, an opacity and spherical-harmonic colour).  float32 device
+ * pointers, already activated (scale = exp(log-scale), opacity =
+ * sigmoid(logit)).  Geometry is structure-of-arrays (coalesced per-Gaussian
+ * loads in projection); quat is (w, x, y, z) and is normalised inside the
+ * library.  sh is per Gaussian, [n][(sh_degree+1)^2][3] (coefficient, then
+ * channel), so that the colour of the few Gaussians that are drawn is one
+ * contiguous gather. */
 typedef struct {
     int64_t n;
     int32_t sh_degree;        /* 0..3 */
@@ -66,7 +69,7 @@ typedef struct {
     const float *scale_dev;   /* [3][n] */
     const float *quat_dev;    /* [4][n] */
     const float *opacity_dev; /* [n] */
-    const float *sh_dev;      /* [(sh_degree+1)^2][3][n] */
+    const float *sh_dev;      /* [n][(sh_degree+1)^2][3] */
 } a3fr_scene;
 
 /* One rendered layer of one eye: a pinhole camera at this layer's resolution

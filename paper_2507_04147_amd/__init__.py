@@ -181,7 +181,8 @@ class DeviceScene:
         import torch
         f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
         nk = (sh_degree + 1) ** 2
-        return cls(f(scene.mean), f(scene.scale), f(scene.quat), f(scene.opacity), f(scene.sh[:nk]), sh_degree)
+        sh = np.transpose(scene.sh[:nk], (2, 0, 1))  # [coef][ch][n] -> [n][coef][ch]
+        return cls(f(scene.mean), f(scene.scale), f(scene.quat), f(scene.opacity), f(sh), sh_degree)
 
     def struct(self) -> Scene_:
         s = Scene_()

@@ -41,6 +41,7 @@ struct DevView {
     int64_t img_off;      // first pixel of this view in the concatenated images
     int64_t mask_off;     // offset of this view's row tables (rows x (tiles_x + 1)) in the mask arrays
     int64_t cum_off;      // offset of this view's 2D active-tile prefix ((rows + 1) x (tiles_x + 1))
+    double limx, limy;    // guard band of the projection Jacobian: (1.3 (W/2)) / fx, (1.3 (H/2)) / fy
     int32_t sel_slot;     // index among selecting views, -1 if none
     int32_t pad;
 };
@@ -54,7 +55,7 @@ constexpr uint32_t kValMask = (1u << 30) - 1;
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
                        hipStream_t s);
-void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
+void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, hipStream_t s);
 void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,

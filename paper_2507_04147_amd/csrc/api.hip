@@ -38,7 +38,7 @@ struct a3fr_ctx {
     int64_t cum_entries = 0;
     int max_tiles_x = 1;
     std::vector<DevView> hviews;
-    std::vector<int32_t> hrow_view, hrow_y, hsel_views;
+    std::vector<int32_t> hrow_view, hrow_y, hsel_views, hgroups;
     // pinned staging for uploads and small readbacks
     void *pinned = nullptr;
     size_t pinned_cap = 0;
@@ -346,6 +346,10 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     c->hrow_view.clear();
     c->hrow_y.clear();
     c->hsel_views.clear();
+    c->hgroups.clear();
+    for (int k = 0; k < nv; ++k)
+        if (k == 0 || views[k].eye != views[k - 1].eye) c->hgroups.push_back(k);
+    c->hgroups.push_back(nv);
     int64_t toff = 0, ioff = 0, moff = 0, coff = 0;
     int max_tx = 1;
     for (int k = 0; k < nv; ++k) {
@@ -353,6 +357,9 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
         std::memset(&d, 0, sizeof(d));
         d.v = views[k];
         d.tiles_x = (views[k].width + kTile - 1) / kTile;
+        // float64, same operations as the key path's definition (no contraction in this file)
+        d.limx = (1.3 * (0.5 * (double)views[k].width)) / views[k].fx;
+        d.limy = (1.3 * (0.5 * (double)views[k].height)) / views[k].fy;
         d.tiles_y = (views[k].height + kTile - 1) / kTile;
         d.tile_off = toff;
         d.img_off = ioff;
@@ -411,8 +418,9 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     // ---- one upload through pinned staging: [views | row views | row ys | selecting views]
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes_v = sizeof(DevView) * nv, bytes_r = sizeof(int32_t) * c->rows_total,
-                 bytes_s = sizeof(int32_t) * (c->nsel + 1);
-    const size_t o_rv = al(bytes_v), o_ry = o_rv + al(bytes_r), o_sv = o_ry + al(bytes_r), total = o_sv + al(bytes_s);
+                 bytes_s = sizeof(int32_t) * (c->nsel + 1), bytes_g = sizeof(int32_t) * c->hgroups.size();
+    const size_t o_rv = al(bytes_v), o_ry = o_rv + al(bytes_r), o_sv = o_ry + al(bytes_r), o_gr = o_sv + al(bytes_s),
+                 total = o_gr + al(bytes_g);
     TRY(ensure(c, c->views, total));
     TRY(ensure_pinned(c, total));
     char *pin = static_cast<char *>(c->pinned);
@@ -420,12 +428,14 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     std::memcpy(pin + o_rv, c->hrow_view.data(), bytes_r);
     std::memcpy(pin + o_ry, c->hrow_y.data(), bytes_r);
     if (c->nsel) std::memcpy(pin + o_sv, c->hsel_views.data(), sizeof(int32_t) * c->nsel);
+    std::memcpy(pin + o_gr, c->hgroups.data(), bytes_g);
     HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, total, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->upload_done, c->stream));
     char *frame = static_cast<char *>(c->views.p);
     const int32_t *d_row_view = reinterpret_cast<const int32_t *>(frame + o_rv);
     const int32_t *d_row_y = reinterpret_cast<const int32_t *>(frame + o_ry);
     const int32_t *d_sel_views = reinterpret_cast<const int32_t *>(frame + o_sv);
+    const int32_t *d_groups = reinterpret_cast<const int32_t *>(frame + o_gr);
 
     // ---- kernels
     const DevView *dv = P<DevView>(c->views);
@@ -434,7 +444,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                       P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream);
       if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
-    launch_preprocess(*scene, dv, nv, nullptr, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
+    launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
                       c->stream); }
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);

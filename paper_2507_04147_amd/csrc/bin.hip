@@ -262,7 +262,8 @@ constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block
 
 // Entry e = view * n + index contributes keys iff it is visible in its view and,
-// for a selecting view, kept.
+// for a selecting view, kept.  A block's 4096 entries span at most two views
+// (n >= 4096) or are resolved per element otherwise.
 struct EntryFlags {
     const uint32_t *counts;
     const uint8_t *keep;
@@ -275,6 +276,7 @@ struct EntryFlags {
         if (views[v].v.select && !keep[e]) return 0;
         return 1;
     }
+    __device__ __forceinline__ int64_t live(int64_t m) const { return m; }
 };
 
 // Key count of the j-th entry in depth order.
@@ -285,6 +287,7 @@ struct SortedCounts {
     __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
         return j < (int64_t)*n_ent ? counts[ent[j]] : 0u;
     }
+    __device__ __forceinline__ int64_t live(int64_t) const { return (int64_t)*n_ent; }
 };
 
 // wave-level inclusive scan of a 64-bit value (wave64 via shuffles)
@@ -319,6 +322,10 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t *total)
 template <class F>
 __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(F f, int64_t m, uint64_t *block_sums) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= f.live(m)) {  // nothing to count in this block (block-uniform)
+        if (threadIdx.x == 0) block_sums[blockIdx.x] = 0;
+        return;
+    }
     uint64_t acc = 0;
 #pragma unroll 4
     for (int j = 0; j < kScanItems; ++j) acc += f(base + (int64_t)j * kScanBlock + threadIdx.x, m);
@@ -360,37 +367,51 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t *block_sums, int6
 }
 
 // Compaction: entry e with flag 1 goes to slot (its exclusive prefix), with
-// its depth bits as sort key.  Thread t owns 16 consecutive entries (blocked),
-// so the running sum inside a thread follows entry order.
+// its depth bits as sort key.  Each wave takes 1024 consecutive entries in 16
+// rounds of 64 (coalesced), packing the flagged ones with a ballot per round;
+// the waves of a block are combined by the block's exclusive scan.
 __global__ void __launch_bounds__(kScanBlock) k_compact_down(EntryFlags f, int64_t m, const uint64_t *block_pre,
                                                              const uint32_t *__restrict__ depth,
                                                              uint32_t *__restrict__ ent, uint32_t *__restrict__ dkey) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t flags = 0, cnt = 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * kScanTile + (int64_t)w * 64 * kScanItems;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint64_t masks[kScanItems];
+    uint32_t cnt = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint32_t fl = f(base + j, m);
-        flags |= fl << j;
-        cnt += fl;
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint32_t fl = f(wbase + r * 64 + lane, m);
+        masks[r] = __ballot(fl != 0);
+        cnt += (uint32_t)__popcll(masks[r]);
     }
-    uint64_t tot;
-    uint64_t run = block_pre[blockIdx.x] + block_excl_scan(cnt, &tot);
+    // block exclusive scan of the per-wave counts (lane 0 of each wave holds it)
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    if (lane == 0) s_w[w] = cnt;
+    __syncthreads();
+    uint64_t run = block_pre[blockIdx.x];
+    for (int q = 0; q < w; ++q) run += s_w[q];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        if ((flags >> j) & 1u) {
-            const int64_t e = base + j;
-            ent[run] = (uint32_t)e;
-            dkey[run] = depth[e];
-            ++run;
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t mk = masks[r];
+        if ((mk >> lane) & 1ull) {
+            const int64_t e = wbase + r * 64 + lane;
+            const uint64_t pos = run + (uint64_t)__popcll(mk & lt);
+            ent[pos] = (uint32_t)e;
+            dkey[pos] = depth[e];
         }
+        run += (uint64_t)__popcll(mk);
     }
 }
 
 // Offsets of the keys of the entries in depth order; offsets[E] = K.
 __global__ void __launch_bounds__(kScanBlock) k_offsets_down(SortedCounts f, int64_t m, const uint64_t *block_pre,
                                                              const uint64_t *total, uint32_t *offsets) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     const int64_t E = *f.n_ent;
+    if ((int64_t)blockIdx.x * kScanTile >= E) {  // block-uniform
+        if (blockIdx.x == 0 && threadIdx.x == 0) offsets[E] = (uint32_t)*total;
+        return;
+    }
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t c[kScanItems];
     uint64_t acc = 0;
 #pragma unroll
@@ -520,29 +541,36 @@ __global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, 
 }
 
 // cum[v][ty][tx] for masked views: active tiles in rows < ty and columns < tx.
-// One thread per (view, column), walking the rows.
-__global__ void k_mask_cum(const DevView *__restrict__ views, const uint16_t *__restrict__ row_prefix,
-                           uint32_t *__restrict__ cum) {
+// One wavefront per (view, column): a wave-wide scan down the rows.
+__global__ void __launch_bounds__(256) k_mask_cum(const DevView *__restrict__ views,
+                                                  const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ cum) {
     const DevView &dv = views[blockIdx.y];
     if (dv.v.mask == A3FR_MASK_ALL) return;
-    const int TX = dv.tiles_x, stride = TX + 1;
-    const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int TX = dv.tiles_x, TY = dv.tiles_y, stride = TX + 1;
+    const int tx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (tx > TX) return;
     uint32_t *cm = cum + dv.cum_off;
     const uint16_t *rp = row_prefix + dv.mask_off;
-    uint32_t acc = 0;
-    cm[tx] = 0;
-    for (int ty = 0; ty < dv.tiles_y; ++ty) {
-        acc += rp[(int64_t)ty * stride + tx];
-        cm[(int64_t)(ty + 1) * stride + tx] = acc;
+    if (lane == 0) cm[tx] = 0;
+    uint32_t carry = 0;
+    for (int r0 = 0; r0 < TY; r0 += 64) {
+        const int ty = r0 + lane;
+        uint32_t x = ty < TY ? (uint32_t)rp[(int64_t)ty * stride + tx] : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (ty < TY) cm[(int64_t)(ty + 1) * stride + tx] = carry + x;
+        carry += __shfl(x, 63, 64);
     }
 }
 
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
                      hipStream_t s) {
     if (nv == 0) return;
-    hipLaunchKernelGGL(k_mask_cum, dim3((unsigned)((max_tiles_x + 1 + 127) / 128), (unsigned)nv), dim3(128), 0, s,
-                       views, row_prefix, cum);
+    hipLaunchKernelGGL(k_mask_cum, dim3((unsigned)((max_tiles_x + 1 + 3) / 4), (unsigned)nv), dim3(256), 0, s, views,
+                       row_prefix, cum);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {

@@ -151,101 +151,105 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
     Y[15] = -c3a * x * (xx - 3.0f * yy);
 }
 
-// One thread per (Gaussian, view): the float64 key path of that view and the
-// blend record (its colour is filled in later, only for the entries that emit
-// keys, by k_entry_colour).
+// One thread per (Gaussian, group of consecutive views of one eye): the
+// Gaussian is loaded, its 3D covariance and view-space covariance computed once,
+// then each view of the group (the layers of that eye) gets the float64 key
+// path and the blend record (its colour is filled in later, only for the
+// entries that emit keys, by k_entry_colour).
 __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views,
+                                                    const int32_t *__restrict__ groups,
                                                     const uint16_t *__restrict__ row_prefix,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
                                                     uint64_t *__restrict__ rect, Record *__restrict__ rec,
                                                     double *__restrict__ score) {
     const int64_t n = sc.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int vi = blockIdx.y;
     if (i >= n) return;
-    const DevView &dv = views[vi];
-    const a3fr_view &v = dv.v;
-    const int64_t slot = (int64_t)vi * n + i;
+    const int v_begin = groups[blockIdx.y], v_end = groups[blockIdx.y + 1];
+    const a3fr_view &v0 = views[v_begin].v;
     const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
-    const double *Rw = v.R;
-    const double p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v.t[0])));
-    const double p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v.t[1])));
-    const double p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v.t[2])));
-    uint32_t cnt = 0;
-    Cov3 S;
-    if (p2 > kZNear &&
-        gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
-                      sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S)) {
-        Cov3 V;
-        view_cov(Rw, S, V);
-        const double xz = p0 / p2, yz = p1 / p2;
-        const double limx = (1.3 * (0.5 * (double)v.width)) / v.fx;
-        const double limy = (1.3 * (0.5 * (double)v.height)) / v.fy;
-        const double txc = fmin(fmax(xz, -limx), limx);
-        const double tyc = fmin(fmax(yz, -limy), limy);
-        const double j00 = v.fx / p2, j02 = -(j00 * txc);
-        const double j11 = v.fy / p2, j12 = -(j11 * tyc);
-        const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
-                     B02 = fma(j00, V.s02, j02 * V.s22);
-        const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
-        const double a = fma(B00, j00, B02 * j02) + kDilate;
-        const double b = fma(B01, j11, B02 * j12);
-        const double c = fma(B11, j11, B12 * j12) + kDilate;
-        const double det = fma(a, c, -(b * b));
-        if (det > 0.0) {
-            const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
-            const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
-            const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
-            if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
-                double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
-                double fx1 = floor((hix - 0.5) / (double)kTile);
-                double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
-                double fy1 = floor((hiy - 0.5) / (double)kTile);
-                fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
-                fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
-                if (fx0 <= fx1 && fy0 <= fy1) {
-                    const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-                    if (v.mask == A3FR_MASK_ALL) {
-                        cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-                    } else {
-                        const uint16_t *pre = row_prefix + dv.mask_off;
-                        for (int ty = y0; ty <= y1; ++ty) {
-                            const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
-                            cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
+    const double *Rw = v0.R;
+    const double p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v0.t[0])));
+    const double p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v0.t[1])));
+    const double p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v0.t[2])));
+    Cov3 S, V;
+    const bool front = p2 > kZNear &&
+                       gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
+                                     sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S);
+    if (front) view_cov(Rw, S, V);
+    const double xz = p0 / p2, yz = p1 / p2;
+    for (int vi = v_begin; vi < v_end; ++vi) {
+        const DevView &dv = views[vi];
+        const a3fr_view &v = dv.v;
+        const int64_t slot = (int64_t)vi * n + i;
+        uint32_t cnt = 0;
+        if (front) {
+            const double limx = dv.limx, limy = dv.limy;  // (1.3 (W/2)) / fx, computed on the host
+            const double txc = fmin(fmax(xz, -limx), limx);
+            const double tyc = fmin(fmax(yz, -limy), limy);
+            const double j00 = v.fx / p2, j02 = -(j00 * txc);
+            const double j11 = v.fy / p2, j12 = -(j11 * tyc);
+            const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
+                         B02 = fma(j00, V.s02, j02 * V.s22);
+            const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
+            const double a = fma(B00, j00, B02 * j02) + kDilate;
+            const double b = fma(B01, j11, B02 * j12);
+            const double c = fma(B11, j11, B12 * j12) + kDilate;
+            const double det = fma(a, c, -(b * b));
+            if (det > 0.0) {
+                const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
+                const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
+                const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
+                if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
+                    double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
+                    double fx1 = floor((hix - 0.5) / (double)kTile);
+                    double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
+                    double fy1 = floor((hiy - 0.5) / (double)kTile);
+                    fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
+                    fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
+                    if (fx0 <= fx1 && fy0 <= fy1) {
+                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+                        if (v.mask == A3FR_MASK_ALL) {
+                            cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+                        } else {
+                            const uint16_t *pre = row_prefix + dv.mask_off;
+                            for (int ty = y0; ty <= y1; ++ty) {
+                                const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+                                cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
+                            }
                         }
+                        depth[slot] = __float_as_uint((float)p2);
+                        rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
+                                     ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
+                        const float op = sc.opacity_dev[i];
+                        if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
+                        // inverse covariance in LDL^T form, float64 then rounded once
+                        const double kLog2e = 1.4426950408889634;
+                        const double inv_c = 1.0 / c, inv_det = 1.0 / det;
+                        Record R;
+                        R.u = u; R.v = w;
+                        R.a2 = (float)(-0.5 * kLog2e * (c * inv_det));
+                        R.k = (float)(-(b * inv_c));
+                        R.c2 = (float)(-0.5 * kLog2e * inv_c);
+                        R.o = op;
+                        R.r = R.g = R.b = 0.0f;
+                        R.pad = 0.0f;
+                        rec[slot] = R;
                     }
-                    depth[slot] = __float_as_uint((float)p2);
-                    rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
-                                 ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
-                    const float op = sc.opacity_dev[i];
-                    if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
-                    // inverse covariance in LDL^T form, float64 then rounded once
-                    const double kLog2e = 1.4426950408889634;
-                    const double inv_c = 1.0 / c, inv_det = 1.0 / det;
-                    Record R;
-                    R.u = u; R.v = w;
-                    R.a2 = (float)(-0.5 * kLog2e * (c * inv_det));
-                    R.k = (float)(-(b * inv_c));
-                    R.c2 = (float)(-0.5 * kLog2e * inv_c);
-                    R.o = op;
-                    R.r = R.g = R.b = 0.0f;
-                    R.pad = 0.0f;
-                    rec[slot] = R;
                 }
             }
         }
+        counts[slot] = cnt;
     }
-    counts[slot] = cnt;
 }
 
-void launch_preprocess(const a3fr_scene &sc, const DevView *views, int nv, const int32_t *eye_first,
+void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, hipStream_t s) {
-    (void)eye_first;
-    if (sc.n == 0 || nv == 0) return;
+    if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)nv), dim3(blk), 0, s, sc, views,
-                       row_prefix, counts, depth, rect, rec, score);
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
+                       views, groups, row_prefix, counts, depth, rect, rec, score);
 }
 
 // View-dependent colour (degree <= 3 real SH, float32) of every entry that
@@ -266,13 +270,30 @@ __global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevVi
     float Y[16];
     sh_basis(dx * inv, dy * inv, dz * inv, Y);
     const int nk = (sc.sh_degree + 1) * (sc.sh_degree + 1);
-    float col[3];
+    // this Gaussian's coefficients are contiguous: [coef][channel]
+    const float *f = sc.sh_dev + i * (int64_t)nk * 3;
+    float col[3] = {0.5f, 0.5f, 0.5f};
+    if (nk == 16) {
+        // degree 3: 48 floats = 12 independent 16-byte loads issued together
+        float4 q[12];
+        const float4 *f4 = reinterpret_cast<const float4 *>(f);
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.5f;
-        for (int k = 0; k < nk; ++k) acc = fmaf(Y[k], sc.sh_dev[((int64_t)k * 3 + ch) * n + i], acc);
-        col[ch] = fmaxf(acc, 0.0f);
+        for (int k = 0; k < 12; ++k) q[k] = f4[k];
+        const float *c = reinterpret_cast<const float *>(q);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            col[0] = fmaf(Y[k], c[3 * k + 0], col[0]);
+            col[1] = fmaf(Y[k], c[3 * k + 1], col[1]);
+            col[2] = fmaf(Y[k], c[3 * k + 2], col[2]);
+        }
+    } else {
+        for (int k = 0; k < nk; ++k) {
+            col[0] = fmaf(Y[k], f[3 * k + 0], col[0]);
+            col[1] = fmaf(Y[k], f[3 * k + 1], col[1]);
+            col[2] = fmaf(Y[k], f[3 * k + 2], col[2]);
+        }
     }
+    col[0] = fmaxf(col[0], 0.0f); col[1] = fmaxf(col[1], 0.0f); col[2] = fmaxf(col[2], 0.0f);
     float *r = &rec[e].r;
     r[0] = col[0]; r[1] = col[1]; r[2] = col[2];
 }

@@ -27,21 +27,25 @@
 
 namespace a3fr {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortThreads = 512;
+constexpr int kSortWaves = kSortThreads / kWave;      // 8
 constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortThreads * kSortItems;  // keys per partition
+constexpr int kSortPart = kSortThreads * kSortItems;  // 8192 keys per partition
 constexpr int kRadix = 256;
+constexpr int kDigitWaves = kRadix / kWave;           // waves holding one digit per lane
 constexpr int kMaxPasses = 4;                         // 32-bit keys
+constexpr int kSortBlocksPerCU = 2;                   // LDS ~74 KB per block
 
 int sort_partitions(int64_t n) { return (int)((n + kSortPart - 1) / kSortPart); }
 
 // Histograms of the npass low digits of n keys (n read from *n_dev).  Each
 // wave keeps its own LDS histograms; the block adds them to the global ones.
-__global__ void __launch_bounds__(256) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
-                                                   int npass, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[kSortWaves][kMaxPasses][kRadix];
-    for (int j = threadIdx.x; j < kSortWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
+constexpr int kHistThreads = 512;
+constexpr int kHistWaves = kHistThreads / kWave;
+__global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
+                                                            int npass, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kHistWaves][kMaxPasses][kRadix];
+    for (int j = threadIdx.x; j < kHistWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
     __syncthreads();
     const int64_t n = *n_dev;
     const int w = threadIdx.x >> 6;
@@ -53,7 +57,7 @@ __global__ void __launch_bounds__(256) k_sort_hist(const uint32_t *__restrict__ 
     for (int j = threadIdx.x; j < npass * kRadix; j += blockDim.x) {
         uint32_t c = 0;
 #pragma unroll
-        for (int q = 0; q < kSortWaves; ++q) c += (&h[q][0][0])[j];
+        for (int q = 0; q < kHistWaves; ++q) c += (&h[q][0][0])[j];
         if (c) atomicAdd(&hist[j], c);
     }
 }
@@ -65,10 +69,13 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One stable pass over digit (key >> shift) & 255.  err: sticky flag set if a
-// look-back wait exceeds its bound (never expected: predecessors always
-// publish; the bound turns a logic error into a report instead of a hang).
-__global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__restrict__ kin,
+// One stable pass over digit (key >> shift) & 255.  Persistent: each block
+// takes partition ids from the pass counter until they run out, so a launch
+// sized by an upper bound costs nothing for the partitions that do not exist.
+// err: sticky flag set if a look-back wait exceeds its bound (never expected:
+// predecessors always publish; the bound turns a logic error into a report
+// instead of a hang).
+__global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                            const uint32_t *n_dev, int shift,
@@ -78,132 +85,161 @@ __global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__res
     __shared__ uint32_t s_wh[kSortWaves][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
-    __shared__ uint32_t s_wsum[kSortWaves];
+    __shared__ uint32_t s_gexcl[kRadix];
+    __shared__ uint32_t s_wsum[kDigitWaves];
     __shared__ uint32_t s_k[kSortPart];
     __shared__ uint32_t s_v[kSortPart];
 
     const int64_t K = *n_dev;
     const int nparts = (int)((K + kSortPart - 1) / kSortPart);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_part = atomicAdd(counter, 1u);
-    for (int j = tid; j < kSortWaves * kRadix; j += kSortThreads) (&s_wh[0][0])[j] = 0;
-    __syncthreads();
-    const uint32_t part = s_part;
-    if ((int)part >= nparts) return;
-    const int64_t base = (int64_t)part * kSortPart;
-
-    uint32_t key[kSortItems], val[kSortItems], rk[kSortItems];
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
-        const bool valid = pos < K;
-        key[it] = valid ? kin[pos] : 0u;
-        val[it] = valid ? vin[pos] : 0u;
-    }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
-        const bool valid = pos < K;
-        const uint32_t d = (key[it] >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        const uint32_t below = (uint32_t)__popcll(m & lt_mask);
-        uint32_t prior = 0;
-        if (valid) prior = s_wh[w][d];
-        rk[it] = prior + below;
-        if (valid && below == 0) s_wh[w][d] = prior + (uint32_t)__popcll(m);
-    }
-    __syncthreads();
 
-    // thread = digit: totals, per-wave exclusive offsets, publication
-    const int d = tid;
-    uint32_t c[kSortWaves];
-    uint32_t tot = 0;
-#pragma unroll
-    for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
-    st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kFlagInc : kFlagAgg) | tot);
-    {
-        uint32_t run = 0;
-#pragma unroll
-        for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
-    }
-    {   // block-local exclusive scan over digits
-        uint32_t inc = tot;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += y;
-        }
-        if (lane == 63) s_wsum[w] = inc;
-        __syncthreads();
-        uint32_t pre = 0;
-#pragma unroll
-        for (int q = 0; q < kSortWaves; ++q) if (q < w) pre += s_wsum[q];
-        s_lstart[d] = pre + inc - tot;
-    }
-    uint32_t gexcl;
-    {   // keys of smaller digits over the whole input
-        const uint32_t g = ghist[d];
+    // exclusive scan of the global digit counts, once per block
+    if (tid < kRadix) {
+        const uint32_t g = ghist[tid];
         uint32_t inc = g;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(inc, off, 64);
             if (lane >= off) inc += y;
         }
-        __syncthreads();
         if (lane == 63) s_wsum[w] = inc;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (tid < kRadix) {
         uint32_t pre = 0;
 #pragma unroll
-        for (int q = 0; q < kSortWaves; ++q) if (q < w) pre += s_wsum[q];
-        gexcl = pre + inc - g;
-    }
-    uint32_t excl = 0;
-    if (part > 0) {
-        int64_t p = (int64_t)part - 1;
-        uint32_t spins = 0;
-        while (p >= 0) {
-            const uint32_t st = ld_status(&status[p * kRadix + d]);
-            const uint32_t flag = st >> 30;
-            if (flag == 0) {
-                if (++spins > (1u << 26)) { atomicOr(err, 1u); break; }
-                continue;
-            }
-            excl += st & kValMask;
-            if (flag == 2) break;
-            --p;
-        }
-        st_status(&status[(int64_t)part * kRadix + d], kFlagInc | (excl + tot));
-    }
-    s_gbase[d] = gexcl + excl;
-    __syncthreads();
-
+        for (int q = 0; q < kDigitWaves; ++q) if (q < w) pre += s_wsum[q];
+        const uint32_t g = ghist[tid];
+        // recompute the inclusive value (cheap) rather than keep it live across the barrier
+        uint32_t inc = g;
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
-        if (pos < K) {
-            const uint32_t dg = (key[it] >> shift) & 255u;
-            const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
-            s_k[lp] = key[it];
-            s_v[lp] = val[it];
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
         }
+        s_gexcl[tid] = pre + inc - g;
     }
-    __syncthreads();
-    const int64_t rem = K - base;
-    const int nvalid = rem < kSortPart ? (int)rem : kSortPart;
-    for (int j = tid; j < nvalid; j += kSortThreads) {
-        const uint32_t kk = s_k[j];
-        const uint32_t dg = (kk >> shift) & 255u;
-        const uint32_t g = s_gbase[dg] + ((uint32_t)j - s_lstart[dg]);
-        if ((int64_t)g < K) {
-            kout[g] = kk;
-            vout[g] = s_v[j];
+
+    for (;;) {
+        __syncthreads();  // previous partition done with the LDS
+        if (tid == 0) s_part = atomicAdd(counter, 1u);
+        for (int j = tid; j < kSortWaves * kRadix; j += kSortThreads) (&s_wh[0][0])[j] = 0;
+        __syncthreads();
+        const uint32_t part = s_part;
+        if ((int)part >= nparts) break;
+        const int64_t base = (int64_t)part * kSortPart;
+
+        uint32_t key[kSortItems], rk[kSortItems];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
+            key[it] = pos < K ? kin[pos] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
+            const bool valid = pos < K;
+            const uint32_t d = (key[it] >> shift) & 255u;
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            const uint32_t below = (uint32_t)__popcll(m & lt_mask);
+            uint32_t prior = 0;
+            if (valid) prior = s_wh[w][d];
+            rk[it] = prior + below;
+            if (valid && below == 0) s_wh[w][d] = prior + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+
+        // threads 0..255 = digits: totals, per-wave exclusive offsets, publication, look-back
+        uint32_t tot = 0;
+        if (tid < kRadix) {
+            const int d = tid;
+            uint32_t c[kSortWaves];
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
+            st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kFlagInc : kFlagAgg) | tot);
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
+            // block-local exclusive scan over digits (waves 0..3)
+            uint32_t inc = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            if (lane == 63) s_wsum[w] = inc;
+            s_lstart[d] = inc - tot;  // wave-local part; the waves' offsets are added below
+        }
+        __syncthreads();
+        if (tid < kRadix) {
+            const int d = tid;
+            uint32_t pre = 0;
+#pragma unroll
+            for (int q = 0; q < kDigitWaves; ++q) if (q < w) pre += s_wsum[q];
+            s_lstart[d] += pre;
+            uint32_t excl = 0;
+            if (part > 0) {
+                // look back over a window of kWin predecessors at a time: the
+                // window's loads are independent, so one round trip to the
+                // coherence point covers up to kWin partitions
+                constexpr int kWin = 8;
+                int64_t p = (int64_t)part - 1;
+                uint32_t spins = 0;
+                bool found = false;
+                while (!found && p >= 0) {
+                    uint32_t st[kWin];
+#pragma unroll
+                    for (int q = 0; q < kWin; ++q)
+                        st[q] = (p - q >= 0) ? ld_status(&status[(p - q) * kRadix + d]) : kFlagInc;
+                    int used = 0;
+#pragma unroll
+                    for (int q = 0; q < kWin; ++q) {
+                        if (found || used < q) continue;  // stopped earlier in this window
+                        const uint32_t flag = st[q] >> 30;
+                        if (flag == 0) continue;           // not published yet: reload from here
+                        excl += st[q] & kValMask;
+                        used = q + 1;
+                        if (flag == 2) found = true;
+                    }
+                    p -= used;
+                    if (!found && used == 0 && ++spins > (1u << 24)) { atomicOr(err, 1u); break; }
+                }
+                st_status(&status[(int64_t)part * kRadix + d], kFlagInc | (excl + tot));
+            }
+            s_gbase[d] = s_gexcl[d] + excl;
+        }
+        __syncthreads();
+
+        // values are loaded only now, so that they are not live during the ranking
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
+            if (pos < K) {
+                const uint32_t dg = (key[it] >> shift) & 255u;
+                const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
+                s_k[lp] = key[it];
+                s_v[lp] = vin[pos];
+            }
+        }
+        __syncthreads();
+        const int64_t rem = K - base;
+        const int nvalid = rem < kSortPart ? (int)rem : kSortPart;
+        for (int j = tid; j < nvalid; j += kSortThreads) {
+            const uint32_t kk = s_k[j];
+            const uint32_t dg = (kk >> shift) & 255u;
+            const uint32_t g = s_gbase[dg] + ((uint32_t)j - s_lstart[dg]);
+            if ((int64_t)g < K) {
+                kout[g] = kk;
+                vout[g] = s_v[j];
+            }
         }
     }
 }
@@ -219,9 +255,9 @@ void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_
     const int nparts = sort_partitions(n_max);
     launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass), s);
     if (nparts == 0) return;
-    int hblocks = (int)((n_max + 256 * 8 - 1) / (256 * 8));
-    if (hblocks > 2048) hblocks = 2048;
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(256), 0, s, keys, n_dev, npass, ws);
+    int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
+    if (hblocks > 256) hblocks = 256;
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(kHistThreads), 0, s, keys, n_dev, npass, ws);
 }
 
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
@@ -229,7 +265,15 @@ void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint
     const int nparts = sort_partitions(n_max);
     if (nparts == 0) return;
     uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix, *status = ctr + 8;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)nparts), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev, 8 * p,
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        resident = (cus > 0 ? cus : 256) * kSortBlocksPerCU;
+    }
+    const int grid = nparts < resident ? nparts : resident;
+    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev, 8 * p,
                        hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
 }
 
