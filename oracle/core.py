@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "a3fr_oracle.c")
+_SRC_GRAD = os.path.join(_HERE, "a3fr_oracle_grad.c")
 _LIB_PATH = os.path.join(_HERE, "liba3fr_oracle.so")
 _lib = None
 
@@ -33,7 +34,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
                "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only",
-               _SRC, "-o", tmp, "-lm"]
+               _SRC, _SRC_GRAD, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -76,6 +77,8 @@ def lib():
         L.or_pixel_trace.restype = I64
         L.or_composite.argtypes = [I32, I32, D, D, D, D, P, P, I32, P, I32, P, P]
         L.or_region_sse.argtypes = [I32, I32, D, D, D, D, P, P, P, P]
+        L.or_render_grad.argtypes = [I64, P, P, P, P, P, I32, P, I32, P, D, D, P, P, P, P, P, P, P, C.c_int]
+        L.or_render_grad.restype = I64
         _lib = L
     return _lib
 
@@ -425,3 +428,43 @@ def render_full(scene, cams, nthreads=None):
     res["views"] = views
     res["out"] = np.stack([im["rgb"] for im in res["images"]])
     return res
+
+
+# ---------------------------------------------------------------------------
+# differentiable render (backward pass of the training loop)
+# ---------------------------------------------------------------------------
+def render_grad(mean, log_scale, quat, logit, sh, view: View, weights, smooth=False, deg=3,
+                eps_alpha=EPS_ALPHA, eps_step=EPS_STEP, nthreads=None):
+    """Render one view from the raw parameters and back-propagate dL/dI.
+
+    The forward is the plain definition (every projectable Gaussian in (depth,
+    index) order at every pixel; scale = exp(log-scale), opacity =
+    sigmoid(logit)); the backward is the analytic chain rule of it, used by the
+    optimisation of the Gaussian parameters (Sec. 2.3).  ``weights`` is dL/dI,
+    float64 [3][H][W].  ``smooth`` drops the alpha skip, the early stop and the
+    clamps so that finite differences can pin the chain.
+
+    Inputs: mean [3][N], log_scale [3][N], quat [4][N] (w,x,y,z), logit [N],
+    sh [16][3][N], all float32.  Returns dict(image [3][H][W] f64, amb [H][W]
+    u8, n_proj, grads mean/log_scale/quat/logit/sh in the input layouts, f64)."""
+    L = lib()
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    mean, log_scale, quat, logit, sh = f32(mean), f32(log_scale), f32(quat), f32(logit), f32(sh)
+    n = int(mean.shape[1])
+    nk = (deg + 1) ** 2
+    assert mean.shape == (3, n) and log_scale.shape == (3, n) and quat.shape == (4, n)
+    assert logit.shape == (n,) and sh.shape[1:] == (3, n) and sh.shape[0] >= nk
+    sh = np.ascontiguousarray(sh[:nk])
+    H, W = view.height, view.width
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    assert w.shape == (3, H, W)
+    img = np.zeros((3, H, W), np.float64)
+    amb = np.zeros((H, W), np.uint8)
+    g = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)), quat=np.zeros((4, n)), logit=np.zeros(n),
+             sh=np.zeros((nk, 3, n)))
+    vc = view.to_c()
+    m = L.or_render_grad(n, _p(mean), _p(log_scale), _p(quat), _p(logit), _p(sh), deg, C.byref(vc),
+                         1 if smooth else 0, _p(w), eps_alpha, eps_step, _p(img), _p(amb),
+                         _p(g["mean"]), _p(g["log_scale"]), _p(g["quat"]), _p(g["logit"]), _p(g["sh"]),
+                         nthreads or default_threads())
+    return dict(image=img, amb=amb, n_proj=int(m), grads=g)
