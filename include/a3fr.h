@@ -226,6 +226,67 @@ a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze,
 /* Counters of the last preprocess / bin_sort (host struct). */
 a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
 
+/* ---- training: device activation and the backward pass ------------------ */
+
+/* The optimised (raw) parameters of the scene.  Sec. 2.3: every point carries
+ * trainable position, scale, rotation, opacity and SH colour; the scale is
+ * optimised as its logarithm and the opacity as a logit, so that any real
+ * value is valid.  float32 device pointers, layouts as in a3fr_scene. */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;          /* 0..3 */
+    int32_t reserved;
+    const float *mean_dev;      /* [3][n] */
+    const float *log_scale_dev; /* [3][n] */
+    const float *quat_dev;      /* [4][n] (w, x, y, z), any non-zero norm */
+    const float *logit_dev;     /* [n] */
+    const float *sh_dev;        /* [n][(sh_degree+1)^2][3] */
+} a3fr_params;
+
+/* Gradients of a scalar loss with respect to a3fr_params, same layouts,
+ * float32 device pointers owned by the caller; overwritten (not accumulated). */
+typedef struct {
+    float *mean_dev;      /* [3][n] */
+    float *log_scale_dev; /* [3][n] */
+    float *quat_dev;      /* [4][n] */
+    float *logit_dev;     /* [n] */
+    float *sh_dev;        /* [n][(sh_degree+1)^2][3] */
+} a3fr_grads;
+
+/* Activation on the device: scale_dev [3][n] = exp(log_scale) and
+ * opacity_dev [n] = 1/(1 + exp(-logit)), each evaluated in float64 and
+ * rounded once to float32.  Together with params->mean_dev, quat_dev and
+ * sh_dev they form the a3fr_scene of the forward render. */
+a3fr_status a3fr_activate(a3fr_ctx *ctx, const a3fr_params *params, float *scale_dev, float *opacity_dev);
+
+/* Reverse mode of a3fr_blend for the frame of the last a3fr_preprocess /
+ * a3fr_bin_sort / a3fr_blend: given dL/d(rgb) (dl_drgb_dev, the layout of
+ * a3fr_blend's rgb_dev) and that blend's T_dev and last_dev outputs, each
+ * active tile walks its list back to front from the last blended Gaussian,
+ * recovering the transmittance in front of every Gaussian by dividing by
+ * (1 - alpha) -- nothing is stored per (pixel, Gaussian) -- and accumulates,
+ * per (view, Gaussian), dL/d(opacity), dL/d(rgb) and the sums that give
+ * dL/d(2D centre) and dL/d(inverse 2D covariance).  Alpha and the skip and
+ * stop decisions are evaluated exactly as in the forward blend; where alpha
+ * is clamped at 0.99 it passes no gradient.  The accumulators stay in the
+ * context for a3fr_preprocess_backward.  Pixels of inactive tiles are
+ * ignored; last values beyond a tile's list are clamped to its length. */
+a3fr_status a3fr_blend_backward(a3fr_ctx *ctx, const float *dl_drgb_dev, const float *T_dev,
+                                const uint32_t *last_dev);
+
+/* Reverse mode of the projection and colour of a3fr_preprocess and of
+ * a3fr_activate, after a3fr_blend_backward: for every Gaussian, the chain
+ * rule in float64 from the accumulated 2D gradients of each view through the
+ * EWA projection (with the guard-band clamp of the Jacobian), the view
+ * covariance, the 3D covariance R(q) S S' R(q)', the quaternion
+ * normalisation, the exponential of the log-scale and the sigmoid of the
+ * logit, and from the colour gradient through the clamp at zero and the SH
+ * basis to the SH coefficients and, through the viewing direction, the
+ * mean.  Gradients are summed over the views and written to *grads.
+ * params must be the parameters whose activation was rendered (same n and
+ * sh_degree as the scene of the last a3fr_preprocess). */
+a3fr_status a3fr_preprocess_backward(a3fr_ctx *ctx, const a3fr_params *params, const a3fr_grads *grads);
+
 /* ---- per-stage timing (HIP events on the context's stream) -------------- */
 typedef enum {
     A3FR_STAGE_MASKS = 0,      /* active-tile masks */
@@ -239,7 +300,10 @@ typedef enum {
     A3FR_STAGE_BLEND = 8,      /* front-to-back blend */
     A3FR_STAGE_COMPOSITE = 9,  /* foveated composite */
     A3FR_STAGE_DEPTH_SORT = 10,/* radix sort of the visible entries by depth (histograms + 4 passes) */
-    A3FR_STAGE_COUNT = 11
+    A3FR_STAGE_ACTIVATE = 11,  /* device activation */
+    A3FR_STAGE_BLEND_BWD = 12, /* reverse blend (including the clear of its accumulators) */
+    A3FR_STAGE_PREPROCESS_BWD = 13, /* reverse projection, colour and activation */
+    A3FR_STAGE_COUNT = 14
 } a3fr_stage;
 
 typedef struct {

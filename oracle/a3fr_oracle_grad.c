@@ -171,23 +171,24 @@ static void og_forward_one(int64_t n, int64_t i, const float *mean, const float 
 
 typedef struct {
     int64_t n; int nk; const og_view *v; int smooth;
+    int64_t wx0, wy0, ww, wh;   /* pixel window */
     const og_g *G; const uint32_t *list; int64_t m;
     const double *wgt; double eps_alpha, eps_step;
     double *img; uint8_t *amb;
     int nchunks;
-    double *acc;  /* [nchunks][n][9]: dA dB dC dmux dmuy do dc0 dc1 dc2 */
+    double *acc;  /* [nchunks][m][9] by list position: dA dB dC du dv do dc0 dc1 dc2 */
 } og_ctx;
 
 static void og_pixels(void *vctx, int64_t chunk) {
     og_ctx *C = (og_ctx *)vctx;
     const og_view *v = C->v;
     const int64_t W = v->width, H = v->height, HW = W * H;
-    int64_t y0 = H * chunk / C->nchunks, y1 = H * (chunk + 1) / C->nchunks;
-    double *acc = C->acc + chunk * C->n * 9;
+    int64_t y0 = C->wy0 + C->wh * chunk / C->nchunks, y1 = C->wy0 + C->wh * (chunk + 1) / C->nchunks;
+    double *acc = C->acc + chunk * C->m * 9;  /* indexed by list position */
     int64_t *bl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C->m > 0 ? C->m : 1));
     double *al = (double *)malloc(sizeof(double) * (size_t)(C->m > 0 ? C->m : 1) * 4);
     for (int64_t py = y0; py < y1; ++py)
-        for (int64_t px = 0; px < W; ++px) {
+        for (int64_t px = C->wx0; px < C->wx0 + C->ww; ++px) {
             const double X = px + 0.5, Yc = py + 0.5;
             double T = 1.0, Col[3] = {0, 0, 0}, relT = 0.0;
             int amb = 0;
@@ -212,7 +213,7 @@ static void og_pixels(void *vctx, int64_t chunk) {
                     relT = relTn;
                 }
                 for (int ch = 0; ch < 3; ++ch) Col[ch] += alpha * T * g->col[ch];
-                bl[nb] = C->list[j];
+                bl[nb] = j;
                 al[4 * nb + 0] = alpha;
                 al[4 * nb + 1] = T;
                 al[4 * nb + 2] = G;
@@ -227,11 +228,11 @@ static void og_pixels(void *vctx, int64_t chunk) {
             const double dC[3] = {C->wgt[pix], C->wgt[HW + pix], C->wgt[2 * HW + pix]};
             double S = T * (v->bg[0] * dC[0] + v->bg[1] * dC[1] + v->bg[2] * dC[2]);
             for (int64_t q = nb - 1; q >= 0; --q) {
-                const int64_t i = bl[q];
-                const og_g *g = &C->G[i];
+                const int64_t j = bl[q];
+                const og_g *g = &C->G[C->list[j]];
                 const double alpha = al[4 * q], Tb = al[4 * q + 1], G = al[4 * q + 2];
                 const int clamped = al[4 * q + 3] != 0.0;
-                double *a9 = acc + i * 9;
+                double *a9 = acc + j * 9;
                 const double cd = g->col[0] * dC[0] + g->col[1] * dC[1] + g->col[2] * dC[2];
                 for (int ch = 0; ch < 3; ++ch) a9[6 + ch] += alpha * Tb * dC[ch];
                 const double dalpha = Tb * cd - S / (1.0 - alpha);
@@ -375,14 +376,19 @@ static void og_chain(const og_g *g, const double *a9, const og_view *v, int smoo
     for (int a = 0; a < 3; ++a) gm[a] += (dd[a] - g->dir[a] * dot) / g->vlen;
 }
 
-/* Render one view from raw parameters and back-propagate w = dL/dI.
+/* Render the pixels of the window [wx0, wx0+ww) x [wy0, wy0+wh) of one view
+ * from raw parameters and back-propagate w = dL/dI (pixels outside the window
+ * are neither rendered nor differentiated: their image entries stay as given).
  * Inputs are [k][n] structure-of-arrays (sh [16][3][n]); outputs image
  * [3][H][W], ambiguity flags [H][W] (non-smooth mode; may be NULL), and the
  * gradients (same layouts as the inputs, float64).  Returns the number of
- * projectable Gaussians. */
+ * Gaussians drawn (projectable and, in thresholded mode, with a footprint box
+ * {d' Sigma2D^-1 d <= 11.1} meeting the window: outside it alpha < 1/255
+ * for any opacity <= 1, as 2 ln 255 < 11.1, so the cull is exact). */
 int64_t or_render_grad(int64_t n, const float *mean, const float *log_s, const float *quat, const float *logit,
                        const float *sh, int32_t deg, const og_view *v, int32_t smooth, const double *wgt,
-                       double eps_alpha, double eps_step, double *img, uint8_t *amb, double *g_mean, double *g_logs,
+                       double eps_alpha, double eps_step, int64_t wx0, int64_t wy0, int64_t ww, int64_t wh,
+                       double *img, uint8_t *amb, double *g_mean, double *g_logs,
                        double *g_quat, double *g_logit, double *g_sh, int nthreads) {
     const int nk = (deg + 1) * (deg + 1);
     og_g *G = (og_g *)calloc((size_t)(n > 0 ? n : 1), sizeof(og_g));
@@ -391,14 +397,21 @@ int64_t or_render_grad(int64_t n, const float *mean, const float *log_s, const f
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i) {
         og_forward_one(n, i, mean, log_s, quat, logit, sh, nk, v, smooth, &G[i]);
+        if (G[i].ok && !smooth) {
+            const double ex = sqrt(11.1 * G[i].a), ey = sqrt(11.1 * G[i].c);
+            if (G[i].u + ex < (double)wx0 + 0.5 || G[i].u - ex > (double)(wx0 + ww) - 0.5 ||
+                G[i].v + ey < (double)wy0 + 0.5 || G[i].v - ey > (double)(wy0 + wh) - 0.5)
+                G[i].ok = 0;
+        }
         if (G[i].ok) ord[m++] = ((uint64_t)G[i].depth_bits << 32) | (uint64_t)i;
     }
     qsort(ord, (size_t)m, sizeof(uint64_t), og_u64cmp);
     for (int64_t a = 0; a < m; ++a) list[a] = (uint32_t)(ord[a] & 0xffffffffu);
     int nchunks = nthreads > 0 ? nthreads : 1;
-    if (nchunks > v->height) nchunks = v->height;
-    og_ctx C = {n, nk, v, smooth, G, list, m, wgt, eps_alpha, eps_step, img, amb, nchunks,
-                (double *)calloc((size_t)nchunks * (size_t)(n > 0 ? n : 1) * 9, sizeof(double))};
+    if (nchunks > wh) nchunks = (int)wh;
+    if (nchunks < 1) nchunks = 1;
+    og_ctx C = {n, nk, v, smooth, wx0, wy0, ww, wh, G, list, m, wgt, eps_alpha, eps_step, img, amb, nchunks,
+                (double *)calloc((size_t)nchunks * (size_t)(m > 0 ? m : 1) * 9, sizeof(double))};
     /* one chunk of image rows per thread, each with its own accumulator */
     if (nchunks > OG_MAX_THREADS) nchunks = OG_MAX_THREADS;
     C.nchunks = nchunks;
@@ -419,16 +432,16 @@ int64_t or_render_grad(int64_t n, const float *mean, const float *log_s, const f
     }
     /* reduce the chunk accumulators */
     for (int k = 1; k < nchunks; ++k)
-        for (int64_t j = 0; j < n * 9; ++j) C.acc[j] += C.acc[(int64_t)k * n * 9 + j];
+        for (int64_t j = 0; j < m * 9; ++j) C.acc[j] += C.acc[(int64_t)k * m * 9 + j];
     memset(g_mean, 0, sizeof(double) * 3 * (size_t)n);
     memset(g_logs, 0, sizeof(double) * 3 * (size_t)n);
     memset(g_quat, 0, sizeof(double) * 4 * (size_t)n);
     memset(g_logit, 0, sizeof(double) * (size_t)n);
     memset(g_sh, 0, sizeof(double) * (size_t)nk * 3 * (size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
-        if (!G[i].ok) continue;
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t i = list[j];
         double gm[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glg = 0;
-        og_chain(&G[i], C.acc + i * 9, v, smooth, nk, sh, n, i, gm, gls, gq, &glg, g_sh + i);
+        og_chain(&G[i], C.acc + j * 9, v, smooth, nk, sh, n, i, gm, gls, gq, &glg, g_sh + i);
         for (int k = 0; k < 3; ++k) { g_mean[(int64_t)k * n + i] = gm[k]; g_logs[(int64_t)k * n + i] = gls[k]; }
         for (int k = 0; k < 4; ++k) g_quat[(int64_t)k * n + i] = gq[k];
         g_logit[i] = glg;

@@ -77,7 +77,8 @@ def lib():
         L.or_pixel_trace.restype = I64
         L.or_composite.argtypes = [I32, I32, D, D, D, D, P, P, I32, P, I32, P, P]
         L.or_region_sse.argtypes = [I32, I32, D, D, D, D, P, P, P, P]
-        L.or_render_grad.argtypes = [I64, P, P, P, P, P, I32, P, I32, P, D, D, P, P, P, P, P, P, P, C.c_int]
+        L.or_render_grad.argtypes = [I64, P, P, P, P, P, I32, P, I32, P, D, D, I64, I64, I64, I64,
+                                     P, P, P, P, P, P, P, C.c_int]
         L.or_render_grad.restype = I64
         _lib = L
     return _lib
@@ -434,7 +435,7 @@ def render_full(scene, cams, nthreads=None):
 # differentiable render (backward pass of the training loop)
 # ---------------------------------------------------------------------------
 def render_grad(mean, log_scale, quat, logit, sh, view: View, weights, smooth=False, deg=3,
-                eps_alpha=EPS_ALPHA, eps_step=EPS_STEP, nthreads=None):
+                eps_alpha=EPS_ALPHA, eps_step=EPS_STEP, nthreads=None, window=None):
     """Render one view from the raw parameters and back-propagate dL/dI.
 
     The forward is the plain definition (every projectable Gaussian in (depth,
@@ -445,8 +446,10 @@ def render_grad(mean, log_scale, quat, logit, sh, view: View, weights, smooth=Fa
     clamps so that finite differences can pin the chain.
 
     Inputs: mean [3][N], log_scale [3][N], quat [4][N] (w,x,y,z), logit [N],
-    sh [16][3][N], all float32.  Returns dict(image [3][H][W] f64, amb [H][W]
-    u8, n_proj, grads mean/log_scale/quat/logit/sh in the input layouts, f64)."""
+    sh [16][3][N], all float32.  ``window`` = (x0, y0, w, h) restricts the
+    rendered and differentiated pixels (default: the whole view).  Returns
+    dict(image [3][H][W] f64, amb [H][W] u8, n_proj, grads
+    mean/log_scale/quat/logit/sh in the input layouts, f64)."""
     L = lib()
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     mean, log_scale, quat, logit, sh = f32(mean), f32(log_scale), f32(quat), f32(logit), f32(sh)
@@ -463,8 +466,10 @@ def render_grad(mean, log_scale, quat, logit, sh, view: View, weights, smooth=Fa
     g = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)), quat=np.zeros((4, n)), logit=np.zeros(n),
              sh=np.zeros((nk, 3, n)))
     vc = view.to_c()
+    x0, y0, ww, wh = (0, 0, W, H) if window is None else (int(a) for a in window)
+    assert 0 <= x0 and 0 <= y0 and ww >= 0 and wh >= 0 and x0 + ww <= W and y0 + wh <= H
     m = L.or_render_grad(n, _p(mean), _p(log_scale), _p(quat), _p(logit), _p(sh), deg, C.byref(vc),
-                         1 if smooth else 0, _p(w), eps_alpha, eps_step, _p(img), _p(amb),
+                         1 if smooth else 0, _p(w), eps_alpha, eps_step, x0, y0, ww, wh, _p(img), _p(amb),
                          _p(g["mean"]), _p(g["log_scale"]), _p(g["quat"]), _p(g["logit"]), _p(g["sh"]),
                          nthreads or default_threads())
     return dict(image=img, amb=amb, n_proj=int(m), grads=g)

@@ -67,12 +67,23 @@ class Fovea_(C.Structure):
 
 
 STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite",
-          "depth_sort"]
+          "depth_sort", "activate", "blend_bwd", "preprocess_bwd"]
 
 
 class Profile_(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 11), ("ms", C.c_double * 11), ("sort_keys", C.c_int64),
+    _fields_ = [("launches", C.c_int64 * len(STAGES)), ("ms", C.c_double * len(STAGES)), ("sort_keys", C.c_int64),
                 ("sort_passes", C.c_int64), ("blend_pairs", C.c_int64)]
+
+
+class Params_(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
+                ("mean_dev", C.c_void_p), ("log_scale_dev", C.c_void_p), ("quat_dev", C.c_void_p),
+                ("logit_dev", C.c_void_p), ("sh_dev", C.c_void_p)]
+
+
+class Grads_(C.Structure):
+    _fields_ = [("mean_dev", C.c_void_p), ("log_scale_dev", C.c_void_p), ("quat_dev", C.c_void_p),
+                ("logit_dev", C.c_void_p), ("sh_dev", C.c_void_p)]
 
 
 class Counts_(C.Structure):
@@ -110,6 +121,9 @@ def lib():
         "a3fr_fp64_probe": [P, P, P, P, P, I64],
         "a3fr_set_profiling": [P, I32],
         "a3fr_get_profile": [P, C.POINTER(Profile_)],
+        "a3fr_activate": [P, C.POINTER(Params_), P, P],
+        "a3fr_blend_backward": [P, P, P, P],
+        "a3fr_preprocess_backward": [P, C.POINTER(Params_), C.POINTER(Grads_)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -192,8 +206,50 @@ class DeviceScene:
         return s
 
 
+def params_struct(n, sh_degree, mean, log_scale, quat, logit, sh) -> Params_:
+    """a3fr_params from device tensors mean [3][n], log_scale [3][n], quat [4][n],
+    logit [n], sh [n][(deg+1)^2][3] (float32, contiguous)."""
+    nk = (sh_degree + 1) ** 2
+    for t, shape in ((mean, (3, n)), (log_scale, (3, n)), (quat, (4, n)), (logit, (n,)), (sh, (n, nk, 3))):
+        if tuple(t.shape) != shape or str(t.dtype) != "torch.float32":
+            raise ValueError(f"expected float32 tensor of shape {shape}, got {tuple(t.shape)} {t.dtype}")
+    p = Params_()
+    p.n, p.sh_degree = n, sh_degree
+    p.mean_dev, p.log_scale_dev, p.quat_dev = _dp(mean), _dp(log_scale), _dp(quat)
+    p.logit_dev, p.sh_dev = _dp(logit), _dp(sh)
+    return p
+
+
+class DeviceParams:
+    """Optimised (raw) parameters resident in device memory: mean [3][n],
+    log_scale [3][n], quat [4][n], logit [n], sh [n][(deg+1)^2][3]."""
+
+    def __init__(self, mean, log_scale, quat, logit, sh, sh_degree=3):
+        self.mean, self.log_scale, self.quat, self.logit, self.sh = mean, log_scale, quat, logit, sh
+        self.n = int(logit.shape[0])
+        self.sh_degree = sh_degree
+
+    @classmethod
+    def from_host(cls, scene, device="cuda", sh_degree=3):
+        import torch
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        nk = (sh_degree + 1) ** 2
+        sh = np.transpose(scene.sh[:nk], (2, 0, 1))  # [coef][ch][n] -> [n][coef][ch]
+        return cls(f(scene.mean), f(scene.log_scale), f(scene.quat), f(scene.logit), f(sh), sh_degree)
+
+    def tensors(self):
+        return self.mean, self.log_scale, self.quat, self.logit, self.sh
+
+    def struct(self) -> Params_:
+        return params_struct(self.n, self.sh_degree, *self.tensors())
+
+
 class Context:
-    """One a3fr context bound to a HIP stream (torch's current stream by default)."""
+    """One a3fr context bound to a HIP stream (torch's current stream by default).
+
+    ``generation`` counts the frames preprocessed on this context; the buffered
+    intermediates that a3fr_blend_backward and a3fr_preprocess_backward read
+    belong to the latest one."""
 
     def __init__(self, stream=None):
         import torch
@@ -204,6 +260,7 @@ class Context:
         h = C.c_void_p()
         self._check(self._L.a3fr_create(C.byref(h), C.c_void_p(stream.cuda_stream)), ctx=None)
         self._h = h
+        self.generation = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -229,6 +286,7 @@ class Context:
         self._check(self._L.a3fr_sync(self._h))
 
     def preprocess(self, scene: DeviceScene, views, keep=(3, 10)):
+        self.generation += 1
         self._scene = scene  # keep the tensors alive while queued work reads them
         arr = (View_ * len(views))(*[view_struct(v) if not isinstance(v, View_) else v for v in views])
         self._views = arr
@@ -244,11 +302,13 @@ class Context:
         self._check(self._L.a3fr_blend(self._h, _dp(rgb), _dp(T), _dp(last)))
 
     def render_full(self, scene: DeviceScene, cams, out):
+        self.generation += 1
         self._scene = scene
         arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
         self._check(self._L.a3fr_render_full(self._h, C.byref(scene.struct()), arr, len(cams), _dp(out)))
 
     def render_foveated(self, scene: DeviceScene, cams, gazes, fovea: Fovea_, out):
+        self.generation += 1
         self._scene = scene
         arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
         gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
@@ -290,6 +350,21 @@ class Context:
         return dict(stages={STAGES[k]: dict(launches=int(p.launches[k]), ms=float(p.ms[k])) for k in range(len(STAGES))},
                     sort_keys=int(p.sort_keys), sort_passes=int(p.sort_passes), blend_pairs=int(p.blend_pairs))
 
+    def activate(self, params: Params_, scale, opacity):
+        """a3fr_activate: scale [3][n] = exp(log_scale), opacity [n] = sigmoid(logit)."""
+        self._check(self._L.a3fr_activate(self._h, C.byref(params), _dp(scale), _dp(opacity)))
+
+    def blend_backward(self, dl_drgb, T, last):
+        """a3fr_blend_backward for the last blended frame (T, last: that blend's outputs)."""
+        self._check(self._L.a3fr_blend_backward(self._h, _dp(dl_drgb), _dp(T), _dp(last)))
+
+    def preprocess_backward(self, params: Params_, g_mean, g_log_scale, g_quat, g_logit, g_sh):
+        """a3fr_preprocess_backward: writes the gradients of the raw parameters."""
+        g = Grads_()
+        g.mean_dev, g.log_scale_dev, g.quat_dev = _dp(g_mean), _dp(g_log_scale), _dp(g_quat)
+        g.logit_dev, g.sh_dev = _dp(g_logit), _dp(g_sh)
+        self._check(self._L.a3fr_preprocess_backward(self._h, C.byref(params), C.byref(g)))
+
     def fp64_probe(self, x, y):
         import torch
         sq, dv = torch.empty_like(x), torch.empty_like(x)
@@ -310,4 +385,5 @@ def make_foveated_views(cams, gazes, fovea: Fovea_):
 EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", "a3fr_sync", "a3fr_status_str",
             "a3fr_last_error", "a3fr_preprocess", "a3fr_bin_sort", "a3fr_blend", "a3fr_render_full",
             "a3fr_render_foveated", "a3fr_make_foveated_views", "a3fr_composite", "a3fr_region_sse",
-            "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe", "a3fr_set_profiling", "a3fr_get_profile"]
+            "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe", "a3fr_set_profiling", "a3fr_get_profile",
+            "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward"]

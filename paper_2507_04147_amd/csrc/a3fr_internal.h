@@ -87,6 +87,12 @@ void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *r
 void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                   const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
                   unsigned long long *pairs /* nullable: count evaluated pairs */, hipStream_t s);
+void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
+                      const uint32_t *vals, const Record *rec, int64_t n, const float *dl_drgb, const float *T,
+                      const uint32_t *last, float *acc /* [nv * n][12] */, hipStream_t s);
+void launch_activate(const a3fr_params &p, float *scale, float *opacity, hipStream_t s);
+void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
+                           const a3fr_grads &g, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
                       float *out, hipStream_t s);

@@ -49,8 +49,9 @@ struct a3fr_ctx {
     DevBuf counts, depth, rect, rec, score, keep, sel_views, sel;
     DevBuf offsets, block_sums, scalars;
     DevBuf ent_a, ent_b, dkey_a, dkey_b;       // visible entries, depth sort
-    DevBuf keys_a, keys_b, vals_a, vals_b, big_list, big_count;
-    DevBuf sort_hist, sort_status, sort_counters, ranges;
+    DevBuf keys_a, keys_b, vals_a, vals_b;
+    DevBuf sort_status, ranges;
+    DevBuf grad_acc;           // reverse blend sums, [n_views * n][12] float
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
     bool keep_emission = false;
@@ -66,6 +67,8 @@ struct a3fr_ctx {
     bool preprocessed = false;
     bool sorted = false;
     bool sorted_in_b = false;
+    bool blend_bwd_done = false;
+    int sh_degree = 0;
     int64_t K = 0;
 };
 
@@ -249,8 +252,8 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
                       &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
-                      &c->vals_a, &c->vals_b, &c->big_list, &c->big_count, &c->sort_hist,
-                      &c->sort_status, &c->sort_counters, &c->ranges, &c->layers, &c->sse_part,
+                      &c->vals_a, &c->vals_b, &c->grad_acc,
+                      &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -389,6 +392,8 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     c->max_tiles_x = max_tx;
     c->preprocessed = false;
     c->sorted = false;
+    c->blend_bwd_done = false;
+    c->sh_degree = scene->sh_degree;
 
     // ---- workspace
     const int64_t m = (int64_t)nv * n;
@@ -544,6 +549,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     }
     TRY(check_launch(c, "bin_sort"));
     c->sorted = true;
+    c->blend_bwd_done = false;
     return A3FR_OK;
 }
 
@@ -670,6 +676,52 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
                            out + (int64_t)e * 3 * W * H));
     }
     return A3FR_OK;
+}
+
+static a3fr_status check_params(a3fr_ctx *c, const a3fr_params *p) {
+    if (!p) return fail(c, A3FR_EINVAL, "params is NULL");
+    if (p->n < 0 || p->n >= (int64_t(1) << 31)) return fail(c, A3FR_EINVAL, "params.n must be in [0, 2^31)");
+    if (p->sh_degree < 0 || p->sh_degree > 3) return fail(c, A3FR_EINVAL, "params.sh_degree must be 0..3");
+    if (p->n > 0 && (!p->mean_dev || !p->log_scale_dev || !p->quat_dev || !p->logit_dev || !p->sh_dev))
+        return fail(c, A3FR_EINVAL, "params arrays must not be NULL");
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_activate(a3fr_ctx *c, const a3fr_params *p, float *scale, float *opacity) {
+    if (!c) return A3FR_EINVAL;
+    TRY(check_params(c, p));
+    if (p->n > 0 && (!scale || !opacity)) return fail(c, A3FR_EINVAL, "activate: output arrays must not be NULL");
+    StageTimer t_(c, A3FR_STAGE_ACTIVATE);
+    launch_activate(*p, scale, opacity, c->stream);
+    return check_launch(c, "activate");
+}
+
+a3fr_status a3fr_blend_backward(a3fr_ctx *c, const float *dl, const float *T, const uint32_t *last) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend_backward before a3fr_bin_sort");
+    if (!dl || !T || !last) return fail(c, A3FR_EINVAL, "blend_backward: dl_drgb, T and last must not be NULL");
+    const int64_t m = (int64_t)c->nv * c->n;
+    TRY(ensure(c, c->grad_acc, sizeof(float) * 12 * (size_t)m));
+    StageTimer t_(c, A3FR_STAGE_BLEND_BWD);
+    launch_fill_u32(P<uint32_t>(c->grad_acc), 0u, 12 * m, c->stream);
+    launch_blend_bwd(P<DevView>(c->views), c->nv, c->ntiles, P<uint8_t>(c->active), P<uint32_t>(c->ranges),
+                     sorted_vals(c), P<Record>(c->rec), c->n, dl, T, last, P<float>(c->grad_acc), c->stream);
+    TRY(check_launch(c, "blend_backward"));
+    c->blend_bwd_done = true;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_preprocess_backward(a3fr_ctx *c, const a3fr_params *p, const a3fr_grads *g) {
+    if (!c) return A3FR_EINVAL;
+    TRY(check_params(c, p));
+    if (!c->blend_bwd_done) return fail(c, A3FR_ENOTREADY, "a3fr_preprocess_backward before a3fr_blend_backward");
+    if (p->n != c->n || p->sh_degree != c->sh_degree)
+        return fail(c, A3FR_EINVAL, "preprocess_backward: params differ in n or sh_degree from the rendered scene");
+    if (!g || (p->n > 0 && (!g->mean_dev || !g->log_scale_dev || !g->quat_dev || !g->logit_dev || !g->sh_dev)))
+        return fail(c, A3FR_EINVAL, "preprocess_backward: gradient arrays must not be NULL");
+    StageTimer t_(c, A3FR_STAGE_PREPROCESS_BWD);
+    launch_preprocess_bwd(*p, P<DevView>(c->views), c->nv, P<float>(c->grad_acc), P<Record>(c->rec), *g, c->stream);
+    return check_launch(c, "preprocess_backward");
 }
 
 a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, double rf, double rm, const float *a,

@@ -132,6 +132,160 @@ void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *a
 }
 
 // ------------------------------------------------------------------------
+// reverse blend
+// ------------------------------------------------------------------------
+// Same tile mapping as k_blend (one wave per tile, four horizontally adjacent
+// pixels per lane, 64-record LDS batches), but the batches are taken from the
+// back: each pixel starts at its last blended Gaussian with its final
+// transmittance T and S = T (bg . D), D = dL/dC, and for each blended
+// Gaussian j (alpha >= 1/255, position < last) going towards the front
+//   T_j   = T_{j+1} / (1 - alpha_j)           (transmittance in front of j)
+//   dL/dalpha_j = T_j (c_j . D) - S / (1 - alpha_j),   S += (c_j . D) alpha_j T_j,
+//   dL/dc_j    += alpha_j T_j D.
+// Through alpha = o 2^e (when not clamped at 0.99): dL/do += dL/dalpha 2^e and
+// g = dL/de = dL/dalpha alpha ln 2.  With e = a2 t^2 + c2 dy^2, t = dx + k dy,
+// the pixel sums kept per Gaussian are
+//   [0] sum g t^2, [1] sum g t, [2] sum g t dy, [3] sum g dy^2, [4] sum g dy,
+//   [5] dL/do, [6..8] dL/d(r, g, b)
+// (a2, k, c2 are constant per Gaussian and are applied in the projection's
+// reverse).  The 9 sums are reduced across the wave and added with one atomic
+// each into acc[(view * n + index) * 12 + 0..8].
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ views, int nv,
+                                                  const uint8_t *__restrict__ active,
+                                                  const uint32_t *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                                  int64_t n, const float *__restrict__ dl, const float *__restrict__ Tin,
+                                                  const uint32_t *__restrict__ lastin, float *__restrict__ acc) {
+    const int64_t gt = blockIdx.x;
+    if (!active[gt]) return;
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    const DevView &dv = views[lo];
+    const int64_t lt = gt - dv.tile_off;
+    const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
+    const int W = dv.v.width, H = dv.v.height;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int lane = threadIdx.x;
+    const int py = lane >> 2, px0 = (lane & 3) * 4;
+    const float fy = (float)py + 0.5f;
+    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    const uint32_t len = end - start;
+    const int64_t HW = (int64_t)W * H;
+    const float *dimg = dl + 3 * dv.img_off;
+    float fxq[4], T[4], S[4], D0[4], D1[4], D2[4];
+    uint32_t last[4];
+    uint32_t maxlast = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        fxq[q] = (float)(px0 + q) + 0.5f;
+        const int x = x0 + px0 + q, y = y0 + py;
+        T[q] = 1.0f; S[q] = 0.0f; D0[q] = D1[q] = D2[q] = 0.0f; last[q] = 0;
+        if (x < W && y < H) {
+            const int64_t pix = (int64_t)y * W + x;
+            T[q] = Tin[dv.img_off + pix];
+            last[q] = min(lastin[dv.img_off + pix], len);
+            D0[q] = dimg[pix]; D1[q] = dimg[HW + pix]; D2[q] = dimg[2 * HW + pix];
+            S[q] = T[q] * (dv.v.bg[0] * D0[q] + dv.v.bg[1] * D1[q] + dv.v.bg[2] * D2[q]);
+            maxlast = max(maxlast, last[q]);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, off, 64));
+    const Record *R = rec + (int64_t)lo * n;
+    float *A = acc + (int64_t)lo * n * 12;
+    __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
+    __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
+    __shared__ uint32_t s_i[kBatch];
+    const double dx0 = (double)x0, dy0 = (double)y0;
+    const float kLn2 = 0.6931471805599453f;
+
+    for (int64_t bend = maxlast; bend > 0; bend -= kBatch) {
+        const uint32_t bstart = bend > kBatch ? (uint32_t)(bend - kBatch) : 0u;
+        const uint32_t cnt = (uint32_t)bend - bstart;
+        if ((uint32_t)lane < cnt) {
+            const uint32_t idx = vals[start + bstart + lane];
+            const Record r = R[idx];
+            s_u[lane] = (float)(r.u - dx0);
+            s_v[lane] = (float)(r.v - dy0);
+            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
+            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
+            s_i[lane] = idx;
+        }
+        __syncthreads();
+        for (int jj = (int)cnt - 1; jj >= 0; --jj) {
+            const uint32_t pos = bstart + (uint32_t)jj;
+            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
+            const float dy = fy - mv;
+            const float kdy = kk * dy;
+            const float cdy = c2 * dy * dy;
+            float g_t2 = 0.f, g_t = 0.f, g_tdy = 0.f, g_dy2 = 0.f, g_dy = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
+            bool hit = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float t = (fxq[q] - mu) + kdy;
+                const float e = fmaf(a2, t * t, cdy);
+                const float ex = __builtin_amdgcn_exp2f(e);
+                const float araw = o * ex;
+                const float al = fminf(kAlphaMax, araw);
+                if (pos < last[q] && al >= kAlphaMin) {
+                    hit = true;
+                    const float oma = 1.0f - al;
+                    const float Tb = T[q] / oma;
+                    const float cD = cr * D0[q] + cg * D1[q] + cb * D2[q];
+                    const float w = al * Tb;
+                    g_r = fmaf(w, D0[q], g_r);
+                    g_g = fmaf(w, D1[q], g_g);
+                    g_b = fmaf(w, D2[q], g_b);
+                    const float dal = Tb * cD - S[q] / oma;
+                    S[q] = fmaf(cD, w, S[q]);
+                    T[q] = Tb;
+                    if (araw < kAlphaMax) {
+                        const float g = dal * al * kLn2;
+                        const float gt = g * t;
+                        g_t2 = fmaf(gt, t, g_t2);
+                        g_t += gt;
+                        g_tdy = fmaf(gt, dy, g_tdy);
+                        const float gdy = g * dy;
+                        g_dy2 = fmaf(gdy, dy, g_dy2);
+                        g_dy += gdy;
+                        g_o = fmaf(dal, ex, g_o);
+                    }
+                }
+            }
+            if (__ballot(hit) != 0ull) {
+                g_t2 = wave_sum(g_t2); g_t = wave_sum(g_t); g_tdy = wave_sum(g_tdy);
+                g_dy2 = wave_sum(g_dy2); g_dy = wave_sum(g_dy); g_o = wave_sum(g_o);
+                g_r = wave_sum(g_r); g_g = wave_sum(g_g); g_b = wave_sum(g_b);
+                if (lane < 9) {
+                    const float val = lane == 0 ? g_t2 : lane == 1 ? g_t : lane == 2 ? g_tdy : lane == 3 ? g_dy2 :
+                                      lane == 4 ? g_dy : lane == 5 ? g_o : lane == 6 ? g_r : lane == 7 ? g_g : g_b;
+                    atomicAdd(&A[(int64_t)s_i[jj] * 12 + lane], val);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
+                      const uint32_t *vals, const Record *rec, int64_t n, const float *dl, const float *T,
+                      const uint32_t *last, float *acc, hipStream_t s) {
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(k_blend_bwd, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals, rec, n,
+                       dl, T, last, acc);
+}
+
+// ------------------------------------------------------------------------
 // composite
 // ------------------------------------------------------------------------
 __device__ __forceinline__ int region_of(int x, int y, double gx, double gy, double rf, double rm) {

@@ -160,3 +160,32 @@ def foveated_stereo(n=1_000_000, width=1832, height=1920, seed=2, half_extent=5.
 
 FOVEA_FRACTIONS = (0.15, 0.35)   # fovea and mid radii as fractions of the image width
 PERIPH_KEEP = (3, 10)            # periphery keeps ceil(3/10 of the visible points)
+
+
+def differentiable(n=500_000, size=1024, seed=5):
+    """Differentiable render: n Gaussians in [-1,1]^3 (the single-view recipe),
+    camera at z=-3 looking +z, 60 degree horizontal FOV, size x size."""
+    scene = make_scene(n, 1.0, seed)
+    cam = make_camera(size, size, 60.0, (0.0, 0.0, -3.0))
+    return scene, cam
+
+
+def perturbed(scene: Scene, seed=51, mean_std=0.01, logit_std=0.1) -> Scene:
+    """The optimisation target: a copy of the scene with means + N(0, mean_std)
+    and opacity logits + N(0, logit_std) (drawn in that order, float64, added to
+    the float32 values and rounded once); the opacity is re-activated like
+    make_scene does."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dm = rng.normal(0.0, mean_std, size=scene.mean.shape)
+    dl = rng.normal(0.0, logit_std, size=scene.logit.shape)
+    logit = (scene.logit.astype(np.float64) + dl).astype(np.float32)
+    return Scene(
+        n=scene.n,
+        mean=(scene.mean.astype(np.float64) + dm).astype(np.float32),
+        log_scale=scene.log_scale.copy(),
+        scale=scene.scale.copy(),
+        quat=scene.quat.copy(),
+        logit=logit,
+        opacity=(1.0 / (1.0 + np.exp(-logit.astype(np.float64)))).astype(np.float32),
+        sh=scene.sh.copy(),
+    )

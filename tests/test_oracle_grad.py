@@ -160,3 +160,36 @@ def test_grad_fd_alpha_clamp_and_stop(name):
     P["logit"][:] = 6.0 + 0.1 * np.arange(150) / 150.0   # opacity ~0.9975
     idxs = _sample(P[name].shape, 10, 40 + _SEEDS[name])
     _fd_check(P, v, wgt, False, name, idxs, rel_h=1e-6, tol=2e-3)
+
+
+def test_grad_window_equals_restricted_full_render():
+    """Rendering and differentiating a pixel window (with the exact footprint
+    cull of the thresholded mode) equals the whole-view run with dL/dI zero
+    outside the window."""
+    sc, cam, v, wgt, P = _setup(n=300, seed=21, w=64, h=48)
+    win = (16, 8, 24, 20)
+    wz = np.zeros_like(wgt)
+    wz[:, 8:28, 16:40] = wgt[:, 8:28, 16:40]
+    full = _run(P, v, wz, False)
+    part = oc.render_grad(P["mean"], P["log_scale"], P["quat"], P["logit"], P["sh"], v, wgt, window=win)
+    np.testing.assert_allclose(part["image"][:, 8:28, 16:40], full["image"][:, 8:28, 16:40], rtol=0, atol=1e-15)
+    assert not part["image"][:, :8].any() and not part["image"][:, :, :16].any()
+    assert part["n_proj"] < full["n_proj"]
+    for k in full["grads"]:
+        np.testing.assert_allclose(part["grads"][k], full["grads"][k], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["mean", "log_scale", "quat", "logit", "sh"])
+def test_grad_fd_differentiable_workload_subset(name):
+    """The finite-difference subset of the differentiable-render workload (its
+    first 1,000 Gaussians at 64 x 64, 60 degree FOV, f = 55.4 px), smooth mode."""
+    sc, _ = synth.differentiable()
+    sub = sc.subset(np.arange(1000))
+    cam = synth.make_camera(64, 64, 60.0, (0.0, 0.0, -3.0))
+    assert abs(cam.fx - 55.4256) < 1e-3
+    v = oc.full_view(cam)
+    wgt = np.random.default_rng(77).normal(size=(3, 64, 64))
+    P = dict(mean=sub.mean.astype(np.float64), log_scale=sub.log_scale.astype(np.float64),
+             quat=sub.quat.astype(np.float64), logit=sub.logit.astype(np.float64), sh=sub.sh.astype(np.float64))
+    idxs = _sample(P[name].shape, 6, 60 + _SEEDS[name])
+    _fd_check(P, v, wgt, True, name, idxs, rel_h=1e-4, tol=2e-4)
