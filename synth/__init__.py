@@ -189,3 +189,22 @@ def perturbed(scene: Scene, seed=51, mean_std=0.01, logit_std=0.1) -> Scene:
         opacity=(1.0 / (1.0 + np.exp(-logit.astype(np.float64)))).astype(np.float32),
         sh=scene.sh.copy(),
     )
+
+
+NET_LAYERS = ((3, 32), (32, 32), (32, 48))  # upsampler convolutions (in, out channels)
+
+
+def net_init(seed=42, last_scale=0.01) -> np.ndarray:
+    """Initial upsampler parameters, flat float32 [24016] in the order
+    W1 [32][3][3][3], b1, W2 [32][32][3][3], b2, W3 [48][32][3][3], b3:
+    each weight and bias ~ U(-1/sqrt(9 in), 1/sqrt(9 in)), the last layer's
+    scaled by last_scale so that the network starts close to its bilinear
+    residual."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for k, (ci, co) in enumerate(NET_LAYERS):
+        bound = 1.0 / math.sqrt(ci * 9)
+        s = last_scale if k == len(NET_LAYERS) - 1 else 1.0
+        parts.append(rng.uniform(-bound, bound, co * ci * 9) * s)
+        parts.append(rng.uniform(-bound, bound, co) * s)
+    return np.concatenate(parts).astype(np.float32)
