@@ -287,6 +287,44 @@ a3fr_status a3fr_blend_backward(a3fr_ctx *ctx, const float *dl_drgb_dev, const f
  * sh_degree as the scene of the last a3fr_preprocess). */
 a3fr_status a3fr_preprocess_backward(a3fr_ctx *ctx, const a3fr_params *params, const a3fr_grads *grads);
 
+/* ---- learned peripheral upsampler ------------------------------------------ */
+
+/* The periphery is rendered at 1/4 resolution per axis (Sec. 2.2: detail
+ * decreases away from the fovea; Sec. 3.5: coarse regions are interpolated
+ * from the rendered samples).  This network brings it back to full
+ * resolution:
+ *   out = pixel_shuffle_x4(conv3(relu(conv2(relu(conv1(x)))))) + bilinear_x4(x),
+ * 3x3 convolutions (zero padding 1, bias) of 3->32, 32->32 and 32->48
+ * channels; channel c*16 + 4i + j of conv3 goes to output pixel
+ * (c, 4y+i, 4x+j); bilinear with align_corners = false, clamp to edge.
+ * bfloat16 operands (input, weights, post-ReLU activations) on the matrix
+ * cores with float32 accumulation; the last layer, the shuffle and the
+ * residual are float32.
+ * theta_dev: the flat float32 parameter vector of A3FR_NET_PARAMS values,
+ *   W1 [32][3][3][3], b1 [32], W2 [32][32][3][3], b2 [32], W3 [48][32][3][3],
+ *   b3 [48] (weights [out][in][ky][kx]). */
+#define A3FR_NET_PARAMS 24016
+
+/* in_dev: float32 [B][3][h][w]; out_dev: float32 [B][3][4h][4w].
+ * for_training = 1 keeps the activations (and their channel-major copies) in
+ * the context for a3fr_net_backward. */
+a3fr_status a3fr_net_forward(a3fr_ctx *ctx, const float *theta_dev, const float *in_dev, int32_t batch, int32_t h,
+                             int32_t w, float *out_dev, int32_t for_training);
+
+/* Mean squared error of the last training forward's out_dev against
+ * target_dev (float32 [B][3][4h][4w]) and its gradient with respect to theta:
+ * grad_dev (float32 [A3FR_NET_PARAMS], overwritten); loss_dev (float32 [1],
+ * may be NULL) receives the loss.  The gradient entering each convolution's
+ * weight and input gradients is rounded to bfloat16 (matrix-core operands);
+ * weight gradients accumulate in float32. */
+a3fr_status a3fr_net_backward(a3fr_ctx *ctx, const float *theta_dev, const float *out_dev, const float *target_dev,
+                              float *grad_dev, float *loss_dev);
+
+/* One Adam step on theta_dev with moment buffers m_dev, v_dev (float32
+ * [A3FR_NET_PARAMS], zero before step 1): bias-corrected moments, step >= 1. */
+a3fr_status a3fr_net_adam(a3fr_ctx *ctx, float *theta_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                          int32_t step, float lr, float beta1, float beta2, float eps);
+
 /* ---- per-stage timing (HIP events on the context's stream) -------------- */
 typedef enum {
     A3FR_STAGE_MASKS = 0,      /* active-tile masks */
@@ -339,7 +377,15 @@ typedef enum {
     A3FR_BUF_ACTIVE = 9,      /* uint8 [n_tiles] active-tile flags */
     A3FR_BUF_KEEP = 10,       /* uint8 [n_views][n] kept by the periphery subset (selecting views) */
     A3FR_BUF_RECORDS = 11,    /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb */
-    A3FR_BUF_DEPTH_ORDER = 12 /* uint32 [E] visible (kept) entries view*n + index, sorted by (depth, view, index) */
+    A3FR_BUF_DEPTH_ORDER = 12,/* uint32 [E] visible (kept) entries view*n + index, sorted by (depth, view, index) */
+    /* upsampler, after a3fr_net_forward(for_training = 1) (gradients after a3fr_net_backward);
+       bfloat16 bits, [B][h][w][C] unless stated */
+    A3FR_BUF_NET_X0 = 13,     /* rounded input, C = 8 (channels 3..7 zero) */
+    A3FR_BUF_NET_A1 = 14,     /* bf16(relu(conv1)), C = 32 */
+    A3FR_BUF_NET_A2 = 15,     /* bf16(relu(conv2)), C = 32 */
+    A3FR_BUF_NET_G3 = 16,     /* bf16(dL/d conv3 output), C = 48 */
+    A3FR_BUF_NET_G2 = 17,     /* bf16(dL/d conv2 output), C = 32 */
+    A3FR_BUF_NET_G1 = 18      /* bf16(dL/d conv1 output), [B][32][h+2][roundup(w,32)+16], data at row 1 and column 8 */
 } a3fr_buffer;
 
 /* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);

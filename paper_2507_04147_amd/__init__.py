@@ -24,7 +24,9 @@ MASK_ALL, MASK_DISC, MASK_ANNULUS = 0, 1, 2
 TILE = 16
 
 BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
-           active=9, keep=10, records=11, depth_order=12)
+           active=9, keep=10, records=11, depth_order=12, net_x0=13, net_a1=14, net_a2=15, net_g3=16, net_g2=17,
+           net_g1=18)
+NET_PARAMS = 24016
 
 _lib = None
 
@@ -124,6 +126,9 @@ def lib():
         "a3fr_activate": [P, C.POINTER(Params_), P, P],
         "a3fr_blend_backward": [P, P, P, P],
         "a3fr_preprocess_backward": [P, C.POINTER(Params_), C.POINTER(Grads_)],
+        "a3fr_net_forward": [P, P, P, I32, I32, I32, P, I32],
+        "a3fr_net_backward": [P, P, P, P, P, P],
+        "a3fr_net_adam": [P, P, P, P, P, I32, C.c_float, C.c_float, C.c_float, C.c_float],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -365,6 +370,24 @@ class Context:
         g.logit_dev, g.sh_dev = _dp(g_logit), _dp(g_sh)
         self._check(self._L.a3fr_preprocess_backward(self._h, C.byref(params), C.byref(g)))
 
+    # ---- upsampler ----
+    def net_forward(self, theta, x, out, for_training=False):
+        """a3fr_net_forward: x [B][3][h][w] -> out [B][3][4h][4w] (float32 device tensors)."""
+        B, c, h, w = x.shape
+        if c != 3 or tuple(out.shape) != (B, 3, 4 * h, 4 * w) or theta.numel() != NET_PARAMS:
+            raise ValueError("net_forward: expected x [B][3][h][w], out [B][3][4h][4w], theta [24016]")
+        self._check(self._L.a3fr_net_forward(self._h, _dp(theta), _dp(x), B, h, w, _dp(out), int(bool(for_training))))
+
+    def net_backward(self, theta, out, target, grad, loss=None):
+        """a3fr_net_backward: MSE of the last training forward against target; grad [24016]."""
+        if tuple(target.shape) != tuple(out.shape) or grad.numel() != NET_PARAMS:
+            raise ValueError("net_backward: target must match out; grad [24016]")
+        self._check(self._L.a3fr_net_backward(self._h, _dp(theta), _dp(out), _dp(target), _dp(grad), _dp(loss)))
+
+    def net_adam(self, theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self._L.a3fr_net_adam(self._h, _dp(theta), _dp(grad), _dp(m), _dp(v), int(step), float(lr),
+                                          float(beta1), float(beta2), float(eps)))
+
     def fp64_probe(self, x, y):
         import torch
         sq, dv = torch.empty_like(x), torch.empty_like(x)
@@ -386,4 +409,5 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_last_error", "a3fr_preprocess", "a3fr_bin_sort", "a3fr_blend", "a3fr_render_full",
             "a3fr_render_foveated", "a3fr_make_foveated_views", "a3fr_composite", "a3fr_region_sse",
             "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe", "a3fr_set_profiling", "a3fr_get_profile",
-            "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward"]
+            "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward", "a3fr_net_forward",
+            "a3fr_net_backward", "a3fr_net_adam"]

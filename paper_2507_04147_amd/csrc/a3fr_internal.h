@@ -51,6 +51,36 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
 
+// ---- upsampler ----
+// flat float32 parameter vector: W1 [32][3][3][3], b1 [32], W2 [32][32][3][3],
+// b2 [32], W3 [48][32][3][3], b3 [48] (weights [out][in][ky][kx])
+constexpr int kNetW1 = 0, kNetB1 = 864, kNetW2 = 896, kNetB2 = 10112, kNetW3 = 10144, kNetB3 = 23968;
+constexpr int kNetParams = 24016;
+// bf16 packed weights: forward [9][co][cin padded to 8], input gradient [9][ci][co]
+struct NetPacked {
+    uint16_t *f1, *f2, *d2, *f3, *d3;
+};
+constexpr int64_t kNetPackedElems = 9 * 32 * 8 + 9 * 32 * 32 * 2 + 9 * 48 * 32 * 2;
+struct NetConvArgs {
+    const uint16_t *in;       // NHWC bf16, KIN channels
+    const uint16_t *wpk;      // [9][NOUT][KIN] bf16
+    const float *bias;        // forward: [NOUT]
+    const uint16_t *mask;     // input gradient: NHWC bf16 activation whose sign masks the result
+    uint16_t *out;            // NHWC bf16 (nullable)
+    uint16_t *out_chw;        // zero-bordered channel-major copy (nullable)
+    const float *img_in;      // last layer: float32 planar input (bilinear residual)
+    float *img_out;           // last layer: float32 planar output [B][3][4h][4w]
+    int B, h, w;
+};
+struct NetWgradArgs {
+    const uint16_t *g;        // channel-major zero-bordered bf16 gradient, NOUT channels
+    const uint16_t *in;       // channel-major zero-bordered bf16 layer input, KIN channels
+    float *grad;              // flat float32 gradient (accumulated with atomics)
+    int off_w, off_b;
+    int B, h, w;
+};
+__host__ __device__ int net_chw_stride(int w);
+
 // ---- kernels' host launchers (all enqueue on `s`) ----
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
@@ -93,6 +123,14 @@ void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_
 void launch_activate(const a3fr_params &p, float *scale, float *opacity, hipStream_t s);
 void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
                            const a3fr_grads &g, hipStream_t s);
+void launch_net_pack(const float *theta, const NetPacked &pk, hipStream_t s);
+void launch_net_input(const float *x, int B, int h, int w, uint16_t *nhwc, uint16_t *chw, hipStream_t s);
+void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a, hipStream_t s);
+void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s);
+void launch_net_mse(const float *out, const float *target, int B, int h, int w, uint16_t *g_nhwc, uint16_t *g_chw,
+                    double *sse, float *loss, hipStream_t s);
+void launch_net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float beta1, float beta2,
+                     float eps, float bc1, float bc2, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
                       float *out, hipStream_t s);

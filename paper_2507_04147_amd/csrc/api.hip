@@ -2,6 +2,7 @@
 // growable device workspace, and the order of launches of one frame.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +53,11 @@ struct a3fr_ctx {
     DevBuf keys_a, keys_b, vals_a, vals_b;
     DevBuf sort_status, ranges;
     DevBuf grad_acc;           // reverse blend sums, [n_views * n][12] float
+    // upsampler workspace: packed weights, activations (NHWC + channel-major copies), gradients
+    DevBuf net_pk, net_x0, net_x0c, net_a1, net_a1c, net_a2, net_a2c, net_g3, net_g3c, net_g2, net_g2c, net_g1c,
+        net_sse;
+    int net_B = 0, net_h = 0, net_w = 0;   // geometry of the channel-major copies (zero borders valid)
+    bool net_trained_fwd = false;          // the last forward kept activations for a backward
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
     bool keep_emission = false;
@@ -252,7 +258,9 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
                       &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
-                      &c->vals_a, &c->vals_b, &c->grad_acc,
+                      &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
+                      &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
+                      &c->net_g1c, &c->net_sse,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
     for (DevBuf *b : bufs)
@@ -724,6 +732,122 @@ a3fr_status a3fr_preprocess_backward(a3fr_ctx *c, const a3fr_params *p, const a3
     return check_launch(c, "preprocess_backward");
 }
 
+// ---- upsampler ------------------------------------------------------------
+static NetPacked net_packed(a3fr_ctx *c) {
+    uint16_t *p = P<uint16_t>(c->net_pk);
+    NetPacked pk;
+    pk.f1 = p;
+    pk.f2 = pk.f1 + 9 * 32 * 8;
+    pk.d2 = pk.f2 + 9 * 32 * 32;
+    pk.f3 = pk.d2 + 9 * 32 * 32;
+    pk.d3 = pk.f3 + 9 * 48 * 32;
+    return pk;
+}
+
+static a3fr_status net_check_geom(a3fr_ctx *c, int B, int h, int w) {
+    if (B < 1 || h < 1 || w < 1) return fail(c, A3FR_EINVAL, "net: batch, height and width must be positive");
+    if ((int64_t)B * h * w > (int64_t(1) << 28) || h > 65535 * 8 || w > 65535 * 64 || B > 65535)
+        return fail(c, A3FR_EINVAL, "net: input too large");
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_net_forward(a3fr_ctx *c, const float *theta, const float *in, int32_t B, int32_t h, int32_t w,
+                             float *out, int32_t for_training) {
+    if (!c) return A3FR_EINVAL;
+    TRY(net_check_geom(c, B, h, w));
+    if (!theta || !in || !out) return fail(c, A3FR_EINVAL, "net_forward: NULL pointer");
+    const int64_t px = (int64_t)B * h * w;
+    const int WS = net_chw_stride(w);
+    const int64_t plane = (int64_t)(h + 2) * WS;
+    TRY(ensure(c, c->net_pk, sizeof(uint16_t) * kNetPackedElems));
+    TRY(ensure(c, c->net_x0, sizeof(uint16_t) * 8 * px));
+    TRY(ensure(c, c->net_a1, sizeof(uint16_t) * 32 * px));
+    TRY(ensure(c, c->net_a2, sizeof(uint16_t) * 32 * px));
+    const bool train = for_training != 0;
+    if (train) {
+        DevBuf *chw[] = {&c->net_x0c, &c->net_a1c, &c->net_a2c, &c->net_g3c, &c->net_g2c, &c->net_g1c};
+        const int chans[] = {8, 32, 32, 48, 32, 32};
+        const bool regeom = c->net_B != B || c->net_h != h || c->net_w != w;
+        for (int k = 0; k < 6; ++k) {
+            const size_t bytes = sizeof(uint16_t) * (size_t)B * chans[k] * plane;
+            const bool grow = chw[k]->cap < bytes;
+            TRY(ensure(c, *chw[k], bytes));
+            // zero borders (and padding columns) hold for a geometry until it changes
+            if (grow || regeom) launch_fill_u32(P<uint32_t>(*chw[k]), 0u, (int64_t)(bytes / 4), c->stream);
+        }
+        TRY(ensure(c, c->net_g3, sizeof(uint16_t) * 48 * px));
+        TRY(ensure(c, c->net_g2, sizeof(uint16_t) * 32 * px));
+        TRY(ensure(c, c->net_sse, 16));
+        c->net_B = B; c->net_h = h; c->net_w = w;
+    }
+    c->net_trained_fwd = false;
+    const NetPacked pk = net_packed(c);
+    launch_net_pack(theta, pk, c->stream);
+    launch_net_input(in, B, h, w, P<uint16_t>(c->net_x0), train ? P<uint16_t>(c->net_x0c) : nullptr, c->stream);
+    NetConvArgs a{};
+    a.B = B; a.h = h; a.w = w;
+    a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1;
+    a.out = P<uint16_t>(c->net_a1); a.out_chw = train ? P<uint16_t>(c->net_a1c) : nullptr;
+    launch_net_conv(1, false, a, c->stream);
+    a.in = P<uint16_t>(c->net_a1); a.wpk = pk.f2; a.bias = theta + kNetB2;
+    a.out = P<uint16_t>(c->net_a2); a.out_chw = train ? P<uint16_t>(c->net_a2c) : nullptr;
+    launch_net_conv(2, false, a, c->stream);
+    a.in = P<uint16_t>(c->net_a2); a.wpk = pk.f3; a.bias = theta + kNetB3;
+    a.out = nullptr; a.out_chw = nullptr; a.img_in = in; a.img_out = out;
+    launch_net_conv(3, false, a, c->stream);
+    TRY(check_launch(c, "net_forward"));
+    c->net_trained_fwd = train;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_net_backward(a3fr_ctx *c, const float *theta, const float *out, const float *target, float *grad,
+                              float *loss) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->net_trained_fwd) return fail(c, A3FR_ENOTREADY, "net_backward needs a net_forward with for_training = 1");
+    if (!theta || !out || !target || !grad) return fail(c, A3FR_EINVAL, "net_backward: NULL pointer");
+    const int B = c->net_B, h = c->net_h, w = c->net_w;
+    const NetPacked pk = net_packed(c);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(grad), 0u, kNetParams, c->stream);
+    launch_fill_u32(P<uint32_t>(c->net_sse), 0u, 2, c->stream);
+    launch_net_mse(out, target, B, h, w, P<uint16_t>(c->net_g3), P<uint16_t>(c->net_g3c), P<double>(c->net_sse), loss,
+                   c->stream);
+    // input gradients: g2 = (g3 * W3') masked by a2 > 0; g1 = (g2 * W2') masked by a1 > 0
+    NetConvArgs a{};
+    a.B = B; a.h = h; a.w = w;
+    a.in = P<uint16_t>(c->net_g3); a.wpk = pk.d3; a.mask = P<uint16_t>(c->net_a2);
+    a.out = P<uint16_t>(c->net_g2); a.out_chw = P<uint16_t>(c->net_g2c);
+    launch_net_conv(3, true, a, c->stream);
+    a.in = P<uint16_t>(c->net_g2); a.wpk = pk.d2; a.mask = P<uint16_t>(c->net_a1);
+    a.out = nullptr; a.out_chw = P<uint16_t>(c->net_g1c);
+    launch_net_conv(2, true, a, c->stream);
+    // weight gradients
+    const int64_t chunks = (int64_t)B * h * ((w + 31) / 32);
+    const int slabs = (int)std::min<int64_t>(chunks, 96);
+    NetWgradArgs wg{};
+    wg.B = B; wg.h = h; wg.w = w; wg.grad = grad;
+    wg.g = P<uint16_t>(c->net_g3c); wg.in = P<uint16_t>(c->net_a2c); wg.off_w = kNetW3; wg.off_b = kNetB3;
+    launch_net_wgrad(3, wg, slabs, c->stream);
+    wg.g = P<uint16_t>(c->net_g2c); wg.in = P<uint16_t>(c->net_a1c); wg.off_w = kNetW2; wg.off_b = kNetB2;
+    launch_net_wgrad(2, wg, slabs, c->stream);
+    wg.g = P<uint16_t>(c->net_g1c); wg.in = P<uint16_t>(c->net_x0c); wg.off_w = kNetW1; wg.off_b = kNetB1;
+    launch_net_wgrad(1, wg, slabs, c->stream);
+    (void)theta;
+    return check_launch(c, "net_backward");
+}
+
+a3fr_status a3fr_net_adam(a3fr_ctx *c, float *theta, const float *grad, float *m, float *v, int32_t step, float lr,
+                          float beta1, float beta2, float eps) {
+    if (!c) return A3FR_EINVAL;
+    if (!theta || !grad || !m || !v) return fail(c, A3FR_EINVAL, "net_adam: NULL pointer");
+    if (step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(c, A3FR_EINVAL, "net_adam: step >= 1, lr >= 0, 0 <= beta < 1, eps > 0");
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    launch_net_adam(theta, grad, m, v, kNetParams, lr, beta1, beta2, eps, bc1, bc2, c->stream);
+    return check_launch(c, "net_adam");
+}
+
 a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, double rf, double rm, const float *a,
                             const float *b, double *sse3, int64_t *count3) {
     if (!c) return A3FR_EINVAL;
@@ -776,8 +900,12 @@ a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
 
 a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_bytes, int64_t *bytes_out) {
     if (!c) return A3FR_EINVAL;
-    if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "nothing preprocessed");
+    const bool net_buf = which >= A3FR_BUF_NET_X0 && which <= A3FR_BUF_NET_G1;
+    if (!net_buf && !c->preprocessed) return fail(c, A3FR_ENOTREADY, "nothing preprocessed");
+    if (net_buf && !c->net_trained_fwd) return fail(c, A3FR_ENOTREADY, "no training forward of the net");
     const int64_t m = (int64_t)c->nv * c->n;
+    const int64_t npx = (int64_t)c->net_B * c->net_h * c->net_w;
+    const int64_t nplane = (int64_t)c->net_B * (c->net_h + 2) * (c->net_w > 0 ? net_chw_stride(c->net_w) : 0);
     const void *src = nullptr;
     int64_t bytes = 0;
     int make64 = 0;  // 1: emission-order keys, 2: sorted keys (rebuilt as tile << 32 | depth)
@@ -805,6 +933,12 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
         case A3FR_BUF_KEEP: src = c->keep.p; bytes = c->nsel ? m : 0; break;
         case A3FR_BUF_RECORDS: src = c->rec.p; bytes = (int64_t)sizeof(Record) * m; break;
         case A3FR_BUF_DEPTH_ORDER: src = c->ent_a.p; bytes = 4 * (int64_t)n_ent; break;
+        case A3FR_BUF_NET_X0: src = c->net_x0.p; bytes = 2 * 8 * npx; break;
+        case A3FR_BUF_NET_A1: src = c->net_a1.p; bytes = 2 * 32 * npx; break;
+        case A3FR_BUF_NET_A2: src = c->net_a2.p; bytes = 2 * 32 * npx; break;
+        case A3FR_BUF_NET_G3: src = c->net_g3.p; bytes = 2 * 48 * npx; break;
+        case A3FR_BUF_NET_G2: src = c->net_g2.p; bytes = 2 * 32 * npx; break;
+        case A3FR_BUF_NET_G1: src = c->net_g1c.p; bytes = 2 * 32 * nplane; break;
         default: return fail(c, A3FR_EINVAL, "unknown buffer");
     }
     if (bytes_out) *bytes_out = bytes;

@@ -208,3 +208,20 @@ def net_init(seed=42, last_scale=0.01) -> np.ndarray:
         parts.append(rng.uniform(-bound, bound, co * ci * 9) * s)
         parts.append(rng.uniform(-bound, bound, co) * s)
     return np.concatenate(parts).astype(np.float32)
+
+
+def crop_poses(seed=41, n=10_000, width=1832, height=1920, crop=256, fov_x_deg=60.0, scale=4):
+    """Camera poses and crop offsets of the upsampler's training pairs: camera
+    at (0,0,-3) + U(-1,1)^3, yaw U(-180,180) deg, pitch U(-30,30) deg, an eye
+    camera of width x height; crop origin uniform over the frame, a multiple
+    of `scale` so that the reduced-resolution crop is pixel-aligned.
+    Returns a list of (Camera, x0, y0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        pos = np.array([0.0, 0.0, -3.0]) + rng.uniform(-1.0, 1.0, 3)
+        yaw, pitch = rng.uniform(-180.0, 180.0), rng.uniform(-30.0, 30.0)
+        x0 = scale * int(rng.integers(0, (width - crop) // scale + 1))
+        y0 = scale * int(rng.integers(0, (height - crop) // scale + 1))
+        out.append((make_camera(width, height, fov_x_deg, pos, rot_yaw_pitch(yaw, pitch)), x0, y0))
+    return out
