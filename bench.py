@@ -38,6 +38,16 @@ BLEND_FLOPS_PER_PAIR = 18
 PREPROCESS_READ_PER_GAUSSIAN = 236
 PREPROCESS_WRITE_PER_VISIBLE = 64  # record 48 + depth 4 + rect 8 + count 4
 PREPROCESS_WRITE_COUNT = 4
+# reverse blend: floating-point operations per revisited (pixel, Gaussian) pair
+# (alpha recomputed: 8; transmittance recovery, colour and alpha gradients: 14;
+# the nine per-Gaussian sums: 21)
+BLEND_BWD_FLOPS_PER_PAIR = 43
+# reverse projection: per Gaussian, parameters read once (mean 12, log-scale 12,
+# quaternion 16, logit 4), the 48-byte accumulator read, gradients written once
+# (236 B at SH degree 3); per drawn Gaussian also its 48-byte record and 192 B
+# of SH coefficients
+PREPROCESS_BWD_BYTES_PER_GAUSSIAN = 44 + 48 + 236
+PREPROCESS_BWD_BYTES_PER_DRAWN = 48 + 192
 
 
 def log(msg):
@@ -54,6 +64,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2, help="oracle frames timed for the CPU baseline")
     ap.add_argument("--only", choices=["both", "foveated", "full"], default="both",
                     help="restrict the timed loops (for profiling runs)")
+    ap.add_argument("--train-steps", type=int, default=10,
+                    help="timed steps of the differentiable-render training loop (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -183,6 +195,8 @@ def main():
         log(f"profiled pass {ms_f_prof:.3f} ms/frame; stages: " +
             ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
 
+    training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline and do_fov:
         import oracle
@@ -226,8 +240,88 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": stages,
+        "training": training,
     }
     print(json.dumps(res), flush=True)
+
+
+def train_leg(pkg, synth, torch, np, steps):
+    """Differentiable-render training step: 500,000 Gaussians at 1024 x 1024,
+    L1 loss against the render of the scene with perturbed means and logits,
+    Adam on all five parameter groups.  One step = activation, preprocess, key
+    sort, blend, loss, reverse blend, reverse projection, Adam update."""
+    from paper_2507_04147_amd import train
+    sc, cam = synth.differentiable()
+    tgt = synth.perturbed(sc)
+    a3 = pkg.Context()
+    v = train.view_from_camera(cam)
+    T = pkg.DeviceParams.from_host(tgt)
+    with torch.no_grad():
+        target = train.render(a3, v, *T.tensors())
+    P = pkg.DeviceParams.from_host(sc)
+    ts = [t.clone().requires_grad_(True) for t in P.tensors()]
+    opt = torch.optim.Adam(ts, lr=1e-3)
+    losses = []
+
+    def step():
+        opt.zero_grad(set_to_none=False)
+        rgb = train.render(a3, v, *ts)
+        loss = (rgb - target).abs().mean()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for _ in range(3):
+        losses.append(float(step().detach()))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1000.0 / steps
+    losses.append(float(loss.detach()))
+    log(f"training step {ms:.3f} ms (L1 {losses[0]:.5f} -> {losses[-1]:.5f})")
+
+    # one profiled step through the C entry points, keeping T and last
+    H, W = cam.height, cam.width
+    n = sc.n
+    with torch.no_grad():
+        pr = pkg.params_struct(n, 3, *[x.detach() for x in ts])
+        scale, opac = torch.empty_like(ts[1]), torch.empty_like(ts[3])
+        rgb = torch.empty((3, H, W), device="cuda")
+        Tt = torch.empty((H, W), device="cuda")
+        last = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        g = [torch.empty_like(x) for x in ts]
+        a3.set_profiling(True)
+        for _ in range(steps):
+            a3.activate(pr, scale, opac)
+            a3.preprocess(pkg.DeviceScene(ts[0].detach(), scale, ts[2].detach(), opac, ts[4].detach()), [v])
+            a3.bin_sort()
+            a3.blend(rgb, Tt, last)
+            dl = torch.sign(rgb - target) / rgb.numel()
+            a3.blend_backward(dl, Tt, last)
+            a3.preprocess_backward(pr, *g)
+        prof = a3.get_profile()
+        a3.set_profiling(False)
+        pairs_bwd = int(last.to(torch.int64).sum().item())
+        drawn = int((a3.inspect("counts", torch.int32) != 0).sum().item())
+    st = {}
+    for name, rec in prof["stages"].items():
+        if rec["launches"]:
+            st[name] = dict(ms_per_step=rec["ms"] / steps, ms_per_launch=rec["ms"] / rec["launches"])
+    bb = st.get("blend_bwd")
+    if bb:
+        tf = BLEND_BWD_FLOPS_PER_PAIR * pairs_bwd / (bb["ms_per_launch"] / 1000.0) / 1e12
+        bb.update(bound="alu", pairs_per_launch=pairs_bwd, achieved_TFLOPs=tf, frac=tf / FP32_VECTOR_PEAK_TF)
+    pb = st.get("preprocess_bwd")
+    if pb:
+        byts = PREPROCESS_BWD_BYTES_PER_GAUSSIAN * n + PREPROCESS_BWD_BYTES_PER_DRAWN * drawn
+        gbs = byts / (pb["ms_per_launch"] / 1000.0) / 1e9
+        pb.update(bound="hbm", bytes_per_launch=byts, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS)
+    a3.close()
+    return dict(workload="differentiable render: 500k-Gaussian uniform cloud over [-1,1]^3, 1024x1024, L1 vs "
+                         "perturbed target, Adam", ms_per_step=ms, steps_per_s=1000.0 / ms,
+                l1_first=losses[0], l1_last=losses[-1], stages=st)
 
 
 if __name__ == "__main__":
