@@ -83,7 +83,7 @@ typedef struct {
     double campos[3];     /* eye centre, world space (view direction for colour) */
     double fx, fy, cx, cy;
     int32_t width, height;
-    int32_t eye;          /* 0 .. 15 */
+    int32_t eye;          /* 0 .. 127 */
     int32_t mask;         /* A3FR_MASK_* */
     int32_t select;       /* 1: draw only the kept periphery subset (see a3fr_preprocess) */
     int32_t reserved;
@@ -127,6 +127,7 @@ typedef struct {
     int64_t n_kept[16];     /* kept periphery points per selecting view (first 16 views) */
     int64_t n_tiles;        /* tiles of all views */
     int64_t n_active_tiles; /* tiles rendered */
+    int64_t n_fallback_tiles; /* periphery tiles re-rendered at full resolution (a3fr_set_fallback) */
 } a3fr_counts;
 
 /* ---- context ------------------------------------------------------------ */
@@ -325,6 +326,75 @@ a3fr_status a3fr_net_backward(a3fr_ctx *ctx, const float *theta_dev, const float
 a3fr_status a3fr_net_adam(a3fr_ctx *ctx, float *theta_dev, const float *grad_dev, float *m_dev, float *v_dev,
                           int32_t step, float lr, float beta1, float beta2, float eps);
 
+/* ---- foveated-frame options -------------------------------------------------- */
+
+/* Upsample the periphery of a3fr_render_foveated with the learned network
+ * (theta_dev: A3FR_NET_PARAMS float32 on the device, used by reference until
+ * changed) instead of bilinear x4; NULL restores bilinear.  The frame width
+ * and height must then be divisible by fovea->scale_periph, which must be 4. */
+a3fr_status a3fr_set_upsampler(a3fr_ctx *ctx, const float *theta_dev);
+
+/* Per-tile error estimate of the periphery with full-resolution fallback in
+ * a3fr_render_foveated.  For each periphery tile, D and K are the opacity
+ * mass per periphery pixel (integral of o exp(-q/2): 2 pi o sqrt(det Sigma2D),
+ * each Gaussian's spread evenly over the tiles of its rectangle) of the
+ * visible Gaussians the periphery subset dropped and kept; with the
+ * transmittance model T ~ exp(-mass), dropping raises the tile's
+ * transmittance by dT = exp(-K) - exp(-(K + D)), and the squared-error
+ * estimate is coef x (dT^2)^power.  Tiles whose estimate is >= mse_threshold
+ * and that reach outside r_mid are rendered at full resolution with every
+ * Gaussian (they join the fovea layer's tile mask in the same pass) and
+ * taken from there by the composite.  mse_threshold = 0: every such tile, so
+ * the periphery equals the plain full-resolution render; +infinity: none
+ * (the default).  mse_threshold >= 0, coef >= 0, power > 0. */
+a3fr_status a3fr_set_fallback(a3fr_ctx *ctx, double mse_threshold, double coef, double power);
+
+/* ---- blend variants and autotuning ----------------------------------------- */
+
+/* The forward blend has A3FR_BLEND_VARIANTS implementations, all giving
+ * bit-identical images (every pixel evaluates the same float32 expressions
+ * over the same list in the same order):
+ *   variant = schedule * 6 + rows_per_lane_index * 3 + batch_index,
+ *   batch (records staged in LDS per step) = {32, 64, 128}[batch_index],
+ *   lane pixel block = 4 x 1 (rows_per_lane_index 0) or 2 x 2 (1),
+ *   schedule 0: one wave per tile in tile order; 1: persistent waves pulling
+ *   active tiles longest list first (the paper's ordering of tiles by their
+ *   number of Gaussians, Sec. 3.5), from an O(tiles) bucket order by the bit
+ *   length of the list length.
+ * The tile itself stays 16 x 16 (the binning unit of the keys). */
+#define A3FR_BLEND_VARIANTS 12
+a3fr_status a3fr_set_blend_variant(a3fr_ctx *ctx, int32_t variant);
+
+/* Times every variant on the current frame (after a3fr_bin_sort; writes a
+ * scratch image, not the caller's), reps timed blends each after one
+ * warm-up, and selects the fastest for later a3fr_blend calls.  ms_out (host,
+ * A3FR_BLEND_VARIANTS, may be NULL): mean ms per blend; best_out (host, may
+ * be NULL): the chosen variant.  Synchronises. */
+a3fr_status a3fr_autotune_blend(a3fr_ctx *ctx, int32_t reps, double *ms_out, int32_t *best_out);
+
+/* ---- HIP graphs ---------------------------------------------------------------- */
+
+/* Records the whole foveated frame of a3fr_render_foveated (preprocess,
+ * selection, fallback, key emission and sort, blend, upsampler, composite,
+ * with the context's options at this moment) into a HIP graph, for frames of
+ * the same layout (image sizes, eyes, fovea parameters) and poses and gazes
+ * given at launch.  No host read-back happens inside the graph: key buffers
+ * hold max_keys keys and the key count stays on the device; a frame with more
+ * keys is cut at max_keys and reported by a3fr_sync as A3FR_ECAPACITY.  One
+ * eager warm-up frame (also written to out_dev) sizes the workspace first.
+ * scene and out_dev must stay valid at the same addresses while the graph is
+ * replayed.  If the context is bound to the null stream it is rebound to an
+ * internal non-blocking stream (stream capture needs one).  While a graph is
+ * held, other calls on the context also run with the key capacity. */
+a3fr_status a3fr_graph_capture(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams,
+                               const a3fr_gaze *gaze, int32_t n_eyes, const a3fr_fovea *fovea, float *out_dev,
+                               int64_t max_keys);
+/* Uploads this frame's views (cameras and gazes; same sizes as captured) and
+ * replays the graph on the context's stream.  Asynchronous. */
+a3fr_status a3fr_graph_launch(a3fr_ctx *ctx, const a3fr_camera *cams, const a3fr_gaze *gaze);
+/* Releases the graph and returns the context to exact key counts. */
+a3fr_status a3fr_graph_destroy(a3fr_ctx *ctx);
+
 /* ---- per-stage timing (HIP events on the context's stream) -------------- */
 typedef enum {
     A3FR_STAGE_MASKS = 0,      /* active-tile masks */
@@ -341,7 +411,9 @@ typedef enum {
     A3FR_STAGE_ACTIVATE = 11,  /* device activation */
     A3FR_STAGE_BLEND_BWD = 12, /* reverse blend (including the clear of its accumulators) */
     A3FR_STAGE_PREPROCESS_BWD = 13, /* reverse projection, colour and activation */
-    A3FR_STAGE_COUNT = 14
+    A3FR_STAGE_FALLBACK = 14,  /* periphery error estimate, fallback masks and recount */
+    A3FR_STAGE_NET = 15,       /* upsampler inference in a3fr_render_foveated */
+    A3FR_STAGE_COUNT = 16
 } a3fr_stage;
 
 typedef struct {
@@ -385,7 +457,10 @@ typedef enum {
     A3FR_BUF_NET_A2 = 15,     /* bf16(relu(conv2)), C = 32 */
     A3FR_BUF_NET_G3 = 16,     /* bf16(dL/d conv3 output), C = 48 */
     A3FR_BUF_NET_G2 = 17,     /* bf16(dL/d conv2 output), C = 32 */
-    A3FR_BUF_NET_G1 = 18      /* bf16(dL/d conv1 output), [B][32][h+2][roundup(w,32)+16], data at row 1 and column 8 */
+    A3FR_BUF_NET_G1 = 18,     /* bf16(dL/d conv1 output), [B][32][h+2][roundup(w,32)+16], data at row 1 and column 8 */
+    /* full-resolution fallback, after an a3fr_render_foveated with a3fr_set_fallback */
+    A3FR_BUF_FB_ENERGY = 19,  /* float32 [2][n_tiles]: dropped, kept opacity mass per pixel (periphery views' tiles) */
+    A3FR_BUF_FB_FLAGS = 20    /* uint8 [n_tiles]: 1 = periphery tile taken from the full-resolution layer */
 } a3fr_buffer;
 
 /* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);

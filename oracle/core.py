@@ -272,9 +272,17 @@ EPS_STEP = 3 * 2.0**-24  # relative rounding of one float32 transmittance update
 
 
 def render(scene, views, tw=TILE, th=TILE, keep_frac=(3, 10), eps_alpha=EPS_ALPHA, eps_step=EPS_STEP,
-           nthreads=None, colours=None, blend=True):
-    """The whole tiled pipeline in FP64. Returns every intermediate."""
+           nthreads=None, colours=None, blend=True, extra_active=None):
+    """The whole tiled pipeline in FP64. Returns every intermediate.
+    extra_active: {view index: bool [tiles_y][tiles_x]} tiles added to that
+    view's mask before counting (the full-resolution fallback)."""
     act, aoff = tile_masks(views, tw, th)
+    if extra_active:
+        act = act.copy()
+        for v, m in extra_active.items():
+            m = np.asarray(m, dtype=bool).reshape(-1)
+            a0 = int(aoff[v])
+            act[a0:a0 + m.size] |= m.astype(act.dtype)
     pr = project(scene, views, tw, th, act, aoff, nthreads)
     n, nv = scene.n, len(views)
     keep = np.zeros((nv, n), np.uint8)
@@ -473,3 +481,67 @@ def render_grad(mean, log_scale, quat, logit, sh, view: View, weights, smooth=Fa
                          _p(g["mean"]), _p(g["log_scale"]), _p(g["quat"]), _p(g["logit"]), _p(g["sh"]),
                          nthreads or default_threads())
     return dict(image=img, amb=amb, n_proj=int(m), grads=g)
+
+
+# ---------------------------------------------------------------------------
+# per-tile error estimate of the periphery and full-resolution fallback
+# ---------------------------------------------------------------------------
+def tile_mass(res, views, pv, tw=TILE, th=TILE):
+    """(D, K) [ty][tx] of periphery view pv: for every visible Gaussian, its
+    opacity mass 2 pi o sqrt(det) = 2 x score split evenly over the tiles of its
+    rectangle, per pixel of a tile; D sums the Gaussians the subset dropped,
+    K the kept ones."""
+    TX = (views[pv].width + tw - 1) // tw
+    TY = (views[pv].height + th - 1) // th
+    D, K = np.zeros((TY, TX)), np.zeros((TY, TX))
+    for i in np.nonzero(res["count"][pv] > 0)[0]:
+        x0, x1, y0, y1 = (int(a) for a in res["rect"][pv][i])
+        nt = (x1 - x0 + 1) * (y1 - y0 + 1)
+        tgt = K if res["keep"][pv][i] else D
+        tgt[y0:y1 + 1, x0:x1 + 1] += 2.0 * res["score"][pv][i] / (nt * tw * th)
+    return D, K
+
+
+def fallback_estimate(D, K, coef, power):
+    """coef x (dT^2)^power, dT = exp(-K) - exp(-(K + D)): the rise of the tile's
+    transmittance under T ~ exp(-opacity mass per pixel) when the dropped mass
+    D is removed."""
+    dT = np.exp(-K) - np.exp(-(K + D))
+    return np.where(dT > 0, coef * np.power(np.maximum(dT * dT, 1e-300), power), 0.0)
+
+
+def fallback_flags(D, K, vp, vf, r_mid, thr, coef, power, tw=TILE, th=TILE):
+    """Periphery tiles whose estimate reaches thr and that contain a
+    full-resolution pixel centre farther than r_mid from the gaze (vf's gaze,
+    full-resolution pixels); s = vf.fx / vp.fx full-resolution pixels per
+    periphery pixel.  Returns (flags [TY][TX], extra bool mask of vf's tiles)."""
+    s = int(round(vf.fx / vp.fx))
+    span = tw * s
+    est = fallback_estimate(D, K, coef, power)
+    TY, TX = D.shape
+    flags = np.zeros((TY, TX), bool)
+    for ty in range(TY):
+        for tx in range(TX):
+            x0, x1 = tx * span + 0.5, min((tx + 1) * span, vf.width) - 0.5
+            y0, y1 = ty * span + 0.5, min((ty + 1) * span, vf.height) - 0.5
+            fx = max(abs(x0 - vf.gx), abs(x1 - vf.gx))
+            fy = max(abs(y0 - vf.gy), abs(y1 - vf.gy))
+            outer = x0 <= x1 and y0 <= y1 and fx * fx + fy * fy > r_mid * r_mid
+            flags[ty, tx] = outer and est[ty, tx] >= thr
+    FX = (vf.width + tw - 1) // tw
+    FY = (vf.height + th - 1) // th
+    extra = np.zeros((FY, FX), bool)
+    for ty, tx in zip(*np.nonzero(flags)):
+        extra[ty * s:(ty + 1) * s, tx * s:(tx + 1) * s] = True
+    return flags, extra
+
+
+def composite_fallback(out, fovea, flags, W, H, gaze, r_mid, span):
+    """Pixels outside r_mid whose periphery tile is flagged take the
+    full-resolution layer's value (out, fovea: [3][H][W])."""
+    out = out.copy()
+    ys, xs = np.mgrid[0:H, 0:W]
+    rho2 = (xs + 0.5 - gaze[0]) ** 2 + (ys + 0.5 - gaze[1]) ** 2
+    sel = (rho2 > r_mid * r_mid) & flags[ys // span, xs // span]
+    out[:, sel] = fovea[:, sel]
+    return out

@@ -25,8 +25,22 @@ TILE = 16
 
 BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
            active=9, keep=10, records=11, depth_order=12, net_x0=13, net_a1=14, net_a2=15, net_g3=16, net_g2=17,
-           net_g1=18)
+           net_g1=18, fb_energy=19, fb_flags=20)
 NET_PARAMS = 24016
+BLEND_VARIANTS = 12
+
+
+def blend_variant_desc(k):
+    """(LDS batch, lane pixel block, schedule) of blend variant k."""
+    return (32, 64, 128)[k % 3], ("4x1", "2x2")[(k // 3) % 2], ("grid", "queue")[k // 6]
+# full-resolution fallback of the periphery: (MSE threshold, coef, power) of the
+# estimate coef x (dT^2)^power, dT the rise of a periphery tile's transmittance
+# caused by the dropped Gaussians; threshold 1e-3 is the squared error of 30 dB.
+# coef maps the 90th percentile of dT^2 over the tiles of 64 frames rendered at
+# the upsampler's training poses to the threshold (calibrate_fallback.py): the
+# top 10% of tiles by dT^2 held 82% of the measured squared error and 10 of the
+# 12 tiles above 1e-3.
+FALLBACK_DEFAULT = (1e-3, 2.41343e+50, 1.0)
 
 _lib = None
 
@@ -69,7 +83,7 @@ class Fovea_(C.Structure):
 
 
 STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite",
-          "depth_sort", "activate", "blend_bwd", "preprocess_bwd"]
+          "depth_sort", "activate", "blend_bwd", "preprocess_bwd", "fallback", "net"]
 
 
 class Profile_(C.Structure):
@@ -90,7 +104,7 @@ class Grads_(C.Structure):
 
 class Counts_(C.Structure):
     _fields_ = [("n_keys", C.c_int64), ("n_kept", C.c_int64 * 16), ("n_tiles", C.c_int64),
-                ("n_active_tiles", C.c_int64)]
+                ("n_active_tiles", C.c_int64), ("n_fallback_tiles", C.c_int64)]
 
 
 def lib():
@@ -129,6 +143,14 @@ def lib():
         "a3fr_net_forward": [P, P, P, I32, I32, I32, P, I32],
         "a3fr_net_backward": [P, P, P, P, P, P],
         "a3fr_net_adam": [P, P, P, P, P, I32, C.c_float, C.c_float, C.c_float, C.c_float],
+        "a3fr_set_upsampler": [P, P],
+        "a3fr_set_blend_variant": [P, I32],
+        "a3fr_graph_capture": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Fovea_), P,
+                               I64],
+        "a3fr_graph_launch": [P, C.POINTER(Camera_), C.POINTER(Gaze_)],
+        "a3fr_graph_destroy": [P],
+        "a3fr_autotune_blend": [P, I32, C.POINTER(D), C.POINTER(I32)],
+        "a3fr_set_fallback": [P, D, D, D],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -334,7 +356,8 @@ class Context:
     def get_counts(self):
         c = Counts_()
         self._check(self._L.a3fr_get_counts(self._h, C.byref(c)))
-        return dict(n_keys=c.n_keys, n_kept=list(c.n_kept), n_tiles=c.n_tiles, n_active_tiles=c.n_active_tiles)
+        return dict(n_keys=c.n_keys, n_kept=list(c.n_kept), n_tiles=c.n_tiles, n_active_tiles=c.n_active_tiles,
+                    n_fallback_tiles=c.n_fallback_tiles)
 
     def inspect(self, which: str, dtype):
         """Copy of a buffered intermediate as a device tensor of `dtype`."""
@@ -369,6 +392,46 @@ class Context:
         g.mean_dev, g.log_scale_dev, g.quat_dev = _dp(g_mean), _dp(g_log_scale), _dp(g_quat)
         g.logit_dev, g.sh_dev = _dp(g_logit), _dp(g_sh)
         self._check(self._L.a3fr_preprocess_backward(self._h, C.byref(params), C.byref(g)))
+
+    # ---- HIP graph of the foveated frame ----
+    def graph_capture(self, scene: DeviceScene, cams, gazes, fovea: Fovea_, out, max_keys):
+        """a3fr_graph_capture: records the foveated frame; writes one warm-up frame to out."""
+        self._graph_refs = (scene, out, scene.struct(), fovea)
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+        self._check(self._L.a3fr_graph_capture(self._h, C.byref(self._graph_refs[2]), arr, gz, len(cams),
+                                               C.byref(fovea), _dp(out), int(max_keys)))
+
+    def graph_launch(self, cams, gazes):
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+        self._check(self._L.a3fr_graph_launch(self._h, arr, gz))
+
+    def graph_destroy(self):
+        self._check(self._L.a3fr_graph_destroy(self._h))
+        self._graph_refs = None
+
+    # ---- blend variants ----
+    def set_blend_variant(self, variant):
+        self._check(self._L.a3fr_set_blend_variant(self._h, int(variant)))
+
+    def autotune_blend(self, reps=3):
+        """a3fr_autotune_blend on the current frame: (ms per variant, chosen variant)."""
+        ms = (C.c_double * BLEND_VARIANTS)()
+        best = C.c_int32()
+        self._check(self._L.a3fr_autotune_blend(self._h, int(reps), ms, C.byref(best)))
+        return list(ms), int(best.value)
+
+    # ---- foveated-frame options ----
+    def set_upsampler(self, theta=None):
+        """a3fr_set_upsampler: periphery through the network (theta [24016] device tensor), or bilinear (None)."""
+        self._net_theta = theta  # keep the tensor alive while the context uses it
+        self._check(self._L.a3fr_set_upsampler(self._h, _dp(theta)))
+
+    def set_fallback(self, mse_threshold=float("inf"), coef=0.0, power=1.0):
+        """a3fr_set_fallback: per-tile error estimate coef * E^power; tiles with estimate >= threshold
+        are rendered at full resolution (threshold inf: off)."""
+        self._check(self._L.a3fr_set_fallback(self._h, float(mse_threshold), float(coef), float(power)))
 
     # ---- upsampler ----
     def net_forward(self, theta, x, out, for_training=False):
@@ -410,4 +473,6 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_render_foveated", "a3fr_make_foveated_views", "a3fr_composite", "a3fr_region_sse",
             "a3fr_get_counts", "a3fr_inspect", "a3fr_fp64_probe", "a3fr_set_profiling", "a3fr_get_profile",
             "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward", "a3fr_net_forward",
-            "a3fr_net_backward", "a3fr_net_adam"]
+            "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
+            "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
+            "a3fr_graph_destroy"]

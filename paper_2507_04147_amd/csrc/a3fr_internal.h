@@ -18,7 +18,7 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr int kMaxViews = 384;
-constexpr int kMaxEyes = 16;
+constexpr int kMaxEyes = 128;  // eye slots per frame batch (64 stereo frames)
 
 // Blend record of one (view, Gaussian): centre in float64 (so that the
 // tile-relative offset keeps full precision at any image size) and the
@@ -43,8 +43,12 @@ struct DevView {
     int64_t cum_off;      // offset of this view's 2D active-tile prefix ((rows + 1) x (tiles_x + 1))
     double limx, limy;    // guard band of the projection Jacobian: (1.3 (W/2)) / fx, (1.3 (H/2)) / fy
     int32_t sel_slot;     // index among selecting views, -1 if none
-    int32_t pad;
+    int32_t remask;       // 1: the tile mask may grow after projection (full-resolution fallback);
+                          //    invisible (view, Gaussian) slots then get an empty rectangle
 };
+
+// rectangle of a (view, Gaussian) slot that is not visible (x0 > x1): x0 = 1, x1 = 0, y0 = 1, y1 = 0
+constexpr uint64_t kEmptyRect = 0x0000000100000001ull;
 
 // Lookback status word of the onesweep sort: [31:30] flag, [29:0] count.
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -102,7 +106,8 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
-                 hipStream_t s);
+                 const uint32_t *K_dev /* nullable: device key count (clamped to K) */, hipStream_t s);
+void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s);
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
                      hipStream_t s);
 void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
@@ -113,10 +118,32 @@ void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_
                          hipStream_t s);
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
                       int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
-void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s);
-void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
-                  const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
-                  unsigned long long *pairs /* nullable: count evaluated pairs */, hipStream_t s);
+void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
+                   hipStream_t s);
+// forward blend: variants (LDS batch depth x lane pixel block x schedule), all bit-identical
+struct BlendArgs {
+    const DevView *views;
+    int nv;
+    int64_t ntiles;
+    const uint8_t *active;
+    const uint32_t *ranges, *vals;
+    const Record *rec;
+    int64_t n;
+    float *rgb, *T;
+    uint32_t *last;
+    unsigned long long *pairs;   // nullable: count evaluated pairs
+    uint32_t *ws;                // kBlendWsWords words (queue schedule)
+    uint32_t *order;             // [ntiles] (queue schedule)
+    int64_t queue_waves;         // persistent waves of the queue schedule
+};
+struct BlendVariant { int batch, rows; bool queue; };
+constexpr int kBlendVariants = A3FR_BLEND_VARIANTS;  // batch {32, 64, 128} x rows {1, 2} x {grid, queue}
+constexpr int kBlendDefault = 1;      // batch 64, 4 x 1 pixels per lane, grid
+constexpr int kBlendWsWords = 68;
+BlendVariant blend_variant(int k);
+void launch_blend(const BlendArgs &a, int variant, hipStream_t s);
+void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t ntiles, uint32_t *ws, uint32_t *order,
+                        hipStream_t s);
 void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                       const uint32_t *vals, const Record *rec, int64_t n, const float *dl_drgb, const float *T,
                       const uint32_t *last, float *acc /* [nv * n][12] */, hipStream_t s);
@@ -131,8 +158,20 @@ void launch_net_mse(const float *out, const float *target, int B, int h, int w, 
                     double *sse, float *loss, hipStream_t s);
 void launch_net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float beta1, float beta2,
                      float eps, float bc1, float bc2, hipStream_t s);
+void launch_drop_energy(const DevView *views, int pv, int64_t n, const uint32_t *counts, const uint8_t *keep,
+                        const uint64_t *rect, const double *score, const float *opacity, int64_t ntiles,
+                        float *energy /* [2][ntiles]: dropped mass, kept mass */, hipStream_t s);
+void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
+                           int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
+                           uint8_t *active, hipStream_t s);
+void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
+                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list, hipStream_t s);
+void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
+                    uint32_t *counts, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
+                      const uint8_t *fb_flags /* nullable: periphery tiles taken from fovea */, int fb_tiles_x,
+                      const DevView *gaze_view /* nullable: read the gaze (v.gx, v.gy) from this device view */,
                       float *out, hipStream_t s);
 void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm, const float *a,
                        const float *b, double *partial /* [nblk][3] */, unsigned long long *cnt /* [nblk][3] */,

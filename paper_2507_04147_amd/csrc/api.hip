@@ -57,6 +57,14 @@ struct a3fr_ctx {
     DevBuf net_pk, net_x0, net_x0c, net_a1, net_a1c, net_a2, net_a2c, net_g3, net_g3c, net_g2, net_g2c, net_g1c,
         net_sse;
     int net_B = 0, net_h = 0, net_w = 0;   // geometry of the channel-major copies (zero borders valid)
+    DevBuf periph_full;                    // upsampled periphery of each eye, [eyes][3][H][W]
+    const float *net_theta = nullptr;      // a3fr_set_upsampler
+    // full-resolution fallback of the periphery (a3fr_set_fallback)
+    double fb_thr = INFINITY, fb_coef = 0.0, fb_pow = 1.0;
+    struct FbPair { int pv, fv; double r_mid; };
+    std::vector<FbPair> fb_plan;           // set by a3fr_render_foveated for its a3fr_preprocess
+    bool fb_last = false;                  // the last preprocess ran the fallback steps
+    DevBuf fb_energy, fb_flags;
     bool net_trained_fwd = false;          // the last forward kept activations for a backward
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
@@ -74,6 +82,19 @@ struct a3fr_ctx {
     bool sorted = false;
     bool sorted_in_b = false;
     bool blend_bwd_done = false;
+    int blend_variant = kBlendDefault;     // a3fr_set_blend_variant / a3fr_autotune_blend
+    // graph mode: key buffers sized to a capacity, counts stay on the device
+    int64_t capacity = 0;                  // 0: exact mode (bin_sort reads the key count)
+    bool capturing = false;                // inside a3fr_graph_capture's stream capture
+    const int32_t *d_row_view = nullptr, *d_row_y = nullptr, *d_sel_views = nullptr, *d_groups = nullptr;
+    hipStream_t own_stream = nullptr;      // capture stream when the caller's is the null stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_eyes = 0;
+    std::vector<a3fr_camera> g_cams;
+    a3fr_fovea g_fovea{};
+    int n_cus = 256;
+    DevBuf blend_ws, blend_order, tune_img;
     int sh_degree = 0;
     int64_t K = 0;
 };
@@ -95,6 +116,10 @@ a3fr_status fail(a3fr_ctx *c, a3fr_status s, const std::string &msg) {
 a3fr_status ensure(a3fr_ctx *c, DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return A3FR_OK;
+    if (c->capturing)
+        return fail(c, A3FR_ECAPACITY, "a buffer would grow during graph capture (the warm-up frame sized it smaller)");
+    if (c->gexec)  // the captured graph holds this buffer's address
+        return fail(c, A3FR_ECAPACITY, "the workspace is frozen while a graph is held (a3fr_graph_destroy first)");
     if (b.p) {
         // the old buffer may still be read by queued work
         HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -199,7 +224,7 @@ a3fr_status check_view(a3fr_ctx *c, const a3fr_view &v, int k) {
     if ((v.width + kTile - 1) / kTile > 65535 || (v.height + kTile - 1) / kTile > 65535)
         return fail(c, A3FR_EINVAL, w + "more than 65535 tiles per axis");
     if ((int64_t)v.width * v.height > (int64_t(1) << 31)) return fail(c, A3FR_EINVAL, w + "image too large");
-    if (v.eye < 0 || v.eye >= kMaxEyes) return fail(c, A3FR_EINVAL, w + "eye must be 0..15");
+    if (v.eye < 0 || v.eye >= kMaxEyes) return fail(c, A3FR_EINVAL, w + "eye must be 0..127");
     if (v.mask < 0 || v.mask > 2) return fail(c, A3FR_EINVAL, w + "mask must be 0, 1 or 2");
     if (v.select != 0 && v.select != 1) return fail(c, A3FR_EINVAL, w + "select must be 0 or 1");
     if (!(v.fx > 0.0) || !(v.fy > 0.0) || !is_fin(v.fx) || !is_fin(v.fy) || !is_fin(v.cx) || !is_fin(v.cy))
@@ -213,6 +238,8 @@ a3fr_status check_view(a3fr_ctx *c, const a3fr_view &v, int k) {
 }
 
 }  // namespace
+
+static void graph_release(a3fr_ctx *c);
 
 extern "C" {
 
@@ -247,6 +274,11 @@ a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
         delete c;
         return A3FR_ENOMEM;
     }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        c->n_cus = cus;
+    (void)hipGetLastError();
     *out = c;
     return A3FR_OK;
 }
@@ -254,13 +286,16 @@ a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
 void a3fr_destroy(a3fr_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    graph_release(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
                       &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
                       &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
-                      &c->net_g1c, &c->net_sse,
+                      &c->net_g1c, &c->net_sse, &c->periph_full, &c->fb_energy, &c->fb_flags, &c->blend_ws,
+                      &c->blend_order, &c->tune_img,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
     for (DevBuf *b : bufs)
@@ -325,10 +360,18 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
     if (c->scalars.p) {
         uint32_t flag = 0;
         HIPCHECK(c, hipMemcpy(&flag, sc_err(c->scalars), sizeof(uint32_t), hipMemcpyDeviceToHost));
-        if (flag) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
+        if (flag & 2u) {
+            launch_fill_u32(sc_err(c->scalars), 0u, 1, c->stream);
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+            return fail(c, A3FR_ECAPACITY, "key count exceeded the graph's key capacity (frame incomplete)");
+        }
+        if (flag & 1u) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
     }
     return A3FR_OK;
 }
+
+static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *views, int32_t nv);
+static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den);
 
 a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_view *views, int32_t nv,
                             int32_t keep_num, int32_t keep_den) {
@@ -351,7 +394,16 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                  std::memcmp(views[j].campos, views[k].campos, sizeof(views[k].campos)) != 0))
                 return fail(c, A3FR_EINVAL, "views with the same eye must share R, t and campos");
     const int64_t n = scene->n;
+    if (c->capturing) {
+        // the view table of each replay is uploaded by a3fr_graph_launch; the layout is the warm-up's
+        if (nv != c->nv || n != c->n) return fail(c, A3FR_EINVAL, "graph capture: frame layout changed");
+    } else {
+        TRY(preprocess_layout(c, n, views, nv));
+    }
+    return preprocess_kernels(c, scene, keep_num, keep_den);
+}
 
+static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *views, int32_t nv) {
     // ---- frame layout
     c->hviews.resize(nv);
     c->hrow_view.clear();
@@ -379,6 +431,8 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
         if (views[k].mask != A3FR_MASK_ALL) coff += (int64_t)(d.tiles_y + 1) * (d.tiles_x + 1);
         if (d.tiles_x > max_tx) max_tx = d.tiles_x;
         d.sel_slot = views[k].select ? (int32_t)c->hsel_views.size() : -1;
+        for (const auto &fp : c->fb_plan)
+            if (fp.fv == k) d.remask = 1;
         if (views[k].select) c->hsel_views.push_back(k);
         if (views[k].mask != A3FR_MASK_ALL) moff += (int64_t)d.tiles_y * (d.tiles_x + 1);
         for (int ty = 0; ty < d.tiles_y; ++ty) {
@@ -401,7 +455,6 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     c->preprocessed = false;
     c->sorted = false;
     c->blend_bwd_done = false;
-    c->sh_degree = scene->sh_degree;
 
     // ---- workspace
     const int64_t m = (int64_t)nv * n;
@@ -445,10 +498,24 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, total, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->upload_done, c->stream));
     char *frame = static_cast<char *>(c->views.p);
-    const int32_t *d_row_view = reinterpret_cast<const int32_t *>(frame + o_rv);
-    const int32_t *d_row_y = reinterpret_cast<const int32_t *>(frame + o_ry);
-    const int32_t *d_sel_views = reinterpret_cast<const int32_t *>(frame + o_sv);
-    const int32_t *d_groups = reinterpret_cast<const int32_t *>(frame + o_gr);
+    c->d_row_view = reinterpret_cast<const int32_t *>(frame + o_rv);
+    c->d_row_y = reinterpret_cast<const int32_t *>(frame + o_ry);
+    c->d_sel_views = reinterpret_cast<const int32_t *>(frame + o_sv);
+    c->d_groups = reinterpret_cast<const int32_t *>(frame + o_gr);
+    return A3FR_OK;
+}
+
+static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den) {
+    const int64_t n = c->n;
+    const int nv = c->nv;
+    const int64_t m = (int64_t)nv * n;
+    const int64_t toff = c->ntiles;
+    const int32_t *d_row_view = c->d_row_view, *d_row_y = c->d_row_y, *d_sel_views = c->d_sel_views,
+                  *d_groups = c->d_groups;
+    c->preprocessed = false;
+    c->sorted = false;
+    c->blend_bwd_done = false;
+    c->sh_degree = scene->sh_degree;
 
     // ---- kernels
     const DevView *dv = P<DevView>(c->views);
@@ -463,6 +530,29 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
         launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
                       keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream); }
+    c->fb_last = false;
+    if (!c->fb_plan.empty() && c->nsel) {
+        // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
+        StageTimer t_(c, A3FR_STAGE_FALLBACK);
+        TRY(ensure(c, c->fb_energy, sizeof(float) * 2 * (size_t)toff));
+        TRY(ensure(c, c->fb_flags, (size_t)toff));
+        launch_fill_u32(P<uint32_t>(c->fb_energy), 0u, 2 * toff, c->stream);
+        for (const auto &fp : c->fb_plan)
+            launch_drop_energy(dv, fp.pv, n, P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
+                               P<double>(c->score), scene->opacity_dev, toff, P<float>(c->fb_energy), c->stream);
+        for (const auto &fp : c->fb_plan)
+            launch_fallback_flags(dv, fp.pv, fp.fv, (int64_t)c->hviews[fp.pv].tiles_x * c->hviews[fp.pv].tiles_y,
+                                  P<float>(c->fb_energy), toff, fp.r_mid, c->fb_thr, c->fb_coef, c->fb_pow,
+                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), c->stream);
+        launch_rows_from_active(dv, c->rows_total, d_row_view, d_row_y, P<uint8_t>(c->active),
+                                P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), c->stream);
+        if (c->cum_entries)
+            launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream);
+        for (const auto &fp : c->fb_plan)
+            launch_recount(dv, fp.fv, n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
+                           c->stream);
+        c->fb_last = true;
+    }
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
@@ -500,12 +590,20 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
 a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (!c) return A3FR_EINVAL;
     if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "a3fr_bin_sort before a3fr_preprocess");
-    HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
-                               c->stream));
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-    const uint64_t K = *c->h_total;
-    if (n_keys_out) *n_keys_out = (int64_t)K;
-    if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
+    uint64_t K = 0;
+    const bool cap_mode = c->capacity > 0;
+    if (cap_mode) {
+        // graph mode: no host read-back; buffers sized to the capacity, counts clamped on the device
+        K = (uint64_t)c->capacity;
+        if (n_keys_out) *n_keys_out = -1;
+    } else {
+        HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                   c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        K = *c->h_total;
+        if (n_keys_out) *n_keys_out = (int64_t)K;
+        if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
+    }
     const int64_t m = (int64_t)c->nv * c->n;
     TRY(ensure(c, c->keys_a, sizeof(uint32_t) * K));
     TRY(ensure(c, c->keys_b, sizeof(uint32_t) * K));
@@ -518,13 +616,16 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass)));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
+    if (cap_mode) launch_clamp_keys(sc_key_total(c->scalars), c->capacity, sc_n_keys(c->scalars), sc_err(c->scalars),
+                                    c->stream);
     {
         StageTimer t_(c, A3FR_STAGE_EMIT);
         launch_emit(dv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
                     P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
-                    P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K, c->stream);
+                    P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
+                    cap_mode ? sc_n_keys(c->scalars) : nullptr, c->stream);
     }
-    if (c->keep_emission) {
+    if (c->keep_emission && !cap_mode) {
         TRY(ensure(c, c->keys_e, sizeof(uint32_t) * K));
         TRY(ensure(c, c->vals_e, sizeof(uint32_t) * K));
         HIPCHECK(c, hipMemcpyAsync(c->keys_e.p, c->keys_a.p, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, c->stream));
@@ -546,13 +647,14 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
             std::swap(vi, vo);
             in_b = !in_b;
         }
-        if (c->profiling) { c->prof_sort_keys += (int64_t)K; c->prof_sort_passes += npass; }
+        if (c->profiling && !cap_mode) { c->prof_sort_keys += (int64_t)K; c->prof_sort_passes += npass; }
     }
     c->sorted_in_b = in_b;
-    c->K = (int64_t)K;
+    c->K = cap_mode ? -1 : (int64_t)K;
     {
         StageTimer t_(c, A3FR_STAGE_RANGES);
-        launch_ranges(in_b ? P<uint32_t>(c->keys_b) : P<uint32_t>(c->keys_a), (int64_t)K, c->ntiles,
+        launch_ranges(in_b ? P<uint32_t>(c->keys_b) : P<uint32_t>(c->keys_a), (int64_t)K,
+                      cap_mode ? sc_n_keys(c->scalars) : nullptr, c->ntiles,
                       P<uint32_t>(c->ranges), c->stream);
     }
     TRY(check_launch(c, "bin_sort"));
@@ -574,6 +676,27 @@ const uint32_t *sorted_vals(a3fr_ctx *c) {
 
 extern "C" {
 
+static a3fr_status blend_with(a3fr_ctx *c, int variant, float *rgb, float *T, uint32_t *last,
+                              unsigned long long *pairs) {
+    TRY(ensure(c, c->blend_ws, sizeof(uint32_t) * kBlendWsWords));
+    TRY(ensure(c, c->blend_order, sizeof(uint32_t) * (size_t)c->ntiles));
+    BlendArgs a{};
+    a.views = P<DevView>(c->views);
+    a.nv = c->nv;
+    a.ntiles = c->ntiles;
+    a.active = P<uint8_t>(c->active);
+    a.ranges = P<uint32_t>(c->ranges);
+    a.vals = sorted_vals(c);
+    a.rec = P<Record>(c->rec);
+    a.n = c->n;
+    a.rgb = rgb; a.T = T; a.last = last; a.pairs = pairs;
+    a.ws = P<uint32_t>(c->blend_ws);
+    a.order = P<uint32_t>(c->blend_order);
+    a.queue_waves = (int64_t)c->n_cus * 24;
+    launch_blend(a, variant, c->stream);
+    return check_launch(c, "blend");
+}
+
 a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
     if (!c) return A3FR_EINVAL;
     if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend before a3fr_bin_sort");
@@ -588,9 +711,53 @@ a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
         }
     }
     StageTimer t_(c, A3FR_STAGE_BLEND);
-    launch_blend(P<DevView>(c->views), c->nv, c->ntiles, P<uint8_t>(c->active), P<uint32_t>(c->ranges),
-                 sorted_vals(c), P<Record>(c->rec), c->n, rgb, T, last, pairs, c->stream);
-    return check_launch(c, "blend");
+    return blend_with(c, c->blend_variant, rgb, T, last, pairs);
+}
+
+a3fr_status a3fr_set_blend_variant(a3fr_ctx *c, int32_t variant) {
+    if (!c) return A3FR_EINVAL;
+    if (variant < 0 || variant >= kBlendVariants) return fail(c, A3FR_EINVAL, "blend variant out of range");
+    c->blend_variant = variant;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_autotune_blend(a3fr_ctx *c, int32_t reps, double *ms_out, int32_t *best_out) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_autotune_blend needs a sorted frame (a3fr_bin_sort)");
+    if (reps < 1 || reps > 1000) return fail(c, A3FR_EINVAL, "reps must be in [1, 1000]");
+    TRY(ensure(c, c->tune_img, sizeof(float) * 3 * (size_t)(c->npix > 0 ? c->npix : 1)));
+    hipEvent_t e0, e1;
+    HIPCHECK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, A3FR_EDEVICE, "hipEventCreate failed");
+    }
+    double best_ms = 1e300;
+    int best = c->blend_variant;
+    a3fr_status st = A3FR_OK;
+    for (int k = 0; k < kBlendVariants && st == A3FR_OK; ++k) {
+        st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr);  // warm-up
+        if (st != A3FR_OK) break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, A3FR_EDEVICE, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == A3FR_OK; ++r)
+            st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr);
+        if (st != A3FR_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(c, A3FR_EDEVICE, "event timing failed");
+            break;
+        }
+        const double per = (double)ms / reps;
+        if (ms_out) ms_out[k] = per;
+        if (per < best_ms) { best_ms = per; best = k; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TRY(st);
+    c->blend_variant = best;
+    if (best_out) *best_out = best;
+    return A3FR_OK;
 }
 
 static void view_from_camera(const a3fr_camera &cam, int eye, a3fr_view &v) {
@@ -609,7 +776,7 @@ static void view_from_camera(const a3fr_camera &cam, int eye, a3fr_view &v) {
 a3fr_status a3fr_render_full(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_cams,
                              float *out) {
     if (!c) return A3FR_EINVAL;
-    if (!cams || n_cams < 1 || n_cams > kMaxEyes) return fail(c, A3FR_EINVAL, "n_cams must be in [1, 16]");
+    if (!cams || n_cams < 1 || n_cams > kMaxEyes) return fail(c, A3FR_EINVAL, "n_cams must be in [1, 128]");
     if (!out) return fail(c, A3FR_EINVAL, "out_dev is NULL");
     std::vector<a3fr_view> v(n_cams);
     for (int e = 0; e < n_cams; ++e) view_from_camera(cams[e], e, v[e]);
@@ -660,7 +827,7 @@ a3fr_status a3fr_composite(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, const
         return fail(c, A3FR_EINVAL, "composite: layer scales too large for the image");
     StageTimer t_(c, A3FR_STAGE_COMPOSITE);
     launch_composite(W, H, g.x, g.y, f->r_fovea, f->r_mid, fov, mid, f->scale_mid, per, f->scale_periph, per_full,
-                     out, c->stream);
+                     nullptr, 0, nullptr, out, c->stream);
     return check_launch(c, "composite");
 }
 
@@ -672,17 +839,64 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     std::vector<a3fr_view> v(3 * n_eyes);
     if (a3fr_make_foveated_views(cams, gaze, n_eyes, f, v.data()) != A3FR_OK)
         return fail(c, A3FR_EINVAL, "render_foveated: bad fovea parameters");
-    TRY(a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den));
+    if (c->net_theta) {
+        if (f->scale_periph != 4) return fail(c, A3FR_EINVAL, "render_foveated: the upsampler needs scale_periph = 4");
+        for (int e = 0; e < n_eyes; ++e)
+            if (cams[e].width % 4 || cams[e].height % 4)
+                return fail(c, A3FR_EINVAL, "render_foveated: the upsampler needs W and H divisible by 4");
+    }
+    const bool fb = std::isfinite(c->fb_thr);
+    c->fb_plan.clear();
+    if (fb)
+        for (int e = 0; e < n_eyes; ++e) c->fb_plan.push_back({3 * e + 2, 3 * e, f->r_mid});
+    a3fr_status st = a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den);
+    c->fb_plan.clear();
+    TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
     TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
     float *L = P<float>(c->layers);
     TRY(a3fr_blend(c, L, nullptr, nullptr));
+    float *pf = nullptr;
+    if (c->net_theta) {
+        int64_t tot = 0;
+        for (int e = 0; e < n_eyes; ++e) tot += 3 * (int64_t)cams[e].width * cams[e].height;
+        TRY(ensure(c, c->periph_full, sizeof(float) * (size_t)tot));
+        pf = P<float>(c->periph_full);
+    }
+    int64_t pf_off = 0;
     for (int e = 0; e < n_eyes; ++e) {
         const DevView &d0 = c->hviews[3 * e], &d1 = c->hviews[3 * e + 1], &d2 = c->hviews[3 * e + 2];
         const int W = cams[e].width, H = cams[e].height;
-        TRY(a3fr_composite(c, W, H, gaze[e], f, L + 3 * d0.img_off, L + 3 * d1.img_off, L + 3 * d2.img_off, nullptr,
-                           out + (int64_t)e * 3 * W * H));
+        const float *per_full = nullptr;
+        if (pf) {
+            StageTimer t_(c, A3FR_STAGE_NET);
+            TRY(a3fr_net_forward(c, c->net_theta, L + 3 * d2.img_off, 1, H / 4, W / 4, pf + pf_off, 0));
+            per_full = pf + pf_off;
+            pf_off += 3 * (int64_t)W * H;
+        }
+        StageTimer t_(c, A3FR_STAGE_COMPOSITE);
+        launch_composite(W, H, gaze[e].x, gaze[e].y, f->r_fovea, f->r_mid, L + 3 * d0.img_off, L + 3 * d1.img_off,
+                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph, per_full,
+                         c->fb_last ? P<uint8_t>(c->fb_flags) + d2.tile_off : nullptr, d2.tiles_x,
+                         P<DevView>(c->views) + 3 * e, out + (int64_t)e * 3 * W * H, c->stream);
+        TRY(check_launch(c, "composite"));
     }
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_set_upsampler(a3fr_ctx *c, const float *theta) {
+    if (!c) return A3FR_EINVAL;
+    c->net_theta = theta;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_set_fallback(a3fr_ctx *c, double thr, double coef, double power) {
+    if (!c) return A3FR_EINVAL;
+    if (!(thr >= 0.0) || !(coef >= 0.0) || !is_fin(coef) || !(power > 0.0) || !is_fin(power))
+        return fail(c, A3FR_EINVAL, "set_fallback: mse_threshold >= 0, coef >= 0 and power > 0, finite");
+    c->fb_thr = thr;
+    c->fb_coef = coef;
+    c->fb_pow = power;
     return A3FR_OK;
 }
 
@@ -848,6 +1062,104 @@ a3fr_status a3fr_net_adam(a3fr_ctx *c, float *theta, const float *grad, float *m
     return check_launch(c, "net_adam");
 }
 
+// ---- graph mode ---------------------------------------------------------------
+static void graph_release(a3fr_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->capacity = 0;
+    c->g_eyes = 0;
+}
+
+a3fr_status a3fr_graph_destroy(a3fr_ctx *c) {
+    if (!c) return A3FR_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    graph_release(c);
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_graph_capture(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, const a3fr_gaze *gaze,
+                               int32_t n_eyes, const a3fr_fovea *f, float *out, int64_t max_keys) {
+    if (!c) return A3FR_EINVAL;
+    if (max_keys < 1 || max_keys >= (int64_t(1) << 30)) return fail(c, A3FR_EINVAL, "max_keys must be in [1, 2^30)");
+    if (c->profiling) return fail(c, A3FR_ENOTREADY, "turn profiling off before capturing a graph");
+    if (!cams || !gaze || !f || !out || n_eyes < 1 || n_eyes > kMaxEyes)
+        return fail(c, A3FR_EINVAL, "graph_capture: bad arguments");
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    graph_release(c);
+    if (!c->stream) {
+        // stream capture needs a stream other than the null stream
+        if (!c->own_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+        c->stream = c->own_stream;
+    }
+    c->capacity = max_keys;
+    // warm-up frame in capacity mode: sizes every buffer for this layout
+    a3fr_status st = a3fr_render_foveated(c, scene, cams, gaze, n_eyes, f, out);
+    if (st == A3FR_OK) st = a3fr_sync(c);
+    if (st != A3FR_OK) {
+        c->capacity = 0;
+        return st;
+    }
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        c->capacity = 0;
+        return fail(c, A3FR_EDEVICE, "hipStreamBeginCapture failed");
+    }
+    c->capturing = true;
+    st = a3fr_render_foveated(c, scene, cams, gaze, n_eyes, f, out);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (st != A3FR_OK || ee != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        c->capacity = 0;
+        return st != A3FR_OK ? st : fail(c, A3FR_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        c->capacity = 0;
+        return fail(c, A3FR_EDEVICE, "hipGraphInstantiate failed");
+    }
+    c->graph = g;
+    c->gexec = x;
+    c->g_eyes = n_eyes;
+    c->g_cams.assign(cams, cams + n_eyes);
+    c->g_fovea = *f;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_graph_launch(a3fr_ctx *c, const a3fr_camera *cams, const a3fr_gaze *gaze) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->gexec) return fail(c, A3FR_ENOTREADY, "no captured graph");
+    if (!cams || !gaze) return fail(c, A3FR_EINVAL, "graph_launch: NULL cameras or gaze");
+    const int ne = c->g_eyes;
+    for (int e = 0; e < ne; ++e)
+        if (cams[e].width != c->g_cams[e].width || cams[e].height != c->g_cams[e].height)
+            return fail(c, A3FR_EINVAL, "graph_launch: image sizes differ from the captured frame");
+    std::vector<a3fr_view> v(3 * ne);
+    if (a3fr_make_foveated_views(cams, gaze, ne, &c->g_fovea, v.data()) != A3FR_OK)
+        return fail(c, A3FR_EINVAL, "graph_launch: bad cameras");
+    for (int k = 0; k < 3 * ne; ++k) TRY(check_view(c, v[k], k));
+    // the fallback plan frozen at capture marks the same views for remasking
+    c->fb_plan.clear();
+    if (c->fb_last)
+        for (int e = 0; e < ne; ++e) c->fb_plan.push_back({3 * e + 2, 3 * e, c->g_fovea.r_mid});
+    const int64_t nt = c->ntiles, np = c->npix, rt = c->rows_total;
+    a3fr_status st = preprocess_layout(c, c->n, v.data(), 3 * ne);
+    c->fb_plan.clear();
+    TRY(st);
+    if (c->ntiles != nt || c->npix != np || c->rows_total != rt)
+        return fail(c, A3FR_EINVAL, "graph_launch: frame layout differs from the captured one");
+    HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
+    c->preprocessed = c->sorted = true;
+    c->K = -1;
+    return A3FR_OK;
+}
+
 a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, double rf, double rm, const float *a,
                             const float *b, double *sse3, int64_t *count3) {
     if (!c) return A3FR_EINVAL;
@@ -874,10 +1186,24 @@ a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, doub
     return A3FR_OK;
 }
 
+// Keys of the last bin_sort: known on the host in exact mode, read from the
+// device (the clamped sort count) in capacity mode.
+static a3fr_status key_count(a3fr_ctx *c, int64_t *K) {
+    if (c->K >= 0 || !c->scalars.p) {
+        *K = c->K < 0 ? 0 : c->K;
+        return A3FR_OK;
+    }
+    uint32_t k = 0;
+    HIPCHECK(c, hipMemcpyAsync(&k, sc_n_keys(c->scalars), 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    *K = (int64_t)k;
+    return A3FR_OK;
+}
+
 a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
     if (!c || !out) return A3FR_EINVAL;
     std::memset(out, 0, sizeof(*out));
-    out->n_keys = c->K;
+    if (c->sorted) TRY(key_count(c, &out->n_keys));
     out->n_tiles = c->ntiles;
     if (!c->preprocessed) return A3FR_OK;
     std::vector<uint8_t> act(c->ntiles > 0 ? c->ntiles : 1);
@@ -891,6 +1217,15 @@ a3fr_status a3fr_get_counts(a3fr_ctx *c, a3fr_counts *out) {
                                    sizeof(uint32_t) * kSelWords * c->nsel, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     for (int64_t t = 0; t < c->ntiles; ++t) out->n_active_tiles += act[t];
+    if (c->fb_last) {
+        std::vector<uint8_t> fl(c->ntiles);
+        HIPCHECK(c, hipMemcpy(fl.data(), c->fb_flags.p, (size_t)c->ntiles, hipMemcpyDeviceToHost));
+        for (int k = 0; k < c->nv; ++k)
+            if (c->hviews[k].v.select) {
+                const DevView &d = c->hviews[k];
+                for (int64_t t = 0; t < (int64_t)d.tiles_x * d.tiles_y; ++t) out->n_fallback_tiles += fl[d.tile_off + t];
+            }
+    }
     for (int s = 0; s < c->nsel; ++s) {
         const int v = c->hsel_views[s];
         if (v < 16) out->n_kept[v] = st[(size_t)kSelWords * s + 1];  // SelState.k
@@ -917,6 +1252,8 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
     const bool need_sort = which == A3FR_BUF_KEYS || which == A3FR_BUF_VALS || which == A3FR_BUF_SORTED_KEYS ||
                            which == A3FR_BUF_SORTED_VALS || which == A3FR_BUF_RANGES;
     if (need_sort && !c->sorted) return fail(c, A3FR_ENOTREADY, "keys not sorted yet");
+    int64_t Kc = 0;
+    if (need_sort) TRY(key_count(c, &Kc));
     if ((which == A3FR_BUF_KEYS || which == A3FR_BUF_VALS) && !c->keep_emission)
         return fail(c, A3FR_ENOTREADY, "emission order kept only with a3fr_set_debug(ctx, 1)");
     switch (which) {
@@ -924,10 +1261,10 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
         case A3FR_BUF_DEPTH: src = c->depth.p; bytes = 4 * m; break;
         case A3FR_BUF_RECT: src = c->rect.p; bytes = 8 * m; break;
         case A3FR_BUF_OFFSETS: src = c->offsets.p; bytes = 4 * ((int64_t)n_ent + 1); break;
-        case A3FR_BUF_KEYS: make64 = 1; bytes = 8 * c->K; break;
-        case A3FR_BUF_VALS: src = c->vals_e.p; bytes = 4 * c->K; break;
-        case A3FR_BUF_SORTED_KEYS: make64 = 2; bytes = 8 * c->K; break;
-        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * c->K; break;
+        case A3FR_BUF_KEYS: make64 = 1; bytes = 8 * Kc; break;
+        case A3FR_BUF_VALS: src = c->vals_e.p; bytes = 4 * Kc; break;
+        case A3FR_BUF_SORTED_KEYS: make64 = 2; bytes = 8 * Kc; break;
+        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * Kc; break;
         case A3FR_BUF_RANGES: src = c->ranges.p; bytes = 8 * c->ntiles; break;
         case A3FR_BUF_ACTIVE: src = c->active.p; bytes = c->ntiles; break;
         case A3FR_BUF_KEEP: src = c->keep.p; bytes = c->nsel ? m : 0; break;
@@ -939,6 +1276,12 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
         case A3FR_BUF_NET_G3: src = c->net_g3.p; bytes = 2 * 48 * npx; break;
         case A3FR_BUF_NET_G2: src = c->net_g2.p; bytes = 2 * 32 * npx; break;
         case A3FR_BUF_NET_G1: src = c->net_g1c.p; bytes = 2 * 32 * nplane; break;
+        case A3FR_BUF_FB_ENERGY:
+            if (!c->fb_last) return fail(c, A3FR_ENOTREADY, "no fallback in the last frame");
+            src = c->fb_energy.p; bytes = 8 * c->ntiles; break;
+        case A3FR_BUF_FB_FLAGS:
+            if (!c->fb_last) return fail(c, A3FR_ENOTREADY, "no fallback in the last frame");
+            src = c->fb_flags.p; bytes = c->ntiles; break;
         default: return fail(c, A3FR_EINVAL, "unknown buffer");
     }
     if (bytes_out) *bytes_out = bytes;
@@ -947,7 +1290,7 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
     if (make64) {
         const uint32_t *t = make64 == 1 ? P<uint32_t>(c->keys_e) : sorted_tiles(c);
         const uint32_t *v = make64 == 1 ? P<uint32_t>(c->vals_e) : sorted_vals(c);
-        launch_make_keys64(P<DevView>(c->views), c->nv, c->n, t, v, c->K, P<uint32_t>(c->depth),
+        launch_make_keys64(P<DevView>(c->views), c->nv, c->n, t, v, Kc, P<uint32_t>(c->depth),
                            reinterpret_cast<uint64_t *>(dst), c->stream);
         return check_launch(c, "inspect");
     }

@@ -471,11 +471,11 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 }
 
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
-                                                      uint32_t *__restrict__ chunk_start) {
+                                                      uint32_t *__restrict__ chunk_start, int64_t nchunks) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent) return;
     const uint32_t lo = offsets[j], hi = offsets[j + 1];
-    for (uint32_t c = (lo + 63) >> 6; ((uint64_t)c << 6) < hi; ++c) chunk_start[c] = (uint32_t)j;
+    for (uint32_t c = (lo + 63) >> 6; ((uint64_t)c << 6) < hi && (int64_t)c < nchunks; ++c) chunk_start[c] = (uint32_t)j;
 }
 
 __global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, int64_t n,
@@ -485,10 +485,13 @@ __global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, 
                                              const uint64_t *__restrict__ rect,
                                              const uint16_t *__restrict__ row_prefix,
                                              const uint16_t *__restrict__ row_list, const uint32_t *__restrict__ cum,
-                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t K) {
+                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t K,
+                                             const uint32_t *K_dev) {
     __shared__ uint32_t s_off[65];
     const int lane = threadIdx.x;
     const int64_t q0 = (int64_t)blockIdx.x * 64;
+    if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode: the device count, clamped
+    if (q0 >= K) return;
     const int64_t E = *n_ent;
     const uint32_t j0 = chunk_start[blockIdx.x];
     {
@@ -588,11 +591,24 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
-                 hipStream_t s) {
+                 const uint32_t *K_dev, hipStream_t s) {
     if (m == 0 || K == 0) return;
-    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((K + 63) / 64)), dim3(64), 0, s, views, n, ent, n_ent, offsets,
-                       chunk_start, rect, row_prefix, row_list, cum, keys, vals, K);
+    const int64_t nchunks = (K + 63) / 64;
+    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start,
+                       nchunks);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(64), 0, s, views, n, ent, n_ent, offsets,
+                       chunk_start, rect, row_prefix, row_list, cum, keys, vals, K, K_dev);
+}
+
+// capacity mode: the sort count is min(key total, capacity); overflow raises bit 1 of the error word
+__global__ void k_clamp_keys(const uint64_t *total, uint64_t cap, uint32_t *n32, uint32_t *err) {
+    const uint64_t t = *total;
+    *n32 = (uint32_t)(t < cap ? t : cap);
+    if (t > cap) atomicOr(err, 2u);
+}
+
+void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_clamp_keys, dim3(1), dim3(1), 0, s, total, (uint64_t)cap, n32, err);
 }
 
 // ------------------------------------------------------------------------

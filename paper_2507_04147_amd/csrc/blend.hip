@@ -15,18 +15,23 @@
 
 namespace a3fr {
 
-constexpr int kBatch = 64;
+constexpr int kBatch = 64;   // LDS batch of the reverse blend
 
+// Blend one tile.  BATCH: records staged in LDS per step; ROWS: pixel rows per
+// lane (1: four horizontally adjacent pixels, 2: a 2 x 2 block).  Every
+// pixel evaluates exactly the same float32 expressions over the same list in
+// the same order whatever BATCH, ROWS and the schedule, so all variants give
+// bit-identical images.
 // COUNT: also count evaluated (pixel, Gaussian) pairs -- every list entry a
 // pixel evaluates while it is live, the one that stops it included.
-template <bool COUNT>
-__global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,
-                                              const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges,
-                                              const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
-                                              int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
-                                              uint32_t *__restrict__ lastout, unsigned long long *__restrict__ pairs) {
-    const int64_t gt = blockIdx.x;
-    if (!active[gt]) return;
+template <bool COUNT, int BATCH, int ROWS>
+__device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict__ views, int nv,
+                                           const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ vals,
+                                           const Record *__restrict__ rec, int64_t n, float *__restrict__ rgb,
+                                           float *__restrict__ Tout, uint32_t *__restrict__ lastout, uint32_t &npairs) {
+    constexpr int COLS = 4 / ROWS;
+    __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
     // view of this tile: views are ordered by tile offset
     int lo = 0, hi = nv - 1;
     while (lo < hi) {
@@ -39,75 +44,82 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
     const int W = dv.v.width, H = dv.v.height;
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int lane = threadIdx.x;
-    const int py = lane >> 2, px0 = (lane & 3) * 4;
-    const float fy = (float)py + 0.5f;
+    // lane's pixel block: COLS columns x ROWS rows
+    const int py0 = ROWS == 1 ? (lane >> 2) : (lane >> 3) * 2;
+    const int px0 = ROWS == 1 ? (lane & 3) * 4 : (lane & 7) * 2;
+    float fyr[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) fyr[r] = (float)(py0 + r) + 0.5f;
     float fxq[4];
     bool alive[4];
     float T[4], Cr[4], Cg[4], Cb[4];
     uint32_t last[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        fxq[q] = (float)(px0 + q) + 0.5f;
-        alive[q] = (x0 + px0 + q < W) && (y0 + py < H);
+        const int cx = px0 + q % COLS, cy = py0 + q / COLS;
+        fxq[q] = (float)cx + 0.5f;
+        alive[q] = (x0 + cx < W) && (y0 + cy < H);
         T[q] = 1.0f; Cr[q] = Cg[q] = Cb[q] = 0.0f; last[q] = 0;
     }
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
     const Record *R = rec + (int64_t)lo * n;
-    __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
-    __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
     const double dx0 = (double)x0, dy0 = (double)y0;
-    uint32_t npairs = 0;
 
-    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
-        const uint32_t j = b0 + lane;
-        if (j < end) {
-            const Record r = R[vals[j]];
-            s_u[lane] = (float)(r.u - dx0);
-            s_v[lane] = (float)(r.v - dy0);
-            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
-            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
-        }
-        __syncthreads();
-        const uint32_t cnt = (end - b0) < (uint32_t)kBatch ? (end - b0) : (uint32_t)kBatch;
-        for (uint32_t jj = 0; jj < cnt; ++jj) {
-            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
-            const float dy = fy - mv;
-            const float kdy = kk * dy;
-            const float cdy = c2 * dy * dy;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (COUNT) npairs += alive[q] ? 1u : 0u;
-                const float t = (fxq[q] - mu) + kdy;
-                const float e = fmaf(a2, t * t, cdy);
-                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                if (alive[q] && al >= kAlphaMin) {
-                    const float Tn = T[q] * (1.0f - al);
-                    if (Tn < kTMin) {
-                        alive[q] = false;
-                    } else {
-                        const float wgt = al * T[q];
-                        Cr[q] = fmaf(wgt, s_r[jj], Cr[q]);
-                        Cg[q] = fmaf(wgt, s_g[jj], Cg[q]);
-                        Cb[q] = fmaf(wgt, s_b[jj], Cb[q]);
-                        T[q] = Tn;
-                        last[q] = b0 - start + jj + 1;
-                    }
-                }
+        for (int part = 0; part < (BATCH + 63) / 64; ++part) {
+            const int slot = part * 64 + lane;
+            const uint32_t j = b0 + slot;
+            if (slot < BATCH && j < end) {
+                const Record r = R[vals[j]];
+                s_u[slot] = (float)(r.u - dx0);
+                s_v[slot] = (float)(r.v - dy0);
+                s_a[slot] = r.a2; s_k[slot] = r.k; s_c[slot] = r.c2; s_o[slot] = r.o;
+                s_r[slot] = r.r; s_g[slot] = r.g; s_b[slot] = r.b;
             }
         }
         __syncthreads();
-    }
-    if (COUNT) {
-        unsigned long long tot = npairs;
-        for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
-        if (lane == 0) atomicAdd(pairs, tot);
+        const uint32_t cnt = (end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH;
+        for (uint32_t jj = 0; jj < cnt; ++jj) {
+            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
+            const uint32_t idx = b0 - start + jj + 1;
+            float kdy[ROWS], cdy[ROWS];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const float dy = fyr[r] - mv;
+                kdy[r] = kk * dy;
+                cdy[r] = c2 * dy * dy;
+            }
+            // branch-free: a pixel that does not blend adds fma(0, c, C) = C (colours >= 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rr = q / COLS;
+                if (COUNT) npairs += alive[q] ? 1u : 0u;
+                const float t = (fxq[q] - mu) + kdy[rr];
+                const float e = fmaf(a2, t * t, cdy[rr]);
+                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
+                const float Tn = T[q] * (1.0f - al);
+                const bool take = alive[q] && al >= kAlphaMin;
+                const bool stop = take && Tn < kTMin;
+                const bool blend = take && !stop;
+                const float wgt = blend ? al * T[q] : 0.0f;
+                Cr[q] = fmaf(wgt, cr, Cr[q]);
+                Cg[q] = fmaf(wgt, cg, Cg[q]);
+                Cb[q] = fmaf(wgt, cb, Cb[q]);
+                T[q] = blend ? Tn : T[q];
+                last[q] = blend ? idx : last[q];
+                alive[q] = alive[q] && !stop;
+            }
+        }
+        __syncthreads();
     }
     const int64_t HW = (int64_t)W * H;
     float *img = rgb + 3 * dv.img_off;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int x = x0 + px0 + q, y = y0 + py;
+        const int x = x0 + px0 + q % COLS, y = y0 + py0 + q / COLS;
         if (x < W && y < H) {
             const int64_t pix = (int64_t)y * W + x;
             img[pix] = Cr[q] + T[q] * dv.v.bg[0];
@@ -119,16 +131,138 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
     }
 }
 
-void launch_blend(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
-                  const uint32_t *vals, const Record *rec, int64_t n, float *rgb, float *T, uint32_t *last,
-                  unsigned long long *pairs, hipStream_t s) {
-    if (ntiles == 0) return;
-    if (pairs)
-        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals, rec,
-                           n, rgb, T, last, pairs);
+template <bool COUNT>
+__device__ __forceinline__ void add_pairs(uint32_t npairs, unsigned long long *pairs) {
+    if (COUNT) {
+        unsigned long long tot = npairs;
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
+        if (threadIdx.x == 0) atomicAdd(pairs, tot);
+    }
+}
+
+// grid schedule: one wave per tile, in tile order
+template <bool COUNT, int BATCH, int ROWS>
+__global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,
+                                              const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges,
+                                              const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                              int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
+                                              uint32_t *__restrict__ lastout, unsigned long long *__restrict__ pairs) {
+    const int64_t gt = blockIdx.x;
+    if (!active[gt]) return;
+    uint32_t npairs = 0;
+    blend_tile<COUNT, BATCH, ROWS>(gt, views, nv, ranges, vals, rec, n, rgb, Tout, lastout, npairs);
+    add_pairs<COUNT>(npairs, pairs);
+}
+
+// queue schedule: persistent waves pull active tiles, longest lists first
+template <bool COUNT, int BATCH, int ROWS>
+__global__ void __launch_bounds__(64) k_blend_queue(const DevView *__restrict__ views, int nv,
+                                                    const uint32_t *__restrict__ order, const uint32_t *n_order,
+                                                    uint32_t *counter, const uint32_t *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                                    int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
+                                                    uint32_t *__restrict__ lastout,
+                                                    unsigned long long *__restrict__ pairs) {
+    const uint32_t total = *n_order;
+    uint32_t npairs = 0;
+    for (;;) {
+        uint32_t t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1u);
+        t = __shfl(t, 0, 64);
+        if (t >= total) break;
+        blend_tile<COUNT, BATCH, ROWS>((int64_t)order[t], views, nv, ranges, vals, rec, n, rgb, Tout, lastout, npairs);
+    }
+    add_pairs<COUNT>(npairs, pairs);
+}
+
+// Longest-first order of the active tiles: bucket b = bit length of the list
+// length (0 for an empty list), buckets in descending order (an O(n) counting
+// sort; within a bucket the order is arbitrary, which changes no pixel).
+// ws: [0..33) histogram, [33..66) running offsets, [66] active count, [67] queue counter.
+__global__ void k_len_hist(const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges, int64_t ntiles,
+                           uint32_t *__restrict__ ws) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles || !active[t]) return;
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const int b = len ? 32 - __clz(len) : 0;
+    atomicAdd(&ws[b], 1u);
+}
+
+__global__ void k_len_scan(uint32_t *ws) {
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int b = 32; b >= 0; --b) {
+        ws[33 + b] = acc;
+        acc += ws[b];
+    }
+    ws[66] = acc;
+    ws[67] = 0;
+}
+
+__global__ void k_len_scatter(const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges, int64_t ntiles,
+                              uint32_t *__restrict__ ws, uint32_t *__restrict__ order) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles || !active[t]) return;
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const int b = len ? 32 - __clz(len) : 0;
+    order[atomicAdd(&ws[33 + b], 1u)] = (uint32_t)t;
+}
+
+template <int BATCH, int ROWS>
+static void launch_variant(const BlendArgs &a, bool queue, hipStream_t s) {
+    if (!queue) {
+        if (a.pairs)
+            hipLaunchKernelGGL((k_blend<true, BATCH, ROWS>), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.views, a.nv,
+                               a.active, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+        else
+            hipLaunchKernelGGL((k_blend<false, BATCH, ROWS>), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.views, a.nv,
+                               a.active, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+        return;
+    }
+    const unsigned grid = (unsigned)(a.ntiles < a.queue_waves ? a.ntiles : a.queue_waves);
+    if (a.pairs)
+        hipLaunchKernelGGL((k_blend_queue<true, BATCH, ROWS>), dim3(grid), dim3(64), 0, s, a.views, a.nv, a.order,
+                           a.ws + 66, a.ws + 67, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
     else
-        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, active, ranges, vals,
-                           rec, n, rgb, T, last, pairs);
+        hipLaunchKernelGGL((k_blend_queue<false, BATCH, ROWS>), dim3(grid), dim3(64), 0, s, a.views, a.nv, a.order,
+                           a.ws + 66, a.ws + 67, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+}
+
+void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t ntiles, uint32_t *ws, uint32_t *order,
+                        hipStream_t s) {
+    launch_fill_u32(ws, 0u, kBlendWsWords, s);
+    if (ntiles == 0) return;
+    const unsigned g = (unsigned)((ntiles + 255) / 256);
+    hipLaunchKernelGGL(k_len_hist, dim3(g), dim3(256), 0, s, active, ranges, ntiles, ws);
+    hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(64), 0, s, ws);
+    hipLaunchKernelGGL(k_len_scatter, dim3(g), dim3(256), 0, s, active, ranges, ntiles, ws, order);
+}
+
+void launch_blend(const BlendArgs &a, int variant, hipStream_t s) {
+    if (a.ntiles == 0) return;
+    const BlendVariant v = blend_variant(variant);
+    if (v.queue) {
+        launch_blend_order(a.active, a.ranges, a.ntiles, a.ws, a.order, s);
+        launch_fill_u32(a.ws + 67, 0u, 1, s);
+    }
+    switch (v.batch * 10 + v.rows) {
+        case 321: launch_variant<32, 1>(a, v.queue, s); break;
+        case 322: launch_variant<32, 2>(a, v.queue, s); break;
+        case 641: launch_variant<64, 1>(a, v.queue, s); break;
+        case 642: launch_variant<64, 2>(a, v.queue, s); break;
+        case 1281: launch_variant<128, 1>(a, v.queue, s); break;
+        default: launch_variant<128, 2>(a, v.queue, s); break;
+    }
+}
+
+BlendVariant blend_variant(int k) {
+    static const int batches[3] = {32, 64, 128};
+    BlendVariant v;
+    k = k < 0 ? 0 : (k >= kBlendVariants ? kBlendVariants - 1 : k);
+    v.batch = batches[k % 3];
+    v.rows = 1 + (k / 3) % 2;
+    v.queue = k / 6 != 0;
+    return v;
 }
 
 // ------------------------------------------------------------------------
@@ -309,13 +443,24 @@ __device__ __forceinline__ void bilinear_setup(int x, int s, int Wl, int &i0, in
 __global__ void k_composite(int W, int H, double gx, double gy, double rf, double rm,
                             const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
                             const float *__restrict__ periph, int sp, const float *__restrict__ periph_full,
+                            const uint8_t *__restrict__ fb_flags, int fb_tiles_x, const DevView *gaze_view,
                             float *__restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gaze_view) {  // the gaze of this frame, from the device view table
+        gx = gaze_view->v.gx;
+        gy = gaze_view->v.gy;
+    }
     const int y = blockIdx.y;
     if (x >= W) return;
     const int64_t HW = (int64_t)W * H, pix = (int64_t)y * W + x;
     const int reg = region_of(x, y, gx, gy, rf, rm);
     if (reg == 0) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = fovea[ch * HW + pix];
+        return;
+    }
+    // periphery tiles flagged for the full-resolution fallback come from the full-resolution layer
+    if (reg == 2 && fb_flags && fb_flags[(int64_t)(y / (kTile * sp)) * fb_tiles_x + x / (kTile * sp)]) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = fovea[ch * HW + pix];
         return;
@@ -344,10 +489,10 @@ __global__ void k_composite(int W, int H, double gx, double gy, double rf, doubl
 
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
-                      float *out, hipStream_t s) {
+                      const uint8_t *fb_flags, int fb_tiles_x, const DevView *gaze_view, float *out, hipStream_t s) {
     if (W <= 0 || H <= 0) return;
     hipLaunchKernelGGL(k_composite, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, W, H, gx, gy,
-                       rf, rm, fovea, mid, sm, periph, sp, periph_full, out);
+                       rf, rm, fovea, mid, sm, periph, sp, periph_full, fb_flags, fb_tiles_x, gaze_view, out);
 }
 
 // ------------------------------------------------------------------------

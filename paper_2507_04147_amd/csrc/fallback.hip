@@ -1,0 +1,158 @@
+// Per-tile error estimate of the periphery and full-resolution fallback.
+//
+// The periphery layer draws only the Gaussians of largest opacity x
+// projected area (the coarse, cheaper rendering of the regions away from the
+// gaze, Sec. 2.2).  Dropping Gaussians changes a tile most where the tile is
+// not saturated (background or far content shows through): with D_t and K_t
+// the opacity mass per pixel of the dropped and of the kept visible Gaussians
+// over periphery tile t (each Gaussian's 2 pi o sqrt(det Sigma2D), the
+// integral of o exp(-q/2), spread evenly over the tiles of its rectangle),
+// the transmittance model T ~ exp(-mass) gives the rise of the tile's
+// transmittance dT = exp(-K) - exp(-(K + D)) caused by the subset, and the
+// squared-error estimate coef x (dT^2)^power (calibrated on rendered frames).
+// Tiles whose estimate reaches the threshold and that reach outside the
+// mid-layer radius are added to the eye's full-resolution layer (same
+// projection, all Gaussians): its tile mask grows, its rows and per-Gaussian
+// tile counts are rebuilt, and the composite takes those pixels from it.
+#include "a3fr_internal.h"
+
+namespace a3fr {
+
+__global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__ views, int pv, int64_t n,
+                                                     const uint32_t *__restrict__ counts,
+                                                     const uint8_t *__restrict__ keep,
+                                                     const uint64_t *__restrict__ rect,
+                                                     const double *__restrict__ score,
+                                                     const float *__restrict__ opacity, int64_t ntiles,
+                                                     float *__restrict__ energy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t slot = (int64_t)pv * n + i;
+    if (counts[slot] == 0) return;
+    const DevView &dv = views[pv];
+    const uint64_t r = rect[slot];
+    const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
+              y1 = (int)(r >> 48);
+    const int nt = (x1 - x0 + 1) * (y1 - y0 + 1);
+    const float share = (float)(2.0 * score[slot] / ((double)nt * (double)(kTile * kTile)));
+    // dropped mass in the first plane, kept mass in the second
+    float *E = energy + (keep[slot] ? ntiles : 0) + dv.tile_off;
+    for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx) atomicAdd(&E[(int64_t)ty * dv.tiles_x + tx], share);
+}
+
+void launch_drop_energy(const DevView *views, int pv, int64_t n, const uint32_t *counts, const uint8_t *keep,
+                        const uint64_t *rect, const double *score, const float *opacity, int64_t ntiles,
+                        float *energy, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, pv, n, counts, keep,
+                       rect, score, opacity, ntiles, energy);
+}
+
+// One thread per periphery tile: flag, and activate the covered tiles of the
+// full-resolution layer fv (s = full-resolution pixels per periphery pixel).
+// A tile can only matter if one of the full-resolution pixel centres it
+// covers lies outside r_mid (the composite's periphery region).
+__global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int fv, const float *__restrict__ energy,
+                                 int64_t ntiles, double r_mid, double threshold, double coef, double power,
+                                 uint8_t *__restrict__ flags, uint8_t *__restrict__ active) {
+    const DevView &dp = views[pv], &df = views[fv];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)dp.tiles_x * dp.tiles_y) return;
+    const int tx = (int)(t % dp.tiles_x), ty = (int)(t / dp.tiles_x);
+    const int s = (int)llround(df.v.fx / dp.v.fx);
+    const int span = kTile * s;  // full-resolution pixels per periphery tile, per axis
+    const double x0 = (double)tx * span + 0.5, x1 = fmin((double)(tx + 1) * span, (double)df.v.width) - 0.5;
+    const double y0 = (double)ty * span + 0.5, y1 = fmin((double)(ty + 1) * span, (double)df.v.height) - 0.5;
+    const double gx = df.v.gx, gy = df.v.gy;
+    const double fx = fmax(fabs(x0 - gx), fabs(x1 - gx)), fy = fmax(fabs(y0 - gy), fabs(y1 - gy));
+    const bool outer = x0 <= x1 && y0 <= y1 && fx * fx + fy * fy > r_mid * r_mid;
+    // Beer-Lambert: transmittance ~ exp(-mass per pixel); dropping raises it by dT
+    const double D = energy[dp.tile_off + t], K = energy[ntiles + dp.tile_off + t];
+    const double dT = exp(-K) - exp(-(K + D));
+    const double est = dT > 0.0 ? coef * pow(dT * dT, power) : 0.0;
+    const bool flag = outer && est >= threshold;
+    flags[dp.tile_off + t] = flag ? 1 : 0;
+    if (!flag) return;
+    for (int yy = ty * s; yy < (ty + 1) * s && yy < df.tiles_y; ++yy)
+        for (int xx = tx * s; xx < (tx + 1) * s && xx < df.tiles_x; ++xx)
+            active[df.tile_off + (int64_t)yy * df.tiles_x + xx] = 1;
+}
+
+void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
+                           int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
+                           uint8_t *active, hipStream_t s) {
+    if (periph_tiles == 0) return;
+    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)((periph_tiles + 255) / 256)), dim3(256), 0, s, views, pv, fv,
+                       energy, ntiles, r_mid, threshold, coef, power, flags, active);
+}
+
+// Row prefix and active-column list of the remasked views' rows from their
+// active flags (wave per row, ballot prefix).
+__global__ void __launch_bounds__(256) k_rows_from_active(const DevView *views, int64_t rows_total,
+                                                          const int32_t *row_view, const int32_t *row_y,
+                                                          const uint8_t *active, uint16_t *row_prefix,
+                                                          uint16_t *row_list) {
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows_total) return;
+    const DevView &dv = views[row_view[r]];
+    if (!dv.remask || dv.v.mask == A3FR_MASK_ALL) return;
+    const int ty = row_y[r];
+    const int TX = dv.tiles_x;
+    const uint8_t *act = active + dv.tile_off + (int64_t)ty * TX;
+    uint16_t *pre = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
+    uint16_t *lst = row_list + dv.mask_off + (int64_t)ty * (TX + 1);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t c = 0;
+    for (int tx0 = 0; tx0 < TX; tx0 += 64) {
+        const int tx = tx0 + lane;
+        const bool a = tx < TX && act[tx] != 0;
+        const uint64_t m = __ballot(a);
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        if (tx < TX) {
+            pre[tx] = (uint16_t)(c + below);
+            if (a) lst[c + below] = (uint16_t)tx;
+        }
+        c += (uint32_t)__popcll(m);
+    }
+    if (lane == 0) pre[TX] = (uint16_t)c;
+}
+
+void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
+                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list, hipStream_t s) {
+    if (rows_total == 0) return;
+    hipLaunchKernelGGL(k_rows_from_active, dim3((unsigned)((rows_total + 3) / 4)), dim3(256), 0, s, views, rows_total,
+                       row_view, row_y, active, row_prefix, row_list);
+}
+
+// Active tiles covered by each visible Gaussian's rectangle in view fv, from
+// the rebuilt row prefixes.
+__global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ views, int fv, int64_t n,
+                                                 const uint64_t *__restrict__ rect,
+                                                 const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevView &dv = views[fv];
+    const int64_t slot = (int64_t)fv * n + i;
+    const uint64_t r = rect[slot];
+    const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
+              y1 = (int)(r >> 48);
+    if (x0 > x1 || y0 > y1) return;  // not visible: count stays 0
+    const uint16_t *pre = row_prefix + dv.mask_off;
+    uint32_t cnt = 0;
+    for (int ty = y0; ty <= y1; ++ty) {
+        const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+        cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
+    }
+    counts[slot] = cnt;
+}
+
+void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
+                    uint32_t *counts, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_recount, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, fv, n, rect, row_prefix,
+                       counts);
+}
+
+}  // namespace a3fr

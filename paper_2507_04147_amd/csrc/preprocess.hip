@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
         const a3fr_view &v = dv.v;
         const int64_t slot = (int64_t)vi * n + i;
         uint32_t cnt = 0;
+        bool visible = false;
         if (front) {
             const double limx = dv.limx, limy = dv.limy;  // (1.3 (W/2)) / fx, computed on the host
             const double txc = fmin(fmax(xz, -limx), limx);
@@ -209,6 +210,7 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                     fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
                     if (fx0 <= fx1 && fy0 <= fy1) {
                         const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+                        visible = true;
                         if (v.mask == A3FR_MASK_ALL) {
                             cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
                         } else {
@@ -240,6 +242,7 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
             }
         }
         counts[slot] = cnt;
+        if (dv.remask && !visible) rect[slot] = kEmptyRect;
     }
 }
 

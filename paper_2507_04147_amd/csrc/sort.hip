@@ -280,8 +280,10 @@ void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint
 // ------------------------------------------------------------------------
 // tile ranges from the sorted tile ids
 // ------------------------------------------------------------------------
-__global__ void k_ranges(const uint32_t *__restrict__ tiles, int64_t K, int64_t ntiles, uint32_t *__restrict__ ranges) {
+__global__ void k_ranges(const uint32_t *__restrict__ tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles,
+                         uint32_t *__restrict__ ranges) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode
     if (j >= K) return;
     const uint32_t t = tiles[j];
     if ((int64_t)t >= ntiles) return;
@@ -289,10 +291,11 @@ __global__ void k_ranges(const uint32_t *__restrict__ tiles, int64_t K, int64_t 
     if (j == K - 1 || tiles[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
 }
 
-void launch_ranges(const uint32_t *tiles, int64_t K, int64_t ntiles, uint32_t *ranges, hipStream_t s) {
+void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
+                   hipStream_t s) {
     launch_fill_u32(ranges, 0u, 2 * ntiles, s);
     if (K == 0) return;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, tiles, K, ntiles, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, tiles, K, K_dev, ntiles, ranges);
 }
 
 }  // namespace a3fr

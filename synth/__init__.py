@@ -225,3 +225,30 @@ def crop_poses(seed=41, n=10_000, width=1832, height=1920, crop=256, fov_x_deg=6
         y0 = scale * int(rng.integers(0, (height - crop) // scale + 1))
         out.append((make_camera(width, height, fov_x_deg, pos, rot_yaw_pitch(yaw, pitch)), x0, y0))
     return out
+
+
+def gaze_trace(seed=31, n_frames=64, width=1832, height=1920, fov_x_deg=60.0, hz=90.0, head=(0.0, 0.0, -3.0),
+               drift_deg=1.0, saccade_deg=(5.0, 20.0), interval_s=(0.2, 0.4), jitter_deg=0.3, max_ecc_deg=25.0):
+    """Frames of a seeded gaze walk: fixations with Gaussian jitter (jitter_deg
+    per axis), saccades of saccade_deg amplitude in a uniform direction every
+    interval_s seconds (frames at hz), the gaze kept within max_ecc_deg of the
+    optical axis; the head turns by drift_deg of yaw and of pitch per frame.
+    Returns [(stereo cameras, [gaze left, gaze right] in pixels)] per frame."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gx = gy = 0.0
+    t_next = rng.uniform(*interval_s)
+    frames = []
+    for k in range(n_frames):
+        t = k / hz
+        if t >= t_next:
+            amp, ang = rng.uniform(*saccade_deg), rng.uniform(0.0, 2.0 * math.pi)
+            gx = float(np.clip(gx + amp * math.cos(ang), -max_ecc_deg, max_ecc_deg))
+            gy = float(np.clip(gy + amp * math.sin(ang), -max_ecc_deg, max_ecc_deg))
+            t_next += rng.uniform(*interval_s)
+        jx, jy = rng.normal(0.0, jitter_deg, 2)
+        cams = stereo_cameras(head, width, height, fov_x_deg, c2w=rot_yaw_pitch(drift_deg * k, drift_deg * k))
+        c = cams[0]
+        px = c.cx + c.fx * math.tan(math.radians(gx + jx))
+        py = c.cy + c.fy * math.tan(math.radians(gy + jy))
+        frames.append((cams, [(px, py), (px, py)]))
+    return frames

@@ -1,0 +1,192 @@
+"""GPU parity of the periphery error estimate, the full-resolution fallback and
+the upsampler in the foveated frame (MI355X only).
+
+Bars: dropped-opacity map within float32 summation error of the oracle's;
+fallback flags equal (the threshold is chosen away from every estimate);
+sorted keys of the frame with the grown full-resolution mask bit-exact;
+composite within 1e-4 (ambiguous layer pixels at 2e-2); threshold 0 equals the
+plain full-resolution render outside r_mid exactly; threshold +inf and a
+zero network leave the frame unchanged bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_parity import AMB_TOL, COLOUR_TOL, composite_ambiguity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2507_04147_amd as p
+    p.lib()
+    assert torch.cuda.is_available()
+    return p
+
+
+def _frame(n, W, H, seed=5, gz=None):
+    scene, cams = synth.foveated_stereo(n=n, width=W, height=H, seed=seed)
+    gz = gz or [(c.cx, c.cy) for c in cams]
+    return scene, cams, gz, (0.15 * W, 0.35 * W)
+
+
+def _gap_threshold(values):
+    """A threshold halfway (geometrically) across the widest relative gap
+    between consecutive sorted estimates near their median."""
+    v = np.unique(values[values > 0])
+    mid = len(v) // 2
+    lo, hi = max(1, mid - len(v) // 4), min(len(v) - 1, mid + len(v) // 4)
+    k = lo + int(np.argmax(v[lo:hi + 1] / v[lo - 1:hi]))
+    return float(np.sqrt(v[k - 1] * v[k])), float(v[k] / v[k - 1])
+
+
+def test_fallback_parity(pkg):
+    W, H = 232, 240
+    scene, cams, _, rad = _frame(50_000, W, H)
+    gz = [(100.5, 130.25), (110.0, 128.0)]
+    views = oracle.foveated_views(cams, gz, rad)
+    ref0 = oracle.render(scene, views, blend=False)
+    DK = [oracle.tile_mass(ref0, views, 3 * e + 2) for e in range(2)]
+    est = np.concatenate([oracle.fallback_estimate(D, K, 1.0, 1.0).ravel() for D, K in DK])
+    thr, gap = _gap_threshold(est)
+    assert gap > 1.001
+    flags, extra = [], {}
+    for e in range(2):
+        f, x = oracle.fallback_flags(*DK[e], views[3 * e + 2], views[3 * e], rad[1], thr, 1.0, 1.0)
+        flags.append(f)
+        extra[3 * e] = x
+    assert any(f.any() for f in flags)
+    ref = oracle.render(scene, views, extra_active=extra)
+
+    ctx = pkg.Context()
+    ds = pkg.DeviceScene.from_host(scene)
+    ctx.set_fallback(thr, 1.0, 1.0)
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_foveated(ds, cams, gz, pkg.fovea_struct(*rad), out)
+    ctx.sync()
+    ge = ctx.inspect("fb_energy", torch.float32).cpu().numpy().astype(np.float64)
+    nt = ge.size // 2
+    gf = ctx.inspect("fb_flags", torch.uint8).cpu().numpy()
+    toff = ref["tile_off"]
+    for e in range(2):
+        pv = 3 * e + 2
+        a, b = int(toff[pv]), int(toff[pv + 1])
+        np.testing.assert_allclose(ge[a:b], DK[e][0].ravel(), rtol=1e-5, atol=1e-12)
+        np.testing.assert_allclose(ge[nt + a:nt + b], DK[e][1].ravel(), rtol=1e-5, atol=1e-12)
+        np.testing.assert_array_equal(gf[a:b].astype(bool), flags[e].ravel())
+    c = ctx.get_counts()
+    assert c["n_fallback_tiles"] == sum(int(f.sum()) for f in flags)
+    assert c["n_keys"] == ref["keys"].size
+    sk = ctx.inspect("sorted_keys", torch.int64).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(sk, ref["sorted_keys"])
+    sv = ctx.inspect("sorted_vals", torch.int32).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(sv, ref["sorted_vals"])
+    for e in range(2):
+        L = ref["images"][3 * e: 3 * e + 3]
+        o = oracle.composite(W, H, gz[e], rad, L[0]["rgb"], L[1]["rgb"], L[2]["rgb"])
+        o = oracle.composite_fallback(o, L[0]["rgb"], flags[e], W, H, gz[e], rad[1], 64)
+        amb = composite_ambiguity(W, H, gz[e], rad, L)
+        err = np.abs(out[e].cpu().numpy() - o)
+        assert err[:, ~amb].max() <= COLOUR_TOL
+        assert err[:, amb].max(initial=0.0) <= AMB_TOL
+    ctx.close()
+
+
+def test_fallback_threshold_zero_equals_frr_outside_mid(pkg):
+    W, H = 464, 480
+    scene, cams, gz, rad = _frame(100_000, W, H, seed=6)
+    ds = pkg.DeviceScene.from_host(scene)
+    ctx = pkg.Context()
+    frr = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_full(ds, cams, frr)
+    ctx.set_fallback(0.0, 1.0, 1.0)
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_foveated(ds, cams, gz, pkg.fovea_struct(*rad), out)
+    ctx.sync()
+    ys, xs = np.mgrid[0:H, 0:W]
+    for e in range(2):
+        outer = (xs + 0.5 - gz[e][0]) ** 2 + (ys + 0.5 - gz[e][1]) ** 2 > rad[1] ** 2
+        a, b = out[e].cpu().numpy(), frr[e].cpu().numpy()
+        np.testing.assert_array_equal(a[:, outer], b[:, outer])
+    assert ctx.get_counts()["n_fallback_tiles"] > 0
+    ctx.close()
+
+
+def test_fallback_off_and_zero_network_leave_frame_unchanged(pkg):
+    W, H = 464, 480
+    scene, cams, gz, rad = _frame(100_000, W, H, seed=7)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    ctx = pkg.Context()
+    base = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_foveated(ds, cams, gz, fov, base)
+    ctx.set_fallback(float("inf"), 1.0, 1.0)
+    o1 = torch.zeros_like(base)
+    ctx.render_foveated(ds, cams, gz, fov, o1)
+    ctx.set_upsampler(torch.zeros(pkg.NET_PARAMS, device="cuda"))
+    o2 = torch.zeros_like(base)
+    ctx.render_foveated(ds, cams, gz, fov, o2)
+    ctx.sync()
+    assert torch.equal(base, o1)
+    assert torch.equal(base, o2)
+    ctx.close()
+
+
+def test_upsampler_in_frame_matches_stage_calls(pkg):
+    """render_foveated with the network equals: the layers through the stage
+    calls, the periphery layer through a3fr_net_forward, a3fr_composite."""
+    W, H = 464, 480
+    scene, cams, gz, rad = _frame(100_000, W, H, seed=8)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    theta = torch.from_numpy(synth.net_init(46, last_scale=1.0)).cuda()
+    ctx = pkg.Context()
+    ctx.set_upsampler(theta)
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_foveated(ds, cams, gz, fov, out)
+    views = pkg.make_foveated_views(cams, gz, fov)
+    ctx.preprocess(ds, views, (3, 10))
+    ctx.bin_sort()
+    sizes = [v.width * v.height for v in views]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    L = torch.zeros(3 * int(offs[-1]), device="cuda")
+    ctx.blend(L)
+    ref = torch.zeros_like(out)
+    for e in range(2):
+        img = [L[3 * offs[3 * e + k]: 3 * offs[3 * e + k + 1]] for k in range(3)]
+        per = img[2].view(1, 3, H // 4, W // 4)
+        pf = torch.empty((1, 3, H, W), device="cuda")
+        ctx.net_forward(theta, per, pf, False)
+        ctx.composite(W, H, gz[e], fov, img[0], img[1], img[2], pf[0], ref[e])
+    ctx.sync()
+    assert torch.equal(out, ref)
+    ctx.close()
+
+
+def test_fallback_full_size_frame(pkg):
+    """The 1M-Gaussian stereo frame with the calibrated estimator (threshold
+    1e-3, the 30 dB level): periphery PSNR against the full-resolution render
+    stays at or above 30 dB; the number of fallback tiles is reported."""
+    from paper_2507_04147_amd import FALLBACK_DEFAULT
+    scene, cams = synth.foveated_stereo()
+    W, H = cams[0].width, cams[0].height
+    gz = [(c.cx, c.cy) for c in cams]
+    rad = (0.15 * W, 0.35 * W)
+    ds = pkg.DeviceScene.from_host(scene)
+    ctx = pkg.Context()
+    frr = torch.zeros((2, 3, H, W), device="cuda")
+    ctx.render_full(ds, cams, frr)
+    ctx.set_fallback(*FALLBACK_DEFAULT)
+    out = torch.zeros_like(frr)
+    ctx.render_foveated(ds, cams, gz, pkg.fovea_struct(*rad), out)
+    nfb = ctx.get_counts()["n_fallback_tiles"]
+    for e in range(2):
+        sse, cnt = ctx.region_sse(W, H, gz[e], rad[0], rad[1], out[e], frr[e])
+        mse = (sse[1] + sse[2]) / (3.0 * (cnt[1] + cnt[2]))
+        psnr = float("inf") if mse == 0 else 10 * np.log10(1 / mse)
+        print(f"eye {e}: periphery PSNR {psnr:.2f} dB, fallback tiles {nfb}", flush=True)
+        assert psnr >= 30.0
+    ctx.close()
