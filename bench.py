@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2, help="oracle frames timed for the CPU baseline")
     ap.add_argument("--only", choices=["both", "foveated", "full"], default="both",
                     help="restrict the timed loops (for profiling runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the graph, upsampler, fallback and gaze-trace legs")
+    ap.add_argument("--trace-window", type=int, default=16, help="frames per graph launch in the gaze-trace leg")
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed steps of the differentiable-render training loop (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -122,10 +125,36 @@ def main():
         if do_frr:
             step_frr()
     torch.cuda.synchronize()
+    tuned = None
+    if do_fov:
+        # the blend autotuner (all variants give identical images) on this frame
+        step_fov()
+        ms_var, best = ctx.autotune_blend(reps=3)
+        tuned = dict(variant=best, desc=list(pkg.blend_variant_desc(best)),
+                     ms=[round(m, 4) for m in ms_var])
+        log(f"blend autotuner: variant {best} {pkg.blend_variant_desc(best)}")
     log("warmup done")
     ms_f = timed(step_fov, args.steps) if do_fov else float("nan")
     ms_r = timed(step_frr, args.steps) if do_frr else float("nan")
     log(f"foveated {ms_f:.3f} ms/frame, full-res {ms_r:.3f} ms/frame")
+
+    # the same frame replayed from a HIP graph (no host read-back inside the frame)
+    ms_g = float("nan")
+    if do_fov and not args.no_extra:
+        ctx.render_foveated(ds, cams, gaze, fov, out_f)
+        keys = ctx.get_counts()["n_keys"]
+        ctxg = pkg.Context()
+        out_g = torch.empty_like(out_f)
+        ctxg.graph_capture(ds, cams, gaze, fov, out_g, int(keys * 1.25) + 1024)
+        for _ in range(args.warmup):
+            ctxg.graph_launch(cams, gaze)
+        ms_g = timed(lambda: ctxg.graph_launch(cams, gaze), args.steps)
+        ctxg.sync()
+        if not torch.equal(out_g, out_f):
+            raise RuntimeError("graph replay differs from the eager frame")
+        ctxg.graph_destroy()
+        ctxg.close()
+        log(f"foveated from a HIP graph {ms_g:.3f} ms/frame")
 
     # quality of the foveated frame against the full-resolution render
     psnr = []
@@ -196,6 +225,12 @@ def main():
             ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
 
     training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 else None
+    extra = {}
+    if do_fov and do_frr and not args.no_extra:
+        extra["upsampler"] = net_leg(pkg, synth, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed)
+        extra["fallback"] = fallback_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed)
+        extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
+        extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline and do_fov:
@@ -211,14 +246,16 @@ def main():
                           f"median {med:.2f} s/frame, {oracle.default_threads()} threads)")
         log(f"cpu oracle {med:.2f} s/frame")
 
+    # the frame as served: the faster of the eager call and the graph replay (identical output)
+    best_ms = ms_f if not (ms_g == ms_g) else min(ms_f, ms_g)
     res = {
         "metric": METRIC,
-        "value": 1000.0 / ms_f if do_fov else None,
+        "value": 1000.0 / best_ms if do_fov else None,
         "unit": "stereo frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_f,
+        "ms_per_step": best_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -232,7 +269,7 @@ def main():
         },
         "full_res_fps": 1000.0 / ms_r if do_frr else None,
         "full_res_ms": ms_r,
-        "speedup_vs_full_res": (ms_r / ms_f) if (do_fov and do_frr) else None,
+        "speedup_vs_full_res": (ms_r / best_ms) if (do_fov and do_frr) else None,
         "periphery_psnr_db": min(psnr) if psnr else None,
         "periphery_psnr_db_per_eye": psnr,
         "outer_psnr_db_per_eye": psnr_outer,
@@ -240,9 +277,140 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": stages,
+        "blend_autotune": tuned,
+        "eager_ms_per_step": ms_f,
+        "graph_ms_per_step": ms_g,
         "training": training,
+        **extra,
     }
     print(json.dumps(res), flush=True)
+
+
+NET_FLOP_PER_INPUT_PIXEL = 47808    # 2 x (3x32 + 32x32 + 32x48) x 9 multiply-adds
+BF16_MFMA_PEAK_TF = 2500.0          # MI355X dense bf16
+
+
+def _psnr_outside_fovea(ctx, W, H, gaze, rad, out, ref):
+    vals = []
+    for e in range(len(gaze)):
+        sse, cnt = ctx.region_sse(W, H, gaze[e], rad[0], rad[1], out[e], ref[e])
+        mse = (sse[1] + sse[2]) / (3.0 * (cnt[1] + cnt[2]))
+        vals.append(math.inf if mse == 0 else 10 * math.log10(1.0 / mse))
+    return vals
+
+
+def net_leg(pkg, synth, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed):
+    """The foveated frame with the periphery through the learned upsampler
+    (parameters: the seeded initialisation; the trained network's quality is
+    measured by the tests and by the training leg)."""
+    W, H = cams[0].width, cams[0].height
+    theta = torch.from_numpy(synth.net_init(42)).cuda()
+    out = torch.empty((2, 3, H, W), device="cuda")
+    ctx.set_upsampler(theta)
+    step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    ctx.set_profiling(True)
+    timed(step, args.steps)
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    ctx.set_upsampler(None)
+    net = prof["stages"]["net"]
+    per_frame = net["ms"] / args.steps
+    flop = 2 * (H // 4) * (W // 4) * NET_FLOP_PER_INPUT_PIXEL
+    tf = flop / (per_frame / 1000.0) / 1e12
+    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
+    log(f"foveated frame with the upsampler {ms:.3f} ms; net {per_frame:.3f} ms/frame = {tf:.1f} TFLOP/s")
+    return dict(ms_per_frame=ms, net_ms_per_frame=per_frame, flop_per_frame=flop, achieved_TFLOPs=tf,
+                peak_TFLOPs=BF16_MFMA_PEAK_TF, frac=tf / BF16_MFMA_PEAK_TF, periphery_psnr_db=min(psnr),
+                weights="seeded initialisation (last layer x 0.01)")
+
+
+def fallback_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed):
+    W, H = cams[0].width, cams[0].height
+    out = torch.empty((2, 3, H, W), device="cuda")
+    ctx.set_fallback(*pkg.FALLBACK_DEFAULT)
+    step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    ctx.set_profiling(True)
+    timed(step, args.steps)
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    fb_ms = prof["stages"]["fallback"]["ms"] / args.steps
+    n_fb = ctx.get_counts()["n_fallback_tiles"]
+    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
+    ctx.set_fallback(float("inf"), 1.0, 1.0)
+    log(f"foveated frame with the fallback estimate {ms:.3f} ms (estimate {fb_ms:.3f} ms), {n_fb} fallback tiles, "
+        f"PSNR {min(psnr):.2f} dB")
+    return dict(ms_per_frame=ms, estimate_ms_per_frame=fb_ms, fallback_tiles=n_fb, periphery_psnr_db=min(psnr),
+                setting=list(pkg.FALLBACK_DEFAULT))
+
+
+def net_train_leg(pkg, synth, torch, np, ctx, ds, n_pairs=2048, epochs=2, batch=32):
+    """Training throughput of the upsampler: pairs rendered by the library at
+    the training poses (64x64 -> 256x256), Adam steps of batch 32."""
+    from paper_2507_04147_amd import upsampler as U
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xs, ts = U.make_pairs(ctx, ds, synth.crop_poses(41, n_pairs))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    net = U.Upsampler(ctx, synth.net_init(42))
+    net.fit(xs[:256], ts[:256], epochs=1, batch=batch)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    net.fit(xs, ts, epochs=epochs, batch=batch)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    steps = epochs * (n_pairs // batch)
+    flop = 3 * 64 * 64 * NET_FLOP_PER_INPUT_PIXEL * batch * steps  # forward + input and weight gradients
+    tf = flop / train_s / 1e12
+    log(f"upsampler training: {n_pairs} pairs rendered in {gen_s:.2f} s; {steps} steps in {train_s:.2f} s "
+        f"({tf:.1f} TFLOP/s)")
+    return dict(pairs=n_pairs, pair_render_s=gen_s, pairs_per_s=n_pairs / gen_s, steps=steps, batch=batch,
+                step_ms=1000.0 * train_s / steps, achieved_TFLOPs=tf, frac=tf / BF16_MFMA_PEAK_TF)
+
+
+def trace_leg(pkg, synth, torch, args, n=3_000_000, n_frames=64):
+    """Batched gaze trace: a 3M-Gaussian cloud over [-5,5]^3, 64 frames of a
+    seeded gaze walk with head drift, rendered as windows of stereo frames
+    (2 eyes x 3 layers per frame, uneven tile counts) in one preprocess / sort /
+    blend each, every window replayed from one captured HIP graph."""
+    win = max(1, min(args.trace_window, 64))
+    scene, _ = synth.foveated_stereo(n=n, seed=3)
+    ds = pkg.DeviceScene.from_host(scene)
+    del scene
+    trace = synth.gaze_trace(seed=31, n_frames=n_frames)
+    W, H = trace[0][0][0].width, trace[0][0][0].height
+    fov = pkg.fovea_struct(synth.FOVEA_FRACTIONS[0] * W, synth.FOVEA_FRACTIONS[1] * W, keep=synth.PERIPH_KEEP)
+    wins = [trace[k:k + win] for k in range(0, n_frames, win)]
+    flat = [([c for f in w for c in f[0]], [g for f in w for g in f[1]]) for w in wins]
+    ctx = pkg.Context()
+    out = torch.empty((2 * win, 3, H, W), device="cuda")
+    keys = 0
+    for cams, gz in flat:
+        ctx.render_foveated(ds, cams, gz, fov, out[:len(cams)])
+        keys = max(keys, ctx.get_counts()["n_keys"])
+    ctx.graph_capture(ds, flat[0][0], flat[0][1], fov, out, min(int(keys * 1.2) + 4096, (1 << 30) - 1))
+    for cams, gz in flat:
+        ctx.graph_launch(cams, gz)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for cams, gz in flat:
+        ctx.graph_launch(cams, gz)
+    ctx.sync()
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t
+    ctx.graph_destroy()
+    ctx.close()
+    log(f"gaze trace: {n_frames} stereo frames of {n} Gaussians in windows of {win}: {s * 1000:.1f} ms "
+        f"({n_frames / s:.1f} frames/s), max {keys} keys per window")
+    return dict(gaussians=n, frames=n_frames, window=win, views_per_launch=6 * win, max_keys_per_window=keys,
+                ms_total=s * 1000.0, stereo_frames_per_s=n_frames / s)
 
 
 def train_leg(pkg, synth, torch, np, steps):

@@ -109,7 +109,7 @@ void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent
                  const uint32_t *K_dev /* nullable: device key count (clamped to K) */, hipStream_t s);
 void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s);
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
-                     hipStream_t s);
+                     hipStream_t s, const uint32_t *skip_if_zero = nullptr /* device count: 0 skips */);
 void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
                         int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s);
 int sort_partitions(int64_t n);
@@ -158,16 +158,20 @@ void launch_net_mse(const float *out, const float *target, int B, int h, int w, 
                     double *sse, float *loss, hipStream_t s);
 void launch_net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float beta1, float beta2,
                      float eps, float bc1, float bc2, hipStream_t s);
-void launch_drop_energy(const DevView *views, int pv, int64_t n, const uint32_t *counts, const uint8_t *keep,
-                        const uint64_t *rect, const double *score, const float *opacity, int64_t ntiles,
+int drop_energy_parts();
+void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
+                        const uint8_t *keep, const uint64_t *rect, const double *score,
+                        double *diff /* zeroed [2][tiles_y+1][tiles_x+1] of view pv */,
+                        double *partials /* [drop_energy_parts()][2][tiles_y+1][tiles_x+1] */, int64_t ntiles,
                         float *energy /* [2][ntiles]: dropped mass, kept mass */, hipStream_t s);
 void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
                            int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
-                           uint8_t *active, hipStream_t s);
+                           uint8_t *active, uint32_t *n_flagged, hipStream_t s);
 void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
-                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list, hipStream_t s);
+                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list,
+                             const uint32_t *n_flagged, hipStream_t s);
 void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
-                    uint32_t *counts, hipStream_t s);
+                    uint32_t *counts, const uint32_t *n_flagged, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
                       const uint8_t *fb_flags /* nullable: periphery tiles taken from fovea */, int fb_tiles_x,

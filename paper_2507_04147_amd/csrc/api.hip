@@ -64,7 +64,7 @@ struct a3fr_ctx {
     struct FbPair { int pv, fv; double r_mid; };
     std::vector<FbPair> fb_plan;           // set by a3fr_render_foveated for its a3fr_preprocess
     bool fb_last = false;                  // the last preprocess ran the fallback steps
-    DevBuf fb_energy, fb_flags;
+    DevBuf fb_energy, fb_flags, fb_diff, fb_part, fb_count;
     bool net_trained_fwd = false;          // the last forward kept activations for a backward
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
     DevBuf keys_e, vals_e;     // emission-order copy (debug option)
@@ -294,7 +294,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
-                      &c->net_g1c, &c->net_sse, &c->periph_full, &c->fb_energy, &c->fb_flags, &c->blend_ws,
+                      &c->net_g1c, &c->net_sse, &c->periph_full, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->fb_count, &c->blend_ws,
                       &c->blend_order, &c->tune_img,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
@@ -534,23 +534,43 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     if (!c->fb_plan.empty() && c->nsel) {
         // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
         StageTimer t_(c, A3FR_STAGE_FALLBACK);
+        // difference planes of every periphery view: [2][tiles_y + 1][tiles_x + 1] doubles each
+        int64_t dwords = 0;
+        for (const auto &fp : c->fb_plan)
+            dwords += 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) * (c->hviews[fp.pv].tiles_x + 1);
         TRY(ensure(c, c->fb_energy, sizeof(float) * 2 * (size_t)toff));
         TRY(ensure(c, c->fb_flags, (size_t)toff));
-        launch_fill_u32(P<uint32_t>(c->fb_energy), 0u, 2 * toff, c->stream);
+        TRY(ensure(c, c->fb_diff, sizeof(double) * (size_t)dwords));
+        int64_t maxcells = 0;
         for (const auto &fp : c->fb_plan)
-            launch_drop_energy(dv, fp.pv, n, P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
-                               P<double>(c->score), scene->opacity_dev, toff, P<float>(c->fb_energy), c->stream);
+            maxcells = std::max<int64_t>(maxcells, 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) *
+                                                       (c->hviews[fp.pv].tiles_x + 1));
+        TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)(maxcells * drop_energy_parts())));
+        TRY(ensure(c, c->fb_count, 16));
+        launch_fill_u32(P<uint32_t>(c->fb_count), 0u, 1, c->stream);
+        launch_fill_u32(P<uint32_t>(c->fb_energy), 0u, 2 * toff, c->stream);
+        launch_fill_u32(P<uint32_t>(c->fb_diff), 0u, 2 * dwords, c->stream);
+        int64_t doff = 0;
+        for (const auto &fp : c->fb_plan) {
+            launch_drop_energy(dv, fp.pv, c->hviews[fp.pv].tiles_x, c->hviews[fp.pv].tiles_y, n,
+                               P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
+                               P<double>(c->score), P<double>(c->fb_diff) + doff, P<double>(c->fb_part), toff,
+                               P<float>(c->fb_energy), c->stream);
+            doff += 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) * (c->hviews[fp.pv].tiles_x + 1);
+        }
         for (const auto &fp : c->fb_plan)
             launch_fallback_flags(dv, fp.pv, fp.fv, (int64_t)c->hviews[fp.pv].tiles_x * c->hviews[fp.pv].tiles_y,
                                   P<float>(c->fb_energy), toff, fp.r_mid, c->fb_thr, c->fb_coef, c->fb_pow,
-                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), c->stream);
+                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), P<uint32_t>(c->fb_count), c->stream);
         launch_rows_from_active(dv, c->rows_total, d_row_view, d_row_y, P<uint8_t>(c->active),
-                                P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), c->stream);
+                                P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->fb_count),
+                                c->stream);
         if (c->cum_entries)
-            launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream);
+            launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream,
+                            P<uint32_t>(c->fb_count));
         for (const auto &fp : c->fb_plan)
             launch_recount(dv, fp.fv, n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
-                           c->stream);
+                           P<uint32_t>(c->fb_count), c->stream);
         c->fb_last = true;
     }
     {

@@ -546,7 +546,9 @@ __global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, 
 // cum[v][ty][tx] for masked views: active tiles in rows < ty and columns < tx.
 // One wavefront per (view, column): a wave-wide scan down the rows.
 __global__ void __launch_bounds__(256) k_mask_cum(const DevView *__restrict__ views,
-                                                  const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ cum) {
+                                                  const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ cum,
+                                                  const uint32_t *skip_if_zero) {
+    if (skip_if_zero && *skip_if_zero == 0) return;
     const DevView &dv = views[blockIdx.y];
     if (dv.v.mask == A3FR_MASK_ALL) return;
     const int TX = dv.tiles_x, TY = dv.tiles_y, stride = TX + 1;
@@ -570,10 +572,10 @@ __global__ void __launch_bounds__(256) k_mask_cum(const DevView *__restrict__ vi
 }
 
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
-                     hipStream_t s) {
+                     hipStream_t s, const uint32_t *skip_if_zero) {
     if (nv == 0) return;
     hipLaunchKernelGGL(k_mask_cum, dim3((unsigned)((max_tiles_x + 1 + 3) / 4), (unsigned)nv), dim3(256), 0, s, views,
-                       row_prefix, cum);
+                       row_prefix, cum, skip_if_zero);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {

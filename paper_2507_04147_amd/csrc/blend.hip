@@ -92,19 +92,28 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 kdy[r] = kk * dy;
                 cdy[r] = c2 * dy * dy;
             }
-            // branch-free: a pixel that does not blend adds fma(0, c, C) = C (colours >= 0)
+            float al[4];
+            bool take[4];
+            bool any = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rr = q / COLS;
                 if (COUNT) npairs += alive[q] ? 1u : 0u;
                 const float t = (fxq[q] - mu) + kdy[rr];
                 const float e = fmaf(a2, t * t, cdy[rr]);
-                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                const float Tn = T[q] * (1.0f - al);
-                const bool take = alive[q] && al >= kAlphaMin;
-                const bool stop = take && Tn < kTMin;
-                const bool blend = take && !stop;
-                const float wgt = blend ? al * T[q] : 0.0f;
+                al[q] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
+                take[q] = alive[q] && al[q] >= kAlphaMin;
+                any = any || take[q];
+            }
+            // most evaluated pairs fall outside the footprint (alpha < 1/255): skip when the whole wave does
+            if (__ballot(any) == 0ull) continue;
+            // branch-free: a pixel that does not blend adds fma(0, c, C) = C (colours >= 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float Tn = T[q] * (1.0f - al[q]);
+                const bool stop = take[q] && Tn < kTMin;
+                const bool blend = take[q] && !stop;
+                const float wgt = blend ? al[q] * T[q] : 0.0f;
                 Cr[q] = fmaf(wgt, cr, Cr[q]);
                 Cg[q] = fmaf(wgt, cg, Cg[q]);
                 Cb[q] = fmaf(wgt, cb, Cb[q]);

@@ -18,13 +18,15 @@
 
 namespace a3fr {
 
+// Each visible Gaussian of the periphery view adds its per-pixel share to the
+// four corners of its tile rectangle in a 2D difference array (float64,
+// [2][TY+1][TX+1]: dropped, kept), so the cost per Gaussian does not depend
+// on its size; a prefix sum over the tile grid then gives D and K.
 __global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__ views, int pv, int64_t n,
                                                      const uint32_t *__restrict__ counts,
                                                      const uint8_t *__restrict__ keep,
                                                      const uint64_t *__restrict__ rect,
-                                                     const double *__restrict__ score,
-                                                     const float *__restrict__ opacity, int64_t ntiles,
-                                                     float *__restrict__ energy) {
+                                                     const double *__restrict__ score, double *__restrict__ diff) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t slot = (int64_t)pv * n + i;
@@ -34,19 +36,120 @@ __global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__
     const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
               y1 = (int)(r >> 48);
     const int nt = (x1 - x0 + 1) * (y1 - y0 + 1);
-    const float share = (float)(2.0 * score[slot] / ((double)nt * (double)(kTile * kTile)));
-    // dropped mass in the first plane, kept mass in the second
-    float *E = energy + (keep[slot] ? ntiles : 0) + dv.tile_off;
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) atomicAdd(&E[(int64_t)ty * dv.tiles_x + tx], share);
+    const double share = 2.0 * score[slot] / ((double)nt * (double)(kTile * kTile));
+    const int S = dv.tiles_x + 1;
+    double *d = diff + (keep[slot] ? (int64_t)(dv.tiles_y + 1) * S : 0);
+    atomicAdd(&d[(int64_t)y0 * S + x0], share);
+    atomicAdd(&d[(int64_t)y0 * S + x1 + 1], -share);
+    atomicAdd(&d[(int64_t)(y1 + 1) * S + x0], -share);
+    atomicAdd(&d[(int64_t)(y1 + 1) * S + x1 + 1], share);
 }
 
-void launch_drop_energy(const DevView *views, int pv, int64_t n, const uint32_t *counts, const uint8_t *keep,
-                        const uint64_t *rect, const double *score, const float *opacity, int64_t ntiles,
-                        float *energy, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, pv, n, counts, keep,
-                       rect, score, opacity, ntiles, energy);
+// One block: 2D inclusive prefix sum of the two difference planes of view pv
+// (in place: first along each row, then down each column, one thread per row
+// or column, so a thread's chain of dependent loads is one row or column
+// long), written as float32 into energy [2][ntiles] at the view's tiles.
+__global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict__ views, int pv, double *diff,
+                                                      int64_t ntiles, float *__restrict__ energy) {
+    extern __shared__ double pre[];  // the two planes when they fit (dynamic size, else unused)
+    const DevView &dv = views[pv];
+    const int TX = dv.tiles_x, TY = dv.tiles_y, S = TX + 1;
+    const int64_t plane = (int64_t)(TY + 1) * S;
+    const bool lds = 2 * plane * (int64_t)sizeof(double) <= 48 * 1024;
+    double *d = diff;
+    if (lds) {
+        for (int64_t k = threadIdx.x; k < 2 * plane; k += blockDim.x) pre[k] = diff[k];
+        __syncthreads();
+        d = pre;
+    }
+    for (int r = threadIdx.x; r < 2 * TY; r += blockDim.x) {
+        double *row = d + (r / TY) * plane + (int64_t)(r % TY) * S;
+        double acc = 0.0;
+        for (int x = 0; x < TX; ++x) {
+            acc += row[x];
+            row[x] = acc;
+        }
+    }
+    __syncthreads();
+    for (int cidx = threadIdx.x; cidx < 2 * TX; cidx += blockDim.x) {
+        const int pl = cidx / TX, x = cidx % TX;
+        const double *col = d + pl * plane + x;
+        float *E = energy + (int64_t)pl * ntiles + dv.tile_off + x;
+        double acc = 0.0;
+        for (int y = 0; y < TY; ++y) {
+            acc += col[(int64_t)y * S];
+            E[(int64_t)y * TX] = (float)acc;
+        }
+    }
+}
+
+// Contention-free variant for grids that fit in LDS: persistent blocks add
+// into a block-local difference array (LDS atomics), write it out as one
+// partial each, and a second kernel sums the partials; device-scope atomics on
+// a few hundred addresses from every XCD would serialise.
+__global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restrict__ views, int pv, int64_t n,
+                                                         const uint32_t *__restrict__ counts,
+                                                         const uint8_t *__restrict__ keep,
+                                                         const uint64_t *__restrict__ rect,
+                                                         const double *__restrict__ score, int cells,
+                                                         double *__restrict__ partials) {
+    extern __shared__ double sh[];
+    for (int k = threadIdx.x; k < cells; k += blockDim.x) sh[k] = 0.0;
+    __syncthreads();
+    const DevView &dv = views[pv];
+    const int S = dv.tiles_x + 1;
+    const int64_t plane = (int64_t)(dv.tiles_y + 1) * S;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t slot = (int64_t)pv * n + i;
+        if (counts[slot] == 0) continue;
+        const uint64_t r = rect[slot];
+        const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
+                  y1 = (int)(r >> 48);
+        const int nt = (x1 - x0 + 1) * (y1 - y0 + 1);
+        const double share = 2.0 * score[slot] / ((double)nt * (double)(kTile * kTile));
+        double *d = sh + (keep[slot] ? plane : 0);
+        atomicAdd(&d[(int64_t)y0 * S + x0], share);
+        atomicAdd(&d[(int64_t)y0 * S + x1 + 1], -share);
+        atomicAdd(&d[(int64_t)(y1 + 1) * S + x0], -share);
+        atomicAdd(&d[(int64_t)(y1 + 1) * S + x1 + 1], share);
+    }
+    __syncthreads();
+    double *out = partials + (int64_t)blockIdx.x * cells;
+    for (int k = threadIdx.x; k < cells; k += blockDim.x) out[k] = sh[k];
+}
+
+// 256 threads per 64 cells: four slices of the partials per cell, summed in LDS.
+__global__ void __launch_bounds__(256) k_drop_reduce(const double *__restrict__ partials, int nparts, int cells,
+                                                     double *__restrict__ diff) {
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + c;
+    double acc = 0.0;
+    if (k < cells)
+        for (int g = slice; g < nparts; g += 4) acc += partials[(int64_t)g * cells + k];
+    red[slice][c] = acc;
+    __syncthreads();
+    if (slice == 0 && k < cells) diff[k] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+int drop_energy_parts() { return 64; }
+
+void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
+                        const uint8_t *keep, const uint64_t *rect, const double *score, double *diff,
+                        double *partials, int64_t ntiles, float *energy, hipStream_t s) {
+    const int cells = 2 * (tiles_y + 1) * (tiles_x + 1);
+    const size_t lds = sizeof(double) * (size_t)cells;
+    if (n > 0 && partials && lds <= 48 * 1024) {
+        const int parts = drop_energy_parts();
+        hipLaunchKernelGGL(k_drop_energy_lds, dim3(parts), dim3(256), lds, s, views, pv, n, counts, keep, rect, score,
+                           cells, partials);
+        hipLaunchKernelGGL(k_drop_reduce, dim3((cells + 63) / 64), dim3(256), 0, s, partials, parts, cells, diff);
+    } else if (n > 0) {
+        hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, pv, n, counts,
+                           keep, rect, score, diff);
+    }
+    hipLaunchKernelGGL(k_drop_prefix, dim3(1), dim3(1024), lds <= 48 * 1024 ? lds : 0, s, views, pv, diff, ntiles,
+                       energy);
 }
 
 // One thread per periphery tile: flag, and activate the covered tiles of the
@@ -55,7 +158,8 @@ void launch_drop_energy(const DevView *views, int pv, int64_t n, const uint32_t 
 // covers lies outside r_mid (the composite's periphery region).
 __global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int fv, const float *__restrict__ energy,
                                  int64_t ntiles, double r_mid, double threshold, double coef, double power,
-                                 uint8_t *__restrict__ flags, uint8_t *__restrict__ active) {
+                                 uint8_t *__restrict__ flags, uint8_t *__restrict__ active,
+                                 uint32_t *__restrict__ n_flagged) {
     const DevView &dp = views[pv], &df = views[fv];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)dp.tiles_x * dp.tiles_y) return;
@@ -74,6 +178,7 @@ __global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int 
     const bool flag = outer && est >= threshold;
     flags[dp.tile_off + t] = flag ? 1 : 0;
     if (!flag) return;
+    atomicAdd(n_flagged, 1u);
     for (int yy = ty * s; yy < (ty + 1) * s && yy < df.tiles_y; ++yy)
         for (int xx = tx * s; xx < (tx + 1) * s && xx < df.tiles_x; ++xx)
             active[df.tile_off + (int64_t)yy * df.tiles_x + xx] = 1;
@@ -81,10 +186,10 @@ __global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int 
 
 void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
                            int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
-                           uint8_t *active, hipStream_t s) {
+                           uint8_t *active, uint32_t *n_flagged, hipStream_t s) {
     if (periph_tiles == 0) return;
     hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)((periph_tiles + 255) / 256)), dim3(256), 0, s, views, pv, fv,
-                       energy, ntiles, r_mid, threshold, coef, power, flags, active);
+                       energy, ntiles, r_mid, threshold, coef, power, flags, active, n_flagged);
 }
 
 // Row prefix and active-column list of the remasked views' rows from their
@@ -92,7 +197,8 @@ void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_
 __global__ void __launch_bounds__(256) k_rows_from_active(const DevView *views, int64_t rows_total,
                                                           const int32_t *row_view, const int32_t *row_y,
                                                           const uint8_t *active, uint16_t *row_prefix,
-                                                          uint16_t *row_list) {
+                                                          uint16_t *row_list, const uint32_t *n_flagged) {
+    if (*n_flagged == 0) return;  // no tile joined any mask: rows unchanged
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= rows_total) return;
@@ -120,17 +226,20 @@ __global__ void __launch_bounds__(256) k_rows_from_active(const DevView *views, 
 }
 
 void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
-                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list, hipStream_t s) {
+                             const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list,
+                             const uint32_t *n_flagged, hipStream_t s) {
     if (rows_total == 0) return;
     hipLaunchKernelGGL(k_rows_from_active, dim3((unsigned)((rows_total + 3) / 4)), dim3(256), 0, s, views, rows_total,
-                       row_view, row_y, active, row_prefix, row_list);
+                       row_view, row_y, active, row_prefix, row_list, n_flagged);
 }
 
 // Active tiles covered by each visible Gaussian's rectangle in view fv, from
 // the rebuilt row prefixes.
 __global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ views, int fv, int64_t n,
                                                  const uint64_t *__restrict__ rect,
-                                                 const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ counts) {
+                                                 const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ counts,
+                                                 const uint32_t *n_flagged) {
+    if (*n_flagged == 0) return;  // masks unchanged: the counts of the projection stand
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const DevView &dv = views[fv];
@@ -149,10 +258,10 @@ __global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ vie
 }
 
 void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
-                    uint32_t *counts, hipStream_t s) {
+                    uint32_t *counts, const uint32_t *n_flagged, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_recount, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, fv, n, rect, row_prefix,
-                       counts);
+                       counts, n_flagged);
 }
 
 }  // namespace a3fr
