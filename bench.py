@@ -35,9 +35,54 @@ HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 FP32_VECTOR_PEAK_TF = 157.3   # MI355X FP32 vector (packed) peak
 SORT_BYTES_PER_KEY_PASS = 16  # tile-id sort: read key (4) + value (4), write key (4) + value (4)
 BLEND_FLOPS_PER_PAIR = 18
-PREPROCESS_READ_PER_GAUSSIAN = 236
-PREPROCESS_WRITE_PER_VISIBLE = 64  # record 48 + depth 4 + rect 8 + count 4
-PREPROCESS_WRITE_COUNT = 4
+# HBM traffic per dispatch from the hardware counters: rocprofv3 --pmc
+# FETCH_SIZE, then WRITE_SIZE (KiB per dispatch) of the profiled benchmark
+# command, each scaled by the factor that maps what the same counter reads for
+# a device-to-device copy of known size to that size.  A table entry is used
+# only while the kernel source it was measured on is unchanged (sha256), else
+# traffic is null.  Keys: the blend variant "batch,block,schedule", else the
+# kernel name.
+# Calibration (bench.py --calibrate-copy 512): a 512 MiB device copy reads
+# FETCH_SIZE = 262,166.6 KiB (its reads are 128-byte requests, which that
+# counter's expression weighs as 64 bytes) and writes WRITE_SIZE = 524,288 KiB.
+PMC_FETCH_FACTOR = 524288.0 / 262166.6
+PMC_WRITE_FACTOR = 1.0
+PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
+    "blend": dict(source="csrc/blend.hip",
+                  sha256="ea6ba1b150fb37adc18453e899c4487b161992f488960bacea798e59e3587dcb",
+                  kib={"32,4x1,grid": (6413.3, 21750.0), "64,4x1,grid": (7190.4, 21750.0),
+                       "128,4x1,grid": (9629.5, 21750.0), "32,2x2,grid": (6414.6, 21750.0),
+                       "64,2x2,grid": (7185.6, 21750.0), "128,2x2,grid": (9584.7, 21750.0),
+                       "32,4x1,queue": (5951.5, 21905.4), "64,4x1,queue": (6634.0, 21875.4),
+                       "128,4x1,queue": (8944.2, 21865.1), "32,2x2,queue": (5917.9, 21845.0),
+                       "64,2x2,queue": (6622.3, 21871.4), "128,2x2,queue": (8977.8, 21872.8)}),
+    "preprocess": dict(source="csrc/preprocess.hip",
+                       sha256="50200eb6778e31d54d4fa2eccc59665b9fec8c917870ca15e5cbcf19a41a7bf4",
+                       kib={"k_preprocess": (43371.0, 115881.5)}),
+    "colour": dict(source="csrc/preprocess.hip",
+                   sha256="50200eb6778e31d54d4fa2eccc59665b9fec8c917870ca15e5cbcf19a41a7bf4",
+                   kib={"k_entry_colour": (82529.7, 13795.5)}),
+    "sort_pass": dict(source="csrc/sort.hip",  # the two tile-id passes of the key sort
+                      sha256="031a3a1107f11ffa173d6cfb354f57dc8d5610e54db00eb1a490a27b1d29bdfe",
+                      kib={"k_onesweep": (45781.8, 89767.0)}),
+}
+# projection, one launch for both eyes (each with its fovea, mid and periphery
+# views): the float32 mean, scale and quaternion of every Gaussian (40 B) once
+# per eye and the opacity of the visible ones (4 B); a 4-byte key count per
+# (view, Gaussian) slot; per slot that emits keys its depth (4), rectangle (8)
+# and 48-byte record, plus an 8-byte score in the periphery (selecting) view.
+PREPROCESS_READ_PER_GAUSSIAN = 40
+PREPROCESS_READ_PER_VISIBLE = 4
+PREPROCESS_WRITE_PER_SLOT = 4
+PREPROCESS_WRITE_PER_EMITTING = 4 + 8 + 48
+PREPROCESS_WRITE_PER_SCORE = 8
+# view-dependent colour, per entry that emits keys: its index (4), mean (12),
+# SH coefficients (4 x 3 x 16 at degree 3) read, colour (12) written
+COLOUR_BYTES_PER_ENTRY = 4 + 12 + 192 + 12
+# key emission (chunk starts + emission): per entry its key offset (4), index
+# (4) and rectangle (8) read; per key its tile id and Gaussian index written
+EMIT_BYTES_PER_ENTRY = 4 + 4 + 8
+EMIT_BYTES_PER_KEY = 8
 # reverse blend: floating-point operations per revisited (pixel, Gaussian) pair
 # (alpha recomputed: 8; transmittance recovery, colour and alpha gradients: 14;
 # the nine per-Gaussian sums: 21)
@@ -48,6 +93,20 @@ BLEND_BWD_FLOPS_PER_PAIR = 43
 # of SH coefficients
 PREPROCESS_BWD_BYTES_PER_GAUSSIAN = 44 + 48 + 236
 PREPROCESS_BWD_BYTES_PER_DRAWN = 48 + 192
+
+
+def pmc_traffic(stage, key):
+    """HBM bytes per dispatch of a stage's kernel from the counter table, or
+    None when there is none or its source has changed since."""
+    t = PMC_TRAFFIC.get(stage)
+    if t is None or key is None or key not in t["kib"] or PMC_FETCH_FACTOR is None or PMC_WRITE_FACTOR is None:
+        return None
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2507_04147_amd", t["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != t["sha256"]:
+            return None
+    fetch, write = t["kib"][key]
+    return 1024.0 * (fetch * PMC_FETCH_FACTOR + write * PMC_WRITE_FACTOR)
 
 
 def log(msg):
@@ -175,13 +234,17 @@ def main():
     roofline = None
     counts = {}
     if do_fov:
-        ctx.set_profiling(True)
+        # evaluated (pixel, Gaussian) pairs of one frame (counting variant of the blend)
+        ctx.set_profiling(True, count_pairs=True)
+        step_fov()
+        pairs = ctx.get_profile()["blend_pairs"]
+        # stage times with the blend variant used for rendering
+        ctx.set_profiling(True, count_pairs=False)
         ms_f_prof = timed(step_fov, args.steps)
         prof = ctx.get_profile()
         ctx.set_profiling(False)
         counts = ctx.get_counts()
         K = prof["sort_keys"] / max(1, args.steps)
-        n_vis_views = None
         st = prof["stages"]
         for name, v in st.items():
             if v["launches"]:
@@ -195,32 +258,46 @@ def main():
             stages["sort_pass"].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
                                        bytes_per_launch=SORT_BYTES_PER_KEY_PASS * K)
         bl = st["blend"]
-        pairs = prof["blend_pairs"] / args.steps
         if bl["launches"]:
             per_launch_s = bl["ms"] / bl["launches"] / 1000.0
             tf = BLEND_FLOPS_PER_PAIR * pairs / per_launch_s / 1e12
             stages["blend"].update(bound="alu", achieved_TFLOPs=tf, frac=tf / FP32_VECTOR_PEAK_TF,
                                    pairs_per_launch=pairs)
-        pp = st["preprocess"]
-        if pp["launches"]:
-            cnt = ctx.inspect("counts", torch.int32)
-            nvis = int((cnt != 0).sum().item())
-            bytes_pp = PREPROCESS_READ_PER_GAUSSIAN * scene.n + PREPROCESS_WRITE_COUNT * cnt.numel() + \
-                PREPROCESS_WRITE_PER_VISIBLE * nvis
-            per_launch_s = pp["ms"] / pp["launches"] / 1000.0
-            gbs = bytes_pp / per_launch_s / 1e9
-            stages["preprocess"].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
-                                        bytes_per_launch=bytes_pp)
-        # dominant kernel: the stage with the most time per frame among sort pass / blend / preprocess
-        cand = [s for s in ("sort_pass", "blend", "preprocess") if s in stages]
-        dom = max(cand, key=lambda s: stages[s]["ms_per_frame"])
+        # views of the frame: per eye fovea, mid, periphery (selecting, every tile active)
+        cnt = ctx.inspect("counts", torch.int32).view(-1, scene.n)
+        nz = (cnt != 0).sum(dim=1).tolist()
+        n_periph = sum(nz[2::3])
+        n_ent = int(ctx.inspect("offsets", torch.int32).numel()) - 1  # entries that emit keys (kept)
+
+        def hbm_stage(name, bytes_per_frame):
+            v = st[name]
+            if not v["launches"]:
+                return
+            gbs = bytes_per_frame / (v["ms"] / args.steps / 1000.0) / 1e9
+            stages[name].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                bytes_per_launch=bytes_per_frame * args.steps / v["launches"])
+
+        hbm_stage("preprocess", 2 * PREPROCESS_READ_PER_GAUSSIAN * scene.n + PREPROCESS_READ_PER_VISIBLE * n_periph +
+                  PREPROCESS_WRITE_PER_SLOT * cnt.numel() + PREPROCESS_WRITE_PER_EMITTING * sum(nz) +
+                  PREPROCESS_WRITE_PER_SCORE * n_periph)
+        sh_bytes = 4 * int(np.prod(scene.sh.shape[:-1]))  # [coef][channel][n]
+        hbm_stage("colour", n_ent * (COLOUR_BYTES_PER_ENTRY - 192 + sh_bytes))
+        hbm_stage("emit", EMIT_BYTES_PER_ENTRY * n_ent + EMIT_BYTES_PER_KEY * K)
+        # dominant kernel: the single-kernel stage with the most time per frame
+        cand = [s_ for s_ in ("sort_pass", "blend", "preprocess", "colour") if "bound" in stages.get(s_, {})]
+        dom = max(cand, key=lambda s_: stages[s_]["ms_per_frame"])
         d = stages[dom]
+        variant = tuned["variant"] if tuned else 1  # the library's default variant when not tuned
+        key = {"blend": ",".join(str(x) for x in pkg.blend_variant_desc(variant)),
+               "preprocess": "k_preprocess", "colour": "k_entry_colour", "sort_pass": "k_onesweep"}[dom]
+        traffic = pmc_traffic(dom, key)
         if d["bound"] == "hbm":
             roofline = dict(kernel=dom, bound="hbm", achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=d["frac"], traffic=None, ms_per_launch=d["ms_per_launch"])
+                            frac=d["frac"], traffic=traffic, ms_per_launch=d["ms_per_launch"],
+                            algorithmic_bytes=d["bytes_per_launch"])
         else:
             roofline = dict(kernel=dom, bound="alu", achieved=d["achieved_TFLOPs"], peak=FP32_VECTOR_PEAK_TF,
-                            unit="TFLOP/s", frac=d["frac"], traffic=None, ms_per_launch=d["ms_per_launch"])
+                            unit="TFLOP/s", frac=d["frac"], traffic=traffic, ms_per_launch=d["ms_per_launch"])
         log(f"profiled pass {ms_f_prof:.3f} ms/frame; stages: " +
             ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
 
@@ -311,7 +388,7 @@ def net_leg(pkg, synth, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed
     for _ in range(args.warmup):
         step()
     ms = timed(step, args.steps)
-    ctx.set_profiling(True)
+    ctx.set_profiling(True, count_pairs=False)
     timed(step, args.steps)
     prof = ctx.get_profile()
     ctx.set_profiling(False)
@@ -335,7 +412,7 @@ def fallback_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed):
     for _ in range(args.warmup):
         step()
     ms = timed(step, args.steps)
-    ctx.set_profiling(True)
+    ctx.set_profiling(True, count_pairs=False)
     timed(step, args.steps)
     prof = ctx.get_profile()
     ctx.set_profiling(False)
@@ -460,7 +537,7 @@ def train_leg(pkg, synth, torch, np, steps):
         Tt = torch.empty((H, W), device="cuda")
         last = torch.empty((H, W), dtype=torch.int32, device="cuda")
         g = [torch.empty_like(x) for x in ts]
-        a3.set_profiling(True)
+        a3.set_profiling(True, count_pairs=False)
         for _ in range(steps):
             a3.activate(pr, scale, opac)
             a3.preprocess(pkg.DeviceScene(ts[0].detach(), scale, ts[2].detach(), opac, ts[4].detach()), [v])

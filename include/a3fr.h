@@ -398,7 +398,7 @@ a3fr_status a3fr_graph_destroy(a3fr_ctx *ctx);
 /* ---- per-stage timing (HIP events on the context's stream) -------------- */
 typedef enum {
     A3FR_STAGE_MASKS = 0,      /* active-tile masks */
-    A3FR_STAGE_PREPROCESS = 1, /* projection, colour, counts */
+    A3FR_STAGE_PREPROCESS = 1, /* projection, blend records, key counts */
     A3FR_STAGE_SELECT = 2,     /* periphery radix select */
     A3FR_STAGE_SCAN = 3,       /* compaction of visible entries; key offsets in depth order */
     A3FR_STAGE_EMIT = 4,       /* key emission */
@@ -413,7 +413,8 @@ typedef enum {
     A3FR_STAGE_PREPROCESS_BWD = 13, /* reverse projection, colour and activation */
     A3FR_STAGE_FALLBACK = 14,  /* periphery error estimate, fallback masks and recount */
     A3FR_STAGE_NET = 15,       /* upsampler inference in a3fr_render_foveated */
-    A3FR_STAGE_COUNT = 16
+    A3FR_STAGE_COLOUR = 16,    /* view-dependent colour of the entries that emit keys */
+    A3FR_STAGE_COUNT = 17
 } a3fr_stage;
 
 typedef struct {
@@ -424,10 +425,12 @@ typedef struct {
     int64_t blend_pairs;                /* evaluated (pixel, Gaussian) pairs of the timed blends */
 } a3fr_profile;
 
-/* Turn per-stage event timing on or off (off by default; each timed interval
- * adds two event records to the stream, and blends also count their evaluated
- * (pixel, Gaussian) pairs: every list entry a pixel evaluates while it has not
- * stopped, the stopping one included). */
+/* Per-stage event timing: enable = 0 off (the default), 1 on and blends also
+ * count their evaluated (pixel, Gaussian) pairs (every list entry a pixel
+ * evaluates while it has not stopped, the stopping one included; this runs
+ * the counting variant of the blend), 2 on without pair counting (the blend
+ * variant timed is the one used for rendering).  Each timed interval adds
+ * two event records to the stream. */
 a3fr_status a3fr_set_profiling(a3fr_ctx *ctx, int32_t enable);
 /* Synchronises, returns the per-stage totals accumulated since the last call
  * (or since profiling was enabled) and resets them. */
@@ -448,7 +451,8 @@ typedef enum {
     A3FR_BUF_RANGES = 8,      /* uint32 [n_tiles][2] start, end */
     A3FR_BUF_ACTIVE = 9,      /* uint8 [n_tiles] active-tile flags */
     A3FR_BUF_KEEP = 10,       /* uint8 [n_views][n] kept by the periphery subset (selecting views) */
-    A3FR_BUF_RECORDS = 11,    /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb */
+    A3FR_BUF_RECORDS = 11,    /* 48-byte blend records [n_views][n]: f64 u, v; f32 conic terms, opacity, rgb
+                                 (valid where count > 0) */
     A3FR_BUF_DEPTH_ORDER = 12,/* uint32 [E] visible (kept) entries view*n + index, sorted by (depth, view, index) */
     /* upsampler, after a3fr_net_forward(for_training = 1) (gradients after a3fr_net_backward);
        bfloat16 bits, [B][h][w][C] unless stated */

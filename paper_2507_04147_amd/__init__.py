@@ -83,7 +83,7 @@ class Fovea_(C.Structure):
 
 
 STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite",
-          "depth_sort", "activate", "blend_bwd", "preprocess_bwd", "fallback", "net"]
+          "depth_sort", "activate", "blend_bwd", "preprocess_bwd", "fallback", "net", "colour"]
 
 
 class Profile_(C.Structure):
@@ -369,8 +369,10 @@ class Context:
         self._check(self._L.a3fr_inspect(self._h, BUF[which], _dp(out), out.numel() * esz, C.byref(nb)))
         return out[: nb.value // esz]
 
-    def set_profiling(self, enable=True):
-        self._check(self._L.a3fr_set_profiling(self._h, int(bool(enable))))
+    def set_profiling(self, enable=True, count_pairs=True):
+        """a3fr_set_profiling: events per stage; count_pairs also counts blend pairs (counting variant)."""
+        mode = 0 if not enable else (1 if count_pairs else 2)
+        self._check(self._L.a3fr_set_profiling(self._h, mode))
 
     def get_profile(self):
         p = Profile_()

@@ -103,6 +103,8 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const D
                             uint64_t *total, uint32_t *n_ent, hipStream_t s);
 void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
                         uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s);
+// number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
+int64_t emit_chunks(int64_t K);
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,

@@ -71,6 +71,7 @@ struct a3fr_ctx {
     bool keep_emission = false;
     // per-stage event timing
     bool profiling = false;
+    bool count_pairs = false;              // profiling mode 1 also counts blend pairs
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_marks;  // (stage, index of the start event)
@@ -323,6 +324,7 @@ a3fr_status a3fr_set_profiling(a3fr_ctx *c, int32_t enable) {
     if (!c) return A3FR_EINVAL;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->profiling = enable != 0;
+    c->count_pairs = enable == 1;
     c->ev_used = 0;
     c->ev_marks.clear();
     c->prof_sort_keys = c->prof_sort_passes = 0;
@@ -580,7 +582,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
                                sc_ent_total(c->scalars), sc_n_ent(c->scalars), c->stream);
     }
     {
-        StageTimer t_(c, A3FR_STAGE_PREPROCESS);
+        StageTimer t_(c, A3FR_STAGE_COLOUR);
         launch_entry_colour(*scene, dv, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m, P<Record>(c->rec), c->stream);
     }
     {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
@@ -629,7 +631,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     TRY(ensure(c, c->keys_b, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_a, sizeof(uint32_t) * K));
     TRY(ensure(c, c->vals_b, sizeof(uint32_t) * K));
-    TRY(ensure(c, c->chunk_start, sizeof(uint32_t) * ((K + 63) / 64 + 1)));
+    TRY(ensure(c, c->chunk_start, sizeof(uint32_t) * (emit_chunks((int64_t)K) + 1)));
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
     const int npass = (tile_bits + 7) / 8;
@@ -722,7 +724,7 @@ a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
     if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend before a3fr_bin_sort");
     if (!rgb) return fail(c, A3FR_EINVAL, "rgb_dev is NULL");
     unsigned long long *pairs = nullptr;
-    if (c->profiling) {
+    if (c->profiling && c->count_pairs) {
         TRY(ensure(c, c->pair_count, 16));
         pairs = P<unsigned long long>(c->pair_count);
         if (!c->pairs_armed) {

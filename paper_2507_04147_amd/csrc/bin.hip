@@ -470,77 +470,92 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
     y0 = (int)((r >> 32) & 0xffff); y1 = (int)((r >> 48) & 0xffff);
 }
 
+// Key chunks of kEmitChunk consecutive keys: chunk c starts inside the entry
+// (depth order) whose key range holds key c * kEmitChunk.
+constexpr int kEmitChunk = 1024;
+constexpr int kEmitBlock = 256;
+
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
                                                       uint32_t *__restrict__ chunk_start, int64_t nchunks) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent) return;
-    const uint32_t lo = offsets[j], hi = offsets[j + 1];
-    for (uint32_t c = (lo + 63) >> 6; ((uint64_t)c << 6) < hi && (int64_t)c < nchunks; ++c) chunk_start[c] = (uint32_t)j;
+    const uint64_t lo = offsets[j], hi = offsets[j + 1];
+    for (uint64_t c = (lo + kEmitChunk - 1) / kEmitChunk; c * kEmitChunk < hi && (int64_t)c < nchunks; ++c)
+        chunk_start[c] = (uint32_t)j;
 }
 
-__global__ void __launch_bounds__(64) k_emit(const DevView *__restrict__ views, int64_t n,
-                                             const uint32_t *__restrict__ ent, const uint32_t *n_ent,
-                                             const uint32_t *__restrict__ offsets,
-                                             const uint32_t *__restrict__ chunk_start,
-                                             const uint64_t *__restrict__ rect,
-                                             const uint16_t *__restrict__ row_prefix,
-                                             const uint16_t *__restrict__ row_list, const uint32_t *__restrict__ cum,
-                                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t K,
-                                             const uint32_t *K_dev) {
-    __shared__ uint32_t s_off[65];
-    const int lane = threadIdx.x;
-    const int64_t q0 = (int64_t)blockIdx.x * 64;
+// One block per chunk of kEmitChunk keys, kEmitChunk / kEmitBlock keys per
+// thread at a stride of kEmitBlock (coalesced stores).  The chunk's keys
+// belong to at most kEmitChunk consecutive entries (each entry has at least
+// one key), whose offsets are staged in LDS; each key finds its entry there by
+// bisection, then its tile: the r-th tile of the entry's rectangle, row-major,
+// counting only active tiles in a masked view.
+__global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__ views, int64_t n,
+                                                     const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                                     const uint32_t *__restrict__ offsets,
+                                                     const uint32_t *__restrict__ chunk_start,
+                                                     const uint64_t *__restrict__ rect,
+                                                     const uint16_t *__restrict__ row_prefix,
+                                                     const uint16_t *__restrict__ row_list,
+                                                     const uint32_t *__restrict__ cum, uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ vals, int64_t K, const uint32_t *K_dev) {
+    __shared__ uint32_t s_off[kEmitChunk + 1];
+    const int tid = threadIdx.x;
+    const int64_t q0 = (int64_t)blockIdx.x * kEmitChunk;
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode: the device count, clamped
-    if (q0 >= K) return;
+    if (q0 >= K) return;                           // block-uniform
     const int64_t E = *n_ent;
-    const uint32_t j0 = chunk_start[blockIdx.x];
-    {
-        const int64_t jj = (int64_t)j0 + lane;
-        s_off[lane] = offsets[jj < E ? jj : E];
-        if (lane == 0) s_off[64] = offsets[(int64_t)j0 + 64 < E ? (int64_t)j0 + 64 : E];
+    const int64_t j0 = chunk_start[blockIdx.x];
+    // s_off[t] = offsets[j0 + t] (offsets[E], the key total, past the last entry):
+    // s_off[0] <= q0 and s_off[kEmitChunk] > q0 + kEmitChunk - 1
+    for (int t = tid; t <= kEmitChunk; t += kEmitBlock) {
+        const int64_t jj = j0 + t;
+        s_off[t] = offsets[jj < E ? jj : E];
     }
     __syncthreads();
-    const int64_t q = q0 + lane;
-    if (q >= K) return;
-    // largest k with s_off[k] <= q (s_off[0] <= q0 <= q < s_off[64] or = K)
-    int lo = 0, hi = 64;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((int64_t)s_off[mid] <= q) lo = mid; else hi = mid;
-    }
-    const int64_t j = (int64_t)j0 + lo;
-    const uint32_t r = (uint32_t)(q - s_off[lo]);
-    const int64_t e = ent[j];
-    const int v = (int)(e / n);
-    const DevView &dv = views[v];
-    const uint32_t i = (uint32_t)(e - (int64_t)v * n);
-    int x0, x1, y0, y1;
-    unpack_rect(rect[e], x0, x1, y0, y1);
-    const int TX = dv.tiles_x;
-    int tx, ty;
-    if (dv.v.mask == A3FR_MASK_ALL) {
-        const uint32_t w = (uint32_t)(x1 - x0 + 1);
-        ty = y0 + (int)(r / w);
-        tx = x0 + (int)(r % w);
-    } else {
-        const uint32_t *cm = cum + dv.cum_off;
-        const int stride = TX + 1;
-        // keys of this entry in rows < y: (cm[y][x1+1] - cm[y][x0]) - base
-        const uint32_t base = cm[(int64_t)y0 * stride + x1 + 1] - cm[(int64_t)y0 * stride + x0];
-        int a = y0, b = y1 + 1;  // row ty: largest y in [y0, y1] with count(rows < y) <= r
-        while (b - a > 1) {
-            const int mid = (a + b) >> 1;
-            const uint32_t before = cm[(int64_t)mid * stride + x1 + 1] - cm[(int64_t)mid * stride + x0] - base;
-            if (before <= r) a = mid; else b = mid;
+#pragma unroll
+    for (int k = 0; k < kEmitChunk / kEmitBlock; ++k) {
+        const int64_t q = q0 + (int64_t)k * kEmitBlock + tid;
+        if (q >= K) break;
+        // largest t with s_off[t] <= q
+        int lo = 0, hi = kEmitChunk;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((int64_t)s_off[mid] <= q) lo = mid; else hi = mid;
         }
-        ty = a;
-        const uint32_t before = cm[(int64_t)ty * stride + x1 + 1] - cm[(int64_t)ty * stride + x0] - base;
-        const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * stride;
-        const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * stride;
-        tx = rl[rp[x0] + (r - before)];
+        const uint32_t r = (uint32_t)(q - s_off[lo]);
+        const int64_t e = ent[j0 + lo];
+        const int v = (int)(e / n);
+        const DevView &dv = views[v];
+        const uint32_t i = (uint32_t)(e - (int64_t)v * n);
+        int x0, x1, y0, y1;
+        unpack_rect(rect[e], x0, x1, y0, y1);
+        const int TX = dv.tiles_x;
+        int tx, ty;
+        if (dv.v.mask == A3FR_MASK_ALL) {
+            const uint32_t w = (uint32_t)(x1 - x0 + 1);
+            ty = y0 + (int)(r / w);
+            tx = x0 + (int)(r % w);
+        } else {
+            const uint32_t *cm = cum + dv.cum_off;
+            const int stride = TX + 1;
+            // keys of this entry in rows < y: (cm[y][x1+1] - cm[y][x0]) - base
+            const uint32_t base = cm[(int64_t)y0 * stride + x1 + 1] - cm[(int64_t)y0 * stride + x0];
+            int a = y0, b = y1 + 1;  // row ty: largest y in [y0, y1] with count(rows < y) <= r
+            while (b - a > 1) {
+                const int mid = (a + b) >> 1;
+                const uint32_t before = cm[(int64_t)mid * stride + x1 + 1] - cm[(int64_t)mid * stride + x0] - base;
+                if (before <= r) a = mid; else b = mid;
+            }
+            ty = a;
+            const uint32_t before = cm[(int64_t)ty * stride + x1 + 1] - cm[(int64_t)ty * stride + x0] - base;
+            const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * stride;
+            const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * stride;
+            tx = rl[rp[x0] + (r - before)];
+        }
+        keys[q] = (uint32_t)dv.tile_off + (uint32_t)(ty * TX + tx);
+        vals[q] = i;
     }
-    keys[q] = (uint32_t)dv.tile_off + (uint32_t)(ty * TX + tx);
-    vals[q] = i;
 }
 
 // cum[v][ty][tx] for masked views: active tiles in rows < ty and columns < tx.
@@ -590,15 +605,17 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
+int64_t emit_chunks(int64_t K) { return (K + kEmitChunk - 1) / kEmitChunk; }
+
 void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev, hipStream_t s) {
     if (m == 0 || K == 0) return;
-    const int64_t nchunks = (K + 63) / 64;
+    const int64_t nchunks = emit_chunks(K);
     hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start,
                        nchunks);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(64), 0, s, views, n, ent, n_ent, offsets,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, n, ent, n_ent, offsets,
                        chunk_start, rect, row_prefix, row_list, cum, keys, vals, K, K_dev);
 }
 

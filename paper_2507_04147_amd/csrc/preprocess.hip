@@ -220,6 +220,14 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                                 cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
                             }
                         }
+                    }
+                    // Only entries that emit keys are read downstream, except in a
+                    // view whose mask may grow later (remask): there every visible
+                    // entry keeps its rectangle and record for the recount.  In the
+                    // masked layers most visible Gaussians touch no active tile, so
+                    // this drops most of their stores.
+                    if (visible && (cnt != 0 || dv.remask)) {
+                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
                         depth[slot] = __float_as_uint((float)p2);
                         rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
                                      ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);

@@ -60,12 +60,15 @@ def compare_stage_outputs(ctx, ref, views, n):
     counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(nv, n)
     vis = ref["vis"].astype(bool)
     np.testing.assert_array_equal(counts, ref["count"].astype(np.uint32) * vis)
+    # depth and rectangle are stored for the entries that emit keys (in a view
+    # with every tile active, every visible entry)
+    emits = vis & (ref["count"] > 0)
     depth = _u(ctx.inspect("depth", torch.int32), np.uint32).reshape(nv, n)
-    np.testing.assert_array_equal(depth[vis], ref["depth_bits"][vis])
+    np.testing.assert_array_equal(depth[emits], ref["depth_bits"][emits])
     rect = _u(ctx.inspect("rect", torch.int64), np.uint64).reshape(nv, n)
     r = ref["rect"].astype(np.uint64)
     want = r[..., 0] | (r[..., 1] << np.uint64(16)) | (r[..., 2] << np.uint64(32)) | (r[..., 3] << np.uint64(48))
-    np.testing.assert_array_equal(rect[vis], want[vis])
+    np.testing.assert_array_equal(rect[emits], want[emits])
     act = ctx.inspect("active", torch.uint8).cpu().numpy()
     np.testing.assert_array_equal(act, ref["active"])
     if any(v.select for v in views):
@@ -331,8 +334,9 @@ def test_full_size_foveated_frame(pkg, ctx):
     counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(6, n)
     vis = ref["vis"].astype(bool)
     np.testing.assert_array_equal(counts, ref["count"].astype(np.uint32) * vis)
+    emits = vis & (ref["count"] > 0)
     depth = _u(ctx.inspect("depth", torch.int32), np.uint32).reshape(6, n)
-    np.testing.assert_array_equal(depth[vis], ref["depth_bits"][vis])
+    np.testing.assert_array_equal(depth[emits], ref["depth_bits"][emits])
     keep = ctx.inspect("keep", torch.uint8).cpu().numpy().reshape(6, n)
     np.testing.assert_array_equal(keep[[2, 5]], ref["keep"][[2, 5]])
     np.testing.assert_array_equal(_u(ctx.inspect("sorted_keys", torch.int64), np.uint64), ref["sorted_keys"])
