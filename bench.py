@@ -158,6 +158,16 @@ def main():
     ds = pkg.DeviceScene.from_host(scene)
     fov = pkg.fovea_struct(*rad, keep=synth.PERIPH_KEEP)
     ctx = pkg.Context()
+    # the method's frame: periphery through the learned upsampler (seeded
+    # initialisation; its training is the upsampler-training leg and the
+    # tests), per-tile error estimate with full-resolution fallback
+    theta = torch.from_numpy(synth.net_init(42)).cuda()
+
+    def method_options(c):
+        c.set_upsampler(theta)
+        c.set_fallback(*pkg.FALLBACK_DEFAULT)
+
+    method_options(ctx)
     out_f = torch.empty((2, 3, H, W), device="cuda")
     out_r = torch.empty((2, 3, H, W), device="cuda")
     log(f"scene ready in {time.time() - t0:.1f}s: {scene.n} Gaussians, {W}x{H} per eye")
@@ -203,6 +213,7 @@ def main():
         ctx.render_foveated(ds, cams, gaze, fov, out_f)
         keys = ctx.get_counts()["n_keys"]
         ctxg = pkg.Context()
+        method_options(ctxg)
         out_g = torch.empty_like(out_f)
         ctxg.graph_capture(ds, cams, gaze, fov, out_g, int(keys * 1.25) + 1024)
         for _ in range(args.warmup):
@@ -283,6 +294,10 @@ def main():
         sh_bytes = 4 * int(np.prod(scene.sh.shape[:-1]))  # [coef][channel][n]
         hbm_stage("colour", n_ent * (COLOUR_BYTES_PER_ENTRY - 192 + sh_bytes))
         hbm_stage("emit", EMIT_BYTES_PER_ENTRY * n_ent + EMIT_BYTES_PER_KEY * K)
+        if st["net"]["launches"]:
+            flop = net_frame_flop(np, W, H, gaze, rad[1])
+            tf = flop / (st["net"]["ms"] / args.steps / 1000.0) / 1e12
+            stages["net"].update(bound="mfma", achieved_TFLOPs=tf, frac=tf / BF16_MFMA_PEAK_TF, flop_per_frame=flop)
         # dominant kernel: the single-kernel stage with the most time per frame
         cand = [s_ for s_ in ("sort_pass", "blend", "preprocess", "colour") if "bound" in stages.get(s_, {})]
         dom = max(cand, key=lambda s_: stages[s_]["ms_per_frame"])
@@ -304,8 +319,7 @@ def main():
     training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 else None
     extra = {}
     if do_fov and do_frr and not args.no_extra:
-        extra["upsampler"] = net_leg(pkg, synth, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed)
-        extra["fallback"] = fallback_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed)
+        extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options)
         extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
         extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
@@ -340,9 +354,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "foveated stereo frame: 1M-Gaussian uniform cloud over [-5,5]^3, 2 eyes x 1832x1920, "
-                        "fovea r=0.15W full res, mid r=0.35W at 1/2, periphery at 1/4 with top-30% subset",
+                        "fovea r=0.15W full res, mid r=0.35W at 1/2, periphery at 1/4 with top-30% subset, "
+                        "periphery through the learned x4 upsampler, per-tile error estimate with "
+                        "full-resolution fallback",
             "gaussians": scene.n, "width": W, "height": H, "eyes": 2, "gaze": "image centre",
-            "key_path": "f64", "blend": "f32",
+            "key_path": "f64", "blend": "f32", "upsampler": "bf16 MFMA, f32 accumulate",
+            "fallback": list(pkg.FALLBACK_DEFAULT),
         },
         "full_res_fps": 1000.0 / ms_r if do_frr else None,
         "full_res_ms": ms_r,
@@ -351,6 +368,7 @@ def main():
         "periphery_psnr_db_per_eye": psnr,
         "outer_psnr_db_per_eye": psnr_outer,
         "keys_foveated": counts.get("n_keys"),
+        "fallback_tiles": counts.get("n_fallback_tiles"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": stages,
@@ -376,54 +394,55 @@ def _psnr_outside_fovea(ctx, W, H, gaze, rad, out, ref):
     return vals
 
 
-def net_leg(pkg, synth, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed):
-    """The foveated frame with the periphery through the learned upsampler
-    (parameters: the seeded initialisation; the trained network's quality is
-    measured by the tests and by the training leg)."""
-    W, H = cams[0].width, cams[0].height
-    theta = torch.from_numpy(synth.net_init(42)).cuda()
-    out = torch.empty((2, 3, H, W), device="cuda")
-    ctx.set_upsampler(theta)
-    step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
-    for _ in range(args.warmup):
-        step()
-    ms = timed(step, args.steps)
-    ctx.set_profiling(True, count_pairs=False)
-    timed(step, args.steps)
-    prof = ctx.get_profile()
-    ctx.set_profiling(False)
-    ctx.set_upsampler(None)
-    net = prof["stages"]["net"]
-    per_frame = net["ms"] / args.steps
-    flop = 2 * (H // 4) * (W // 4) * NET_FLOP_PER_INPUT_PIXEL
-    tf = flop / (per_frame / 1000.0) / 1e12
-    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
-    log(f"foveated frame with the upsampler {ms:.3f} ms; net {per_frame:.3f} ms/frame = {tf:.1f} TFLOP/s")
-    return dict(ms_per_frame=ms, net_ms_per_frame=per_frame, flop_per_frame=flop, achieved_TFLOPs=tf,
-                peak_TFLOPs=BF16_MFMA_PEAK_TF, frac=tf / BF16_MFMA_PEAK_TF, periphery_psnr_db=min(psnr),
-                weights="seeded initialisation (last layer x 0.01)")
+def net_frame_flop(np, W, H, gaze, r_mid):
+    """Multiply-add FLOPs the upsampler must spend on one stereo frame: layer 3
+    on every quarter-resolution pixel whose x4 block has a pixel centre outside
+    r_mid (the composite's periphery), layers 2 and 1 on those pixels widened by
+    one and two pixels (their receptive field)."""
+    h, w = H // 4, W // 4
+    total = 0
+    for gx, gy in gaze:
+        # farthest full-resolution pixel centre of each x4 block from the gaze
+        fx = np.maximum(np.abs(4.0 * np.arange(w) + 0.5 - gx), np.abs(4.0 * np.arange(w) + 3.5 - gx))
+        fy = np.maximum(np.abs(4.0 * np.arange(h) + 0.5 - gy), np.abs(4.0 * np.arange(h) + 3.5 - gy))
+        need = (fy[:, None] ** 2 + fx[None, :] ** 2) > r_mid * r_mid
+        n3 = int(need.sum())
+        grown = need.copy()
+        counts = []
+        for _ in range(2):
+            g = grown.copy()
+            g[1:, :] |= grown[:-1, :]; g[:-1, :] |= grown[1:, :]
+            g2 = g.copy()
+            g2[:, 1:] |= g[:, :-1]; g2[:, :-1] |= g[:, 1:]
+            grown = g2
+            counts.append(int(grown.sum()))
+        n2, n1 = counts
+        total += 2 * 9 * (3 * 32 * n1 + 32 * 32 * n2 + 32 * 48 * n3)
+    return total
 
 
-def fallback_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed):
+def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options):
+    """The foveated frame without each of the method's additions: bilinear
+    periphery without the error estimate, with the upsampler only, with the
+    estimate only (ms per frame and periphery PSNR)."""
     W, H = cams[0].width, cams[0].height
     out = torch.empty((2, 3, H, W), device="cuda")
-    ctx.set_fallback(*pkg.FALLBACK_DEFAULT)
-    step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
-    for _ in range(args.warmup):
-        step()
-    ms = timed(step, args.steps)
-    ctx.set_profiling(True, count_pairs=False)
-    timed(step, args.steps)
-    prof = ctx.get_profile()
-    ctx.set_profiling(False)
-    fb_ms = prof["stages"]["fallback"]["ms"] / args.steps
-    n_fb = ctx.get_counts()["n_fallback_tiles"]
-    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
-    ctx.set_fallback(float("inf"), 1.0, 1.0)
-    log(f"foveated frame with the fallback estimate {ms:.3f} ms (estimate {fb_ms:.3f} ms), {n_fb} fallback tiles, "
-        f"PSNR {min(psnr):.2f} dB")
-    return dict(ms_per_frame=ms, estimate_ms_per_frame=fb_ms, fallback_tiles=n_fb, periphery_psnr_db=min(psnr),
-                setting=list(pkg.FALLBACK_DEFAULT))
+    res = {}
+    for name, net, fb in (("bilinear_no_fallback", False, False), ("upsampler_only", True, False),
+                          ("fallback_only", False, True)):
+        method_options(ctx)
+        if not net:
+            ctx.set_upsampler(None)
+        if not fb:
+            ctx.set_fallback(float("inf"), 1.0, 1.0)
+        step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
+        for _ in range(args.warmup):
+            step()
+        ms = timed(step, args.steps)
+        res[name] = dict(ms_per_frame=ms, periphery_psnr_db=min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)))
+        log(f"frame {name}: {ms:.3f} ms")
+    method_options(ctx)
+    return res
 
 
 def net_train_leg(pkg, synth, torch, np, ctx, ds, n_pairs=2048, epochs=2, batch=32):

@@ -72,9 +72,18 @@ struct NetConvArgs {
     const uint16_t *mask;     // input gradient: NHWC bf16 activation whose sign masks the result
     uint16_t *out;            // NHWC bf16 (nullable)
     uint16_t *out_chw;        // zero-bordered channel-major copy (nullable)
-    const float *img_in;      // last layer: float32 planar input (bilinear residual)
-    float *img_out;           // last layer: float32 planar output [B][3][4h][4w]
+    const float *img_in;      // last layer: float32 planar input (bilinear residual), batch stride img_bstride
+    float *img_out;           // last layer: float32 planar output [B][3][4h][4w], batch stride out_bstride
+    int64_t img_bstride, out_bstride;  // floats between batch items (0: 3 h w and 3 (4h)(4w))
     int B, h, w;
+    int rows;                 // image rows per block (forward launches)
+    // frame mode (the periphery of a foveated frame, batch item b = eye b): the gaze
+    // of item b is gv[b * gv_stride].v.gx / gy; waves whose pixels (with the
+    // layer's halo) all lie within r_mid of the gaze are skipped, and the last
+    // layer writes only output pixels outside r_mid (the composite's periphery)
+    const DevView *gv;        // nullable: frame mode off
+    int gv_stride;
+    double rm;
 };
 struct NetWgradArgs {
     const uint16_t *g;        // channel-major zero-bordered bf16 gradient, NOUT channels
@@ -114,12 +123,16 @@ void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16
                      hipStream_t s, const uint32_t *skip_if_zero = nullptr /* device count: 0 skips */);
 void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
                         int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s);
-int sort_partitions(int64_t n);
-int64_t sort_workspace_words(int64_t n_max, int npass);
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
-                         hipStream_t s);
+// keys per thread of the onesweep passes: 16 (8192-key partitions) for the
+// tile-id sort, 4 (2048-key partitions) for the entry depth sort
+constexpr int kSortItemsLarge = 16;
+constexpr int kSortItemsSmall = 4;
+int sort_partitions(int64_t n, int items);
+int64_t sort_workspace_words(int64_t n_max, int npass, int items);
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
+                         uint32_t *ws, hipStream_t s);
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
+                      int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
                    hipStream_t s);
 // forward blend: variants (LDS batch depth x lane pixel block x schedule), all bit-identical
@@ -153,7 +166,8 @@ void launch_activate(const a3fr_params &p, float *scale, float *opacity, hipStre
 void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
                            const a3fr_grads &g, hipStream_t s);
 void launch_net_pack(const float *theta, const NetPacked &pk, hipStream_t s);
-void launch_net_input(const float *x, int B, int h, int w, uint16_t *nhwc, uint16_t *chw, hipStream_t s);
+void launch_net_input(const float *x, int64_t x_bstride, int B, int h, int w, uint16_t *nhwc, uint16_t *chw,
+                      hipStream_t s);
 void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a, hipStream_t s);
 void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s);
 void launch_net_mse(const float *out, const float *target, int B, int h, int w, uint16_t *g_nhwc, uint16_t *g_chw,
@@ -176,6 +190,7 @@ void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rec
                     uint32_t *counts, const uint32_t *n_flagged, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
+                      bool periph_done /* outside r_mid already written (unless fallback-flagged) */,
                       const uint8_t *fb_flags /* nullable: periphery tiles taken from fovea */, int fb_tiles_x,
                       const DevView *gaze_view /* nullable: read the gaze (v.gx, v.gy) from this device view */,
                       float *out, hipStream_t s);

@@ -57,7 +57,6 @@ struct a3fr_ctx {
     DevBuf net_pk, net_x0, net_x0c, net_a1, net_a1c, net_a2, net_a2c, net_g3, net_g3c, net_g2, net_g2c, net_g1c,
         net_sse;
     int net_B = 0, net_h = 0, net_w = 0;   // geometry of the channel-major copies (zero borders valid)
-    DevBuf periph_full;                    // upsampled periphery of each eye, [eyes][3][H][W]
     const float *net_theta = nullptr;      // a3fr_set_upsampler
     // full-resolution fallback of the periphery (a3fr_set_fallback)
     double fb_thr = INFINITY, fb_coef = 0.0, fb_pow = 1.0;
@@ -295,7 +294,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
-                      &c->net_g1c, &c->net_sse, &c->periph_full, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->fb_count, &c->blend_ws,
+                      &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->fb_count, &c->blend_ws,
                       &c->blend_order, &c->tune_img,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
@@ -481,7 +480,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_a, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4)));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4, kSortItemsSmall)));
 
     // ---- one upload through pinned staging: [views | row views | row ys | selecting views]
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -587,12 +586,12 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     }
     {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
         StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
-        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, P<uint32_t>(c->sort_status),
+        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, kSortItemsSmall, P<uint32_t>(c->sort_status),
                             c->stream);
         uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
         uint32_t *vi = P<uint32_t>(c->ent_a), *vo = P<uint32_t>(c->ent_b);
         for (int p = 0; p < 4; ++p) {
-            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, p, P<uint32_t>(c->sort_status),
+            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, kSortItemsSmall, p, P<uint32_t>(c->sort_status),
                              sc_err(c->scalars), c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
@@ -635,7 +634,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
     const int npass = (tile_bits + 7) / 8;
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass)));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass, kSortItemsLarge)));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
     if (cap_mode) launch_clamp_keys(sc_key_total(c->scalars), c->capacity, sc_n_keys(c->scalars), sc_err(c->scalars),
@@ -659,11 +658,12 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (K > 1) {
         {
             StageTimer t_(c, A3FR_STAGE_SORT_HIST);
-            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, P<uint32_t>(c->sort_status), c->stream);
+            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, kSortItemsLarge, P<uint32_t>(c->sort_status),
+                                c->stream);
         }
         for (int p = 0; p < npass; ++p) {
             StageTimer t_(c, A3FR_STAGE_SORT_PASS);
-            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, npass, p,
+            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, npass, kSortItemsLarge, p,
                              P<uint32_t>(c->sort_status), sc_err(c->scalars), c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
@@ -849,8 +849,51 @@ a3fr_status a3fr_composite(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, const
         return fail(c, A3FR_EINVAL, "composite: layer scales too large for the image");
     StageTimer t_(c, A3FR_STAGE_COMPOSITE);
     launch_composite(W, H, g.x, g.y, f->r_fovea, f->r_mid, fov, mid, f->scale_mid, per, f->scale_periph, per_full,
-                     nullptr, 0, nullptr, out, c->stream);
+                     false, nullptr, 0, nullptr, out, c->stream);
     return check_launch(c, "composite");
+}
+
+static NetPacked net_packed(a3fr_ctx *c);
+static a3fr_status net_check_geom(a3fr_ctx *c, int B, int h, int w);
+constexpr int kNetFrameRows = 2;  // image rows per block of the frame's convolutions
+
+// The upsampler on the periphery layers of a foveated frame, all eyes in one
+// batch (frame mode of the convolutions): layer images of eye e sit at a
+// constant distance from eye 0's (every eye has the same layer sizes);
+// waves whose receptive field lies within r_mid are skipped and only pixels
+// outside r_mid are written to out, where the composite leaves them.
+static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n_eyes, double r_mid, const float *L,
+                                     float *out) {
+    const int W = cams[0].width, H = cams[0].height;
+    for (int e = 1; e < n_eyes; ++e)
+        if (cams[e].width != W || cams[e].height != H)
+            return fail(c, A3FR_EINVAL, "render_foveated: the upsampler needs every eye at the same image size");
+    const int h = H / 4, w = W / 4;
+    TRY(net_check_geom(c, n_eyes, h, w));
+    const int64_t in_stride = n_eyes > 1 ? 3 * (c->hviews[5].img_off - c->hviews[2].img_off) : 3 * (int64_t)h * w;
+    const int64_t px = (int64_t)n_eyes * h * w;
+    TRY(ensure(c, c->net_pk, sizeof(uint16_t) * kNetPackedElems));
+    TRY(ensure(c, c->net_x0, sizeof(uint16_t) * 8 * px));
+    TRY(ensure(c, c->net_a1, sizeof(uint16_t) * 32 * px));
+    TRY(ensure(c, c->net_a2, sizeof(uint16_t) * 32 * px));
+    c->net_trained_fwd = false;
+    const float *theta = c->net_theta;
+    const NetPacked pk = net_packed(c);
+    const float *in = L + 3 * c->hviews[2].img_off;
+    launch_net_pack(theta, pk, c->stream);
+    launch_net_input(in, in_stride, n_eyes, h, w, P<uint16_t>(c->net_x0), nullptr, c->stream);
+    NetConvArgs a{};
+    a.B = n_eyes; a.h = h; a.w = w;
+    a.rows = kNetFrameRows;
+    a.gv = P<DevView>(c->views); a.gv_stride = 3; a.rm = r_mid;
+    a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1; a.out = P<uint16_t>(c->net_a1);
+    launch_net_conv(1, false, a, c->stream);
+    a.in = P<uint16_t>(c->net_a1); a.wpk = pk.f2; a.bias = theta + kNetB2; a.out = P<uint16_t>(c->net_a2);
+    launch_net_conv(2, false, a, c->stream);
+    a.in = P<uint16_t>(c->net_a2); a.wpk = pk.f3; a.bias = theta + kNetB3; a.out = nullptr;
+    a.img_in = in; a.img_bstride = in_stride; a.img_out = out; a.out_bstride = 3 * (int64_t)W * H;
+    launch_net_conv(3, false, a, c->stream);
+    return check_launch(c, "upsampler");
 }
 
 a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams,
@@ -878,30 +921,23 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
     float *L = P<float>(c->layers);
     TRY(a3fr_blend(c, L, nullptr, nullptr));
-    float *pf = nullptr;
-    if (c->net_theta) {
-        int64_t tot = 0;
-        for (int e = 0; e < n_eyes; ++e) tot += 3 * (int64_t)cams[e].width * cams[e].height;
-        TRY(ensure(c, c->periph_full, sizeof(float) * (size_t)tot));
-        pf = P<float>(c->periph_full);
+    const bool net = c->net_theta != nullptr;
+    if (net) {
+        // the network writes the periphery (outside r_mid) of every eye straight into out
+        StageTimer t_(c, A3FR_STAGE_NET);
+        TRY(net_frame_forward(c, cams, n_eyes, f->r_mid, L, out));
     }
-    int64_t pf_off = 0;
+    int64_t o_off = 0;
     for (int e = 0; e < n_eyes; ++e) {
         const DevView &d0 = c->hviews[3 * e], &d1 = c->hviews[3 * e + 1], &d2 = c->hviews[3 * e + 2];
         const int W = cams[e].width, H = cams[e].height;
-        const float *per_full = nullptr;
-        if (pf) {
-            StageTimer t_(c, A3FR_STAGE_NET);
-            TRY(a3fr_net_forward(c, c->net_theta, L + 3 * d2.img_off, 1, H / 4, W / 4, pf + pf_off, 0));
-            per_full = pf + pf_off;
-            pf_off += 3 * (int64_t)W * H;
-        }
         StageTimer t_(c, A3FR_STAGE_COMPOSITE);
         launch_composite(W, H, gaze[e].x, gaze[e].y, f->r_fovea, f->r_mid, L + 3 * d0.img_off, L + 3 * d1.img_off,
-                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph, per_full,
+                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph, nullptr, net,
                          c->fb_last ? P<uint8_t>(c->fb_flags) + d2.tile_off : nullptr, d2.tiles_x,
-                         P<DevView>(c->views) + 3 * e, out + (int64_t)e * 3 * W * H, c->stream);
+                         P<DevView>(c->views) + 3 * e, out + o_off, c->stream);
         TRY(check_launch(c, "composite"));
+        o_off += 3 * (int64_t)W * H;
     }
     return A3FR_OK;
 }
@@ -1019,7 +1055,7 @@ a3fr_status a3fr_net_forward(a3fr_ctx *c, const float *theta, const float *in, i
     c->net_trained_fwd = false;
     const NetPacked pk = net_packed(c);
     launch_net_pack(theta, pk, c->stream);
-    launch_net_input(in, B, h, w, P<uint16_t>(c->net_x0), train ? P<uint16_t>(c->net_x0c) : nullptr, c->stream);
+    launch_net_input(in, 0, B, h, w, P<uint16_t>(c->net_x0), train ? P<uint16_t>(c->net_x0c) : nullptr, c->stream);
     NetConvArgs a{};
     a.B = B; a.h = h; a.w = w;
     a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1;

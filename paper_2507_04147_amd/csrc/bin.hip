@@ -487,9 +487,16 @@ __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, con
 // One block per chunk of kEmitChunk keys, kEmitChunk / kEmitBlock keys per
 // thread at a stride of kEmitBlock (coalesced stores).  The chunk's keys
 // belong to at most kEmitChunk consecutive entries (each entry has at least
-// one key), whose offsets are staged in LDS; each key finds its entry there by
-// bisection, then its tile: the r-th tile of the entry's rectangle, row-major,
-// counting only active tiles in a masked view.
+// one key); their key offsets, Gaussian indices, views and rectangles are
+// staged in LDS first (all loads of the block in flight together).  A key then
+// finds its entry by bisection in LDS and its tile as the r-th tile of the
+// entry's rectangle, row-major: directly when every tile of the rectangle is
+// active (a view with all tiles active, or a rectangle inside the mask), else
+// by bisection over the rows with the view's 2D active-tile prefix and the
+// row's list of active columns.  The four keys of a thread advance through
+// each bisection step together, so their dependent loads overlap.
+constexpr int kEmitPer = kEmitChunk / kEmitBlock;
+
 __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__ views, int64_t n,
                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
                                                      const uint32_t *__restrict__ offsets,
@@ -500,12 +507,16 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
                                                      const uint32_t *__restrict__ cum, uint32_t *__restrict__ keys,
                                                      uint32_t *__restrict__ vals, int64_t K, const uint32_t *K_dev) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
+    __shared__ uint32_t s_i[kEmitChunk];
+    __shared__ uint32_t s_v[kEmitChunk];
+    __shared__ uint64_t s_rect[kEmitChunk];
     const int tid = threadIdx.x;
     const int64_t q0 = (int64_t)blockIdx.x * kEmitChunk;
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode: the device count, clamped
     if (q0 >= K) return;                           // block-uniform
     const int64_t E = *n_ent;
     const int64_t j0 = chunk_start[blockIdx.x];
+    const int64_t qend = q0 + kEmitChunk < K ? q0 + kEmitChunk : K;
     // s_off[t] = offsets[j0 + t] (offsets[E], the key total, past the last entry):
     // s_off[0] <= q0 and s_off[kEmitChunk] > q0 + kEmitChunk - 1
     for (int t = tid; t <= kEmitChunk; t += kEmitBlock) {
@@ -513,49 +524,102 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         s_off[t] = offsets[jj < E ? jj : E];
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kEmitChunk / kEmitBlock; ++k) {
-        const int64_t q = q0 + (int64_t)k * kEmitBlock + tid;
-        if (q >= K) break;
-        // largest t with s_off[t] <= q
-        int lo = 0, hi = kEmitChunk;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if ((int64_t)s_off[mid] <= q) lo = mid; else hi = mid;
+    // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E)
+    for (int t = tid; t < kEmitChunk; t += kEmitBlock) {
+        if ((int64_t)s_off[t] < qend) {
+            const int64_t e = ent[j0 + t];
+            const int v = (int)(e / n);
+            s_v[t] = (uint32_t)v;
+            s_i[t] = (uint32_t)(e - (int64_t)v * n);
+            s_rect[t] = rect[e];
         }
-        const uint32_t r = (uint32_t)(q - s_off[lo]);
-        const int64_t e = ent[j0 + lo];
-        const int v = (int)(e / n);
-        const DevView &dv = views[v];
-        const uint32_t i = (uint32_t)(e - (int64_t)v * n);
-        int x0, x1, y0, y1;
-        unpack_rect(rect[e], x0, x1, y0, y1);
-        const int TX = dv.tiles_x;
-        int tx, ty;
-        if (dv.v.mask == A3FR_MASK_ALL) {
-            const uint32_t w = (uint32_t)(x1 - x0 + 1);
-            ty = y0 + (int)(r / w);
-            tx = x0 + (int)(r % w);
-        } else {
-            const uint32_t *cm = cum + dv.cum_off;
-            const int stride = TX + 1;
-            // keys of this entry in rows < y: (cm[y][x1+1] - cm[y][x0]) - base
-            const uint32_t base = cm[(int64_t)y0 * stride + x1 + 1] - cm[(int64_t)y0 * stride + x0];
-            int a = y0, b = y1 + 1;  // row ty: largest y in [y0, y1] with count(rows < y) <= r
-            while (b - a > 1) {
-                const int mid = (a + b) >> 1;
-                const uint32_t before = cm[(int64_t)mid * stride + x1 + 1] - cm[(int64_t)mid * stride + x0] - base;
-                if (before <= r) a = mid; else b = mid;
-            }
-            ty = a;
-            const uint32_t before = cm[(int64_t)ty * stride + x1 + 1] - cm[(int64_t)ty * stride + x0] - base;
-            const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty * stride;
-            const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty * stride;
-            tx = rl[rp[x0] + (r - before)];
-        }
-        keys[q] = (uint32_t)dv.tile_off + (uint32_t)(ty * TX + tx);
-        vals[q] = i;
     }
+    __syncthreads();
+    int lo[kEmitPer], hi[kEmitPer];
+    int64_t q[kEmitPer];
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+        q[k] = q0 + (int64_t)k * kEmitBlock + tid;
+        lo[k] = 0;
+        hi[k] = kEmitChunk;
+    }
+    // largest t with s_off[t] <= q (kEmitChunk is a power of two: exact after log2 steps)
+#pragma unroll
+    for (int step = kEmitChunk; step > 1; step >>= 1) {
+#pragma unroll
+        for (int k = 0; k < kEmitPer; ++k) {
+            const int mid = (lo[k] + hi[k]) >> 1;
+            if ((int64_t)s_off[mid] <= q[k]) lo[k] = mid; else hi[k] = mid;
+        }
+    }
+    // keys past qend (last chunk, capacity mode) take entry 0, which is staged; nothing is stored for them
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k)
+        if (q[k] >= qend) lo[k] = 0;
+    // per key: entry fields, and the row search state for partially active rectangles
+    uint32_t r[kEmitPer], base[kEmitPer];
+    int x0[kEmitPer], x1[kEmitPer], y0[kEmitPer], y1[kEmitPer], ra[kEmitPer], rb[kEmitPer];
+    int tx[kEmitPer], ty[kEmitPer], TX[kEmitPer];
+    bool search[kEmitPer];
+    const uint32_t *cm[kEmitPer];
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+        const int t = lo[k];
+        r[k] = (uint32_t)(q[k] - s_off[t]);
+        unpack_rect(s_rect[t], x0[k], x1[k], y0[k], y1[k]);
+        const DevView &dv = views[s_v[t]];
+        TX[k] = dv.tiles_x;
+        const uint32_t w = (uint32_t)(x1[k] - x0[k] + 1);
+        const uint32_t cnt = s_off[t + 1] - s_off[t];
+        search[k] = q[k] < qend && dv.v.mask != A3FR_MASK_ALL && cnt != w * (uint32_t)(y1[k] - y0[k] + 1);
+        ty[k] = y0[k] + (int)(r[k] / w);
+        tx[k] = x0[k] + (int)(r[k] % w);
+        cm[k] = cum + (search[k] ? dv.cum_off : 0);
+        ra[k] = y0[k];
+        rb[k] = y1[k] + 1;
+        base[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k)
+        if (search[k]) {
+            const int64_t st = TX[k] + 1;
+            base[k] = cm[k][(int64_t)y0[k] * st + x1[k] + 1] - cm[k][(int64_t)y0[k] * st + x0[k]];
+        }
+    // row ty: largest y in [y0, y1] with (keys of the entry in rows < y) <= r
+    bool more = true;
+    while (more) {
+        more = false;
+#pragma unroll
+        for (int k = 0; k < kEmitPer; ++k)
+            if (search[k] && rb[k] - ra[k] > 1) {
+                const int64_t st = TX[k] + 1;
+                const int mid = (ra[k] + rb[k]) >> 1;
+                const uint32_t before = cm[k][(int64_t)mid * st + x1[k] + 1] - cm[k][(int64_t)mid * st + x0[k]] -
+                                        base[k];
+                if (before <= r[k]) ra[k] = mid; else rb[k] = mid;
+                more |= rb[k] - ra[k] > 1;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k)
+        if (search[k]) {
+            const int64_t st = TX[k] + 1;
+            const int t = lo[k];
+            const DevView &dv = views[s_v[t]];
+            ty[k] = ra[k];
+            const uint32_t before = cm[k][(int64_t)ty[k] * st + x1[k] + 1] - cm[k][(int64_t)ty[k] * st + x0[k]] -
+                                    base[k];
+            const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty[k] * st;
+            const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty[k] * st;
+            tx[k] = rl[rp[x0[k]] + (r[k] - before)];
+        }
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k)
+        if (q[k] < qend) {
+            const int t = lo[k];
+            keys[q[k]] = (uint32_t)views[s_v[t]].tile_off + (uint32_t)(ty[k] * TX[k] + tx[k]);
+            vals[q[k]] = s_i[t];
+        }
 }
 
 // cum[v][ty][tx] for masked views: active tiles in rows < ty and columns < tx.

@@ -452,6 +452,7 @@ __device__ __forceinline__ void bilinear_setup(int x, int s, int Wl, int &i0, in
 __global__ void k_composite(int W, int H, double gx, double gy, double rf, double rm,
                             const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
                             const float *__restrict__ periph, int sp, const float *__restrict__ periph_full,
+                            int periph_done,
                             const uint8_t *__restrict__ fb_flags, int fb_tiles_x, const DevView *gaze_view,
                             float *__restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,6 +475,7 @@ __global__ void k_composite(int W, int H, double gx, double gy, double rf, doubl
         for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = fovea[ch * HW + pix];
         return;
     }
+    if (reg == 2 && periph_done) return;  // already written by the upsampler
     if (reg == 2 && periph_full) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) out[ch * HW + pix] = periph_full[ch * HW + pix];
@@ -497,11 +499,12 @@ __global__ void k_composite(int W, int H, double gx, double gy, double rf, doubl
 }
 
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
-                      const float *mid, int sm, const float *periph, int sp, const float *periph_full,
+                      const float *mid, int sm, const float *periph, int sp, const float *periph_full, bool periph_done,
                       const uint8_t *fb_flags, int fb_tiles_x, const DevView *gaze_view, float *out, hipStream_t s) {
     if (W <= 0 || H <= 0) return;
     hipLaunchKernelGGL(k_composite, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, W, H, gx, gy,
-                       rf, rm, fovea, mid, sm, periph, sp, periph_full, fb_flags, fb_tiles_x, gaze_view, out);
+                       rf, rm, fovea, mid, sm, periph, sp, periph_full, (int)periph_done, fb_flags, fb_tiles_x, gaze_view,
+                       out);
 }
 
 // ------------------------------------------------------------------------

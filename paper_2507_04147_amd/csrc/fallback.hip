@@ -118,21 +118,30 @@ __global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restri
     for (int k = threadIdx.x; k < cells; k += blockDim.x) out[k] = sh[k];
 }
 
-// 256 threads per 64 cells: four slices of the partials per cell, summed in LDS.
+// 256 threads per 16 cells: sixteen slices of the partials per cell, each
+// summed by one thread (independent loads, no dependent chain), then the
+// slices summed in LDS.
 __global__ void __launch_bounds__(256) k_drop_reduce(const double *__restrict__ partials, int nparts, int cells,
                                                      double *__restrict__ diff) {
-    __shared__ double red[4][64];
-    const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + c;
+    __shared__ double red[16][16];
+    const int c = threadIdx.x & 15, slice = threadIdx.x >> 4;
+    const int k = blockIdx.x * 16 + c;
     double acc = 0.0;
     if (k < cells)
-        for (int g = slice; g < nparts; g += 4) acc += partials[(int64_t)g * cells + k];
+        for (int g = slice; g < nparts; g += 16) acc += partials[(int64_t)g * cells + k];
     red[slice][c] = acc;
     __syncthreads();
-    if (slice == 0 && k < cells) diff[k] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (slice == 0 && k < cells) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += red[q][c];
+        diff[k] = t;
+    }
 }
 
-int drop_energy_parts() { return 64; }
+// Persistent blocks of the mass maps: two per compute unit of the MI355X, so
+// each thread visits a few Gaussians and the dependent loads overlap.
+int drop_energy_parts() { return 512; }
 
 void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score, double *diff,
@@ -143,7 +152,7 @@ void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, 
         const int parts = drop_energy_parts();
         hipLaunchKernelGGL(k_drop_energy_lds, dim3(parts), dim3(256), lds, s, views, pv, n, counts, keep, rect, score,
                            cells, partials);
-        hipLaunchKernelGGL(k_drop_reduce, dim3((cells + 63) / 64), dim3(256), 0, s, partials, parts, cells, diff);
+        hipLaunchKernelGGL(k_drop_reduce, dim3((cells + 15) / 16), dim3(256), 0, s, partials, parts, cells, diff);
     } else if (n > 0) {
         hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, pv, n, counts,
                            keep, rect, score, diff);

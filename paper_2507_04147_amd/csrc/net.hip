@@ -82,8 +82,8 @@ __global__ void k_net_pack(const float *__restrict__ theta, NetPacked pk) {
 
 // FP32 planar [B][3][h][w] -> bf16 NHWC8 (channels 3..7 zero) and, if chw is
 // not NULL, the zero-bordered channel-major copy [B][8][h+2][WS].
-__global__ void k_net_input(const float *__restrict__ x, int B, int h, int w, uint16_t *__restrict__ nhwc,
-                            uint16_t *__restrict__ chw) {
+__global__ void k_net_input(const float *__restrict__ x, int64_t x_bstride, int B, int h, int w,
+                            uint16_t *__restrict__ nhwc, uint16_t *__restrict__ chw) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t HW = (int64_t)h * w;
     if (p >= (int64_t)B * HW) return;
@@ -91,7 +91,7 @@ __global__ void k_net_input(const float *__restrict__ x, int B, int h, int w, ui
     const int y = (int)(q / w), xx = (int)(q - (int64_t)y * w);
     uint16_t v[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) v[c] = c < 3 ? bf16_bits(x[(b * 3 + c) * HW + q]) : (uint16_t)0;
+    for (int c = 0; c < 8; ++c) v[c] = c < 3 ? bf16_bits(x[b * x_bstride + c * HW + q]) : (uint16_t)0;
     uint4 pk;
     pk.x = v[0] | ((uint32_t)v[1] << 16);
     pk.y = v[2] | ((uint32_t)v[3] << 16);
@@ -109,6 +109,18 @@ __global__ void k_net_input(const float *__restrict__ x, int B, int h, int w, ui
 // convolution (forward and input gradient)
 // ---------------------------------------------------------------------------
 enum { kEpiRelu = 0, kEpiShuffle = 1, kEpiMask = 2 };
+
+// Frame mode: true when every full-resolution pixel centre of the x4 blocks of
+// input pixels [xa, xb] x [ya, yb] (this layer's pixels widened by its halo)
+// lies within r_mid of the gaze, i.e. the composite takes none of them from the
+// periphery.  The region test is convex, so the four extreme centres decide;
+// a relative margin keeps rounding on the safe side (such waves are computed).
+__device__ __forceinline__ bool inside_mid(int xa, int xb, int ya, int yb, double gx, double gy, double rm) {
+    const double x0 = 4.0 * xa + 0.5 - gx, x1 = 4.0 * xb + 3.5 - gx;
+    const double y0 = 4.0 * ya + 0.5 - gy, y1 = 4.0 * yb + 3.5 - gy;
+    const double mx = fmax(x0 * x0, x1 * x1), my = fmax(y0 * y0, y1 * y1);
+    return mx + my <= rm * rm * (1.0 - 1e-12);
+}
 
 template <int KIN, int NOUT, int EPI>
 __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
@@ -130,10 +142,20 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     const int b = blockIdx.z;
     const int xs = blockIdx.x * 64 + wave * 16;  // this wave's 16 pixels
     if (xs >= w) return;
-    const int y0 = blockIdx.y * kRowsPerBlock;
+    const int y0 = blockIdx.y * a.rows;
     const uint16_t *in = a.in + (int64_t)b * h * w * KIN;
     const int WS = net_chw_stride(w);
-    for (int y = y0; y < y0 + kRowsPerBlock && y < h; ++y) {
+    // frame mode: halo of this layer's outputs in the last layer's pixels
+    constexpr int HALO = NOUT == 48 ? 0 : (KIN == 8 ? 2 : 1);
+    double gx = 0.0, gy = 0.0;
+    if (a.gv) {
+        gx = a.gv[(int64_t)b * a.gv_stride].v.gx;
+        gy = a.gv[(int64_t)b * a.gv_stride].v.gy;
+    }
+    for (int y = y0; y < y0 + a.rows && y < h; ++y) {
+        if (a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1), max(y - HALO, 0), min(y + HALO, h - 1),
+                               gx, gy, a.rm))
+            continue;  // wave-uniform
         floatx4 acc[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -167,8 +189,8 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
                 const float bias = a.bias[ch];
                 const int i = li >> 2, j = li & 3;
                 const int H4 = 4 * h, W4 = 4 * w;
-                const float *src = a.img_in + ((int64_t)b * 3 + nb) * h * w;
-                float *dst = a.img_out + ((int64_t)b * 3 + nb) * H4 * W4;
+                const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)nb * h * w;
+                float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)nb * H4 * W4;
                 const int Y = 4 * y + i;
                 float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
                 sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
@@ -187,7 +209,12 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
                         const float wx = sx - fx0;
                         const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
                         const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
-                        dst[(int64_t)Y * W4 + X] = (acc[nb][r] + bias) + ((1.0f - wy) * top + wy * bot);
+                        bool put = true;
+                        if (a.gv) {  // frame mode: only the composite's periphery (outside r_mid)
+                            const double dx = ((double)X + 0.5) - gx, dy = ((double)Y + 0.5) - gy;
+                            put = dx * dx + dy * dy > a.rm * a.rm;
+                        }
+                        if (put) dst[(int64_t)Y * W4 + X] = (acc[nb][r] + bias) + ((1.0f - wy) * top + wy * bot);
                     }
                 }
             } else {
@@ -357,15 +384,21 @@ void launch_net_pack(const float *theta, const NetPacked &pk, hipStream_t s) {
     hipLaunchKernelGGL(k_net_pack, dim3((9 * 48 * 32 + 255) / 256), dim3(256), 0, s, theta, pk);
 }
 
-void launch_net_input(const float *x, int B, int h, int w, uint16_t *nhwc, uint16_t *chw, hipStream_t s) {
+void launch_net_input(const float *x, int64_t x_bstride, int B, int h, int w, uint16_t *nhwc, uint16_t *chw,
+                      hipStream_t s) {
     const int64_t n = (int64_t)B * h * w;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_net_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, B, h, w, nhwc, chw);
+    if (x_bstride == 0) x_bstride = 3 * (int64_t)h * w;
+    hipLaunchKernelGGL(k_net_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, x_bstride, B, h, w, nhwc,
+                       chw);
 }
 
-void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)((a.h + kRowsPerBlock - 1) / kRowsPerBlock),
-                    (unsigned)a.B);
+void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a_in, hipStream_t s) {
+    NetConvArgs a = a_in;
+    if (a.rows <= 0) a.rows = kRowsPerBlock;
+    if (a.img_bstride == 0) a.img_bstride = 3 * (int64_t)a.h * a.w;
+    if (a.out_bstride == 0) a.out_bstride = 3 * (int64_t)(4 * a.h) * (4 * a.w);
+    const dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)((a.h + a.rows - 1) / a.rows), (unsigned)a.B);
     if (!dgrad) {
         if (layer == 1) hipLaunchKernelGGL((k_net_conv<8, 32, kEpiRelu>), grid, dim3(256), 0, s, a);
         else if (layer == 2) hipLaunchKernelGGL((k_net_conv<32, 32, kEpiRelu>), grid, dim3(256), 0, s, a);

@@ -29,14 +29,17 @@ namespace a3fr {
 
 constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;      // 8
-constexpr int kSortItems = 16;
-constexpr int kSortPart = kSortThreads * kSortItems;  // 8192 keys per partition
+// keys per thread (kSortItemsLarge / kSortItemsSmall): the entry depth sort's
+// few hundred thousand keys in 8192-key partitions would leave most compute
+// units idle with one long partition each, so it runs 2048-key partitions
 constexpr int kRadix = 256;
 constexpr int kDigitWaves = kRadix / kWave;           // waves holding one digit per lane
 constexpr int kMaxPasses = 4;                         // 32-bit keys
-constexpr int kSortBlocksPerCU = 2;                   // LDS ~74 KB per block
 
-int sort_partitions(int64_t n) { return (int)((n + kSortPart - 1) / kSortPart); }
+int sort_partitions(int64_t n, int items) {
+    const int64_t part = (int64_t)kSortThreads * items;
+    return (int)((n + part - 1) / part);
+}
 
 // Histograms of the npass low digits of n keys (n read from *n_dev).  Each
 // wave keeps its own LDS histograms; the block adds them to the global ones.
@@ -75,12 +78,14 @@ __device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
 // err: sticky flag set if a look-back wait exceeds its bound (never expected:
 // predecessors always publish; the bound turns a logic error into a report
 // instead of a hang).
+template <int kSortItems>
 __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                            const uint32_t *n_dev, int shift,
                                                            const uint32_t *__restrict__ ghist, uint32_t *status,
                                                            uint32_t *counter, uint32_t *err) {
+    constexpr int kSortPart = kSortThreads * kSortItems;
     __shared__ uint32_t s_part;
     __shared__ uint32_t s_wh[kSortWaves][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -92,6 +97,10 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
 
     const int64_t K = *n_dev;
     const int nparts = (int)((K + kSortPart - 1) / kSortPart);
+    // the grid is sized for the largest count; blocks beyond the partitions of
+    // this count leave without touching the shared partition counter (every
+    // partition is still taken: the lower blocks keep pulling until none is left)
+    if ((int)blockIdx.x >= nparts) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -246,14 +255,14 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
 
 // ws: one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256]
 // cleared by one fill, then the digit histograms of all passes.
-int64_t sort_workspace_words(int64_t n_max, int npass) {
-    return (int64_t)npass * kRadix + 8 + (int64_t)npass * sort_partitions(n_max) * kRadix;
+int64_t sort_workspace_words(int64_t n_max, int npass, int items) {
+    return (int64_t)npass * kRadix + 8 + (int64_t)npass * sort_partitions(n_max, items) * kRadix;
 }
 
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
-                         hipStream_t s) {
-    const int nparts = sort_partitions(n_max);
-    launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass), s);
+void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
+                         uint32_t *ws, hipStream_t s) {
+    const int nparts = sort_partitions(n_max, items);
+    launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass, items), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
     if (hblocks > 256) hblocks = 256;
@@ -261,20 +270,28 @@ void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_
 }
 
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
-    const int nparts = sort_partitions(n_max);
+                      int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
+    const int nparts = sort_partitions(n_max, items);
     if (nparts == 0) return;
     uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix, *status = ctr + 8;
-    static int resident = 0;
-    if (resident == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        resident = (cus > 0 ? cus : 256) * kSortBlocksPerCU;
     }
+    // persistent blocks: LDS per block ~74 KB (16 items) or ~26 KB (4 items)
+    const int resident = cus * (items == kSortItemsSmall ? 4 : 2);
     const int grid = nparts < resident ? nparts : resident;
-    hipLaunchKernelGGL(k_onesweep, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev, 8 * p,
-                       hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
+    if (items == kSortItemsSmall)
+        hipLaunchKernelGGL(k_onesweep<kSortItemsSmall>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
+                           n_dev, 8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p,
+                           err);
+    else
+        hipLaunchKernelGGL(k_onesweep<kSortItemsLarge>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
+                           n_dev, 8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p,
+                           err);
 }
 
 // ------------------------------------------------------------------------

@@ -135,11 +135,16 @@ def test_fallback_off_and_zero_network_leave_frame_unchanged(pkg):
     ctx.close()
 
 
-def test_upsampler_in_frame_matches_stage_calls(pkg):
+@pytest.mark.parametrize("gaze", ["centre", "off_centre"])
+def test_upsampler_in_frame_matches_stage_calls(pkg, gaze):
     """render_foveated with the network equals: the layers through the stage
-    calls, the periphery layer through a3fr_net_forward, a3fr_composite."""
+    calls, the periphery layer through a3fr_net_forward, a3fr_composite.  In
+    the frame the network runs on both eyes in one batch, skips what lies
+    within r_mid of each eye's own gaze and writes the periphery in place, so
+    distinct gazes near the image border are checked too."""
     W, H = 464, 480
-    scene, cams, gz, rad = _frame(100_000, W, H, seed=8)
+    gz = [(0.3 * W, 0.7 * H), (0.9 * W, 0.08 * H)] if gaze == "off_centre" else None
+    scene, cams, gz, rad = _frame(100_000, W, H, seed=8, gz=gz)
     ds = pkg.DeviceScene.from_host(scene)
     fov = pkg.fovea_struct(*rad)
     theta = torch.from_numpy(synth.net_init(46, last_scale=1.0)).cuda()
