@@ -320,6 +320,7 @@ def main():
     extra = {}
     if do_fov and do_frr and not args.no_extra:
         extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options)
+        extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
         extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
         extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
@@ -442,6 +443,54 @@ def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, met
         res[name] = dict(ms_per_frame=ms, periphery_psnr_db=min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)))
         log(f"frame {name}: {ms:.3f} ms")
     method_options(ctx)
+    return res
+
+
+def incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options, n_trials=8):
+    """Incremental foveal rounds (Sec. 3.3) on the benchmark frame, driven by a
+    seeded early-exit gaze stream (Table 2 spreads): round 0 (projection and
+    periphery) before any gaze, per exit a round at r_f - E (Eq. 4) and its
+    speculative growth to r_f + E (Eq. 5), the final round and composite at
+    the last prediction.  Compared with the sequential frame (the whole
+    foveated frame rendered after the last prediction, same options: the
+    upsampler, no fallback): the time left after the last prediction."""
+    import statistics as stats
+    from paper_2507_04147_amd import incremental as inc
+    W, H = cams[0].width, cams[0].height
+    trials, sig = synth.gaze_exits(seed=61, n_trials=n_trials, width=W, height=H)
+    c = pkg.Context()
+    method_options(c)
+    c.set_fallback(float("inf"), 1.0, 1.0)
+    out = torch.empty((2, 3, H, W), device="cuda")
+
+    def gpu_ms(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1000.0
+
+    for _ in range(2):  # warm-up
+        inc.run_frame(c, ds, cams, fov, inc.schedule(trials[0][1], sig, rad[0]), trials[0][0], out)
+        c.render_foveated(ds, cams, trials[0][0], fov, out)
+    rows = []
+    for final, exits in trials:
+        steps = inc.run_frame(c, ds, cams, fov, inc.schedule(exits, sig, rad[0]), final, out, timed=gpu_ms)
+        sfr = gpu_ms(lambda: c.render_foveated(ds, cams, final, fov, out))
+        one = c.get_counts()
+        rows.append(dict(begin=steps[0]["ms"], rounds=sum(s["ms"] for s in steps[1:-1]), finish=steps[-1]["ms"],
+                         sfr=sfr, tiles=sum(s["tiles"] for s in steps), tiles_one_shot=one["n_active_tiles"],
+                         finish_tiles=steps[-1]["tiles"], steps=[(s["step"], round(s["radius"] or 0.0, 1),
+                                                                 s["tiles"], s["keys"]) for s in steps]))
+    c.close()
+    med = lambda k: stats.median(r[k] for r in rows)
+    res = dict(trials=n_trials, exits=len(sig), exit_latency_ms=list(synth.EXIT_LATENCY_MS),
+               begin_ms=med("begin"), rounds_ms=med("rounds"), finish_ms=med("finish"), sequential_frame_ms=med("sfr"),
+               latency_ratio_after_last_gaze=med("sfr") / med("finish"),
+               extra_fovea_tiles=stats.median(r["tiles"] - r["tiles_one_shot"] for r in rows),
+               finish_tiles=med("finish_tiles"), example_steps=rows[0]["steps"])
+    log(f"incremental rounds: begin {res['begin_ms']:.3f} ms, rounds {res['rounds_ms']:.3f} ms, finish "
+        f"{res['finish_ms']:.3f} ms after the last prediction vs {res['sequential_frame_ms']:.3f} ms sequential")
     return res
 
 

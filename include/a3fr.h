@@ -50,6 +50,7 @@ typedef enum {
 #define A3FR_MASK_ALL 0      /* every tile of the view is rendered */
 #define A3FR_MASK_DISC 1     /* tiles whose pixel-centre rectangle is within r_out of the gaze */
 #define A3FR_MASK_ANNULUS 2  /* as DISC with r_out, minus tiles lying wholly within r_in */
+/* (DISC and ANNULUS: a negative r_out selects no tile) */
 
 typedef struct a3fr_ctx a3fr_ctx;
 
@@ -226,6 +227,42 @@ a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze,
 
 /* Counters of the last preprocess / bin_sort (host struct). */
 a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
+
+/* ---- incremental foveal rendering -------------------------------------------- */
+
+/* Incremental rendering of the foveal region as ever more accurate gaze
+ * predictions arrive (Sec. 3.3): the layered frame of a3fr_render_foveated
+ * built over several calls on one context.
+ *
+ * a3fr_incremental_begin: round 0, before any gaze.  Projects every layer of
+ * every eye once and keeps the results in the context (Sec. 3.5: later rounds
+ * use the buffered projection and never read the scene again), selects the
+ * periphery subset and renders the periphery layer, which needs no gaze.
+ * The fovea and mid layers are projected with empty masks; every visible
+ * entry keeps its rectangle and record, coloured now.  Arguments as in
+ * a3fr_render_foveated (no fallback in this mode).
+ *
+ * a3fr_incremental_round: for each eye, renders the fovea-layer tiles within
+ * radius (full-resolution pixels, the same tile test as A3FR_MASK_DISC) of
+ * gaze[e] that no earlier round of this frame rendered; radius 0 renders
+ * nothing.  The radius of a round follows from the expected distance between
+ * this prediction and the final one (Eq. 4: r_f - E[dist], at least 0; with no
+ * newer prediction, rendering may continue around the same gaze up to
+ * r_f + E[dist], Eq. 5) -- the caller's schedule.
+ *
+ * a3fr_incremental_finish: the final gaze (one per eye).  Renders the fovea
+ * tiles within r_fovea of it not yet rendered and the mid layer's annulus
+ * around it, then composites into out_dev [eyes][3][H][W] (upsampler if set).
+ * The result equals a3fr_render_foveated with that gaze.
+ *
+ * Tiles and keys of each round: a3fr_get_counts after the call.  Any other
+ * a3fr_preprocess, render or graph call on the context ends the frame (the
+ * rounds share its buffers): a later round or finish then returns
+ * A3FR_ENOTREADY.  A3FR_EINVAL while a captured graph is held. */
+a3fr_status a3fr_incremental_begin(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_eyes,
+                                   const a3fr_fovea *fovea);
+a3fr_status a3fr_incremental_round(a3fr_ctx *ctx, const a3fr_gaze *gaze, double radius);
+a3fr_status a3fr_incremental_finish(a3fr_ctx *ctx, const a3fr_gaze *gaze, float *out_dev);
 
 /* ---- training: device activation and the backward pass ------------------ */
 

@@ -87,9 +87,12 @@ static inline int32_t or_tiles_y(const or_view *v, int32_t th) { return (v->heig
  * the image) is tested against the gaze disc(s). disc: active iff the squared
  * distance from the gaze to the rectangle is <= r_out^2. annulus: the same outer
  * test, and inactive when all four corners lie within r_in of the gaze (the tile
- * is covered by the inner layer). */
+ * is covered by the inner layer).  A negative r_out is an empty mask (a layer
+ * with nothing to render, as in the incremental rounds of Sec. 3.3 before a
+ * radius is known). */
 static int or_tile_active(const or_view *v, int32_t tw, int32_t th, int32_t tx, int32_t ty) {
     if (v->mask == 0) return 1;
+    if (v->r_out < 0.0) return 0;
     int32_t xe = (tx + 1) * tw; if (xe > v->width) xe = v->width;
     int32_t ye = (ty + 1) * th; if (ye > v->height) ye = v->height;
     double x0 = (double)(tx * tw) + 0.5, x1 = (double)xe - 0.5;

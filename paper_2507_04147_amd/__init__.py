@@ -130,6 +130,9 @@ def lib():
                                  C.POINTER(Fovea_), P],
         "a3fr_make_foveated_views": [C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Fovea_),
                                      C.POINTER(View_)],
+        "a3fr_incremental_begin": [P, C.POINTER(Scene_), C.POINTER(Camera_), I32, C.POINTER(Fovea_)],
+        "a3fr_incremental_round": [P, C.POINTER(Gaze_), D],
+        "a3fr_incremental_finish": [P, C.POINTER(Gaze_), P],
         "a3fr_composite": [P, I32, I32, Gaze_, C.POINTER(Fovea_), P, P, P, P, P],
         "a3fr_region_sse": [P, I32, I32, Gaze_, D, D, P, P, C.POINTER(D), C.POINTER(I64)],
         "a3fr_get_counts": [P, C.POINTER(Counts_)],
@@ -342,6 +345,29 @@ class Context:
         self._check(self._L.a3fr_render_foveated(self._h, C.byref(scene.struct()), arr, gz, len(cams),
                                                  C.byref(fovea), _dp(out)))
 
+    def incremental_begin(self, scene: DeviceScene, cams, fovea: Fovea_):
+        """Round 0 of an incremental foveated frame: project every layer once,
+        render the periphery (no gaze needed)."""
+        self.generation += 1
+        self._scene = scene
+        self._inc_eyes = len(cams)
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        self._check(self._L.a3fr_incremental_begin(self._h, C.byref(scene.struct()), arr, len(cams),
+                                                   C.byref(fovea)))
+
+    def _gazes(self, gazes):
+        if len(gazes) != getattr(self, "_inc_eyes", -1):
+            raise ValueError("one gaze per eye of a3fr_incremental_begin")
+        return (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+
+    def incremental_round(self, gazes, radius):
+        """Render the fovea tiles within radius of each eye's gaze not rendered yet."""
+        self._check(self._L.a3fr_incremental_round(self._h, self._gazes(gazes), float(radius)))
+
+    def incremental_finish(self, gazes, out):
+        """Final gaze: remaining fovea tiles, mid layer, composite into out."""
+        self._check(self._L.a3fr_incremental_finish(self._h, self._gazes(gazes), _dp(out)))
+
     def composite(self, W, H, gaze, fovea: Fovea_, fov_img, mid_img, per_img, per_full, out):
         self._check(self._L.a3fr_composite(self._h, W, H, Gaze_(float(gaze[0]), float(gaze[1])), C.byref(fovea),
                                            _dp(fov_img), _dp(mid_img), _dp(per_img), _dp(per_full), _dp(out)))
@@ -477,4 +503,4 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward", "a3fr_net_forward",
             "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
             "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
-            "a3fr_graph_destroy"]
+            "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish"]

@@ -43,9 +43,15 @@ struct DevView {
     int64_t cum_off;      // offset of this view's 2D active-tile prefix ((rows + 1) x (tiles_x + 1))
     double limx, limy;    // guard band of the projection Jacobian: (1.3 (W/2)) / fx, (1.3 (H/2)) / fy
     int32_t sel_slot;     // index among selecting views, -1 if none
-    int32_t remask;       // 1: the tile mask may grow after projection (full-resolution fallback);
-                          //    invisible (view, Gaussian) slots then get an empty rectangle
+    int32_t remask;       // 1: the tile mask may change after projection (full-resolution fallback,
+                          //    incremental rounds); invisible (view, Gaussian) slots then get an
+                          //    empty rectangle
+    int32_t round_flags;  // incremental rounds: kRoundExclDone, kRoundFrozen
 };
+// tiles already rendered by an earlier round (the done flags) are left out, and the new ones marked done
+constexpr int32_t kRoundExclDone = 1;
+// no tile of the view is rendered in this round
+constexpr int32_t kRoundFrozen = 2;
 
 // rectangle of a (view, Gaussian) slot that is not visible (x0 > x1): x0 = 1, x1 = 0, y0 = 1, y1 = 0
 constexpr uint64_t kEmptyRect = 0x0000000100000001ull;
@@ -97,7 +103,10 @@ __host__ __device__ int net_chw_stride(int w);
 // ---- kernels' host launchers (all enqueue on `s`) ----
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
-                       hipStream_t s);
+                       uint8_t *done /* [tiles] nullable: incremental rounds */, hipStream_t s);
+// colour of every visible (view, Gaussian) slot of the remask views, into the records
+void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, int64_t n, const uint64_t *rect,
+                          Record *rec, hipStream_t s);
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, hipStream_t s);
@@ -114,8 +123,9 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
                         uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s);
 // number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
 int64_t emit_chunks(int64_t K);
-void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
-                 const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
+void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
+                 const uint32_t *offsets, const uint64_t *rect,
+                 const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev /* nullable: device key count (clamped to K) */, hipStream_t s);
 void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s);

@@ -63,6 +63,15 @@ struct a3fr_ctx {
     struct FbPair { int pv, fv; double r_mid; };
     std::vector<FbPair> fb_plan;           // set by a3fr_render_foveated for its a3fr_preprocess
     bool fb_last = false;                  // the last preprocess ran the fallback steps
+    // incremental foveal rounds (a3fr_incremental_*)
+    bool inc_mode = false;                 // layouts made now: remask fovea and mid layers, apply inc_flags
+    std::vector<int32_t> inc_flags;        // round flags per view of the next layout
+    bool inc_ready = false;                // a3fr_incremental_begin done, frame not finished
+    int inc_eyes = 0;
+    int64_t inc_n = 0, inc_ntiles = 0, inc_npix = 0;
+    std::vector<a3fr_camera> inc_cams;
+    a3fr_fovea inc_fovea{};
+    DevBuf inc_done;                       // [tiles] rendered by an earlier round
     DevBuf fb_energy, fb_flags, fb_diff, fb_part, fb_count;
     bool net_trained_fwd = false;          // the last forward kept activations for a backward
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
@@ -294,7 +303,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
-                      &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->fb_count, &c->blend_ws,
+                      &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->inc_done, &c->fb_count, &c->blend_ws,
                       &c->blend_order, &c->tune_img,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
@@ -373,6 +382,7 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
 
 static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *views, int32_t nv);
 static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den);
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene);
 
 a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_view *views, int32_t nv,
                             int32_t keep_num, int32_t keep_den) {
@@ -395,6 +405,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                  std::memcmp(views[j].campos, views[k].campos, sizeof(views[k].campos)) != 0))
                 return fail(c, A3FR_EINVAL, "views with the same eye must share R, t and campos");
     const int64_t n = scene->n;
+    if (!c->inc_mode) c->inc_ready = false;  // another frame reuses the buffers of the rounds
     if (c->capturing) {
         // the view table of each replay is uploaded by a3fr_graph_launch; the layout is the warm-up's
         if (nv != c->nv || n != c->n) return fail(c, A3FR_EINVAL, "graph capture: frame layout changed");
@@ -434,6 +445,10 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         d.sel_slot = views[k].select ? (int32_t)c->hsel_views.size() : -1;
         for (const auto &fp : c->fb_plan)
             if (fp.fv == k) d.remask = 1;
+        if (c->inc_mode) {
+            if (k % 3 != 2) d.remask = 1;  // fovea and mid layers: their masks change between rounds
+            d.round_flags = k < (int)c->inc_flags.size() ? c->inc_flags[k] : 0;
+        }
         if (views[k].select) c->hsel_views.push_back(k);
         if (views[k].mask != A3FR_MASK_ALL) moff += (int64_t)d.tiles_y * (d.tiles_x + 1);
         for (int ty = 0; ty < d.tiles_y; ++ty) {
@@ -522,7 +537,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     const DevView *dv = P<DevView>(c->views);
     { StageTimer t_(c, A3FR_STAGE_MASKS);
     launch_tile_masks(dv, nv, c->rows_total, d_row_view, d_row_y,
-                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), c->stream);
+                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), nullptr, c->stream);
       if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
@@ -574,13 +589,23 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
                            P<uint32_t>(c->fb_count), c->stream);
         c->fb_last = true;
     }
+    return entry_stages(c, scene);
+}
+
+// Entries that emit keys (count > 0, kept): compaction, colour (scene not
+// NULL), stable sort by depth, key offsets in depth order.
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
+    const int64_t n = c->n;
+    const int nv = c->nv;
+    const int64_t m = (int64_t)nv * n;
+    const DevView *dv = P<DevView>(c->views);
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
                                P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
                                sc_ent_total(c->scalars), sc_n_ent(c->scalars), c->stream);
     }
-    {
+    if (scene) {
         StageTimer t_(c, A3FR_STAGE_COLOUR);
         launch_entry_colour(*scene, dv, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m, P<Record>(c->rec), c->stream);
     }
@@ -641,7 +666,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
                                     c->stream);
     {
         StageTimer t_(c, A3FR_STAGE_EMIT);
-        launch_emit(dv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
+        launch_emit(dv, c->nv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
                     P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
                     P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
                     cap_mode ? sc_n_keys(c->scalars) : nullptr, c->stream);
@@ -935,6 +960,154 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
         launch_composite(W, H, gaze[e].x, gaze[e].y, f->r_fovea, f->r_mid, L + 3 * d0.img_off, L + 3 * d1.img_off,
                          f->scale_mid, L + 3 * d2.img_off, f->scale_periph, nullptr, net,
                          c->fb_last ? P<uint8_t>(c->fb_flags) + d2.tile_off : nullptr, d2.tiles_x,
+                         P<DevView>(c->views) + 3 * e, out + o_off, c->stream);
+        TRY(check_launch(c, "composite"));
+        o_off += 3 * (int64_t)W * H;
+    }
+    return A3FR_OK;
+}
+
+// ---- incremental foveal rounds ------------------------------------------------
+
+static a3fr_status inc_check(a3fr_ctx *c, const a3fr_camera *cams, const a3fr_gaze *gaze, int32_t n_eyes,
+                             const a3fr_fovea *f, const char *who) {
+    if (!cams || !gaze || !f || n_eyes < 1 || n_eyes > kMaxEyes)
+        return fail(c, A3FR_EINVAL, std::string(who) + ": bad arguments");
+    if (c->gexec) return fail(c, A3FR_EINVAL, std::string(who) + ": release the captured graph first");
+    return A3FR_OK;
+}
+
+// One round on the buffered projection: the fovea layer's tiles within radius
+// of each eye's gaze that no earlier round rendered (and, in the final round,
+// the mid layer's annulus around the final gaze) get counts from the stored
+// rectangles, are binned and sorted, and are blended into the persistent
+// layer images; no other tile is touched and the scene is not read.
+static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, bool final_round) {
+    const int ne = c->inc_eyes;
+    std::vector<a3fr_view> v(3 * ne);
+    if (a3fr_make_foveated_views(c->inc_cams.data(), gaze, ne, &c->inc_fovea, v.data()) != A3FR_OK)
+        return fail(c, A3FR_EINVAL, "incremental round: bad gaze");
+    for (int e = 0; e < ne; ++e) {
+        v[3 * e].r_out = radius > 0.0 ? radius : -1.0;  // the fovea layer is at full resolution
+        if (!final_round) v[3 * e + 1].r_out = -1.0;    // the mid layer waits for the final gaze
+    }
+    c->inc_flags.assign(3 * ne, 0);
+    for (int e = 0; e < ne; ++e) {
+        c->inc_flags[3 * e] = kRoundExclDone;
+        c->inc_flags[3 * e + 2] = kRoundFrozen;  // the periphery was rendered by a3fr_incremental_begin
+    }
+    c->inc_mode = true;
+    a3fr_status st = preprocess_layout(c, c->inc_n, v.data(), 3 * ne);
+    c->inc_mode = false;
+    TRY(st);
+    if (c->ntiles != c->inc_ntiles || c->npix != c->inc_npix)
+        return fail(c, A3FR_EINVAL, "incremental round: frame layout changed");
+    const DevView *dv = P<DevView>(c->views);
+    {
+        StageTimer t_(c, A3FR_STAGE_MASKS);
+        launch_tile_masks(dv, c->nv, c->rows_total, c->d_row_view, c->d_row_y, P<uint16_t>(c->row_prefix),
+                          P<uint16_t>(c->row_list), P<uint8_t>(c->active), P<uint8_t>(c->inc_done), c->stream);
+        if (c->cum_entries)
+            launch_mask_cum(dv, c->nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream);
+        for (int e = 0; e < ne; ++e)
+            for (int k = 0; k < 2; ++k)
+                launch_recount(dv, 3 * e + k, c->n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix),
+                               P<uint32_t>(c->counts), nullptr, c->stream);
+    }
+    c->fb_last = false;
+    TRY(entry_stages(c, nullptr));
+    TRY(a3fr_bin_sort(c, nullptr));
+    StageTimer t_(c, A3FR_STAGE_BLEND);
+    return blend_with(c, c->blend_variant, P<float>(c->layers), nullptr, nullptr, nullptr);
+}
+
+a3fr_status a3fr_incremental_begin(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_eyes,
+                                   const a3fr_fovea *f) {
+    if (!c) return A3FR_EINVAL;
+    c->inc_ready = false;
+    std::vector<a3fr_gaze> centre(n_eyes > 0 && n_eyes <= kMaxEyes ? n_eyes : 1);
+    for (int e = 0; cams && e < (int)centre.size(); ++e) centre[e] = a3fr_gaze{cams[e].cx, cams[e].cy};
+    TRY(inc_check(c, cams, centre.data(), n_eyes, f, "incremental_begin"));
+    std::vector<a3fr_view> v(3 * n_eyes);
+    if (a3fr_make_foveated_views(cams, centre.data(), n_eyes, f, v.data()) != A3FR_OK)
+        return fail(c, A3FR_EINVAL, "incremental_begin: bad fovea parameters");
+    if (c->net_theta) {
+        if (f->scale_periph != 4) return fail(c, A3FR_EINVAL, "incremental_begin: the upsampler needs scale_periph = 4");
+        for (int e = 0; e < n_eyes; ++e)
+            if (cams[e].width % 4 || cams[e].height % 4)
+                return fail(c, A3FR_EINVAL, "incremental_begin: the upsampler needs W and H divisible by 4");
+    }
+    // round 0: every layer projected once (the fovea and mid layers with empty
+    // masks, keeping every visible entry's rectangle and record), the periphery
+    // subset selected and the periphery layer rendered: it needs no gaze
+    for (int e = 0; e < n_eyes; ++e) {
+        v[3 * e].r_out = -1.0;
+        v[3 * e + 1].r_out = -1.0;
+    }
+    c->fb_plan.clear();
+    c->inc_flags.assign(3 * n_eyes, 0);
+    c->inc_mode = true;
+    a3fr_status st = a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den);
+    c->inc_mode = false;
+    TRY(st);
+    {
+        StageTimer t_(c, A3FR_STAGE_COLOUR);
+        launch_colour_remask(*scene, P<DevView>(c->views), c->nv, c->n, P<uint64_t>(c->rect), P<Record>(c->rec),
+                             c->stream);
+    }
+    TRY(a3fr_bin_sort(c, nullptr));
+    TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
+    TRY(a3fr_blend(c, P<float>(c->layers), nullptr, nullptr));
+    // the periphery's entries are done: later rounds compact only fovea and mid entries
+    for (int e = 0; e < n_eyes; ++e)
+        launch_fill_u32(P<uint32_t>(c->counts) + (int64_t)(3 * e + 2) * c->n, 0u, c->n, c->stream);
+    const int64_t done_words = ((int64_t)c->ntiles + 3) / 4;
+    TRY(ensure(c, c->inc_done, sizeof(uint32_t) * (size_t)done_words));
+    launch_fill_u32(P<uint32_t>(c->inc_done), 0u, done_words, c->stream);
+    TRY(check_launch(c, "incremental_begin"));
+    c->inc_eyes = n_eyes;
+    c->inc_n = c->n;
+    c->inc_ntiles = c->ntiles;
+    c->inc_npix = c->npix;
+    c->inc_cams.assign(cams, cams + n_eyes);
+    c->inc_fovea = *f;
+    c->inc_ready = true;
+    return A3FR_OK;
+}
+
+a3fr_status a3fr_incremental_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->inc_ready) return fail(c, A3FR_ENOTREADY, "a3fr_incremental_round before a3fr_incremental_begin");
+    if (!gaze) return fail(c, A3FR_EINVAL, "incremental_round: gaze is NULL");
+    if (!(radius >= 0.0) || !is_fin(radius)) return fail(c, A3FR_EINVAL, "incremental_round: radius must be >= 0");
+    TRY(inc_check(c, c->inc_cams.data(), gaze, c->inc_eyes, &c->inc_fovea, "incremental_round"));
+    a3fr_status st = inc_round(c, gaze, radius, false);
+    if (st != A3FR_OK) c->inc_ready = false;
+    return st;
+}
+
+a3fr_status a3fr_incremental_finish(a3fr_ctx *c, const a3fr_gaze *gaze, float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (!c->inc_ready) return fail(c, A3FR_ENOTREADY, "a3fr_incremental_finish before a3fr_incremental_begin");
+    if (!gaze || !out) return fail(c, A3FR_EINVAL, "incremental_finish: NULL gaze or out");
+    TRY(inc_check(c, c->inc_cams.data(), gaze, c->inc_eyes, &c->inc_fovea, "incremental_finish"));
+    c->inc_ready = false;
+    const a3fr_fovea *f = &c->inc_fovea;
+    const int ne = c->inc_eyes;
+    TRY(inc_round(c, gaze, f->r_fovea, true));
+    float *L = P<float>(c->layers);
+    const bool net = c->net_theta != nullptr;
+    if (net) {
+        StageTimer t_(c, A3FR_STAGE_NET);
+        TRY(net_frame_forward(c, c->inc_cams.data(), ne, f->r_mid, L, out));
+    }
+    int64_t o_off = 0;
+    for (int e = 0; e < ne; ++e) {
+        const DevView &d0 = c->hviews[3 * e], &d1 = c->hviews[3 * e + 1], &d2 = c->hviews[3 * e + 2];
+        const int W = c->inc_cams[e].width, H = c->inc_cams[e].height;
+        StageTimer t_(c, A3FR_STAGE_COMPOSITE);
+        launch_composite(W, H, gaze[e].x, gaze[e].y, f->r_fovea, f->r_mid, L + 3 * d0.img_off, L + 3 * d1.img_off,
+                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph, nullptr, net, nullptr, d2.tiles_x,
                          P<DevView>(c->views) + 3 * e, out + o_off, c->stream);
         TRY(check_launch(c, "composite"));
         o_off += 3 * (int64_t)W * H;

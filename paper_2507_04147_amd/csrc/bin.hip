@@ -455,15 +455,15 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
 // ------------------------------------------------------------------------
 // key emission (entries in depth order)
 // ------------------------------------------------------------------------
-// One thread per output key, so every wavefront writes 64 consecutive keys
-// (coalesced) whatever the sizes of the entries.  A first kernel records, for
-// every 64-key chunk, the entry holding its first key; the chunk's keys then
-// belong to at most 64 consecutive entries, whose offsets the wavefront stages
-// in LDS and binary-searches.  Within its entry a key's tile is found
-// directly: column-major division of the rectangle for views with every tile
-// active; for masked views, a binary search over rows of the view's 2D prefix
-// table of active tiles (cum[ty][tx] = active tiles in rows < ty, columns < tx),
-// then the row's list of active columns.
+// Key-parallel, so every wavefront writes 64 consecutive keys (coalesced)
+// whatever the sizes of the entries.  A first kernel records, for every chunk
+// of kEmitChunk keys, the entry holding its first key; the chunk's keys then
+// belong to at most kEmitChunk consecutive entries, which the block stages in
+// LDS.  Within its entry a key's tile is found directly (row-major division of
+// the rectangle) when every tile of the rectangle is active; otherwise (a
+// masked view) by a binary search over rows of the view's 2D prefix table of
+// active tiles (cum[ty][tx] = active tiles in rows < ty, columns < tx), then
+// the row's list of active columns.
 
 __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y0, int &y1) {
     x0 = (int)(r & 0xffff); x1 = (int)((r >> 16) & 0xffff);
@@ -497,7 +497,16 @@ __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, con
 // each bisection step together, so their dependent loads overlap.
 constexpr int kEmitPer = kEmitChunk / kEmitBlock;
 
-__global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__ views, int64_t n,
+// per-view fields the emission needs, staged in LDS
+struct EmitView {
+    uint32_t tile_off;
+    int32_t tiles_x;
+    int32_t cum_off;   // -1: every tile active
+    int32_t mask_off;
+};
+constexpr int kEmitMaxViews = kMaxViews;
+
+__global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__ views, int nv, int64_t n,
                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
                                                      const uint32_t *__restrict__ offsets,
                                                      const uint32_t *__restrict__ chunk_start,
@@ -510,6 +519,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     __shared__ uint32_t s_i[kEmitChunk];
     __shared__ uint32_t s_v[kEmitChunk];
     __shared__ uint64_t s_rect[kEmitChunk];
+    __shared__ EmitView s_view[kEmitMaxViews];
     const int tid = threadIdx.x;
     const int64_t q0 = (int64_t)blockIdx.x * kEmitChunk;
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode: the device count, clamped
@@ -523,15 +533,23 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         const int64_t jj = j0 + t;
         s_off[t] = offsets[jj < E ? jj : E];
     }
+    for (int v = tid; v < nv; v += kEmitBlock) {
+        const DevView &dv = views[v];
+        const bool all = dv.v.mask == A3FR_MASK_ALL;
+        s_view[v] = EmitView{(uint32_t)dv.tile_off, dv.tiles_x, all ? -1 : (int32_t)dv.cum_off,
+                             all ? -1 : (int32_t)dv.mask_off};
+    }
     __syncthreads();
-    // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E)
+    // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E);
+    // their Gaussian index, view and rectangle
+    const uint32_t nn = (uint32_t)n;
     for (int t = tid; t < kEmitChunk; t += kEmitBlock) {
         if ((int64_t)s_off[t] < qend) {
-            const int64_t e = ent[j0 + t];
-            const int v = (int)(e / n);
-            s_v[t] = (uint32_t)v;
-            s_i[t] = (uint32_t)(e - (int64_t)v * n);
+            const uint32_t e = ent[j0 + t];
             s_rect[t] = rect[e];
+            const uint32_t v = e / nn;
+            s_v[t] = v;
+            s_i[t] = e - v * nn;
         }
     }
     __syncthreads();
@@ -567,14 +585,14 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         const int t = lo[k];
         r[k] = (uint32_t)(q[k] - s_off[t]);
         unpack_rect(s_rect[t], x0[k], x1[k], y0[k], y1[k]);
-        const DevView &dv = views[s_v[t]];
-        TX[k] = dv.tiles_x;
+        const EmitView &ev = s_view[s_v[t]];
+        TX[k] = ev.tiles_x;
         const uint32_t w = (uint32_t)(x1[k] - x0[k] + 1);
         const uint32_t cnt = s_off[t + 1] - s_off[t];
-        search[k] = q[k] < qend && dv.v.mask != A3FR_MASK_ALL && cnt != w * (uint32_t)(y1[k] - y0[k] + 1);
+        search[k] = q[k] < qend && ev.cum_off >= 0 && cnt != w * (uint32_t)(y1[k] - y0[k] + 1);
         ty[k] = y0[k] + (int)(r[k] / w);
         tx[k] = x0[k] + (int)(r[k] % w);
-        cm[k] = cum + (search[k] ? dv.cum_off : 0);
+        cm[k] = cum + (search[k] ? ev.cum_off : 0);
         ra[k] = y0[k];
         rb[k] = y1[k] + 1;
         base[k] = 0;
@@ -605,19 +623,19 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         if (search[k]) {
             const int64_t st = TX[k] + 1;
             const int t = lo[k];
-            const DevView &dv = views[s_v[t]];
+            const EmitView &ev = s_view[s_v[t]];
             ty[k] = ra[k];
             const uint32_t before = cm[k][(int64_t)ty[k] * st + x1[k] + 1] - cm[k][(int64_t)ty[k] * st + x0[k]] -
                                     base[k];
-            const uint16_t *rp = row_prefix + dv.mask_off + (int64_t)ty[k] * st;
-            const uint16_t *rl = row_list + dv.mask_off + (int64_t)ty[k] * st;
+            const uint16_t *rp = row_prefix + ev.mask_off + (int64_t)ty[k] * st;
+            const uint16_t *rl = row_list + ev.mask_off + (int64_t)ty[k] * st;
             tx[k] = rl[rp[x0[k]] + (r[k] - before)];
         }
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k)
         if (q[k] < qend) {
             const int t = lo[k];
-            keys[q[k]] = (uint32_t)views[s_v[t]].tile_off + (uint32_t)(ty[k] * TX[k] + tx[k]);
+            keys[q[k]] = s_view[s_v[t]].tile_off + (uint32_t)(ty[k] * TX[k] + tx[k]);
             vals[q[k]] = s_i[t];
         }
 }
@@ -671,7 +689,7 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 
 int64_t emit_chunks(int64_t K) { return (K + kEmitChunk - 1) / kEmitChunk; }
 
-void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
+void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev, hipStream_t s) {
@@ -679,7 +697,7 @@ void launch_emit(const DevView *views, int64_t n, int64_t m, const uint32_t *ent
     const int64_t nchunks = emit_chunks(K);
     hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start,
                        nchunks);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, n, ent, n_ent, offsets,
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, nv, n, ent, n_ent, offsets,
                        chunk_start, rect, row_prefix, row_list, cum, keys, vals, K, K_dev);
 }
 

@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ vie
                                                  const uint64_t *__restrict__ rect,
                                                  const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ counts,
                                                  const uint32_t *n_flagged) {
-    if (*n_flagged == 0) return;  // masks unchanged: the counts of the projection stand
+    if (n_flagged && *n_flagged == 0) return;  // masks unchanged: the counts of the projection stand
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const DevView &dv = views[fv];

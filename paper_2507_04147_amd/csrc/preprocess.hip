@@ -19,6 +19,7 @@ namespace a3fr {
 // ------------------------------------------------------------------------
 __device__ __forceinline__ bool tile_active(const a3fr_view &v, int tx, int ty) {
     if (v.mask == A3FR_MASK_ALL) return true;
+    if (v.r_out < 0.0) return false;  // an empty mask
     int xe = (tx + 1) * kTile; if (xe > v.width) xe = v.width;
     int ye = (ty + 1) * kTile; if (ye > v.height) ye = v.height;
     double x0 = (double)(tx * kTile) + 0.5, x1 = (double)xe - 0.5;
@@ -40,9 +41,11 @@ __device__ __forceinline__ bool tile_active(const a3fr_view &v, int tx, int ty) 
 // One wavefront per tile row of every view: active flags, and for masked views
 // a row prefix count (row_prefix[x] = active tiles in columns < x) and the
 // columns of the row's active tiles in order (row_list), built with ballots.
+// Incremental rounds: a frozen view has no active tile; a view excluding done
+// tiles drops the tiles an earlier round rendered and marks its new ones done.
 __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_t rows_total, const int32_t *row_view,
                                                     const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list,
-                                                    uint8_t *active) {
+                                                    uint8_t *active, uint8_t *done) {
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= rows_total) return;
@@ -50,8 +53,11 @@ __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_
     const int ty = row_y[r];
     const int TX = dv.tiles_x;
     uint8_t *act = active + dv.tile_off + (int64_t)ty * TX;
+    const bool frozen = (dv.round_flags & kRoundFrozen) != 0;
+    const bool excl = done && (dv.round_flags & kRoundExclDone) != 0;
+    uint8_t *dn = excl ? done + dv.tile_off + (int64_t)ty * TX : nullptr;
     if (dv.v.mask == A3FR_MASK_ALL) {
-        for (int tx = lane; tx < TX; tx += 64) act[tx] = 1;
+        for (int tx = lane; tx < TX; tx += 64) act[tx] = frozen ? 0 : 1;
         return;
     }
     uint16_t *pre = row_prefix + dv.mask_off + (int64_t)ty * (TX + 1);
@@ -60,7 +66,11 @@ __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_
     uint32_t c = 0;
     for (int tx0 = 0; tx0 < TX; tx0 += 64) {
         const int tx = tx0 + lane;
-        const bool a = tx < TX && tile_active(dv.v, tx, ty);
+        bool a = !frozen && tx < TX && tile_active(dv.v, tx, ty);
+        if (excl && a) {
+            a = dn[tx] == 0;
+            if (a) dn[tx] = 1;
+        }
         const uint64_t m = __ballot(a);
         const uint32_t below = (uint32_t)__popcll(m & lt);
         if (tx < TX) {
@@ -75,11 +85,11 @@ __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_
 
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
-                       hipStream_t s) {
+                       uint8_t *done, hipStream_t s) {
     (void)nv;
     if (rows_total == 0) return;
     hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((rows_total + 3) / 4)), dim3(256), 0, s, views, rows_total,
-                       row_view, row_y, row_prefix, row_list, active);
+                       row_view, row_y, row_prefix, row_list, active, done);
 }
 
 // ------------------------------------------------------------------------
@@ -263,18 +273,10 @@ void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, 
                        views, groups, row_prefix, counts, depth, rect, rec, score);
 }
 
-// View-dependent colour (degree <= 3 real SH, float32) of every entry that
-// emits keys, seen from its view's eye centre, written into its record.
-__global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevView *__restrict__ views,
-                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
-                                                      Record *__restrict__ rec) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)*n_ent) return;
+// View-dependent colour (degree <= 3 real SH, float32) of Gaussian i seen
+// from its view's eye centre, clamped at zero, written into its record.
+__device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_view &vw, int64_t i, Record &rr) {
     const int64_t n = sc.n;
-    const int64_t e = ent[j];
-    const int v = (int)(e / n);
-    const int64_t i = e - (int64_t)v * n;
-    const a3fr_view &vw = views[v].v;
     const float dx = sc.mean_dev[i] - (float)vw.campos[0], dy = sc.mean_dev[n + i] - (float)vw.campos[1],
                 dz = sc.mean_dev[2 * n + i] - (float)vw.campos[2];
     const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -304,9 +306,40 @@ __global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevVi
             col[2] = fmaf(Y[k], f[3 * k + 2], col[2]);
         }
     }
-    col[0] = fmaxf(col[0], 0.0f); col[1] = fmaxf(col[1], 0.0f); col[2] = fmaxf(col[2], 0.0f);
-    float *r = &rec[e].r;
-    r[0] = col[0]; r[1] = col[1]; r[2] = col[2];
+    rr.r = fmaxf(col[0], 0.0f);
+    rr.g = fmaxf(col[1], 0.0f);
+    rr.b = fmaxf(col[2], 0.0f);
+}
+
+// Colour of every entry that emits keys.
+__global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevView *__restrict__ views,
+                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                                      Record *__restrict__ rec) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)*n_ent) return;
+    const int64_t n = sc.n;
+    const int64_t e = ent[j];
+    const int v = (int)(e / n);
+    colour_into(sc, views[v].v, e - (int64_t)v * n, rec[e]);
+}
+
+// Colour of every visible slot of the views whose mask changes after the
+// projection (their entries are coloured once, before the rounds that draw them).
+__global__ void __launch_bounds__(256) k_colour_remask(a3fr_scene sc, const DevView *__restrict__ views, int64_t n,
+                                                       const uint64_t *__restrict__ rect, Record *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevView &dv = views[blockIdx.y];
+    if (i >= n || !dv.remask) return;
+    const int64_t slot = (int64_t)blockIdx.y * n + i;
+    if (rect[slot] == kEmptyRect) return;
+    colour_into(sc, dv.v, i, rec[slot]);
+}
+
+void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, int64_t n, const uint64_t *rect,
+                          Record *rec, hipStream_t s) {
+    if (n == 0 || nv == 0) return;
+    hipLaunchKernelGGL(k_colour_remask, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0, s, sc, views, n,
+                       rect, rec);
 }
 
 void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,

@@ -252,3 +252,35 @@ def gaze_trace(seed=31, n_frames=64, width=1832, height=1920, fov_x_deg=60.0, hz
         py = c.cy + c.fy * math.tan(math.radians(gy + jy))
         frames.append((cams, [(px, py), (px, py)]))
     return frames
+
+
+# Early-exit gaze predictions (Table 2, A3FR-ViT without pruning): per exit
+# 1..6 the error spread (sigma_x, sigma_y) in degrees and the cumulative CPU
+# latency in milliseconds at which the prediction is available.
+EXIT_SIGMA_DEG = ((8.40, 9.33), (6.08, 7.05), (4.50, 4.46), (3.58, 3.38), (2.97, 2.85), (2.05, 2.16))
+EXIT_LATENCY_MS = (5.11, 9.45, 13.91, 18.31, 22.21, 26.28)
+
+
+def gaze_exits(seed=61, n_trials=16, width=1832, height=1920, fov_x_deg=60.0, max_ecc_deg=15.0, n_eyes=2):
+    """Synthetic early-exit gaze streams for the incremental rounds: per trial a
+    final gaze u_N (uniform direction, eccentricity uniform in [0, max_ecc_deg],
+    the same pixel for every eye) and the predictions of exits 1..N-1, each
+    u_N plus independent normal offsets with the exit's spread (Table 2,
+    degrees at the image centre turned into pixels with f tan(theta)).
+    Returns (trials, sigmas_px): trials = [(final [(x, y)] * n_eyes,
+    [[(x, y)] * n_eyes for each exit 1..N-1])], sigmas_px = [(sx, sy)] for
+    exits 1..N-1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = stereo_cameras((0.0, 0.0, -3.0), width, height, fov_x_deg)[0]
+    sig = [(c.fx * math.tan(math.radians(sx)), c.fy * math.tan(math.radians(sy))) for sx, sy in EXIT_SIGMA_DEG[:-1]]
+    trials = []
+    for _ in range(n_trials):
+        ecc, ang = rng.uniform(0.0, max_ecc_deg), rng.uniform(0.0, 2.0 * math.pi)
+        ux = c.cx + c.fx * math.tan(math.radians(ecc * math.cos(ang)))
+        uy = c.cy + c.fy * math.tan(math.radians(ecc * math.sin(ang)))
+        exits = []
+        for sx, sy in sig:
+            ox, oy = rng.normal(0.0, 1.0, 2)
+            exits.append([(float(ux + sx * ox), float(uy + sy * oy))] * n_eyes)
+        trials.append(([(float(ux), float(uy))] * n_eyes, exits))
+    return trials, sig

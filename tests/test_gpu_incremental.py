@@ -1,0 +1,148 @@
+"""GPU parity of the incremental foveal rounds (MI355X only).
+
+The frame built by a3fr_incremental_begin / _round / _finish must equal the
+one-shot a3fr_render_foveated with the final gaze bit for bit (every tile is
+blended from the same list whichever round renders it), and the oracle's
+foveated frame within the composite tolerances.  Each round's rendered tiles
+and emitted keys must equal the oracle's: the round's new tiles (Eq. 4 / Eq. 5
+discs minus earlier rounds, same tile test as the fovea disc mask) and the
+keys the projected rectangles give them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.incremental as oi
+import synth
+from test_gpu_parity import AMB_TOL, COLOUR_TOL, composite_ambiguity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2507_04147_amd as p
+    p.lib()
+    assert torch.cuda.is_available()
+    return p
+
+
+def _setup(n, W, H, seed, n_trials):
+    scene, cams = synth.foveated_stereo(n=n, width=W, height=H, seed=seed)
+    trials, sig = synth.gaze_exits(seed=seed + 60, n_trials=n_trials, width=W, height=H)
+    rad = (0.15 * W, 0.35 * W)
+    return scene, cams, trials, sig, rad
+
+
+def _oracle_rounds(scene, cams, final, rounds, rad):
+    """Per round (then the finish): new fovea tiles and keys over both eyes; the
+    finish also the mid layer's annulus around the final gaze."""
+    views = oracle.foveated_views(cams, final, rad)
+    pr = oracle.project(scene, views)
+    out = [[0, 0] for _ in range(len(rounds) + 1)]
+    for e, cam in enumerate(cams):
+        news, _ = oi.round_tiles(cam, [(g[e], r) for g, r, _ in rounds], final[e], rad[0])
+        tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+        for k, nw in enumerate(news):
+            out[k][0] += int(nw.sum())
+            out[k][1] += oi.keys_for_tiles(pr["rect"][3 * e], pr["vis"][3 * e], nw, tx, ty)
+        mid = views[3 * e + 1]
+        act, _ = oracle.tile_masks([mid])
+        mtx, mty = (mid.width + 15) // 16, (mid.height + 15) // 16
+        out[-1][0] += int(act.sum())
+        out[-1][1] += oi.keys_for_tiles(pr["rect"][3 * e + 1], pr["vis"][3 * e + 1], act, mtx, mty)
+    return out
+
+
+def _run(pkg, ctx, ds, cams, fov, rounds, final, out):
+    from paper_2507_04147_amd import incremental as inc
+    steps = inc.run_frame(ctx, ds, cams, fov, rounds, final, out)
+    ctx.sync()
+    return steps
+
+
+@pytest.mark.parametrize("speculative", [True, False])
+def test_incremental_equals_one_shot_and_oracle(pkg, speculative):
+    from paper_2507_04147_amd import incremental as inc
+    W, H = 464, 480
+    scene, cams, trials, sig, rad = _setup(100_000, W, H, 3, 2)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    ctx = pkg.Context()
+    for final, exits in trials:
+        rounds = inc.schedule(exits, sig, rad[0], speculative=speculative)
+        out = torch.full((2, 3, H, W), float("nan"), device="cuda")
+        steps = _run(pkg, ctx, ds, cams, fov, rounds, final, out)
+        ref = torch.zeros_like(out)
+        ctx.render_foveated(ds, cams, final, fov, ref)
+        ctx.sync()
+        assert torch.equal(out, ref)
+        want = _oracle_rounds(scene, cams, final, rounds, rad)
+        got = [[s["tiles"], s["keys"]] for s in steps[1:]]
+        print("rounds (tiles, keys):", got, flush=True)
+        assert got == want
+    # the last frame against the oracle's foveated frame
+    o = oracle.render_foveated(scene, cams, final, rad)
+    img = out.cpu().numpy()
+    for e in range(2):
+        d = np.abs(img[e] - o["out"][e]).max(axis=0)
+        amb = composite_ambiguity(W, H, final[e], rad, o["images"][3 * e: 3 * e + 3])
+        assert d[~amb].max() <= COLOUR_TOL and d.max() <= AMB_TOL
+    ctx.close()
+
+
+def test_incremental_full_size(pkg):
+    """The 1M-Gaussian stereo frame at 2 x 1832 x 1920 (the benchmark's
+    launches): one trial of the early-exit stream with speculative rounds."""
+    from paper_2507_04147_amd import incremental as inc
+    scene, cams, trials, sig, rad = _setup(1_000_000, 1832, 1920, 2, 1)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    ctx = pkg.Context()
+    final, exits = trials[0]
+    rounds = inc.schedule(exits, sig, rad[0])
+    out = torch.empty((2, 3, 1920, 1832), device="cuda")
+    steps = _run(pkg, ctx, ds, cams, fov, rounds, final, out)
+    ref = torch.empty_like(out)
+    ctx.render_foveated(ds, cams, final, fov, ref)
+    ctx.sync()
+    assert torch.equal(out, ref)
+    got = [[s["tiles"], s["keys"]] for s in steps[1:]]
+    assert got == _oracle_rounds(scene, cams, final, rounds, rad)
+    ctx.close()
+
+
+def test_incremental_call_order_and_args(pkg):
+    W, H = 128, 96
+    scene, cams, trials, sig, rad = _setup(2_000, W, H, 4, 1)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    ctx = pkg.Context()
+    final, exits = trials[0]
+    out = torch.zeros((2, 3, H, W), device="cuda")
+    ctx._inc_eyes = 2
+    with pytest.raises(pkg.A3FRError) as e:
+        ctx.incremental_round(final, 10.0)
+    assert e.value.status == pkg.A3FR_ENOTREADY
+    ctx.incremental_begin(ds, cams, fov)
+    with pytest.raises(pkg.A3FRError) as e:
+        ctx.incremental_round(final, -1.0)
+    assert e.value.status == pkg.A3FR_EINVAL
+    ctx.incremental_round(final, 0.0)  # radius 0: nothing to render
+    assert ctx.get_counts()["n_active_tiles"] == 0 and ctx.get_counts()["n_keys"] == 0
+    with pytest.raises(ValueError):
+        ctx.incremental_round(final[:1], 5.0)
+    # another frame on the context ends the incremental one
+    ctx.render_foveated(ds, cams, final, fov, out)
+    with pytest.raises(pkg.A3FRError) as e:
+        ctx.incremental_finish(final, out)
+    assert e.value.status == pkg.A3FR_ENOTREADY
+    # a finished frame takes no further round
+    ctx.incremental_begin(ds, cams, fov)
+    ctx.incremental_finish(final, out)
+    with pytest.raises(pkg.A3FRError) as e:
+        ctx.incremental_round(final, 5.0)
+    assert e.value.status == pkg.A3FR_ENOTREADY
+    ctx.sync()
+    ctx.close()
