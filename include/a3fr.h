@@ -244,16 +244,20 @@ a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
  *
  * a3fr_incremental_round: for each eye, renders the fovea-layer tiles within
  * radius (full-resolution pixels, the same tile test as A3FR_MASK_DISC) of
- * gaze[e] that no earlier round of this frame rendered; radius 0 renders
- * nothing.  The radius of a round follows from the expected distance between
- * this prediction and the final one (Eq. 4: r_f - E[dist], at least 0; with no
- * newer prediction, rendering may continue around the same gaze up to
- * r_f + E[dist], Eq. 5) -- the caller's schedule.
+ * gaze[e], and the mid-layer tiles within radius + (r_mid - r_fovea) of it
+ * (plus the mid layer's margin, in its pixels), that no earlier round of this
+ * frame rendered; radius 0 renders no fovea tile.  The radius of a round
+ * follows from the expected distance E between this prediction and the final
+ * one (Eq. 4: r_f - E, at least 0; with no newer prediction, rendering may
+ * continue around the same gaze up to r_f + E, Eq. 5; the mid layer's outer
+ * radius is offset by the same E) -- the caller's schedule.
  *
  * a3fr_incremental_finish: the final gaze (one per eye).  Renders the fovea
- * tiles within r_fovea of it not yet rendered and the mid layer's annulus
- * around it, then composites into out_dev [eyes][3][H][W] (upsampler if set).
- * The result equals a3fr_render_foveated with that gaze.
+ * tiles within r_fovea of it and the mid layer's annulus around it that are
+ * not yet rendered, then composites into out_dev [eyes][3][H][W].  With the
+ * upsampler set at a3fr_incremental_begin the whole periphery is upsampled
+ * there, before any gaze.  The result equals a3fr_render_foveated with that
+ * gaze.
  *
  * Tiles and keys of each round: a3fr_get_counts after the call.  Any other
  * a3fr_preprocess, render or graph call on the context ends the frame (the

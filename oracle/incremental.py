@@ -48,32 +48,56 @@ def speculative_radius(r_f, e):
     return r_f + e
 
 
-def disc_tiles(cam, gaze, radius, tw=core.TILE, th=core.TILE):
-    """Active flags [tiles_y * tiles_x] of a full-resolution disc mask of the
-    given radius around gaze (the fovea layer's tile test); radius <= 0: none."""
+def _empty(v):
+    tx, ty = (v.width + core.TILE - 1) // core.TILE, (v.height + core.TILE - 1) // core.TILE
+    return np.zeros(tx * ty, np.uint8)
+
+
+def disc_tiles(cam, gaze, radius, scale=1):
+    """Active flags [tiles_y * tiles_x] of the disc mask of the given radius
+    (in this layer's pixels) around gaze (full-resolution pixels) on the layer
+    of the given scale; radius <= 0: none."""
+    v = core.foveated_views([cam], [gaze], (1.0, 2.0), scales=(scale, scale, scale))[0]
     if radius <= 0.0:
-        tx, ty = (cam.width + tw - 1) // tw, (cam.height + th - 1) // th
-        return np.zeros(tx * ty, np.uint8)
-    v = core.full_view(cam)
-    v.mask, v.gx, v.gy, v.r_out = 1, float(gaze[0]), float(gaze[1]), float(radius)
-    act, _ = core.tile_masks([v], tw, th)
+        return _empty(v)
+    v.mask, v.r_in, v.r_out = 1, 0.0, float(radius)
+    act, _ = core.tile_masks([v])
     return act
 
 
-def round_tiles(cam, rounds, final_gaze, r_f):
-    """New fovea tiles of each round for one eye: rounds = [(gaze, radius)];
-    the final round is (final_gaze, r_f).  Returns the list of new-tile flag
-    arrays (rounds then final) and the union."""
-    done = None
+def layer_rounds(masks):
+    """New tiles of each round of one layer, given each round's tile mask (the
+    last one the final round's): a tile is new where its round's mask has it
+    and no earlier round rendered it.  Returns the list and the union."""
+    done = np.zeros_like(masks[0])
     out = []
-    for g, r in list(rounds) + [(final_gaze, r_f)]:
-        a = disc_tiles(cam, g, r)
-        if done is None:
-            done = np.zeros_like(a)
-        new = (a != 0) & (done == 0)
+    for a in masks:
+        new = ((a != 0) & (done == 0)).astype(np.uint8)
         done = done | new
-        out.append(new.astype(np.uint8))
+        out.append(new)
     return out, done
+
+
+def round_tiles(cam, rounds, final_gaze, r_f):
+    """Fovea layer: rounds = [(gaze, radius)] then (final_gaze, r_f)."""
+    return layer_rounds([disc_tiles(cam, g, r) for g, r in rounds] + [disc_tiles(cam, final_gaze, r_f)])
+
+
+def mid_round_tiles(cam, rounds, final_gaze, radius_px, scale=2, margin=core.MID_MARGIN):
+    """Mid layer: a round with fovea radius r renders the disc of radius
+    r + (r_m - r_f) (full-resolution pixels; Eq. 4 and 5 offset the mid
+    layer's outer radius by the same expected distance) plus the bilinear
+    margin, in its own pixels; the final round its annulus around the final gaze."""
+    rf, rm = radius_px
+    masks = []
+    for g, r in rounds:
+        rr = r + (rm - rf)
+        masks.append(disc_tiles(cam, g, rr / scale + margin, scale) if rr > 0.0 else
+                     disc_tiles(cam, g, -1.0, scale))
+    fin = core.foveated_views([cam], [final_gaze], radius_px)[1]
+    act, _ = core.tile_masks([fin])
+    masks.append(act)
+    return layer_rounds(masks)
 
 
 def keys_for_tiles(rect, vis, tiles, tiles_x, tiles_y):

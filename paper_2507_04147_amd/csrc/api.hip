@@ -72,6 +72,8 @@ struct a3fr_ctx {
     std::vector<a3fr_camera> inc_cams;
     a3fr_fovea inc_fovea{};
     DevBuf inc_done;                       // [tiles] rendered by an earlier round
+    DevBuf inc_periph;                     // upsampled periphery of each eye [eyes][3][H][W] (network set)
+    bool inc_net = false;                  // the periphery of the incremental frame went through the network
     DevBuf fb_energy, fb_flags, fb_diff, fb_part, fb_count;
     bool net_trained_fwd = false;          // the last forward kept activations for a backward
     DevBuf layers, sse_part, sse_cnt, cum, chunk_start;
@@ -303,7 +305,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
-                      &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->inc_done, &c->fb_count, &c->blend_ws,
+                      &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->inc_periph, &c->inc_done, &c->fb_count, &c->blend_ws,
                       &c->blend_order, &c->tune_img,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
@@ -886,9 +888,10 @@ constexpr int kNetFrameRows = 2;  // image rows per block of the frame's convolu
 // batch (frame mode of the convolutions): layer images of eye e sit at a
 // constant distance from eye 0's (every eye has the same layer sizes);
 // waves whose receptive field lies within r_mid are skipped and only pixels
-// outside r_mid are written to out, where the composite leaves them.
+// outside r_mid are written to out, where the composite leaves them (whole:
+// every pixel is computed and written, for a periphery whose gaze comes later).
 static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n_eyes, double r_mid, const float *L,
-                                     float *out) {
+                                     float *out, bool whole = false) {
     const int W = cams[0].width, H = cams[0].height;
     for (int e = 1; e < n_eyes; ++e)
         if (cams[e].width != W || cams[e].height != H)
@@ -910,7 +913,9 @@ static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n
     NetConvArgs a{};
     a.B = n_eyes; a.h = h; a.w = w;
     a.rows = kNetFrameRows;
-    a.gv = P<DevView>(c->views); a.gv_stride = 3; a.rm = r_mid;
+    if (!whole) {  // skip what lies within r_mid, write only outside it
+        a.gv = P<DevView>(c->views); a.gv_stride = 3; a.rm = r_mid;
+    }
     a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1; a.out = P<uint16_t>(c->net_a1);
     launch_net_conv(1, false, a, c->stream);
     a.in = P<uint16_t>(c->net_a1); a.wpk = pk.f2; a.bias = theta + kNetB2; a.out = P<uint16_t>(c->net_a2);
@@ -987,13 +992,21 @@ static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, 
     std::vector<a3fr_view> v(3 * ne);
     if (a3fr_make_foveated_views(c->inc_cams.data(), gaze, ne, &c->inc_fovea, v.data()) != A3FR_OK)
         return fail(c, A3FR_EINVAL, "incremental round: bad gaze");
+    const a3fr_fovea *f = &c->inc_fovea;
     for (int e = 0; e < ne; ++e) {
+        if (final_round) continue;  // fovea disc r_f and mid annulus around the final gaze
         v[3 * e].r_out = radius > 0.0 ? radius : -1.0;  // the fovea layer is at full resolution
-        if (!final_round) v[3 * e + 1].r_out = -1.0;    // the mid layer waits for the final gaze
+        // the mid layer: a disc whose radius is offset from its final outer radius
+        // as the fovea's is (r_mid - E for Eq. 4, r_mid + E for Eq. 5)
+        const double rmid = radius + (f->r_mid - f->r_fovea);
+        v[3 * e + 1].mask = A3FR_MASK_DISC;
+        v[3 * e + 1].r_in = 0.0;
+        v[3 * e + 1].r_out = rmid > 0.0 ? rmid / f->scale_mid + f->margin : -1.0;
     }
     c->inc_flags.assign(3 * ne, 0);
     for (int e = 0; e < ne; ++e) {
         c->inc_flags[3 * e] = kRoundExclDone;
+        c->inc_flags[3 * e + 1] = kRoundExclDone;
         c->inc_flags[3 * e + 2] = kRoundFrozen;  // the periphery was rendered by a3fr_incremental_begin
     }
     c->inc_mode = true;
@@ -1058,6 +1071,13 @@ a3fr_status a3fr_incremental_begin(a3fr_ctx *c, const a3fr_scene *scene, const a
     TRY(a3fr_bin_sort(c, nullptr));
     TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
     TRY(a3fr_blend(c, P<float>(c->layers), nullptr, nullptr));
+    if (c->net_theta) {  // the periphery needs no gaze: upsample all of it now
+        int64_t tot = 0;
+        for (int e = 0; e < n_eyes; ++e) tot += 3 * (int64_t)cams[e].width * cams[e].height;
+        TRY(ensure(c, c->inc_periph, sizeof(float) * (size_t)tot));
+        StageTimer t_(c, A3FR_STAGE_NET);
+        TRY(net_frame_forward(c, cams, n_eyes, f->r_mid, P<float>(c->layers), P<float>(c->inc_periph), true));
+    }
     // the periphery's entries are done: later rounds compact only fovea and mid entries
     for (int e = 0; e < n_eyes; ++e)
         launch_fill_u32(P<uint32_t>(c->counts) + (int64_t)(3 * e + 2) * c->n, 0u, c->n, c->stream);
@@ -1071,6 +1091,7 @@ a3fr_status a3fr_incremental_begin(a3fr_ctx *c, const a3fr_scene *scene, const a
     c->inc_npix = c->npix;
     c->inc_cams.assign(cams, cams + n_eyes);
     c->inc_fovea = *f;
+    c->inc_net = c->net_theta != nullptr;
     c->inc_ready = true;
     return A3FR_OK;
 }
@@ -1096,18 +1117,14 @@ a3fr_status a3fr_incremental_finish(a3fr_ctx *c, const a3fr_gaze *gaze, float *o
     const int ne = c->inc_eyes;
     TRY(inc_round(c, gaze, f->r_fovea, true));
     float *L = P<float>(c->layers);
-    const bool net = c->net_theta != nullptr;
-    if (net) {
-        StageTimer t_(c, A3FR_STAGE_NET);
-        TRY(net_frame_forward(c, c->inc_cams.data(), ne, f->r_mid, L, out));
-    }
     int64_t o_off = 0;
     for (int e = 0; e < ne; ++e) {
         const DevView &d0 = c->hviews[3 * e], &d1 = c->hviews[3 * e + 1], &d2 = c->hviews[3 * e + 2];
         const int W = c->inc_cams[e].width, H = c->inc_cams[e].height;
         StageTimer t_(c, A3FR_STAGE_COMPOSITE);
         launch_composite(W, H, gaze[e].x, gaze[e].y, f->r_fovea, f->r_mid, L + 3 * d0.img_off, L + 3 * d1.img_off,
-                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph, nullptr, net, nullptr, d2.tiles_x,
+                         f->scale_mid, L + 3 * d2.img_off, f->scale_periph,
+                         c->inc_net ? P<float>(c->inc_periph) + o_off : nullptr, false, nullptr, d2.tiles_x,
                          P<DevView>(c->views) + 3 * e, out + o_off, c->stream);
         TRY(check_launch(c, "composite"));
         o_off += 3 * (int64_t)W * H;

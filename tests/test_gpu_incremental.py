@@ -36,22 +36,20 @@ def _setup(n, W, H, seed, n_trials):
 
 
 def _oracle_rounds(scene, cams, final, rounds, rad):
-    """Per round (then the finish): new fovea tiles and keys over both eyes; the
-    finish also the mid layer's annulus around the final gaze."""
+    """Per round (then the finish): new fovea and mid tiles and their keys over
+    both eyes."""
     views = oracle.foveated_views(cams, final, rad)
     pr = oracle.project(scene, views)
     out = [[0, 0] for _ in range(len(rounds) + 1)]
     for e, cam in enumerate(cams):
-        news, _ = oi.round_tiles(cam, [(g[e], r) for g, r, _ in rounds], final[e], rad[0])
-        tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
-        for k, nw in enumerate(news):
-            out[k][0] += int(nw.sum())
-            out[k][1] += oi.keys_for_tiles(pr["rect"][3 * e], pr["vis"][3 * e], nw, tx, ty)
-        mid = views[3 * e + 1]
-        act, _ = oracle.tile_masks([mid])
-        mtx, mty = (mid.width + 15) // 16, (mid.height + 15) // 16
-        out[-1][0] += int(act.sum())
-        out[-1][1] += oi.keys_for_tiles(pr["rect"][3 * e + 1], pr["vis"][3 * e + 1], act, mtx, mty)
+        per_eye = [(g[e], r) for g, r, _ in rounds]
+        for lvl, (news, _) in enumerate((oi.round_tiles(cam, per_eye, final[e], rad[0]),
+                                         oi.mid_round_tiles(cam, per_eye, final[e], rad))):
+            v = views[3 * e + lvl]
+            tx, ty = (v.width + 15) // 16, (v.height + 15) // 16
+            for k, nw in enumerate(news):
+                out[k][0] += int(nw.sum())
+                out[k][1] += oi.keys_for_tiles(pr["rect"][3 * e + lvl], pr["vis"][3 * e + lvl], nw, tx, ty)
     return out
 
 
@@ -129,8 +127,10 @@ def test_incremental_call_order_and_args(pkg):
     with pytest.raises(pkg.A3FRError) as e:
         ctx.incremental_round(final, -1.0)
     assert e.value.status == pkg.A3FR_EINVAL
-    ctx.incremental_round(final, 0.0)  # radius 0: nothing to render
-    assert ctx.get_counts()["n_active_tiles"] == 0 and ctx.get_counts()["n_keys"] == 0
+    ctx.incremental_round(final, 0.0)  # radius 0: no fovea tile; the mid disc of radius r_m - r_f
+    cnt = ctx.get_counts()
+    assert [cnt["n_active_tiles"], cnt["n_keys"]] == _oracle_rounds(scene, cams, final, [(final, 0.0, "exit")],
+                                                                     rad)[0]
     with pytest.raises(ValueError):
         ctx.incremental_round(final[:1], 5.0)
     # another frame on the context ends the incremental one
