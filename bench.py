@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--trace-window", type=int, default=16, help="frames per graph launch in the gaze-trace leg")
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed steps of the differentiable-render training loop (0: skip)")
+    ap.add_argument("--net-pairs", type=int, default=2048, help="training pairs of the frame's upsampler")
+    ap.add_argument("--net-epochs", type=int, default=2, help="training epochs of the frame's upsampler")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -158,10 +160,10 @@ def main():
     ds = pkg.DeviceScene.from_host(scene)
     fov = pkg.fovea_struct(*rad, keep=synth.PERIPH_KEEP)
     ctx = pkg.Context()
-    # the method's frame: periphery through the learned upsampler (seeded
-    # initialisation; its training is the upsampler-training leg and the
-    # tests), per-tile error estimate with full-resolution fallback
-    theta = torch.from_numpy(synth.net_init(42)).cuda()
+    # the method's frame: periphery through the learned upsampler, trained here
+    # (untimed) on pairs the library renders at the training poses, and the
+    # per-tile error estimate with full-resolution fallback
+    theta = train_upsampler(pkg, synth, torch, ctx, ds, args.net_pairs, args.net_epochs)
 
     def method_options(c):
         c.set_upsampler(theta)
@@ -321,6 +323,7 @@ def main():
     if do_fov and do_frr and not args.no_extra:
         extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options)
         extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
+        extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
         extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
         extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
@@ -359,7 +362,9 @@ def main():
                         "periphery through the learned x4 upsampler, per-tile error estimate with "
                         "full-resolution fallback",
             "gaussians": scene.n, "width": W, "height": H, "eyes": 2, "gaze": "image centre",
-            "key_path": "f64", "blend": "f32", "upsampler": "bf16 MFMA, f32 accumulate",
+            "key_path": "f64", "blend": "f32",
+            "upsampler": f"bf16 MFMA, f32 accumulate; trained on {args.net_pairs} rendered pairs x "
+                         f"{args.net_epochs} epochs before timing",
             "fallback": list(pkg.FALLBACK_DEFAULT),
         },
         "full_res_fps": 1000.0 / ms_r if do_frr else None,
@@ -446,6 +451,24 @@ def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, met
     return res
 
 
+def amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed):
+    """AMR levels (Sec. 3.4) as the alternative foveation mode: one
+    full-resolution view per eye, 2 x 2 blocks rendered at 4, 3, 2, 1
+    positions within r_f, (r_f + r_m)/2, r_m and beyond; frame time and
+    periphery PSNR against the full-resolution render."""
+    W, H = cams[0].width, cams[0].height
+    radii = (rad[0], 0.5 * (rad[0] + rad[1]), rad[1])
+    amr = pkg.amr_struct(*radii)
+    out = torch.empty((2, 3, H, W), device="cuda")
+    step = lambda: ctx.render_amr(ds, cams, gaze, amr, out)
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
+    log(f"AMR frame {ms:.3f} ms, periphery PSNR {min(psnr):.2f} dB")
+    return dict(ms_per_frame=ms, radii=list(radii), periphery_psnr_db=min(psnr))
+
+
 def incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options, n_trials=8):
     """Incremental foveal rounds (Sec. 3.3) on the benchmark frame, driven by a
     seeded early-exit gaze stream (Table 2 spreads): round 0 (projection and
@@ -492,6 +515,23 @@ def incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options, n_tri
     log(f"incremental rounds: begin {res['begin_ms']:.3f} ms, rounds {res['rounds_ms']:.3f} ms, finish "
         f"{res['finish_ms']:.3f} ms after the last prediction vs {res['sequential_frame_ms']:.3f} ms sequential")
     return res
+
+
+def train_upsampler(pkg, synth, torch, ctx, ds, n_pairs, epochs, batch=32):
+    """The frame's upsampler: Adam from the seeded initialisation on pairs the
+    library renders at the training poses (full-resolution 256x256 crops and
+    their quarter-resolution periphery renders)."""
+    from paper_2507_04147_amd import upsampler as U
+    net = U.Upsampler(ctx, synth.net_init(42))
+    if n_pairs > 0 and epochs > 0:
+        t = time.perf_counter()
+        xs, ts = U.make_pairs(ctx, ds, synth.crop_poses(41, n_pairs))
+        hist = net.fit(xs, ts, epochs=epochs, batch=batch)
+        torch.cuda.synchronize()
+        log(f"upsampler trained on {n_pairs} pairs x {epochs} epochs in {time.perf_counter() - t:.2f} s "
+            f"(loss {hist[0]:.3e} -> {hist[-1]:.3e})")
+        del xs, ts
+    return net.theta
 
 
 def net_train_leg(pkg, synth, torch, np, ctx, ds, n_pairs=2048, epochs=2, batch=32):

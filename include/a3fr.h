@@ -228,6 +228,27 @@ a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze,
 /* Counters of the last preprocess / bin_sort (host struct). */
 a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
 
+/* ---- AMR levels -------------------------------------------------------------- */
+
+/* Adaptive resolution by 2 x 2 pixel blocks (Sec. 3.4; Sec. 3.5: tiles
+ * labelled with levels 1 to 4 by eccentricity): every tile of the
+ * full-resolution view is split into 2 x 2 blocks; a tile of level L renders
+ * the first L positions of each block (top-left, top-right, bottom-left,
+ * bottom-right) with all Gaussians, and the other positions inherit the
+ * rendered pixel above them, else the top-left one.  The level of a tile is 4
+ * if its pixel-centre rectangle lies within r_level[0] of the gaze, 3 within
+ * r_level[1], 2 within r_level[2], else 1 (0 <= r_level[0] <= r_level[1] <=
+ * r_level[2], full-resolution pixels; the same distance test as
+ * A3FR_MASK_DISC).  A level-4 tile equals a3fr_render_full's pixels. */
+typedef struct {
+    double r_level[3];
+} a3fr_amr;
+
+/* One full-resolution view per eye (as a3fr_render_full) rendered with AMR
+ * levels around gaze[e]; out_dev [n_eyes][3][H][W] (every pixel written). */
+a3fr_status a3fr_render_amr(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams, const a3fr_gaze *gaze,
+                            int32_t n_eyes, const a3fr_amr *amr, float *out_dev);
+
 /* ---- incremental foveal rendering -------------------------------------------- */
 
 /* Incremental rendering of the foveal region as ever more accurate gaze

@@ -82,6 +82,16 @@ class Fovea_(C.Structure):
                 ("margin", C.c_double)]
 
 
+class Amr_(C.Structure):
+    _fields_ = [("r_level", C.c_double * 3)]
+
+
+def amr_struct(r4, r3, r2) -> Amr_:
+    a = Amr_()
+    a.r_level[0], a.r_level[1], a.r_level[2] = float(r4), float(r3), float(r2)
+    return a
+
+
 STAGES = ["masks", "preprocess", "select", "scan", "emit", "sort_hist", "sort_pass", "ranges", "blend", "composite",
           "depth_sort", "activate", "blend_bwd", "preprocess_bwd", "fallback", "net", "colour"]
 
@@ -130,6 +140,7 @@ def lib():
                                  C.POINTER(Fovea_), P],
         "a3fr_make_foveated_views": [C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Fovea_),
                                      C.POINTER(View_)],
+        "a3fr_render_amr": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Amr_), P],
         "a3fr_incremental_begin": [P, C.POINTER(Scene_), C.POINTER(Camera_), I32, C.POINTER(Fovea_)],
         "a3fr_incremental_round": [P, C.POINTER(Gaze_), D],
         "a3fr_incremental_finish": [P, C.POINTER(Gaze_), P],
@@ -345,6 +356,15 @@ class Context:
         self._check(self._L.a3fr_render_foveated(self._h, C.byref(scene.struct()), arr, gz, len(cams),
                                                  C.byref(fovea), _dp(out)))
 
+    def render_amr(self, scene: DeviceScene, cams, gazes, amr: Amr_, out):
+        """Full-resolution views with AMR levels 4..1 by distance from the gaze."""
+        self.generation += 1
+        self._scene = scene
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+        self._check(self._L.a3fr_render_amr(self._h, C.byref(scene.struct()), arr, gz, len(cams), C.byref(amr),
+                                            _dp(out)))
+
     def incremental_begin(self, scene: DeviceScene, cams, fovea: Fovea_):
         """Round 0 of an incremental foveated frame: project every layer once,
         render the periphery (no gaze needed)."""
@@ -503,4 +523,5 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_activate", "a3fr_blend_backward", "a3fr_preprocess_backward", "a3fr_net_forward",
             "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
             "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
-            "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish"]
+            "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish",
+            "a3fr_render_amr"]

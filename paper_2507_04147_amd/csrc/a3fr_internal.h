@@ -166,6 +166,9 @@ constexpr int kBlendVariants = A3FR_BLEND_VARIANTS;  // batch {32, 64, 128} x ro
 constexpr int kBlendDefault = 1;      // batch 64, 4 x 1 pixels per lane, grid
 constexpr int kBlendWsWords = 68;
 BlendVariant blend_variant(int k);
+// AMR levels of every tile of full views (gaze in the views): r4 >= distance: 4 positions of each 2 x 2 block, ...
+void launch_blend_amr(const DevView *views, int nv, int64_t ntiles, const uint32_t *ranges, const uint32_t *vals,
+                      const Record *rec, int64_t n, double r4, double r3, double r2, float *rgb, hipStream_t s);
 void launch_blend(const BlendArgs &a, int variant, hipStream_t s);
 void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t ntiles, uint32_t *ws, uint32_t *order,
                         hipStream_t s);

@@ -834,6 +834,29 @@ a3fr_status a3fr_render_full(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_ca
     return a3fr_blend(c, out, nullptr, nullptr);
 }
 
+a3fr_status a3fr_render_amr(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, const a3fr_gaze *gaze,
+                            int32_t n_eyes, const a3fr_amr *amr, float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (!cams || !gaze || !amr || !out || n_eyes < 1 || n_eyes > kMaxEyes)
+        return fail(c, A3FR_EINVAL, "render_amr: bad arguments");
+    const double *r = amr->r_level;
+    if (!(r[0] >= 0.0) || !(r[1] >= r[0]) || !(r[2] >= r[1]) || !is_fin(r[2]))
+        return fail(c, A3FR_EINVAL, "render_amr: radii must satisfy 0 <= r_level[0] <= r_level[1] <= r_level[2]");
+    std::vector<a3fr_view> v(n_eyes);
+    for (int e = 0; e < n_eyes; ++e) {
+        view_from_camera(cams[e], e, v[e]);
+        v[e].gx = gaze[e].x;
+        v[e].gy = gaze[e].y;
+        if (!is_fin(gaze[e].x) || !is_fin(gaze[e].y)) return fail(c, A3FR_EINVAL, "render_amr: gaze not finite");
+    }
+    TRY(a3fr_preprocess(c, scene, v.data(), n_eyes, 1, 1));
+    TRY(a3fr_bin_sort(c, nullptr));
+    StageTimer t_(c, A3FR_STAGE_BLEND);
+    launch_blend_amr(P<DevView>(c->views), c->nv, c->ntiles, P<uint32_t>(c->ranges), sorted_vals(c), P<Record>(c->rec),
+                     c->n, r[0], r[1], r[2], out, c->stream);
+    return check_launch(c, "render_amr");
+}
+
 a3fr_status a3fr_make_foveated_views(const a3fr_camera *cams, const a3fr_gaze *gaze, int32_t n_eyes,
                                      const a3fr_fovea *f, a3fr_view *out) {
     if (!cams || !gaze || !f || !out || n_eyes < 1 || n_eyes > kMaxEyes) return A3FR_EINVAL;

@@ -149,6 +149,150 @@ __device__ __forceinline__ void add_pairs(uint32_t npairs, unsigned long long *p
     }
 }
 
+// ------------------------------------------------------------------------
+// AMR levels (Sec. 3.4): each tile is split into 8 x 8 blocks of 2 x 2
+// pixels; a tile of level L renders the first L positions of every block
+// (top-left, top-right, bottom-left, bottom-right) and the other positions
+// inherit the rendered pixel above them, else the top-left one.  Lane l owns
+// block (l % 8, l / 8), so a level-L tile costs L pixels per lane.  The
+// level follows the distance from the gaze to the tile's pixel-centre
+// rectangle: <= r4: 4, <= r3: 3, <= r2: 2, else 1.  Rendered pixels evaluate
+// the same float32 expressions over the same list as k_blend.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int amr_level(const a3fr_view &v, int tx, int ty, double r4, double r3, double r2) {
+    int xe = (tx + 1) * kTile; if (xe > v.width) xe = v.width;
+    int ye = (ty + 1) * kTile; if (ye > v.height) ye = v.height;
+    const double x0 = (double)(tx * kTile) + 0.5, x1 = (double)xe - 0.5;
+    const double y0 = (double)(ty * kTile) + 0.5, y1 = (double)ye - 0.5;
+    const double ddx = fmax(fmax(x0 - v.gx, v.gx - x1), 0.0);
+    const double ddy = fmax(fmax(y0 - v.gy, v.gy - y1), 0.0);
+    const double d2 = ddx * ddx + ddy * ddy;
+    return d2 <= r4 * r4 ? 4 : d2 <= r3 * r3 ? 3 : d2 <= r2 * r2 ? 2 : 1;
+}
+
+template <int NP>
+__device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, int ty, uint32_t start, uint32_t end,
+                                         const uint32_t *__restrict__ vals, const Record *__restrict__ rec, int64_t n,
+                                         float *__restrict__ rgb) {
+    constexpr int BATCH = 64;
+    __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    const int W = dv.v.width, H = dv.v.height;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int lane = threadIdx.x;
+    const int bx = 2 * (lane & 7), by = 2 * (lane >> 3);  // the lane's 2 x 2 block in the tile
+    float fx[NP], fy[NP], T[NP], Cr[NP], Cg[NP], Cb[NP];
+    bool alive[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int cx = bx + (k & 1), cy = by + (k >> 1);
+        fx[k] = (float)cx + 0.5f;
+        fy[k] = (float)cy + 0.5f;
+        alive[k] = (x0 + cx < W) && (y0 + cy < H);
+        T[k] = 1.0f; Cr[k] = Cg[k] = Cb[k] = 0.0f;
+    }
+    const Record *R = rec + lo * n;
+    const double dx0 = (double)x0, dy0 = (double)y0;
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+        bool any_alive = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) any_alive = any_alive || alive[k];
+        if (__ballot(any_alive) == 0ull) break;
+        const uint32_t j = b0 + lane;
+        if (j < end) {
+            const Record r = R[vals[j]];
+            s_u[lane] = (float)(r.u - dx0);
+            s_v[lane] = (float)(r.v - dy0);
+            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
+            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
+        }
+        __syncthreads();
+        const uint32_t cnt = (end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH;
+        for (uint32_t jj = 0; jj < cnt; ++jj) {
+            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+            float al[NP];
+            bool take[NP];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const float dy = fy[k] - mv;
+                const float kdy = kk * dy;
+                const float cdy = c2 * dy * dy;
+                const float t = (fx[k] - mu) + kdy;
+                const float e = fmaf(a2, t * t, cdy);
+                al[k] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
+                take[k] = alive[k] && al[k] >= kAlphaMin;
+                any = any || take[k];
+            }
+            if (__ballot(any) == 0ull) continue;
+            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const float Tn = T[k] * (1.0f - al[k]);
+                const bool stop = take[k] && Tn < kTMin;
+                const bool blend = take[k] && !stop;
+                const float wgt = blend ? al[k] * T[k] : 0.0f;
+                Cr[k] = fmaf(wgt, cr, Cr[k]);
+                Cg[k] = fmaf(wgt, cg, Cg[k]);
+                Cb[k] = fmaf(wgt, cb, Cb[k]);
+                T[k] = blend ? Tn : T[k];
+                alive[k] = alive[k] && !stop;
+            }
+        }
+        __syncthreads();
+    }
+    // rendered positions, then the inherited ones
+    const int64_t HW = (int64_t)W * H;
+    float *img = rgb + 3 * dv.img_off;
+    float vr[4], vg[4], vb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int src = k < NP ? k : (k - 2 >= 0 && k - 2 < NP ? k - 2 : 0);
+        vr[k] = Cr[src] + T[src] * dv.v.bg[0];
+        vg[k] = Cg[src] + T[src] * dv.v.bg[1];
+        vb[k] = Cb[src] + T[src] * dv.v.bg[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = x0 + bx + (k & 1), y = y0 + by + (k >> 1);
+        if (x < W && y < H) {
+            const int64_t pix = (int64_t)y * W + x;
+            img[pix] = vr[k];
+            img[HW + pix] = vg[k];
+            img[2 * HW + pix] = vb[k];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_blend_amr(const DevView *__restrict__ views, int nv,
+                                                  const uint32_t *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                                  int64_t n, double r4, double r3, double r2, float *__restrict__ rgb) {
+    const int64_t gt = blockIdx.x;
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    const DevView &dv = views[lo];
+    const int64_t lt = gt - dv.tile_off;
+    const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
+    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    switch (amr_level(dv.v, tx, ty, r4, r3, r2)) {  // wave-uniform
+        case 4: amr_tile<4>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
+        case 3: amr_tile<3>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
+        case 2: amr_tile<2>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
+        default: amr_tile<1>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
+    }
+}
+
+void launch_blend_amr(const DevView *views, int nv, int64_t ntiles, const uint32_t *ranges, const uint32_t *vals,
+                      const Record *rec, int64_t n, double r4, double r3, double r2, float *rgb, hipStream_t s) {
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(k_blend_amr, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, ranges, vals, rec, n, r4, r3,
+                       r2, rgb);
+}
+
 // grid schedule: one wave per tile, in tile order
 template <bool COUNT, int BATCH, int ROWS>
 __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,

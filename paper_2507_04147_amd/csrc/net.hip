@@ -122,6 +122,137 @@ __device__ __forceinline__ bool inside_mid(int xa, int xb, int ya, int yb, doubl
     return mx + my <= rm * rm * (1.0 - 1e-12);
 }
 
+// Epilogue of one image row: lane holds pixels xs + 4g + r (r = 0..3) of
+// channel nb*16 + li of every 16-channel block nb.
+template <int KIN, int NOUT, int EPI>
+__device__ __forceinline__ void conv_epilogue(const NetConvArgs &a, const floatx4 *acc, int b, int y, int xs, int li,
+                                              int g, int WS, double gx, double gy) {
+    constexpr int NB = NOUT / 16;
+    const int h = a.h, w = a.w;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ch = nb * 16 + li;
+        if (EPI == kEpiShuffle) {
+            // channel c*16 + 4i + j -> output (c, 4y + i, 4x + j); c = nb
+            const float bias = a.bias[ch];
+            const int i = li >> 2, j = li & 3;
+            const int H4 = 4 * h, W4 = 4 * w;
+            const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)nb * h * w;
+            float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)nb * H4 * W4;
+            const int Y = 4 * y + i;
+            float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
+            sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
+            const float fy0 = floorf(sy);
+            const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
+            const float wy = sy - fy0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = xs + 4 * g + r;
+                if (x < w) {
+                    const int X = 4 * x + j;
+                    float sx = ((float)X + 0.5f) * 0.25f - 0.5f;
+                    sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
+                    const float fx0 = floorf(sx);
+                    const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
+                    const float wx = sx - fx0;
+                    const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
+                    const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
+                    bool put = true;
+                    if (a.gv) {  // frame mode: only the composite's periphery (outside r_mid)
+                        const double dx = ((double)X + 0.5) - gx, dy = ((double)Y + 0.5) - gy;
+                        put = dx * dx + dy * dy > a.rm * a.rm;
+                    }
+                    if (put) dst[(int64_t)Y * W4 + X] = (acc[nb][r] + bias) + ((1.0f - wy) * top + wy * bot);
+                }
+            }
+        } else {
+            uint16_t q[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = xs + 4 * g + r;
+                float v = acc[nb][r];
+                if (EPI == kEpiRelu) {
+                    v = fmaxf(v + a.bias[ch], 0.0f);
+                } else {
+                    // active where the forward activation is positive (bf16 bits as int16 > 0)
+                    const bool on = x < w && (int16_t)a.mask[(((int64_t)b * h + y) * w + x) * NOUT + ch] > 0;
+                    v = on ? v : 0.0f;
+                }
+                q[r] = bf16_bits(v);
+                if (x < w && a.out) a.out[(((int64_t)b * h + y) * w + x) * NOUT + ch] = q[r];
+            }
+            if (a.out_chw) {
+                uint16_t *o = a.out_chw + (((int64_t)b * NOUT + ch) * (h + 2) + y + 1) * WS + 8 + xs + 4 * g;
+                if (xs + 4 * g + 3 < w) {
+                    uint2 pk;
+                    pk.x = q[0] | ((uint32_t)q[1] << 16);
+                    pk.y = q[2] | ((uint32_t)q[3] << 16);
+                    *reinterpret_cast<uint2 *>(o) = pk;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (xs + 4 * g + r < w) o[r] = q[r];
+                }
+            }
+        }
+    }
+}
+
+// Epilogue of the last layer for one image row, through LDS: the wave's 16
+// pixels x 48 channels are staged, then lane l produces output column
+// X = 4 xs + l (pixel x = xs + l/4, j = l%4) of the four output rows and three
+// colour channels: out(c, 4y+i, X) = y3[x][c*16 + 4i + j] + b3 + bilinear,
+// so every store writes 64 consecutive floats.
+constexpr int kShufStride = 49;  // floats per staged pixel (48 channels + 1: bank spread)
+
+__device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const floatx4 *acc, float *st, int b, int y,
+                                                 int xs, int li, int g, int lane, double gx, double gy) {
+    const int h = a.h, w = a.w;
+#pragma unroll
+    for (int nb = 0; nb < 3; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) st[(4 * g + r) * kShufStride + nb * 16 + li] = acc[nb][r];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int x = xs + (lane >> 2), j = lane & 3;
+    if (x < w) {
+        const int H4 = 4 * h, W4 = 4 * w;
+        const int X = 4 * x + j;
+        float sx = ((float)X + 0.5f) * 0.25f - 0.5f;
+        sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
+        const float fx0 = floorf(sx);
+        const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
+        const float wx = sx - fx0;
+        const float *px = st + (lane >> 2) * kShufStride;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int Y = 4 * y + i;
+            if (a.gv) {  // frame mode: only the composite's periphery (outside r_mid)
+                const double dx = ((double)X + 0.5) - gx, dy = ((double)Y + 0.5) - gy;
+                if (!(dx * dx + dy * dy > a.rm * a.rm)) continue;
+            }
+            float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
+            sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
+            const float fy0 = floorf(sy);
+            const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
+            const float wy = sy - fy0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)c * h * w;
+                float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)c * H4 * W4;
+                const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
+                const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
+                const int ch = c * 16 + 4 * i + j;
+                dst[(int64_t)Y * W4 + X] = (px[ch] + a.bias[ch]) + ((1.0f - wy) * top + wy * bot);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the staging area is reused by the next row
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KIN, int NOUT, int EPI>
 __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     constexpr int KS = KIN + 8;                       // padded LDS row (bank spread, 16-byte aligned)
@@ -129,6 +260,7 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     constexpr int NKS = (KTOT + 31) / 32;
     constexpr int NB = NOUT / 16;
     __shared__ __attribute__((aligned(16))) uint16_t wl[9 * NOUT * KS];
+    __shared__ float shuf[EPI == kEpiShuffle ? 4 * 16 * kShufStride : 1];
     const int tid = threadIdx.x;
     // weights [9][NOUT][KIN] -> LDS, 16 bytes per thread per step
     for (int c = tid; c < 9 * NOUT * KIN / 8; c += 256) {
@@ -152,101 +284,53 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
         gx = a.gv[(int64_t)b * a.gv_stride].v.gx;
         gy = a.gv[(int64_t)b * a.gv_stride].v.gy;
     }
-    for (int y = y0; y < y0 + a.rows && y < h; ++y) {
-        if (a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1), max(y - HALO, 0), min(y + HALO, h - 1),
-                               gx, gy, a.rm))
-            continue;  // wave-uniform
-        floatx4 acc[NB];
+    // two image rows per pass: each weight fragment read from LDS feeds two
+    // matrix-core instructions (one per row)
+    for (int y = y0; y < y0 + a.rows && y < h; y += 2) {
+        const bool has1 = y + 1 < y0 + a.rows && y + 1 < h;
+        const bool skip0 = a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1), max(y - HALO, 0),
+                                              min(y + HALO, h - 1), gx, gy, a.rm);
+        const bool skip1 = !has1 || (a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1),
+                                                        max(y + 1 - HALO, 0), min(y + 1 + HALO, h - 1), gx, gy, a.rm));
+        if (skip0 && skip1) continue;  // wave-uniform
+        floatx4 acc[2][NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[r][nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k0 = 32 * s + 8 * g;
-            uint4 av = {0u, 0u, 0u, 0u};
+            uint4 av0 = {0u, 0u, 0u, 0u}, av1 = {0u, 0u, 0u, 0u};
             int tap = 0, c0 = 0;
             const bool kval = k0 < KTOT;
             if (kval) {
                 tap = k0 / KIN;
                 c0 = k0 - tap * KIN;
                 const int py = y + tap / 3 - 1, px = xs + li + tap % 3 - 1;
-                if (py >= 0 && py < h && px >= 0 && px < w)
-                    av = *reinterpret_cast<const uint4 *>(in + ((int64_t)py * w + px) * KIN + c0);
+                if (px >= 0 && px < w) {
+                    if (py >= 0 && py < h)
+                        av0 = *reinterpret_cast<const uint4 *>(in + ((int64_t)py * w + px) * KIN + c0);
+                    if (has1 && py + 1 >= 0 && py + 1 < h)
+                        av1 = *reinterpret_cast<const uint4 *>(in + ((int64_t)(py + 1) * w + px) * KIN + c0);
+                }
             }
-            const bf16x8 A = as_bf16x8(av);
+            const bf16x8 A0 = as_bf16x8(av0), A1 = as_bf16x8(av1);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 uint4 bv = {0u, 0u, 0u, 0u};
                 if (kval) bv = *reinterpret_cast<const uint4 *>(&wl[(tap * NOUT + nb * 16 + li) * KS + c0]);
-                acc[nb] = mfma16(A, as_bf16x8(bv), acc[nb]);
+                acc[0][nb] = mfma16(A0, as_bf16x8(bv), acc[0][nb]);
+                if (has1) acc[1][nb] = mfma16(A1, as_bf16x8(bv), acc[1][nb]);  // wave-uniform
             }
         }
-        // epilogue: lane holds pixels xs + 4g + r (r = 0..3) of channel nb*16 + li
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int ch = nb * 16 + li;
-            if (EPI == kEpiShuffle) {
-                // channel c*16 + 4i + j -> output (c, 4y + i, 4x + j); c = nb
-                const float bias = a.bias[ch];
-                const int i = li >> 2, j = li & 3;
-                const int H4 = 4 * h, W4 = 4 * w;
-                const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)nb * h * w;
-                float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)nb * H4 * W4;
-                const int Y = 4 * y + i;
-                float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
-                sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
-                const float fy0 = floorf(sy);
-                const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
-                const float wy = sy - fy0;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int x = xs + 4 * g + r;
-                    if (x < w) {
-                        const int X = 4 * x + j;
-                        float sx = ((float)X + 0.5f) * 0.25f - 0.5f;
-                        sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
-                        const float fx0 = floorf(sx);
-                        const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
-                        const float wx = sx - fx0;
-                        const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
-                        const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
-                        bool put = true;
-                        if (a.gv) {  // frame mode: only the composite's periphery (outside r_mid)
-                            const double dx = ((double)X + 0.5) - gx, dy = ((double)Y + 0.5) - gy;
-                            put = dx * dx + dy * dy > a.rm * a.rm;
-                        }
-                        if (put) dst[(int64_t)Y * W4 + X] = (acc[nb][r] + bias) + ((1.0f - wy) * top + wy * bot);
-                    }
-                }
-            } else {
-                uint16_t q[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int x = xs + 4 * g + r;
-                    float v = acc[nb][r];
-                    if (EPI == kEpiRelu) {
-                        v = fmaxf(v + a.bias[ch], 0.0f);
-                    } else {
-                        // active where the forward activation is positive (bf16 bits as int16 > 0)
-                        const bool on = x < w && (int16_t)a.mask[(((int64_t)b * h + y) * w + x) * NOUT + ch] > 0;
-                        v = on ? v : 0.0f;
-                    }
-                    q[r] = bf16_bits(v);
-                    if (x < w && a.out) a.out[(((int64_t)b * h + y) * w + x) * NOUT + ch] = q[r];
-                }
-                if (a.out_chw) {
-                    uint16_t *o = a.out_chw + (((int64_t)b * NOUT + ch) * (h + 2) + y + 1) * WS + 8 + xs + 4 * g;
-                    if (xs + 4 * g + 3 < w) {
-                        uint2 pk;
-                        pk.x = q[0] | ((uint32_t)q[1] << 16);
-                        pk.y = q[2] | ((uint32_t)q[3] << 16);
-                        *reinterpret_cast<uint2 *>(o) = pk;
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (xs + 4 * g + r < w) o[r] = q[r];
-                    }
-                }
-            }
+        for (int rr = 0; rr < 2; ++rr) {
+            if (rr == 1 && !has1) break;
+            if (EPI == kEpiShuffle)
+                shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy);
+            else
+                conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], b, y + rr, xs, li, g, WS, gx, gy);
         }
     }
 }
