@@ -324,6 +324,7 @@ def main():
         extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options)
         extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
         extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
+        extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
         extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
         extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
@@ -448,6 +449,50 @@ def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, met
         res[name] = dict(ms_per_frame=ms, periphery_psnr_db=min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)))
         log(f"frame {name}: {ms:.3f} ms")
     method_options(ctx)
+    return res
+
+
+def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=4, loads=(1.0, 2.0)):
+    """Algorithm 1: a stand-in gaze tracker publishes the early-exit predictions
+    at the network's per-exit CPU latencies (Table 2, Orin CPU; load scales
+    them, standing for a busier CPU) while this GPU renders round 0 at once and
+    then incremental rounds on the newest prediction.  Latency with sensing and
+    transfer T_s = 1 ms, T_c = 1 ms (Sec. 3.1): T_s + T_c + max(T_d, T_r)
+    against the sequential T_s + T_c + T_d + T_r (the foveated frame rendered
+    after the last prediction).  The tracker's times are the paper's, not this
+    host's: the figures say how much of the rendering the GPU hides."""
+    import statistics as stats
+    from paper_2507_04147_amd import pipeline
+    W, H = cams[0].width, cams[0].height
+    trials, sig = synth.gaze_exits(seed=71, n_trials=n_trials, width=W, height=H)
+    c = pkg.Context()
+    method_options(c)
+    c.set_fallback(float("inf"), 1.0, 1.0)
+    out = torch.empty((2, 3, H, W), device="cuda")
+    t_sc = 2.0
+    res = {}
+    for load in loads:
+        rows = []
+        for final, exits in trials:
+            r = pipeline.run(c, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
+                             torch.cuda.synchronize, load=load, out=out)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            c.render_foveated(ds, cams, final, fov, out)
+            torch.cuda.synchronize()
+            sfr = (time.perf_counter() - t) * 1000.0
+            t_d = r["exit_ms"][-1]
+            rows.append(dict(t_d=t_d, done=r["render_done_ms"], after_last=r["render_done_ms"] - t_d, sfr=sfr,
+                             rounds=len(r["events"]) - 2))
+        med = lambda k: stats.median(x[k] for x in rows)
+        a3fr, seq = t_sc + med("done"), t_sc + med("t_d") + med("sfr")
+        res[f"load_{load:g}"] = dict(tracker_ms=med("t_d"), render_after_last_prediction_ms=med("after_last"),
+                                     sequential_render_ms=med("sfr"), total_latency_ms=a3fr,
+                                     sequential_total_latency_ms=seq, speedup=seq / a3fr,
+                                     incremental_rounds=med("rounds"))
+        log(f"Algorithm 1, load {load:g}: total {a3fr:.2f} ms vs sequential {seq:.2f} ms "
+            f"(rendering left after the last prediction {med('after_last'):.3f} ms)")
+    c.close()
     return res
 
 

@@ -146,3 +146,33 @@ def test_incremental_call_order_and_args(pkg):
     assert e.value.status == pkg.A3FR_ENOTREADY
     ctx.sync()
     ctx.close()
+
+
+@pytest.mark.parametrize("load", [0.05, 0.5])
+def test_concurrent_pipeline_frame_is_exact(pkg, load):
+    """Algorithm 1 with a stand-in tracker publishing exits at the network's
+    latencies (scaled by load, so which rounds run depends on timing): the frame
+    is the one-shot frame of the last prediction whatever the rounds were, the
+    rounds follow the exits in order and the finish comes after the last exit."""
+    from paper_2507_04147_amd import pipeline
+    W, H = 464, 480
+    scene, cams, trials, sig, rad = _setup(100_000, W, H, 7, 2)
+    ds = pkg.DeviceScene.from_host(scene)
+    fov = pkg.fovea_struct(*rad)
+    ctx = pkg.Context()
+    for final, exits in trials:
+        out = torch.full((2, 3, H, W), float("nan"), device="cuda")
+        res = pipeline.run(ctx, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
+                           torch.cuda.synchronize, load=load, out=out)
+        ref = torch.zeros_like(out)
+        ctx.render_foveated(ds, cams, final, fov, ref)
+        ctx.sync()
+        assert torch.equal(out, ref)
+        ev = res["events"]
+        assert ev[0][0] == "round 0" and ev[-1][0] == "finish"
+        layers = [e[1] for e in ev[1:]]
+        assert layers == sorted(layers) and layers[-1] == len(synth.EXIT_LATENCY_MS)
+        assert ev[-1][2] >= res["exit_ms"][-1] - 1e-6  # the finish starts once the last exit is published
+        for a, b in zip(ev, ev[1:]):
+            assert b[2] >= a[3] - 1e-6  # one round at a time
+    ctx.close()
