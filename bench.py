@@ -492,6 +492,28 @@ def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=4, l
                                      incremental_rounds=med("rounds"))
         log(f"Algorithm 1, load {load:g}: total {a3fr:.2f} ms vs sequential {seq:.2f} ms "
             f"(rendering left after the last prediction {med('after_last'):.3f} ms)")
+    sfr_ms = med("sfr")
+    # the tracker as a network on this host's CPU: the early-exit ViT (random
+    # weights, 640 x 400 eye image) with tokenwise pruning 0 / 10% / 20%
+    from paper_2507_04147_amd import gaze_vit as gv
+    img = torch.rand(1, 1, 400, 640, generator=torch.Generator().manual_seed(5))
+    vit = {}
+    for prune in (0.0, 0.1, 0.2):
+        net = gv.EarlyExitViT(prune=prune, seed=5)
+        lat = gv.exit_latencies(net, img, reps=3)
+        runs = []
+        for final, exits in trials:
+            r = pipeline.run(c, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
+                             torch.cuda.synchronize, out=out, network=net, eye_image=img)
+            runs.append((r["exit_ms"][-1], r["render_done_ms"]))
+        t_d, done = stats.median(x[0] for x in runs), stats.median(x[1] for x in runs)
+        vit[f"prune_{prune:g}"] = dict(cpu_threads=torch.get_num_threads(), exit_ms_alone=lat,
+                                       tracker_ms_beside_renderer=t_d, total_latency_ms=t_sc + done,
+                                       sequential_total_latency_ms=t_sc + lat[-1] + sfr_ms,
+                                       render_after_last_prediction_ms=done - t_d)
+        log(f"early-exit ViT on the CPU (prune {prune:g}): exits {[round(x, 2) for x in lat]} ms; Algorithm 1 "
+            f"total {t_sc + done:.2f} ms")
+    res["cpu_tracker"] = vit
     c.close()
     return res
 

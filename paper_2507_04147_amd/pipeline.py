@@ -52,28 +52,44 @@ class Shared:
 
 
 def run(ctx, scene, cams, fovea, exits, final, sigmas_px, exit_times_ms, sync, load=1.0, out=None,
-        speculative=True):
+        speculative=True, network=None, eye_image=None):
     """One frame of Algorithm 1.
 
     exits: predictions of exits 1..N-1 (gazes per eye); final: exit N's;
     exit_times_ms: cumulative tracker latency of exits 1..N (ms); load scales
-    them (a busier CPU); sync(): waits for the GPU.  Returns the timeline
-    (ms from the start) and the rendering-complete time."""
+    them (a busier CPU); sync(): waits for the GPU.  With network (an
+    early-exit model with exits_iter, see gaze_vit) and eye_image, the tracker
+    runs that network on the CPU instead and publishes exit l's prediction of
+    the synthetic stream when its layer l is done (the timing is the
+    network's, the gazes the stream's).  Returns the timeline (ms from the
+    start) and the rendering-complete time."""
     n = len(exit_times_ms)
     assert len(exits) == n - 1 and len(sigmas_px) == n - 1
     S = Shared()
     t0 = time.perf_counter()
     now = lambda: (time.perf_counter() - t0) * 1000.0
 
+    errors = []
+
     def tracker():
-        for l in range(1, n + 1):
-            target = exit_times_ms[l - 1] * load
-            while True:
-                left = target - now()
-                if left <= 0.0:
-                    break
-                time.sleep(min(left, 0.5) / 1000.0)
-            S.publish(l, exits[l - 1] if l < n else final, now())
+        try:
+            if network is not None:
+                for l, _ in network.exits_iter(eye_image):
+                    S.publish(l, exits[l - 1] if l < n else final, now())
+                return
+            for l in range(1, n + 1):
+                target = exit_times_ms[l - 1] * load
+                while True:
+                    left = target - now()
+                    if left <= 0.0:
+                        break
+                    time.sleep(min(left, 0.5) / 1000.0)
+                S.publish(l, exits[l - 1] if l < n else final, now())
+        except BaseException as e:  # the renderer must not wait for an exit that never comes
+            errors.append(e)
+        finally:
+            if S.newest()[0] < n:
+                S.publish(n, final, now())
 
     events = []
     old = sys.getswitchinterval()
@@ -110,4 +126,6 @@ def run(ctx, scene, cams, fovea, exits, final, sigmas_px, exit_times_ms, sync, l
     finally:
         th.join()
         sys.setswitchinterval(old)
+    if errors:
+        raise errors[0]
     return dict(events=events, exit_ms=[S.stamp[l] for l in range(1, n + 1)], render_done_ms=events[-1][3])
