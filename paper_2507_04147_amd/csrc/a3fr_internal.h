@@ -212,5 +212,12 @@ void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm,
                        int nblk, hipStream_t s);
 void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+constexpr int kFillSegs = 4;
+struct FillSegs {
+    uint32_t *p[kFillSegs];
+    int64_t n[kFillSegs];  // words; only the first count are used
+    int count;
+};
+void launch_zero_segs(const FillSegs &f, hipStream_t s);
 
 }  // namespace a3fr

@@ -565,9 +565,12 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
                                                        (c->hviews[fp.pv].tiles_x + 1));
         TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)(maxcells * drop_energy_parts())));
         TRY(ensure(c, c->fb_count, 16));
-        launch_fill_u32(P<uint32_t>(c->fb_count), 0u, 1, c->stream);
-        launch_fill_u32(P<uint32_t>(c->fb_energy), 0u, 2 * toff, c->stream);
-        launch_fill_u32(P<uint32_t>(c->fb_diff), 0u, 2 * dwords, c->stream);
+        FillSegs z{};
+        z.p[0] = P<uint32_t>(c->fb_count), z.n[0] = 1;
+        z.p[1] = P<uint32_t>(c->fb_energy), z.n[1] = 2 * toff;
+        z.p[2] = P<uint32_t>(c->fb_diff), z.n[2] = 2 * dwords;
+        z.count = 3;
+        launch_zero_segs(z, c->stream);
         int64_t doff = 0;
         for (const auto &fp : c->fb_plan) {
             launch_drop_energy(dv, fp.pv, c->hviews[fp.pv].tiles_x, c->hviews[fp.pv].tiles_y, n,

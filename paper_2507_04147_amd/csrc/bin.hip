@@ -687,6 +687,28 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
+// Zeroes up to kFillSegs buffers in one launch (the segments are walked as one
+// concatenated range).
+__global__ void k_zero_segs(FillSegs f) {
+    int64_t total = 0;
+    for (int k = 0; k < f.count; ++k) total += f.n[k];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = j;
+        int k = 0;
+        while (r >= f.n[k]) r -= f.n[k++];
+        f.p[k][r] = 0u;
+    }
+}
+
+void launch_zero_segs(const FillSegs &f, hipStream_t s) {
+    int64_t total = 0;
+    for (int k = 0; k < f.count; ++k) total += f.n[k];
+    if (total <= 0) return;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_segs, dim3((unsigned)blocks), dim3(256), 0, s, f);
+}
+
 int64_t emit_chunks(int64_t K) { return (K + kEmitChunk - 1) / kEmitChunk; }
 
 void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,

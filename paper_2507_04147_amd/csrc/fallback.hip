@@ -127,8 +127,10 @@ __global__ void __launch_bounds__(256) k_drop_reduce(const double *__restrict__ 
     const int c = threadIdx.x & 15, slice = threadIdx.x >> 4;
     const int k = blockIdx.x * 16 + c;
     double acc = 0.0;
-    if (k < cells)
+    if (k < cells) {
+#pragma unroll 8
         for (int g = slice; g < nparts; g += 16) acc += partials[(int64_t)g * cells + k];
+    }
     red[slice][c] = acc;
     __syncthreads();
     if (slice == 0 && k < cells) {
@@ -139,9 +141,9 @@ __global__ void __launch_bounds__(256) k_drop_reduce(const double *__restrict__ 
     }
 }
 
-// Persistent blocks of the mass maps: two per compute unit of the MI355X, so
+// Persistent blocks of the mass maps: one per compute unit of the MI355X, so
 // each thread visits a few Gaussians and the dependent loads overlap.
-int drop_energy_parts() { return 512; }
+int drop_energy_parts() { return 256; }
 
 void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score, double *diff,

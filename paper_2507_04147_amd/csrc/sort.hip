@@ -297,22 +297,41 @@ void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint
 // ------------------------------------------------------------------------
 // tile ranges from the sorted tile ids
 // ------------------------------------------------------------------------
-__global__ void k_ranges(const uint32_t *__restrict__ tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles,
-                         uint32_t *__restrict__ ranges) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per tile: its range [start, end) in the sorted tile ids by two
+// binary searches (lower bounds of t and t + 1); an empty tile gets (0, 0).
+// Threads of a wave search neighbouring tiles, so the upper levels of the
+// searches hit the same cache lines.
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, len = n;
+    while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (a[lo + half] < v) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_ranges(const uint32_t *__restrict__ tiles, int64_t K, const uint32_t *K_dev,
+                                                int64_t ntiles, uint32_t *__restrict__ ranges) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode
-    if (j >= K) return;
-    const uint32_t t = tiles[j];
-    if ((int64_t)t >= ntiles) return;
-    if (j == 0 || tiles[j - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)j;
-    if (j == K - 1 || tiles[j + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(j + 1);
+    const uint32_t n = (uint32_t)K;
+    const uint32_t s0 = lower_bound_u32(tiles, n, (uint32_t)t);
+    const uint32_t s1 = lower_bound_u32(tiles, n, (uint32_t)t + 1u);
+    ranges[2 * t] = s0 == s1 ? 0u : s0;
+    ranges[2 * t + 1] = s0 == s1 ? 0u : s1;
 }
 
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
                    hipStream_t s) {
-    launch_fill_u32(ranges, 0u, 2 * ntiles, s);
-    if (K == 0) return;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, tiles, K, K_dev, ntiles, ranges);
+    if (ntiles == 0) return;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, tiles, K, K_dev, ntiles,
+                       ranges);
 }
 
 }  // namespace a3fr

@@ -88,12 +88,17 @@ class Upsampler:
         return self.loss
 
     def fit(self, xs, ts, epochs=20, batch=32, lr=1e-3, seed=0):
-        """Adam on mini-batches of a seeded permutation each epoch; returns the
-        mean training loss of each epoch."""
+        """Adam on mini-batches of a seeded permutation each epoch; lr is one
+        rate or one per epoch (a step schedule).  Returns the mean training
+        loss of each epoch."""
         n = xs.shape[0]
         rng = np.random.default_rng(seed)
+        rates = list(lr) if isinstance(lr, (list, tuple)) else [lr] * epochs
+        if len(rates) != epochs:
+            raise ValueError("one learning rate per epoch")
         hist = []
-        for _ in range(epochs):
+        for ep in range(epochs):
+            lr = rates[ep]
             perm = torch.as_tensor(rng.permutation(n), device="cuda")
             tot, cnt = torch.zeros(1, device="cuda"), 0
             for s in range(0, n - batch + 1, batch):
