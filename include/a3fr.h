@@ -375,7 +375,8 @@ a3fr_status a3fr_net_forward(a3fr_ctx *ctx, const float *theta_dev, const float 
                              int32_t w, float *out_dev, int32_t for_training);
 
 /* Mean squared error of the last training forward's out_dev against
- * target_dev (float32 [B][3][4h][4w]) and its gradient with respect to theta:
+ * target_dev (float32 [B][3][4h][4w], both 16-byte aligned, else
+ * A3FR_EINVAL) and its gradient with respect to theta:
  * grad_dev (float32 [A3FR_NET_PARAMS], overwritten); loss_dev (float32 [1],
  * may be NULL) receives the loss.  The gradient entering each convolution's
  * weight and input gradients is rounded to bfloat16 (matrix-core operands);

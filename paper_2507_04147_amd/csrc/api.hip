@@ -1293,6 +1293,8 @@ a3fr_status a3fr_net_backward(a3fr_ctx *c, const float *theta, const float *out,
     if (!c) return A3FR_EINVAL;
     if (!c->net_trained_fwd) return fail(c, A3FR_ENOTREADY, "net_backward needs a net_forward with for_training = 1");
     if (!theta || !out || !target || !grad) return fail(c, A3FR_EINVAL, "net_backward: NULL pointer");
+    if ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(target)) & 15u)
+        return fail(c, A3FR_EINVAL, "net_backward: out and target must be 16-byte aligned");
     const int B = c->net_B, h = c->net_h, w = c->net_w;
     const NetPacked pk = net_packed(c);
     launch_fill_u32(reinterpret_cast<uint32_t *>(grad), 0u, kNetParams, c->stream);

@@ -342,6 +342,8 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
 // load of 8 pixels and two single-pixel loads (funnel-shifted with
 // alignbyte).  A = g^T (M = co, K = pixels), B = in (K = pixels, N = ci).
 // ---------------------------------------------------------------------------
+constexpr int kWgradUnroll = 4;
+
 template <int CIN, int KIN, int NOUT>
 __global__ void __launch_bounds__(64) k_net_wgrad(NetWgradArgs a) {
     constexpr int NBK = (KIN + 15) / 16;
@@ -358,41 +360,55 @@ __global__ void __launch_bounds__(64) k_net_wgrad(NetWgradArgs a) {
     for (int d = 0; d < 3; ++d) acc[d] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     float dbias = 0.0f;
     const bool do_bias = nb == 0 && dy == 0;
-    for (int64_t c = blockIdx.y; c < chunks; c += gridDim.y) {
-        const int xc = (int)(c % xchunks) * 32;
-        const int64_t by = c / xchunks;
-        const int y = (int)(by % h);
-        const int b = (int)(by / h);
-        const int p = xc + 8 * g;
-        const uint4 av = *reinterpret_cast<const uint4 *>(
-            a.g + (((int64_t)b * NOUT + co) * (h + 2) + y + 1) * WS + 8 + p);
-        if (do_bias) {
-            const uint32_t wd[4] = {av.x, av.y, av.z, av.w};
+    // kWgradUnroll chunks per step, their loads issued before any product so
+    // that several round trips to memory overlap
+    for (int64_t c0 = blockIdx.y; c0 < chunks; c0 += (int64_t)kWgradUnroll * gridDim.y) {
+        uint4 av[kWgradUnroll], bc[kWgradUnroll];
+        uint32_t left[kWgradUnroll], right[kWgradUnroll];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dbias += bf16_val((uint16_t)(wd[k] & 0xffffu)) + bf16_val((uint16_t)(wd[k] >> 16));
+        for (int u = 0; u < kWgradUnroll; ++u) {
+            const int64_t c = c0 + (int64_t)u * gridDim.y;
+            av[u] = uint4{0u, 0u, 0u, 0u};
+            bc[u] = uint4{0u, 0u, 0u, 0u};
+            left[u] = right[u] = 0u;
+            if (c < chunks) {
+                const int xc = (int)(c % xchunks) * 32;
+                const int64_t by = c / xchunks;
+                const int y = (int)(by % h);
+                const int b = (int)(by / h);
+                const int p = xc + 8 * g;
+                av[u] = *reinterpret_cast<const uint4 *>(a.g + (((int64_t)b * NOUT + co) * (h + 2) + y + 1) * WS + 8 + p);
+                if (cival) {
+                    const uint16_t *row = a.in + (((int64_t)b * KIN + ci) * (h + 2) + y + 1 + dy) * WS + 8 + p;
+                    bc[u] = *reinterpret_cast<const uint4 *>(row);
+                    left[u] = row[-1];
+                    right[u] = row[8];
+                }
+            }
         }
-        uint4 bc = {0u, 0u, 0u, 0u};
-        uint32_t left = 0u, right = 0u;
-        if (cival) {
-            const uint16_t *row = a.in + (((int64_t)b * KIN + ci) * (h + 2) + y + 1 + dy) * WS + 8 + p;
-            bc = *reinterpret_cast<const uint4 *>(row);
-            left = row[-1];
-            right = row[8];
+#pragma unroll
+        for (int u = 0; u < kWgradUnroll; ++u) {
+            if (do_bias) {
+                const uint32_t wd[4] = {av[u].x, av[u].y, av[u].z, av[u].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    dbias += bf16_val((uint16_t)(wd[k] & 0xffffu)) + bf16_val((uint16_t)(wd[k] >> 16));
+            }
+            // pixels p-1 .. p+6 and p+1 .. p+8
+            uint4 bm, bp;
+            bm.x = __builtin_amdgcn_alignbyte(bc[u].x, left[u] << 16, 2);
+            bm.y = __builtin_amdgcn_alignbyte(bc[u].y, bc[u].x, 2);
+            bm.z = __builtin_amdgcn_alignbyte(bc[u].z, bc[u].y, 2);
+            bm.w = __builtin_amdgcn_alignbyte(bc[u].w, bc[u].z, 2);
+            bp.x = __builtin_amdgcn_alignbyte(bc[u].y, bc[u].x, 2);
+            bp.y = __builtin_amdgcn_alignbyte(bc[u].z, bc[u].y, 2);
+            bp.z = __builtin_amdgcn_alignbyte(bc[u].w, bc[u].z, 2);
+            bp.w = __builtin_amdgcn_alignbyte(right[u], bc[u].w, 2);
+            const bf16x8 A = as_bf16x8(av[u]);
+            acc[0] = mfma16(A, as_bf16x8(bm), acc[0]);
+            acc[1] = mfma16(A, as_bf16x8(bc[u]), acc[1]);
+            acc[2] = mfma16(A, as_bf16x8(bp), acc[2]);
         }
-        // pixels p-1 .. p+6 and p+1 .. p+8
-        uint4 bm, bp;
-        bm.x = __builtin_amdgcn_alignbyte(bc.x, left << 16, 2);
-        bm.y = __builtin_amdgcn_alignbyte(bc.y, bc.x, 2);
-        bm.z = __builtin_amdgcn_alignbyte(bc.z, bc.y, 2);
-        bm.w = __builtin_amdgcn_alignbyte(bc.w, bc.z, 2);
-        bp.x = __builtin_amdgcn_alignbyte(bc.y, bc.x, 2);
-        bp.y = __builtin_amdgcn_alignbyte(bc.z, bc.y, 2);
-        bp.z = __builtin_amdgcn_alignbyte(bc.w, bc.z, 2);
-        bp.w = __builtin_amdgcn_alignbyte(right, bc.w, 2);
-        const bf16x8 A = as_bf16x8(av);
-        acc[0] = mfma16(A, as_bf16x8(bm), acc[0]);
-        acc[1] = mfma16(A, as_bf16x8(bc), acc[1]);
-        acc[2] = mfma16(A, as_bf16x8(bp), acc[2]);
     }
     // D lane: rows co = 16 mb + 4g + r, column ci = 16 nb + li
     if (ci < CIN) {
@@ -417,30 +433,56 @@ __global__ void __launch_bounds__(64) k_net_wgrad(NetWgradArgs a) {
 // loss: mean squared error; dL/dy3 = unshuffle(2 (out - target) / N) in bf16
 // (NHWC48 and the channel-major copy); sum of squares accumulated in float64
 // ---------------------------------------------------------------------------
+// One thread per low-resolution pixel (x fastest): its 48 gradient channels
+// come from 3 colours x 4 rows x 4 contiguous output pixels (16-byte loads,
+// coalesced across the wave), its NHWC48 row is written as six 16-byte
+// stores and each channel-major plane gets one coalesced 2-byte store per
+// lane.  The sum of squares is reduced in the block, one atomic per block.
 __global__ void __launch_bounds__(256) k_net_mse(const float *__restrict__ out, const float *__restrict__ target,
                                                  int B, int h, int w, uint16_t *__restrict__ g_nhwc,
                                                  uint16_t *__restrict__ g_chw, double *__restrict__ sse) {
+    __shared__ double red[4];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_lo = (int64_t)B * h * w * 48;
+    const int64_t npix = (int64_t)B * h * w;
     double e2 = 0.0;
-    if (t < n_lo) {
-        const int ch = (int)(t % 48);
-        const int64_t pix = t / 48;
-        const int x = (int)(pix % w);
-        const int64_t by = pix / w;
+    if (t < npix) {
+        const int x = (int)(t % w);
+        const int64_t by = t / w;
         const int y = (int)(by % h), b = (int)(by / h);
-        const int c = ch >> 4, i = (ch >> 2) & 3, j = ch & 3;
         const int64_t H4 = 4 * (int64_t)h, W4 = 4 * (int64_t)w;
-        const int64_t o = (((int64_t)b * 3 + c) * H4 + 4 * y + i) * W4 + 4 * x + j;
-        const float d = out[o] - target[o];
         const float inv_n = 1.0f / (float)((int64_t)B * 3 * H4 * W4);
-        const uint16_t q = bf16_bits(2.0f * d * inv_n);
-        g_nhwc[t] = q;
-        g_chw[(((int64_t)b * 48 + ch) * (h + 2) + y + 1) * net_chw_stride(w) + 8 + x] = q;
-        e2 = (double)d * (double)d;
+        const int WS = net_chw_stride(w);
+        uint32_t q[24];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t o = (((int64_t)b * 3 + c) * H4 + 4 * y + i) * W4 + 4 * x;
+                const float4 ov = *reinterpret_cast<const float4 *>(out + o);
+                const float4 tv = *reinterpret_cast<const float4 *>(target + o);
+                const float d[4] = {ov.x - tv.x, ov.y - tv.y, ov.z - tv.z, ov.w - tv.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ch = c * 16 + i * 4 + j;
+                    const uint16_t v = bf16_bits(2.0f * d[j] * inv_n);
+                    g_chw[(((int64_t)b * 48 + ch) * (h + 2) + y + 1) * WS + 8 + x] = v;
+                    if (j & 1) q[ch >> 1] |= (uint32_t)v << 16;
+                    else q[ch >> 1] = v;
+                    e2 += (double)d[j] * (double)d[j];
+                }
+            }
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(g_nhwc + t * 48);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[k] = uint4{q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]};
     }
     for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 64);
-    if ((threadIdx.x & 63) == 0 && e2 != 0.0) atomicAdd(sse, e2);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double s4 = red[0] + red[1] + red[2] + red[3];
+        if (s4 != 0.0) atomicAdd(sse, s4);
+    }
 }
 
 __global__ void k_net_loss_final(const double *sse, int64_t n, float *loss) { *loss = (float)(*sse / (double)n); }
@@ -502,7 +544,7 @@ void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s
 
 void launch_net_mse(const float *out, const float *target, int B, int h, int w, uint16_t *g_nhwc, uint16_t *g_chw,
                     double *sse, float *loss, hipStream_t s) {
-    const int64_t n = (int64_t)B * h * w * 48;
+    const int64_t n = (int64_t)B * h * w;
     if (n > 0)
         hipLaunchKernelGGL(k_net_mse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, target, B, h, w, g_nhwc,
                            g_chw, sse);
