@@ -116,11 +116,15 @@ void launch_select(const DevView *views, int nv, const int32_t *sel_views, int n
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
                    uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s);
 int64_t select_workspace_words(int nsel, int64_t n);
+// scan workspace (uint64 words) for m = nv * n entry slots; the compaction
+// clears it, so the key offsets must follow that compaction
+int64_t scan_workspace_words(int64_t m);
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *block_sums,
-                            uint64_t *total, uint32_t *n_ent, hipStream_t s);
+                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
+                            uint32_t *n_ent, uint32_t *err, hipStream_t s);
 void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
-                        uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s);
+                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+                        hipStream_t s);
 // number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
 int64_t emit_chunks(int64_t K);
 void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
@@ -187,20 +191,32 @@ void launch_net_mse(const float *out, const float *target, int B, int h, int w, 
                     double *sse, float *loss, hipStream_t s);
 void launch_net_adam(float *theta, const float *grad, float *m, float *v, int n, float lr, float beta1, float beta2,
                      float eps, float bc1, float bc2, hipStream_t s);
+// The fallback pairs of a frame (one per eye): periphery view pv, its eye's
+// full-resolution view fv, the mid radius, and where the pair's difference
+// planes [2][tiles_y+1][tiles_x+1] (float64) start in the shared buffer.
+constexpr int kFbMax = 16;
+constexpr int kFbLdsBytes = 48 * 1024;
+struct FbBatch {
+    int count;
+    int max_cells;  // largest 2 (tiles_y+1)(tiles_x+1) over the pairs
+    int pv[kFbMax], fv[kFbMax];
+    double r_mid[kFbMax];
+    int64_t doff[kFbMax];
+};
 int drop_energy_parts();
-void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
+void launch_drop_energy(const DevView *views, const FbBatch &b, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score,
-                        double *diff /* zeroed [2][tiles_y+1][tiles_x+1] of view pv */,
-                        double *partials /* [drop_energy_parts()][2][tiles_y+1][tiles_x+1] */, int64_t ntiles,
+                        double *diff /* zeroed planes of every pair, at b.doff */,
+                        double *partials /* [b.count][drop_energy_parts()][b.max_cells] */, int64_t ntiles,
                         float *energy /* [2][ntiles]: dropped mass, kept mass */, hipStream_t s);
-void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
-                           int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
+void launch_fallback_flags(const DevView *views, const FbBatch &b, int64_t max_periph_tiles, const float *energy,
+                           int64_t ntiles, double threshold, double coef, double power, uint8_t *flags,
                            uint8_t *active, uint32_t *n_flagged, hipStream_t s);
 void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
                              const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list,
                              const uint32_t *n_flagged, hipStream_t s);
-void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
-                    uint32_t *counts, const uint32_t *n_flagged, hipStream_t s);
+void launch_recount(const DevView *views, const FbBatch &b, int64_t n, const uint64_t *rect,
+                    const uint16_t *row_prefix, uint32_t *counts, const uint32_t *n_flagged, hipStream_t s);
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full,
                       bool periph_done /* outside r_mid already written (unless fallback-flagged) */,

@@ -488,7 +488,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     TRY(ensure(c, c->keep, c->nsel ? (size_t)m : 16));
     TRY(ensure(c, c->sel, sizeof(uint32_t) * (size_t)select_workspace_words(c->nsel, n)));
     TRY(ensure(c, c->offsets, sizeof(uint32_t) * (m + 1)));
-    TRY(ensure(c, c->block_sums, sizeof(uint64_t) * ((m + 4095) / 4096 + 1)));
+    TRY(ensure(c, c->block_sums, sizeof(uint64_t) * (size_t)scan_workspace_words(m)));
     if (!c->scalars.p) {
         TRY(ensure(c, c->scalars, 64));
         launch_fill_u32(P<uint32_t>(c->scalars), 0u, 16, c->stream);
@@ -526,7 +526,6 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
 static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den) {
     const int64_t n = c->n;
     const int nv = c->nv;
-    const int64_t m = (int64_t)nv * n;
     const int64_t toff = c->ntiles;
     const int32_t *d_row_view = c->d_row_view, *d_row_y = c->d_row_y, *d_sel_views = c->d_sel_views,
                   *d_groups = c->d_groups;
@@ -552,18 +551,29 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     if (!c->fb_plan.empty() && c->nsel) {
         // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
         StageTimer t_(c, A3FR_STAGE_FALLBACK);
-        // difference planes of every periphery view: [2][tiles_y + 1][tiles_x + 1] doubles each
-        int64_t dwords = 0;
-        for (const auto &fp : c->fb_plan)
-            dwords += 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) * (c->hviews[fp.pv].tiles_x + 1);
+        // difference planes of every periphery view: [2][tiles_y + 1][tiles_x + 1] doubles each;
+        // the pairs go in batches of up to kFbMax per launch
+        std::vector<FbBatch> fbs;
+        int64_t dwords = 0, max_ptiles = 0, max_part = 0;
+        for (const auto &fp : c->fb_plan) {
+            if (fbs.empty() || fbs.back().count == kFbMax) fbs.push_back(FbBatch{});
+            FbBatch &fb = fbs.back();
+            const DevView &hp = c->hviews[fp.pv];
+            const int cells = 2 * (hp.tiles_y + 1) * (hp.tiles_x + 1);
+            fb.pv[fb.count] = fp.pv;
+            fb.fv[fb.count] = fp.fv;
+            fb.r_mid[fb.count] = fp.r_mid;
+            fb.doff[fb.count] = dwords;
+            fb.max_cells = std::max(fb.max_cells, cells);
+            ++fb.count;
+            dwords += cells;
+            max_ptiles = std::max<int64_t>(max_ptiles, (int64_t)hp.tiles_x * hp.tiles_y);
+            max_part = std::max<int64_t>(max_part, (int64_t)fb.count * fb.max_cells);
+        }
         TRY(ensure(c, c->fb_energy, sizeof(float) * 2 * (size_t)toff));
         TRY(ensure(c, c->fb_flags, (size_t)toff));
         TRY(ensure(c, c->fb_diff, sizeof(double) * (size_t)dwords));
-        int64_t maxcells = 0;
-        for (const auto &fp : c->fb_plan)
-            maxcells = std::max<int64_t>(maxcells, 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) *
-                                                       (c->hviews[fp.pv].tiles_x + 1));
-        TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)(maxcells * drop_energy_parts())));
+        TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)drop_energy_parts() * (size_t)max_part));
         TRY(ensure(c, c->fb_count, 16));
         FillSegs z{};
         z.p[0] = P<uint32_t>(c->fb_count), z.n[0] = 1;
@@ -571,26 +581,22 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         z.p[2] = P<uint32_t>(c->fb_diff), z.n[2] = 2 * dwords;
         z.count = 3;
         launch_zero_segs(z, c->stream);
-        int64_t doff = 0;
-        for (const auto &fp : c->fb_plan) {
-            launch_drop_energy(dv, fp.pv, c->hviews[fp.pv].tiles_x, c->hviews[fp.pv].tiles_y, n,
-                               P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
-                               P<double>(c->score), P<double>(c->fb_diff) + doff, P<double>(c->fb_part), toff,
+        for (const FbBatch &fb : fbs) {
+            launch_drop_energy(dv, fb, n, P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
+                               P<double>(c->score), P<double>(c->fb_diff), P<double>(c->fb_part), toff,
                                P<float>(c->fb_energy), c->stream);
-            doff += 2 * (int64_t)(c->hviews[fp.pv].tiles_y + 1) * (c->hviews[fp.pv].tiles_x + 1);
+            launch_fallback_flags(dv, fb, max_ptiles, P<float>(c->fb_energy), toff, c->fb_thr, c->fb_coef, c->fb_pow,
+                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), P<uint32_t>(c->fb_count),
+                                  c->stream);
         }
-        for (const auto &fp : c->fb_plan)
-            launch_fallback_flags(dv, fp.pv, fp.fv, (int64_t)c->hviews[fp.pv].tiles_x * c->hviews[fp.pv].tiles_y,
-                                  P<float>(c->fb_energy), toff, fp.r_mid, c->fb_thr, c->fb_coef, c->fb_pow,
-                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), P<uint32_t>(c->fb_count), c->stream);
         launch_rows_from_active(dv, c->rows_total, d_row_view, d_row_y, P<uint8_t>(c->active),
                                 P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->fb_count),
                                 c->stream);
         if (c->cum_entries)
             launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream,
                             P<uint32_t>(c->fb_count));
-        for (const auto &fp : c->fb_plan)
-            launch_recount(dv, fp.fv, n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
+        for (const FbBatch &fb : fbs)
+            launch_recount(dv, fb, n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                            P<uint32_t>(c->fb_count), c->stream);
         c->fb_last = true;
     }
@@ -608,7 +614,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
                                P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
-                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), c->stream);
+                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), sc_err(c->scalars), c->stream);
     }
     if (scene) {
         StageTimer t_(c, A3FR_STAGE_COLOUR);
@@ -631,7 +637,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         launch_key_offsets(P<uint32_t>(c->counts), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m,
                            P<uint32_t>(c->offsets), P<uint64_t>(c->block_sums), sc_key_total(c->scalars),
-                           sc_n_keys(c->scalars), c->stream);
+                           sc_n_keys(c->scalars), sc_err(c->scalars), c->stream);
     }
     TRY(check_launch(c, "preprocess"));
     c->preprocessed = true;
@@ -1048,10 +1054,17 @@ static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, 
                           P<uint16_t>(c->row_list), P<uint8_t>(c->active), P<uint8_t>(c->inc_done), c->stream);
         if (c->cum_entries)
             launch_mask_cum(dv, c->nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream);
+        // fovea and mid layers of every eye, up to kFbMax views per launch
+        FbBatch rb{};
         for (int e = 0; e < ne; ++e)
-            for (int k = 0; k < 2; ++k)
-                launch_recount(dv, 3 * e + k, c->n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix),
-                               P<uint32_t>(c->counts), nullptr, c->stream);
+            for (int k = 0; k < 2; ++k) {
+                rb.fv[rb.count++] = 3 * e + k;
+                if (rb.count == kFbMax || (e == ne - 1 && k == 1)) {
+                    launch_recount(dv, rb, c->n, P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix),
+                                   P<uint32_t>(c->counts), nullptr, c->stream);
+                    rb.count = 0;
+                }
+            }
     }
     c->fb_last = false;
     TRY(entry_stages(c, nullptr));

@@ -262,21 +262,12 @@ constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block
 
 // Entry e = view * n + index contributes keys iff it is visible in its view and,
-// for a selecting view, kept.  A block's 4096 entries span at most two views
-// (n >= 4096) or are resolved per element otherwise.
+// for a selecting view, kept.
 struct EntryFlags {
     const uint32_t *counts;
     const uint8_t *keep;
     const DevView *views;
     int64_t n;
-    __device__ __forceinline__ uint32_t operator()(int64_t e, int64_t m) const {
-        if (e >= m) return 0;
-        if (counts[e] == 0) return 0;
-        const int v = (int)(e / n);
-        if (views[v].v.select && !keep[e]) return 0;
-        return 1;
-    }
-    __device__ __forceinline__ int64_t live(int64_t m) const { return m; }
 };
 
 // Key count of the j-th entry in depth order.
@@ -287,7 +278,6 @@ struct SortedCounts {
     __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
         return j < (int64_t)*n_ent ? counts[ent[j]] : 0u;
     }
-    __device__ __forceinline__ int64_t live(int64_t) const { return (int64_t)*n_ent; }
 };
 
 // wave-level inclusive scan of a 64-bit value (wave64 via shuffles)
@@ -319,137 +309,231 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t *total)
     return wpre + inc - x;
 }
 
-template <class F>
-__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(F f, int64_t m, uint64_t *block_sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    if (base >= f.live(m)) {  // nothing to count in this block (block-uniform)
-        if (threadIdx.x == 0) block_sums[blockIdx.x] = 0;
-        return;
-    }
-    uint64_t acc = 0;
-#pragma unroll 4
-    for (int j = 0; j < kScanItems; ++j) acc += f(base + (int64_t)j * kScanBlock + threadIdx.x, m);
-    uint64_t tot;
-    block_excl_scan(acc, &tot);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+// Single-pass scans with decoupled look-back.  Each block takes its
+// partition (kScanTile consecutive items) from a ticket counter, so a
+// partition's predecessors are already held by running blocks; it publishes
+// its total (flag AGG), then wave 0 walks back over the predecessors' words,
+// 64 at a time, adding totals until it meets an inclusive prefix (flag INC),
+// and publishes its own inclusive prefix.  Status words are 64-bit: flag in
+// the top two bits, value in the low 62, zeroed before the launch.
+// Workspace (uint64): [0] compaction ticket, [1] offsets ticket, then the
+// compaction partitions' words, then the offsets partitions' words.
+constexpr uint64_t kStAgg = 1ull << 62, kStInc = 2ull << 62, kStVal = (1ull << 62) - 1;
+constexpr uint32_t kLookbackSpins = 1u << 22;  // bound on a wait (never expected: a report, not a hang)
+
+__device__ __forceinline__ uint64_t ld_st64(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_st64(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
 }
 
-// one block: exclusive scan of nb block sums in chunks of 1024; writes the
-// grand total as u64 and (clamped) u32
-__global__ void __launch_bounds__(1024) k_scan_blocks(uint64_t *block_sums, int64_t nb, uint64_t *total,
-                                                      uint32_t *total32) {
-    __shared__ uint64_t wsum[16];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
-        const int64_t j = c0 + threadIdx.x;
-        const uint64_t x = j < nb ? block_sums[j] : 0;
-        const uint64_t inc = wave_incl_scan(x);
-        if (lane == 63) wsum[w] = inc;
-        __syncthreads();
-        uint64_t wpre = 0, tot = 0;
-        for (int k = 0; k < 16; ++k) {
-            if (k < w) wpre += wsum[k];
-            tot += wsum[k];
+// Called by all 64 lanes of wave 0 of the block: the exclusive prefix of
+// partition part, whose own total is tot; publishes part's inclusive prefix.
+__device__ uint64_t chained_prefix(uint64_t *status, int64_t part, uint64_t tot, uint32_t *err) {
+    const int lane = threadIdx.x & 63;
+    if (part == 0) {
+        if (lane == 0) st_st64(&status[0], kStInc | tot);
+        return 0;
+    }
+    if (lane == 0) st_st64(&status[part], kStAgg | tot);
+    uint64_t excl = 0;
+    uint32_t spins = 0;
+    for (int64_t top = part - 1;; top -= 64) {
+        const int64_t q = top - lane;
+        uint64_t st = q >= 0 ? ld_st64(&status[q]) : kStInc;  // below partition 0: nothing to add
+        while (__ballot((st >> 62) == 0) != 0) {
+            if (++spins > kLookbackSpins) {
+                if (lane == 0) atomicOr(err, 1u);
+                st = (st >> 62) == 0 ? kStInc : st;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((st >> 62) == 0) st = ld_st64(&status[q]);
         }
-        const uint64_t base = carry;
-        if (j < nb) block_sums[j] = base + wpre + inc - x;
-        __syncthreads();
-        if (threadIdx.x == 0) carry = base + tot;
-        __syncthreads();
+        const uint64_t inc = __ballot((st >> 62) == 2);
+        if (inc) {
+            const int first = __ffsll((unsigned long long)inc) - 1;  // nearest inclusive prefix
+            excl += wave_sum64(lane <= first ? (st & kStVal) : 0ull);
+            break;
+        }
+        excl += wave_sum64(st & kStVal);
     }
-    if (threadIdx.x == 0) {
-        *total = carry;
-        *total32 = carry > 0xffffffffull ? 0xffffffffu : (uint32_t)carry;
-    }
+    if (lane == 0) st_st64(&status[part], kStInc | (excl + tot));
+    return excl;
 }
 
 // Compaction: entry e with flag 1 goes to slot (its exclusive prefix), with
 // its depth bits as sort key.  Each wave takes 1024 consecutive entries in 16
 // rounds of 64 (coalesced), packing the flagged ones with a ballot per round;
-// the waves of a block are combined by the block's exclusive scan.
-__global__ void __launch_bounds__(kScanBlock) k_compact_down(EntryFlags f, int64_t m, const uint64_t *block_pre,
-                                                             const uint32_t *__restrict__ depth,
-                                                             uint32_t *__restrict__ ent, uint32_t *__restrict__ dkey) {
+// the waves of a block are combined in LDS and the blocks by the look-back.
+// All loads of a kind are issued before any is used (counts, then the keep
+// bytes where a selecting view needs them, then the depths of the flagged
+// entries), so a wave waits for three round trips, not one per round.
+__global__ void __launch_bounds__(kScanBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
+                                                        const uint32_t *__restrict__ depth, uint32_t *__restrict__ ent,
+                                                        uint32_t *__restrict__ dkey, uint64_t *total, uint32_t *total32,
+                                                        uint32_t *err) {
+    __shared__ uint32_t s_part;
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    __shared__ uint64_t s_excl;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t wbase = (int64_t)blockIdx.x * kScanTile + (int64_t)w * 64 * kScanItems;
+    if (threadIdx.x == 0) s_part = atomicAdd(reinterpret_cast<uint32_t *>(&ws[0]), 1u);
+    __syncthreads();
+    const int64_t part = s_part;
+    const int64_t wbase = part * kScanTile + (int64_t)w * 64 * kScanItems;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // views of the block's entries: at most two when n >= kScanTile
+    const bool per_elem = f.n < kScanTile;
+    const int64_t v0 = (part * kScanTile) / f.n, b1 = (v0 + 1) * f.n;
+    const bool sel0 = f.views[v0].v.select != 0, sel1 = b1 < m && f.views[v0 + 1].v.select != 0;
+    uint32_t cv[kScanItems];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t e = wbase + r * 64 + lane;
+        cv[r] = e < m ? f.counts[e] : 0u;
+    }
+    if (per_elem || sel0 || sel1) {
+        uint8_t kv[kScanItems];
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            const int64_t e = wbase + r * 64 + lane;
+            bool sel = false;
+            if (cv[r] != 0) sel = per_elem ? f.views[e / f.n].v.select != 0 : (e < b1 ? sel0 : sel1);
+            kv[r] = sel ? f.keep[e] : (uint8_t)1;
+        }
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r)
+            if (kv[r] == 0) cv[r] = 0;
+    }
     uint64_t masks[kScanItems];
+    uint32_t dv[kScanItems];
     uint32_t cnt = 0;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
-        const uint32_t fl = f(wbase + r * 64 + lane, m);
-        masks[r] = __ballot(fl != 0);
+        const int64_t e = wbase + r * 64 + lane;
+        masks[r] = __ballot(cv[r] != 0);
         cnt += (uint32_t)__popcll(masks[r]);
+        dv[r] = cv[r] != 0 ? depth[e] : 0u;
     }
-    // block exclusive scan of the per-wave counts (lane 0 of each wave holds it)
-    __shared__ uint64_t s_w[kScanBlock / 64];
     if (lane == 0) s_w[w] = cnt;
     __syncthreads();
-    uint64_t run = block_pre[blockIdx.x];
+    if (w == 0) {
+        uint64_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < kScanBlock / 64; ++q) tot += s_w[q];
+        const uint64_t excl = chained_prefix(ws + 2, part, tot, err);
+        if (lane == 0) {
+            s_excl = excl;
+            if (part == nb - 1) {
+                *total = excl + tot;
+                *total32 = excl + tot > 0xffffffffull ? 0xffffffffu : (uint32_t)(excl + tot);
+            }
+        }
+    }
+    __syncthreads();
+    uint64_t run = s_excl;
     for (int q = 0; q < w; ++q) run += s_w[q];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t mk = masks[r];
         if ((mk >> lane) & 1ull) {
-            const int64_t e = wbase + r * 64 + lane;
             const uint64_t pos = run + (uint64_t)__popcll(mk & lt);
-            ent[pos] = (uint32_t)e;
-            dkey[pos] = depth[e];
+            ent[pos] = (uint32_t)(wbase + r * 64 + lane);
+            dkey[pos] = dv[r];
         }
         run += (uint64_t)__popcll(mk);
     }
 }
 
-// Offsets of the keys of the entries in depth order; offsets[E] = K.
-__global__ void __launch_bounds__(kScanBlock) k_offsets_down(SortedCounts f, int64_t m, const uint64_t *block_pre,
-                                                             const uint64_t *total, uint32_t *offsets) {
+// Offsets of the keys of the entries in depth order; offsets[E] = K.  The
+// grid is sized for the largest entry count; blocks past the partitions of
+// the device count leave without a ticket.
+__global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t nb_max, uint64_t *ws,
+                                                        uint64_t *total, uint32_t *total32, uint32_t *offsets,
+                                                        uint32_t *err) {
+    __shared__ uint32_t s_part;
+    __shared__ uint64_t s_excl;
     const int64_t E = *f.n_ent;
-    if ((int64_t)blockIdx.x * kScanTile >= E) {  // block-uniform
-        if (blockIdx.x == 0 && threadIdx.x == 0) offsets[E] = (uint32_t)*total;
+    const int64_t nparts = (E + kScanTile - 1) / kScanTile;
+    if (E == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            offsets[0] = 0;
+            *total = 0;
+            *total32 = 0;
+        }
         return;
     }
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    if ((int64_t)blockIdx.x >= nparts) return;  // block-uniform
+    if (threadIdx.x == 0) s_part = atomicAdd(reinterpret_cast<uint32_t *>(&ws[1]), 1u);
+    __syncthreads();
+    const int64_t part = s_part;
+    const int64_t base = part * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t c[kScanItems];
     uint64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        c[j] = f(base + j, m);
+        c[j] = f(base + j, 0);
         acc += c[j];
     }
     uint64_t tot;
-    uint64_t run = block_pre[blockIdx.x] + block_excl_scan(acc, &tot);
+    const uint64_t pre = block_excl_scan(acc, &tot);
+    if (threadIdx.x < 64) {
+        const uint64_t excl = chained_prefix(ws + 2 + nb_max, part, tot, err);
+        if (threadIdx.x == 0) {
+            s_excl = excl;
+            if (part == nparts - 1) {
+                const uint64_t K = excl + tot;
+                offsets[E] = (uint32_t)K;
+                *total = K;
+                *total32 = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+            }
+        }
+    }
+    __syncthreads();
+    uint64_t run = s_excl + pre;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t e = base + j;
         if (e < E) offsets[e] = (uint32_t)run;
         run += c[j];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[E] = (uint32_t)*total;
 }
 
+int64_t scan_workspace_words(int64_t m) { return 2 + 2 * ((m + kScanTile - 1) / kScanTile); }
+
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *block_sums,
-                            uint64_t *total, uint32_t *n_ent, hipStream_t s) {
+                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
+                            uint32_t *n_ent, uint32_t *err, hipStream_t s) {
     const int64_t m = (int64_t)nv * n;
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    // both scans' tickets and status words
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, 2 * scan_workspace_words(m), s);
+    if (nb == 0) {
+        FillSegs z{};
+        z.p[0] = reinterpret_cast<uint32_t *>(total), z.n[0] = 2;
+        z.p[1] = n_ent, z.n[1] = 1;
+        z.count = 2;
+        launch_zero_segs(z, s);
+        return;
+    }
     EntryFlags f{counts, keep, views, n};
-    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<EntryFlags>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total, n_ent);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_compact_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums, depth, ent, dkey);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, nb, ws, depth, ent, dkey, total,
+                       n_ent, err);
 }
 
 void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
-                        uint32_t *offsets, uint64_t *block_sums, uint64_t *total, uint32_t *total32, hipStream_t s) {
+                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+                        hipStream_t s) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
     SortedCounts f{counts, ent, n_ent};
-    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<SortedCounts>, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, block_sums);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sums, nb, total, total32);
-    hipLaunchKernelGGL(k_offsets_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, block_sums,
-                       total, offsets);
+    hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, nb, ws, total,
+                       total32, offsets, err);
 }
 
 // ------------------------------------------------------------------------
@@ -473,7 +557,7 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 // Key chunks of kEmitChunk consecutive keys: chunk c starts inside the entry
 // (depth order) whose key range holds key c * kEmitChunk.
 constexpr int kEmitChunk = 1024;
-constexpr int kEmitBlock = 256;
+constexpr int kEmitBlock = 512;
 
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
                                                       uint32_t *__restrict__ chunk_start, int64_t nchunks) {
@@ -493,8 +577,11 @@ __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, con
 // entry's rectangle, row-major: directly when every tile of the rectangle is
 // active (a view with all tiles active, or a rectangle inside the mask), else
 // by bisection over the rows with the view's 2D active-tile prefix and the
-// row's list of active columns.  The four keys of a thread advance through
-// each bisection step together, so their dependent loads overlap.
+// row's list of active columns.  The keys of a thread advance through each
+// bisection step together, so their dependent loads overlap; two keys per
+// thread keep the registers low enough for eight blocks per compute unit (the
+// LDS limit), which hides the latency of the chains better than more keys
+// per thread.
 constexpr int kEmitPer = kEmitChunk / kEmitBlock;
 
 // per-view fields the emission needs, staged in LDS

@@ -18,47 +18,114 @@
 
 namespace a3fr {
 
+// Every kernel below handles all eyes of the frame in one launch: pair k of
+// the batch (a periphery view and its eye's full-resolution view) is
+// blockIdx.y.
+
 // Each visible Gaussian of the periphery view adds its per-pixel share to the
 // four corners of its tile rectangle in a 2D difference array (float64,
 // [2][TY+1][TX+1]: dropped, kept), so the cost per Gaussian does not depend
 // on its size; a prefix sum over the tile grid then gives D and K.
-__global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__ views, int pv, int64_t n,
-                                                     const uint32_t *__restrict__ counts,
-                                                     const uint8_t *__restrict__ keep,
-                                                     const uint64_t *__restrict__ rect,
-                                                     const double *__restrict__ score, double *__restrict__ diff) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t slot = (int64_t)pv * n + i;
-    if (counts[slot] == 0) return;
-    const DevView &dv = views[pv];
-    const uint64_t r = rect[slot];
+__device__ __forceinline__ void drop_share(double *d, int64_t plane, int S, uint64_t r, double score, bool kept) {
     const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
               y1 = (int)(r >> 48);
     const int nt = (x1 - x0 + 1) * (y1 - y0 + 1);
-    const double share = 2.0 * score[slot] / ((double)nt * (double)(kTile * kTile));
-    const int S = dv.tiles_x + 1;
-    double *d = diff + (keep[slot] ? (int64_t)(dv.tiles_y + 1) * S : 0);
+    const double share = 2.0 * score / ((double)nt * (double)(kTile * kTile));
+    d += kept ? plane : 0;
     atomicAdd(&d[(int64_t)y0 * S + x0], share);
     atomicAdd(&d[(int64_t)y0 * S + x1 + 1], -share);
     atomicAdd(&d[(int64_t)(y1 + 1) * S + x0], -share);
     atomicAdd(&d[(int64_t)(y1 + 1) * S + x1 + 1], share);
 }
 
-// One block: 2D inclusive prefix sum of the two difference planes of view pv
+__global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__ views, FbBatch b, int64_t n,
+                                                     const uint32_t *__restrict__ counts,
+                                                     const uint8_t *__restrict__ keep,
+                                                     const uint64_t *__restrict__ rect,
+                                                     const double *__restrict__ score, double *__restrict__ diff) {
+    const int k = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int pv = b.pv[k];
+    const int64_t slot = (int64_t)pv * n + i;
+    if (counts[slot] == 0) return;
+    const DevView &dv = views[pv];
+    const int S = dv.tiles_x + 1;
+    drop_share(diff + b.doff[k], (int64_t)(dv.tiles_y + 1) * S, S, rect[slot], score[slot], keep[slot] != 0);
+}
+
+// Contention-free variant for grids that fit in LDS: persistent blocks add
+// into a block-local difference array (LDS atomics), write it out as one
+// partial each ([pair][block][cells], cells = b.max_cells apart), and
+// k_drop_reduce sums the partials; device-scope atomics on a few hundred
+// addresses from every XCD would serialise.
+__global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restrict__ views, FbBatch b, int64_t n,
+                                                         const uint32_t *__restrict__ counts,
+                                                         const uint8_t *__restrict__ keep,
+                                                         const uint64_t *__restrict__ rect,
+                                                         const double *__restrict__ score,
+                                                         double *__restrict__ partials) {
+    extern __shared__ double sh[];
+    const int k = blockIdx.y, pv = b.pv[k];
+    const DevView &dv = views[pv];
+    const int S = dv.tiles_x + 1;
+    const int64_t plane = (int64_t)(dv.tiles_y + 1) * S;
+    const int cells = (int)(2 * plane);
+    for (int c = threadIdx.x; c < cells; c += blockDim.x) sh[c] = 0.0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t slot = (int64_t)pv * n + i;
+        if (counts[slot] == 0) continue;
+        drop_share(sh, plane, S, rect[slot], score[slot], keep[slot] != 0);
+    }
+    __syncthreads();
+    double *out = partials + ((int64_t)k * gridDim.x + blockIdx.x) * b.max_cells;
+    for (int c = threadIdx.x; c < cells; c += blockDim.x) out[c] = sh[c];
+}
+
+// 256 threads per 16 cells of one pair: sixteen slices of the partials per
+// cell, each summed by one thread (independent loads, no dependent chain),
+// then the slices summed in LDS.
+__global__ void __launch_bounds__(256) k_drop_reduce(const DevView *__restrict__ views, FbBatch b,
+                                                     const double *__restrict__ partials, int nparts,
+                                                     double *__restrict__ diff) {
+    __shared__ double red[16][16];
+    const int kp = blockIdx.y;
+    const DevView &dv = views[b.pv[kp]];
+    const int cells = 2 * (dv.tiles_y + 1) * (dv.tiles_x + 1);
+    const int c = threadIdx.x & 15, slice = threadIdx.x >> 4;
+    const int k = blockIdx.x * 16 + c;
+    const double *part = partials + (int64_t)kp * nparts * b.max_cells;
+    double acc = 0.0;
+    if (k < cells) {
+#pragma unroll 8
+        for (int g = slice; g < nparts; g += 16) acc += part[(int64_t)g * b.max_cells + k];
+    }
+    red[slice][c] = acc;
+    __syncthreads();
+    if (slice == 0 && k < cells) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += red[q][c];
+        diff[b.doff[kp] + k] = t;
+    }
+}
+
+// One block per pair: 2D inclusive prefix sum of its two difference planes
 // (in place: first along each row, then down each column, one thread per row
 // or column, so a thread's chain of dependent loads is one row or column
 // long), written as float32 into energy [2][ntiles] at the view's tiles.
-__global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict__ views, int pv, double *diff,
+__global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict__ views, FbBatch b, double *diff,
                                                       int64_t ntiles, float *__restrict__ energy) {
     extern __shared__ double pre[];  // the two planes when they fit (dynamic size, else unused)
-    const DevView &dv = views[pv];
+    const int kp = blockIdx.x;
+    const DevView &dv = views[b.pv[kp]];
     const int TX = dv.tiles_x, TY = dv.tiles_y, S = TX + 1;
     const int64_t plane = (int64_t)(TY + 1) * S;
-    const bool lds = 2 * plane * (int64_t)sizeof(double) <= 48 * 1024;
-    double *d = diff;
+    const bool lds = 2 * plane * (int64_t)sizeof(double) <= kFbLdsBytes;
+    double *d = diff + b.doff[kp];
     if (lds) {
-        for (int64_t k = threadIdx.x; k < 2 * plane; k += blockDim.x) pre[k] = diff[k];
+        for (int64_t k = threadIdx.x; k < 2 * plane; k += blockDim.x) pre[k] = d[k];
         __syncthreads();
         d = pre;
     }
@@ -83,95 +150,41 @@ __global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict_
     }
 }
 
-// Contention-free variant for grids that fit in LDS: persistent blocks add
-// into a block-local difference array (LDS atomics), write it out as one
-// partial each, and a second kernel sums the partials; device-scope atomics on
-// a few hundred addresses from every XCD would serialise.
-__global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restrict__ views, int pv, int64_t n,
-                                                         const uint32_t *__restrict__ counts,
-                                                         const uint8_t *__restrict__ keep,
-                                                         const uint64_t *__restrict__ rect,
-                                                         const double *__restrict__ score, int cells,
-                                                         double *__restrict__ partials) {
-    extern __shared__ double sh[];
-    for (int k = threadIdx.x; k < cells; k += blockDim.x) sh[k] = 0.0;
-    __syncthreads();
-    const DevView &dv = views[pv];
-    const int S = dv.tiles_x + 1;
-    const int64_t plane = (int64_t)(dv.tiles_y + 1) * S;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t slot = (int64_t)pv * n + i;
-        if (counts[slot] == 0) continue;
-        const uint64_t r = rect[slot];
-        const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
-                  y1 = (int)(r >> 48);
-        const int nt = (x1 - x0 + 1) * (y1 - y0 + 1);
-        const double share = 2.0 * score[slot] / ((double)nt * (double)(kTile * kTile));
-        double *d = sh + (keep[slot] ? plane : 0);
-        atomicAdd(&d[(int64_t)y0 * S + x0], share);
-        atomicAdd(&d[(int64_t)y0 * S + x1 + 1], -share);
-        atomicAdd(&d[(int64_t)(y1 + 1) * S + x0], -share);
-        atomicAdd(&d[(int64_t)(y1 + 1) * S + x1 + 1], share);
-    }
-    __syncthreads();
-    double *out = partials + (int64_t)blockIdx.x * cells;
-    for (int k = threadIdx.x; k < cells; k += blockDim.x) out[k] = sh[k];
-}
-
-// 256 threads per 16 cells: sixteen slices of the partials per cell, each
-// summed by one thread (independent loads, no dependent chain), then the
-// slices summed in LDS.
-__global__ void __launch_bounds__(256) k_drop_reduce(const double *__restrict__ partials, int nparts, int cells,
-                                                     double *__restrict__ diff) {
-    __shared__ double red[16][16];
-    const int c = threadIdx.x & 15, slice = threadIdx.x >> 4;
-    const int k = blockIdx.x * 16 + c;
-    double acc = 0.0;
-    if (k < cells) {
-#pragma unroll 8
-        for (int g = slice; g < nparts; g += 16) acc += partials[(int64_t)g * cells + k];
-    }
-    red[slice][c] = acc;
-    __syncthreads();
-    if (slice == 0 && k < cells) {
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) t += red[q][c];
-        diff[k] = t;
-    }
-}
-
-// Persistent blocks of the mass maps: one per compute unit of the MI355X, so
-// each thread visits a few Gaussians and the dependent loads overlap.
+// Persistent blocks of the mass maps: one per compute unit of the MI355X per
+// pair, so each thread visits a few Gaussians and the dependent loads overlap.
 int drop_energy_parts() { return 256; }
 
-void launch_drop_energy(const DevView *views, int pv, int tiles_x, int tiles_y, int64_t n, const uint32_t *counts,
+void launch_drop_energy(const DevView *views, const FbBatch &b, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score, double *diff,
                         double *partials, int64_t ntiles, float *energy, hipStream_t s) {
-    const int cells = 2 * (tiles_y + 1) * (tiles_x + 1);
-    const size_t lds = sizeof(double) * (size_t)cells;
-    if (n > 0 && partials && lds <= 48 * 1024) {
+    if (b.count == 0) return;
+    const size_t lds = sizeof(double) * (size_t)b.max_cells;
+    const bool fits = lds <= (size_t)kFbLdsBytes;
+    if (n > 0 && partials && fits) {
         const int parts = drop_energy_parts();
-        hipLaunchKernelGGL(k_drop_energy_lds, dim3(parts), dim3(256), lds, s, views, pv, n, counts, keep, rect, score,
-                           cells, partials);
-        hipLaunchKernelGGL(k_drop_reduce, dim3((cells + 15) / 16), dim3(256), 0, s, partials, parts, cells, diff);
+        hipLaunchKernelGGL(k_drop_energy_lds, dim3(parts, b.count), dim3(256), lds, s, views, b, n, counts, keep, rect,
+                           score, partials);
+        hipLaunchKernelGGL(k_drop_reduce, dim3((b.max_cells + 15) / 16, b.count), dim3(256), 0, s, views, b, partials,
+                           parts, diff);
     } else if (n > 0) {
-        hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, pv, n, counts,
-                           keep, rect, score, diff);
+        hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256), b.count), dim3(256), 0, s, views, b, n,
+                           counts, keep, rect, score, diff);
     }
-    hipLaunchKernelGGL(k_drop_prefix, dim3(1), dim3(1024), lds <= 48 * 1024 ? lds : 0, s, views, pv, diff, ntiles,
-                       energy);
+    hipLaunchKernelGGL(k_drop_prefix, dim3(b.count), dim3(1024), fits ? lds : 0, s, views, b, diff, ntiles, energy);
 }
 
-// One thread per periphery tile: flag, and activate the covered tiles of the
-// full-resolution layer fv (s = full-resolution pixels per periphery pixel).
-// A tile can only matter if one of the full-resolution pixel centres it
-// covers lies outside r_mid (the composite's periphery region).
-__global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int fv, const float *__restrict__ energy,
-                                 int64_t ntiles, double r_mid, double threshold, double coef, double power,
+// One thread per periphery tile of pair blockIdx.y: flag, and activate the
+// covered tiles of the full-resolution layer fv (s = full-resolution pixels
+// per periphery pixel).  A tile can only matter if one of the
+// full-resolution pixel centres it covers lies outside r_mid (the
+// composite's periphery region).
+__global__ void k_fallback_flags(const DevView *__restrict__ views, FbBatch b, const float *__restrict__ energy,
+                                 int64_t ntiles, double threshold, double coef, double power,
                                  uint8_t *__restrict__ flags, uint8_t *__restrict__ active,
                                  uint32_t *__restrict__ n_flagged) {
-    const DevView &dp = views[pv], &df = views[fv];
+    const int k = blockIdx.y;
+    const DevView &dp = views[b.pv[k]], &df = views[b.fv[k]];
+    const double r_mid = b.r_mid[k];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)dp.tiles_x * dp.tiles_y) return;
     const int tx = (int)(t % dp.tiles_x), ty = (int)(t / dp.tiles_x);
@@ -195,12 +208,12 @@ __global__ void k_fallback_flags(const DevView *__restrict__ views, int pv, int 
             active[df.tile_off + (int64_t)yy * df.tiles_x + xx] = 1;
 }
 
-void launch_fallback_flags(const DevView *views, int pv, int fv, int64_t periph_tiles, const float *energy,
-                           int64_t ntiles, double r_mid, double threshold, double coef, double power, uint8_t *flags,
+void launch_fallback_flags(const DevView *views, const FbBatch &b, int64_t max_periph_tiles, const float *energy,
+                           int64_t ntiles, double threshold, double coef, double power, uint8_t *flags,
                            uint8_t *active, uint32_t *n_flagged, hipStream_t s) {
-    if (periph_tiles == 0) return;
-    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)((periph_tiles + 255) / 256)), dim3(256), 0, s, views, pv, fv,
-                       energy, ntiles, r_mid, threshold, coef, power, flags, active, n_flagged);
+    if (b.count == 0 || max_periph_tiles == 0) return;
+    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)((max_periph_tiles + 255) / 256), b.count), dim3(256), 0, s,
+                       views, b, energy, ntiles, threshold, coef, power, flags, active, n_flagged);
 }
 
 // Row prefix and active-column list of the remasked views' rows from their
@@ -244,15 +257,16 @@ void launch_rows_from_active(const DevView *views, int64_t rows_total, const int
                        row_view, row_y, active, row_prefix, row_list, n_flagged);
 }
 
-// Active tiles covered by each visible Gaussian's rectangle in view fv, from
-// the rebuilt row prefixes.
-__global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ views, int fv, int64_t n,
+// Active tiles covered by each visible Gaussian's rectangle in the
+// full-resolution view of pair blockIdx.y, from the rebuilt row prefixes.
+__global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ views, FbBatch b, int64_t n,
                                                  const uint64_t *__restrict__ rect,
                                                  const uint16_t *__restrict__ row_prefix, uint32_t *__restrict__ counts,
                                                  const uint32_t *n_flagged) {
     if (n_flagged && *n_flagged == 0) return;  // masks unchanged: the counts of the projection stand
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int fv = b.fv[blockIdx.y];
     const DevView &dv = views[fv];
     const int64_t slot = (int64_t)fv * n + i;
     const uint64_t r = rect[slot];
@@ -268,11 +282,11 @@ __global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ vie
     counts[slot] = cnt;
 }
 
-void launch_recount(const DevView *views, int fv, int64_t n, const uint64_t *rect, const uint16_t *row_prefix,
-                    uint32_t *counts, const uint32_t *n_flagged, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_recount, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, views, fv, n, rect, row_prefix,
-                       counts, n_flagged);
+void launch_recount(const DevView *views, const FbBatch &b, int64_t n, const uint64_t *rect,
+                    const uint16_t *row_prefix, uint32_t *counts, const uint32_t *n_flagged, hipStream_t s) {
+    if (n == 0 || b.count == 0) return;
+    hipLaunchKernelGGL(k_recount, dim3((unsigned)((n + 255) / 256), b.count), dim3(256), 0, s, views, b, n, rect,
+                       row_prefix, counts, n_flagged);
 }
 
 }  // namespace a3fr

@@ -43,18 +43,50 @@ int sort_partitions(int64_t n, int items) {
 
 // Histograms of the npass low digits of n keys (n read from *n_dev).  Each
 // wave keeps its own LDS histograms; the block adds them to the global ones.
+// Keys come four to a lane (16-byte loads).  Neighbouring keys often share a
+// digit (tile ids of one Gaussian's rectangle, depths of one depth range),
+// and LDS atomics of a wave on one address serialise: when every valid key of
+// the wave's step has the same digit, one lane adds the count.
 constexpr int kHistThreads = 512;
 constexpr int kHistWaves = kHistThreads / kWave;
+__device__ __forceinline__ void hist_add(uint32_t (*h)[kRadix], int npass, uint32_t k, bool valid, int lane) {
+    const uint64_t vm = __ballot(valid);
+    const int first = __ffsll((unsigned long long)vm) - 1;  // a valid lane (vm != 0 for the callers)
+    for (int p = 0; p < npass; ++p) {
+        const uint32_t d = (k >> (8 * p)) & 255u;
+        const uint32_t d0 = __shfl(d, first, 64);
+        const uint64_t same = __ballot(valid && d == d0);
+        if (same == vm) {
+            if (lane == first) atomicAdd(&h[p][d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[p][d], 1u);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                             int npass, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[kHistWaves][kMaxPasses][kRadix];
     for (int j = threadIdx.x; j < kHistWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
     __syncthreads();
     const int64_t n = *n_dev;
-    const int w = threadIdx.x >> 6;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = keys[j];
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[w][p][(k >> (8 * p)) & 255u], 1u);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform loop over 256-key steps (64 lanes x 4 keys)
+    const int64_t nwaves = (int64_t)gridDim.x * kHistWaves;
+    for (int64_t base = ((int64_t)blockIdx.x * kHistWaves + w) * 256; base < n; base += nwaves * 256) {
+        const int64_t j = base + 4 * lane;
+        uint4 k4 = {0u, 0u, 0u, 0u};
+        if (j + 3 < n) {
+            k4 = *reinterpret_cast<const uint4 *>(keys + j);
+        } else {
+            if (j < n) k4.x = keys[j];
+            if (j + 1 < n) k4.y = keys[j + 1];
+            if (j + 2 < n) k4.z = keys[j + 2];
+        }
+        hist_add(h[w], npass, k4.x, j < n, lane);
+        if (base + 1 < n) hist_add(h[w], npass, k4.y, j + 1 < n, lane);
+        if (base + 2 < n) hist_add(h[w], npass, k4.z, j + 2 < n, lane);
+        if (base + 3 < n) hist_add(h[w], npass, k4.w, j + 3 < n, lane);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < npass * kRadix; j += blockDim.x) {
@@ -265,7 +297,7 @@ void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_
     launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass, items), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
-    if (hblocks > 256) hblocks = 256;
+    if (hblocks > 512) hblocks = 512;
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(kHistThreads), 0, s, keys, n_dev, npass, ws);
 }
 
