@@ -45,6 +45,11 @@ struct a3fr_ctx {
     size_t pinned_cap = 0;
     hipEvent_t upload_done = nullptr;
     uint64_t *h_total = nullptr;
+    hipEvent_t total_ready = nullptr;  // the key total has reached h_total
+    // a frame of this library defers the view-dependent colour of its entries
+    // into a3fr_bin_sort, where it runs while the host waits for the key total
+    bool defer_colour = false, colour_pending = false;
+    a3fr_scene colour_scene{};
     // device workspace
     DevBuf views, row_view, row_y, row_prefix, row_list, active;
     DevBuf counts, depth, rect, rec, score, keep, sel_views, sel;
@@ -279,6 +284,12 @@ a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
         delete c;
         return A3FR_EDEVICE;
     }
+    if (hipEventCreateWithFlags(&c->total_ready, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(c->upload_done);
+        delete c;
+        return A3FR_EDEVICE;
+    }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_total), 64, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipEventDestroy(c->upload_done);
@@ -314,6 +325,7 @@ void a3fr_destroy(a3fr_ctx *c) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->h_total) (void)hipHostFree(c->h_total);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    if (c->total_ready) (void)hipEventDestroy(c->total_ready);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -408,6 +420,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                 return fail(c, A3FR_EINVAL, "views with the same eye must share R, t and campos");
     const int64_t n = scene->n;
     if (!c->inc_mode) c->inc_ready = false;  // another frame reuses the buffers of the rounds
+    c->colour_pending = false;
     if (c->capturing) {
         // the view table of each replay is uploaded by a3fr_graph_launch; the layout is the warm-up's
         if (nv != c->nv || n != c->n) return fail(c, A3FR_EINVAL, "graph capture: frame layout changed");
@@ -616,7 +629,10 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
                                P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
                                sc_ent_total(c->scalars), sc_n_ent(c->scalars), sc_err(c->scalars), c->stream);
     }
-    if (scene) {
+    if (scene && c->defer_colour) {
+        c->colour_scene = *scene;
+        c->colour_pending = true;
+    } else if (scene) {
         StageTimer t_(c, A3FR_STAGE_COLOUR);
         launch_entry_colour(*scene, dv, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m, P<Record>(c->rec), c->stream);
     }
@@ -644,6 +660,16 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
     return A3FR_OK;
 }
 
+// The colour of the entries (any order: it is stored per slot) deferred by
+// entry_stages; the entry list is final once the compaction has run.
+static void run_pending_colour(a3fr_ctx *c) {
+    if (!c->colour_pending) return;
+    c->colour_pending = false;
+    StageTimer t_(c, A3FR_STAGE_COLOUR);
+    launch_entry_colour(c->colour_scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
+                        (int64_t)c->nv * c->n, P<Record>(c->rec), c->stream);
+}
+
 a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (!c) return A3FR_EINVAL;
     if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "a3fr_bin_sort before a3fr_preprocess");
@@ -651,12 +677,15 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     const bool cap_mode = c->capacity > 0;
     if (cap_mode) {
         // graph mode: no host read-back; buffers sized to the capacity, counts clamped on the device
+        run_pending_colour(c);
         K = (uint64_t)c->capacity;
         if (n_keys_out) *n_keys_out = -1;
     } else {
         HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
                                    c->stream));
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        HIPCHECK(c, hipEventRecord(c->total_ready, c->stream));
+        run_pending_colour(c);  // the GPU works on it while the host waits for the total
+        HIPCHECK(c, hipEventSynchronize(c->total_ready));
         K = *c->h_total;
         if (n_keys_out) *n_keys_out = (int64_t)K;
         if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
@@ -838,7 +867,10 @@ a3fr_status a3fr_render_full(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_ca
     if (!out) return fail(c, A3FR_EINVAL, "out_dev is NULL");
     std::vector<a3fr_view> v(n_cams);
     for (int e = 0; e < n_cams; ++e) view_from_camera(cams[e], e, v[e]);
-    TRY(a3fr_preprocess(c, scene, v.data(), n_cams, 1, 1));
+    c->defer_colour = true;
+    const a3fr_status st = a3fr_preprocess(c, scene, v.data(), n_cams, 1, 1);
+    c->defer_colour = false;
+    TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
     return a3fr_blend(c, out, nullptr, nullptr);
 }
@@ -858,7 +890,10 @@ a3fr_status a3fr_render_amr(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_cam
         v[e].gy = gaze[e].y;
         if (!is_fin(gaze[e].x) || !is_fin(gaze[e].y)) return fail(c, A3FR_EINVAL, "render_amr: gaze not finite");
     }
-    TRY(a3fr_preprocess(c, scene, v.data(), n_eyes, 1, 1));
+    c->defer_colour = true;
+    const a3fr_status st = a3fr_preprocess(c, scene, v.data(), n_eyes, 1, 1);
+    c->defer_colour = false;
+    TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
     StageTimer t_(c, A3FR_STAGE_BLEND);
     launch_blend_amr(P<DevView>(c->views), c->nv, c->ntiles, P<uint32_t>(c->ranges), sorted_vals(c), P<Record>(c->rec),
@@ -976,7 +1011,9 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     c->fb_plan.clear();
     if (fb)
         for (int e = 0; e < n_eyes; ++e) c->fb_plan.push_back({3 * e + 2, 3 * e, f->r_mid});
+    c->defer_colour = true;
     a3fr_status st = a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den);
+    c->defer_colour = false;
     c->fb_plan.clear();
     TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
