@@ -259,7 +259,11 @@ int64_t select_workspace_words(int nsel, int64_t n) {
 // ------------------------------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = 256;
-constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block
+constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block (key offsets)
+// the compaction's partitions are larger (16 waves of 1024 entries): fewer
+// partitions, so the look-back finds an inclusive prefix within fewer windows
+constexpr int kCompactBlock = 1024;
+constexpr int kCompactTile = kScanItems * kCompactBlock;
 
 // Entry e = view * n + index contributes keys iff it is visible in its view and,
 // for a selecting view, kept.
@@ -375,22 +379,22 @@ __device__ uint64_t chained_prefix(uint64_t *status, int64_t part, uint64_t tot,
 // All loads of a kind are issued before any is used (counts, then the keep
 // bytes where a selecting view needs them, then the depths of the flagged
 // entries), so a wave waits for three round trips, not one per round.
-__global__ void __launch_bounds__(kScanBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
+__global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
                                                         const uint32_t *__restrict__ depth, uint32_t *__restrict__ ent,
                                                         uint32_t *__restrict__ dkey, uint64_t *total, uint32_t *total32,
                                                         uint32_t *err) {
     __shared__ uint32_t s_part;
-    __shared__ uint64_t s_w[kScanBlock / 64];
+    __shared__ uint64_t s_w[kCompactBlock / 64];
     __shared__ uint64_t s_excl;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_part = atomicAdd(reinterpret_cast<uint32_t *>(&ws[0]), 1u);
     __syncthreads();
     const int64_t part = s_part;
-    const int64_t wbase = part * kScanTile + (int64_t)w * 64 * kScanItems;
+    const int64_t wbase = part * kCompactTile + (int64_t)w * 64 * kScanItems;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // views of the block's entries: at most two when n >= kScanTile
-    const bool per_elem = f.n < kScanTile;
-    const int64_t v0 = (part * kScanTile) / f.n, b1 = (v0 + 1) * f.n;
+    // views of the block's entries: at most two when n >= kCompactTile
+    const bool per_elem = f.n < kCompactTile;
+    const int64_t v0 = (part * kCompactTile) / f.n, b1 = (v0 + 1) * f.n;
     const bool sel0 = f.views[v0].v.select != 0, sel1 = b1 < m && f.views[v0 + 1].v.select != 0;
     uint32_t cv[kScanItems];
 #pragma unroll
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(EntryFlags f, int64_t m,
     if (w == 0) {
         uint64_t tot = 0;
 #pragma unroll
-        for (int q = 0; q < kScanBlock / 64; ++q) tot += s_w[q];
+        for (int q = 0; q < kCompactBlock / 64; ++q) tot += s_w[q];
         const uint64_t excl = chained_prefix(ws + 2, part, tot, err);
         if (lane == 0) {
             s_excl = excl;
@@ -454,7 +458,9 @@ __global__ void __launch_bounds__(kScanBlock) k_compact(EntryFlags f, int64_t m,
 // Offsets of the keys of the entries in depth order; offsets[E] = K.  The
 // grid is sized for the largest entry count; blocks past the partitions of
 // the device count leave without a ticket.
-__global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t nb_max, uint64_t *ws,
+__host__ __device__ inline int64_t compact_parts(int64_t m) { return (m + kCompactTile - 1) / kCompactTile; }
+
+__global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t m, uint64_t *ws,
                                                         uint64_t *total, uint32_t *total32, uint32_t *offsets,
                                                         uint32_t *err) {
     __shared__ uint32_t s_part;
@@ -484,7 +490,7 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
     uint64_t tot;
     const uint64_t pre = block_excl_scan(acc, &tot);
     if (threadIdx.x < 64) {
-        const uint64_t excl = chained_prefix(ws + 2 + nb_max, part, tot, err);
+        const uint64_t excl = chained_prefix(ws + 2 + compact_parts(m), part, tot, err);
         if (threadIdx.x == 0) {
             s_excl = excl;
             if (part == nparts - 1) {
@@ -505,13 +511,13 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
     }
 }
 
-int64_t scan_workspace_words(int64_t m) { return 2 + 2 * ((m + kScanTile - 1) / kScanTile); }
+int64_t scan_workspace_words(int64_t m) { return 2 + compact_parts(m) + (m + kScanTile - 1) / kScanTile; }
 
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
                             const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
                             uint32_t *n_ent, uint32_t *err, hipStream_t s) {
     const int64_t m = (int64_t)nv * n;
-    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    const int64_t nb = compact_parts(m);
     // both scans' tickets and status words
     launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, 2 * scan_workspace_words(m), s);
     if (nb == 0) {
@@ -523,7 +529,7 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const D
         return;
     }
     EntryFlags f{counts, keep, views, n};
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kScanBlock), 0, s, f, m, nb, ws, depth, ent, dkey, total,
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kCompactBlock), 0, s, f, m, nb, ws, depth, ent, dkey, total,
                        n_ent, err);
 }
 
@@ -532,7 +538,7 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
                         hipStream_t s) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
     SortedCounts f{counts, ent, n_ent};
-    hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, nb, ws, total,
+    hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, ws, total,
                        total32, offsets, err);
 }
 
