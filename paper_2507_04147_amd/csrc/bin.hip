@@ -26,8 +26,9 @@ namespace a3fr {
 // descending, index ascending.  Scores are non-negative doubles, so their bit
 // patterns order like the values and bit 63 is 0.
 //   1. two histogram levels of 12 bits each (score bits 62..51, then 50..39 of
-//      the Gaussians in the chosen level-1 bucket), per block in LDS; after
-//      each, one block per view picks the bucket holding the k-th largest key;
+//      the Gaussians in the chosen level-1 bucket), per block in LDS; the
+//      blocks of the next kernel each pick the bucket holding the k-th largest
+//      key from it;
 //   2. every visible Gaussian outside the chosen 24-bit bucket is decided at
 //      once, those inside are listed as candidates (usually a handful);
 //   3. one block per view runs an MSD radix select over the candidates'
@@ -47,43 +48,28 @@ __device__ __forceinline__ uint32_t sel_level(uint64_t bits, int level) {
     return (uint32_t)(bits >> (63 - kSelBits * (level + 1))) & (uint32_t)(kSelBuckets - 1);
 }
 
-__global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, const uint32_t *__restrict__ counts,
-                                                  const double *__restrict__ score, int64_t n, int level,
-                                                  const SelState *st, uint32_t *hist) {
-    const int slot = blockIdx.y;
-    if (level > 0 && st[slot].mode != 0) return;
-    __shared__ uint32_t lh[kSelBuckets];
-    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x) lh[b] = 0;
-    __syncthreads();
-    const uint32_t b0 = level > 0 ? st[slot].b0 : 0u;
-    const int64_t base = (int64_t)sel_views[slot] * n;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (counts[base + i] == 0) continue;
-        const uint64_t bits = (uint64_t)__double_as_longlong(score[base + i]);
-        if (level > 0 && sel_level(bits, 0) != b0) continue;
-        atomicAdd(&lh[sel_level(bits, level)], 1u);
-    }
-    __syncthreads();
-    uint32_t *h = hist + ((int64_t)slot * 2 + level) * kSelBuckets;
-    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x)
-        if (lh[b]) atomicAdd(&h[b], lh[b]);
-}
-
-// One block of 1024 threads per view: thread t owns kSelBuckets/1024
-// consecutive buckets, the highest first; finds the bucket holding the
-// k_rem-th largest key of this level.
-__global__ void __launch_bounds__(1024) k_sel_pick(const uint32_t *hist, int level, int keep_num, int keep_den,
-                                                   SelState *st) {
-    constexpr int kPer = kSelBuckets / 1024;
-    const int slot = blockIdx.x, t = threadIdx.x;
-    SelState &S = st[slot];
-    if (level > 0 && S.mode != 0) return;
-    const uint32_t *h = hist + ((int64_t)slot * 2 + level) * kSelBuckets;
+// The bucket of one level holding the k-th largest key, found by a whole
+// block of 256 threads: thread t owns kSelBuckets/256 consecutive buckets,
+// the highest first.  Every block of the kernel that needs it repeats this
+// (16 KB of histogram from L2) instead of a separate one-block launch.
+// k: ceil(keep_num x total / keep_den) for the first level (total = visible
+// count), else k_fixed.  out->bucket and out->krem are set when 0 < k <= total.
+struct PickOut {
+    uint32_t total, k, bucket, krem;
+};
+__device__ void pick_bucket(const uint32_t *h, bool first_level, uint32_t k_fixed, int keep_num, int keep_den,
+                            PickOut *out) {
+    constexpr int kPer = kSelBuckets / 256;
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int hi = kSelBuckets - kPer * t;
+    uint32_t c[kPer];
     uint32_t loc = 0;
-    for (int b = hi - 1; b >= hi - kPer; --b) loc += h[b];
-    __shared__ uint32_t wsum[16];
-    const int lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        c[q] = h[hi - 1 - q];
+        loc += c[q];
+    }
     uint32_t inc = loc;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(inc, off, 64);
@@ -92,78 +78,173 @@ __global__ void __launch_bounds__(1024) k_sel_pick(const uint32_t *hist, int lev
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
-    for (int q = 0; q < 16; ++q) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
         if (q < w) pre += wsum[q];
         tot += wsum[q];
     }
-    const uint32_t above0 = pre + inc - loc;
-    uint64_t k;
-    if (level == 0) {
-        const uint32_t nvis = tot;
-        k = ((uint64_t)keep_num * nvis + (uint64_t)keep_den - 1) / (uint64_t)keep_den;
-        __syncthreads();
-        if (t == 0) {
-            S.n_vis = nvis;
-            S.k = (uint32_t)k;
-            S.ncand = 0;
-            S.mode = k == 0 ? 2u : (k >= nvis ? 1u : 0u);
-        }
-        if (k == 0 || k >= nvis) return;
-    } else {
-        k = S.k_rem;
-        __syncthreads();
+    const uint64_t k = first_level ? ((uint64_t)keep_num * tot + (uint64_t)keep_den - 1) / (uint64_t)keep_den
+                                   : (uint64_t)k_fixed;
+    if (t == 0) {
+        out->total = tot;
+        out->k = (uint32_t)k;
     }
-    if (above0 < k && above0 + loc >= k) {
-        uint32_t above = above0;
-        for (int b = hi - 1; b >= hi - kPer; --b) {
-            const uint32_t c = h[b];
-            if (above + c >= k) {
-                if (level == 0) S.b0 = (uint32_t)b; else S.b1 = (uint32_t)b;
-                S.k_rem = (uint32_t)(k - above);
+    uint32_t above = pre + inc - loc;
+    if (k > 0 && above < k && above + loc >= k) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (above + c[q] >= k) {
+                out->bucket = (uint32_t)(hi - 1 - q);
+                out->krem = (uint32_t)(k - above);
                 break;
             }
-            above += c;
+            above += c[q];
         }
     }
+    __syncthreads();
 }
 
+// First-level decision of a view from its level-0 histogram: mode 0 select,
+// 1 keep every visible Gaussian, 2 keep none.
+__device__ __forceinline__ uint32_t pick_mode(const PickOut &p) {
+    return p.k == 0 ? 2u : (p.k >= p.total ? 1u : 0u);
+}
+
+// Adds one to bucket d of the wave's lanes with valid set: lanes sharing the
+// first valid lane's bucket (often most of them: scores of similar size share
+// their top bits) add with a single LDS atomic.
+__device__ __forceinline__ void sel_count(uint32_t *lh, uint32_t d, bool valid) {
+    const uint64_t vm = __ballot(valid);
+    if (vm == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((unsigned long long)vm) - 1;
+    const uint32_t d0 = __shfl(d, first, 64);
+    const uint64_t same = __ballot(valid && d == d0);
+    if (lane == first) atomicAdd(&lh[d0], (uint32_t)__popcll(same));
+    if (valid && d != d0) atomicAdd(&lh[d], 1u);
+}
+
+constexpr int kSelUnroll = 4;
+// Level histograms; a level-1 block first takes the level-0 decision (block
+// 0 of the view stores it in the state for the later kernels).
+__global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, const uint32_t *__restrict__ counts,
+                                                  const double *__restrict__ score, int64_t n, int level,
+                                                  SelState *st, uint32_t *hist, int keep_num, int keep_den) {
+    const int slot = blockIdx.y;
+    __shared__ uint32_t lh[kSelBuckets];
+    __shared__ PickOut p0;
+    uint32_t b0 = 0;
+    if (level > 0) {
+        pick_bucket(hist + (int64_t)slot * 2 * kSelBuckets, true, 0u, keep_num, keep_den, &p0);
+        const uint32_t mode = pick_mode(p0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            SelState &S = st[slot];
+            S.n_vis = p0.total;
+            S.k = p0.k;
+            S.mode = mode;
+            S.ncand = 0;
+            S.b0 = p0.bucket;
+            S.k_rem = p0.krem;
+        }
+        if (mode != 0) return;  // block-uniform
+        b0 = p0.bucket;
+    }
+    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x) lh[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)sel_views[slot] * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // block-uniform trip count (the ballots need whole waves); loads first
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += kSelUnroll * stride) {
+        uint32_t cv[kSelUnroll];
+        uint64_t bits[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            cv[u] = i < n ? counts[base + i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            bits[u] = cv[u] != 0 ? (uint64_t)__double_as_longlong(score[base + i]) : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const bool valid = cv[u] != 0 && (level == 0 || sel_level(bits[u], 0) == b0);
+            sel_count(lh, sel_level(bits[u], level), valid);
+        }
+    }
+    __syncthreads();
+    uint32_t *h = hist + ((int64_t)slot * 2 + level) * kSelBuckets;
+    for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x)
+        if (lh[b]) atomicAdd(&h[b], lh[b]);
+}
+
+// Decides every visible Gaussian outside the chosen 24-bit bucket and lists
+// those inside as candidates; every block takes both level decisions from the
+// histograms (block 0 of the view stores the second in the state).
 __global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, const uint32_t *__restrict__ counts,
                                                     const double *__restrict__ score, int64_t n, SelState *st,
+                                                    const uint32_t *hist, int keep_num, int keep_den,
                                                     uint64_t *cand_key, uint32_t *cand_idx, uint8_t *keep) {
     const int slot = blockIdx.y;
     const int64_t base = (int64_t)sel_views[slot] * n;
-    const uint32_t mode = st[slot].mode;
-    const uint32_t top = (st[slot].b0 << kSelBits) | st[slot].b1;  // chosen 24-bit prefix
+    __shared__ PickOut p0, p1;
+    pick_bucket(hist + (int64_t)slot * 2 * kSelBuckets, true, 0u, keep_num, keep_den, &p0);
+    const uint32_t mode = pick_mode(p0);
+    uint32_t top = 0;  // chosen 24-bit prefix
+    if (mode == 0) {
+        pick_bucket(hist + ((int64_t)slot * 2 + 1) * kSelBuckets, false, p0.krem, keep_num, keep_den, &p1);
+        top = (p0.bucket << kSelBits) | p1.bucket;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st[slot].b1 = p1.bucket;
+            st[slot].k_rem = p1.krem;
+        }
+    }
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = i0 + threadIdx.x;
-        uint8_t kp = 0;
-        bool cand = false;
-        uint64_t bits = 0;
-        if (i < n && counts[base + i] != 0) {
-            if (mode == 1) {
-                kp = 1;
-            } else if (mode == 0) {
-                bits = (uint64_t)__double_as_longlong(score[base + i]);
-                const uint32_t tb = (uint32_t)(bits >> kSelLow);
-                kp = tb > top ? 1 : 0;
-                cand = tb == top;
-            }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // block-uniform trip count; each step's loads issued before any is used
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += kSelUnroll * stride) {
+        uint32_t cv[kSelUnroll];
+        uint64_t bits[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            cv[u] = i < n ? counts[base + i] : 0u;
         }
-        const uint64_t m = __ballot(cand);  // one atomic per wave for its candidates
-        if (m) {
-            uint32_t first = 0;
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            if (lane == leader) first = atomicAdd(&st[slot].ncand, (uint32_t)__popcll(m));
-            first = __shfl(first, leader, 64);
-            if (cand) {
-                const uint32_t c = first + (uint32_t)__popcll(m & lt);
-                cand_key[(int64_t)slot * n + c] = bits & ((1ull << kSelLow) - 1);
-                cand_idx[(int64_t)slot * n + c] = (uint32_t)i;
-            }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            bits[u] = cv[u] != 0 && mode == 0 ? (uint64_t)__double_as_longlong(score[base + i]) : 0ull;
         }
-        if (i < n) keep[base + i] = kp;
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            uint8_t kp = 0;
+            bool cand = false;
+            if (cv[u] != 0) {
+                if (mode == 1) {
+                    kp = 1;
+                } else if (mode == 0) {
+                    const uint32_t tb = (uint32_t)(bits[u] >> kSelLow);
+                    kp = tb > top ? 1 : 0;
+                    cand = tb == top;
+                }
+            }
+            const uint64_t m = __ballot(cand);  // one atomic per wave for its candidates
+            if (m) {
+                uint32_t first = 0;
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                if (lane == leader) first = atomicAdd(&st[slot].ncand, (uint32_t)__popcll(m));
+                first = __shfl(first, leader, 64);
+                if (cand) {
+                    const uint32_t c = first + (uint32_t)__popcll(m & lt);
+                    cand_key[(int64_t)slot * n + c] = bits[u] & ((1ull << kSelLow) - 1);
+                    cand_idx[(int64_t)slot * n + c] = (uint32_t)i;
+                }
+            }
+            if (i < n) keep[base + i] = kp;
+        }
     }
 }
 
@@ -239,13 +320,11 @@ void launch_select(const DevView *views, int nv, const int32_t *sel_views, int n
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     const unsigned hb = (unsigned)(blocks < 256 ? blocks : 256);
-    for (int level = 0; level < 2; ++level) {
+    for (int level = 0; level < 2; ++level)
         hipLaunchKernelGGL(k_sel_hist, dim3(hb, (unsigned)nsel), dim3(256), 0, s, sel_views, counts, score, n, level, st,
-                           hist);
-        hipLaunchKernelGGL(k_sel_pick, dim3((unsigned)nsel), dim3(1024), 0, s, hist, level, keep_num, keep_den, st);
-    }
-    hipLaunchKernelGGL(k_sel_gather, dim3((unsigned)blocks, (unsigned)nsel), dim3(256), 0, s, sel_views, counts, score,
-                       n, st, ck, ci, keep);
+                           hist, keep_num, keep_den);
+    hipLaunchKernelGGL(k_sel_gather, dim3(hb, (unsigned)nsel), dim3(256), 0, s, sel_views, counts, score, n, st, hist,
+                       keep_num, keep_den, ck, ci, keep);
     hipLaunchKernelGGL(k_sel_final, dim3((unsigned)nsel), dim3(1024), 0, s, sel_views, n, st, ck, ci, keep);
 }
 
