@@ -122,80 +122,69 @@ __device__ __forceinline__ bool inside_mid(int xa, int xb, int ya, int yb, doubl
     return mx + my <= rm * rm * (1.0 - 1e-12);
 }
 
-// Epilogue of one image row: lane holds pixels xs + 4g + r (r = 0..3) of
-// channel nb*16 + li of every 16-channel block nb.
+// Epilogue of one image row of a hidden layer (ReLU forward, or the
+// activation mask of the input gradient): lane holds pixels xs + 4g + r
+// (r = 0..3) of channel nb*16 + li of every 16-channel block nb.  The
+// bfloat16 row of the wave (16 pixels x NOUT channels) is staged in LDS (st:
+// 16 rows of kStageStride<NOUT> halves) and stored NHWC with 16-byte stores,
+// NOUT/8 lanes per pixel; the channel-major copy (training) is written from
+// the registers.
+template <int NOUT>
+constexpr int kStageStride = NOUT + 8;  // halves per staged pixel (16-byte aligned rows)
+
 template <int KIN, int NOUT, int EPI>
-__device__ __forceinline__ void conv_epilogue(const NetConvArgs &a, const floatx4 *acc, int b, int y, int xs, int li,
-                                              int g, int WS, double gx, double gy) {
+__device__ __forceinline__ void conv_epilogue(const NetConvArgs &a, const floatx4 *acc, uint16_t *st, int b, int y,
+                                              int xs, int li, int g, int lane, int WS) {
     constexpr int NB = NOUT / 16;
+    constexpr int SS = kStageStride<NOUT>;
     const int h = a.h, w = a.w;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int ch = nb * 16 + li;
-        if (EPI == kEpiShuffle) {
-            // channel c*16 + 4i + j -> output (c, 4y + i, 4x + j); c = nb
-            const float bias = a.bias[ch];
-            const int i = li >> 2, j = li & 3;
-            const int H4 = 4 * h, W4 = 4 * w;
-            const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)nb * h * w;
-            float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)nb * H4 * W4;
-            const int Y = 4 * y + i;
-            float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
-            sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
-            const float fy0 = floorf(sy);
-            const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
-            const float wy = sy - fy0;
+        uint16_t q[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = xs + 4 * g + r;
-                if (x < w) {
-                    const int X = 4 * x + j;
-                    float sx = ((float)X + 0.5f) * 0.25f - 0.5f;
-                    sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
-                    const float fx0 = floorf(sx);
-                    const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
-                    const float wx = sx - fx0;
-                    const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
-                    const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
-                    bool put = true;
-                    if (a.gv) {  // frame mode: only the composite's periphery (outside r_mid)
-                        const double dx = ((double)X + 0.5) - gx, dy = ((double)Y + 0.5) - gy;
-                        put = dx * dx + dy * dy > a.rm * a.rm;
-                    }
-                    if (put) dst[(int64_t)Y * W4 + X] = (acc[nb][r] + bias) + ((1.0f - wy) * top + wy * bot);
-                }
+        for (int r = 0; r < 4; ++r) {
+            const int x = xs + 4 * g + r;
+            float v = acc[nb][r];
+            if (EPI == kEpiRelu) {
+                v = fmaxf(v + a.bias[ch], 0.0f);
+            } else {
+                // active where the forward activation is positive (bf16 bits as int16 > 0)
+                const bool on = x < w && (int16_t)a.mask[(((int64_t)b * h + y) * w + x) * NOUT + ch] > 0;
+                v = on ? v : 0.0f;
             }
-        } else {
-            uint16_t q[4];
+            q[r] = bf16_bits(v);
+            st[(4 * g + r) * SS + ch] = q[r];
+        }
+        if (a.out_chw) {
+            uint16_t *o = a.out_chw + (((int64_t)b * NOUT + ch) * (h + 2) + y + 1) * WS + 8 + xs + 4 * g;
+            if (xs + 4 * g + 3 < w) {
+                uint2 pk;
+                pk.x = q[0] | ((uint32_t)q[1] << 16);
+                pk.y = q[2] | ((uint32_t)q[3] << 16);
+                *reinterpret_cast<uint2 *>(o) = pk;
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = xs + 4 * g + r;
-                float v = acc[nb][r];
-                if (EPI == kEpiRelu) {
-                    v = fmaxf(v + a.bias[ch], 0.0f);
-                } else {
-                    // active where the forward activation is positive (bf16 bits as int16 > 0)
-                    const bool on = x < w && (int16_t)a.mask[(((int64_t)b * h + y) * w + x) * NOUT + ch] > 0;
-                    v = on ? v : 0.0f;
-                }
-                q[r] = bf16_bits(v);
-                if (x < w && a.out) a.out[(((int64_t)b * h + y) * w + x) * NOUT + ch] = q[r];
-            }
-            if (a.out_chw) {
-                uint16_t *o = a.out_chw + (((int64_t)b * NOUT + ch) * (h + 2) + y + 1) * WS + 8 + xs + 4 * g;
-                if (xs + 4 * g + 3 < w) {
-                    uint2 pk;
-                    pk.x = q[0] | ((uint32_t)q[1] << 16);
-                    pk.y = q[2] | ((uint32_t)q[3] << 16);
-                    *reinterpret_cast<uint2 *>(o) = pk;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (xs + 4 * g + r < w) o[r] = q[r];
-                }
+                for (int r = 0; r < 4; ++r)
+                    if (xs + 4 * g + r < w) o[r] = q[r];
             }
         }
     }
+    if (a.out) {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        constexpr int kParts = NOUT / 8;  // 16-byte pieces per pixel
+        for (int k = lane; k < 16 * kParts; k += 64) {
+            const int px = k / kParts, part = k % kParts;
+            if (xs + px < w)
+                *reinterpret_cast<uint4 *>(a.out + (((int64_t)b * h + y) * w + xs + px) * NOUT + part * 8) =
+                    *reinterpret_cast<const uint4 *>(st + px * SS + part * 8);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // the staging area is reused by the next row
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Epilogue of the last layer for one image row, through LDS: the wave's 16
@@ -225,6 +214,17 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
         const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
         const float wx = sx - fx0;
         const float *px = st + (lane >> 2) * kShufStride;
+        // the four output rows 4y + i sample input rows y - 1, y, y + 1 (clamped):
+        // their horizontal interpolations, once per row and channel
+        const int rows[3] = {y > 0 ? y - 1 : 0, y, y + 1 < h ? y + 1 : h - 1};
+        float hz[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)c * h * w;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                hz[c][k] = (1.0f - wx) * src[(int64_t)rows[k] * w + xa] + wx * src[(int64_t)rows[k] * w + xb];
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int Y = 4 * y + i;
@@ -237,12 +237,14 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
             const float fy0 = floorf(sy);
             const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
             const float wy = sy - fy0;
+            // ya and yb are among the three rows (equal rows hold equal values)
+            const int ka = ya == rows[0] ? 0 : (ya == rows[1] ? 1 : 2);
+            const int kb = yb == rows[0] ? 0 : (yb == rows[1] ? 1 : 2);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)c * h * w;
                 float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)c * H4 * W4;
-                const float top = (1.0f - wx) * src[(int64_t)ya * w + xa] + wx * src[(int64_t)ya * w + xb];
-                const float bot = (1.0f - wx) * src[(int64_t)yb * w + xa] + wx * src[(int64_t)yb * w + xb];
+                const float top = ka == 0 ? hz[c][0] : (ka == 1 ? hz[c][1] : hz[c][2]);
+                const float bot = kb == 0 ? hz[c][0] : (kb == 1 ? hz[c][1] : hz[c][2]);
                 const int ch = c * 16 + 4 * i + j;
                 dst[(int64_t)Y * W4 + X] = (px[ch] + a.bias[ch]) + ((1.0f - wy) * top + wy * bot);
             }
@@ -261,6 +263,7 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     constexpr int NB = NOUT / 16;
     __shared__ __attribute__((aligned(16))) uint16_t wl[9 * NOUT * KS];
     __shared__ float shuf[EPI == kEpiShuffle ? 4 * 16 * kShufStride : 1];
+    __shared__ __attribute__((aligned(16))) uint16_t stage[EPI == kEpiShuffle ? 8 : 4 * 16 * kStageStride<NOUT>];
     const int tid = threadIdx.x;
     // weights [9][NOUT][KIN] -> LDS, 16 bytes per thread per step
     for (int c = tid; c < 9 * NOUT * KIN / 8; c += 256) {
@@ -330,7 +333,8 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
             if (EPI == kEpiShuffle)
                 shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy);
             else
-                conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], b, y + rr, xs, li, g, WS, gx, gy);
+                conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], stage + wave * 16 * kStageStride<NOUT>, b, y + rr, xs, li, g,
+                                              lane, WS);
         }
     }
 }
