@@ -23,7 +23,8 @@ constexpr int kBatch = 64;   // LDS batch of the reverse blend
 // the same order whatever BATCH, ROWS and the schedule, so all variants give
 // bit-identical images.
 // COUNT: also count evaluated (pixel, Gaussian) pairs -- every list entry a
-// pixel evaluates while it is live, the one that stops it included.
+// pixel reaches while it is live, the one that stops it included (the
+// method's work; entries dropped by the tile bound below count as well).
 template <bool COUNT, int BATCH, int ROWS>
 __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict__ views, int nv,
                                            const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ vals,
@@ -32,6 +33,7 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
     constexpr int COLS = 4 / ROWS;
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
     __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    __shared__ uint32_t s_j[BATCH];
     // view of this tile: views are ordered by tile offset
     int lo = 0, hi = nv - 1;
     while (lo < hi) {
@@ -67,24 +69,60 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
+        // Stage the batch, keeping only the entries that can reach alpha >= 1/255
+        // at some pixel centre of the tile: over the box of centres, the
+        // exponent a2 t^2 + c2 dy^2 (a2, c2 <= 0) is at most a2 min t^2 +
+        // c2 min dy^2, with dy over its interval and t = dx + k dy over the
+        // sum of intervals; an entry whose bound gives o 2^e below half the
+        // threshold is below it at every pixel, so dropping it changes no
+        // pixel.  The kept entries are packed in list order, with their
+        // positions for the last-blended index.
+        uint32_t cnt = 0;
 #pragma unroll
         for (int part = 0; part < (BATCH + 63) / 64; ++part) {
             const int slot = part * 64 + lane;
             const uint32_t j = b0 + slot;
+            bool keep = false;
+            Record r;
+            float mu = 0.0f, mv = 0.0f;
             if (slot < BATCH && j < end) {
-                const Record r = R[vals[j]];
-                s_u[slot] = (float)(r.u - dx0);
-                s_v[slot] = (float)(r.v - dy0);
-                s_a[slot] = r.a2; s_k[slot] = r.k; s_c[slot] = r.c2; s_o[slot] = r.o;
-                s_r[slot] = r.r; s_g[slot] = r.g; s_b[slot] = r.b;
+                r = R[vals[j]];
+                mu = (float)(r.u - dx0);
+                mv = (float)(r.v - dy0);
+                const float dlo = 0.5f - mv, dhi = (float)kTile - 0.5f - mv;
+                const float mdy2 = dlo > 0.0f ? dlo * dlo : (dhi < 0.0f ? dhi * dhi : 0.0f);
+                const float k0 = r.k * dlo, k1 = r.k * dhi;
+                const float tlo = (0.5f - mu) + fminf(k0, k1), thi = ((float)kTile - 0.5f - mu) + fmaxf(k0, k1);
+                const float mt2 = tlo > 0.0f ? tlo * tlo : (thi < 0.0f ? thi * thi : 0.0f);
+                const float eb = r.a2 * mt2 + r.c2 * mdy2;
+                keep = !(r.a2 <= 0.0f && r.c2 <= 0.0f) || r.o * __builtin_amdgcn_exp2f(eb) >= 0.5f * kAlphaMin;
             }
+            const uint64_t km = __ballot(keep);
+            if (keep) {
+                const int at = (int)cnt + __popcll(km & ((1ull << lane) - 1ull));
+                s_u[at] = mu;
+                s_v[at] = mv;
+                s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
+                s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
+                s_j[at] = (uint32_t)slot;
+            }
+            cnt += (uint32_t)__popcll(km);
         }
         __syncthreads();
-        const uint32_t cnt = (end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH;
+        // COUNT: a dropped entry is still a pair of every live pixel (nothing
+        // changes between kept entries, so the live pixels are those at the next one)
+        int prev = -1;
         for (uint32_t jj = 0; jj < cnt; ++jj) {
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
             const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
-            const uint32_t idx = b0 - start + jj + 1;
+            const uint32_t idx = b0 - start + s_j[jj] + 1;
+            if (COUNT) {
+                uint32_t live = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) live += alive[q] ? 1u : 0u;
+                npairs += live * (uint32_t)((int)s_j[jj] - prev - 1);
+                prev = (int)s_j[jj];
+            }
             float kdy[ROWS], cdy[ROWS];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
@@ -121,6 +159,13 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 last[q] = blend ? idx : last[q];
                 alive[q] = alive[q] && !stop;
             }
+        }
+        if (COUNT) {
+            const int nb = (int)((end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH);
+            uint32_t live = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) live += alive[q] ? 1u : 0u;
+            npairs += live * (uint32_t)(nb - prev - 1);
         }
         __syncthreads();
     }
