@@ -16,6 +16,25 @@
 namespace a3fr {
 
 constexpr int kBatch = 64;   // LDS batch of the reverse blend
+constexpr float kCullAlpha = 0.95f * kAlphaMin;  // tile bound below which a list entry is dropped
+
+// Whether a list entry can reach alpha >= 1/255 at some pixel centre of its
+// tile ((mu, mv): its centre relative to the tile corner).  Over the box of
+// centres, the exponent a2 t^2 + c2 dy^2 (a2, c2 <= 0) is at most
+// a2 min t^2 + c2 min dy^2, with dy over its interval and t = dx + k dy over
+// the sum of intervals; an entry whose bound gives o 2^e below kCullAlpha is
+// below the threshold at every pixel (the 5% margin, 0.074 in the exponent,
+// is far above the float32 rounding of either side), so dropping it changes
+// no pixel and no gradient.
+__device__ __forceinline__ bool tile_reach(const Record &r, float mu, float mv) {
+    const float dlo = 0.5f - mv, dhi = (float)kTile - 0.5f - mv;
+    const float mdy2 = dlo > 0.0f ? dlo * dlo : (dhi < 0.0f ? dhi * dhi : 0.0f);
+    const float k0 = r.k * dlo, k1 = r.k * dhi;
+    const float tlo = (0.5f - mu) + fminf(k0, k1), thi = ((float)kTile - 0.5f - mu) + fmaxf(k0, k1);
+    const float mt2 = tlo > 0.0f ? tlo * tlo : (thi < 0.0f ? thi * thi : 0.0f);
+    const float eb = r.a2 * mt2 + r.c2 * mdy2;
+    return !(r.a2 <= 0.0f && r.c2 <= 0.0f) || r.o * __builtin_amdgcn_exp2f(eb) >= kCullAlpha;
+}
 
 // Blend one tile.  BATCH: records staged in LDS per step; ROWS: pixel rows per
 // lane (1: four horizontally adjacent pixels, 2: a 2 x 2 block).  Every
@@ -69,14 +88,9 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
-        // Stage the batch, keeping only the entries that can reach alpha >= 1/255
-        // at some pixel centre of the tile: over the box of centres, the
-        // exponent a2 t^2 + c2 dy^2 (a2, c2 <= 0) is at most a2 min t^2 +
-        // c2 min dy^2, with dy over its interval and t = dx + k dy over the
-        // sum of intervals; an entry whose bound gives o 2^e below half the
-        // threshold is below it at every pixel, so dropping it changes no
-        // pixel.  The kept entries are packed in list order, with their
-        // positions for the last-blended index.
+        // Stage the batch, keeping only the entries that can reach the tile
+        // (tile_reach), packed in list order with their positions for the
+        // last-blended index.
         uint32_t cnt = 0;
 #pragma unroll
         for (int part = 0; part < (BATCH + 63) / 64; ++part) {
@@ -89,13 +103,7 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 r = R[vals[j]];
                 mu = (float)(r.u - dx0);
                 mv = (float)(r.v - dy0);
-                const float dlo = 0.5f - mv, dhi = (float)kTile - 0.5f - mv;
-                const float mdy2 = dlo > 0.0f ? dlo * dlo : (dhi < 0.0f ? dhi * dhi : 0.0f);
-                const float k0 = r.k * dlo, k1 = r.k * dhi;
-                const float tlo = (0.5f - mu) + fminf(k0, k1), thi = ((float)kTile - 0.5f - mu) + fmaxf(k0, k1);
-                const float mt2 = tlo > 0.0f ? tlo * tlo : (thi < 0.0f ? thi * thi : 0.0f);
-                const float eb = r.a2 * mt2 + r.c2 * mdy2;
-                keep = !(r.a2 <= 0.0f && r.c2 <= 0.0f) || r.o * __builtin_amdgcn_exp2f(eb) >= 0.5f * kAlphaMin;
+                keep = tile_reach(r, mu, mv);
             }
             const uint64_t km = __ballot(keep);
             if (keep) {
@@ -244,15 +252,25 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
         for (int k = 0; k < NP; ++k) any_alive = any_alive || alive[k];
         if (__ballot(any_alive) == 0ull) break;
         const uint32_t j = b0 + lane;
+        bool keep = false;
+        Record r;
+        float mu = 0.0f, mv = 0.0f;
         if (j < end) {
-            const Record r = R[vals[j]];
-            s_u[lane] = (float)(r.u - dx0);
-            s_v[lane] = (float)(r.v - dy0);
-            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
-            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
+            r = R[vals[j]];
+            mu = (float)(r.u - dx0);
+            mv = (float)(r.v - dy0);
+            keep = tile_reach(r, mu, mv);
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            const int at = __popcll(km & ((1ull << lane) - 1ull));
+            s_u[at] = mu;
+            s_v[at] = mv;
+            s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
+            s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
         }
         __syncthreads();
-        const uint32_t cnt = (end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH;
+        const uint32_t cnt = (uint32_t)__popcll(km);
         for (uint32_t jj = 0; jj < cnt; ++jj) {
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
             float al[NP];
@@ -536,25 +554,38 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
     float *A = acc + (int64_t)lo * n * 12;
     __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
     __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
-    __shared__ uint32_t s_i[kBatch];
+    __shared__ uint32_t s_i[kBatch], s_p[kBatch];
     const double dx0 = (double)x0, dy0 = (double)y0;
     const float kLn2 = 0.6931471805599453f;
 
     for (int64_t bend = maxlast; bend > 0; bend -= kBatch) {
         const uint32_t bstart = bend > kBatch ? (uint32_t)(bend - kBatch) : 0u;
         const uint32_t cnt = (uint32_t)bend - bstart;
+        // the batch's entries that can reach the tile (tile_reach), packed in list order
+        bool keep = false;
+        Record r;
+        uint32_t idx = 0;
+        float mu = 0.0f, mv = 0.0f;
         if ((uint32_t)lane < cnt) {
-            const uint32_t idx = vals[start + bstart + lane];
-            const Record r = R[idx];
-            s_u[lane] = (float)(r.u - dx0);
-            s_v[lane] = (float)(r.v - dy0);
-            s_a[lane] = r.a2; s_k[lane] = r.k; s_c[lane] = r.c2; s_o[lane] = r.o;
-            s_r[lane] = r.r; s_g[lane] = r.g; s_b[lane] = r.b;
-            s_i[lane] = idx;
+            idx = vals[start + bstart + lane];
+            r = R[idx];
+            mu = (float)(r.u - dx0);
+            mv = (float)(r.v - dy0);
+            keep = tile_reach(r, mu, mv);
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            const int at = __popcll(km & ((1ull << lane) - 1ull));
+            s_u[at] = mu;
+            s_v[at] = mv;
+            s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
+            s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
+            s_i[at] = idx;
+            s_p[at] = bstart + (uint32_t)lane;
         }
         __syncthreads();
-        for (int jj = (int)cnt - 1; jj >= 0; --jj) {
-            const uint32_t pos = bstart + (uint32_t)jj;
+        for (int jj = __popcll(km) - 1; jj >= 0; --jj) {
+            const uint32_t pos = s_p[jj];
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
             const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
             const float dy = fy - mv;
