@@ -49,22 +49,22 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="ea6ba1b150fb37adc18453e899c4487b161992f488960bacea798e59e3587dcb",
-                  kib={"32,4x1,grid": (6413.3, 21750.0), "64,4x1,grid": (7190.4, 21750.0),
-                       "128,4x1,grid": (9629.5, 21750.0), "32,2x2,grid": (6414.6, 21750.0),
-                       "64,2x2,grid": (7185.6, 21750.0), "128,2x2,grid": (9584.7, 21750.0),
-                       "32,4x1,queue": (5951.5, 21905.4), "64,4x1,queue": (6634.0, 21875.4),
-                       "128,4x1,queue": (8944.2, 21865.1), "32,2x2,queue": (5917.9, 21845.0),
-                       "64,2x2,queue": (6622.3, 21871.4), "128,2x2,queue": (8977.8, 21872.8)}),
+                  sha256="fcc0913ac5d68e27bdcfe01ff7a168e5196611ef80547738eee99cf8e9d6f04b",
+                  kib={"32,4x1,grid": (6394.3, 21750.0), "64,4x1,grid": (7177.2, 21750.0),
+                       "128,4x1,grid": (9587.9, 21750.0), "32,2x2,grid": (6389.6, 21750.0),
+                       "64,2x2,grid": (7168.8, 21750.0), "128,2x2,grid": (9576.0, 21750.0),
+                       "32,4x1,queue": (5940.3, 21890.3), "64,4x1,queue": (6633.2, 21878.1),
+                       "128,4x1,queue": (8990.4, 21882.5), "32,2x2,queue": (5967.6, 22022.8),
+                       "64,2x2,queue": (6630.2, 21840.2), "128,2x2,queue": (8987.9, 21931.5)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="50200eb6778e31d54d4fa2eccc59665b9fec8c917870ca15e5cbcf19a41a7bf4",
-                       kib={"k_preprocess": (43371.0, 115881.5)}),
+                       sha256="8dcc71bd18b51a6682afd769ab143ad5284dbd6845e5c34bf2bf72cbdbbcbf96",
+                       kib={"k_preprocess": (43593.6, 164107.4)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="50200eb6778e31d54d4fa2eccc59665b9fec8c917870ca15e5cbcf19a41a7bf4",
-                   kib={"k_entry_colour": (82529.7, 13795.5)}),
+                   sha256="8dcc71bd18b51a6682afd769ab143ad5284dbd6845e5c34bf2bf72cbdbbcbf96",
+                   kib={"k_entry_colour": (50111.0, 13817.6)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the two tile-id passes of the key sort
-                      sha256="031a3a1107f11ffa173d6cfb354f57dc8d5610e54db00eb1a490a27b1d29bdfe",
-                      kib={"k_onesweep": (45781.8, 89767.0)}),
+                      sha256="5bb1141157425798afc95ec2f928a1de2b00324a65083696d567abfa165802bf",
+                      kib={"k_onesweep": (45731.5, 89889.1)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale and quaternion of every Gaussian (40 B) once
@@ -263,7 +263,7 @@ def main():
             if v["launches"]:
                 stages[name] = dict(ms_per_frame=v["ms"] / args.steps, launches_per_frame=v["launches"] / args.steps,
                                     ms_per_launch=v["ms"] / v["launches"])
-        # sort pass: bytes per launch = 24 B x keys
+        # sort pass: bytes per launch = SORT_BYTES_PER_KEY_PASS x keys
         sp = st["sort_pass"]
         if sp["launches"]:
             per_launch_s = sp["ms"] / sp["launches"] / 1000.0
