@@ -196,6 +196,14 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
             rk[it] = prior + below;
             if (valid && below == 0) s_wh[w][d] = prior + (uint32_t)__popcll(m);
         }
+        // the values are loaded now, so that their round trip overlaps the
+        // digit bookkeeping and the look-back (they were not live during the ranking)
+        uint32_t val[kSortItems];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
+            val[it] = pos < K ? vin[pos] : 0u;
+        }
         __syncthreads();
 
         // threads 0..255 = digits: totals, per-wave exclusive offsets, publication, look-back
@@ -221,11 +229,26 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
         }
         __syncthreads();
         if (tid < kRadix) {
-            const int d = tid;
             uint32_t pre = 0;
 #pragma unroll
             for (int q = 0; q < kDigitWaves; ++q) if (q < w) pre += s_wsum[q];
-            s_lstart[d] += pre;
+            s_lstart[tid] += pre;
+        }
+        __syncthreads();
+        // local scatter into LDS (positions within the partition are known
+        // before the look-back), then the digit threads look back
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
+            if (pos < K) {
+                const uint32_t dg = (key[it] >> shift) & 255u;
+                const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
+                s_k[lp] = key[it];
+                s_v[lp] = val[it];
+            }
+        }
+        if (tid < kRadix) {
+            const int d = tid;
             uint32_t excl = 0;
             if (part > 0) {
                 // look back over a window of kWin predecessors at a time: the
@@ -256,19 +279,6 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
                 st_status(&status[(int64_t)part * kRadix + d], kFlagInc | (excl + tot));
             }
             s_gbase[d] = s_gexcl[d] + excl;
-        }
-        __syncthreads();
-
-        // values are loaded only now, so that they are not live during the ranking
-#pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
-            const int64_t pos = base + w * (kSortItems * kWave) + it * kWave + lane;
-            if (pos < K) {
-                const uint32_t dg = (key[it] >> shift) & 255u;
-                const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
-                s_k[lp] = key[it];
-                s_v[lp] = vin[pos];
-            }
         }
         __syncthreads();
         const int64_t rem = K - base;
