@@ -423,9 +423,14 @@ a3fr_status a3fr_set_fallback(a3fr_ctx *ctx, double mse_threshold, double coef, 
  *   schedule 0: one wave per tile in tile order; 1: persistent waves pulling
  *   active tiles longest list first (the paper's ordering of tiles by their
  *   number of Gaussians, Sec. 3.5), from an O(tiles) bucket order by the bit
- *   length of the list length.
+ *   length of the list length;
+ * and, for variant = 12 + batch_index, a block of four waves per tile in tile
+ * order, each wave one 8 x 8 quadrant with one pixel per lane (the
+ * cooperative groups of the paper's AMR renderer, Sec. 3.4), batch
+ * {64, 128, 256}[batch_index]: each wave walks only the entries that can
+ * reach its quadrant.
  * The tile itself stays 16 x 16 (the binning unit of the keys). */
-#define A3FR_BLEND_VARIANTS 12
+#define A3FR_BLEND_VARIANTS 15
 a3fr_status a3fr_set_blend_variant(a3fr_ctx *ctx, int32_t variant);
 
 /* Times every variant on the current frame (after a3fr_bin_sort; writes a

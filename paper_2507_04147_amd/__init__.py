@@ -27,11 +27,13 @@ BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, 
            active=9, keep=10, records=11, depth_order=12, net_x0=13, net_a1=14, net_a2=15, net_g3=16, net_g2=17,
            net_g1=18, fb_energy=19, fb_flags=20)
 NET_PARAMS = 24016
-BLEND_VARIANTS = 12
+BLEND_VARIANTS = 15
 
 
 def blend_variant_desc(k):
     """(LDS batch, lane pixel block, schedule) of blend variant k."""
+    if k >= 12:
+        return (64, 128, 256)[k - 12], "8x8q", "grid"
     return (32, 64, 128)[k % 3], ("4x1", "2x2")[(k // 3) % 2], ("grid", "queue")[k // 6]
 # full-resolution fallback of the periphery: (MSE threshold, coef, power) of the
 # estimate coef x (dT^2)^power, dT the rise of a periphery tile's transmittance

@@ -165,8 +165,9 @@ struct BlendArgs {
     uint32_t *order;             // [ntiles] (queue schedule)
     int64_t queue_waves;         // persistent waves of the queue schedule
 };
-struct BlendVariant { int batch, rows; bool queue; };
-constexpr int kBlendVariants = A3FR_BLEND_VARIANTS;  // batch {32, 64, 128} x rows {1, 2} x {grid, queue}
+struct BlendVariant { int batch, rows; bool queue, quad; };
+// batch {32, 64, 128} x rows {1, 2} x {grid, queue}, then the quadrant blocks with batch {64, 128, 256}
+constexpr int kBlendVariants = A3FR_BLEND_VARIANTS;
 constexpr int kBlendDefault = 1;      // batch 64, 4 x 1 pixels per lane, grid
 constexpr int kBlendWsWords = 68;
 BlendVariant blend_variant(int k);

@@ -26,14 +26,21 @@ constexpr float kCullAlpha = 0.95f * kAlphaMin;  // tile bound below which a lis
 // below the threshold at every pixel (the 5% margin, 0.074 in the exponent,
 // is far above the float32 rounding of either side), so dropping it changes
 // no pixel and no gradient.
-__device__ __forceinline__ bool tile_reach(const Record &r, float mu, float mv) {
-    const float dlo = 0.5f - mv, dhi = (float)kTile - 0.5f - mv;
+// The same bound over the pixel centres [bx + 0.5, bx + size - 0.5] x
+// [by + 0.5, by + size - 0.5] of a square block of the tile.
+__device__ __forceinline__ bool box_reach(float a2, float k, float c2, float o, float mu, float mv, float bx, float by,
+                                          float size) {
+    const float dlo = (by + 0.5f) - mv, dhi = (by + size - 0.5f) - mv;
     const float mdy2 = dlo > 0.0f ? dlo * dlo : (dhi < 0.0f ? dhi * dhi : 0.0f);
-    const float k0 = r.k * dlo, k1 = r.k * dhi;
-    const float tlo = (0.5f - mu) + fminf(k0, k1), thi = ((float)kTile - 0.5f - mu) + fmaxf(k0, k1);
+    const float k0 = k * dlo, k1 = k * dhi;
+    const float tlo = ((bx + 0.5f) - mu) + fminf(k0, k1), thi = ((bx + size - 0.5f) - mu) + fmaxf(k0, k1);
     const float mt2 = tlo > 0.0f ? tlo * tlo : (thi < 0.0f ? thi * thi : 0.0f);
-    const float eb = r.a2 * mt2 + r.c2 * mdy2;
-    return !(r.a2 <= 0.0f && r.c2 <= 0.0f) || r.o * __builtin_amdgcn_exp2f(eb) >= kCullAlpha;
+    const float eb = a2 * mt2 + c2 * mdy2;
+    return !(a2 <= 0.0f && c2 <= 0.0f) || o * __builtin_amdgcn_exp2f(eb) >= kCullAlpha;
+}
+
+__device__ __forceinline__ bool tile_reach(const Record &r, float mu, float mv) {
+    return box_reach(r.a2, r.k, r.c2, r.o, mu, mv, 0.0f, 0.0f, (float)kTile);
 }
 
 // Blend one tile.  BATCH: records staged in LDS per step; ROWS: pixel rows per
@@ -198,7 +205,7 @@ __device__ __forceinline__ void add_pairs(uint32_t npairs, unsigned long long *p
     if (COUNT) {
         unsigned long long tot = npairs;
         for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
-        if (threadIdx.x == 0) atomicAdd(pairs, tot);
+        if ((threadIdx.x & 63) == 0) atomicAdd(pairs, tot);
     }
 }
 
@@ -356,6 +363,125 @@ void launch_blend_amr(const DevView *views, int nv, int64_t ntiles, const uint32
                        r2, rgb);
 }
 
+// Quadrant schedule: a block of four waves per tile, wave w owning the 8 x 8
+// quadrant (w % 2, w / 2) with one pixel per lane.  The block stages each
+// batch of the list in LDS; every wave then keeps the staged entries that can
+// reach its quadrant (box_reach over its pixel centres) and walks only those,
+// so an entry costs the quadrants it can touch rather than the whole tile.
+// Every pixel evaluates the same float32 expressions over the same list in
+// the same order as k_blend, so the images are bit-identical.
+template <bool COUNT, int BATCH>
+__global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ views, int nv,
+                                                   const uint8_t *__restrict__ active,
+                                                   const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
+                                                   int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
+                                                   uint32_t *__restrict__ lastout,
+                                                   unsigned long long *__restrict__ pairs) {
+    const int64_t gt = blockIdx.x;
+    if (!active[gt]) return;  // block-uniform
+    __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    __shared__ uint16_t s_list[4][BATCH];
+    __shared__ uint32_t s_live[4];
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    const DevView &dv = views[lo];
+    const int64_t lt = gt - dv.tile_off;
+    const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
+    const int W = dv.v.width, H = dv.v.height;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int qx = (w & 1) * 8, qy = (w >> 1) * 8;
+    const int px = qx + (lane & 7), py = qy + (lane >> 3);
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    bool alive = (x0 + px < W) && (y0 + py < H);
+    float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
+    uint32_t last = 0, npairs = 0;
+    const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
+    const Record *R = rec + (int64_t)lo * n;
+    const double dx0 = (double)x0, dy0 = (double)y0;
+    const uint64_t ltm = (1ull << lane) - 1ull;
+
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+        const uint64_t live = __ballot(alive);
+        if (lane == 0) s_live[w] = live != 0ull ? 1u : 0u;
+        for (int slot = tid; slot < BATCH; slot += 256) {
+            const uint32_t j = b0 + slot;
+            if (j < end) {
+                const Record r = R[vals[j]];
+                s_u[slot] = (float)(r.u - dx0);
+                s_v[slot] = (float)(r.v - dy0);
+                s_a[slot] = r.a2; s_k[slot] = r.k; s_c[slot] = r.c2; s_o[slot] = r.o;
+                s_r[slot] = r.r; s_g[slot] = r.g; s_b[slot] = r.b;
+            }
+        }
+        __syncthreads();
+        if ((s_live[0] | s_live[1] | s_live[2] | s_live[3]) == 0u) break;  // block-uniform: every pixel done
+        const uint32_t cnt = (end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH;
+        uint32_t wcnt = 0;
+        if (live != 0ull) {
+            for (uint32_t base = 0; base < cnt; base += 64) {
+                const uint32_t jj = base + (uint32_t)lane;
+                const bool keep = jj < cnt && box_reach(s_a[jj], s_k[jj], s_c[jj], s_o[jj], s_u[jj], s_v[jj],
+                                                        (float)qx, (float)qy, 8.0f);
+                const uint64_t km = __ballot(keep);
+                if (keep) s_list[w][wcnt + (uint32_t)__popcll(km & ltm)] = (uint16_t)jj;
+                wcnt += (uint32_t)__popcll(km);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // COUNT: a dropped entry is still a pair of every live pixel
+        int prev = -1;
+        for (uint32_t q = 0; q < wcnt; ++q) {
+            const uint32_t jj = s_list[w][q];
+            if (COUNT) {
+                npairs += alive ? (uint32_t)((int)jj - prev) : 0u;  // the dropped ones before it, and itself
+                prev = (int)jj;
+            }
+            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+            const float dy = fy - mv;
+            const float kdy = kk * dy;
+            const float cdy = c2 * dy * dy;
+            const float t = (fx - mu) + kdy;
+            const float e = fmaf(a2, t * t, cdy);
+            const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
+            const bool take = alive && al >= kAlphaMin;
+            if (__ballot(take) == 0ull) continue;
+            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
+            const float Tn = T * (1.0f - al);
+            const bool stop = take && Tn < kTMin;
+            const bool blend = take && !stop;
+            const float wgt = blend ? al * T : 0.0f;
+            Cr = fmaf(wgt, cr, Cr);
+            Cg = fmaf(wgt, cg, Cg);
+            Cb = fmaf(wgt, cb, Cb);
+            T = blend ? Tn : T;
+            last = blend ? b0 - start + jj + 1 : last;
+            alive = alive && !stop;
+        }
+        if (COUNT) npairs += alive ? (uint32_t)((int)cnt - 1 - prev) : 0u;
+        __syncthreads();  // the staging is reused by the next batch
+    }
+    const int x = x0 + px, y = y0 + py;
+    if (x < W && y < H) {
+        const int64_t HW = (int64_t)W * H;
+        float *img = rgb + 3 * dv.img_off;
+        const int64_t pix = (int64_t)y * W + x;
+        img[pix] = Cr + T * dv.v.bg[0];
+        img[HW + pix] = Cg + T * dv.v.bg[1];
+        img[2 * HW + pix] = Cb + T * dv.v.bg[2];
+        if (Tout) Tout[dv.img_off + pix] = T;
+        if (lastout) lastout[dv.img_off + pix] = last;
+    }
+    add_pairs<COUNT>(npairs, pairs);
+}
+
 // grid schedule: one wave per tile, in tile order
 template <bool COUNT, int BATCH, int ROWS>
 __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views, int nv,
@@ -457,6 +583,30 @@ void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t n
 void launch_blend(const BlendArgs &a, int variant, hipStream_t s) {
     if (a.ntiles == 0) return;
     const BlendVariant v = blend_variant(variant);
+    if (v.quad) {
+        const dim3 g((unsigned)a.ntiles), b(256);
+        switch (v.batch) {
+            case 64:
+                if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 64>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                else hipLaunchKernelGGL((k_blend_quad<false, 64>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                break;
+            case 128:
+                if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 128>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                else hipLaunchKernelGGL((k_blend_quad<false, 128>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                break;
+            default:
+                if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 256>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                else hipLaunchKernelGGL((k_blend_quad<false, 256>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                break;
+        }
+        return;
+    }
     if (v.queue) {
         launch_blend_order(a.active, a.ranges, a.ntiles, a.ws, a.order, s);
         launch_fill_u32(a.ws + 67, 0u, 1, s);
@@ -472,12 +622,20 @@ void launch_blend(const BlendArgs &a, int variant, hipStream_t s) {
 }
 
 BlendVariant blend_variant(int k) {
-    static const int batches[3] = {32, 64, 128};
+    static const int batches[3] = {32, 64, 128}, quad_batches[3] = {64, 128, 256};
     BlendVariant v;
     k = k < 0 ? 0 : (k >= kBlendVariants ? kBlendVariants - 1 : k);
+    if (k >= 12) {  // four waves per tile, an 8 x 8 quadrant each
+        v.batch = quad_batches[k - 12];
+        v.rows = 1;
+        v.queue = false;
+        v.quad = true;
+        return v;
+    }
     v.batch = batches[k % 3];
     v.rows = 1 + (k / 3) % 2;
     v.queue = k / 6 != 0;
+    v.quad = false;
     return v;
 }
 

@@ -401,9 +401,11 @@ def test_full_size_full_res_frame_sampled(pkg, ctx):
         assert np.abs(g - o_rgb)[~ok].max(initial=0.0) <= AMB_TOL
 
 
-def test_blend_pair_count_matches_oracle(pkg, ctx):
+@pytest.mark.parametrize("variant", [1, 3, 12, 14])
+def test_blend_pair_count_matches_oracle(pkg, ctx, variant):
     """The evaluated-pair counter behind the blend roofline counts what the
-    oracle counts: per pixel, the list entries evaluated until it stops."""
+    oracle counts: per pixel, the list entries evaluated until it stops
+    (entries a variant drops by its tile or quadrant bound included)."""
     W, H = 232, 240
     scene, cams = synth.foveated_stereo(n=60_000, width=W, height=H, seed=4)
     views = oracle.foveated_views(cams, [(c.cx, c.cy) for c in cams], (0.15 * W, 0.35 * W))
@@ -414,10 +416,12 @@ def test_blend_pair_count_matches_oracle(pkg, ctx):
     ctx.bin_sort()
     npx = sum(v.width * v.height for v in views)
     rgb = torch.zeros(3 * npx, device="cuda")
+    ctx.set_blend_variant(variant)
     ctx.set_profiling(True)
     ctx.blend(rgb)
     prof = ctx.get_profile()
     ctx.set_profiling(False)
+    ctx.set_blend_variant(1)
     want = 0
     amb_pairs = 0
     for v, vw in enumerate(views):
