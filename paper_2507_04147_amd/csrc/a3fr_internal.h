@@ -114,14 +114,16 @@ void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint3
                          int64_t m, Record *rec, hipStream_t s);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
-                   uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s);
+                   uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s,
+                   bool zeroed = false /* the first select_hist_words(nsel) words already zero */);
+int64_t select_hist_words(int nsel);
 int64_t select_workspace_words(int nsel, int64_t n);
 // scan workspace (uint64 words) for m = nv * n entry slots; the compaction
 // clears it, so the key offsets must follow that compaction
 int64_t scan_workspace_words(int64_t m);
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
                             const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
-                            uint32_t *n_ent, uint32_t *err, hipStream_t s);
+                            uint32_t *n_ent, uint32_t *err, hipStream_t s, bool zeroed = false /* ws already zero */);
 void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
                         uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
                         hipStream_t s);
@@ -144,7 +146,7 @@ constexpr int kSortItemsSmall = 4;
 int sort_partitions(int64_t n, int items);
 int64_t sort_workspace_words(int64_t n_max, int npass, int items);
 void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
-                         uint32_t *ws, hipStream_t s);
+                         uint32_t *ws, hipStream_t s, bool zeroed = false /* ws already zero */);
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
                       int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
@@ -229,7 +231,7 @@ void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm,
                        int nblk, hipStream_t s);
 void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-constexpr int kFillSegs = 4;
+constexpr int kFillSegs = 8;
 struct FillSegs {
     uint32_t *p[kFillSegs];
     int64_t n[kFillSegs];  // words; only the first count are used

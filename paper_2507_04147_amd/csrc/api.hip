@@ -396,7 +396,7 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
 
 static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *views, int32_t nv);
 static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den);
-static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene);
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed = false);
 
 a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_view *views, int32_t nv,
                             int32_t keep_num, int32_t keep_den) {
@@ -557,17 +557,13 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
                       c->stream); }
-    if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
-        launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
-                      keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream); }
-    c->fb_last = false;
-    if (!c->fb_plan.empty() && c->nsel) {
-        // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
-        StageTimer t_(c, A3FR_STAGE_FALLBACK);
-        // difference planes of every periphery view: [2][tiles_y + 1][tiles_x + 1] doubles each;
-        // the pairs go in batches of up to kFbMax per launch
-        std::vector<FbBatch> fbs;
-        int64_t dwords = 0, max_ptiles = 0, max_part = 0;
+    // the fallback pairs (periphery view, its eye's full-resolution view); their
+    // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of
+    // up to kFbMax per launch
+    const bool do_fb = !c->fb_plan.empty() && c->nsel;
+    std::vector<FbBatch> fbs;
+    int64_t dwords = 0, max_ptiles = 0, max_part = 0;
+    if (do_fb) {
         for (const auto &fp : c->fb_plan) {
             if (fbs.empty() || fbs.back().count == kFbMax) fbs.push_back(FbBatch{});
             FbBatch &fb = fbs.back();
@@ -588,12 +584,35 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         TRY(ensure(c, c->fb_diff, sizeof(double) * (size_t)dwords));
         TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)drop_energy_parts() * (size_t)max_part));
         TRY(ensure(c, c->fb_count, 16));
+    }
+    {   // one launch clears what the later stages accumulate into: the select
+        // histograms, the fallback's counters and planes, the scans' tickets and
+        // status words, the depth sort's histograms and status words
+        StageTimer t_(c, A3FR_STAGE_MASKS);
+        const int64_t m = (int64_t)nv * n;
         FillSegs z{};
-        z.p[0] = P<uint32_t>(c->fb_count), z.n[0] = 1;
-        z.p[1] = P<uint32_t>(c->fb_energy), z.n[1] = 2 * toff;
-        z.p[2] = P<uint32_t>(c->fb_diff), z.n[2] = 2 * dwords;
-        z.count = 3;
+        const auto add = [&z](void *p, int64_t words) {
+            z.p[z.count] = reinterpret_cast<uint32_t *>(p);
+            z.n[z.count] = words;
+            ++z.count;
+        };
+        if (c->nsel) add(c->sel.p, select_hist_words(c->nsel));
+        if (do_fb) {
+            add(c->fb_count.p, 1);
+            add(c->fb_energy.p, 2 * toff);
+            add(c->fb_diff.p, 2 * dwords);
+        }
+        add(c->block_sums.p, 2 * scan_workspace_words(m));
+        add(c->sort_status.p, sort_workspace_words(m, 4, kSortItemsSmall));
         launch_zero_segs(z, c->stream);
+    }
+    if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
+        launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
+                      keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream, true); }
+    c->fb_last = false;
+    if (do_fb) {
+        // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
+        StageTimer t_(c, A3FR_STAGE_FALLBACK);
         for (const FbBatch &fb : fbs) {
             launch_drop_energy(dv, fb, n, P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
                                P<double>(c->score), P<double>(c->fb_diff), P<double>(c->fb_part), toff,
@@ -613,12 +632,13 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
                            P<uint32_t>(c->fb_count), c->stream);
         c->fb_last = true;
     }
-    return entry_stages(c, scene);
+    return entry_stages(c, scene, true);
 }
 
 // Entries that emit keys (count > 0, kept): compaction, colour (scene not
-// NULL), stable sort by depth, key offsets in depth order.
-static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
+// NULL), stable sort by depth, key offsets in depth order.  zeroed: the scan
+// and depth-sort workspaces were cleared by the frame's first clearing launch.
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed) {
     const int64_t n = c->n;
     const int nv = c->nv;
     const int64_t m = (int64_t)nv * n;
@@ -627,7 +647,8 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
                                P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
-                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), sc_err(c->scalars), c->stream);
+                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), sc_err(c->scalars), c->stream,
+                               zeroed);
     }
     if (scene && c->defer_colour) {
         c->colour_scene = *scene;
@@ -639,7 +660,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene) {
     {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
         StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
         launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, kSortItemsSmall, P<uint32_t>(c->sort_status),
-                            c->stream);
+                            c->stream, zeroed);
         uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
         uint32_t *vi = P<uint32_t>(c->ent_a), *vo = P<uint32_t>(c->ent_b);
         for (int p = 0; p < 4; ++p) {

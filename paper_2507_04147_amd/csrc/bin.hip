@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(1024) k_sel_final(const int32_t *sel_views, in
 
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
-                   uint32_t *sel_ws, uint8_t *keep, hipStream_t s) {
+                   uint32_t *sel_ws, uint8_t *keep, hipStream_t s, bool zeroed) {
     (void)views; (void)nv;
     if (nsel == 0 || n == 0) return;
     // workspace: hist [nsel][2][4096] u32 | state [nsel] (8 words) | cand_key [nsel][n] u64 | cand_idx [nsel][n] u32
@@ -316,7 +316,7 @@ void launch_select(const DevView *views, int nv, const int32_t *sel_views, int n
     SelState *st = reinterpret_cast<SelState *>(sel_ws + (int64_t)nsel * 2 * kSelBuckets);
     uint64_t *ck = reinterpret_cast<uint64_t *>(sel_ws + (int64_t)nsel * 2 * kSelBuckets + (int64_t)nsel * 8);
     uint32_t *ci = reinterpret_cast<uint32_t *>(ck + (int64_t)nsel * n);
-    launch_fill_u32(hist, 0u, (int64_t)nsel * 2 * kSelBuckets, s);
+    if (!zeroed) launch_fill_u32(hist, 0u, select_hist_words(nsel), s);
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     const unsigned hb = (unsigned)(blocks < 256 ? blocks : 256);
@@ -327,6 +327,9 @@ void launch_select(const DevView *views, int nv, const int32_t *sel_views, int n
                        keep_num, keep_den, ck, ci, keep);
     hipLaunchKernelGGL(k_sel_final, dim3((unsigned)nsel), dim3(1024), 0, s, sel_views, n, st, ck, ci, keep);
 }
+
+// words of the level histograms at the start of the select workspace (cleared before each select)
+int64_t select_hist_words(int nsel) { return (int64_t)nsel * 2 * kSelBuckets; }
 
 // words of select workspace (hist, state, candidates) for nsel views of n Gaussians
 int64_t select_workspace_words(int nsel, int64_t n) {
@@ -594,11 +597,11 @@ int64_t scan_workspace_words(int64_t m) { return 2 + compact_parts(m) + (m + kSc
 
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
                             const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
-                            uint32_t *n_ent, uint32_t *err, hipStream_t s) {
+                            uint32_t *n_ent, uint32_t *err, hipStream_t s, bool zeroed) {
     const int64_t m = (int64_t)nv * n;
     const int64_t nb = compact_parts(m);
     // both scans' tickets and status words
-    launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, 2 * scan_workspace_words(m), s);
+    if (!zeroed) launch_fill_u32(reinterpret_cast<uint32_t *>(ws), 0u, 2 * scan_workspace_words(m), s);
     if (nb == 0) {
         FillSegs z{};
         z.p[0] = reinterpret_cast<uint32_t *>(total), z.n[0] = 2;

@@ -302,9 +302,9 @@ int64_t sort_workspace_words(int64_t n_max, int npass, int items) {
 }
 
 void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
-                         uint32_t *ws, hipStream_t s) {
+                         uint32_t *ws, hipStream_t s, bool zeroed) {
     const int nparts = sort_partitions(n_max, items);
-    launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass, items), s);
+    if (!zeroed) launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass, items), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
     if (hblocks > 512) hblocks = 512;
