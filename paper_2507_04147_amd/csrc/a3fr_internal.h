@@ -185,9 +185,10 @@ void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_
 void launch_activate(const a3fr_params &p, float *scale, float *opacity, hipStream_t s);
 void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
                            const a3fr_grads &g, hipStream_t s);
-void launch_net_pack(const float *theta, const NetPacked &pk, hipStream_t s);
-void launch_net_input(const float *x, int64_t x_bstride, int B, int h, int w, uint16_t *nhwc, uint16_t *chw,
-                      hipStream_t s);
+// the packed weights of theta and the bf16 input (NHWC8, plus the
+// channel-major copy when chw is not NULL; x_bstride 0: 3 h w), one launch
+void launch_net_prep(const float *theta, const NetPacked &pk, const float *x, int64_t x_bstride, int B, int h, int w,
+                     uint16_t *nhwc, uint16_t *chw, hipStream_t s);
 void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a, hipStream_t s);
 void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s);
 void launch_net_mse(const float *out, const float *target, int B, int h, int w, uint16_t *g_nhwc, uint16_t *g_chw,
@@ -207,14 +208,15 @@ struct FbBatch {
     int64_t doff[kFbMax];
 };
 int drop_energy_parts();
+// Mass maps of every pair of the batch, then each pair's periphery tiles
+// flagged (estimate coef (dT^2)^power >= threshold, outside r_mid) with the
+// covered full-resolution tiles activated and n_flagged counted.
 void launch_drop_energy(const DevView *views, const FbBatch &b, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score,
                         double *diff /* zeroed planes of every pair, at b.doff */,
                         double *partials /* [b.count][drop_energy_parts()][b.max_cells] */, int64_t ntiles,
-                        float *energy /* [2][ntiles]: dropped mass, kept mass */, hipStream_t s);
-void launch_fallback_flags(const DevView *views, const FbBatch &b, int64_t max_periph_tiles, const float *energy,
-                           int64_t ntiles, double threshold, double coef, double power, uint8_t *flags,
-                           uint8_t *active, uint32_t *n_flagged, hipStream_t s);
+                        float *energy /* [2][ntiles]: dropped mass, kept mass */, double threshold, double coef,
+                        double power, uint8_t *flags, uint8_t *active, uint32_t *n_flagged, hipStream_t s);
 void launch_rows_from_active(const DevView *views, int64_t rows_total, const int32_t *row_view, const int32_t *row_y,
                              const uint8_t *active, uint16_t *row_prefix, uint16_t *row_list,
                              const uint32_t *n_flagged, hipStream_t s);

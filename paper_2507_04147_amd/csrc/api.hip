@@ -562,7 +562,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     // up to kFbMax per launch
     const bool do_fb = !c->fb_plan.empty() && c->nsel;
     std::vector<FbBatch> fbs;
-    int64_t dwords = 0, max_ptiles = 0, max_part = 0;
+    int64_t dwords = 0, max_part = 0;
     if (do_fb) {
         for (const auto &fp : c->fb_plan) {
             if (fbs.empty() || fbs.back().count == kFbMax) fbs.push_back(FbBatch{});
@@ -576,7 +576,6 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
             fb.max_cells = std::max(fb.max_cells, cells);
             ++fb.count;
             dwords += cells;
-            max_ptiles = std::max<int64_t>(max_ptiles, (int64_t)hp.tiles_x * hp.tiles_y);
             max_part = std::max<int64_t>(max_part, (int64_t)fb.count * fb.max_cells);
         }
         TRY(ensure(c, c->fb_energy, sizeof(float) * 2 * (size_t)toff));
@@ -616,10 +615,8 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         for (const FbBatch &fb : fbs) {
             launch_drop_energy(dv, fb, n, P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect),
                                P<double>(c->score), P<double>(c->fb_diff), P<double>(c->fb_part), toff,
-                               P<float>(c->fb_energy), c->stream);
-            launch_fallback_flags(dv, fb, max_ptiles, P<float>(c->fb_energy), toff, c->fb_thr, c->fb_coef, c->fb_pow,
-                                  P<uint8_t>(c->fb_flags), P<uint8_t>(c->active), P<uint32_t>(c->fb_count),
-                                  c->stream);
+                               P<float>(c->fb_energy), c->fb_thr, c->fb_coef, c->fb_pow, P<uint8_t>(c->fb_flags),
+                               P<uint8_t>(c->active), P<uint32_t>(c->fb_count), c->stream);
         }
         launch_rows_from_active(dv, c->rows_total, d_row_view, d_row_y, P<uint8_t>(c->active),
                                 P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->fb_count),
@@ -996,8 +993,7 @@ static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n
     const float *theta = c->net_theta;
     const NetPacked pk = net_packed(c);
     const float *in = L + 3 * c->hviews[2].img_off;
-    launch_net_pack(theta, pk, c->stream);
-    launch_net_input(in, in_stride, n_eyes, h, w, P<uint16_t>(c->net_x0), nullptr, c->stream);
+    launch_net_prep(theta, pk, in, in_stride, n_eyes, h, w, P<uint16_t>(c->net_x0), nullptr, c->stream);
     NetConvArgs a{};
     a.B = n_eyes; a.h = h; a.w = w;
     a.rows = kNetFrameRows;
@@ -1341,8 +1337,8 @@ a3fr_status a3fr_net_forward(a3fr_ctx *c, const float *theta, const float *in, i
     }
     c->net_trained_fwd = false;
     const NetPacked pk = net_packed(c);
-    launch_net_pack(theta, pk, c->stream);
-    launch_net_input(in, 0, B, h, w, P<uint16_t>(c->net_x0), train ? P<uint16_t>(c->net_x0c) : nullptr, c->stream);
+    launch_net_prep(theta, pk, in, 0, B, h, w, P<uint16_t>(c->net_x0), train ? P<uint16_t>(c->net_x0c) : nullptr,
+                    c->stream);
     NetConvArgs a{};
     a.B = B; a.h = h; a.w = w;
     a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1;

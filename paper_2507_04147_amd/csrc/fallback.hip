@@ -111,12 +111,45 @@ __global__ void __launch_bounds__(256) k_drop_reduce(const DevView *__restrict__
     }
 }
 
+// Flag of periphery tile t of pair k: set when the tile's estimate reaches the
+// threshold and one of the full-resolution pixel centres it covers lies
+// outside r_mid (the composite's periphery region); a flagged tile activates
+// the tiles it covers in the full-resolution layer fv (s = full-resolution
+// pixels per periphery pixel).
+__device__ __forceinline__ void fallback_flag_tile(const DevView &dp, const DevView &df, double r_mid, int64_t t,
+                                                   const float *energy, int64_t ntiles, double threshold, double coef,
+                                                   double power, uint8_t *flags, uint8_t *active,
+                                                   uint32_t *n_flagged) {
+    const int tx = (int)(t % dp.tiles_x), ty = (int)(t / dp.tiles_x);
+    const int s = (int)llround(df.v.fx / dp.v.fx);
+    const int span = kTile * s;  // full-resolution pixels per periphery tile, per axis
+    const double x0 = (double)tx * span + 0.5, x1 = fmin((double)(tx + 1) * span, (double)df.v.width) - 0.5;
+    const double y0 = (double)ty * span + 0.5, y1 = fmin((double)(ty + 1) * span, (double)df.v.height) - 0.5;
+    const double gx = df.v.gx, gy = df.v.gy;
+    const double fx = fmax(fabs(x0 - gx), fabs(x1 - gx)), fy = fmax(fabs(y0 - gy), fabs(y1 - gy));
+    const bool outer = x0 <= x1 && y0 <= y1 && fx * fx + fy * fy > r_mid * r_mid;
+    // Beer-Lambert: transmittance ~ exp(-mass per pixel); dropping raises it by dT
+    const double D = energy[dp.tile_off + t], K = energy[ntiles + dp.tile_off + t];
+    const double dT = exp(-K) - exp(-(K + D));
+    const double est = dT > 0.0 ? coef * pow(dT * dT, power) : 0.0;
+    const bool flag = outer && est >= threshold;
+    flags[dp.tile_off + t] = flag ? 1 : 0;
+    if (!flag) return;
+    atomicAdd(n_flagged, 1u);
+    for (int yy = ty * s; yy < (ty + 1) * s && yy < df.tiles_y; ++yy)
+        for (int xx = tx * s; xx < (tx + 1) * s && xx < df.tiles_x; ++xx)
+            active[df.tile_off + (int64_t)yy * df.tiles_x + xx] = 1;
+}
+
 // One block per pair: 2D inclusive prefix sum of its two difference planes
 // (in place: first along each row, then down each column, one thread per row
 // or column, so a thread's chain of dependent loads is one row or column
-// long), written as float32 into energy [2][ntiles] at the view's tiles.
+// long), written as float32 into energy [2][ntiles] at the view's tiles; then
+// the same block flags the pair's periphery tiles (fallback_flag_tile).
 __global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict__ views, FbBatch b, double *diff,
-                                                      int64_t ntiles, float *__restrict__ energy) {
+                                                      int64_t ntiles, float *__restrict__ energy, double threshold,
+                                                      double coef, double power, uint8_t *__restrict__ flags,
+                                                      uint8_t *__restrict__ active, uint32_t *__restrict__ n_flagged) {
     extern __shared__ double pre[];  // the two planes when they fit (dynamic size, else unused)
     const int kp = blockIdx.x;
     const DevView &dv = views[b.pv[kp]];
@@ -148,6 +181,10 @@ __global__ void __launch_bounds__(1024) k_drop_prefix(const DevView *__restrict_
             E[(int64_t)y * TX] = (float)acc;
         }
     }
+    __syncthreads();  // the block's energies are in memory
+    const DevView &df = views[b.fv[kp]];
+    for (int64_t t = threadIdx.x; t < (int64_t)TX * TY; t += blockDim.x)
+        fallback_flag_tile(dv, df, b.r_mid[kp], t, energy, ntiles, threshold, coef, power, flags, active, n_flagged);
 }
 
 // Persistent blocks of the mass maps: one per compute unit of the MI355X per
@@ -156,7 +193,8 @@ int drop_energy_parts() { return 256; }
 
 void launch_drop_energy(const DevView *views, const FbBatch &b, int64_t n, const uint32_t *counts,
                         const uint8_t *keep, const uint64_t *rect, const double *score, double *diff,
-                        double *partials, int64_t ntiles, float *energy, hipStream_t s) {
+                        double *partials, int64_t ntiles, float *energy, double threshold, double coef, double power,
+                        uint8_t *flags, uint8_t *active, uint32_t *n_flagged, hipStream_t s) {
     if (b.count == 0) return;
     const size_t lds = sizeof(double) * (size_t)b.max_cells;
     const bool fits = lds <= (size_t)kFbLdsBytes;
@@ -170,50 +208,8 @@ void launch_drop_energy(const DevView *views, const FbBatch &b, int64_t n, const
         hipLaunchKernelGGL(k_drop_energy, dim3((unsigned)((n + 255) / 256), b.count), dim3(256), 0, s, views, b, n,
                            counts, keep, rect, score, diff);
     }
-    hipLaunchKernelGGL(k_drop_prefix, dim3(b.count), dim3(1024), fits ? lds : 0, s, views, b, diff, ntiles, energy);
-}
-
-// One thread per periphery tile of pair blockIdx.y: flag, and activate the
-// covered tiles of the full-resolution layer fv (s = full-resolution pixels
-// per periphery pixel).  A tile can only matter if one of the
-// full-resolution pixel centres it covers lies outside r_mid (the
-// composite's periphery region).
-__global__ void k_fallback_flags(const DevView *__restrict__ views, FbBatch b, const float *__restrict__ energy,
-                                 int64_t ntiles, double threshold, double coef, double power,
-                                 uint8_t *__restrict__ flags, uint8_t *__restrict__ active,
-                                 uint32_t *__restrict__ n_flagged) {
-    const int k = blockIdx.y;
-    const DevView &dp = views[b.pv[k]], &df = views[b.fv[k]];
-    const double r_mid = b.r_mid[k];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)dp.tiles_x * dp.tiles_y) return;
-    const int tx = (int)(t % dp.tiles_x), ty = (int)(t / dp.tiles_x);
-    const int s = (int)llround(df.v.fx / dp.v.fx);
-    const int span = kTile * s;  // full-resolution pixels per periphery tile, per axis
-    const double x0 = (double)tx * span + 0.5, x1 = fmin((double)(tx + 1) * span, (double)df.v.width) - 0.5;
-    const double y0 = (double)ty * span + 0.5, y1 = fmin((double)(ty + 1) * span, (double)df.v.height) - 0.5;
-    const double gx = df.v.gx, gy = df.v.gy;
-    const double fx = fmax(fabs(x0 - gx), fabs(x1 - gx)), fy = fmax(fabs(y0 - gy), fabs(y1 - gy));
-    const bool outer = x0 <= x1 && y0 <= y1 && fx * fx + fy * fy > r_mid * r_mid;
-    // Beer-Lambert: transmittance ~ exp(-mass per pixel); dropping raises it by dT
-    const double D = energy[dp.tile_off + t], K = energy[ntiles + dp.tile_off + t];
-    const double dT = exp(-K) - exp(-(K + D));
-    const double est = dT > 0.0 ? coef * pow(dT * dT, power) : 0.0;
-    const bool flag = outer && est >= threshold;
-    flags[dp.tile_off + t] = flag ? 1 : 0;
-    if (!flag) return;
-    atomicAdd(n_flagged, 1u);
-    for (int yy = ty * s; yy < (ty + 1) * s && yy < df.tiles_y; ++yy)
-        for (int xx = tx * s; xx < (tx + 1) * s && xx < df.tiles_x; ++xx)
-            active[df.tile_off + (int64_t)yy * df.tiles_x + xx] = 1;
-}
-
-void launch_fallback_flags(const DevView *views, const FbBatch &b, int64_t max_periph_tiles, const float *energy,
-                           int64_t ntiles, double threshold, double coef, double power, uint8_t *flags,
-                           uint8_t *active, uint32_t *n_flagged, hipStream_t s) {
-    if (b.count == 0 || max_periph_tiles == 0) return;
-    hipLaunchKernelGGL(k_fallback_flags, dim3((unsigned)((max_periph_tiles + 255) / 256), b.count), dim3(256), 0, s,
-                       views, b, energy, ntiles, threshold, coef, power, flags, active, n_flagged);
+    hipLaunchKernelGGL(k_drop_prefix, dim3(b.count), dim3(1024), fits ? lds : 0, s, views, b, diff, ntiles, energy,
+                       threshold, coef, power, flags, active, n_flagged);
 }
 
 // Row prefix and active-column list of the remasked views' rows from their

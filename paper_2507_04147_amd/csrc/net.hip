@@ -53,8 +53,7 @@ __host__ __device__ int net_chw_stride(int w) { return ((w + 31) / 32) * 32 + 16
 // weight packing: float32 master -> bf16 forward [9][co][cinpad] and
 // input-gradient [9][ci][co] (taps rotated by 180 degrees) layouts
 // ---------------------------------------------------------------------------
-__global__ void k_net_pack(const float *__restrict__ theta, NetPacked pk) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void net_pack_item(const float *__restrict__ theta, const NetPacked &pk, int t) {
     // layer 1: W1 [32][3][3][3] -> f1 [9][32][8]
     if (t < 9 * 32 * 8) {
         const int c = t % 8, co = (t / 8) % 32, tap = t / 256;
@@ -82,9 +81,8 @@ __global__ void k_net_pack(const float *__restrict__ theta, NetPacked pk) {
 
 // FP32 planar [B][3][h][w] -> bf16 NHWC8 (channels 3..7 zero) and, if chw is
 // not NULL, the zero-bordered channel-major copy [B][8][h+2][WS].
-__global__ void k_net_input(const float *__restrict__ x, int64_t x_bstride, int B, int h, int w,
-                            uint16_t *__restrict__ nhwc, uint16_t *__restrict__ chw) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void net_input_item(const float *__restrict__ x, int64_t x_bstride, int B, int h, int w,
+                                               uint16_t *__restrict__ nhwc, uint16_t *__restrict__ chw, int64_t p) {
     const int64_t HW = (int64_t)h * w;
     if (p >= (int64_t)B * HW) return;
     const int64_t b = p / HW, q = p - b * HW;
@@ -103,6 +101,18 @@ __global__ void k_net_input(const float *__restrict__ x, int64_t x_bstride, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c) chw[((b * 8 + c) * (int64_t)(h + 2) + y + 1) * WS + 8 + xx] = v[c];
     }
+}
+
+// Both preparations of a forward in one launch (they are independent): the
+// first pack_blocks blocks pack the weights, the others convert the input.
+constexpr int kNetPackBlocks = (9 * 48 * 32 + 255) / 256;
+__global__ void __launch_bounds__(256) k_net_prep(const float *__restrict__ theta, NetPacked pk,
+                                                  const float *__restrict__ x, int64_t x_bstride, int B, int h, int w,
+                                                  uint16_t *__restrict__ nhwc, uint16_t *__restrict__ chw) {
+    if ((int)blockIdx.x < kNetPackBlocks)
+        net_pack_item(theta, pk, blockIdx.x * 256 + threadIdx.x);
+    else
+        net_input_item(x, x_bstride, B, h, w, nhwc, chw, (int64_t)(blockIdx.x - kNetPackBlocks) * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -510,17 +520,12 @@ __global__ void k_net_adam(float *__restrict__ theta, const float *__restrict__ 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_net_pack(const float *theta, const NetPacked &pk, hipStream_t s) {
-    hipLaunchKernelGGL(k_net_pack, dim3((9 * 48 * 32 + 255) / 256), dim3(256), 0, s, theta, pk);
-}
-
-void launch_net_input(const float *x, int64_t x_bstride, int B, int h, int w, uint16_t *nhwc, uint16_t *chw,
-                      hipStream_t s) {
+void launch_net_prep(const float *theta, const NetPacked &pk, const float *x, int64_t x_bstride, int B, int h, int w,
+                     uint16_t *nhwc, uint16_t *chw, hipStream_t s) {
     const int64_t n = (int64_t)B * h * w;
-    if (n == 0) return;
     if (x_bstride == 0) x_bstride = 3 * (int64_t)h * w;
-    hipLaunchKernelGGL(k_net_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, x_bstride, B, h, w, nhwc,
-                       chw);
+    hipLaunchKernelGGL(k_net_prep, dim3((unsigned)(kNetPackBlocks + (n + 255) / 256)), dim3(256), 0, s, theta, pk, x,
+                       x_bstride, B, h, w, nhwc, chw);
 }
 
 void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a_in, hipStream_t s) {
