@@ -131,6 +131,7 @@ void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint3
 int64_t emit_chunks(int64_t K);
 void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
                  const uint32_t *offsets, const uint64_t *rect,
+                 uint64_t *rect_s /* [m] scratch: the rectangles in depth order */,
                  const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev /* nullable: device key count (clamped to K) */, hipStream_t s);

@@ -52,7 +52,7 @@ struct a3fr_ctx {
     a3fr_scene colour_scene{};
     // device workspace
     DevBuf views, row_view, row_y, row_prefix, row_list, active;
-    DevBuf counts, depth, rect, rec, score, keep, sel_views, sel;
+    DevBuf counts, depth, rect, rect_s, rec, score, keep, sel_views, sel;
     DevBuf offsets, block_sums, scalars;
     DevBuf ent_a, ent_b, dkey_a, dkey_b;       // visible entries, depth sort
     DevBuf keys_a, keys_b, vals_a, vals_b;
@@ -311,7 +311,7 @@ void a3fr_destroy(a3fr_ctx *c) {
     graph_release(c);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
-                      &c->counts, &c->depth, &c->rect, &c->rec, &c->score, &c->keep, &c->sel_views,
+                      &c->counts, &c->depth, &c->rect, &c->rect_s, &c->rec, &c->score, &c->keep, &c->sel_views,
                       &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
@@ -496,6 +496,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     TRY(ensure(c, c->counts, sizeof(uint32_t) * m));
     TRY(ensure(c, c->depth, sizeof(uint32_t) * m));
     TRY(ensure(c, c->rect, sizeof(uint64_t) * m));
+    TRY(ensure(c, c->rect_s, sizeof(uint64_t) * m));
     TRY(ensure(c, c->rec, sizeof(Record) * m));
     TRY(ensure(c, c->score, c->nsel ? sizeof(double) * m : 16));
     TRY(ensure(c, c->keep, c->nsel ? (size_t)m : 16));
@@ -725,7 +726,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     {
         StageTimer t_(c, A3FR_STAGE_EMIT);
         launch_emit(dv, c->nv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
-                    P<uint64_t>(c->rect), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
+                    P<uint64_t>(c->rect), P<uint64_t>(c->rect_s), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
                     P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
                     cap_mode ? sc_n_keys(c->scalars) : nullptr, c->stream);
     }

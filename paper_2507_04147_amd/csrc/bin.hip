@@ -647,10 +647,16 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 constexpr int kEmitChunk = 1024;
 constexpr int kEmitBlock = 512;
 
+// Thread per entry j (depth order): the chunks whose first key lies in its
+// key range start at j; and its rectangle is copied to rect_s[j], so the
+// emission reads it next to the offsets instead of through the entry index.
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
+                                                      const uint32_t *__restrict__ ent,
+                                                      const uint64_t *__restrict__ rect, uint64_t *__restrict__ rect_s,
                                                       uint32_t *__restrict__ chunk_start, int64_t nchunks) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent) return;
+    rect_s[j] = rect[ent[j]];
     const uint64_t lo = offsets[j], hi = offsets[j + 1];
     for (uint64_t c = (lo + kEmitChunk - 1) / kEmitChunk; c * kEmitChunk < hi && (int64_t)c < nchunks; ++c)
         chunk_start[c] = (uint32_t)j;
@@ -685,7 +691,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
                                                      const uint32_t *__restrict__ ent, const uint32_t *n_ent,
                                                      const uint32_t *__restrict__ offsets,
                                                      const uint32_t *__restrict__ chunk_start,
-                                                     const uint64_t *__restrict__ rect,
+                                                     const uint64_t *__restrict__ rect_s,
                                                      const uint16_t *__restrict__ row_prefix,
                                                      const uint16_t *__restrict__ row_list,
                                                      const uint32_t *__restrict__ cum, uint32_t *__restrict__ keys,
@@ -721,7 +727,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     for (int t = tid; t < kEmitChunk; t += kEmitBlock) {
         if ((int64_t)s_off[t] < qend) {
             const uint32_t e = ent[j0 + t];
-            s_rect[t] = rect[e];
+            s_rect[t] = rect_s[j0 + t];
             const uint32_t v = e / nn;
             s_v[t] = v;
             s_i[t] = e - v * nn;
@@ -887,15 +893,16 @@ void launch_zero_segs(const FillSegs &f, hipStream_t s) {
 int64_t emit_chunks(int64_t K) { return (K + kEmitChunk - 1) / kEmitChunk; }
 
 void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
-                 const uint32_t *offsets, const uint64_t *rect, const uint16_t *row_prefix, const uint16_t *row_list,
+                 const uint32_t *offsets, const uint64_t *rect, uint64_t *rect_s, const uint16_t *row_prefix,
+                 const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev, hipStream_t s) {
     if (m == 0 || K == 0) return;
     const int64_t nchunks = emit_chunks(K);
-    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, chunk_start,
-                       nchunks);
+    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, ent, rect,
+                       rect_s, chunk_start, nchunks);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, nv, n, ent, n_ent, offsets,
-                       chunk_start, rect, row_prefix, row_list, cum, keys, vals, K, K_dev);
+                       chunk_start, rect_s, row_prefix, row_list, cum, keys, vals, K, K_dev);
 }
 
 // capacity mode: the sort count is min(key total, capacity); overflow raises bit 1 of the error word
