@@ -47,6 +47,10 @@ struct DevView {
                           //    incremental rounds); invisible (view, Gaussian) slots then get an
                           //    empty rectangle
     int32_t round_flags;  // incremental rounds: kRoundExclDone, kRoundFrozen
+    // tile columns [ax0, ax1] x rows [ay0, ay1] hold every tile the view's mask
+    // can activate (a margin of one tile; the whole grid for MASK_ALL; empty
+    // when ax0 > ax1)
+    int32_t ax0, ax1, ay0, ay1;
 };
 // tiles already rendered by an earlier round (the done flags) are left out, and the new ones marked done
 constexpr int32_t kRoundExclDone = 1;

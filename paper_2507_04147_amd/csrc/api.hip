@@ -451,6 +451,21 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         d.limx = (1.3 * (0.5 * (double)views[k].width)) / views[k].fx;
         d.limy = (1.3 * (0.5 * (double)views[k].height)) / views[k].fy;
         d.tiles_y = (views[k].height + kTile - 1) / kTile;
+        d.ax0 = 0; d.ax1 = d.tiles_x - 1; d.ay0 = 0; d.ay1 = d.tiles_y - 1;
+        if (views[k].mask != A3FR_MASK_ALL) {
+            // an active tile's pixel-centre rectangle comes within r_out of the gaze
+            const double r = views[k].r_out, gx = views[k].gx, gy = views[k].gy, t = (double)kTile;
+            if (!(r >= 0.0)) {
+                d.ax0 = 1; d.ax1 = 0;
+            } else {
+                // clamped in float64 to [-1, tiles] before the conversion
+                const auto cl = [](double v, int hi) { return (int32_t)std::min(std::max(v, -1.0), (double)hi); };
+                d.ax0 = std::max(0, cl(std::floor((gx - r - (t - 0.5)) / t) - 1.0, d.tiles_x));
+                d.ax1 = std::min(d.tiles_x - 1, cl(std::floor((gx + r - 0.5) / t) + 1.0, d.tiles_x));
+                d.ay0 = std::max(0, cl(std::floor((gy - r - (t - 0.5)) / t) - 1.0, d.tiles_y));
+                d.ay1 = std::min(d.tiles_y - 1, cl(std::floor((gy + r - 0.5) / t) + 1.0, d.tiles_y));
+            }
+        }
         d.tile_off = toff;
         d.img_off = ioff;
         d.mask_off = views[k].mask == A3FR_MASK_ALL ? -1 : moff;

@@ -224,11 +224,15 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                         if (v.mask == A3FR_MASK_ALL) {
                             cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
                         } else {
+                            // only the part of the rectangle that can hold active tiles
+                            const int cx0 = max(x0, dv.ax0), cx1 = min(x1, dv.ax1);
+                            const int cy0 = max(y0, dv.ay0), cy1 = min(y1, dv.ay1);
                             const uint16_t *pre = row_prefix + dv.mask_off;
-                            for (int ty = y0; ty <= y1; ++ty) {
-                                const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
-                                cnt += (uint32_t)(rp[x1 + 1] - rp[x0]);
-                            }
+                            if (cx0 <= cx1)
+                                for (int ty = cy0; ty <= cy1; ++ty) {
+                                    const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+                                    cnt += (uint32_t)(rp[cx1 + 1] - rp[cx0]);
+                                }
                         }
                     }
                     // Only entries that emit keys are read downstream, except in a
