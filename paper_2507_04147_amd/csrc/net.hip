@@ -265,7 +265,7 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KIN, int NOUT, int EPI>
+template <int KIN, int NOUT, int EPI, bool PERSIST>
 __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     constexpr int KS = KIN + 8;                       // padded LDS row (bank spread, 16-byte aligned)
     constexpr int KTOT = 9 * KIN;
@@ -284,67 +284,79 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int h = a.h, w = a.w;
-    const int b = blockIdx.z;
-    const int xs = blockIdx.x * 64 + wave * 16;  // this wave's 16 pixels
-    if (xs >= w) return;
-    const int y0 = blockIdx.y * a.rows;
-    const uint16_t *in = a.in + (int64_t)b * h * w * KIN;
     const int WS = net_chw_stride(w);
     // frame mode: halo of this layer's outputs in the last layer's pixels
     constexpr int HALO = NOUT == 48 ? 0 : (KIN == 8 ? 2 : 1);
-    double gx = 0.0, gy = 0.0;
-    if (a.gv) {
-        gx = a.gv[(int64_t)b * a.gv_stride].v.gx;
-        gy = a.gv[(int64_t)b * a.gv_stride].v.gy;
-    }
-    // two image rows per pass: each weight fragment read from LDS feeds two
-    // matrix-core instructions (one per row)
-    for (int y = y0; y < y0 + a.rows && y < h; y += 2) {
-        const bool has1 = y + 1 < y0 + a.rows && y + 1 < h;
-        const bool skip0 = a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1), max(y - HALO, 0),
-                                              min(y + HALO, h - 1), gx, gy, a.rm);
-        const bool skip1 = !has1 || (a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1),
-                                                        max(y + 1 - HALO, 0), min(y + 1 + HALO, h - 1), gx, gy, a.rm));
-        if (skip0 && skip1) continue;  // wave-uniform
-        floatx4 acc[2][NB];
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[r][nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k0 = 32 * s + 8 * g;
-            uint4 av0 = {0u, 0u, 0u, 0u}, av1 = {0u, 0u, 0u, 0u};
-            int tap = 0, c0 = 0;
-            const bool kval = k0 < KTOT;
-            if (kval) {
-                tap = k0 / KIN;
-                c0 = k0 - tap * KIN;
-                const int py = y + tap / 3 - 1, px = xs + li + tap % 3 - 1;
-                if (px >= 0 && px < w) {
-                    if (py >= 0 && py < h)
-                        av0 = *reinterpret_cast<const uint4 *>(in + ((int64_t)py * w + px) * KIN + c0);
-                    if (has1 && py + 1 >= 0 && py + 1 < h)
-                        av1 = *reinterpret_cast<const uint4 *>(in + ((int64_t)(py + 1) * w + px) * KIN + c0);
+    // tiles of 64 pixels x a.rows rows: one per block (grid x, y, batch), or,
+    // PERSIST, resident blocks taking them in a grid-stride loop, so that the
+    // weights are staged once per block for several tiles
+    const int nbx = (w + 63) / 64, nby = (h + a.rows - 1) / a.rows;
+    const int64_t ntile = PERSIST ? (int64_t)nbx * nby * a.B : 1;
+    for (int64_t tile = PERSIST ? (int64_t)blockIdx.x : 0; tile < ntile; tile += PERSIST ? gridDim.x : 1) {
+        int bx = blockIdx.x, y0 = blockIdx.y * a.rows, b = blockIdx.z;
+        if (PERSIST) {
+            bx = (int)(tile % nbx);
+            const int64_t rest = tile / nbx;
+            y0 = (int)(rest % nby) * a.rows;
+            b = (int)(rest / nby);
+        }
+        const int xs = bx * 64 + wave * 16;  // this wave's 16 pixels
+        if (xs >= w) continue;
+        const uint16_t *in = a.in + (int64_t)b * h * w * KIN;
+        double gx = 0.0, gy = 0.0;
+        if (a.gv) {
+            gx = a.gv[(int64_t)b * a.gv_stride].v.gx;
+            gy = a.gv[(int64_t)b * a.gv_stride].v.gy;
+        }
+        // two image rows per pass: each weight fragment read from LDS feeds two
+        // matrix-core instructions (one per row)
+        for (int y = y0; y < y0 + a.rows && y < h; y += 2) {
+            const bool has1 = y + 1 < y0 + a.rows && y + 1 < h;
+            const bool skip0 = a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1), max(y - HALO, 0),
+                                                  min(y + HALO, h - 1), gx, gy, a.rm);
+            const bool skip1 = !has1 || (a.gv && inside_mid(max(xs - HALO, 0), min(xs + 15 + HALO, w - 1),
+                                                            max(y + 1 - HALO, 0), min(y + 1 + HALO, h - 1), gx, gy, a.rm));
+            if (skip0 && skip1) continue;  // wave-uniform
+            floatx4 acc[2][NB];
+    #pragma unroll
+            for (int r = 0; r < 2; ++r)
+    #pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[r][nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                const int k0 = 32 * s + 8 * g;
+                uint4 av0 = {0u, 0u, 0u, 0u}, av1 = {0u, 0u, 0u, 0u};
+                int tap = 0, c0 = 0;
+                const bool kval = k0 < KTOT;
+                if (kval) {
+                    tap = k0 / KIN;
+                    c0 = k0 - tap * KIN;
+                    const int py = y + tap / 3 - 1, px = xs + li + tap % 3 - 1;
+                    if (px >= 0 && px < w) {
+                        if (py >= 0 && py < h)
+                            av0 = *reinterpret_cast<const uint4 *>(in + ((int64_t)py * w + px) * KIN + c0);
+                        if (has1 && py + 1 >= 0 && py + 1 < h)
+                            av1 = *reinterpret_cast<const uint4 *>(in + ((int64_t)(py + 1) * w + px) * KIN + c0);
+                    }
+                }
+                const bf16x8 A0 = as_bf16x8(av0), A1 = as_bf16x8(av1);
+    #pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    uint4 bv = {0u, 0u, 0u, 0u};
+                    if (kval) bv = *reinterpret_cast<const uint4 *>(&wl[(tap * NOUT + nb * 16 + li) * KS + c0]);
+                    acc[0][nb] = mfma16(A0, as_bf16x8(bv), acc[0][nb]);
+                    if (has1) acc[1][nb] = mfma16(A1, as_bf16x8(bv), acc[1][nb]);  // wave-uniform
                 }
             }
-            const bf16x8 A0 = as_bf16x8(av0), A1 = as_bf16x8(av1);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                uint4 bv = {0u, 0u, 0u, 0u};
-                if (kval) bv = *reinterpret_cast<const uint4 *>(&wl[(tap * NOUT + nb * 16 + li) * KS + c0]);
-                acc[0][nb] = mfma16(A0, as_bf16x8(bv), acc[0][nb]);
-                if (has1) acc[1][nb] = mfma16(A1, as_bf16x8(bv), acc[1][nb]);  // wave-uniform
+    #pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                if (rr == 1 && !has1) break;
+                if (EPI == kEpiShuffle)
+                    shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy);
+                else
+                    conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], stage + wave * 16 * kStageStride<NOUT>, b, y + rr, xs, li, g,
+                                                  lane, WS);
             }
-        }
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            if (rr == 1 && !has1) break;
-            if (EPI == kEpiShuffle)
-                shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy);
-            else
-                conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], stage + wave * 16 * kStageStride<NOUT>, b, y + rr, xs, li, g,
-                                              lane, WS);
         }
     }
 }
@@ -528,6 +540,9 @@ void launch_net_prep(const float *theta, const NetPacked &pk, const float *x, in
                        x_bstride, B, h, w, nhwc, chw);
 }
 
+// persistent blocks of the last layer's forward: three per compute unit of the MI355X
+constexpr int64_t kNetConvBlocks = 3 * 256;
+
 void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a_in, hipStream_t s) {
     NetConvArgs a = a_in;
     if (a.rows <= 0) a.rows = kRowsPerBlock;
@@ -535,13 +550,18 @@ void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a_in, hipStream_t
     if (a.out_bstride == 0) a.out_bstride = 3 * (int64_t)(4 * a.h) * (4 * a.w);
     const dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)((a.h + a.rows - 1) / a.rows), (unsigned)a.B);
     if (!dgrad) {
-        if (layer == 1) hipLaunchKernelGGL((k_net_conv<8, 32, kEpiRelu>), grid, dim3(256), 0, s, a);
-        else if (layer == 2) hipLaunchKernelGGL((k_net_conv<32, 32, kEpiRelu>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_net_conv<32, 48, kEpiShuffle>), grid, dim3(256), 0, s, a);
+        if (layer == 1) hipLaunchKernelGGL((k_net_conv<8, 32, kEpiRelu, false>), grid, dim3(256), 0, s, a);
+        else if (layer == 2) hipLaunchKernelGGL((k_net_conv<32, 32, kEpiRelu, false>), grid, dim3(256), 0, s, a);
+        else {
+            // the last layer (the largest weights) keeps its blocks resident
+            const int64_t ntile = (int64_t)grid.x * grid.y * grid.z;
+            hipLaunchKernelGGL((k_net_conv<32, 48, kEpiShuffle, true>),
+                               dim3((unsigned)std::min<int64_t>(ntile, kNetConvBlocks)), dim3(256), 0, s, a);
+        }
     } else {
         // input gradient of layer 3 (g3: 48 channels -> 32) and of layer 2 (32 -> 32)
-        if (layer == 3) hipLaunchKernelGGL((k_net_conv<48, 32, kEpiMask>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_net_conv<32, 32, kEpiMask>), grid, dim3(256), 0, s, a);
+        if (layer == 3) hipLaunchKernelGGL((k_net_conv<48, 32, kEpiMask, false>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_net_conv<32, 32, kEpiMask, false>), grid, dim3(256), 0, s, a);
     }
 }
 
