@@ -532,7 +532,10 @@ typedef enum {
     A3FR_BUF_NET_G1 = 18,     /* bf16(dL/d conv1 output), [B][32][h+2][roundup(w,32)+16], data at row 1 and column 8 */
     /* full-resolution fallback, after an a3fr_render_foveated with a3fr_set_fallback */
     A3FR_BUF_FB_ENERGY = 19,  /* float32 [2][n_tiles]: dropped, kept opacity mass per pixel (periphery views' tiles) */
-    A3FR_BUF_FB_FLAGS = 20    /* uint8 [n_tiles]: 1 = periphery tile taken from the full-resolution layer */
+    A3FR_BUF_FB_FLAGS = 20,   /* uint8 [n_tiles]: 1 = periphery tile taken from the full-resolution layer */
+    A3FR_BUF_SEL_STATE = 21   /* uint32 [n_selecting_views][8]: periphery select of each selecting view:
+                                 visible count, kept count k, rank left in the chosen bucket, mode (0 select,
+                                 1 keep all, 2 keep none), level-1 and level-2 buckets, candidates, 0 */
 } a3fr_buffer;
 
 /* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);

@@ -188,8 +188,32 @@ typedef struct {
     uint32_t depth_bits;
 } or_proj;
 
-static void or_project_one(const float *mean, const float *scale, const float *quat, int64_t n, int64_t i,
-                           const or_view *v, int32_t tw, int32_t th, or_proj *o) {
+/* Footprint bound of a Gaussian of opacity o (Sec. 2.3: the tiles its ellipse
+ * covers; a pixel takes it only where alpha = o exp(-q/2) >= 1/255, i.e.
+ * q <= 2 ln(255 o)): Q(o) = the smallest k/8, k = 1..88, with
+ * exp(k/16) >= (1.001 x 255) o, else 11.1 (>= 2 ln 255).  So
+ * Q(o) >= 2 ln(255 o) + 2 ln 1.001, a margin far above the float32 rounding
+ * of the blend's alpha, and the box of {d' S^-1 d <= Q(o)} holds every pixel
+ * the Gaussian can reach.  Steps of 1/8 make Q(o) comparisons against exp at
+ * fixed points, so no last bit of a logarithm moves a tile boundary. */
+static double or_exp_tab[89];
+static pthread_once_t or_exp_once = PTHREAD_ONCE_INIT;
+static void or_exp_init(void) {
+    for (int k = 0; k <= 88; ++k) or_exp_tab[k] = exp((double)k / 16.0);
+}
+static double or_extent_q(double o) {
+    pthread_once(&or_exp_once, or_exp_init);
+    const double t = (1.001 * 255.0) * o;
+    for (int k = 1; k <= 88; ++k)
+        if (or_exp_tab[k] >= t) return (double)k / 8.0;
+    return OR_EXTENT_Q;
+}
+
+/* Exported for the pins: the footprint bound Q(o). */
+double or_footprint_q(double o) { return or_extent_q(o); }
+
+static void or_project_one(const float *mean, const float *scale, const float *quat, const float *opac, int64_t n,
+                           int64_t i, const or_view *v, int32_t tw, int32_t th, or_proj *o) {
     memset(o, 0, sizeof(*o));
     double p[3], Sv[6];
     if (!or_view_space(mean, scale, quat, n, i, v, p, Sv)) return;
@@ -217,7 +241,8 @@ static void or_project_one(const float *mean, const float *scale, const float *q
     float dz = (float)p[2];
     memcpy(&o->depth_bits, &dz, 4);
 
-    double ex = sqrt(OR_EXTENT_Q * a), ey = sqrt(OR_EXTENT_Q * c);
+    const double q = or_extent_q((double)opac[i]);
+    double ex = sqrt(q * a), ey = sqrt(q * c);
     double lox = o->u - ex, hix = o->u + ex, loy = o->v - ey, hiy = o->v + ey;
     if (!(hix >= 0.5 && lox <= (double)v->width - 0.5 && hiy >= 0.5 && loy <= (double)v->height - 0.5)) return;
     int32_t TX = or_tiles_x(v, tw), TY = or_tiles_y(v, th);
@@ -248,7 +273,7 @@ static void or_project_body(void *vctx, int64_t item) {
     int64_t i = item % n;
     const or_view *vw = &C->views[v];
     or_proj o;
-    or_project_one(C->mean, C->scale, C->quat, n, i, vw, C->tw, C->th, &o);
+    or_project_one(C->mean, C->scale, C->quat, C->opac, n, i, vw, C->tw, C->th, &o);
     int64_t k = (int64_t)v * n + i;
     C->proj[k] = (uint8_t)o.ok;
     C->vis[k] = (uint8_t)o.vis;

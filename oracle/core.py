@@ -62,6 +62,8 @@ def lib():
         L.or_sh_basis.argtypes = [D, D, D, P]
         L.or_view_cov.argtypes = [P, P, P, I64, I64, P, P, P]
         L.or_view_cov.restype = C.c_int
+        L.or_footprint_q.argtypes = [D]
+        L.or_footprint_q.restype = D
         L.or_colour.argtypes = [I64, P, P, I32, I32, P, P]
         L.or_select.argtypes = [I64, P, P, I32, I32, P]
         L.or_select.restype = I64
@@ -86,6 +88,12 @@ def lib():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def footprint_q(opacity):
+    """Q(o) of the footprint box {d' Sigma2D^-1 d <= Q(o)} (Sec. 2.3): the
+    smallest k/8 (k = 1..88) with exp(k/16) >= 1.001 x 255 o, else 11.1."""
+    return float(lib().or_footprint_q(float(opacity)))
 
 
 def default_threads() -> int:

@@ -25,7 +25,7 @@ TILE = 16
 
 BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
            active=9, keep=10, records=11, depth_order=12, net_x0=13, net_a1=14, net_a2=15, net_g3=16, net_g2=17,
-           net_g1=18, fb_energy=19, fb_flags=20)
+           net_g1=18, fb_energy=19, fb_flags=20, sel_state=21)
 NET_PARAMS = 24016
 BLEND_VARIANTS = 15
 

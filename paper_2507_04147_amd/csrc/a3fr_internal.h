@@ -14,6 +14,10 @@ constexpr int kWave = 64;                 // CDNA wavefront
 constexpr double kZNear = 0.2;
 constexpr double kDilate = 0.3;           // low-pass dilation of the 2D covariance, px^2
 constexpr double kExtentQ = 11.1;         // footprint box of {d' S^-1 d <= Q}; Q >= 2 ln 255
+// The footprint of a Gaussian of opacity o is the box of {d' S^-1 d <= Q(o)}:
+// Q(o) = the smallest k/8, k = 1..kExtentSteps, with exp(k/16) >= (1.001 x 255) o,
+// else kExtentQ.  The projection takes exp(k/16), k = 0..kExtentSteps, as a table.
+constexpr int kExtentSteps = 88;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
@@ -113,7 +117,7 @@ void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, in
                           Record *rec, hipStream_t s);
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       Record *rec, double *score, hipStream_t s);
+                       Record *rec, double *score, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
 void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
                          int64_t m, Record *rec, hipStream_t s);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,

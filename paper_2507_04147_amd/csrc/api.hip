@@ -103,6 +103,7 @@ struct a3fr_ctx {
     int64_t capacity = 0;                  // 0: exact mode (bin_sort reads the key count)
     bool capturing = false;                // inside a3fr_graph_capture's stream capture
     const int32_t *d_row_view = nullptr, *d_row_y = nullptr, *d_sel_views = nullptr, *d_groups = nullptr;
+    const double *d_exp_tab = nullptr;
     hipStream_t own_stream = nullptr;      // capture stream when the caller's is the null stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -528,12 +529,14 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4, kSortItemsSmall)));
 
-    // ---- one upload through pinned staging: [views | row views | row ys | selecting views]
+    // ---- one upload through pinned staging:
+    // [views | row views | row ys | selecting views | groups | exp(k/16) table of the footprint bound]
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes_v = sizeof(DevView) * nv, bytes_r = sizeof(int32_t) * c->rows_total,
-                 bytes_s = sizeof(int32_t) * (c->nsel + 1), bytes_g = sizeof(int32_t) * c->hgroups.size();
+                 bytes_s = sizeof(int32_t) * (c->nsel + 1), bytes_g = sizeof(int32_t) * c->hgroups.size(),
+                 bytes_e = sizeof(double) * (kExtentSteps + 1);
     const size_t o_rv = al(bytes_v), o_ry = o_rv + al(bytes_r), o_sv = o_ry + al(bytes_r), o_gr = o_sv + al(bytes_s),
-                 total = o_gr + al(bytes_g);
+                 o_ex = o_gr + al(bytes_g), total = o_ex + al(bytes_e);
     TRY(ensure(c, c->views, total));
     TRY(ensure_pinned(c, total));
     char *pin = static_cast<char *>(c->pinned);
@@ -542,6 +545,8 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     std::memcpy(pin + o_ry, c->hrow_y.data(), bytes_r);
     if (c->nsel) std::memcpy(pin + o_sv, c->hsel_views.data(), sizeof(int32_t) * c->nsel);
     std::memcpy(pin + o_gr, c->hgroups.data(), bytes_g);
+    double *ex_tab = reinterpret_cast<double *>(pin + o_ex);
+    for (int k = 0; k <= kExtentSteps; ++k) ex_tab[k] = std::exp((double)k / 16.0);
     HIPCHECK(c, hipMemcpyAsync(c->views.p, pin, total, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->upload_done, c->stream));
     char *frame = static_cast<char *>(c->views.p);
@@ -549,6 +554,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     c->d_row_y = reinterpret_cast<const int32_t *>(frame + o_ry);
     c->d_sel_views = reinterpret_cast<const int32_t *>(frame + o_sv);
     c->d_groups = reinterpret_cast<const int32_t *>(frame + o_gr);
+    c->d_exp_tab = reinterpret_cast<const double *>(frame + o_ex);
     return A3FR_OK;
 }
 
@@ -572,7 +578,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
-                      c->stream); }
+                      c->d_exp_tab, c->stream); }
     // the fallback pairs (periphery view, its eye's full-resolution view); their
     // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of
     // up to kFbMax per launch
@@ -1641,6 +1647,8 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
         case A3FR_BUF_FB_FLAGS:
             if (!c->fb_last) return fail(c, A3FR_ENOTREADY, "no fallback in the last frame");
             src = c->fb_flags.p; bytes = c->ntiles; break;
+        case A3FR_BUF_SEL_STATE:
+            src = P<uint32_t>(c->sel) + select_hist_words(c->nsel); bytes = 32 * (int64_t)c->nsel; break;
         default: return fail(c, A3FR_EINVAL, "unknown buffer");
     }
     if (bytes_out) *bytes_out = bytes;

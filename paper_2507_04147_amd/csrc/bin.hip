@@ -248,6 +248,8 @@ __global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, co
     }
 }
 
+constexpr uint32_t kSelDirect = 1024;  // candidates ranked by direct comparison (one block)
+
 // Candidate key (score low bits, ~index) as a 128-bit integer: larger is kept first.
 __device__ __forceinline__ unsigned __int128 sel_ckey(uint64_t lo, uint32_t idx) {
     return ((unsigned __int128)lo << 32) | (unsigned __int128)(~idx);
@@ -265,6 +267,22 @@ __global__ void __launch_bounds__(1024) k_sel_final(const int32_t *sel_views, in
     __shared__ uint32_t hist[256];
     __shared__ uint32_t s_krem, s_done, s_np;
     __shared__ unsigned long long s_pre_hi, s_pre_lo;  // chosen key prefix (digits so far), 128-bit
+    if (nc <= kSelDirect) {
+        // few candidates (the usual case): each is kept iff fewer than k_rem
+        // candidates have a larger key (keys are unique), one comparison pass in LDS
+        __shared__ uint64_t s_ck[kSelDirect];
+        __shared__ uint32_t s_ci[kSelDirect];
+        for (uint32_t c = t; c < nc; c += blockDim.x) { s_ck[c] = ck[c]; s_ci[c] = ci[c]; }
+        __syncthreads();
+        const uint32_t krem = st[slot].k_rem;
+        for (uint32_t c = t; c < nc; c += blockDim.x) {
+            const unsigned __int128 key = sel_ckey(s_ck[c], s_ci[c]);
+            uint32_t above = 0;
+            for (uint32_t d = 0; d < nc; ++d) above += sel_ckey(s_ck[d], s_ci[d]) > key ? 1u : 0u;
+            keep[base + s_ci[c]] = above < krem ? 1 : 0;
+        }
+        return;
+    }
     if (t == 0) { s_krem = st[slot].k_rem; s_done = 0; s_np = 0; s_pre_hi = 0; s_pre_lo = 0; }
     __syncthreads();
     for (int p = 0; p < kSelDigits; ++p) {

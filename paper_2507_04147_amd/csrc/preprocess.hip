@@ -171,7 +171,10 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                                                     const uint16_t *__restrict__ row_prefix,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
                                                     uint64_t *__restrict__ rect, Record *__restrict__ rec,
-                                                    double *__restrict__ score) {
+                                                    double *__restrict__ score, const double *__restrict__ exp_tab) {
+    __shared__ double s_exp[kExtentSteps + 1];
+    for (int k = threadIdx.x; k <= kExtentSteps; k += blockDim.x) s_exp[k] = exp_tab[k];
+    __syncthreads();
     const int64_t n = sc.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -188,6 +191,25 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                                      sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S);
     if (front) view_cov(Rw, S, V);
     const double xz = p0 / p2, yz = p1 / p2;
+    // footprint bound Q(o): a pixel takes the Gaussian only where
+    // o exp(-q/2) >= 1/255; the smallest step k/8 with exp(k/16) >= (1.001 x 255) o
+    // (a lower bound search over the increasing table), else kExtentQ
+    const float op = sc.opacity_dev[i];
+    double qe = kExtentQ;
+    {
+        const double t = (1.001 * 255.0) * (double)op;
+        int lo = 1, cnt_k = kExtentSteps;
+        while (cnt_k > 0) {
+            const int half = cnt_k >> 1;
+            if (s_exp[lo + half] < t) {
+                lo += half + 1;
+                cnt_k -= half + 1;
+            } else {
+                cnt_k = half;
+            }
+        }
+        if (lo <= kExtentSteps) qe = (double)lo / 8.0;
+    }
     for (int vi = v_begin; vi < v_end; ++vi) {
         const DevView &dv = views[vi];
         const a3fr_view &v = dv.v;
@@ -209,7 +231,7 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
             const double det = fma(a, c, -(b * b));
             if (det > 0.0) {
                 const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
-                const double ex = sqrt(kExtentQ * a), ey = sqrt(kExtentQ * c);
+                const double ex = sqrt(qe * a), ey = sqrt(qe * c);
                 const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
                 if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
                     double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
@@ -245,7 +267,6 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                         depth[slot] = __float_as_uint((float)p2);
                         rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
                                      ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
-                        const float op = sc.opacity_dev[i];
                         if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
                         // inverse covariance in LDL^T form, float64 then rounded once
                         const double kLog2e = 1.4426950408889634;
@@ -270,11 +291,11 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
 
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       Record *rec, double *score, hipStream_t s) {
+                       Record *rec, double *score, const double *exp_tab, hipStream_t s) {
     if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
-                       views, groups, row_prefix, counts, depth, rect, rec, score);
+                       views, groups, row_prefix, counts, depth, rect, rec, score, exp_tab);
 }
 
 // View-dependent colour (degree <= 3 real SH, float32) of Gaussian i seen

@@ -73,9 +73,12 @@ def compare_stage_outputs(ctx, ref, views, n):
     np.testing.assert_array_equal(act, ref["active"])
     if any(v.select for v in views):
         keep = ctx.inspect("keep", torch.uint8).cpu().numpy().reshape(nv, n)
-        for v, vw in enumerate(views):
-            if vw.select:
-                np.testing.assert_array_equal(keep[v], ref["keep"][v])
+        st = ctx.inspect("sel_state", torch.int32).cpu().numpy().reshape(-1, 8)
+        for slot, v in enumerate([v for v, vw in enumerate(views) if vw.select]):
+            np.testing.assert_array_equal(keep[v], ref["keep"][v])
+            # the select's visible and kept counts (mode 0: a strict subset)
+            n_vis = int(((ref["count"][v] > 0) & ref["vis"][v].astype(bool)).sum())
+            assert st[slot][0] == n_vis and st[slot][1] == int(ref["keep"][v].sum())
     # visible entries in depth order, their key offsets, and keys in emission order
     ent, offs, ekeys, evals = expected_emission(ref, views, n)
     np.testing.assert_array_equal(_u(ctx.inspect("depth_order", torch.int32), np.uint32), ent)

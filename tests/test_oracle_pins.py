@@ -292,9 +292,22 @@ def test_foveated_layers_equal_brute_force_on_active_tiles():
 # --------------------------------------------------------------------------
 # keys
 # --------------------------------------------------------------------------
+def test_footprint_bound_brackets_the_alpha_threshold():
+    """Q(o) is a step of 1/8 above 2 ln(1.001 x 255 o) -- every q with
+    o exp(-q/2) >= 1/255 (with the margin) is inside -- and at most 11.1,
+    the bound for opacity 1 (2 ln 255 < 11.1)."""
+    rng = np.random.default_rng(5)
+    for o in np.concatenate([rng.uniform(0.0, 1.0, 2000), [1e-6, 1.0 / 255.0, 0.5, 0.97, 0.99, 1.0]]):
+        q = oracle.footprint_q(o)
+        lo = 2.0 * math.log(max(1.001 * 255.0 * o, 1e-300))
+        assert q <= 11.1 and q >= lo - 1e-12
+        assert q == 11.1 or (q * 8.0 == round(q * 8.0) and (q - 0.125 < lo or q == 0.125))
+    assert oracle.footprint_q(1.0) == 11.1 and oracle.footprint_q(0.0) == 0.125
+
+
 def test_tile_rectangles_equal_brute_force_overlap():
     """Tile range of each Gaussian = the tiles holding a pixel centre inside the
-    box [u - e_x, u + e_x] x [v - e_y, v + e_y], e = sqrt(11.1 diag(Sigma2D));
+    box [u - e_x, u + e_x] x [v - e_y, v + e_y], e = sqrt(Q(o) diag(Sigma2D));
     every pixel centre outside the box has alpha < 1/255."""
     sc = synth.make_scene(400, 1.0, 31, log_scale_mean=-2.6)
     cam = synth.make_camera(88, 56, 60, (0, 0, -3))
@@ -309,7 +322,8 @@ def test_tile_rectangles_equal_brute_force_overlap():
                 continue
             u, vv = r["mu"][0, i]
             a, b, c = r["cov"][0, i]
-            ex, ey = math.sqrt(11.1 * a), math.sqrt(11.1 * c)
+            q_o = oracle.footprint_q(float(sc.opacity[i]))
+            ex, ey = math.sqrt(q_o * a), math.sqrt(q_o * c)
             inx = (xs >= u - ex) & (xs <= u + ex)
             iny = (ys >= vv - ey) & (ys <= vv + ey)
             want = set()
