@@ -49,22 +49,24 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="fcc0913ac5d68e27bdcfe01ff7a168e5196611ef80547738eee99cf8e9d6f04b",
-                  kib={"32,4x1,grid": (6394.3, 21750.0), "64,4x1,grid": (7177.2, 21750.0),
-                       "128,4x1,grid": (9587.9, 21750.0), "32,2x2,grid": (6389.6, 21750.0),
-                       "64,2x2,grid": (7168.8, 21750.0), "128,2x2,grid": (9576.0, 21750.0),
-                       "32,4x1,queue": (5940.3, 21890.3), "64,4x1,queue": (6633.2, 21878.1),
-                       "128,4x1,queue": (8990.4, 21882.5), "32,2x2,queue": (5967.6, 22022.8),
-                       "64,2x2,queue": (6630.2, 21840.2), "128,2x2,queue": (8987.9, 21931.5)}),
+                  sha256="3c4261b66f34011563560c74b955a2243dac024cbfcb445e5764bdb2be270794",
+                  kib={"32,4x1,grid": (5970.9, 21750.0), "64,4x1,grid": (6989.4, 21750.0),
+                       "128,4x1,grid": (10140.6, 21750.0), "32,2x2,grid": (5974.4, 21750.0),
+                       "64,2x2,grid": (6982.0, 21750.0), "128,2x2,grid": (10127.3, 21750.0),
+                       "32,4x1,queue": (5531.7, 21838.4), "64,4x1,queue": (6480.9, 21855.2),
+                       "128,4x1,queue": (9359.9, 21939.4), "32,2x2,queue": (5490.4, 21799.4),
+                       "64,2x2,queue": (6452.5, 21733.2), "128,2x2,queue": (9415.8, 21919.2),
+                       "64,8x8q,grid": (10379.9, 21750.0), "128,8x8q,grid": (18920.4, 21750.0),
+                       "256,8x8q,grid": (35761.2, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="8dcc71bd18b51a6682afd769ab143ad5284dbd6845e5c34bf2bf72cbdbbcbf96",
-                       kib={"k_preprocess": (43593.6, 164107.4)}),
+                       sha256="4810cd024fdba27ec23b3c35b2c9b93d664dca16a54dc06d601439642d48a0f5",
+                       kib={"k_preprocess": (43142.7, 162834.8)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="8dcc71bd18b51a6682afd769ab143ad5284dbd6845e5c34bf2bf72cbdbbcbf96",
-                   kib={"k_entry_colour": (50111.0, 13817.6)}),
+                   sha256="4810cd024fdba27ec23b3c35b2c9b93d664dca16a54dc06d601439642d48a0f5",
+                   kib={"k_entry_colour": (49397.9, 13557.0)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the two tile-id passes of the key sort
-                      sha256="5bb1141157425798afc95ec2f928a1de2b00324a65083696d567abfa165802bf",
-                      kib={"k_onesweep": (45731.5, 89889.1)}),
+                      sha256="585dc28c58de76317f49e6eef01624c5f3a62fab24e6442aab95a4eaf5a09348",
+                      kib={"k_onesweep": (39740.8, 78474.3)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale and quaternion of every Gaussian (40 B) once
