@@ -142,7 +142,8 @@ void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint3
                  uint64_t *rect_s /* [m] scratch: the rectangles in depth order */,
                  const uint16_t *row_prefix, const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
-                 const uint32_t *K_dev /* nullable: device key count (clamped to K) */, hipStream_t s);
+                 const uint32_t *K_dev /* nullable: device key count (clamped to K) */,
+                 uint32_t *zero, int zero_words /* cleared by the first kernel (nullable when 0) */, hipStream_t s);
 void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s);
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
                      hipStream_t s, const uint32_t *skip_if_zero = nullptr /* device count: 0 skips */);
@@ -154,8 +155,12 @@ constexpr int kSortItemsLarge = 16;
 constexpr int kSortItemsSmall = 4;
 int sort_partitions(int64_t n, int items);
 int64_t sort_workspace_words(int64_t n_max, int npass, int items);
+// leading words of the workspace (digit counts, pass counters) that must be zero
+// before launch_sort_prepare; the histogram kernel clears the status words itself
+int64_t sort_zero_words(int npass);
 void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
-                         uint32_t *ws, hipStream_t s, bool zeroed = false /* ws already zero */);
+                         uint32_t *ws, hipStream_t s,
+                         bool zeroed = false /* the first sort_zero_words(npass) words already zero */);
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
                       int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
@@ -237,6 +242,12 @@ void launch_composite(int W, int H, double gx, double gy, double rf, double rm, 
                       const uint8_t *fb_flags /* nullable: periphery tiles taken from fovea */, int fb_tiles_x,
                       const DevView *gaze_view /* nullable: read the gaze (v.gx, v.gy) from this device view */,
                       float *out, hipStream_t s);
+// every eye of a frame, all W x H, in one launch: eye e's gaze, layers (at layers + 3 img_off) and
+// fallback flags (fb_flags + tile_off of its periphery view; nullable) from views[3e .. 3e + 2];
+// output at out + 3 W H e
+void launch_composite_eyes(int n_eyes, int W, int H, double rf, double rm, int sm, int sp, const DevView *views,
+                           const float *layers, bool periph_done, const uint8_t *fb_flags, float *out,
+                           hipStream_t s);
 void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm, const float *a,
                        const float *b, double *partial /* [nblk][3] */, unsigned long long *cnt /* [nblk][3] */,
                        int nblk, hipStream_t s);

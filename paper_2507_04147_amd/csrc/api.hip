@@ -608,7 +608,8 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     }
     {   // one launch clears what the later stages accumulate into: the select
         // histograms, the fallback's counters and planes, the scans' tickets and
-        // status words, the depth sort's histograms and status words
+        // status words, the depth sort's digit counts and pass counters (its
+        // histogram kernel clears the status words of the partitions in use)
         StageTimer t_(c, A3FR_STAGE_MASKS);
         const int64_t m = (int64_t)nv * n;
         FillSegs z{};
@@ -624,7 +625,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
             add(c->fb_diff.p, 2 * dwords);
         }
         add(c->block_sums.p, 2 * scan_workspace_words(m));
-        add(c->sort_status.p, sort_workspace_words(m, 4, kSortItemsSmall));
+        add(c->sort_status.p, sort_zero_words(4));
         launch_zero_segs(z, c->stream);
     }
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
@@ -749,7 +750,8 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
         launch_emit(dv, c->nv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
                     P<uint64_t>(c->rect), P<uint64_t>(c->rect_s), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
                     P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
-                    cap_mode ? sc_n_keys(c->scalars) : nullptr, c->stream);
+                    cap_mode ? sc_n_keys(c->scalars) : nullptr, P<uint32_t>(c->sort_status),
+                    (int)sort_zero_words(npass), c->stream);
     }
     if (c->keep_emission && !cap_mode) {
         TRY(ensure(c, c->keys_e, sizeof(uint32_t) * K));
@@ -763,8 +765,9 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (K > 1) {
         {
             StageTimer t_(c, A3FR_STAGE_SORT_HIST);
+            // the digit counts and pass counters were cleared by the emission's first kernel
             launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, kSortItemsLarge, P<uint32_t>(c->sort_status),
-                                c->stream);
+                                c->stream, true);
         }
         for (int p = 0; p < npass; ++p) {
             StageTimer t_(c, A3FR_STAGE_SORT_PASS);
@@ -1064,6 +1067,16 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
         // the network writes the periphery (outside r_mid) of every eye straight into out
         StageTimer t_(c, A3FR_STAGE_NET);
         TRY(net_frame_forward(c, cams, n_eyes, f->r_mid, L, out));
+    }
+    bool same_size = true;
+    for (int e = 1; e < n_eyes; ++e)
+        same_size = same_size && cams[e].width == cams[0].width && cams[e].height == cams[0].height;
+    if (same_size) {  // every eye in one launch
+        StageTimer t_(c, A3FR_STAGE_COMPOSITE);
+        launch_composite_eyes(n_eyes, cams[0].width, cams[0].height, f->r_fovea, f->r_mid, f->scale_mid,
+                              f->scale_periph, P<DevView>(c->views), L, net,
+                              c->fb_last ? P<uint8_t>(c->fb_flags) : nullptr, out, c->stream);
+        return check_launch(c, "composite");
     }
     int64_t o_off = 0;
     for (int e = 0; e < n_eyes; ++e) {

@@ -668,10 +668,15 @@ constexpr int kEmitBlock = 512;
 // Thread per entry j (depth order): the chunks whose first key lies in its
 // key range start at j; and its rectangle is copied to rect_s[j], so the
 // emission reads it next to the offsets instead of through the entry index.
+// Block 0 also clears zero[0, zero_words) (the key sort's digit counts and
+// pass counters).
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ ent,
                                                       const uint64_t *__restrict__ rect, uint64_t *__restrict__ rect_s,
-                                                      uint32_t *__restrict__ chunk_start, int64_t nchunks) {
+                                                      uint32_t *__restrict__ chunk_start, int64_t nchunks,
+                                                      uint32_t *__restrict__ zero, int zero_words) {
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0u;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent) return;
     rect_s[j] = rect[ent[j]];
@@ -914,11 +919,11 @@ void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint3
                  const uint32_t *offsets, const uint64_t *rect, uint64_t *rect_s, const uint16_t *row_prefix,
                  const uint16_t *row_list,
                  const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
-                 const uint32_t *K_dev, hipStream_t s) {
+                 const uint32_t *K_dev, uint32_t *zero, int zero_words, hipStream_t s) {
     if (m == 0 || K == 0) return;
     const int64_t nchunks = emit_chunks(K);
     hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, ent, rect,
-                       rect_s, chunk_start, nchunks);
+                       rect_s, chunk_start, nchunks, zero, zero_words);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, nv, n, ent, n_ent, offsets,
                        chunk_start, rect_s, row_prefix, row_list, cum, keys, vals, K, K_dev);
 }

@@ -827,19 +827,16 @@ __device__ __forceinline__ void bilinear_setup(int x, int s, int Wl, int &i0, in
     w = sx - f;
 }
 
-__global__ void k_composite(int W, int H, double gx, double gy, double rf, double rm,
-                            const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
-                            const float *__restrict__ periph, int sp, const float *__restrict__ periph_full,
-                            int periph_done,
-                            const uint8_t *__restrict__ fb_flags, int fb_tiles_x, const DevView *gaze_view,
-                            float *__restrict__ out) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gaze_view) {  // the gaze of this frame, from the device view table
-        gx = gaze_view->v.gx;
-        gy = gaze_view->v.gy;
-    }
-    const int y = blockIdx.y;
-    if (x >= W) return;
+// One output pixel (x, y): fovea inside r_f, bilinear mid layer inside r_mid,
+// then the periphery: a flagged periphery tile from the full-resolution layer,
+// else nothing when the network already wrote it, else the given
+// full-resolution periphery or the bilinear periphery layer.
+__device__ __forceinline__ void composite_px(int x, int y, int W, int H, double gx, double gy, double rf, double rm,
+                                             const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
+                                             const float *__restrict__ periph, int sp,
+                                             const float *__restrict__ periph_full, int periph_done,
+                                             const uint8_t *__restrict__ fb_flags, int fb_tiles_x,
+                                             float *__restrict__ out) {
     const int64_t HW = (int64_t)W * H, pix = (int64_t)y * W + x;
     const int reg = region_of(x, y, gx, gy, rf, rm);
     if (reg == 0) {
@@ -876,6 +873,23 @@ __global__ void k_composite(int W, int H, double gx, double gy, double rf, doubl
     }
 }
 
+__global__ void k_composite(int W, int H, double gx, double gy, double rf, double rm,
+                            const float *__restrict__ fovea, const float *__restrict__ mid, int sm,
+                            const float *__restrict__ periph, int sp, const float *__restrict__ periph_full,
+                            int periph_done,
+                            const uint8_t *__restrict__ fb_flags, int fb_tiles_x, const DevView *gaze_view,
+                            float *__restrict__ out) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gaze_view) {  // the gaze of this frame, from the device view table
+        gx = gaze_view->v.gx;
+        gy = gaze_view->v.gy;
+    }
+    const int y = blockIdx.y;
+    if (x >= W) return;
+    composite_px(x, y, W, H, gx, gy, rf, rm, fovea, mid, sm, periph, sp, periph_full, periph_done, fb_flags,
+                 fb_tiles_x, out);
+}
+
 void launch_composite(int W, int H, double gx, double gy, double rf, double rm, const float *fovea,
                       const float *mid, int sm, const float *periph, int sp, const float *periph_full, bool periph_done,
                       const uint8_t *fb_flags, int fb_tiles_x, const DevView *gaze_view, float *out, hipStream_t s) {
@@ -883,6 +897,61 @@ void launch_composite(int W, int H, double gx, double gy, double rf, double rm, 
     hipLaunchKernelGGL(k_composite, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, W, H, gx, gy,
                        rf, rm, fovea, mid, sm, periph, sp, periph_full, (int)periph_done, fb_flags, fb_tiles_x, gaze_view,
                        out);
+}
+
+// Every eye of a frame (all W x H) in one launch: blockIdx.z = eye, a block
+// covers 64 x 16 pixels (a wave per row, each thread four rows at a stride of
+// four).  Eye e's gaze, layers and fallback flags come from its views in the
+// device view table: fovea 3e, mid 3e + 1, periphery 3e + 2; its output is
+// out + 3 W H e.  When the network has written the periphery, a block whose
+// pixel centre nearest the gaze lies outside r_mid holds periphery pixels
+// only (the distances of the others are at least as large, also after
+// rounding), so it has nothing to write unless the one periphery tile that
+// holds it is flagged.
+constexpr int kCompW = 64, kCompH = 16;
+
+__global__ void __launch_bounds__(256) k_composite_eyes(int W, int H, double rf, double rm, int sm, int sp,
+                                                        const DevView *__restrict__ views,
+                                                        const float *__restrict__ layers, int periph_done,
+                                                        const uint8_t *__restrict__ fb_flags,
+                                                        float *__restrict__ out) {
+    const int e = blockIdx.z;
+    const DevView &d0 = views[3 * e], &d1 = views[3 * e + 1], &d2 = views[3 * e + 2];
+    const double gx = d0.v.gx, gy = d0.v.gy;
+    const int x0 = blockIdx.x * kCompW, y0 = blockIdx.y * kCompH;
+    const int xe = x0 + kCompW - 1 < W ? x0 + kCompW - 1 : W - 1;
+    const int ye = y0 + kCompH - 1 < H ? y0 + kCompH - 1 : H - 1;
+    const uint8_t *flags = fb_flags ? fb_flags + d2.tile_off : nullptr;
+    if (periph_done) {
+        const int xn = (int)fmin(fmax(floor(gx), (double)x0), (double)xe);
+        const int yn = (int)fmin(fmax(floor(gy), (double)y0), (double)ye);
+        if (region_of(xn, yn, gx, gy, rf, rm) == 2) {
+            if (!flags) return;
+            const int pt = kTile * sp;
+            if (x0 / pt == xe / pt && y0 / pt == ye / pt && !flags[(int64_t)(y0 / pt) * d2.tiles_x + x0 / pt]) return;
+        }
+    }
+    const int64_t HW = (int64_t)W * H;
+    const float *fov = layers + 3 * d0.img_off, *mid = layers + 3 * d1.img_off, *per = layers + 3 * d2.img_off;
+    float *o = out + (int64_t)e * 3 * HW;
+    const int x = x0 + (int)(threadIdx.x & 63);
+    if (x >= W) return;
+#pragma unroll
+    for (int k = 0; k < kCompH / 4; ++k) {
+        const int y = y0 + (int)(threadIdx.x >> 6) + 4 * k;
+        if (y < H)
+            composite_px(x, y, W, H, gx, gy, rf, rm, fov, mid, sm, per, sp, nullptr, periph_done, flags, d2.tiles_x,
+                         o);
+    }
+}
+
+void launch_composite_eyes(int n_eyes, int W, int H, double rf, double rm, int sm, int sp, const DevView *views,
+                           const float *layers, bool periph_done, const uint8_t *fb_flags, float *out,
+                           hipStream_t s) {
+    if (n_eyes <= 0 || W <= 0 || H <= 0) return;
+    hipLaunchKernelGGL(k_composite_eyes, dim3((unsigned)((W + kCompW - 1) / kCompW),
+                                              (unsigned)((H + kCompH - 1) / kCompH), (unsigned)n_eyes),
+                       dim3(256), 0, s, W, H, rf, rm, sm, sp, views, layers, (int)periph_done, fb_flags, out);
 }
 
 // ------------------------------------------------------------------------

@@ -64,12 +64,28 @@ __device__ __forceinline__ void hist_add(uint32_t (*h)[kRadix], int npass, uint3
     }
 }
 
+// The kernel also clears the look-back status words of the partitions the
+// passes will use (those of n keys, not of the n_max the workspace is sized
+// for): pass p's words start at status + p x parts_max x kRadix.
 __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
-                                                            int npass, uint32_t *__restrict__ hist) {
+                                                            int npass, uint32_t *__restrict__ hist, int items,
+                                                            int64_t parts_max) {
     __shared__ uint32_t h[kHistWaves][kMaxPasses][kRadix];
     for (int j = threadIdx.x; j < kHistWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
-    __syncthreads();
     const int64_t n = *n_dev;
+    {
+        // status = hist + npass x kRadix + 8: 16-byte aligned with the workspace, and so is each pass's part
+        uint4 *status = reinterpret_cast<uint4 *>(hist + (int64_t)npass * kRadix + 8);
+        const int64_t parts = (n + (int64_t)kSortThreads * items - 1) / ((int64_t)kSortThreads * items);
+        const int64_t per = parts * (kRadix / 4), stride = parts_max * (kRadix / 4);
+        const uint4 z = {0u, 0u, 0u, 0u};
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npass * per;
+             j += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t p = j / per;
+            status[p * stride + (j - p * per)] = z;
+        }
+    }
+    __syncthreads();
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform loop over 256-key steps (64 lanes x 4 keys)
     const int64_t nwaves = (int64_t)gridDim.x * kHistWaves;
@@ -298,17 +314,20 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
 // ws: one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256]
 // cleared by one fill, then the digit histograms of all passes.
 int64_t sort_workspace_words(int64_t n_max, int npass, int items) {
-    return (int64_t)npass * kRadix + 8 + (int64_t)npass * sort_partitions(n_max, items) * kRadix;
+    return sort_zero_words(npass) + (int64_t)npass * sort_partitions(n_max, items) * kRadix;
 }
+
+int64_t sort_zero_words(int npass) { return (int64_t)npass * kRadix + 8; }
 
 void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
                          uint32_t *ws, hipStream_t s, bool zeroed) {
     const int nparts = sort_partitions(n_max, items);
-    if (!zeroed) launch_fill_u32(ws, 0u, sort_workspace_words(n_max, npass, items), s);
+    if (!zeroed) launch_fill_u32(ws, 0u, sort_zero_words(npass), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
     if (hblocks > 512) hblocks = 512;
-    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(kHistThreads), 0, s, keys, n_dev, npass, ws);
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)hblocks), dim3(kHistThreads), 0, s, keys, n_dev, npass, ws, items,
+                       (int64_t)nparts);
 }
 
 void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
