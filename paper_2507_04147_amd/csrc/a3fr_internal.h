@@ -166,6 +166,13 @@ void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
                    hipStream_t s);
 // forward blend: variants (LDS batch depth x lane pixel block x schedule), all bit-identical
+// Tile ids of one blend launch: range y holds the global tiles
+// [base[y], base[y] + len[y]); count 0 means every tile.
+constexpr int kMaxTileRanges = 8;
+struct TileRanges {
+    int count;
+    int64_t base[kMaxTileRanges], len[kMaxTileRanges];
+};
 struct BlendArgs {
     const DevView *views;
     int nv;
@@ -180,6 +187,7 @@ struct BlendArgs {
     uint32_t *ws;                // kBlendWsWords words (queue schedule)
     uint32_t *order;             // [ntiles] (queue schedule)
     int64_t queue_waves;         // persistent waves of the queue schedule
+    TileRanges tr;               // grid schedules only (the queue schedule takes every tile)
 };
 struct BlendVariant { int batch, rows; bool queue, quad; };
 // batch {32, 64, 128} x rows {1, 2} x {grid, queue}, then the quadrant blocks with batch {64, 128, 256}

@@ -46,6 +46,10 @@ struct a3fr_ctx {
     hipEvent_t upload_done = nullptr;
     uint64_t *h_total = nullptr;
     hipEvent_t total_ready = nullptr;  // the key total has reached h_total
+    // second stream of a foveated frame: the fovea and mid layers are blended
+    // on it while the main stream blends the periphery and runs the network
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // a frame of this library defers the view-dependent colour of its entries
     // into a3fr_bin_sort, where it runs while the host waits for the key total
     bool defer_colour = false, colour_pending = false;
@@ -327,6 +331,12 @@ void a3fr_destroy(a3fr_ctx *c) {
     if (c->h_total) (void)hipHostFree(c->h_total);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->total_ready) (void)hipEventDestroy(c->total_ready);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -807,7 +817,7 @@ const uint32_t *sorted_vals(a3fr_ctx *c) {
 extern "C" {
 
 static a3fr_status blend_with(a3fr_ctx *c, int variant, float *rgb, float *T, uint32_t *last,
-                              unsigned long long *pairs) {
+                              unsigned long long *pairs, hipStream_t stream, const TileRanges *tr = nullptr) {
     TRY(ensure(c, c->blend_ws, sizeof(uint32_t) * kBlendWsWords));
     TRY(ensure(c, c->blend_order, sizeof(uint32_t) * (size_t)c->ntiles));
     BlendArgs a{};
@@ -823,7 +833,8 @@ static a3fr_status blend_with(a3fr_ctx *c, int variant, float *rgb, float *T, ui
     a.ws = P<uint32_t>(c->blend_ws);
     a.order = P<uint32_t>(c->blend_order);
     a.queue_waves = (int64_t)c->n_cus * 24;
-    launch_blend(a, variant, c->stream);
+    if (tr) a.tr = *tr;
+    launch_blend(a, variant, stream);
     return check_launch(c, "blend");
 }
 
@@ -841,7 +852,7 @@ a3fr_status a3fr_blend(a3fr_ctx *c, float *rgb, float *T, uint32_t *last) {
         }
     }
     StageTimer t_(c, A3FR_STAGE_BLEND);
-    return blend_with(c, c->blend_variant, rgb, T, last, pairs);
+    return blend_with(c, c->blend_variant, rgb, T, last, pairs, c->stream);
 }
 
 a3fr_status a3fr_set_blend_variant(a3fr_ctx *c, int32_t variant) {
@@ -866,11 +877,11 @@ a3fr_status a3fr_autotune_blend(a3fr_ctx *c, int32_t reps, double *ms_out, int32
     int best = c->blend_variant;
     a3fr_status st = A3FR_OK;
     for (int k = 0; k < kBlendVariants && st == A3FR_OK; ++k) {
-        st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr);  // warm-up
+        st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr, c->stream);  // warm-up
         if (st != A3FR_OK) break;
         if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, A3FR_EDEVICE, "hipEventRecord"); break; }
         for (int r = 0; r < reps && st == A3FR_OK; ++r)
-            st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr);
+            st = blend_with(c, k, P<float>(c->tune_img), nullptr, nullptr, nullptr, c->stream);
         if (st != A3FR_OK) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1061,12 +1072,46 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     TRY(a3fr_bin_sort(c, nullptr));
     TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
     float *L = P<float>(c->layers);
-    TRY(a3fr_blend(c, L, nullptr, nullptr));
     const bool net = c->net_theta != nullptr;
-    if (net) {
-        // the network writes the periphery (outside r_mid) of every eye straight into out
-        StageTimer t_(c, A3FR_STAGE_NET);
+    // Overlap: the main stream blends the periphery layers and runs them
+    // through the network while the side stream blends the fovea and mid
+    // layers (different layers, different pixels; the composite waits for both).
+    // Profiled frames keep one stream, so that each stage is timed alone.
+    const bool overlap = net && !c->profiling && !c->capturing && n_eyes <= kMaxTileRanges &&
+                         !blend_variant(c->blend_variant).queue;
+    if (overlap) {
+        if (!c->side) HIPCHECK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        if (!c->ev_fork) HIPCHECK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        if (!c->ev_join) HIPCHECK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        TileRanges per{}, fm{};
+        per.count = fm.count = n_eyes;
+        for (int e = 0; e < n_eyes; ++e) {
+            const DevView &d0 = c->hviews[3 * e], &d2 = c->hviews[3 * e + 2];
+            per.base[e] = d2.tile_off;
+            per.len[e] = (int64_t)d2.tiles_x * d2.tiles_y;
+            fm.base[e] = d0.tile_off;  // fovea and mid views: the tiles before the periphery's
+            fm.len[e] = d2.tile_off - d0.tile_off;
+        }
+        // the periphery's waves are queued first (on the main stream, no
+        // cross-stream wait before them), so they are not left behind the
+        // far more numerous fovea and mid waves
+        // the periphery's few long-list tiles take four waves each (8 x 8
+        // quadrant blocks), so that the network can start sooner
+        constexpr int kPeriphVariant = 12;
+        HIPCHECK(c, hipEventRecord(c->ev_fork, c->stream));
+        TRY(blend_with(c, kPeriphVariant, L, nullptr, nullptr, nullptr, c->stream, &per));
+        HIPCHECK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        TRY(blend_with(c, c->blend_variant, L, nullptr, nullptr, nullptr, c->side, &fm));
+        HIPCHECK(c, hipEventRecord(c->ev_join, c->side));
         TRY(net_frame_forward(c, cams, n_eyes, f->r_mid, L, out));
+        HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    } else {
+        TRY(a3fr_blend(c, L, nullptr, nullptr));
+        if (net) {
+            // the network writes the periphery (outside r_mid) of every eye straight into out
+            StageTimer t_(c, A3FR_STAGE_NET);
+            TRY(net_frame_forward(c, cams, n_eyes, f->r_mid, L, out));
+        }
     }
     bool same_size = true;
     for (int e = 1; e < n_eyes; ++e)
@@ -1159,7 +1204,7 @@ static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, 
     TRY(entry_stages(c, nullptr));
     TRY(a3fr_bin_sort(c, nullptr));
     StageTimer t_(c, A3FR_STAGE_BLEND);
-    return blend_with(c, c->blend_variant, P<float>(c->layers), nullptr, nullptr, nullptr);
+    return blend_with(c, c->blend_variant, P<float>(c->layers), nullptr, nullptr, nullptr, c->stream);
 }
 
 a3fr_status a3fr_incremental_begin(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, int32_t n_eyes,

@@ -377,8 +377,9 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
                                                    const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
                                                    int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
                                                    uint32_t *__restrict__ lastout,
-                                                   unsigned long long *__restrict__ pairs) {
-    const int64_t gt = blockIdx.x;
+                                                   unsigned long long *__restrict__ pairs, TileRanges tr) {
+    if ((int64_t)blockIdx.x >= tr.len[blockIdx.y]) return;  // block-uniform
+    const int64_t gt = tr.base[blockIdx.y] + blockIdx.x;
     if (!active[gt]) return;  // block-uniform
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
     __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
@@ -488,8 +489,10 @@ __global__ void __launch_bounds__(64) k_blend(const DevView *__restrict__ views,
                                               const uint8_t *__restrict__ active, const uint32_t *__restrict__ ranges,
                                               const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
                                               int64_t n, float *__restrict__ rgb, float *__restrict__ Tout,
-                                              uint32_t *__restrict__ lastout, unsigned long long *__restrict__ pairs) {
-    const int64_t gt = blockIdx.x;
+                                              uint32_t *__restrict__ lastout, unsigned long long *__restrict__ pairs,
+                                              TileRanges tr) {
+    if ((int64_t)blockIdx.x >= tr.len[blockIdx.y]) return;  // block-uniform
+    const int64_t gt = tr.base[blockIdx.y] + blockIdx.x;
     if (!active[gt]) return;
     uint32_t npairs = 0;
     blend_tile<COUNT, BATCH, ROWS>(gt, views, nv, ranges, vals, rec, n, rgb, Tout, lastout, npairs);
@@ -551,14 +554,15 @@ __global__ void k_len_scatter(const uint8_t *__restrict__ active, const uint32_t
 }
 
 template <int BATCH, int ROWS>
-static void launch_variant(const BlendArgs &a, bool queue, hipStream_t s) {
+static void launch_variant(const BlendArgs &a, const TileRanges &tr, int64_t longest, bool queue, hipStream_t s) {
     if (!queue) {
+        const dim3 g((unsigned)longest, (unsigned)tr.count);
         if (a.pairs)
-            hipLaunchKernelGGL((k_blend<true, BATCH, ROWS>), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.views, a.nv,
-                               a.active, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+            hipLaunchKernelGGL((k_blend<true, BATCH, ROWS>), g, dim3(64), 0, s, a.views, a.nv, a.active, a.ranges,
+                               a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
         else
-            hipLaunchKernelGGL((k_blend<false, BATCH, ROWS>), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.views, a.nv,
-                               a.active, a.ranges, a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+            hipLaunchKernelGGL((k_blend<false, BATCH, ROWS>), g, dim3(64), 0, s, a.views, a.nv, a.active, a.ranges,
+                               a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
         return;
     }
     const unsigned grid = (unsigned)(a.ntiles < a.queue_waves ? a.ntiles : a.queue_waves);
@@ -583,41 +587,50 @@ void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t n
 void launch_blend(const BlendArgs &a, int variant, hipStream_t s) {
     if (a.ntiles == 0) return;
     const BlendVariant v = blend_variant(variant);
+    TileRanges tr = a.tr;
+    if (tr.count <= 0) {
+        tr.count = 1;
+        tr.base[0] = 0;
+        tr.len[0] = a.ntiles;
+    }
+    int64_t longest = 0;
+    for (int k = 0; k < tr.count; ++k) longest = tr.len[k] > longest ? tr.len[k] : longest;
+    if (longest == 0) return;
     if (v.quad) {
-        const dim3 g((unsigned)a.ntiles), b(256);
+        const dim3 g((unsigned)longest, (unsigned)tr.count), b(256);
         switch (v.batch) {
             case 64:
                 if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 64>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 else hipLaunchKernelGGL((k_blend_quad<false, 64>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 break;
             case 128:
                 if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 128>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 else hipLaunchKernelGGL((k_blend_quad<false, 128>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 break;
             default:
                 if (a.pairs) hipLaunchKernelGGL((k_blend_quad<true, 256>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                                a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 else hipLaunchKernelGGL((k_blend_quad<false, 256>), g, b, 0, s, a.views, a.nv, a.active, a.ranges,
-                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs);
+                                        a.vals, a.rec, a.n, a.rgb, a.T, a.last, a.pairs, tr);
                 break;
         }
         return;
     }
-    if (v.queue) {
+    if (v.queue) {  // every tile (the callers pass no ranges with a queue variant)
         launch_blend_order(a.active, a.ranges, a.ntiles, a.ws, a.order, s);
         launch_fill_u32(a.ws + 67, 0u, 1, s);
     }
     switch (v.batch * 10 + v.rows) {
-        case 321: launch_variant<32, 1>(a, v.queue, s); break;
-        case 322: launch_variant<32, 2>(a, v.queue, s); break;
-        case 641: launch_variant<64, 1>(a, v.queue, s); break;
-        case 642: launch_variant<64, 2>(a, v.queue, s); break;
-        case 1281: launch_variant<128, 1>(a, v.queue, s); break;
-        default: launch_variant<128, 2>(a, v.queue, s); break;
+        case 321: launch_variant<32, 1>(a, tr, longest, v.queue, s); break;
+        case 322: launch_variant<32, 2>(a, tr, longest, v.queue, s); break;
+        case 641: launch_variant<64, 1>(a, tr, longest, v.queue, s); break;
+        case 642: launch_variant<64, 2>(a, tr, longest, v.queue, s); break;
+        case 1281: launch_variant<128, 1>(a, tr, longest, v.queue, s); break;
+        default: launch_variant<128, 2>(a, tr, longest, v.queue, s); break;
     }
 }
 
