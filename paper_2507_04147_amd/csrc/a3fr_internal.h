@@ -119,7 +119,8 @@ void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, 
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
                        Record *rec, double *score, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
 void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, Record *rec, hipStream_t s);
+                         int64_t m, Record *rec, hipStream_t s,
+                         int max_blocks = 2048 /* grid cap (grid-stride loop); 0: one thread per slot */);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
                    uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s,

@@ -337,15 +337,18 @@ __device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_vie
 }
 
 // Colour of every entry that emits keys.
+// Grid-stride over the entries: the grid is capped, so that it does not
+// dispatch blocks for the slots past the device entry count (the grid is
+// sized on the host by the slot count m, the entries are known on the device).
 __global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevView *__restrict__ views,
                                                       const uint32_t *__restrict__ ent, const uint32_t *n_ent,
                                                       Record *__restrict__ rec) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)*n_ent) return;
-    const int64_t n = sc.n;
-    const int64_t e = ent[j];
-    const int v = (int)(e / n);
-    colour_into(sc, views[v].v, e - (int64_t)v * n, rec[e]);
+    const int64_t E = *n_ent, n = sc.n;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = ent[j];
+        const int v = (int)(e / n);
+        colour_into(sc, views[v].v, e - (int64_t)v * n, rec[e]);
+    }
 }
 
 // Colour of every visible slot of the views whose mask changes after the
@@ -368,9 +371,11 @@ void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, in
 }
 
 void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, Record *rec, hipStream_t s) {
+                         int64_t m, Record *rec, hipStream_t s, int max_blocks) {
     if (m == 0) return;
-    hipLaunchKernelGGL(k_entry_colour, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, sc, views, ent, n_ent, rec);
+    int64_t blocks = (m + 255) / 256;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL(k_entry_colour, dim3((unsigned)blocks), dim3(256), 0, s, sc, views, ent, n_ent, rec);
 }
 
 }  // namespace a3fr
