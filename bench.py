@@ -49,24 +49,24 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="3c4261b66f34011563560c74b955a2243dac024cbfcb445e5764bdb2be270794",
-                  kib={"32,4x1,grid": (5970.9, 21750.0), "64,4x1,grid": (6989.4, 21750.0),
-                       "128,4x1,grid": (10140.6, 21750.0), "32,2x2,grid": (5974.4, 21750.0),
-                       "64,2x2,grid": (6982.0, 21750.0), "128,2x2,grid": (10127.3, 21750.0),
-                       "32,4x1,queue": (5531.7, 21838.4), "64,4x1,queue": (6480.9, 21855.2),
-                       "128,4x1,queue": (9359.9, 21939.4), "32,2x2,queue": (5490.4, 21799.4),
-                       "64,2x2,queue": (6452.5, 21733.2), "128,2x2,queue": (9415.8, 21919.2),
-                       "64,8x8q,grid": (10379.9, 21750.0), "128,8x8q,grid": (18920.4, 21750.0),
-                       "256,8x8q,grid": (35761.2, 21750.0)}),
+                  sha256="cb611d71c86df04cbb7921af994ddd9815598e3347bcacb2f72e1e555270b5be",
+                  kib={"32,4x1,grid": (5984.8, 21750.0), "64,4x1,grid": (6995.0, 21750.0),
+                       "128,4x1,grid": (10140.3, 21750.0), "32,2x2,grid": (5986.7, 21750.0),
+                       "64,2x2,grid": (6989.9, 21750.0), "128,2x2,grid": (10145.6, 21750.0),
+                       "32,4x1,queue": (5556.0, 22083.5), "64,4x1,queue": (6483.3, 21817.7),
+                       "128,4x1,queue": (9520.0, 22240.2), "32,2x2,queue": (5516.1, 21793.3),
+                       "64,2x2,queue": (6430.7, 21769.4), "128,2x2,queue": (9354.4, 21932.1),
+                       "64,8x8q,grid": (10377.4, 21750.0), "128,8x8q,grid": (18920.5, 21750.0),
+                       "256,8x8q,grid": (35748.6, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="4810cd024fdba27ec23b3c35b2c9b93d664dca16a54dc06d601439642d48a0f5",
-                       kib={"k_preprocess": (43142.7, 162834.8)}),
+                       sha256="e25e4eb0efedef2841c5fc8d1b9f4e92e64b1be01373667307f388b9fe7fa370",
+                       kib={"k_preprocess": (43145.0, 162834.9)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="4810cd024fdba27ec23b3c35b2c9b93d664dca16a54dc06d601439642d48a0f5",
-                   kib={"k_entry_colour": (49397.9, 13557.0)}),
+                   sha256="e25e4eb0efedef2841c5fc8d1b9f4e92e64b1be01373667307f388b9fe7fa370",
+                   kib={"k_entry_colour": (49271.2, 13557.5)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the two tile-id passes of the key sort
-                      sha256="585dc28c58de76317f49e6eef01624c5f3a62fab24e6442aab95a4eaf5a09348",
-                      kib={"k_onesweep": (39740.8, 78474.3)}),
+                      sha256="7d7634a17e8b9014540af3f74c77957c4493eddf386d1e488f377f9c9c9da7fe",
+                      kib={"k_onesweep": (39684.9, 78171.9)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale and quaternion of every Gaussian (40 B) once
