@@ -1076,9 +1076,10 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     // Overlap: the main stream blends the periphery layers and runs them
     // through the network while the side stream blends the fovea and mid
     // layers (different layers, different pixels; the composite waits for both).
-    // Profiled frames keep one stream, so that each stage is timed alone.
-    const bool overlap = net && !c->profiling && !c->capturing && n_eyes <= kMaxTileRanges &&
-                         !blend_variant(c->blend_variant).queue;
+    // Profiled frames keep one stream, so that each stage is timed alone.  A
+    // graph capture records the same fork and join (the side stream joins the
+    // capture through the fork event).
+    const bool overlap = net && !c->profiling && n_eyes <= kMaxTileRanges && !blend_variant(c->blend_variant).queue;
     if (overlap) {
         if (!c->side) HIPCHECK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         if (!c->ev_fork) HIPCHECK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));

@@ -39,9 +39,9 @@ def _setup(pkg, n, W, H, n_frames, seed):
 @pytest.mark.parametrize("options", ["plain", "fallback+net+queue", "fallback+net"])
 def test_graph_replays_match_eager(pkg, options):
     """Graph replays equal eager frames bit for bit.  With the network and a
-    grid blend variant ("fallback+net") the eager frame blends the fovea and
-    mid layers on a second stream beside the periphery's blend and the
-    network, while the captured graph keeps one stream."""
+    grid blend variant ("fallback+net") the frame blends the fovea and mid
+    layers on a second stream beside the periphery's blend and the network,
+    in the eager frames and in the captured graph (fork and join recorded)."""
     W, H = 232, 240
     scene, ds, trace, fov = _setup(pkg, 60_000, W, H, 6, 11)
     ce, cg = pkg.Context(), pkg.Context()
