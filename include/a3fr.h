@@ -196,7 +196,11 @@ a3fr_status a3fr_render_full(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_
 /* Foveated stereo frame: the three layers of each of n_eyes eyes
  * (a3fr_make_foveated_views) rendered in one preprocess / sort / blend,
  * then composited to full resolution: out_dev [n_eyes][3][H][W].
- * Synchronises once (a3fr_bin_sort). */
+ * Synchronises once (a3fr_bin_sort).  With the upsampler set (and at most 8
+ * eyes, a grid blend variant, profiling off) the fovea and mid layers are
+ * blended on a second, internal stream beside the periphery's blend and the
+ * network; the context's stream waits for it before the composite, so the
+ * output is ordered on the context's stream as for any other call. */
 a3fr_status a3fr_render_foveated(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams,
                                  const a3fr_gaze *gaze, int32_t n_eyes, const a3fr_fovea *fovea, float *out_dev);
 
