@@ -95,11 +95,17 @@ def test_fallback_parity(pkg):
     ctx.close()
 
 
-def test_fallback_threshold_zero_equals_frr_outside_mid(pkg):
+@pytest.mark.parametrize("net", [False, True])
+def test_fallback_threshold_zero_equals_frr_outside_mid(pkg, net):
+    """Threshold 0 flags every periphery tile: outside r_mid the frame is the
+    full-resolution render, also when the network has written the periphery
+    first (the composite then replaces every flagged tile)."""
     W, H = 464, 480
     scene, cams, gz, rad = _frame(100_000, W, H, seed=6)
     ds = pkg.DeviceScene.from_host(scene)
     ctx = pkg.Context()
+    if net:
+        ctx.set_upsampler(torch.from_numpy(synth.net_init(48, last_scale=1.0)).cuda())
     frr = torch.zeros((2, 3, H, W), device="cuda")
     ctx.render_full(ds, cams, frr)
     ctx.set_fallback(0.0, 1.0, 1.0)
