@@ -79,14 +79,17 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) fyr[r] = (float)(py0 + r) + 0.5f;
     float fxq[4];
-    bool alive[4];
+    // per pixel the alpha a Gaussian needs to be blended: 1/255 while the
+    // pixel is live, +inf once it has stopped or when it lies outside the
+    // image (one compare per pair then also carries the live test)
+    float thr[4];
     float T[4], Cr[4], Cg[4], Cb[4];
     uint32_t last[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int cx = px0 + q % COLS, cy = py0 + q / COLS;
         fxq[q] = (float)cx + 0.5f;
-        alive[q] = (x0 + cx < W) && (y0 + cy < H);
+        thr[q] = (x0 + cx < W) && (y0 + cy < H) ? kAlphaMin : INFINITY;
         T[q] = 1.0f; Cr[q] = Cg[q] = Cb[q] = 0.0f; last[q] = 0;
     }
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
@@ -94,7 +97,7 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
     const double dx0 = (double)x0, dy0 = (double)y0;
 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-        if (__ballot(alive[0] || alive[1] || alive[2] || alive[3]) == 0ull) break;
+        if (__ballot(fminf(fminf(thr[0], thr[1]), fminf(thr[2], thr[3])) < INFINITY) == 0ull) break;
         // Stage the batch, keeping only the entries that can reach the tile
         // (tile_reach), packed in list order with their positions for the
         // last-blended index.
@@ -134,7 +137,7 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
             if (COUNT) {
                 uint32_t live = 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) live += alive[q] ? 1u : 0u;
+                for (int q = 0; q < 4; ++q) live += thr[q] < INFINITY ? 1u : 0u;
                 npairs += live * (uint32_t)((int)s_j[jj] - prev - 1);
                 prev = (int)s_j[jj];
             }
@@ -151,11 +154,11 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int rr = q / COLS;
-                if (COUNT) npairs += alive[q] ? 1u : 0u;
+                if (COUNT) npairs += thr[q] < INFINITY ? 1u : 0u;
                 const float t = (fxq[q] - mu) + kdy[rr];
                 const float e = fmaf(a2, t * t, cdy[rr]);
                 al[q] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                take[q] = alive[q] && al[q] >= kAlphaMin;
+                take[q] = al[q] >= thr[q];
                 any = any || take[q];
             }
             // most evaluated pairs fall outside the footprint (alpha < 1/255): skip when the whole wave does
@@ -172,14 +175,14 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 Cb[q] = fmaf(wgt, cb, Cb[q]);
                 T[q] = blend ? Tn : T[q];
                 last[q] = blend ? idx : last[q];
-                alive[q] = alive[q] && !stop;
+                thr[q] = stop ? INFINITY : thr[q];
             }
         }
         if (COUNT) {
             const int nb = (int)((end - b0) < (uint32_t)BATCH ? (end - b0) : (uint32_t)BATCH);
             uint32_t live = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) live += alive[q] ? 1u : 0u;
+            for (int q = 0; q < 4; ++q) live += thr[q] < INFINITY ? 1u : 0u;
             npairs += live * (uint32_t)(nb - prev - 1);
         }
         __syncthreads();
