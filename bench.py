@@ -49,15 +49,15 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="cb611d71c86df04cbb7921af994ddd9815598e3347bcacb2f72e1e555270b5be",
-                  kib={"32,4x1,grid": (5984.8, 21750.0), "64,4x1,grid": (6995.0, 21750.0),
-                       "128,4x1,grid": (10140.3, 21750.0), "32,2x2,grid": (5986.7, 21750.0),
-                       "64,2x2,grid": (6989.9, 21750.0), "128,2x2,grid": (10145.6, 21750.0),
-                       "32,4x1,queue": (5556.0, 22083.5), "64,4x1,queue": (6483.3, 21817.7),
-                       "128,4x1,queue": (9520.0, 22240.2), "32,2x2,queue": (5516.1, 21793.3),
-                       "64,2x2,queue": (6430.7, 21769.4), "128,2x2,queue": (9354.4, 21932.1),
-                       "64,8x8q,grid": (10377.4, 21750.0), "128,8x8q,grid": (18920.5, 21750.0),
-                       "256,8x8q,grid": (35748.6, 21750.0)}),
+                  sha256="cd399d01b838d1578e92e48774828312475720ace13839eebb27064f8a026e09",
+                  kib={"32,4x1,grid": (5986.2, 21750.0), "64,4x1,grid": (7002.2, 21750.0),
+                       "128,4x1,grid": (10132.4, 21750.0), "32,2x2,grid": (5991.6, 21750.0),
+                       "64,2x2,grid": (6995.4, 21750.0), "128,2x2,grid": (10133.3, 21750.0),
+                       "32,4x1,queue": (5533.1, 21831.2), "64,4x1,queue": (6518.6, 21866.3),
+                       "128,4x1,queue": (9377.5, 21884.2), "32,2x2,queue": (5517.7, 21755.1),
+                       "64,2x2,queue": (6469.1, 21811.4), "128,2x2,queue": (9382.8, 21968.6),
+                       "64,8x8q,grid": (10377.3, 21750.0), "128,8x8q,grid": (18923.1, 21750.0),
+                       "256,8x8q,grid": (35774.1, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
                        sha256="e25e4eb0efedef2841c5fc8d1b9f4e92e64b1be01373667307f388b9fe7fa370",
                        kib={"k_preprocess": (43145.0, 162834.9)}),

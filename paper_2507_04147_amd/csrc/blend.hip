@@ -402,7 +402,9 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
     const int qx = (w & 1) * 8, qy = (w >> 1) * 8;
     const int px = qx + (lane & 7), py = qy + (lane >> 3);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    bool alive = (x0 + px < W) && (y0 + py < H);
+    // the alpha a Gaussian needs to be blended: 1/255 while the pixel is live,
+    // +inf once it has stopped or when it lies outside the image
+    float thr = (x0 + px < W) && (y0 + py < H) ? kAlphaMin : INFINITY;
     float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
     uint32_t last = 0, npairs = 0;
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
@@ -411,7 +413,7 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
     const uint64_t ltm = (1ull << lane) - 1ull;
 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-        const uint64_t live = __ballot(alive);
+        const uint64_t live = __ballot(thr < INFINITY);
         if (lane == 0) s_live[w] = live != 0ull ? 1u : 0u;
         for (int slot = tid; slot < BATCH; slot += 256) {
             const uint32_t j = b0 + slot;
@@ -445,7 +447,7 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
         for (uint32_t q = 0; q < wcnt; ++q) {
             const uint32_t jj = s_list[w][q];
             if (COUNT) {
-                npairs += alive ? (uint32_t)((int)jj - prev) : 0u;  // the dropped ones before it, and itself
+                npairs += thr < INFINITY ? (uint32_t)((int)jj - prev) : 0u;  // the dropped ones before it, and itself
                 prev = (int)jj;
             }
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
@@ -455,7 +457,7 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
             const float t = (fx - mu) + kdy;
             const float e = fmaf(a2, t * t, cdy);
             const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-            const bool take = alive && al >= kAlphaMin;
+            const bool take = al >= thr;
             if (__ballot(take) == 0ull) continue;
             const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
             const float Tn = T * (1.0f - al);
@@ -467,9 +469,9 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
             Cb = fmaf(wgt, cb, Cb);
             T = blend ? Tn : T;
             last = blend ? b0 - start + jj + 1 : last;
-            alive = alive && !stop;
+            thr = stop ? INFINITY : thr;
         }
-        if (COUNT) npairs += alive ? (uint32_t)((int)cnt - 1 - prev) : 0u;
+        if (COUNT) npairs += thr < INFINITY ? (uint32_t)((int)cnt - 1 - prev) : 0u;
         __syncthreads();  // the staging is reused by the next batch
     }
     const int x = x0 + px, y = y0 + py;
