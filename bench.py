@@ -49,7 +49,7 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="cd399d01b838d1578e92e48774828312475720ace13839eebb27064f8a026e09",
+                  sha256="b9a74ea12a52acdfd3a21cf45e81263eff19c40749a36e2b51301f4a95819574",
                   kib={"32,4x1,grid": (5986.2, 21750.0), "64,4x1,grid": (7002.2, 21750.0),
                        "128,4x1,grid": (10132.4, 21750.0), "32,2x2,grid": (5991.6, 21750.0),
                        "64,2x2,grid": (6995.4, 21750.0), "128,2x2,grid": (10133.3, 21750.0),

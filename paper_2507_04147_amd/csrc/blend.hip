@@ -245,13 +245,13 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
     const int lane = threadIdx.x;
     const int bx = 2 * (lane & 7), by = 2 * (lane >> 3);  // the lane's 2 x 2 block in the tile
     float fx[NP], fy[NP], T[NP], Cr[NP], Cg[NP], Cb[NP];
-    bool alive[NP];
+    float thr[NP];  // 1/255 while the pixel is live, +inf once stopped or outside the image
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int cx = bx + (k & 1), cy = by + (k >> 1);
         fx[k] = (float)cx + 0.5f;
         fy[k] = (float)cy + 0.5f;
-        alive[k] = (x0 + cx < W) && (y0 + cy < H);
+        thr[k] = (x0 + cx < W) && (y0 + cy < H) ? kAlphaMin : INFINITY;
         T[k] = 1.0f; Cr[k] = Cg[k] = Cb[k] = 0.0f;
     }
     const Record *R = rec + lo * n;
@@ -259,7 +259,7 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         bool any_alive = false;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) any_alive = any_alive || alive[k];
+        for (int k = 0; k < NP; ++k) any_alive = any_alive || thr[k] < INFINITY;
         if (__ballot(any_alive) == 0ull) break;
         const uint32_t j = b0 + lane;
         bool keep = false;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
                 const float t = (fx[k] - mu) + kdy;
                 const float e = fmaf(a2, t * t, cdy);
                 al[k] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                take[k] = alive[k] && al[k] >= kAlphaMin;
+                take[k] = al[k] >= thr[k];
                 any = any || take[k];
             }
             if (__ballot(any) == 0ull) continue;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
                 Cg[k] = fmaf(wgt, cg, Cg[k]);
                 Cb[k] = fmaf(wgt, cb, Cb[k]);
                 T[k] = blend ? Tn : T[k];
-                alive[k] = alive[k] && !stop;
+                thr[k] = stop ? INFINITY : thr[k];
             }
         }
         __syncthreads();
