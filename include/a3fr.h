@@ -149,15 +149,23 @@ const char *a3fr_last_error(const a3fr_ctx *ctx);
 
 /* ---- the rendering path ---------------------------------------------------*/
 
-/* Projection of every (view, Gaussian) pair (Sec. 2.3, projection stage):
+/* Projection of every (view, Gaussian) pair (Sec. 2.3, projection stage: each
+ * ellipsoid becomes a screen ellipse and the tiles it intersects are found):
  * near-plane cull (z <= 0.2), EWA projection of the 3D covariance to a 2D
- * covariance dilated by 0.3 px^2, the tile rectangle of the footprint box
- * {d : d' Sigma2D^-1 d <= 11.1}, the number of active tiles it covers, the
- * float32 depth key and view-dependent SH colour per eye.  The integer
- * results are computed in float64 in a fixed operation order (bit-exact
- * against the reference definition).  For views with select = 1 the
- * periphery subset is chosen here (radix select on opacity x pi x
- * sqrt(det Sigma2D)).  Then the key counts are prefix-summed.
+ * covariance Sigma2D dilated by 0.3 px^2, and the tile rectangle of the
+ * axis-aligned box around the part of the ellipse where the Gaussian can be
+ * drawn: {d : d' Sigma2D^-1 d <= Q(o)}, where Q(o), for opacity o, is the
+ * smallest k/8 (k = 1..88) with exp(k/16) >= 1.001 x 255 o, else 11.1.  A
+ * pixel outside that box has alpha = o exp(-q/2) < 1/255 and is skipped by
+ * the blend, so the tile lists, and the images, do not depend on the tile
+ * shape.  Then: the number of active tiles the rectangle covers, the float32
+ * depth key, and the view-dependent SH colour per eye.  The integer results
+ * are computed in float64 in a fixed operation order (bit-exact against the
+ * reference definition).  For views with select = 1 the periphery subset is
+ * chosen here: over the Gaussians whose box meets the view, the
+ * ceil(keep_num/keep_den x N_vis) of largest opacity x pi x sqrt(det Sigma2D),
+ * ties to the lower index (radix select on the float64 score bits).  Then the
+ * key counts are prefix-summed.
  * views: host array of n_views (1..384) views.  keep = keep_num/keep_den
  * (ignored without selecting views).  The results stay in the context and are
  * reused by a3fr_bin_sort and a3fr_blend until the next a3fr_preprocess
@@ -203,6 +211,21 @@ a3fr_status a3fr_render_full(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_
  * output is ordered on the context's stream as for any other call. */
 a3fr_status a3fr_render_foveated(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams,
                                  const a3fr_gaze *gaze, int32_t n_eyes, const a3fr_fovea *fovea, float *out_dev);
+
+/* Batched gaze trace: n_frames consecutive stereo frames, each with its own
+ * head pose and gaze, rendered as ONE batch -- every layer of every eye of every
+ * frame in one projection pass over the scene, one key sort and one blend
+ * launch (tiles of all views in one grid, uneven tile counts), then
+ * composited (Sec. 3.5: the projection and per-tile lists of the scene are
+ * shared by all the regions rendered from it).  This is a3fr_render_foveated
+ * with n_eyes = 2 n_frames, eye 2f + k being eye k (0 left, 1 right) of frame
+ * f, and gives the same images as the frames rendered one at a time.
+ * cams, gaze: host arrays [n_frames][2], frame-major.  out_dev: device
+ * [n_frames][2][3][H][W].  n_frames in [1, 64].  Synchronises once
+ * (a3fr_bin_sort); for a batch without host read-back capture it with
+ * a3fr_graph_capture (n_eyes = 2 n_frames) and replay it per window. */
+a3fr_status a3fr_render_batch(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_camera *cams,
+                              const a3fr_gaze *gaze, int32_t n_frames, const a3fr_fovea *fovea, float *out_dev);
 
 /* Host helper: the 3 layer views of each eye (eye-major, layer-minor:
  * fovea disc of radius r_fovea at full resolution; mid annulus at 1/scale_mid

@@ -450,7 +450,15 @@ void or_ranges(int64_t K, const uint64_t *keys, int64_t ntiles, int64_t *range) 
  * error a float32 evaluation of the same blend can make: eps_alpha bounds the
  * relative error of a float32 alpha, eps_step the relative rounding of one
  * float32 transmittance update.  The bound on T's relative error grows along the
- * list by alpha eps_alpha / (1 - alpha) + eps_step per blended Gaussian. */
+ * list by alpha eps_alpha / (1 - alpha) + eps_step per blended Gaussian.
+ *
+ * For such a pixel the float32 renderer may take the other branch of the
+ * decision.  Its colour then is the one the definition gives with that single
+ * decision reversed (every other decision taken as in float64), so the
+ * tolerance of an ambiguous pixel is derived by rendering it that way: amb_tol
+ * is the sum, over its near-threshold decisions, of the largest channel change
+ * that reversing the decision alone causes (a first-order bound when several
+ * decisions are near their thresholds at once). */
 typedef struct {
     double eps_alpha, eps_step;
 } or_blend_opts;
@@ -460,14 +468,21 @@ typedef struct {
     int32_t last;   /* 1 + list position of the last blended Gaussian, 0 if none */
     int32_t amb;    /* a skip/stop decision fell within the margin of its threshold */
     int64_t pairs;  /* list entries evaluated before the pixel stopped */
+    double amb_tol; /* largest colour change a reversed near-threshold decision causes */
 } or_pix;
+
+enum { OR_FLIP_NONE = 0, OR_FLIP_SKIP = 1, OR_FLIP_STOP = 2 };
+#define OR_MAX_FLIPS 16
 
 /* Front-to-back compositing of one pixel (centre px, py) over an ordered list:
  * alpha = min(0.99, o exp(p)) with p = min(0, -q/2), q = d' Sigma^-1 d; skip
- * alpha < 1/255; stop before blending when T (1 - alpha) < 1e-4. */
-static void or_blend_pixel(double px, double py, const uint32_t *list, int64_t len, int32_t v, int64_t n,
-                           const double *mu, const double *cov, const double *det, const float *opac,
-                           const double *colour_e, const double *bg, const or_blend_opts *op, or_pix *out) {
+ * alpha < 1/255; stop before blending when T (1 - alpha) < 1e-4.  With flip_j
+ * >= 0 the decision of kind flip_kind at list position flip_j goes the other
+ * way.  Near-threshold decisions are recorded in flips (when not NULL). */
+static void or_blend_path(double px, double py, const uint32_t *list, int64_t len, int32_t v, int64_t n,
+                          const double *mu, const double *cov, const double *det, const float *opac,
+                          const double *colour_e, const double *bg, const or_blend_opts *op, int64_t flip_j,
+                          int flip_kind, or_pix *out, int64_t *flip_pos, int *flip_kinds, int *nflips) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, relT = 0.0;
     int32_t last = 0, amb = 0;
     int64_t pairs = 0;
@@ -480,13 +495,25 @@ static void or_blend_pixel(double px, double py, const uint32_t *list, int64_t l
         double p = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy;
         if (p > 0.0) p = 0.0;
         double araw = (double)opac[i] * exp(p);
-        if (fabs(araw - OR_ALPHA_MIN) <= op->eps_alpha * OR_ALPHA_MIN) amb = 1;
-        if (araw < OR_ALPHA_MIN) continue;
+        if (fabs(araw - OR_ALPHA_MIN) <= op->eps_alpha * OR_ALPHA_MIN) {
+            amb = 1;
+            if (flip_pos && *nflips < OR_MAX_FLIPS) { flip_pos[*nflips] = j; flip_kinds[*nflips] = OR_FLIP_SKIP; }
+            if (nflips) ++*nflips;
+        }
+        int skip = araw < OR_ALPHA_MIN;
+        if (j == flip_j && flip_kind == OR_FLIP_SKIP) skip = !skip;
+        if (skip) continue;
         double alpha = araw < OR_ALPHA_MAX ? araw : OR_ALPHA_MAX;
         double Tn = T * (1.0 - alpha);
         double relTn = relT + (araw < OR_ALPHA_MAX ? alpha * op->eps_alpha / (1.0 - alpha) : 0.0) + op->eps_step;
-        if (fabs(Tn - OR_T_MIN) <= relTn * OR_T_MIN) amb = 1;
-        if (Tn < OR_T_MIN) break;
+        if (fabs(Tn - OR_T_MIN) <= relTn * OR_T_MIN) {
+            amb = 1;
+            if (flip_pos && *nflips < OR_MAX_FLIPS) { flip_pos[*nflips] = j; flip_kinds[*nflips] = OR_FLIP_STOP; }
+            if (nflips) ++*nflips;
+        }
+        int stop = Tn < OR_T_MIN;
+        if (j == flip_j && flip_kind == OR_FLIP_STOP) stop = !stop;
+        if (stop) break;
         const double *c = &colour_e[3 * i];
         for (int ch = 0; ch < 3; ++ch) C[ch] += alpha * T * c[ch];
         T = Tn;
@@ -494,7 +521,31 @@ static void or_blend_pixel(double px, double py, const uint32_t *list, int64_t l
         last = (int32_t)(j + 1);
     }
     for (int ch = 0; ch < 3; ++ch) out->rgb[ch] = C[ch] + T * bg[ch];
-    out->T = T; out->last = last; out->amb = amb; out->pairs = pairs;
+    out->T = T; out->last = last; out->amb = amb; out->pairs = pairs; out->amb_tol = 0.0;
+}
+
+static void or_blend_pixel(double px, double py, const uint32_t *list, int64_t len, int32_t v, int64_t n,
+                           const double *mu, const double *cov, const double *det, const float *opac,
+                           const double *colour_e, const double *bg, const or_blend_opts *op, or_pix *out) {
+    int64_t fpos[OR_MAX_FLIPS];
+    int fkind[OR_MAX_FLIPS];
+    int nf = 0;
+    or_blend_path(px, py, list, len, v, n, mu, cov, det, opac, colour_e, bg, op, -1, OR_FLIP_NONE, out, fpos, fkind,
+                  &nf);
+    if (nf > OR_MAX_FLIPS) {  /* not expected: no bound derived, the colour is not checked */
+        out->amb_tol = INFINITY;
+        return;
+    }
+    double tol = 0.0;
+    for (int f = 0; f < nf; ++f) {
+        or_pix alt;
+        or_blend_path(px, py, list, len, v, n, mu, cov, det, opac, colour_e, bg, op, fpos[f], fkind[f], &alt, NULL,
+                      NULL, NULL);
+        double d = 0.0;
+        for (int ch = 0; ch < 3; ++ch) d = fmax(d, fabs(alt.rgb[ch] - out->rgb[ch]));
+        tol += d;
+    }
+    out->amb_tol = tol;
 }
 
 typedef struct {
@@ -503,7 +554,7 @@ typedef struct {
     const uint32_t *vals; const int64_t *range;
     int64_t n; const double *mu, *cov, *det; const float *opac; const double *colour;
     or_blend_opts op;
-    double *rgb, *Tout; int32_t *last; uint8_t *amb; int64_t *pairs;
+    double *rgb, *Tout; int32_t *last; uint8_t *amb; int64_t *pairs; double *amb_tol;
     int64_t total_tiles;
 } or_blend_ctx;
 
@@ -530,6 +581,7 @@ static void or_blend_tile(void *vctx, int64_t gt) {
             C->Tout[C->img_off[v] + pix] = P.T;
             C->last[C->img_off[v] + pix] = P.last;
             C->amb[C->img_off[v] + pix] = (uint8_t)P.amb;
+            if (C->amb_tol) C->amb_tol[C->img_off[v] + pix] = P.amb_tol;
             C->pairs[C->img_off[v] + pix] = P.pairs;
         }
 }
@@ -541,11 +593,12 @@ void or_blend(int32_t nv, const or_view *views, int32_t tw, int32_t th,
               const uint32_t *sorted_vals, const int64_t *range,
               int64_t n, const double *mu, const double *cov, const double *det, const float *opac,
               const double *colour, double eps_alpha, double eps_step,
-              double *rgb, double *Tout, int32_t *last, uint8_t *amb, int64_t *pairs, int nthreads) {
+              double *rgb, double *Tout, int32_t *last, uint8_t *amb, int64_t *pairs, double *amb_tol,
+              int nthreads) {
     int64_t total = tile_off[nv];
     or_blend_ctx C = {nv, views, tw, th, active, aoff, tile_off, img_off, sorted_vals, range,
                       n, mu, cov, det, opac, colour, {eps_alpha, eps_step},
-                      rgb, Tout, last, amb, pairs, total};
+                      rgb, Tout, last, amb, pairs, amb_tol, total};
     or_parallel(total, or_blend_tile, &C, nthreads);
 }
 
@@ -593,7 +646,7 @@ void or_blend_brute(int64_t n, int32_t nv, const or_view *views, const int64_t *
 typedef struct {
     const uint32_t *list; int64_t len; int32_t v; int64_t n;
     const double *mu, *cov, *det; const float *opac; const double *col; const double *bg;
-    or_blend_opts op; const int32_t *xs, *ys; double *rgb, *T; int32_t *amb;
+    or_blend_opts op; const int32_t *xs, *ys; double *rgb, *T; int32_t *amb; double *amb_tol;
 } or_pixels_ctx;
 
 static void or_pixels_body(void *vctx, int64_t j) {
@@ -604,6 +657,7 @@ static void or_pixels_body(void *vctx, int64_t j) {
     for (int ch = 0; ch < 3; ++ch) C->rgb[3 * j + ch] = P.rgb[ch];
     C->T[j] = P.T;
     C->amb[j] = P.amb;
+    if (C->amb_tol) C->amb_tol[j] = P.amb_tol;
 }
 
 /* The plain definition for a sample of pixels of view v of a large scene:
@@ -612,7 +666,8 @@ static void or_pixels_body(void *vctx, int64_t j) {
 void or_blend_pixels(int64_t n, int32_t v, const or_view *views, const uint8_t *proj, const uint8_t *keep,
                      const uint32_t *depth_bits, const double *mu, const double *cov, const double *det,
                      const float *opac, const double *colour, double eps_alpha, double eps_step, int64_t npx,
-                     const int32_t *xs, const int32_t *ys, double *rgb, double *T, int32_t *amb, int nthreads) {
+                     const int32_t *xs, const int32_t *ys, double *rgb, double *T, int32_t *amb, double *amb_tol,
+                     int nthreads) {
     const or_view *vw = &views[v];
     uint64_t *ord = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     uint32_t *list = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
@@ -626,7 +681,7 @@ void or_blend_pixels(int64_t n, int32_t v, const or_view *views, const uint8_t *
     qsort(ord, (size_t)m, sizeof(uint64_t), or_u64_cmp);
     for (int64_t a = 0; a < m; ++a) list[a] = (uint32_t)(ord[a] & 0xffffffffu);
     or_pixels_ctx C = {list, m, v, n, mu, cov, det, opac, colour + (int64_t)vw->eye * n * 3, vw->bg,
-                       {eps_alpha, eps_step}, xs, ys, rgb, T, amb};
+                       {eps_alpha, eps_step}, xs, ys, rgb, T, amb, amb_tol};
     or_parallel(npx, or_pixels_body, &C, nthreads);
     free(ord);
     free(list);

@@ -72,9 +72,9 @@ def lib():
         L.or_sort.argtypes = [I64, P, P]
         L.or_ranges.argtypes = [I64, P, I64, P]
         L.or_blend.argtypes = [I32, P, I32, I32, P, P, P, P, P, P, I64, P, P, P, P, P, D, D,
-                               P, P, P, P, P, C.c_int]
+                               P, P, P, P, P, P, C.c_int]
         L.or_blend_brute.argtypes = [I64, I32, P, P, P, P, P, P, P, P, P, P, P, P]
-        L.or_blend_pixels.argtypes = [I64, I32, P, P, P, P, P, P, P, P, P, D, D, I64, P, P, P, P, P, C.c_int]
+        L.or_blend_pixels.argtypes = [I64, I32, P, P, P, P, P, P, P, P, P, D, D, I64, P, P, P, P, P, P, C.c_int]
         L.or_pixel_trace.argtypes = [I32, D, D, P, I64, I64, P, P, P, P, P]
         L.or_pixel_trace.restype = I64
         L.or_composite.argtypes = [I32, I32, D, D, D, D, P, P, I32, P, I32, P, P]
@@ -315,23 +315,26 @@ def render(scene, views, tw=TILE, th=TILE, keep_frac=(3, 10), eps_alpha=EPS_ALPH
     npx = int(ioff[-1])
     rgb, T = np.zeros(3 * npx), np.zeros(npx)
     last, amb, pairs = np.zeros(npx, np.int32), np.zeros(npx, np.uint8), np.zeros(npx, np.int64)
+    amb_tol = np.zeros(npx)
     vc = _views_c(views)
     op = np.ascontiguousarray(scene.opacity, np.float32)
     lib().or_blend(nv, vc, tw, th, _p(act), _p(aoff), _p(toff), _p(ioff), _p(svals), _p(rng), n,
                    _p(pr["mu"]), _p(pr["cov"]), _p(pr["det"]), _p(op), _p(colours), eps_alpha, eps_step,
-                   _p(rgb), _p(T), _p(last), _p(amb), _p(pairs), nthreads or default_threads())
-    res.update(colour=colours, img_off=ioff, rgb=rgb, T=T, last=last, amb=amb, pairs=pairs, _opac=op)
-    res["images"] = split_images(views, ioff, rgb, T, last, amb, pairs)
+                   _p(rgb), _p(T), _p(last), _p(amb), _p(pairs), _p(amb_tol), nthreads or default_threads())
+    res.update(colour=colours, img_off=ioff, rgb=rgb, T=T, last=last, amb=amb, pairs=pairs, amb_tol=amb_tol,
+               _opac=op)
+    res["images"] = split_images(views, ioff, rgb, T, last, amb, pairs, amb_tol)
     return res
 
 
-def split_images(views, ioff, rgb, T, last, amb, pairs):
+def split_images(views, ioff, rgb, T, last, amb, pairs, amb_tol):
     out = []
     for v, vw in enumerate(views):
         a, b = int(ioff[v]), int(ioff[v + 1])
         H, W = vw.height, vw.width
         out.append(dict(rgb=rgb[3 * a:3 * b].reshape(3, H, W), T=T[a:b].reshape(H, W),
                         last=last[a:b].reshape(H, W), amb=amb[a:b].reshape(H, W),
+                        amb_tol=amb_tol[a:b].reshape(H, W),
                         pairs=pairs[a:b].reshape(H, W)))
     return out
 
@@ -364,20 +367,21 @@ def render_brute(scene, views, keep=None, colours=None, tw=TILE, th=TILE):
 
 
 def blend_pixels(scene, views, pr, keep, colours, v, xs, ys, eps_alpha=None, eps_step=None, nthreads=None):
-    """Brute-force colours (and T, ambiguity) of sampled pixels (xs, ys) of view v,
-    from the projection arrays of project()."""
+    """Brute-force colours, T, ambiguity flags and ambiguity tolerances (the
+    colour change a reversed near-threshold decision causes) of sampled pixels
+    (xs, ys) of view v, from the projection arrays of project()."""
     xs = np.ascontiguousarray(xs, np.int32)
     ys = np.ascontiguousarray(ys, np.int32)
     npx = xs.size
-    rgb, T, amb = np.zeros((npx, 3)), np.zeros(npx), np.zeros(npx, np.int32)
+    rgb, T, amb, tol = np.zeros((npx, 3)), np.zeros(npx), np.zeros(npx, np.int32), np.zeros(npx)
     vc = _views_c(views)
     op = np.ascontiguousarray(scene.opacity, np.float32)
     lib().or_blend_pixels(scene.n, v, vc, _p(pr["proj"]), _p(None if keep is None else np.ascontiguousarray(keep)),
                           _p(pr["depth_bits"]), _p(pr["mu"]), _p(pr["cov"]), _p(pr["det"]), _p(op),
                           _p(np.ascontiguousarray(colours)), EPS_ALPHA if eps_alpha is None else eps_alpha,
                           EPS_STEP if eps_step is None else eps_step, npx, _p(xs), _p(ys), _p(rgb), _p(T), _p(amb),
-                          nthreads or default_threads())
-    return rgb, T, amb
+                          _p(tol), nthreads or default_threads())
+    return rgb, T, amb, tol
 
 
 def pixel_trace(res, view_index, px, py, tw=TILE, th=TILE, views=None):

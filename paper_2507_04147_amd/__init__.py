@@ -140,6 +140,8 @@ def lib():
         "a3fr_render_full": [P, C.POINTER(Scene_), C.POINTER(Camera_), I32, P],
         "a3fr_render_foveated": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32,
                                  C.POINTER(Fovea_), P],
+        "a3fr_render_batch": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32,
+                              C.POINTER(Fovea_), P],
         "a3fr_make_foveated_views": [C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Fovea_),
                                      C.POINTER(View_)],
         "a3fr_render_amr": [P, C.POINTER(Scene_), C.POINTER(Camera_), C.POINTER(Gaze_), I32, C.POINTER(Amr_), P],
@@ -358,6 +360,17 @@ class Context:
         self._check(self._L.a3fr_render_foveated(self._h, C.byref(scene.struct()), arr, gz, len(cams),
                                                  C.byref(fovea), _dp(out)))
 
+    def render_batch(self, scene: DeviceScene, frames, fovea: Fovea_, out):
+        """frames: [(stereo cameras, [gaze left, gaze right])]; out [n_frames][2][3][H][W]."""
+        self.generation += 1
+        self._scene = scene
+        cams = [c for f in frames for c in f[0]]
+        gazes = [g for f in frames for g in f[1]]
+        arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])
+        gz = (Gaze_ * len(gazes))(*[Gaze_(float(g[0]), float(g[1])) for g in gazes])
+        self._check(self._L.a3fr_render_batch(self._h, C.byref(scene.struct()), arr, gz, len(frames),
+                                              C.byref(fovea), _dp(out)))
+
     def render_amr(self, scene: DeviceScene, cams, gazes, amr: Amr_, out):
         """Full-resolution views with AMR levels 4..1 by distance from the gaze."""
         self.generation += 1
@@ -526,4 +539,4 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
             "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
             "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish",
-            "a3fr_render_amr"]
+            "a3fr_render_amr", "a3fr_render_batch"]

@@ -1139,6 +1139,13 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     return A3FR_OK;
 }
 
+a3fr_status a3fr_render_batch(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, const a3fr_gaze *gaze,
+                              int32_t n_frames, const a3fr_fovea *f, float *out) {
+    if (!c) return A3FR_EINVAL;
+    if (n_frames < 1 || 2 * n_frames > kMaxEyes) return fail(c, A3FR_EINVAL, "render_batch: n_frames must be in [1, 64]");
+    return a3fr_render_foveated(c, scene, cams, gaze, 2 * n_frames, f, out);
+}
+
 // ---- incremental foveal rounds ------------------------------------------------
 
 static a3fr_status inc_check(a3fr_ctx *c, const a3fr_camera *cams, const a3fr_gaze *gaze, int32_t n_eyes,

@@ -1,8 +1,11 @@
 // Projection stage of 3D Gaussian Splatting (paper Sec. 2.3: every ellipsoid
 // is projected to a screen ellipse and the tiles it intersects are found), run
 // once per frame for every layer of every eye so that later stages reuse it
-// (Sec. 3.5).  One thread per Gaussian: the scene is read once (236 B per
-// Gaussian, coalesced structure-of-arrays loads) and serves all views.
+// (Sec. 3.5).  One thread per (Gaussian, eye): its geometry is loaded with
+// coalesced structure-of-arrays reads, its 3D and view-space covariances are
+// formed once, and every layer view of that eye is projected from them.  The
+// view-dependent colour (SH, 192 B per Gaussian) is evaluated later, only for
+// the entries that emit keys (k_entry_colour).
 //
 // The integer outputs (tile rectangle, active-tile count, depth key, periphery
 // score bits) come from a float64 "key path" whose every operation is written

@@ -151,3 +151,52 @@ def test_graph_batched_full_size(pkg):
     cg.graph_destroy()
     ce.close()
     cg.close()
+
+
+@pytest.mark.parametrize("variant", [1, 7])
+def test_batched_frames_vs_oracle(pkg, variant):
+    """Row 12 against the FP64 oracle: four stereo frames of a drifting gaze
+    trace (head turning 1 deg/frame, saccades and jitter) in ONE a3fr_render_batch
+    (8 eyes, 24 layer views with uneven tile counts, ragged 232 x 240 grids).
+    Bit-exact against oracle.render on the same concatenated views: per-entry
+    counts, depths and rectangles, the kept sets, the depth order, key offsets,
+    keys in emission order, sorted keys and values, tile ranges; layer colours
+    within 1e-4 (ambiguous pixels within their derived tolerance), T, last
+    index; and the composite of every eye against the oracle's composite."""
+    import oracle
+    from test_gpu_parity import compare_images, compare_stage_outputs, composite_ambiguity, assert_amb_within, \
+        COLOUR_TOL
+    W, H = 232, 240
+    scene, ds, trace, fov = _setup(pkg, 40_000, W, H, 4, 17)
+    rad = (0.15 * W, 0.35 * W)
+    cams = [c for f in trace for c in f[0]]
+    gz = [g for f in trace for g in f[1]]
+    views = oracle.foveated_views(cams, gz, rad)
+    ref = oracle.render(scene, views)
+    ctx = pkg.Context()
+    ctx.set_blend_variant(variant)
+    ctx.set_debug(True)
+    out = torch.full((4, 2, 3, H, W), float("nan"), device="cuda")
+    ctx.render_batch(ds, trace, fov, out)
+    ctx.sync()
+    assert ctx.get_counts()["n_keys"] == ref["keys"].size
+    compare_stage_outputs(ctx, ref, views, scene.n)
+    o = out.cpu().numpy().reshape(8, 3, H, W)
+    for e in range(8):
+        L = ref["images"][3 * e: 3 * e + 3]
+        want = oracle.composite(W, H, gz[e], rad, L[0]["rgb"], L[1]["rgb"], L[2]["rgb"])
+        amb, tol = composite_ambiguity(W, H, gz[e], rad, L)
+        err = np.abs(o[e] - want)
+        assert err[:, ~amb].max() <= COLOUR_TOL, e
+        assert_amb_within(err, amb, tol, e)
+    # the layer images of the same batch (stage calls on the same views)
+    ctx.preprocess(ds, views)
+    assert ctx.bin_sort() == ref["keys"].size
+    npx = sum(v.width * v.height for v in views)
+    rgb = torch.full((3 * npx,), float("nan"), device="cuda")
+    T = torch.full((npx,), float("nan"), device="cuda")
+    last = torch.zeros(npx, dtype=torch.int32, device="cuda")
+    ctx.blend(rgb, T, last)
+    ctx.sync()
+    compare_images(views, ref, rgb, T, last, ref["active"])
+    ctx.close()

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import oracle.incremental as oi
 import synth
-from test_gpu_parity import AMB_TOL, COLOUR_TOL, composite_ambiguity
+from test_gpu_parity import COLOUR_TOL, assert_amb_within, composite_ambiguity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -84,9 +84,10 @@ def test_incremental_equals_one_shot_and_oracle(pkg, speculative):
     o = oracle.render_foveated(scene, cams, final, rad)
     img = out.cpu().numpy()
     for e in range(2):
-        d = np.abs(img[e] - o["out"][e]).max(axis=0)
-        amb = composite_ambiguity(W, H, final[e], rad, o["images"][3 * e: 3 * e + 3])
-        assert d[~amb].max() <= COLOUR_TOL and d.max() <= AMB_TOL
+        err = np.abs(img[e] - o["out"][e])
+        amb, tol = composite_ambiguity(W, H, final[e], rad, o["images"][3 * e: 3 * e + 3])
+        assert err.max(axis=0)[~amb].max() <= COLOUR_TOL
+        assert_amb_within(err, amb, tol)
     ctx.close()
 
 
@@ -153,7 +154,9 @@ def test_concurrent_pipeline_frame_is_exact(pkg, load):
     """Algorithm 1 with a stand-in tracker publishing exits at the network's
     latencies (scaled by load, so which rounds run depends on timing): the frame
     is the one-shot frame of the last prediction whatever the rounds were, the
-    rounds follow the exits in order and the finish comes after the last exit."""
+    rounds follow the exits in order and the finish comes after the last exit;
+    the frame also equals the FP64 oracle's frame of the last prediction
+    (colours within 1e-4, ambiguous pixels within their derived tolerance)."""
     from paper_2507_04147_amd import pipeline
     W, H = 464, 480
     scene, cams, trials, sig, rad = _setup(100_000, W, H, 7, 2)
@@ -168,6 +171,14 @@ def test_concurrent_pipeline_frame_is_exact(pkg, load):
         ctx.render_foveated(ds, cams, final, fov, ref)
         ctx.sync()
         assert torch.equal(out, ref)
+        # and the frame against the FP64 oracle's foveated frame of the final gaze
+        o = oracle.render_foveated(scene, cams, final, rad)
+        img = out.cpu().numpy()
+        for e in range(2):
+            err = np.abs(img[e] - o["out"][e])
+            amb, tol = composite_ambiguity(W, H, final[e], rad, o["images"][3 * e: 3 * e + 3])
+            assert err.max(axis=0)[~amb].max() <= COLOUR_TOL
+            assert_amb_within(err, amb, tol)
         ev = res["events"]
         assert ev[0][0] == "round 0" and ev[-1][0] == "finish"
         layers = [e[1] for e in ev[1:]]

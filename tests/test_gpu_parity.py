@@ -5,7 +5,9 @@ rectangles, offsets, keys in emission order, sorted keys and values, tile
 ranges, active tiles, periphery subset, last-contributor index) bit-exact;
 float32 colours within 1e-4 absolute of the FP64 oracle, except on pixels the
 oracle flags as ambiguous (a skip/stop decision inside the float32 error bound
-of its threshold), which are counted and checked at 2e-2.
+of its threshold), which are counted and checked against the tolerance the
+oracle derives for each of them: 1e-4 plus the colour change that reversing
+its near-threshold decisions causes (oracle amb_tol).
 """
 import math
 
@@ -19,7 +21,15 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 COLOUR_TOL = 1e-4
-AMB_TOL = 2e-2
+
+
+def assert_amb_within(err, amb, tol, what=None):
+    """err [3][...] of the ambiguous pixels (mask amb) is within 1e-4 plus each
+    pixel's derived tolerance."""
+    t = np.asarray(tol)[amb]
+    assert np.isfinite(t).all(), what
+    e = err[:, amb]
+    assert (e <= COLOUR_TOL + t[None]).all(), (what, float((e - t[None]).max(initial=0.0)))
 
 
 @pytest.fixture(scope="module")
@@ -125,13 +135,14 @@ def compare_images(views, ref, rgb, T, last, active):
         act = active[ref["aoff"][v]: ref["aoff"][v + 1]].reshape(-1, TX)
         pm = np.kron(act, np.ones((16, 16), np.uint8))[:H, :W].astype(bool)
         amb = ref["amb"][a:b].reshape(H, W).astype(bool) & pm
+        tol = ref["amb_tol"][a:b].reshape(H, W)
         ok = pm & ~amb
         g = rgb[3 * a: 3 * b].reshape(3, H, W)
         o = ref["rgb"][3 * a: 3 * b].reshape(3, H, W)
         err = np.abs(g - o)
         assert np.isfinite(g[:, pm]).all()
         assert err[:, ok].max(initial=0.0) <= COLOUR_TOL, (v, err[:, ok].max())
-        assert err[:, amb].max(initial=0.0) <= AMB_TOL, (v, err[:, amb].max())
+        assert_amb_within(err, amb, tol, v)
         gT = T[a:b].reshape(H, W)
         oT = ref["T"][a:b].reshape(H, W)
         assert np.abs(gT - oT)[ok].max(initial=0.0) <= COLOUR_TOL
@@ -202,16 +213,16 @@ def test_full_render_and_composite_parity(pkg, ctx):
         amb = fr["images"][e]["amb"].astype(bool)
         err = np.abs(out[e].cpu().numpy() - fr["out"][e])
         assert err[:, ~amb].max() <= COLOUR_TOL
-        assert err[:, amb].max(initial=0.0) <= AMB_TOL
+        assert_amb_within(err, amb, fr["images"][e]["amb_tol"])
     fv = oracle.render_foveated(scene, cams, gz, rad)
     outf = torch.zeros((2, 3, H, W), device="cuda")
     ctx.render_foveated(ds, cams, gz, pkg.fovea_struct(*rad), outf)
     ctx.sync()
     for e in range(2):
-        amb = composite_ambiguity(W, H, gz[e], rad, fv["images"][3 * e: 3 * e + 3])
+        amb, tol = composite_ambiguity(W, H, gz[e], rad, fv["images"][3 * e: 3 * e + 3])
         err = np.abs(outf[e].cpu().numpy() - fv["out"][e])
         assert err[:, ~amb].max() <= COLOUR_TOL
-        assert err[:, amb].max(initial=0.0) <= AMB_TOL
+        assert_amb_within(err, amb, tol)
     # the quality judge on the GPU equals the oracle's region sums
     sse, cnt = ctx.region_sse(W, H, gz[0], rad[0], rad[1], outf[0], out[0])
     osse, ocnt = oracle.region_sse(W, H, gz[0], rad, outf[0].cpu().numpy().astype(np.float64),
@@ -221,13 +232,18 @@ def test_full_render_and_composite_parity(pkg, ctx):
 
 
 def composite_ambiguity(W, H, gaze, rad, layers):
-    """Full-resolution pixels whose composite reads an ambiguous layer pixel."""
+    """Full-resolution pixels whose composite reads an ambiguous layer pixel,
+    and their tolerance: the bilinear weights are non-negative and sum to one,
+    so a composite pixel moves by at most the largest tolerance among the layer
+    pixels it reads."""
     ys, xs = np.mgrid[0:H, 0:W]
     px, py = xs + 0.5, ys + 0.5
     r2 = (px - gaze[0]) ** 2 + (py - gaze[1]) ** 2
     out = np.zeros((H, W), bool)
+    tol = np.zeros((H, W))
     f = r2 <= rad[0] ** 2
     out[f] = layers[0]["amb"][f].astype(bool)
+    tol[f] = layers[0]["amb_tol"][f]
     for reg, s, L in ((1, 2, layers[1]), (2, 4, layers[2])):
         sel = (~f & (r2 <= rad[1] ** 2)) if reg == 1 else (r2 > rad[1] ** 2)
         Hl, Wl = H // s, W // s
@@ -236,8 +252,10 @@ def composite_ambiguity(W, H, gaze, rad, layers):
         x0, y0 = np.floor(sx).astype(int), np.floor(sy).astype(int)
         x1, y1 = np.minimum(x0 + 1, Wl - 1), np.minimum(y0 + 1, Hl - 1)
         a = L["amb"].astype(bool)
+        t = L["amb_tol"]
         out[sel] = a[y0, x0] | a[y0, x1] | a[y1, x0] | a[y1, x1]
-    return out
+        tol[sel] = np.maximum(np.maximum(t[y0, x0], t[y0, x1]), np.maximum(t[y1, x0], t[y1, x1]))
+    return out, tol
 
 
 # ---------------------------------------------------------------------------
@@ -354,19 +372,19 @@ def test_full_size_foveated_frame(pkg, ctx):
         TX = (vw.width + 15) // 16
         act = ref["active"][ref["aoff"][v]: ref["aoff"][v + 1]].reshape(-1, TX)
         ys, xs = np.nonzero(np.kron(act, np.ones((16, 16), np.uint8))[: vw.height, : vw.width])
-        pick = rng.choice(ys.size, size=min(150, ys.size), replace=False)
+        pick = rng.choice(ys.size, size=min(300, ys.size), replace=False)
         px, py = xs[pick], ys[pick]
-        o_rgb, o_T, o_amb = oracle.blend_pixels(scene, views, ref, ref["keep"], col, v, px, py)
+        o_rgb, o_T, o_amb, o_tol = oracle.blend_pixels(scene, views, ref, ref["keep"], col, v, px, py)
         HW = vw.width * vw.height
         a = int(ioff[v])
         g = np.stack([rgb_h[3 * a + ch * HW + py * vw.width + px] for ch in range(3)], 1)
         err = np.abs(g - o_rgb)
         ok = o_amb == 0
         assert err[ok].max(initial=0.0) <= COLOUR_TOL, (v, err[ok].max())
-        assert err[~ok].max(initial=0.0) <= AMB_TOL
+        assert_amb_within(err.T, ~ok, o_tol, v)
         assert np.abs(T_h[a + py * vw.width + px] - o_T)[ok].max(initial=0.0) <= COLOUR_TOL
         n_amb += int((~ok).sum())
-    assert n_amb <= 30
+    assert n_amb <= 60
     # composite of the GPU layers: oracle composite (float64) vs the benchmark's output
     L = [rgb_h[3 * int(ioff[v]): 3 * int(ioff[v + 1])].reshape(3, vw.height, vw.width).astype(np.float64)
          for v, vw in enumerate(views)]
@@ -377,8 +395,9 @@ def test_full_size_foveated_frame(pkg, ctx):
 
 
 def test_full_size_full_res_frame_sampled(pkg, ctx):
-    """The plain full-resolution stereo render at full size: per-entry outputs
-    bit-exact, sampled pixels against the brute-force definition."""
+    """The plain full-resolution stereo render at full size (41.8M keys):
+    per-entry outputs and the whole sorted key and value lists bit-exact,
+    400 sampled pixels per eye against the brute-force definition."""
     scene, cams = synth.foveated_stereo()
     views = [oracle.full_view(c, e) for e, c in enumerate(cams)]
     ds = pkg.DeviceScene.from_host(scene)
@@ -387,21 +406,24 @@ def test_full_size_full_res_frame_sampled(pkg, ctx):
     ctx.set_debug(False)
     ctx.render_full(ds, cams, out)
     ctx.sync()
-    act, aoff = oracle.tile_masks(views)
-    pr = oracle.project(scene, views, active=act, aoff=aoff)
+    pr = oracle.render(scene, views, blend=False)
     counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(2, scene.n)
     np.testing.assert_array_equal(counts, pr["count"].astype(np.uint32) * pr["vis"])
-    assert ctx.get_counts()["n_keys"] == int(pr["count"].sum())
+    assert ctx.get_counts()["n_keys"] == int(pr["count"].sum()) == pr["keys"].size
+    np.testing.assert_array_equal(_u(ctx.inspect("sorted_keys", torch.int64), np.uint64), pr["sorted_keys"])
+    np.testing.assert_array_equal(_u(ctx.inspect("sorted_vals", torch.int32), np.uint32), pr["sorted_vals"])
+    np.testing.assert_array_equal(_u(ctx.inspect("ranges", torch.int32), np.uint32).reshape(-1, 2).astype(np.int64),
+                                  pr["ranges"])
     col = oracle.colour(scene, [cams[0].campos, cams[1].campos])
     rng = np.random.default_rng(321)
     o = out.cpu().numpy()
     for e in range(2):
-        px, py = rng.integers(0, W, 200), rng.integers(0, H, 200)
-        o_rgb, o_T, o_amb = oracle.blend_pixels(scene, views, pr, None, col, e, px, py)
+        px, py = rng.integers(0, W, 400), rng.integers(0, H, 400)
+        o_rgb, o_T, o_amb, o_tol = oracle.blend_pixels(scene, views, pr, None, col, e, px, py)
         g = o[e][:, py, px].T
         ok = o_amb == 0
         assert np.abs(g - o_rgb)[ok].max() <= COLOUR_TOL
-        assert np.abs(g - o_rgb)[~ok].max(initial=0.0) <= AMB_TOL
+        assert_amb_within(np.abs(g - o_rgb).T, ~ok, o_tol)
 
 
 @pytest.mark.parametrize("variant", [1, 3, 12, 14])

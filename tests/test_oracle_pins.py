@@ -462,3 +462,54 @@ def test_psnr_closed_forms():
     c = np.full((3, H, W), 1.5)
     d = np.ones((3, H, W))
     assert oracle.periphery_psnr(W, H, (20.0, 16.0), (5.0, 10.0), c, d)[0] == math.inf
+
+
+# --------------------------------------------------------------------------
+# tolerance of ambiguous pixels: the colour change of the reversed decision
+# --------------------------------------------------------------------------
+def test_ambiguity_tolerance_of_a_skip_decision():
+    """A near Gaussian whose alpha at one pixel centre is 1/255 up to float32
+    rounding of its opacity: the pixel is ambiguous, and its tolerance is the
+    closed-form difference between blending that Gaussian and skipping it,
+    max over channels of |a1 (c1 - c2 a2)| (two on-axis Gaussians, bg 0)."""
+    z, sig = (3.0, 2.0), (float(F32(0.09)), float(F32(0.05)))
+    f0 = [(1.2, 0.1, 0.4), (-0.3, 0.9, 0.2)]
+    cam = origin_cam()
+    px, py = 34, 33
+    r2p = (px + 0.5 - cam.cx) ** 2 + (py + 0.5 - cam.cy) ** 2
+    s2n = (cam.fx * sig[1] / z[1]) ** 2 + 0.3
+    o_near = float(F32((1.0 / 255.0) / math.exp(-0.5 * r2p / s2n)))
+    assert o_near < 0.99
+    sc = tiny_scene([(0, 0, z[0]), (0, 0, z[1])], [(s,) * 3 for s in sig], [(1, 0, 0, 0)] * 2, (0.6, o_near), f0)
+    r = oracle.render(sc, [oracle.full_view(cam)])
+    img = r["images"][0]
+    s2f = (cam.fx * sig[0] / z[0]) ** 2 + 0.3
+    a1 = o_near * math.exp(-0.5 * r2p / s2n)
+    a2 = min(0.99, float(F32(0.6)) * math.exp(-0.5 * r2p / s2f))
+    c1, c2 = dc_colour(f0[1]), dc_colour(f0[0])
+    assert abs(a1 - 1 / 255) <= oracle.EPS_ALPHA / 255
+    assert img["amb"][py, px] == 1
+    want = np.max(np.abs(a1 * (c1 - c2 * a2)))
+    np.testing.assert_allclose(img["amb_tol"][py, px], want, rtol=1e-12)
+    # pixels with no near-threshold decision carry no tolerance
+    assert np.all(img["amb_tol"][img["amb"] == 0] == 0.0)
+
+
+def test_ambiguity_tolerance_of_a_stop_decision():
+    """Two opaque on-axis Gaussians (alpha clamped at 0.99): after both,
+    T = (1 - 0.99)^2, which is 1e-4 up to rounding, so the stop decision at
+    the second is ambiguous.  Blending it or stopping before it differ by
+    0.99 (1 - 0.99) c2 + ((1 - 0.99)^2 - (1 - 0.99)) bg, the tolerance."""
+    bg = (0.25, 0.5, 0.75)
+    f0 = [(1.2, 0.1, 0.4), (-0.3, 0.9, 0.2)]
+    sc = tiny_scene([(0, 0, 3.0), (0, 0, 2.0)], [(0.3,) * 3, (0.3,) * 3], [(1, 0, 0, 0)] * 2, (0.999, 0.999), f0)
+    cam = origin_cam(bg=bg)
+    r = oracle.render(sc, [oracle.full_view(cam)])
+    img = r["images"][0]
+    py, px = 31, 31  # pixel centre 0.5 px from the principal point: both alphas clamp
+    c2 = dc_colour(f0[0])
+    t1 = 1.0 - 0.99
+    want = np.max(np.abs(0.99 * t1 * c2 + (t1 * t1 - t1) * np.asarray(bg)))
+    assert img["amb"][py, px] == 1 and img["last"][py, px] == 2
+    np.testing.assert_allclose(img["amb_tol"][py, px], want, rtol=1e-12)
+    assert want > 5e-3  # a stop decision can move a colour far more than 1e-4
