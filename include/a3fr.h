@@ -252,6 +252,23 @@ a3fr_status a3fr_composite(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze, 
 a3fr_status a3fr_region_sse(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze, double r_fovea, double r_mid,
                             const float *a_dev, const float *b_dev, double *sse3, int64_t *count3);
 
+/* For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: a3fr_region_sse with no
+ * device or host allocation and no synchronisation.  The same sums, bit for
+ * bit, written to device memory on the context's stream:
+ * sse3_dev: double[3] and count3_dev: int64_t[3], device pointers owned by the
+ * caller.  The per-block partial sums live in a static device array of the
+ * library (1024 blocks x 3 regions x (8 + 8) bytes = 48 KiB; every GPU the
+ * library runs on holds its own copy until the process ends), which every call
+ * overwrites in full (nothing is cleared).  Calls that overlap on one GPU (on
+ * different streams or contexts) race on that array: serialise them.
+ * Limits: 1 <= W, H and W x H <= A3FR_NOALLOC_MAX_PIXELS, else A3FR_EINVAL
+ * with nothing enqueued. */
+#define A3FR_NOALLOC_MAX_PIXELS 2147483647
+a3fr_status a3fr_region_sse_noalloc(a3fr_ctx *ctx, int32_t W, int32_t H, a3fr_gaze gaze, double r_fovea,
+                                    double r_mid, const float *a_dev, const float *b_dev, double *sse3_dev,
+                                    int64_t *count3_dev);
+
 /* Counters of the last preprocess / bin_sort (host struct). */
 a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
 

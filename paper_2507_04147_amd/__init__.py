@@ -150,6 +150,7 @@ def lib():
         "a3fr_incremental_finish": [P, C.POINTER(Gaze_), P],
         "a3fr_composite": [P, I32, I32, Gaze_, C.POINTER(Fovea_), P, P, P, P, P],
         "a3fr_region_sse": [P, I32, I32, Gaze_, D, D, P, P, C.POINTER(D), C.POINTER(I64)],
+        "a3fr_region_sse_noalloc": [P, I32, I32, Gaze_, D, D, P, P, P, P],
         "a3fr_get_counts": [P, C.POINTER(Counts_)],
         "a3fr_inspect": [P, I32, P, I64, C.POINTER(I64)],
         "a3fr_fp64_probe": [P, P, P, P, P, I64],
@@ -414,6 +415,13 @@ class Context:
                                             float(r_mid), _dp(a), _dp(b), sse, cnt))
         return np.array(sse[:]), np.array(cnt[:])
 
+    def region_sse_noalloc(self, W, H, gaze, r_fovea, r_mid, a, b, sse_dev, count_dev):
+        """a3fr_region_sse_noalloc: sums into device tensors sse_dev (float64 [3])
+        and count_dev (int64 [3]); enqueued on the context's stream, no sync."""
+        self._check(self._L.a3fr_region_sse_noalloc(self._h, W, H, Gaze_(float(gaze[0]), float(gaze[1])),
+                                                    float(r_fovea), float(r_mid), _dp(a), _dp(b), _dp(sse_dev),
+                                                    _dp(count_dev)))
+
     def get_counts(self):
         c = Counts_()
         self._check(self._L.a3fr_get_counts(self._h, C.byref(c)))
@@ -539,4 +547,4 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
             "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
             "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish",
-            "a3fr_render_amr", "a3fr_render_batch"]
+            "a3fr_render_amr", "a3fr_render_batch", "a3fr_region_sse_noalloc"]

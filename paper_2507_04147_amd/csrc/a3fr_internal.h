@@ -260,6 +260,9 @@ void launch_composite_eyes(int n_eyes, int W, int H, double rf, double rm, int s
 void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm, const float *a,
                        const float *b, double *partial /* [nblk][3] */, unsigned long long *cnt /* [nblk][3] */,
                        int nblk, hipStream_t s);
+// the three region sums of the partials of launch_region_sse into device outputs
+void launch_region_sse_sum(const double *partial, const unsigned long long *cnt, int nblk, double *sse3,
+                           int64_t *count3, hipStream_t s);
 void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 constexpr int kFillSegs = 8;

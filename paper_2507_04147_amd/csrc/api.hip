@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdint>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <string>
@@ -22,6 +23,46 @@ struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
 };
+
+// Region sums of the PSNR judge: per-block partials [kSseParts][3] float64,
+// then [kSseParts][3] uint64 pixel counts.
+constexpr int kSseParts = 1024;
+constexpr size_t kSseScratchBytes = (size_t)kSseParts * 3 * (sizeof(double) + sizeof(unsigned long long));
+
+}  // namespace
+
+// Scratch of a3fr_region_sse_noalloc: a static device array (one copy per GPU,
+// kept until the process ends), so that entry point allocates nothing.  In host
+// code the name stands for a host-side handle, not a device address: kernels
+// and copies take the address hipGetSymbolAddress returns for each device.
+static __device__ __align__(256) unsigned char scratch[kSseScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of scratch on device dev, looked up once per device with that
+// device current (it is made current for the lookup and restored after).
+hipError_t scratch_on_device(int dev, void **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -306,6 +347,13 @@ a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         c->n_cus = cus;
     (void)hipGetLastError();
+    {   // the scratch of the allocation-free entry point on the context's device
+        hipDevice_t sdev = 0;
+        void *p = nullptr;
+        if (hipStreamGetDevice(c->stream, &sdev) != hipSuccess || scratch_on_device((int)sdev, &p) != hipSuccess) {
+            (void)hipGetLastError();  // a later call of that entry point retries and reports
+        }
+    }
     *out = c;
     return A3FR_OK;
 }
@@ -1595,7 +1643,7 @@ a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, doub
                             const float *b, double *sse3, int64_t *count3) {
     if (!c) return A3FR_EINVAL;
     if (W <= 0 || H <= 0 || !a || !b || !sse3 || !count3) return fail(c, A3FR_EINVAL, "region_sse: bad arguments");
-    const int nblk = 1024;
+    const int nblk = kSseParts;
     TRY(ensure(c, c->sse_part, sizeof(double) * 3 * nblk));
     TRY(ensure(c, c->sse_cnt, sizeof(unsigned long long) * 3 * nblk));
     launch_region_sse(W, H, g.x, g.y, rf, rm, a, b, P<double>(c->sse_part), P<unsigned long long>(c->sse_cnt), nblk,
@@ -1615,6 +1663,27 @@ a3fr_status a3fr_region_sse(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, doub
         count3[r] = k;
     }
     return A3FR_OK;
+}
+
+a3fr_status a3fr_region_sse_noalloc(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, double rf, double rm,
+                                    const float *a, const float *b, double *sse3_dev, int64_t *count3_dev) {
+    if (!c) return A3FR_EINVAL;
+    if (W <= 0 || H <= 0 || !a || !b || !sse3_dev || !count3_dev)
+        return fail(c, A3FR_EINVAL, "region_sse_noalloc: bad arguments");
+    if ((int64_t)W * H > (int64_t)A3FR_NOALLOC_MAX_PIXELS)
+        return fail(c, A3FR_EINVAL, "region_sse_noalloc: W x H = " + std::to_string((int64_t)W * H) +
+                                        " exceeds the maximum of " + std::to_string((int64_t)A3FR_NOALLOC_MAX_PIXELS) +
+                                        " pixels");
+    hipDevice_t dev = 0;
+    HIPCHECK(c, hipStreamGetDevice(c->stream, &dev));
+    void *p = nullptr;
+    HIPCHECK(c, scratch_on_device((int)dev, &p));
+    double *part = static_cast<double *>(p);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(part + 3 * kSseParts);
+    // every block writes its own partial slot: nothing to clear
+    launch_region_sse(W, H, g.x, g.y, rf, rm, a, b, part, cnt, kSseParts, c->stream);
+    launch_region_sse_sum(part, cnt, kSseParts, sse3_dev, count3_dev, c->stream);
+    return check_launch(c, "region_sse_noalloc");
 }
 
 // Keys of the last bin_sort: known on the host in exact mode, read from the

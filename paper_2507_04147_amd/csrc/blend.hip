@@ -1016,6 +1016,28 @@ void launch_region_sse(int W, int H, double gx, double gy, double rf, double rm,
     hipLaunchKernelGGL(k_region_sse, dim3((unsigned)nblk), dim3(256), 0, s, W, H, gx, gy, rf, rm, a, b, partial, cnt);
 }
 
+// Sums of the per-block partials of k_region_sse, on the device: one lane per
+// region adds the blocks' values in block order, as a3fr_region_sse's host loop
+// does, so both give the same bits.
+__global__ void k_region_sse_sum(const double *__restrict__ partial, const unsigned long long *__restrict__ cnt,
+                                 int nblk, double *sse3, int64_t *count3) {
+    const int r = threadIdx.x;
+    if (r >= 3) return;
+    double s = 0.0;
+    unsigned long long k = 0;
+    for (int j = 0; j < nblk; ++j) {
+        s += partial[3 * j + r];
+        k += cnt[3 * j + r];
+    }
+    sse3[r] = s;
+    count3[r] = (int64_t)k;
+}
+
+void launch_region_sse_sum(const double *partial, const unsigned long long *cnt, int nblk, double *sse3,
+                           int64_t *count3, hipStream_t s) {
+    hipLaunchKernelGGL(k_region_sse_sum, dim3(1), dim3(64), 0, s, partial, cnt, nblk, sse3, count3);
+}
+
 // ------------------------------------------------------------------------
 // float64 self-check
 // ------------------------------------------------------------------------
