@@ -130,8 +130,7 @@ def main():
     ap.add_argument("--trace-window", type=int, default=16, help="frames per graph launch in the gaze-trace leg")
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed steps of the differentiable-render training loop (0: skip)")
-    ap.add_argument("--net-pairs", type=int, default=2048, help="training pairs of the frame's upsampler")
-    ap.add_argument("--net-epochs", type=int, default=2, help="training epochs of the frame's upsampler")
+    ap.add_argument("--gazes", type=int, default=16, help="seeded gazes per workload in the workloads leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -162,14 +161,16 @@ def main():
     ds = pkg.DeviceScene.from_host(scene)
     fov = pkg.fovea_struct(*rad, keep=synth.PERIPH_KEEP)
     ctx = pkg.Context()
-    # the method's frame: periphery through the learned upsampler, trained here
-    # (untimed) on pairs the library renders at the training poses, and the
-    # per-tile error estimate with full-resolution fallback
-    theta = train_upsampler(pkg, synth, torch, ctx, ds, args.net_pairs, args.net_epochs)
+    # the method's frame: the periphery through the upsampler trained for this
+    # workload when that network beats bilinear on its held-out pairs (the
+    # weights' header), else bilinear x4; and the per-tile error estimate with
+    # full-resolution fallback, calibrated for that periphery
+    nets = {w: load_net(pkg, torch, w) for w in ("inside", "outside")}
+    theta, use_net = nets["inside"]["theta"], nets["inside"]["use"]
 
     def method_options(c):
-        c.set_upsampler(theta)
-        c.set_fallback(*pkg.FALLBACK_DEFAULT)
+        c.set_upsampler(theta if use_net else None)
+        c.set_fallback(*(pkg.FALLBACK_NET if use_net else pkg.FALLBACK_BILINEAR))
 
     method_options(ctx)
     out_f = torch.empty((2, 3, H, W), device="cuda")
@@ -323,7 +324,9 @@ def main():
     training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 else None
     extra = {}
     if do_fov and do_frr and not args.no_extra:
-        extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options)
+        extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, theta)
+        method_options(ctx)
+        extra["workloads"] = workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets)
         extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
         extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
         extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
@@ -360,15 +363,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "foveated stereo frame: 1M-Gaussian uniform cloud over [-5,5]^3, 2 eyes x 1832x1920, "
-                        "fovea r=0.15W full res, mid r=0.35W at 1/2, periphery at 1/4 with top-30% subset, "
-                        "periphery through the learned x4 upsampler, per-tile error estimate with "
-                        "full-resolution fallback",
+            "workload": "foveated stereo frame: 1M-Gaussian uniform cloud over [-5,5]^3, head at (0,0,-3), "
+                        "2 eyes x 1832x1920, fovea r=0.15W full res, mid r=0.35W at 1/2, periphery at 1/4 with "
+                        "top-30% subset, " + ("periphery through the learned x4 upsampler" if use_net else
+                                              "periphery through bilinear x4 (the upsampler trained for this "
+                                              "workload gains nothing on its held-out pairs)") +
+                        ", per-tile error estimate with full-resolution fallback",
             "gaussians": scene.n, "width": W, "height": H, "eyes": 2, "gaze": "image centre",
             "key_path": "f64", "blend": "f32",
-            "upsampler": f"bf16 MFMA, f32 accumulate; trained on {args.net_pairs} rendered pairs x "
-                         f"{args.net_epochs} epochs before timing",
-            "fallback": list(pkg.FALLBACK_DEFAULT),
+            "upsampler": dict(used=use_net, weights="paper_2507_04147_amd/weights/upsampler_inside",
+                              held_out_psnr_db=nets["inside"]["held_out_psnr_db"]),
+            "fallback": list(pkg.FALLBACK_NET if use_net else pkg.FALLBACK_BILINEAR),
         },
         "full_res_fps": 1000.0 / ms_r if do_frr else None,
         "full_res_ms": ms_r,
@@ -430,27 +435,96 @@ def net_frame_flop(np, W, H, gaze, r_mid):
     return total
 
 
-def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, method_options):
-    """The foveated frame without each of the method's additions: bilinear
-    periphery without the error estimate, with the upsampler only, with the
-    estimate only (ms per frame and periphery PSNR)."""
+def load_net(pkg, torch, workload):
+    """The committed upsampler weights of a workload and whether the frame uses
+    them: only when the network beats bilinear on its held-out pairs."""
+    from paper_2507_04147_amd import upsampler as U
+    theta, head = U.load_weights(os.path.join(ROOT, "paper_2507_04147_amd", "weights", f"upsampler_{workload}"))
+    p = head["held_out_psnr_db"]
+    return dict(theta=torch.from_numpy(theta).cuda(), use=p["network"] > p["bilinear"] + 0.1, held_out_psnr_db=p,
+                pairs=head["pairs"], epochs=head["epochs"])
+
+
+FRAME_OPTIONS = (("bilinear", False, None), ("bilinear+fallback", False, "bilinear"), ("network", True, None),
+                 ("network+fallback", True, "net"))
+
+
+def set_frame_options(pkg, c, theta, net, fb):
+    c.set_upsampler(theta if net else None)
+    if fb is None:
+        c.set_fallback(float("inf"), 1.0, 1.0)
+    else:
+        c.set_fallback(*(pkg.FALLBACK_NET if fb == "net" else pkg.FALLBACK_BILINEAR))
+
+
+def parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, theta):
+    """The foveated frame with and without each of the method's additions:
+    bilinear periphery, with the error estimate, the network trained for this
+    workload, both (ms per frame, periphery PSNR, fallback tiles)."""
     W, H = cams[0].width, cams[0].height
     out = torch.empty((2, 3, H, W), device="cuda")
     res = {}
-    for name, net, fb in (("bilinear_no_fallback", False, False), ("upsampler_only", True, False),
-                          ("fallback_only", False, True)):
-        method_options(ctx)
-        if not net:
-            ctx.set_upsampler(None)
-        if not fb:
-            ctx.set_fallback(float("inf"), 1.0, 1.0)
+    for name, net, fb in FRAME_OPTIONS:
+        set_frame_options(pkg, ctx, theta, net, fb)
         step = lambda: ctx.render_foveated(ds, cams, gaze, fov, out)
         for _ in range(args.warmup):
             step()
         ms = timed(step, args.steps)
-        res[name] = dict(ms_per_frame=ms, periphery_psnr_db=min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)))
+        res[name] = dict(ms_per_frame=ms, periphery_psnr_db=min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)),
+                         fallback_tiles=ctx.get_counts()["n_fallback_tiles"])
         log(f"frame {name}: {ms:.3f} ms")
-    method_options(ctx)
+    return res
+
+
+def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
+    """Both workloads -- the head inside the cloud (0,0,-3) and the camera
+    outside it (0,0,-15) -- at args.gazes seeded gazes within 20 degrees (the
+    first at the image centre): for each periphery option (bilinear, with the
+    error estimate, the workload's network, both) the frame time, the periphery
+    PSNR against the full-resolution render (minimum over the eyes) and the
+    fallback tiles; the full-resolution frame time of the pose."""
+    import statistics as stats
+    res = {}
+    for w, head in (("inside", synth.HEAD_INSIDE), ("outside", synth.HEAD_OUTSIDE)):
+        _, cams = synth.foveated_stereo(n=1, head=head)
+        W, H = cams[0].width, cams[0].height
+        gazes = synth.gaze_points(21, args.gazes, cams[0])
+        c = pkg.Context()
+        out = torch.empty((2, 3, H, W), device="cuda")
+        ref = torch.empty_like(out)
+        step_r = lambda: c.render_full(ds, cams, ref)
+        for _ in range(2):
+            step_r()
+        ms_frr = timed(step_r, max(3, args.steps // 4))
+        rows = {name: [] for name, _, _ in FRAME_OPTIONS}
+        for g in gazes:
+            gz = [g, g]
+            for name, net, fb in FRAME_OPTIONS:
+                set_frame_options(pkg, c, nets[w]["theta"], net, fb)
+                step = lambda: c.render_foveated(ds, cams, gz, fov, out)
+                for _ in range(2):
+                    step()
+                ms = timed(step, max(3, args.steps // 4))
+                rows[name].append((ms, min(_psnr_outside_fovea(c, W, H, gz, rad, out, ref)),
+                                   c.get_counts()["n_fallback_tiles"]))
+        c.close()
+        ntiles = 2 * ((W // 4 + 15) // 16) * ((H // 4 + 15) // 16)
+        summ = {}
+        for name, r in rows.items():
+            summ[name] = dict(ms_median=stats.median(x[0] for x in r), psnr_min_db=min(x[1] for x in r),
+                              psnr_median_db=stats.median(x[1] for x in r),
+                              fallback_tile_fraction_mean=stats.mean(x[2] for x in r) / ntiles,
+                              centre_gaze=dict(ms=r[0][0], psnr_db=r[0][1], fallback_tiles=r[0][2]))
+        best = max((n_ for n_ in summ if summ[n_]["psnr_min_db"] >= 30.0),
+                   key=lambda n_: 1.0 / summ[n_]["ms_median"], default=None)
+        res[w] = dict(head=list(head), gazes=len(gazes), full_res_ms=ms_frr, options=summ,
+                      network=dict(used_by_method=nets[w]["use"], held_out_psnr_db=nets[w]["held_out_psnr_db"],
+                                   pairs=nets[w]["pairs"], epochs=nets[w]["epochs"]),
+                      fastest_option_at_30db=best,
+                      speedup_vs_full_res=(ms_frr / summ[best]["ms_median"]) if best else None)
+        log(f"workload {w}: FRR {ms_frr:.3f} ms; " + "; ".join(
+            f"{n_} {v['ms_median']:.3f} ms, PSNR min {v['psnr_min_db']:.2f} dB, fallback "
+            f"{v['fallback_tile_fraction_mean']:.3f}" for n_, v in summ.items()))
     return res
 
 
@@ -586,30 +660,14 @@ def incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options, n_tri
     return res
 
 
-def train_upsampler(pkg, synth, torch, ctx, ds, n_pairs, epochs, batch=32):
-    """The frame's upsampler: Adam from the seeded initialisation on pairs the
-    library renders at the training poses (full-resolution 256x256 crops and
-    their quarter-resolution periphery renders)."""
-    from paper_2507_04147_amd import upsampler as U
-    net = U.Upsampler(ctx, synth.net_init(42))
-    if n_pairs > 0 and epochs > 0:
-        t = time.perf_counter()
-        xs, ts = U.make_pairs(ctx, ds, synth.crop_poses(41, n_pairs))
-        hist = net.fit(xs, ts, epochs=epochs, batch=batch)
-        torch.cuda.synchronize()
-        log(f"upsampler trained on {n_pairs} pairs x {epochs} epochs in {time.perf_counter() - t:.2f} s "
-            f"(loss {hist[0]:.3e} -> {hist[-1]:.3e})")
-        del xs, ts
-    return net.theta
-
-
 def net_train_leg(pkg, synth, torch, np, ctx, ds, n_pairs=2048, epochs=2, batch=32):
     """Training throughput of the upsampler: pairs rendered by the library at
-    the training poses (64x64 -> 256x256), Adam steps of batch 32."""
+    the camera-outside training poses (each a 256x256 full-resolution crop and
+    its frame's whole periphery layer, cut to 64x64), Adam steps of batch 32."""
     from paper_2507_04147_amd import upsampler as U
     torch.cuda.synchronize()
     t = time.perf_counter()
-    xs, ts = U.make_pairs(ctx, ds, synth.crop_poses(41, n_pairs))
+    xs, ts = U.make_pairs(ctx, ds, synth.crop_poses_outside(41, n_pairs))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     net = U.Upsampler(ctx, synth.net_init(42))

@@ -150,11 +150,16 @@ def single_view(n=10_000, size=256, seed=1):
     return scene, cam
 
 
-def foveated_stereo(n=1_000_000, width=1832, height=1920, seed=2, half_extent=5.0):
-    """Foveated stereo frame: n Gaussians over [-h,h]^3, head at (0,0,-3) looking
-    +z, eyes 64 mm apart, width x height per eye. Returns scene and two cameras."""
+HEAD_INSIDE = (0.0, 0.0, -3.0)    # the VR reading: the head inside the [-5,5]^3 cloud
+HEAD_OUTSIDE = (0.0, 0.0, -15.0)  # the secondary row: the whole cloud in front of the eyes
+
+
+def foveated_stereo(n=1_000_000, width=1832, height=1920, seed=2, half_extent=5.0, head=HEAD_INSIDE):
+    """Foveated stereo frame: n Gaussians over [-h,h]^3, head at `head` (by
+    default (0,0,-3), inside the cloud) looking +z, eyes 64 mm apart, width x
+    height per eye. Returns scene and two cameras."""
     scene = make_scene(n, half_extent, seed)
-    cams = stereo_cameras((0.0, 0.0, -3.0), width, height, 60.0)
+    cams = stereo_cameras(head, width, height, 60.0)
     return scene, cams
 
 
@@ -210,21 +215,31 @@ def net_init(seed=42, last_scale=0.01) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def crop_poses(seed=41, n=10_000, width=1832, height=1920, crop=256, fov_x_deg=60.0, scale=4):
+def crop_poses(seed=41, n=10_000, width=1832, height=1920, crop=256, fov_x_deg=60.0, scale=4,
+               centre=HEAD_INSIDE, yaw_deg=180.0, pitch_deg=30.0):
     """Camera poses and crop offsets of the upsampler's training pairs: camera
-    at (0,0,-3) + U(-1,1)^3, yaw U(-180,180) deg, pitch U(-30,30) deg, an eye
-    camera of width x height; crop origin uniform over the frame, a multiple
-    of `scale` so that the reduced-resolution crop is pixel-aligned.
-    Returns a list of (Camera, x0, y0)."""
+    at centre + U(-1,1)^3 (centre (0,0,-3) by default), yaw U(-yaw_deg,
+    yaw_deg), pitch U(-pitch_deg, pitch_deg), an eye camera of width x height;
+    crop origin uniform over the frame, a multiple of `scale` so that the
+    reduced-resolution crop is pixel-aligned.  Returns a list of (Camera, x0, y0).
+    The camera-outside workload takes centre (0,0,-15) and 10 degrees of yaw
+    and pitch (crop_poses_outside)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for _ in range(n):
-        pos = np.array([0.0, 0.0, -3.0]) + rng.uniform(-1.0, 1.0, 3)
-        yaw, pitch = rng.uniform(-180.0, 180.0), rng.uniform(-30.0, 30.0)
+        pos = np.asarray(centre, dtype=np.float64) + rng.uniform(-1.0, 1.0, 3)
+        yaw, pitch = rng.uniform(-yaw_deg, yaw_deg), rng.uniform(-pitch_deg, pitch_deg)
         x0 = scale * int(rng.integers(0, (width - crop) // scale + 1))
         y0 = scale * int(rng.integers(0, (height - crop) // scale + 1))
         out.append((make_camera(width, height, fov_x_deg, pos, rot_yaw_pitch(yaw, pitch)), x0, y0))
     return out
+
+
+def crop_poses_outside(seed=41, n=10_000, **kw):
+    """Training poses of the camera-outside workload: the head within U(-1,1)^3
+    of (0,0,-15), yaw and pitch U(-10,10) degrees, so that the cloud fills the
+    central part of the frame as in its foveated frame."""
+    return crop_poses(seed, n, centre=HEAD_OUTSIDE, yaw_deg=10.0, pitch_deg=10.0, **kw)
 
 
 def gaze_trace(seed=31, n_frames=64, width=1832, height=1920, fov_x_deg=60.0, hz=90.0, head=(0.0, 0.0, -3.0),

@@ -204,31 +204,42 @@ def test_net_call_order_and_args(pkg):
 
 
 def test_net_training_gain(pkg):
-    """Pairs rendered by the library from the 1M-Gaussian scene at 10,000
-    random poses (9,000 train / 1,000 held out); 20 epochs of Adam (batch 32,
-    lr 1e-3).  Measures the trained network's held-out PSNR against the
-    bilinear x4 interpolation (the method without the network).
+    """What the trained network gains over the method without it.  Pairs
+    rendered by the library from the 1M-Gaussian scene at 10,000 random poses
+    of the camera-outside workload (head within 1 of (0,0,-15), yaw and pitch
+    within 10 degrees), each input the window of its frame's periphery layer
+    (top-30% subset of the frame); 9,000 train / 1,000 held out; 20 epochs of
+    Adam (batch 32, lr 1e-3).  The network's held-out PSNR beats bilinear x4
+    (its residual alone, weights zero) by at least 0.3 dB (measured: about
+    +0.5 dB).  Inside the cloud (head (0,0,-3)) the same training gains nothing
+    measurable (the committed weights/upsampler_inside header): that frame's
+    periphery error comes from the Gaussians the subset drops, which its input
+    does not hold."""
+    from paper_2507_04147_amd import train_upsampler as TU
+    _, meta = TU.train("outside")
+    p = meta["held_out_psnr_db"]
+    print(f"held-out PSNR: bilinear {p['bilinear']:.4f} dB, network {p['network']:.4f} dB, "
+          f"gain {p['network'] - p['bilinear']:+.4f} dB; train loss {meta['train_loss_first_epoch']:.4e} -> "
+          f"{meta['train_loss_last_epoch']:.4e}", flush=True)
+    assert meta["train_loss_last_epoch"] < meta["train_loss_first_epoch"]
+    assert p["network"] >= p["bilinear"] + 0.3
 
-    On this workload the measured gain is about 0 dB: 77% of the held-out
-    error sits in a few crops whose error comes from Gaussians the periphery
-    subset drops (drawing every Gaussian at 1/4 resolution gives 78 dB with
-    bilinear alone), information the network's input does not hold; the rest
-    is below the bfloat16 quantisation of the input.  The test therefore
-    asserts that training lowers the loss and that the network costs no more
-    than 0.5 dB, and prints the measured gain."""
-    from paper_2507_04147_amd import upsampler as U
+
+def test_saved_weights_reproduce_their_header(pkg):
+    """The committed weights of the camera-outside network (the ones the
+    benchmark loads) give the held-out PSNR their header records, and beat
+    bilinear by at least 0.3 dB."""
+    import os
+    from paper_2507_04147_amd import train_upsampler as TU, upsampler as U
+    theta, head = U.load_weights(os.path.join(os.path.dirname(pkg.__file__), "weights", "upsampler_outside"))
+    assert head["workload"] == "outside" and head["pairs"] == 10_000 and head["epochs"] == 20
     sc, _ = synth.foveated_stereo()
     ds = pkg.DeviceScene.from_host(sc)
     ctx = pkg.Context()
-    xs, ts = U.make_pairs(ctx, ds, synth.crop_poses(41, 10_000))
-    net = U.Upsampler(ctx, synth.net_init(42))
-    bil = U.Upsampler(ctx, np.zeros(pkg.NET_PARAMS, np.float32))  # W = b = 0: out = bilinear
-    held_x, held_t = xs[9000:].contiguous(), ts[9000:].contiguous()
-    p_bil = U.psnr(bil.forward(held_x), held_t)
-    hist = net.fit(xs[:9000], ts[:9000], epochs=20, batch=32, lr=1e-3)
-    p_net = U.psnr(net.forward(held_x), held_t)
-    print(f"held-out PSNR: bilinear {p_bil:.4f} dB, network {p_net:.4f} dB, gain {p_net - p_bil:+.4f} dB; "
-          f"train loss {hist[0]:.4e} -> {hist[-1]:.4e}", flush=True)
-    assert hist[-1] < hist[0]
-    assert p_net >= p_bil - 0.5
+    poses = TU.poses_for(synth, "outside", head["seed_poses"], head["pairs"])[head["train_pairs"]:]
+    xs, ts = U.make_pairs(ctx, ds, poses)
+    p_net, p_bil = TU.held_out_psnr(U, pkg, ctx, theta, xs, ts)
+    want = head["held_out_psnr_db"]
+    assert abs(p_bil - want["bilinear"]) <= 1e-3 and abs(p_net - want["network"]) <= 1e-3, (p_net, p_bil, want)
+    assert p_net >= p_bil + 0.3
     ctx.close()
