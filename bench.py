@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed steps of the differentiable-render training loop (0: skip)")
     ap.add_argument("--gazes", type=int, default=16, help="seeded gazes per workload in the workloads leg")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated extra legs to run (parts, workloads, incremental, amr, pipeline, "
+                         "net_training, trace, training) or 'all'")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -321,17 +324,27 @@ def main():
         log(f"profiled pass {ms_f_prof:.3f} ms/frame; stages: " +
             ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
 
-    training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 else None
+    legs = set(args.legs.split(",")) if args.legs != "all" else {"parts", "workloads", "incremental", "amr", "pipeline",
+                                                                "net_training", "trace", "training"}
+    training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 and "training" in legs \
+        else None
     extra = {}
     if do_fov and do_frr and not args.no_extra:
-        extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, theta)
-        method_options(ctx)
-        extra["workloads"] = workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets)
-        extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
-        extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
-        extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
-        extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
-        extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
+        if "parts" in legs:
+            extra["frame_parts"] = parts_leg(pkg, torch, ctx, ds, cams, gaze, rad, fov, out_r, args, timed, theta)
+            method_options(ctx)
+        if "workloads" in legs:
+            extra["workloads"] = workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets)
+        if "incremental" in legs:
+            extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
+        if "amr" in legs:
+            extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
+        if "pipeline" in legs:
+            extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
+        if "net_training" in legs:
+            extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
+        if "trace" in legs:
+            extra["gaze_trace"] = trace_leg(pkg, synth, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline and do_fov:
@@ -528,15 +541,25 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
     return res
 
 
-def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=4, loads=(1.0, 2.0)):
-    """Algorithm 1: a stand-in gaze tracker publishes the early-exit predictions
-    at the network's per-exit CPU latencies (Table 2, Orin CPU; load scales
-    them, standing for a busier CPU) while this GPU renders round 0 at once and
-    then incremental rounds on the newest prediction.  Latency with sensing and
-    transfer T_s = 1 ms, T_c = 1 ms (Sec. 3.1): T_s + T_c + max(T_d, T_r)
-    against the sequential T_s + T_c + T_d + T_r (the foveated frame rendered
-    after the last prediction).  The tracker's times are the paper's, not this
-    host's: the figures say how much of the rendering the GPU hides."""
+def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=6, tracker_threads=8):
+    """Algorithm 1 with the early-exit ViT (random weights, 640 x 400 eye
+    image) running on this host's CPU beside the renderer, which renders round
+    0 at once and then incremental rounds on the newest prediction; the
+    renderer's waits sleep (a3fr_set_host_wait) so that the tracker keeps the
+    CPU.  Latency with sensing and transfer T_s = T_c = 1 ms (Sec. 3.1):
+    T_s + T_c + max(T_d, T_r) against the sequential T_s + T_c + T_d + T_r,
+    with T_d the tracker alone and T_r the foveated frame rendered after the
+    last prediction (medians over trials).
+      * per pruning ratio 0 / 10% / 20% of tokens per block;
+      * the paper's load experiment (Sec. 4.5): processes taking the CPU with
+        utilisation alternating between 50% and 100% every 0.1 s, A3FR with
+        and without speculative rounds (without: after a round the renderer
+        waits for the next prediction);
+      * a stand-in tracker publishing at the paper's per-exit latencies
+        (Table 2, Orin CPU).
+    The tracker is a process of its own (Algorithm 1's two processes: it shares
+    no interpreter lock with the renderer) on tracker_threads CPU threads in
+    both pipelines, leaving the renderer's host thread a core."""
     import statistics as stats
     from paper_2507_04147_amd import pipeline
     W, H = cams[0].width, cams[0].height
@@ -544,52 +567,73 @@ def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=4, l
     c = pkg.Context()
     method_options(c)
     c.set_fallback(float("inf"), 1.0, 1.0)
+    c.set_host_wait(True)
     out = torch.empty((2, 3, H, W), device="cuda")
     t_sc = 2.0
-    res = {}
-    for load in loads:
+
+    def frame_ms(final):
+        t = time.perf_counter()
+        c.render_foveated(ds, cams, final, fov, out)
+        c.sync()
+        return (time.perf_counter() - t) * 1000.0
+
+    def measure(tracker, speculative=True, exit_ms=None):
+        """Medians over the trials; tracker: a TrackerProcess (the ViT in its own
+        process) or None (the stand-in publishing at exit_ms)."""
         rows = []
         for final, exits in trials:
-            r = pipeline.run(c, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
-                             torch.cuda.synchronize, load=load, out=out)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            c.render_foveated(ds, cams, final, fov, out)
-            torch.cuda.synchronize()
-            sfr = (time.perf_counter() - t) * 1000.0
-            t_d = r["exit_ms"][-1]
-            rows.append(dict(t_d=t_d, done=r["render_done_ms"], after_last=r["render_done_ms"] - t_d, sfr=sfr,
+            if tracker is not None:
+                t = time.perf_counter()
+                t_d = (tracker.run_alone(len(exits) + 1)[-1] - t) * 1000.0
+            else:
+                t_d = exit_ms[-1]
+            sfr = frame_ms(final)
+            if tracker is not None:
+                r = pipeline.run_process(c, ds, cams, fov, exits, final, sig, tracker, out=out,
+                                         speculative=speculative)
+            else:
+                r = pipeline.run(c, ds, cams, fov, exits, final, sig, exit_ms, out=out, speculative=speculative)
+            rows.append(dict(t_d=t_d, beside=r["exit_ms"][-1], done=r["render_done_ms"], sfr=sfr,
                              rounds=len(r["events"]) - 2))
         med = lambda k: stats.median(x[k] for x in rows)
         a3fr, seq = t_sc + med("done"), t_sc + med("t_d") + med("sfr")
-        res[f"load_{load:g}"] = dict(tracker_ms=med("t_d"), render_after_last_prediction_ms=med("after_last"),
-                                     sequential_render_ms=med("sfr"), total_latency_ms=a3fr,
-                                     sequential_total_latency_ms=seq, speedup=seq / a3fr,
-                                     incremental_rounds=med("rounds"))
-        log(f"Algorithm 1, load {load:g}: total {a3fr:.2f} ms vs sequential {seq:.2f} ms "
-            f"(rendering left after the last prediction {med('after_last'):.3f} ms)")
-    sfr_ms = med("sfr")
-    # the tracker as a network on this host's CPU: the early-exit ViT (random
-    # weights, 640 x 400 eye image) with tokenwise pruning 0 / 10% / 20%
-    from paper_2507_04147_amd import gaze_vit as gv
-    img = torch.rand(1, 1, 400, 640, generator=torch.Generator().manual_seed(5))
+        return dict(tracker_alone_ms=med("t_d"), tracker_beside_renderer_ms=med("beside"),
+                    render_after_last_prediction_ms=med("done") - med("beside"), sequential_render_ms=med("sfr"),
+                    total_latency_ms=a3fr, sequential_total_latency_ms=seq, speedup=seq / a3fr,
+                    incremental_rounds=med("rounds"))
+
+    for _ in range(2):  # warm-up of the frame and the network
+        frame_ms(trials[0][0])
+    threads = min(tracker_threads, torch.get_num_threads())
+    res = dict(tracker_threads=threads, host_threads=torch.get_num_threads())
     vit = {}
     for prune in (0.0, 0.1, 0.2):
-        net = gv.EarlyExitViT(prune=prune, seed=5)
-        lat = gv.exit_latencies(net, img, reps=3)
-        runs = []
-        for final, exits in trials:
-            r = pipeline.run(c, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
-                             torch.cuda.synchronize, out=out, network=net, eye_image=img)
-            runs.append((r["exit_ms"][-1], r["render_done_ms"]))
-        t_d, done = stats.median(x[0] for x in runs), stats.median(x[1] for x in runs)
-        vit[f"prune_{prune:g}"] = dict(cpu_threads=torch.get_num_threads(), exit_ms_alone=lat,
-                                       tracker_ms_beside_renderer=t_d, total_latency_ms=t_sc + done,
-                                       sequential_total_latency_ms=t_sc + lat[-1] + sfr_ms,
-                                       render_after_last_prediction_ms=done - t_d)
-        log(f"early-exit ViT on the CPU (prune {prune:g}): exits {[round(x, 2) for x in lat]} ms; Algorithm 1 "
-            f"total {t_sc + done:.2f} ms")
+        tr = pipeline.TrackerProcess(prune=prune, seed=5, threads=threads)
+        try:
+            tr.run_alone(6)
+            vit[f"prune_{prune:g}"] = m = measure(tr)
+        finally:
+            tr.close()
+        log(f"Algorithm 1, ViT on the CPU (prune {prune:g}): total {m['total_latency_ms']:.2f} ms vs sequential "
+            f"{m['sequential_total_latency_ms']:.2f} ms (tracker {m['tracker_alone_ms']:.2f} ms alone, "
+            f"{m['tracker_beside_renderer_ms']:.2f} ms beside the renderer)")
     res["cpu_tracker"] = vit
+    tr = pipeline.TrackerProcess(prune=0.0, seed=5, threads=threads)
+    try:
+        tr.run_alone(6)
+        with pipeline.CpuLoad(torch.get_num_threads()):
+            spec = measure(tr, speculative=True)
+            nospec = measure(tr, speculative=False)
+    finally:
+        tr.close()
+    res["cpu_load_50_100"] = dict(load_processes=torch.get_num_threads(), period_s=0.1, speculative=spec,
+                                  without_speculative=nospec)
+    log(f"Algorithm 1 under CPU load (50%/100% every 0.1 s): total {spec['total_latency_ms']:.2f} ms with "
+        f"speculative rounds, {nospec['total_latency_ms']:.2f} ms without; sequential "
+        f"{spec['sequential_total_latency_ms']:.2f} ms")
+    res["stand_in_table2"] = m = measure(None, exit_ms=list(synth.EXIT_LATENCY_MS))
+    log(f"Algorithm 1, stand-in tracker at the paper's exit latencies: total {m['total_latency_ms']:.2f} ms vs "
+        f"sequential {m['sequential_total_latency_ms']:.2f} ms")
     c.close()
     return res
 

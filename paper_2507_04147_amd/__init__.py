@@ -141,6 +141,7 @@ def lib():
         "a3fr_set_stream": [P, P],
         "a3fr_set_debug": [P, I32],
         "a3fr_sync": [P],
+        "a3fr_set_host_wait": [P, I32],
         "a3fr_preprocess": [P, C.POINTER(Scene_), C.POINTER(View_), I32, I32, I32],
         "a3fr_bin_sort": [P, C.POINTER(I64)],
         "a3fr_blend": [P, P, P, P],
@@ -332,6 +333,10 @@ class Context:
             raise A3FRError(st, msg or self._L.a3fr_status_str(st).decode())
 
     # ---- C entry points ----
+    def set_host_wait(self, blocking=True):
+        """a3fr_set_host_wait: library waits sleep (blocking) or poll."""
+        self._check(self._L.a3fr_set_host_wait(self._h, 1 if blocking else 0))
+
     def set_debug(self, keep_emission_order=True):
         self._check(self._L.a3fr_set_debug(self._h, int(bool(keep_emission_order))))
 
@@ -554,4 +559,4 @@ EXPORTED = ["a3fr_create", "a3fr_destroy", "a3fr_set_stream", "a3fr_set_debug", 
             "a3fr_net_backward", "a3fr_net_adam", "a3fr_set_upsampler", "a3fr_set_fallback",
             "a3fr_set_blend_variant", "a3fr_autotune_blend", "a3fr_graph_capture", "a3fr_graph_launch",
             "a3fr_graph_destroy", "a3fr_incremental_begin", "a3fr_incremental_round", "a3fr_incremental_finish",
-            "a3fr_render_amr", "a3fr_render_batch", "a3fr_region_sse_noalloc"]
+            "a3fr_render_amr", "a3fr_render_batch", "a3fr_region_sse_noalloc", "a3fr_set_host_wait"]

@@ -87,6 +87,9 @@ struct a3fr_ctx {
     hipEvent_t upload_done = nullptr;
     uint64_t *h_total = nullptr;
     hipEvent_t total_ready = nullptr;  // the key total has reached h_total
+    // a3fr_set_host_wait(1): host waits sleep on blocking-sync events instead of polling
+    bool block_wait = false;
+    hipEvent_t total_ready_block = nullptr, sync_block = nullptr;
     // second stream of a foveated frame: the fovea and mid layers are blended
     // on it while the main stream blends the periphery and runs the network
     hipStream_t side = nullptr;
@@ -379,6 +382,8 @@ void a3fr_destroy(a3fr_ctx *c) {
     if (c->h_total) (void)hipHostFree(c->h_total);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->total_ready) (void)hipEventDestroy(c->total_ready);
+    if (c->total_ready_block) (void)hipEventDestroy(c->total_ready_block);
+    if (c->sync_block) (void)hipEventDestroy(c->sync_block);
     if (c->side) {
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
@@ -436,8 +441,24 @@ a3fr_status a3fr_get_profile(a3fr_ctx *c, a3fr_profile *out) {
     return A3FR_OK;
 }
 
+a3fr_status a3fr_set_host_wait(a3fr_ctx *c, int32_t blocking) {
+    if (!c) return A3FR_EINVAL;
+    if (blocking != 0 && blocking != 1) return fail(c, A3FR_EINVAL, "set_host_wait: blocking must be 0 or 1");
+    if (blocking) {
+        const unsigned fl = hipEventBlockingSync | hipEventDisableTiming;
+        if (!c->total_ready_block) HIPCHECK(c, hipEventCreateWithFlags(&c->total_ready_block, fl));
+        if (!c->sync_block) HIPCHECK(c, hipEventCreateWithFlags(&c->sync_block, fl));
+    }
+    c->block_wait = blocking != 0;
+    return A3FR_OK;
+}
+
 a3fr_status a3fr_sync(a3fr_ctx *c) {
     if (!c) return A3FR_EINVAL;
+    if (c->block_wait) {
+        HIPCHECK(c, hipEventRecord(c->sync_block, c->stream));
+        HIPCHECK(c, hipEventSynchronize(c->sync_block));
+    }
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     HIPCHECK(c, hipGetLastError());
     if (c->scalars.p) {
@@ -782,9 +803,10 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     } else {
         HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
                                    c->stream));
-        HIPCHECK(c, hipEventRecord(c->total_ready, c->stream));
+        hipEvent_t ready = c->block_wait ? c->total_ready_block : c->total_ready;
+        HIPCHECK(c, hipEventRecord(ready, c->stream));
         run_pending_colour(c);  // the GPU works on it while the host waits for the total
-        HIPCHECK(c, hipEventSynchronize(c->total_ready));
+        HIPCHECK(c, hipEventSynchronize(ready));
         K = *c->h_total;
         if (n_keys_out) *n_keys_out = (int64_t)K;
         if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));

@@ -149,8 +149,8 @@ def test_incremental_call_order_and_args(pkg):
     ctx.close()
 
 
-@pytest.mark.parametrize("load", [0.05, 0.5])
-def test_concurrent_pipeline_frame_is_exact(pkg, load):
+@pytest.mark.parametrize("load,speculative", [(0.05, True), (0.5, True), (0.5, False)])
+def test_concurrent_pipeline_frame_is_exact(pkg, load, speculative):
     """Algorithm 1 with a stand-in tracker publishing exits at the network's
     latencies (scaled by load, so which rounds run depends on timing): the frame
     is the one-shot frame of the last prediction whatever the rounds were, the
@@ -163,10 +163,11 @@ def test_concurrent_pipeline_frame_is_exact(pkg, load):
     ds = pkg.DeviceScene.from_host(scene)
     fov = pkg.fovea_struct(*rad)
     ctx = pkg.Context()
+    ctx.set_host_wait(True)  # the renderer's waits sleep, as beside a CPU tracker
     for final, exits in trials:
         out = torch.full((2, 3, H, W), float("nan"), device="cuda")
-        res = pipeline.run(ctx, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS),
-                           torch.cuda.synchronize, load=load, out=out)
+        res = pipeline.run(ctx, ds, cams, fov, exits, final, sig, list(synth.EXIT_LATENCY_MS), load=load, out=out,
+                           speculative=speculative)
         ref = torch.zeros_like(out)
         ctx.render_foveated(ds, cams, final, fov, ref)
         ctx.sync()
@@ -186,4 +187,6 @@ def test_concurrent_pipeline_frame_is_exact(pkg, load):
         assert ev[-1][2] >= res["exit_ms"][-1] - 1e-6  # the finish starts once the last exit is published
         for a, b in zip(ev, ev[1:]):
             assert b[2] >= a[3] - 1e-6  # one round at a time
+        if not speculative:
+            assert all(e[0] != "speculative" for e in ev)
     ctx.close()
