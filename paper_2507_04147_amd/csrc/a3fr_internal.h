@@ -24,16 +24,19 @@ constexpr float kTMin = 1e-4f;
 constexpr int kMaxViews = 384;
 constexpr int kMaxEyes = 128;  // eye slots per frame batch (64 stereo frames)
 
-// Blend record of one (view, Gaussian): centre in float64 (so that the
-// tile-relative offset keeps full precision at any image size) and the
-// inverse 2D covariance in LDL^T form scaled for exp2:
+// Blend record of one entry (a (view, Gaussian) pair that is drawn): centre in
+// float64 (so that the tile-relative offset keeps full precision at any image
+// size) and the inverse 2D covariance in LDL^T form scaled for exp2:
 //   log2 G(d) = a2 (dx + k dy)^2 + c2 dy^2,
 //   a2 = -log2(e)/2 * c/det, k = -b/c, c2 = -log2(e)/2 / c,
-// where (a, b, c) is the dilated 2D covariance and det = a c - b^2.
+// where (a, b, c) is the dilated 2D covariance and det = a c - b^2; opacity,
+// view-dependent colour and the float32 depth bits.  Records are stored per
+// entry, contiguously; a key's value is its entry's record index.
 struct alignas(16) Record {
     double u, v;
     float a2, k, c2, o;
-    float r, g, b, pad;
+    float r, g, b;
+    uint32_t dbits;
 };
 static_assert(sizeof(Record) == 48, "record layout");
 
@@ -51,6 +54,10 @@ struct DevView {
                           //    incremental rounds); invisible (view, Gaussian) slots then get an
                           //    empty rectangle
     int32_t round_flags;  // incremental rounds: kRoundExclDone, kRoundFrozen
+    int32_t rect_slot;    // >= 0: the projection keeps every slot's rectangle at rect[rect_slot * n + i]
+                          //    (views whose mask may grow, and the fallback's periphery views)
+    int32_t keep_visible; // 1: every visible slot of the view becomes an entry with a record, with keys or
+                          //    not (the first round of an incremental frame, for the later rounds)
     // tile columns [ax0, ax1] x rows [ay0, ay1] hold every tile the view's mask
     // can activate (a margin of one tile; the whole grid for MASK_ALL; empty
     // when ax0 > ax1)
@@ -112,15 +119,16 @@ __host__ __device__ int net_chw_stride(int w);
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
                        uint8_t *done /* [tiles] nullable: incremental rounds */, hipStream_t s);
-// colour of every visible (view, Gaussian) slot of the remask views, into the records
-void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, int64_t n, const uint64_t *rect,
-                          Record *rec, hipStream_t s);
+// counts [nv][n] every slot; depth [nv][n] of entries; rect [n_rect_views][n] (views with rect_slot >= 0);
+// score [nsel][n] (selecting views, by sel_slot)
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       Record *rec, double *score, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
-void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, Record *rec, hipStream_t s,
-                         int max_blocks = 2048 /* grid cap (grid-stride loop); 0: one thread per slot */);
+                       double *score, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
+// records and rectangles of the entries ent[0 .. min(*n_ent, cap)), at the entry's index; map[slot] = index;
+// a count above cap raises bit 2 of err
+void launch_entry_record(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
+                         int64_t m, int64_t cap, const double *exp_tab, Record *rec, uint64_t *rect_e, uint32_t *map,
+                         uint32_t *err, hipStream_t s);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
                    uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s,
@@ -130,26 +138,46 @@ int64_t select_workspace_words(int nsel, int64_t n);
 // scan workspace (uint64 words) for m = nv * n entry slots; the compaction
 // clears it, so the key offsets must follow that compaction
 int64_t scan_workspace_words(int64_t m);
-void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
-                            uint32_t *n_ent, uint32_t *err, hipStream_t s, bool zeroed = false /* ws already zero */);
-void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
-                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+// entries (slots with keys, kept; every visible slot of a keep_visible view) in slot order:
+// ent[j] = slot, dkey[j] = depth bits, dval[j] = j
+void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const uint64_t *rect, const DevView *views,
+                            int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
+                            uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err, hipStream_t s,
+                            bool zeroed = false /* ws already zero */);
+// key offsets of the entries in depth order: order[k] = entry index, its count counts[ent[order[k]]]
+void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *order, const uint32_t *n_ent,
+                        int64_t m, uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
                         hipStream_t s);
 // number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
 int64_t emit_chunks(int64_t K);
-void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
-                 const uint32_t *offsets, const uint64_t *rect,
-                 uint64_t *rect_s /* [m] scratch: the rectangles in depth order */,
-                 const uint16_t *row_prefix, const uint16_t *row_list,
-                 const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
+// The entries of one emission, in depth order: entry order[k] of this pass has slot ent[order[k]]
+// and record r = map ? map[slot] : order[k]; its rectangle is rect_e[r].  rect_s, esort, rsort
+// (capacity cap) receive the rectangle, slot and record per depth-ordered entry.
+struct EmitEntries {
+    const uint32_t *order, *ent, *map;
+    const uint64_t *rect_e;
+    uint64_t *rect_s;
+    uint32_t *esort, *rsort;
+    int64_t cap;
+};
+void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const EmitEntries &ee, const uint32_t *n_ent,
+                 const uint32_t *offsets, const uint16_t *row_prefix, const uint16_t *row_list, const uint32_t *cum,
+                 uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
                  const uint32_t *K_dev /* nullable: device key count (clamped to K) */,
                  uint32_t *zero, int zero_words /* cleared by the first kernel (nullable when 0) */, hipStream_t s);
-void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s);
+void launch_clamp_keys(const uint64_t *total, int64_t cap, const uint32_t *n_ent, const uint32_t *offsets,
+                       int64_t ecap, uint32_t *n32, uint32_t *err, hipStream_t s);
 void launch_mask_cum(const DevView *views, int nv, int max_tiles_x, const uint16_t *row_prefix, uint32_t *cum,
                      hipStream_t s, const uint32_t *skip_if_zero = nullptr /* device count: 0 skips */);
-void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
-                        int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s);
+// inspection helpers: 64-bit keys (tile << 32 | record depth bits); key values as Gaussian indices;
+// gathers and dense scatters of per-entry arrays
+void launch_make_keys64(const uint32_t *tiles, const uint32_t *vals, int64_t K, const Record *rec, int64_t n_rec,
+                        uint64_t *out, hipStream_t s);
+void launch_vals_to_index(const uint32_t *vals, int64_t K, const uint32_t *rent, int64_t n_rec, int64_t n,
+                          uint32_t *out, hipStream_t s);
+void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t cnt, uint32_t *out, hipStream_t s);
+void launch_scatter_dense_u64(const uint64_t *src, const uint32_t *ent, int64_t cnt, uint64_t *out, hipStream_t s);
+void launch_scatter_dense_rec(const Record *src, const uint32_t *ent, int64_t cnt, Record *out, hipStream_t s);
 // keys per thread of the onesweep passes: 16 (8192-key partitions) for the
 // tile-id sort, 4 (2048-key partitions) for the entry depth sort
 constexpr int kSortItemsLarge = 16;
@@ -204,9 +232,12 @@ void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t n
                         hipStream_t s);
 void launch_blend_bwd(const DevView *views, int nv, int64_t ntiles, const uint8_t *active, const uint32_t *ranges,
                       const uint32_t *vals, const Record *rec, int64_t n, const float *dl_drgb, const float *T,
-                      const uint32_t *last, float *acc /* [nv * n][12] */, hipStream_t s);
+                      const uint32_t *last, float *acc /* [records][12] (n = 0: indexed by the key value) */,
+                      hipStream_t s);
 void launch_activate(const a3fr_params &p, float *scale, float *opacity, hipStream_t s);
-void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
+// per Gaussian, over the views where its slot is an entry (count > 0, kept): record map[slot], sums acc[record]
+void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const uint32_t *counts,
+                           const uint8_t *keep, const uint32_t *map, const float *acc, const Record *rec,
                            const a3fr_grads &g, hipStream_t s);
 // the packed weights of theta and the bf16 input (NHWC8, plus the
 // channel-major copy when chw is not NULL; x_bstride 0: 3 h w), one launch

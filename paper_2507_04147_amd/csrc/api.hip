@@ -94,18 +94,29 @@ struct a3fr_ctx {
     // on it while the main stream blends the periphery and runs the network
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // a frame of this library defers the view-dependent colour of its entries
-    // into a3fr_bin_sort, where it runs while the host waits for the key total
-    bool defer_colour = false, colour_pending = false;
-    a3fr_scene colour_scene{};
-    // device workspace
+    // the records of a frame's entries are formed in a3fr_bin_sort, where they
+    // are computed while the host waits for the key total
+    bool records_pending = false;
+    a3fr_scene rec_scene{};
+    // device workspace.  Per (view, Gaussian) slot: counts, depth, keep, map
+    // (slot -> record), the compaction and depth-sort arrays, offsets; rect only
+    // for views that keep every slot's rectangle (rect_slot), score only for
+    // selecting views (sel_slot).  Per record (entry): rec, rect_e.  Per
+    // depth-ordered entry of an emission: rect_s, esort, rsort.
     DevBuf views, row_view, row_y, row_prefix, row_list, active;
-    DevBuf counts, depth, rect, rect_s, rec, score, keep, sel_views, sel;
+    DevBuf counts, depth, rect, score, keep, sel_views, sel, map;
+    DevBuf rec, rect_e, rect_s, esort, rsort;
     DevBuf offsets, block_sums, scalars;
-    DevBuf ent_a, ent_b, dkey_a, dkey_b;       // visible entries, depth sort
+    DevBuf ent_a, ent_b, dkey_a, dkey_b, dval_a, dval_b;  // entries (records' / a round's), depth sort
     DevBuf keys_a, keys_b, vals_a, vals_b;
     DevBuf sort_status, ranges;
-    DevBuf grad_acc;           // reverse blend sums, [n_views * n][12] float
+    DevBuf grad_acc;           // reverse blend sums, [records][12] float
+    int nrect = 0;             // views keeping every slot's rectangle
+    int64_t n_rec = 0;         // records of the last record pass (exact mode)
+    int64_t n_ent_pass = 0;    // entries of the last emission (exact mode)
+    bool map_mode = false;     // the last emission's records belong to an earlier pass (incremental rounds)
+    bool inc_round0 = false;   // layouts made now: the first round of an incremental frame (keep_visible)
+    int64_t ecap = 0;          // graph mode: entry (and record) capacity
     // upsampler workspace: packed weights, activations (NHWC + channel-major copies), gradients
     DevBuf net_pk, net_x0, net_x0c, net_a1, net_a1c, net_a2, net_a2c, net_g3, net_g3c, net_g2, net_g2c, net_g1c,
         net_sse;
@@ -368,7 +379,8 @@ void a3fr_destroy(a3fr_ctx *c) {
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
                       &c->counts, &c->depth, &c->rect, &c->rect_s, &c->rec, &c->score, &c->keep, &c->sel_views,
-                      &c->sel, &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
+                      &c->sel, &c->map, &c->rect_e, &c->esort, &c->rsort, &c->dval_a, &c->dval_b,
+                      &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
@@ -464,10 +476,10 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
     if (c->scalars.p) {
         uint32_t flag = 0;
         HIPCHECK(c, hipMemcpy(&flag, sc_err(c->scalars), sizeof(uint32_t), hipMemcpyDeviceToHost));
-        if (flag & 2u) {
+        if (flag & 6u) {
             launch_fill_u32(sc_err(c->scalars), 0u, 1, c->stream);
             HIPCHECK(c, hipStreamSynchronize(c->stream));
-            return fail(c, A3FR_ECAPACITY, "key count exceeded the graph's key capacity (frame incomplete)");
+            return fail(c, A3FR_ECAPACITY, "key or entry count exceeded the graph's capacity (frame incomplete)");
         }
         if (flag & 1u) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
     }
@@ -476,7 +488,7 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
 
 static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *views, int32_t nv);
 static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int32_t keep_num, int32_t keep_den);
-static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed = false);
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed = false, bool map_mode = false);
 
 a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_view *views, int32_t nv,
                             int32_t keep_num, int32_t keep_den) {
@@ -500,7 +512,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_vie
                 return fail(c, A3FR_EINVAL, "views with the same eye must share R, t and campos");
     const int64_t n = scene->n;
     if (!c->inc_mode) c->inc_ready = false;  // another frame reuses the buffers of the rounds
-    c->colour_pending = false;
+    c->records_pending = false;
     if (c->capturing) {
         // the view table of each replay is uploaded by a3fr_graph_launch; the layout is the warm-up's
         if (nv != c->nv || n != c->n) return fail(c, A3FR_EINVAL, "graph capture: frame layout changed");
@@ -521,7 +533,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         if (k == 0 || views[k].eye != views[k - 1].eye) c->hgroups.push_back(k);
     c->hgroups.push_back(nv);
     int64_t toff = 0, ioff = 0, moff = 0, coff = 0;
-    int max_tx = 1;
+    int max_tx = 1, nrect = 0;
     for (int k = 0; k < nv; ++k) {
         DevView &d = c->hviews[k];
         std::memset(&d, 0, sizeof(d));
@@ -553,12 +565,19 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         if (views[k].mask != A3FR_MASK_ALL) coff += (int64_t)(d.tiles_y + 1) * (d.tiles_x + 1);
         if (d.tiles_x > max_tx) max_tx = d.tiles_x;
         d.sel_slot = views[k].select ? (int32_t)c->hsel_views.size() : -1;
-        for (const auto &fp : c->fb_plan)
+        bool fb_periph = false;
+        for (const auto &fp : c->fb_plan) {
             if (fp.fv == k) d.remask = 1;
+            if (fp.pv == k) fb_periph = true;
+        }
         if (c->inc_mode) {
             if (k % 3 != 2) d.remask = 1;  // fovea and mid layers: their masks change between rounds
             d.round_flags = k < (int)c->inc_flags.size() ? c->inc_flags[k] : 0;
+            d.keep_visible = c->inc_round0 && d.remask ? 1 : 0;
         }
+        // rectangles of every slot: views recounted after the projection, and the
+        // fallback's periphery views (their mass maps)
+        d.rect_slot = d.remask || fb_periph ? nrect++ : -1;
         if (views[k].select) c->hsel_views.push_back(k);
         if (views[k].mask != A3FR_MASK_ALL) moff += (int64_t)d.tiles_y * (d.tiles_x + 1);
         for (int ty = 0; ty < d.tiles_y; ++ty) {
@@ -578,22 +597,23 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     c->mask_entries = moff;
     c->cum_entries = coff;
     c->max_tiles_x = max_tx;
+    c->nrect = nrect;
     c->preprocessed = false;
     c->sorted = false;
     c->blend_bwd_done = false;
 
     // ---- workspace
     const int64_t m = (int64_t)nv * n;
+    if (m >= (int64_t(1) << 32)) return fail(c, A3FR_ECAPACITY, "more than 2^32 - 1 (view, Gaussian) slots");
     TRY(ensure(c, c->row_prefix, sizeof(uint16_t) * moff));
     TRY(ensure(c, c->row_list, sizeof(uint16_t) * moff));
     TRY(ensure(c, c->cum, sizeof(uint32_t) * coff));
     TRY(ensure(c, c->active, (size_t)toff));
     TRY(ensure(c, c->counts, sizeof(uint32_t) * m));
     TRY(ensure(c, c->depth, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->rect, sizeof(uint64_t) * m));
-    TRY(ensure(c, c->rect_s, sizeof(uint64_t) * m));
-    TRY(ensure(c, c->rec, sizeof(Record) * m));
-    TRY(ensure(c, c->score, c->nsel ? sizeof(double) * m : 16));
+    TRY(ensure(c, c->map, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->rect, sizeof(uint64_t) * (size_t)nrect * n));
+    TRY(ensure(c, c->score, sizeof(double) * (size_t)c->nsel * n));
     TRY(ensure(c, c->keep, c->nsel ? (size_t)m : 16));
     TRY(ensure(c, c->sel, sizeof(uint32_t) * (size_t)select_workspace_words(c->nsel, n)));
     TRY(ensure(c, c->offsets, sizeof(uint32_t) * (m + 1)));
@@ -603,9 +623,11 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         launch_fill_u32(P<uint32_t>(c->scalars), 0u, 16, c->stream);
     }
     TRY(ensure(c, c->ent_a, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
+    if (c->inc_mode) TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_a, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->dval_a, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->dval_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4, kSortItemsSmall)));
 
     // ---- one upload through pinned staging:
@@ -656,8 +678,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
       if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
-                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<Record>(c->rec), P<double>(c->score),
-                      c->d_exp_tab, c->stream); }
+                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), c->d_exp_tab, c->stream); }
     // the fallback pairs (periphery view, its eye's full-resolution view); their
     // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of
     // up to kFbMax per launch
@@ -734,34 +755,84 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     return entry_stages(c, scene, true);
 }
 
-// Entries that emit keys (count > 0, kept): compaction, colour (scene not
-// NULL), stable sort by depth, key offsets in depth order.  zeroed: the scan
-// and depth-sort workspaces were cleared by the frame's first clearing launch.
-static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed) {
+// The record pass: records and rectangles of the entries ent_a[0 .. E) (E on
+// the device, at most cap of them written; a larger E is reported by bit 2 of
+// the error word) and the slot -> record map.
+static void launch_records(a3fr_ctx *c, const a3fr_scene &scene, int64_t cap) {
+    StageTimer t_(c, A3FR_STAGE_COLOUR);
+    launch_entry_record(scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
+                        (int64_t)c->nv * c->n, cap, c->d_exp_tab, P<Record>(c->rec), P<uint64_t>(c->rect_e),
+                        P<uint32_t>(c->map), sc_err(c->scalars), c->stream);
+}
+
+// Sizes the record arrays for cap records.
+static a3fr_status ensure_records(a3fr_ctx *c, int64_t cap) {
+    TRY(ensure(c, c->rec, sizeof(Record) * (size_t)cap));
+    TRY(ensure(c, c->rect_e, sizeof(uint64_t) * (size_t)cap));
+    return A3FR_OK;
+}
+
+// Records held by the record arrays (without growing them).
+static int64_t record_capacity(const a3fr_ctx *c) {
+    return (int64_t)std::min(c->rec.cap / sizeof(Record), c->rect_e.cap / sizeof(uint64_t));
+}
+
+// The entries of one emission: compaction of the slots that have keys (kept)
+// into ent (ent_a when this pass makes the records, ent_b when the records come
+// from an earlier pass: map_mode), their stable sort by depth, and their key
+// offsets in depth order.  With scene set the records are formed for these
+// entries in a3fr_bin_sort.  zeroed: the scan and depth-sort workspaces were
+// cleared by the frame's first clearing launch.  visible_pass: before that, a
+// compaction keeping every visible slot of the keep_visible views, whose
+// records are formed at once (the first round of an incremental frame).
+static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroed, bool map_mode) {
     const int64_t n = c->n;
     const int nv = c->nv;
     const int64_t m = (int64_t)nv * n;
     const DevView *dv = P<DevView>(c->views);
+    c->records_pending = false;
+    c->map_mode = map_mode;
+    const bool visible_pass = c->inc_round0;
+    if (visible_pass) {
+        // every visible entry of the fovea and mid layers gets its record now, for the later rounds
+        {
+            StageTimer t_(c, A3FR_STAGE_SCAN);
+            launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect), dv, nv, n,
+                                   P<uint32_t>(c->depth), P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_b),
+                                   P<uint32_t>(c->dval_b), P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
+                                   sc_n_ent(c->scalars), sc_err(c->scalars), c->stream, zeroed);
+        }
+        uint32_t E = 0;
+        HIPCHECK(c, hipMemcpyAsync(&E, sc_n_ent(c->scalars), 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        TRY(ensure_records(c, E));
+        launch_records(c, *scene, E);
+        c->n_rec = E;
+        // the compaction below reuses the scan workspace
+        launch_fill_u32(reinterpret_cast<uint32_t *>(c->block_sums.p), 0u, 2 * scan_workspace_words(m), c->stream);
+        zeroed = true;
+        scene = nullptr;
+        map_mode = c->map_mode = true;
+    }
+    DevBuf &ent = map_mode ? c->ent_b : c->ent_a;
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
-        launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), dv, nv, n, P<uint32_t>(c->depth),
-                               P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_a), P<uint64_t>(c->block_sums),
-                               sc_ent_total(c->scalars), sc_n_ent(c->scalars), sc_err(c->scalars), c->stream,
-                               zeroed);
+        // (keep_visible views count as such only in the visible pass)
+        launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), visible_pass ? nullptr : P<uint64_t>(c->rect),
+                               dv, nv, n, P<uint32_t>(c->depth), P<uint32_t>(ent), P<uint32_t>(c->dkey_a),
+                               P<uint32_t>(c->dval_a), P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
+                               sc_n_ent(c->scalars), sc_err(c->scalars), c->stream, zeroed);
     }
-    if (scene && c->defer_colour) {
-        c->colour_scene = *scene;
-        c->colour_pending = true;
-    } else if (scene) {
-        StageTimer t_(c, A3FR_STAGE_COLOUR);
-        launch_entry_colour(*scene, dv, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m, P<Record>(c->rec), c->stream);
+    if (scene) {
+        c->rec_scene = *scene;
+        c->records_pending = true;
     }
-    {   // stable sort of the visible entries by depth (4 passes: even, ends in the "a" buffers)
+    {   // stable sort of the entries by depth (4 passes: even, ends in the "a" buffers)
         StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
         launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, kSortItemsSmall, P<uint32_t>(c->sort_status),
                             c->stream, zeroed);
         uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
-        uint32_t *vi = P<uint32_t>(c->ent_a), *vo = P<uint32_t>(c->ent_b);
+        uint32_t *vi = P<uint32_t>(c->dval_a), *vo = P<uint32_t>(c->dval_b);
         for (int p = 0; p < 4; ++p) {
             launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, kSortItemsSmall, p, P<uint32_t>(c->sort_status),
                              sc_err(c->scalars), c->stream);
@@ -771,7 +842,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     }
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
-        launch_key_offsets(P<uint32_t>(c->counts), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), m,
+        launch_key_offsets(P<uint32_t>(c->counts), P<uint32_t>(ent), P<uint32_t>(c->dval_a), sc_n_ent(c->scalars), m,
                            P<uint32_t>(c->offsets), P<uint64_t>(c->block_sums), sc_key_total(c->scalars),
                            sc_n_keys(c->scalars), sc_err(c->scalars), c->stream);
     }
@@ -780,37 +851,55 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     return A3FR_OK;
 }
 
-// The colour of the entries (any order: it is stored per slot) deferred by
-// entry_stages; the entry list is final once the compaction has run.
-static void run_pending_colour(a3fr_ctx *c) {
-    if (!c->colour_pending) return;
-    c->colour_pending = false;
-    StageTimer t_(c, A3FR_STAGE_COLOUR);
-    launch_entry_colour(c->colour_scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
-                        (int64_t)c->nv * c->n, P<Record>(c->rec), c->stream);
-}
-
 a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     if (!c) return A3FR_EINVAL;
     if (!c->preprocessed) return fail(c, A3FR_ENOTREADY, "a3fr_bin_sort before a3fr_preprocess");
-    uint64_t K = 0;
+    uint64_t K = 0, E = 0;
     const bool cap_mode = c->capacity > 0;
+    const bool recs = c->records_pending;
+    c->records_pending = false;
     if (cap_mode) {
-        // graph mode: no host read-back; buffers sized to the capacity, counts clamped on the device
-        run_pending_colour(c);
+        // graph mode: no host read-back; buffers sized to the capacities, counts clamped on the device
         K = (uint64_t)c->capacity;
+        E = (uint64_t)c->ecap;
+        if (recs) {
+            TRY(ensure_records(c, (int64_t)E));
+            launch_records(c, c->rec_scene, (int64_t)E);
+            c->n_rec = -1;
+        }
         if (n_keys_out) *n_keys_out = -1;
     } else {
-        HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_key_total(c->scalars), sizeof(uint64_t), hipMemcpyDeviceToHost,
+        // the entry and key totals (scalars [0], [1]) in one read-back; the
+        // records are formed meanwhile into the arrays as they are (formed again
+        // after the wait if they turn out too small)
+        HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_ent_total(c->scalars), 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                    c->stream));
         hipEvent_t ready = c->block_wait ? c->total_ready_block : c->total_ready;
         HIPCHECK(c, hipEventRecord(ready, c->stream));
-        run_pending_colour(c);  // the GPU works on it while the host waits for the total
+        const int64_t cap0 = recs ? record_capacity(c) : 0;
+        if (cap0 > 0) {
+            StageTimer t_(c, A3FR_STAGE_COLOUR);
+            launch_entry_record(c->rec_scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
+                                (int64_t)c->nv * c->n, cap0, c->d_exp_tab, P<Record>(c->rec), P<uint64_t>(c->rect_e),
+                                P<uint32_t>(c->map), nullptr, c->stream);
+        }
         HIPCHECK(c, hipEventSynchronize(ready));
-        K = *c->h_total;
+        E = c->h_total[0];
+        K = c->h_total[1];
+        if (recs) {
+            if ((int64_t)E > cap0) {
+                TRY(ensure_records(c, (int64_t)E));
+                launch_records(c, c->rec_scene, (int64_t)E);
+            }
+            c->n_rec = (int64_t)E;
+        }
+        c->n_ent_pass = (int64_t)E;
         if (n_keys_out) *n_keys_out = (int64_t)K;
         if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
     }
+    TRY(ensure(c, c->rect_s, sizeof(uint64_t) * (size_t)E));
+    TRY(ensure(c, c->esort, sizeof(uint32_t) * (size_t)E));
+    TRY(ensure(c, c->rsort, sizeof(uint32_t) * (size_t)E));
     const int64_t m = (int64_t)c->nv * c->n;
     TRY(ensure(c, c->keys_a, sizeof(uint32_t) * K));
     TRY(ensure(c, c->keys_b, sizeof(uint32_t) * K));
@@ -823,13 +912,23 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass, kSortItemsLarge)));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
-    if (cap_mode) launch_clamp_keys(sc_key_total(c->scalars), c->capacity, sc_n_keys(c->scalars), sc_err(c->scalars),
-                                    c->stream);
+    if (cap_mode)
+        launch_clamp_keys(sc_key_total(c->scalars), c->capacity, sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
+                          c->ecap, sc_n_keys(c->scalars), sc_err(c->scalars), c->stream);
     {
         StageTimer t_(c, A3FR_STAGE_EMIT);
-        launch_emit(dv, c->nv, c->n, m, P<uint32_t>(c->ent_a), sc_n_ent(c->scalars), P<uint32_t>(c->offsets),
-                    P<uint64_t>(c->rect), P<uint64_t>(c->rect_s), P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint32_t>(c->cum),
-                    P<uint32_t>(c->chunk_start), P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
+        EmitEntries ee{};
+        ee.order = P<uint32_t>(c->dval_a);
+        ee.ent = c->map_mode ? P<uint32_t>(c->ent_b) : P<uint32_t>(c->ent_a);
+        ee.map = c->map_mode ? P<uint32_t>(c->map) : nullptr;
+        ee.rect_e = P<uint64_t>(c->rect_e);
+        ee.rect_s = P<uint64_t>(c->rect_s);
+        ee.esort = P<uint32_t>(c->esort);
+        ee.rsort = P<uint32_t>(c->rsort);
+        ee.cap = (int64_t)E;
+        launch_emit(dv, c->nv, c->n, m, ee, sc_n_ent(c->scalars), P<uint32_t>(c->offsets), P<uint16_t>(c->row_prefix),
+                    P<uint16_t>(c->row_list), P<uint32_t>(c->cum), P<uint32_t>(c->chunk_start),
+                    P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
                     cap_mode ? sc_n_keys(c->scalars) : nullptr, P<uint32_t>(c->sort_status),
                     (int)sort_zero_words(npass), c->stream);
     }
@@ -898,7 +997,7 @@ static a3fr_status blend_with(a3fr_ctx *c, int variant, float *rgb, float *T, ui
     a.ranges = P<uint32_t>(c->ranges);
     a.vals = sorted_vals(c);
     a.rec = P<Record>(c->rec);
-    a.n = c->n;
+    a.n = 0;  // key values are record indices
     a.rgb = rgb; a.T = T; a.last = last; a.pairs = pairs;
     a.ws = P<uint32_t>(c->blend_ws);
     a.order = P<uint32_t>(c->blend_order);
@@ -991,9 +1090,7 @@ a3fr_status a3fr_render_full(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_ca
     if (!out) return fail(c, A3FR_EINVAL, "out_dev is NULL");
     std::vector<a3fr_view> v(n_cams);
     for (int e = 0; e < n_cams; ++e) view_from_camera(cams[e], e, v[e]);
-    c->defer_colour = true;
     const a3fr_status st = a3fr_preprocess(c, scene, v.data(), n_cams, 1, 1);
-    c->defer_colour = false;
     TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
     return a3fr_blend(c, out, nullptr, nullptr);
@@ -1014,14 +1111,12 @@ a3fr_status a3fr_render_amr(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_cam
         v[e].gy = gaze[e].y;
         if (!is_fin(gaze[e].x) || !is_fin(gaze[e].y)) return fail(c, A3FR_EINVAL, "render_amr: gaze not finite");
     }
-    c->defer_colour = true;
     const a3fr_status st = a3fr_preprocess(c, scene, v.data(), n_eyes, 1, 1);
-    c->defer_colour = false;
     TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
     StageTimer t_(c, A3FR_STAGE_BLEND);
     launch_blend_amr(P<DevView>(c->views), c->nv, c->ntiles, P<uint32_t>(c->ranges), sorted_vals(c), P<Record>(c->rec),
-                     c->n, r[0], r[1], r[2], out, c->stream);
+                     0, r[0], r[1], r[2], out, c->stream);
     return check_launch(c, "render_amr");
 }
 
@@ -1134,9 +1229,7 @@ a3fr_status a3fr_render_foveated(a3fr_ctx *c, const a3fr_scene *scene, const a3f
     c->fb_plan.clear();
     if (fb)
         for (int e = 0; e < n_eyes; ++e) c->fb_plan.push_back({3 * e + 2, 3 * e, f->r_mid});
-    c->defer_colour = true;
     a3fr_status st = a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den);
-    c->defer_colour = false;
     c->fb_plan.clear();
     TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
@@ -1279,7 +1372,7 @@ static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, 
             }
     }
     c->fb_last = false;
-    TRY(entry_stages(c, nullptr));
+    TRY(entry_stages(c, nullptr, false, true));  // the records of round 0, through the slot -> record map
     TRY(a3fr_bin_sort(c, nullptr));
     StageTimer t_(c, A3FR_STAGE_BLEND);
     return blend_with(c, c->blend_variant, P<float>(c->layers), nullptr, nullptr, nullptr, c->stream);
@@ -1311,14 +1404,11 @@ a3fr_status a3fr_incremental_begin(a3fr_ctx *c, const a3fr_scene *scene, const a
     c->fb_plan.clear();
     c->inc_flags.assign(3 * n_eyes, 0);
     c->inc_mode = true;
+    c->inc_round0 = true;  // every visible fovea and mid entry gets its record now
     a3fr_status st = a3fr_preprocess(c, scene, v.data(), 3 * n_eyes, f->keep_num, f->keep_den);
     c->inc_mode = false;
+    c->inc_round0 = false;
     TRY(st);
-    {
-        StageTimer t_(c, A3FR_STAGE_COLOUR);
-        launch_colour_remask(*scene, P<DevView>(c->views), c->nv, c->n, P<uint64_t>(c->rect), P<Record>(c->rec),
-                             c->stream);
-    }
     TRY(a3fr_bin_sort(c, nullptr));
     TRY(ensure(c, c->layers, sizeof(float) * 3 * (size_t)c->npix));
     TRY(a3fr_blend(c, P<float>(c->layers), nullptr, nullptr));
@@ -1421,12 +1511,14 @@ a3fr_status a3fr_blend_backward(a3fr_ctx *c, const float *dl, const float *T, co
     if (!c) return A3FR_EINVAL;
     if (!c->sorted) return fail(c, A3FR_ENOTREADY, "a3fr_blend_backward before a3fr_bin_sort");
     if (!dl || !T || !last) return fail(c, A3FR_EINVAL, "blend_backward: dl_drgb, T and last must not be NULL");
-    const int64_t m = (int64_t)c->nv * c->n;
-    TRY(ensure(c, c->grad_acc, sizeof(float) * 12 * (size_t)m));
+    if (c->map_mode) return fail(c, A3FR_EINVAL, "blend_backward: not for the rounds of an incremental frame");
+    // the reverse blend's sums per record (the key values)
+    const int64_t nr = c->n_rec >= 0 ? c->n_rec : record_capacity(c);
+    TRY(ensure(c, c->grad_acc, sizeof(float) * 12 * (size_t)nr));
     StageTimer t_(c, A3FR_STAGE_BLEND_BWD);
-    launch_fill_u32(P<uint32_t>(c->grad_acc), 0u, 12 * m, c->stream);
+    launch_fill_u32(P<uint32_t>(c->grad_acc), 0u, 12 * nr, c->stream);
     launch_blend_bwd(P<DevView>(c->views), c->nv, c->ntiles, P<uint8_t>(c->active), P<uint32_t>(c->ranges),
-                     sorted_vals(c), P<Record>(c->rec), c->n, dl, T, last, P<float>(c->grad_acc), c->stream);
+                     sorted_vals(c), P<Record>(c->rec), 0, dl, T, last, P<float>(c->grad_acc), c->stream);
     TRY(check_launch(c, "blend_backward"));
     c->blend_bwd_done = true;
     return A3FR_OK;
@@ -1441,7 +1533,8 @@ a3fr_status a3fr_preprocess_backward(a3fr_ctx *c, const a3fr_params *p, const a3
     if (!g || (p->n > 0 && (!g->mean_dev || !g->log_scale_dev || !g->quat_dev || !g->logit_dev || !g->sh_dev)))
         return fail(c, A3FR_EINVAL, "preprocess_backward: gradient arrays must not be NULL");
     StageTimer t_(c, A3FR_STAGE_PREPROCESS_BWD);
-    launch_preprocess_bwd(*p, P<DevView>(c->views), c->nv, P<float>(c->grad_acc), P<Record>(c->rec), *g, c->stream);
+    launch_preprocess_bwd(*p, P<DevView>(c->views), c->nv, P<uint32_t>(c->counts), P<uint8_t>(c->keep),
+                          P<uint32_t>(c->map), P<float>(c->grad_acc), P<Record>(c->rec), *g, c->stream);
     return check_launch(c, "preprocess_backward");
 }
 
@@ -1570,6 +1663,7 @@ static void graph_release(a3fr_ctx *c) {
     c->gexec = nullptr;
     c->graph = nullptr;
     c->capacity = 0;
+    c->ecap = 0;
     c->g_eyes = 0;
 }
 
@@ -1594,17 +1688,32 @@ a3fr_status a3fr_graph_capture(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_
         if (!c->own_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
         c->stream = c->own_stream;
     }
+    // an exact frame gives this layout's key and entry counts; the entry (and
+    // record) capacity keeps the same headroom over the entries as max_keys
+    // over the keys
+    a3fr_status st = a3fr_render_foveated(c, scene, cams, gaze, n_eyes, f, out);
+    if (st == A3FR_OK) st = a3fr_sync(c);
+    if (st != A3FR_OK) return st;
+    const int64_t K0 = c->K, E0 = c->n_ent_pass;
+    if (K0 > max_keys)
+        return fail(c, A3FR_ECAPACITY, "max_keys " + std::to_string(max_keys) + " is below the warm-up frame's " +
+                                           std::to_string(K0) + " keys");
+    const double head = K0 > 0 ? (double)max_keys / (double)K0 : 1.0;
+    c->ecap = std::min<int64_t>((int64_t)c->nv * c->n,
+                                std::max<int64_t>(E0, (int64_t)std::ceil((double)E0 * head)) + 1024);
     c->capacity = max_keys;
     // warm-up frame in capacity mode: sizes every buffer for this layout
-    a3fr_status st = a3fr_render_foveated(c, scene, cams, gaze, n_eyes, f, out);
+    st = a3fr_render_foveated(c, scene, cams, gaze, n_eyes, f, out);
     if (st == A3FR_OK) st = a3fr_sync(c);
     if (st != A3FR_OK) {
         c->capacity = 0;
+        c->ecap = 0;
         return st;
     }
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         c->capacity = 0;
+        c->ecap = 0;
         return fail(c, A3FR_EDEVICE, "hipStreamBeginCapture failed");
     }
     c->capturing = true;
@@ -1616,6 +1725,7 @@ a3fr_status a3fr_graph_capture(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_
         (void)hipGetLastError();
         if (g) (void)hipGraphDestroy(g);
         c->capacity = 0;
+        c->ecap = 0;
         return st != A3FR_OK ? st : fail(c, A3FR_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
     }
     hipGraphExec_t x = nullptr;
@@ -1623,6 +1733,7 @@ a3fr_status a3fr_graph_capture(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_
         (void)hipGetLastError();
         (void)hipGraphDestroy(g);
         c->capacity = 0;
+        c->ecap = 0;
         return fail(c, A3FR_EDEVICE, "hipGraphInstantiate failed");
     }
     c->graph = g;
@@ -1766,6 +1877,8 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
     const void *src = nullptr;
     int64_t bytes = 0;
     int make64 = 0;  // 1: emission-order keys, 2: sorted keys (rebuilt as tile << 32 | depth)
+    int conv = 0;    // 1: key values as Gaussian indices (emission order), 2: the same, sorted;
+                     // 3: rectangles, 4: records, scattered to their slots; 5: entry slots in depth order
     uint32_t n_ent = 0;
     if (which == A3FR_BUF_OFFSETS || which == A3FR_BUF_DEPTH_ORDER) {
         HIPCHECK(c, hipMemcpyAsync(&n_ent, sc_n_ent(c->scalars), 4, hipMemcpyDeviceToHost, c->stream));
@@ -1778,20 +1891,24 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
     if (need_sort) TRY(key_count(c, &Kc));
     if ((which == A3FR_BUF_KEYS || which == A3FR_BUF_VALS) && !c->keep_emission)
         return fail(c, A3FR_ENOTREADY, "emission order kept only with a3fr_set_debug(ctx, 1)");
+    const bool need_records = which == A3FR_BUF_RECT || which == A3FR_BUF_RECORDS || make64 || need_sort;
+    if (need_records && c->records_pending)
+        return fail(c, A3FR_ENOTREADY, "the entries' records are formed by a3fr_bin_sort");
+    const int64_t nrec = c->n_rec >= 0 ? c->n_rec : record_capacity(c);
     switch (which) {
         case A3FR_BUF_COUNTS: src = c->counts.p; bytes = 4 * m; break;
         case A3FR_BUF_DEPTH: src = c->depth.p; bytes = 4 * m; break;
-        case A3FR_BUF_RECT: src = c->rect.p; bytes = 8 * m; break;
+        case A3FR_BUF_RECT: conv = 3; bytes = 8 * m; break;
         case A3FR_BUF_OFFSETS: src = c->offsets.p; bytes = 4 * ((int64_t)n_ent + 1); break;
         case A3FR_BUF_KEYS: make64 = 1; bytes = 8 * Kc; break;
-        case A3FR_BUF_VALS: src = c->vals_e.p; bytes = 4 * Kc; break;
+        case A3FR_BUF_VALS: conv = 1; bytes = 4 * Kc; break;
         case A3FR_BUF_SORTED_KEYS: make64 = 2; bytes = 8 * Kc; break;
-        case A3FR_BUF_SORTED_VALS: src = sorted_vals(c); bytes = 4 * Kc; break;
+        case A3FR_BUF_SORTED_VALS: conv = 2; bytes = 4 * Kc; break;
         case A3FR_BUF_RANGES: src = c->ranges.p; bytes = 8 * c->ntiles; break;
         case A3FR_BUF_ACTIVE: src = c->active.p; bytes = c->ntiles; break;
         case A3FR_BUF_KEEP: src = c->keep.p; bytes = c->nsel ? m : 0; break;
-        case A3FR_BUF_RECORDS: src = c->rec.p; bytes = (int64_t)sizeof(Record) * m; break;
-        case A3FR_BUF_DEPTH_ORDER: src = c->ent_a.p; bytes = 4 * (int64_t)n_ent; break;
+        case A3FR_BUF_RECORDS: conv = 4; bytes = (int64_t)sizeof(Record) * m; break;
+        case A3FR_BUF_DEPTH_ORDER: conv = 5; bytes = 4 * (int64_t)n_ent; break;
         case A3FR_BUF_NET_X0: src = c->net_x0.p; bytes = 2 * 8 * npx; break;
         case A3FR_BUF_NET_A1: src = c->net_a1.p; bytes = 2 * 32 * npx; break;
         case A3FR_BUF_NET_A2: src = c->net_a2.p; bytes = 2 * 32 * npx; break;
@@ -1814,9 +1931,30 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
     if (make64) {
         const uint32_t *t = make64 == 1 ? P<uint32_t>(c->keys_e) : sorted_tiles(c);
         const uint32_t *v = make64 == 1 ? P<uint32_t>(c->vals_e) : sorted_vals(c);
-        launch_make_keys64(P<DevView>(c->views), c->nv, c->n, t, v, Kc, P<uint32_t>(c->depth),
-                           reinterpret_cast<uint64_t *>(dst), c->stream);
+        launch_make_keys64(t, v, Kc, P<Record>(c->rec), nrec, reinterpret_cast<uint64_t *>(dst), c->stream);
         return check_launch(c, "inspect");
+    }
+    // the records' slots: the compaction that formed them
+    const uint32_t *rent = P<uint32_t>(c->ent_a);
+    switch (conv) {
+        case 1:
+        case 2:
+            launch_vals_to_index(conv == 1 ? P<uint32_t>(c->vals_e) : sorted_vals(c), Kc, rent, nrec, c->n,
+                                 static_cast<uint32_t *>(dst), c->stream);
+            return check_launch(c, "inspect");
+        case 3:  // rectangles of the slots with records; x0 = 1, x1 = 0, y0 = 1, y1 = 0 elsewhere
+            launch_fill_u32(static_cast<uint32_t *>(dst), 1u, 2 * m, c->stream);
+            launch_scatter_dense_u64(P<uint64_t>(c->rect_e), rent, nrec, static_cast<uint64_t *>(dst), c->stream);
+            return check_launch(c, "inspect");
+        case 4:
+            launch_fill_u32(static_cast<uint32_t *>(dst), 0u, (int64_t)(sizeof(Record) / 4) * m, c->stream);
+            launch_scatter_dense_rec(P<Record>(c->rec), rent, nrec, static_cast<Record *>(dst), c->stream);
+            return check_launch(c, "inspect");
+        case 5:
+            launch_gather_u32(c->map_mode ? P<uint32_t>(c->ent_b) : rent, P<uint32_t>(c->dval_a), n_ent,
+                              static_cast<uint32_t *>(dst), c->stream);
+            return check_launch(c, "inspect");
+        default: break;
     }
     HIPCHECK(c, hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, c->stream));
     return A3FR_OK;

@@ -72,6 +72,9 @@ __device__ __forceinline__ void sh_basis_grad64(double x, double y, double z, do
 }
 
 __global__ void __launch_bounds__(256) k_preprocess_bwd(a3fr_params p, const DevView *__restrict__ views, int nv,
+                                                        const uint32_t *__restrict__ counts,
+                                                        const uint8_t *__restrict__ keep,
+                                                        const uint32_t *__restrict__ map,
                                                         const float *__restrict__ acc,
                                                         const Record *__restrict__ rec, a3fr_grads g) {
     const int64_t n = p.n;
@@ -116,8 +119,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(a3fr_params p, const Dev
     }
 
     for (int vi = 0; vi < nv && valid; ++vi) {
+        // the slot's entry (drawn: it has keys and, in a selecting view, is kept) and its record
         const int64_t slot = (int64_t)vi * n + i;
-        const float4 *a4 = reinterpret_cast<const float4 *>(acc + slot * 12);
+        if (counts[slot] == 0 || (views[vi].v.select && !keep[slot])) continue;
+        const int64_t r = map[slot];
+        const float4 *a4 = reinterpret_cast<const float4 *>(acc + r * 12);
         const float4 A0 = a4[0], A1 = a4[1], A2 = a4[2];
         const float sums[9] = {A0.x, A0.y, A0.z, A0.w, A1.x, A1.y, A1.z, A1.w, A2.x};
         bool nz = false;
@@ -219,7 +225,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(a3fr_params p, const Dev
             dS3[e] += Rw[ur[e]] * B[uc[e]] + Rw[3 + ur[e]] * B[3 + uc[e]] + Rw[6 + ur[e]] * B[6 + uc[e]];
         gop += (double)sums[5];
         // colour: clamp at zero (the record holds the clamped forward colour), SH basis, direction
-        const Record &rr = rec[slot];
+        const Record &rr = rec[r];
         const double dcol[3] = {rr.r > 0.0f ? (double)sums[6] : 0.0, rr.g > 0.0f ? (double)sums[7] : 0.0,
                                 rr.b > 0.0f ? (double)sums[8] : 0.0};
         if (dcol[0] != 0.0 || dcol[1] != 0.0 || dcol[2] != 0.0) {
@@ -299,11 +305,12 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(a3fr_params p, const Dev
         if (k < 3 * nk) gs[k] = gsh[k];
 }
 
-void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const float *acc, const Record *rec,
+void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, const uint32_t *counts,
+                           const uint8_t *keep, const uint32_t *map, const float *acc, const Record *rec,
                            const a3fr_grads &g, hipStream_t s) {
     if (p.n == 0) return;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p, views, nv, acc, rec,
-                       g);
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p, views, nv, counts,
+                       keep, map, acc, rec, g);
 }
 
 }  // namespace a3fr

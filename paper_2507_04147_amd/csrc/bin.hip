@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, cons
     }
     for (int b = threadIdx.x; b < kSelBuckets; b += blockDim.x) lh[b] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)sel_views[slot] * n;
+    const int64_t base = (int64_t)sel_views[slot] * n, sbase = (int64_t)slot * n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // block-uniform trip count (the ballots need whole waves); loads first
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += kSelUnroll * stride) {
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, cons
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
             const int64_t i = i0 + u * stride + threadIdx.x;
-            bits[u] = cv[u] != 0 ? (uint64_t)__double_as_longlong(score[base + i]) : 0ull;
+            bits[u] = cv[u] != 0 ? (uint64_t)__double_as_longlong(score[sbase + i]) : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, co
                                                     const uint32_t *hist, int keep_num, int keep_den,
                                                     uint64_t *cand_key, uint32_t *cand_idx, uint8_t *keep) {
     const int slot = blockIdx.y;
-    const int64_t base = (int64_t)sel_views[slot] * n;
+    const int64_t base = (int64_t)sel_views[slot] * n, sbase = (int64_t)slot * n;
     __shared__ PickOut p0, p1;
     pick_bucket(hist + (int64_t)slot * 2 * kSelBuckets, true, 0u, keep_num, keep_den, &p0);
     const uint32_t mode = pick_mode(p0);
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, co
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
             const int64_t i = i0 + u * stride + threadIdx.x;
-            bits[u] = cv[u] != 0 && mode == 0 ? (uint64_t)__double_as_longlong(score[base + i]) : 0ull;
+            bits[u] = cv[u] != 0 && mode == 0 ? (uint64_t)__double_as_longlong(score[sbase + i]) : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
@@ -365,22 +365,25 @@ constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block (k
 constexpr int kCompactBlock = 1024;
 constexpr int kCompactTile = kScanItems * kCompactBlock;
 
-// Entry e = view * n + index contributes keys iff it is visible in its view and,
-// for a selecting view, kept.
+// Slot e = view * n + index is an entry iff it has keys (a count) and, in a
+// selecting view, is kept; in a view with keep_visible, iff its rectangle
+// (kept for that view) is not empty, keys or not.
 struct EntryFlags {
     const uint32_t *counts;
     const uint8_t *keep;
+    const uint64_t *rect;
     const DevView *views;
     int64_t n;
 };
 
-// Key count of the j-th entry in depth order.
+// Key count of the j-th entry in depth order (order: entry indices sorted by depth).
 struct SortedCounts {
     const uint32_t *counts;
     const uint32_t *ent;
+    const uint32_t *order;
     const uint32_t *n_ent;
     __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
-        return j < (int64_t)*n_ent ? counts[ent[j]] : 0u;
+        return j < (int64_t)*n_ent ? counts[ent[order[j]]] : 0u;
     }
 };
 
@@ -472,17 +475,18 @@ __device__ uint64_t chained_prefix(uint64_t *status, int64_t part, uint64_t tot,
     return excl;
 }
 
-// Compaction: entry e with flag 1 goes to slot (its exclusive prefix), with
-// its depth bits as sort key.  Each wave takes 1024 consecutive entries in 16
-// rounds of 64 (coalesced), packing the flagged ones with a ballot per round;
-// the waves of a block are combined in LDS and the blocks by the look-back.
-// All loads of a kind are issued before any is used (counts, then the keep
-// bytes where a selecting view needs them, then the depths of the flagged
-// entries), so a wave waits for three round trips, not one per round.
+// Compaction: slot e with flag 1 becomes entry j (its exclusive prefix):
+// ent[j] = e, with its depth bits as sort key dkey[j] and j itself as sort
+// value dval[j].  Each wave takes 1024 consecutive slots in 16 rounds of 64
+// (coalesced), packing the flagged ones with a ballot per round; the waves of
+// a block are combined in LDS and the blocks by the look-back.  All loads of a
+// kind are issued before any is used (counts, then the keep bytes or
+// rectangles where a view needs them, then the depths of the flagged slots), so
+// a wave waits for a few round trips, not one per round.
 __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
                                                         const uint32_t *__restrict__ depth, uint32_t *__restrict__ ent,
-                                                        uint32_t *__restrict__ dkey, uint64_t *total, uint32_t *total32,
-                                                        uint32_t *err) {
+                                                        uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
+                                                        uint64_t *total, uint32_t *total32, uint32_t *err) {
     __shared__ uint32_t s_part;
     __shared__ uint64_t s_w[kCompactBlock / 64];
     __shared__ uint64_t s_excl;
@@ -496,6 +500,8 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
     const bool per_elem = f.n < kCompactTile;
     const int64_t v0 = (part * kCompactTile) / f.n, b1 = (v0 + 1) * f.n;
     const bool sel0 = f.views[v0].v.select != 0, sel1 = b1 < m && f.views[v0 + 1].v.select != 0;
+    // keep_visible views count as such only when the rectangles are given
+    const bool vis0 = f.rect && f.views[v0].keep_visible != 0, vis1 = f.rect && b1 < m && f.views[v0 + 1].keep_visible != 0;
     uint32_t cv[kScanItems];
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
@@ -514,6 +520,24 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
 #pragma unroll
         for (int r = 0; r < kScanItems; ++r)
             if (kv[r] == 0) cv[r] = 0;
+    }
+    if (f.rect && (per_elem || vis0 || vis1)) {
+        // every visible slot of a keep_visible view is an entry (flag as a count of 1 when it has none)
+        uint32_t vv[kScanItems];
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            const int64_t e = wbase + r * 64 + lane;
+            vv[r] = 0u;
+            if (e < m && cv[r] == 0) {
+                const int64_t v = per_elem ? e / f.n : (e < b1 ? v0 : v0 + 1);
+                const DevView &dv = f.views[v];
+                if (dv.keep_visible && dv.rect_slot >= 0 &&
+                    f.rect[(int64_t)dv.rect_slot * f.n + (e - v * f.n)] != kEmptyRect)
+                    vv[r] = 1u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) cv[r] |= vv[r];
     }
     uint64_t masks[kScanItems];
     uint32_t dv[kScanItems];
@@ -550,6 +574,7 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
             const uint64_t pos = run + (uint64_t)__popcll(mk & lt);
             ent[pos] = (uint32_t)(wbase + r * 64 + lane);
             dkey[pos] = dv[r];
+            dval[pos] = (uint32_t)pos;
         }
         run += (uint64_t)__popcll(mk);
     }
@@ -613,9 +638,10 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
 
 int64_t scan_workspace_words(int64_t m) { return 2 + compact_parts(m) + (m + kScanTile - 1) / kScanTile; }
 
-void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const DevView *views, int nv, int64_t n,
-                            const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint64_t *ws, uint64_t *total,
-                            uint32_t *n_ent, uint32_t *err, hipStream_t s, bool zeroed) {
+void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const uint64_t *rect, const DevView *views,
+                            int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
+                            uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err, hipStream_t s,
+                            bool zeroed) {
     const int64_t m = (int64_t)nv * n;
     const int64_t nb = compact_parts(m);
     // both scans' tickets and status words
@@ -628,16 +654,16 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const D
         launch_zero_segs(z, s);
         return;
     }
-    EntryFlags f{counts, keep, views, n};
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kCompactBlock), 0, s, f, m, nb, ws, depth, ent, dkey, total,
-                       n_ent, err);
+    EntryFlags f{counts, keep, rect, views, n};
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kCompactBlock), 0, s, f, m, nb, ws, depth, ent, dkey, dval,
+                       total, n_ent, err);
 }
 
-void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *n_ent, int64_t m,
-                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *order, const uint32_t *n_ent,
+                        int64_t m, uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
                         hipStream_t s) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
-    SortedCounts f{counts, ent, n_ent};
+    SortedCounts f{counts, ent, order, n_ent};
     hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, ws, total,
                        total32, offsets, err);
 }
@@ -665,21 +691,32 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 constexpr int kEmitChunk = 1024;
 constexpr int kEmitBlock = 512;
 
-// Thread per entry j (depth order): the chunks whose first key lies in its
-// key range start at j; and its rectangle is copied to rect_s[j], so the
-// emission reads it next to the offsets instead of through the entry index.
-// Block 0 also clears zero[0, zero_words) (the key sort's digit counts and
-// pass counters).
+// Thread per entry j (depth order: entry order[j] of this pass, slot
+// ent[order[j]], record r = map[slot] when the records belong to an earlier
+// pass, else order[j]): the chunks whose first key lies in its key range start
+// at j; and its slot, record index and rectangle (rect_e[r]) are copied to
+// esort[j], rsort[j] and rect_s[j], so the emission reads them next to the
+// offsets instead of through the indices.  Block 0 also clears
+// zero[0, zero_words) (the key sort's digit counts and pass counters).
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
+                                                      const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ ent,
-                                                      const uint64_t *__restrict__ rect, uint64_t *__restrict__ rect_s,
+                                                      const uint32_t *__restrict__ map,
+                                                      const uint64_t *__restrict__ rect_e,
+                                                      uint64_t *__restrict__ rect_s, uint32_t *__restrict__ esort,
+                                                      uint32_t *__restrict__ rsort,
                                                       uint32_t *__restrict__ chunk_start, int64_t nchunks,
-                                                      uint32_t *__restrict__ zero, int zero_words) {
+                                                      int64_t cap, uint32_t *__restrict__ zero, int zero_words) {
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0u;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)*n_ent) return;
-    rect_s[j] = rect[ent[j]];
+    if (j >= (int64_t)*n_ent || j >= cap) return;  // entries past the capacity emit no key (k_clamp_keys)
+    const uint32_t e = order[j];
+    const uint32_t slot = ent[e];
+    const uint32_t r = map ? map[slot] : e;
+    rect_s[j] = rect_e[r];
+    esort[j] = slot;
+    rsort[j] = r;
     const uint64_t lo = offsets[j], hi = offsets[j + 1];
     for (uint64_t c = (lo + kEmitChunk - 1) / kEmitChunk; c * kEmitChunk < hi && (int64_t)c < nchunks; ++c)
         chunk_start[c] = (uint32_t)j;
@@ -711,7 +748,8 @@ struct EmitView {
 constexpr int kEmitMaxViews = kMaxViews;
 
 __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__ views, int nv, int64_t n,
-                                                     const uint32_t *__restrict__ ent, const uint32_t *n_ent,
+                                                     const uint32_t *__restrict__ esort,
+                                                     const uint32_t *__restrict__ rsort, const uint32_t *n_ent,
                                                      const uint32_t *__restrict__ offsets,
                                                      const uint32_t *__restrict__ chunk_start,
                                                      const uint64_t *__restrict__ rect_s,
@@ -745,15 +783,13 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     }
     __syncthreads();
     // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E);
-    // their Gaussian index, view and rectangle
+    // their record index (the keys' value), view and rectangle
     const uint32_t nn = (uint32_t)n;
     for (int t = tid; t < kEmitChunk; t += kEmitBlock) {
         if ((int64_t)s_off[t] < qend) {
-            const uint32_t e = ent[j0 + t];
             s_rect[t] = rect_s[j0 + t];
-            const uint32_t v = e / nn;
-            s_v[t] = v;
-            s_i[t] = e - v * nn;
+            s_v[t] = esort[j0 + t] / nn;
+            s_i[t] = rsort[j0 + t];
         }
     }
     __syncthreads();
@@ -915,53 +951,106 @@ void launch_zero_segs(const FillSegs &f, hipStream_t s) {
 
 int64_t emit_chunks(int64_t K) { return (K + kEmitChunk - 1) / kEmitChunk; }
 
-void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const uint32_t *ent, const uint32_t *n_ent,
-                 const uint32_t *offsets, const uint64_t *rect, uint64_t *rect_s, const uint16_t *row_prefix,
-                 const uint16_t *row_list,
-                 const uint32_t *cum, uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K,
-                 const uint32_t *K_dev, uint32_t *zero, int zero_words, hipStream_t s) {
+void launch_emit(const DevView *views, int nv, int64_t n, int64_t m, const EmitEntries &ee, const uint32_t *n_ent,
+                 const uint32_t *offsets, const uint16_t *row_prefix, const uint16_t *row_list, const uint32_t *cum,
+                 uint32_t *chunk_start, uint32_t *keys, uint32_t *vals, int64_t K, const uint32_t *K_dev,
+                 uint32_t *zero, int zero_words, hipStream_t s) {
     if (m == 0 || K == 0) return;
     const int64_t nchunks = emit_chunks(K);
-    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n_ent, offsets, ent, rect,
-                       rect_s, chunk_start, nchunks, zero, zero_words);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, nv, n, ent, n_ent, offsets,
-                       chunk_start, rect_s, row_prefix, row_list, cum, keys, vals, K, K_dev);
+    const int64_t work = ee.cap < m ? ee.cap : m;
+    hipLaunchKernelGGL(k_chunk_starts, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, n_ent, offsets, ee.order,
+                       ee.ent, ee.map, ee.rect_e, ee.rect_s, ee.esort, ee.rsort, chunk_start, nchunks, ee.cap, zero,
+                       zero_words);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nchunks), dim3(kEmitBlock), 0, s, views, nv, n, ee.esort, ee.rsort,
+                       n_ent, offsets, chunk_start, ee.rect_s, row_prefix, row_list, cum, keys, vals, K, K_dev);
 }
 
-// capacity mode: the sort count is min(key total, capacity); overflow raises bit 1 of the error word
-__global__ void k_clamp_keys(const uint64_t *total, uint64_t cap, uint32_t *n32, uint32_t *err) {
-    const uint64_t t = *total;
+// capacity mode: the sort count is min(key total, key capacity), and when the
+// entries exceed the entry capacity, no more than the keys of the entries
+// within it; an overflow raises bit 1 of the error word
+__global__ void k_clamp_keys(const uint64_t *total, uint64_t cap, const uint32_t *n_ent, const uint32_t *offsets,
+                             uint64_t ecap, uint32_t *n32, uint32_t *err) {
+    uint64_t t = *total;
+    bool over = t > cap;
+    if ((uint64_t)*n_ent > ecap) {
+        const uint64_t te = offsets[ecap];
+        if (te < t) t = te;
+        over = true;
+    }
     *n32 = (uint32_t)(t < cap ? t : cap);
-    if (t > cap) atomicOr(err, 2u);
+    if (over) atomicOr(err, 2u);
 }
 
-void launch_clamp_keys(const uint64_t *total, int64_t cap, uint32_t *n32, uint32_t *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_clamp_keys, dim3(1), dim3(1), 0, s, total, (uint64_t)cap, n32, err);
+void launch_clamp_keys(const uint64_t *total, int64_t cap, const uint32_t *n_ent, const uint32_t *offsets,
+                       int64_t ecap, uint32_t *n32, uint32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_clamp_keys, dim3(1), dim3(1), 0, s, total, (uint64_t)cap, n_ent, offsets, (uint64_t)ecap,
+                       n32, err);
 }
 
 // ------------------------------------------------------------------------
 // inspection: 64-bit (tile << 32 | depth bits) keys from tile ids and values
 // ------------------------------------------------------------------------
-__global__ void k_make_keys64(const DevView *__restrict__ views, int nv, int64_t n, const uint32_t *__restrict__ tiles,
-                              const uint32_t *__restrict__ vals, int64_t K, const uint32_t *__restrict__ depth,
-                              uint64_t *__restrict__ out) {
+__global__ void k_make_keys64(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ vals, int64_t K,
+                              const Record *__restrict__ rec, int64_t n_rec, uint64_t *__restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K) return;
-    const uint32_t t = tiles[j];
-    int lo = 0, hi = nv - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].tile_off <= (int64_t)t) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t i = vals[j] < (uint32_t)n ? vals[j] : 0u;
-    out[j] = ((uint64_t)t << 32) | (uint64_t)depth[(int64_t)lo * n + i];
+    const uint32_t r = vals[j];
+    out[j] = ((uint64_t)tiles[j] << 32) | (uint64_t)((int64_t)r < n_rec ? rec[r].dbits : 0u);
 }
 
-void launch_make_keys64(const DevView *views, int nv, int64_t n, const uint32_t *tiles, const uint32_t *vals,
-                        int64_t K, const uint32_t *depth, uint64_t *out, hipStream_t s) {
+void launch_make_keys64(const uint32_t *tiles, const uint32_t *vals, int64_t K, const Record *rec, int64_t n_rec,
+                        uint64_t *out, hipStream_t s) {
     if (K == 0) return;
-    hipLaunchKernelGGL(k_make_keys64, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, views, nv, n, tiles, vals, K,
-                       depth, out);
+    hipLaunchKernelGGL(k_make_keys64, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, tiles, vals, K, rec, n_rec,
+                       out);
+}
+
+// inspection: key values (record indices) as Gaussian indices: the record's slot modulo n
+__global__ void k_vals_to_index(const uint32_t *__restrict__ vals, int64_t K, const uint32_t *__restrict__ rent,
+                                int64_t n_rec, int64_t n, uint32_t *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    const uint32_t r = vals[j];
+    out[j] = (int64_t)r < n_rec ? (uint32_t)((uint64_t)rent[r] % (uint64_t)n) : 0xffffffffu;
+}
+
+void launch_vals_to_index(const uint32_t *vals, int64_t K, const uint32_t *rent, int64_t n_rec, int64_t n,
+                          uint32_t *out, hipStream_t s) {
+    if (K == 0) return;
+    hipLaunchKernelGGL(k_vals_to_index, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, vals, K, rent, n_rec, n,
+                       out);
+}
+
+// inspection: out[j] = src[idx[j]] (u32), or a dense [m] array from per-entry
+// values: out[ent[j]] = src[j] (64-bit or record words) after a fill
+__global__ void k_gather_u32(const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx, int64_t cnt,
+                             uint32_t *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < cnt) out[j] = src[idx[j]];
+}
+
+void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t cnt, uint32_t *out, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_gather_u32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, src, idx, cnt, out);
+}
+
+template <typename T>
+__global__ void k_scatter_dense(const T *__restrict__ src, const uint32_t *__restrict__ ent, int64_t cnt,
+                                T *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < cnt) out[ent[j]] = src[j];
+}
+
+void launch_scatter_dense_u64(const uint64_t *src, const uint32_t *ent, int64_t cnt, uint64_t *out, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_scatter_dense<uint64_t>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, src, ent, cnt,
+                       out);
+}
+
+void launch_scatter_dense_rec(const Record *src, const uint32_t *ent, int64_t cnt, Record *out, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_scatter_dense<Record>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, src, ent, cnt,
+                       out);
 }
 
 }  // namespace a3fr

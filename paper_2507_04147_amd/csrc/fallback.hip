@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__
     if (counts[slot] == 0) return;
     const DevView &dv = views[pv];
     const int S = dv.tiles_x + 1;
-    drop_share(diff + b.doff[k], (int64_t)(dv.tiles_y + 1) * S, S, rect[slot], score[slot], keep[slot] != 0);
+    drop_share(diff + b.doff[k], (int64_t)(dv.tiles_y + 1) * S, S, rect[(int64_t)dv.rect_slot * n + i],
+               score[(int64_t)dv.sel_slot * n + i], keep[slot] != 0);
 }
 
 // Contention-free variant for grids that fit in LDS: persistent blocks add
@@ -73,10 +74,12 @@ __global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restri
     const int cells = (int)(2 * plane);
     for (int c = threadIdx.x; c < cells; c += blockDim.x) sh[c] = 0.0;
     __syncthreads();
+    const uint64_t *rv = rect + (int64_t)dv.rect_slot * n;
+    const double *sv = score + (int64_t)dv.sel_slot * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t slot = (int64_t)pv * n + i;
         if (counts[slot] == 0) continue;
-        drop_share(sh, plane, S, rect[slot], score[slot], keep[slot] != 0);
+        drop_share(sh, plane, S, rv[i], sv[i], keep[slot] != 0);
     }
     __syncthreads();
     double *out = partials + ((int64_t)k * gridDim.x + blockIdx.x) * b.max_cells;
@@ -265,7 +268,7 @@ __global__ void __launch_bounds__(256) k_recount(const DevView *__restrict__ vie
     const int fv = b.fv[blockIdx.y];
     const DevView &dv = views[fv];
     const int64_t slot = (int64_t)fv * n + i;
-    const uint64_t r = rect[slot];
+    const uint64_t r = rect[(int64_t)dv.rect_slot * n + i];  // the view keeps every slot's rectangle
     const int x0 = (int)(r & 0xffff), x1 = (int)((r >> 16) & 0xffff), y0 = (int)((r >> 32) & 0xffff),
               y1 = (int)(r >> 48);
     if (x0 > x1 || y0 > y1) return;  // not visible: count stays 0

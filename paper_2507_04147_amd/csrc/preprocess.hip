@@ -164,17 +164,110 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
     Y[15] = -c3a * x * (xx - 3.0f * yy);
 }
 
+// Footprint bound Q(o) of opacity o: a pixel takes the Gaussian only where
+// o exp(-q/2) >= 1/255; the smallest step k/8 with exp(k/16) >= (1.001 x 255) o
+// (a lower-bound search over the increasing table exp(k/16), k = 0..kExtentSteps),
+// else kExtentQ.
+__device__ __forceinline__ double footprint_q(float op, const double *s_exp) {
+    double qe = kExtentQ;
+    const double t = (1.001 * 255.0) * (double)op;
+    int lo = 1, cnt_k = kExtentSteps;
+    while (cnt_k > 0) {
+        const int half = cnt_k >> 1;
+        if (s_exp[lo + half] < t) {
+            lo += half + 1;
+            cnt_k -= half + 1;
+        } else {
+            cnt_k = half;
+        }
+    }
+    if (lo <= kExtentSteps) qe = (double)lo / 8.0;
+    return qe;
+}
+
+// The Gaussian in one eye's camera: view-space centre p and covariance V
+// (front: in front of the near plane with a valid rotation).
+struct EyeProj {
+    double p0, p1, p2, xz, yz;
+    Cov3 V;
+    bool front;
+};
+
+__device__ __forceinline__ void eye_project(const a3fr_view &v0, double mx, double my, double mz, bool cov_ok,
+                                            const Cov3 &S, EyeProj &E) {
+    const double *Rw = v0.R;
+    E.p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v0.t[0])));
+    E.p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v0.t[1])));
+    E.p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v0.t[2])));
+    E.front = E.p2 > kZNear && cov_ok;
+    if (E.front) view_cov(Rw, S, E.V);
+    E.xz = E.p0 / E.p2;
+    E.yz = E.p1 / E.p2;
+}
+
+// One layer view: the dilated 2D covariance (a, b, c), its determinant, the
+// centre (u, w) and the footprint box's tile rectangle [x0, x1] x [y0, y1]
+// (clamped to the grid); visible when the box meets the image.
+struct LayerProj {
+    double a, b, c, det, u, w;
+    int x0, x1, y0, y1;
+    bool visible;
+};
+
+__device__ __forceinline__ void layer_project(const DevView &dv, const EyeProj &E, double qe, LayerProj &L) {
+    const a3fr_view &v = dv.v;
+    L.visible = false;
+    if (!E.front) return;
+    const Cov3 &V = E.V;
+    const double limx = dv.limx, limy = dv.limy;  // (1.3 (W/2)) / fx, computed on the host
+    const double txc = fmin(fmax(E.xz, -limx), limx);
+    const double tyc = fmin(fmax(E.yz, -limy), limy);
+    const double j00 = v.fx / E.p2, j02 = -(j00 * txc);
+    const double j11 = v.fy / E.p2, j12 = -(j11 * tyc);
+    const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
+                 B02 = fma(j00, V.s02, j02 * V.s22);
+    const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
+    L.a = fma(B00, j00, B02 * j02) + kDilate;
+    L.b = fma(B01, j11, B02 * j12);
+    L.c = fma(B11, j11, B12 * j12) + kDilate;
+    L.det = fma(L.a, L.c, -(L.b * L.b));
+    if (!(L.det > 0.0)) return;
+    L.u = fma(v.fx, E.xz, v.cx);
+    L.w = fma(v.fy, E.yz, v.cy);
+    const double ex = sqrt(qe * L.a), ey = sqrt(qe * L.c);
+    const double lox = L.u - ex, hix = L.u + ex, loy = L.w - ey, hiy = L.w + ey;
+    if (!(hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5)) return;
+    double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
+    double fx1 = floor((hix - 0.5) / (double)kTile);
+    double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
+    double fy1 = floor((hiy - 0.5) / (double)kTile);
+    fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
+    fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return;
+    L.x0 = (int)fx0; L.x1 = (int)fx1; L.y0 = (int)fy0; L.y1 = (int)fy1;
+    L.visible = true;
+}
+
+__device__ __forceinline__ uint64_t pack_rect(const LayerProj &L) {
+    return (uint64_t)(uint16_t)L.x0 | ((uint64_t)(uint16_t)L.x1 << 16) | ((uint64_t)(uint16_t)L.y0 << 32) |
+           ((uint64_t)(uint16_t)L.y1 << 48);
+}
+
 // One thread per (Gaussian, group of consecutive views of one eye): the
-// Gaussian is loaded, its 3D covariance and view-space covariance computed once,
-// then each view of the group (the layers of that eye) gets the float64 key
-// path and the blend record (its colour is filled in later, only for the
-// entries that emit keys, by k_entry_colour).
+// Gaussian's geometry is loaded once, its 3D and view-space covariances
+// formed once, and each view of the group (the layers of that eye) gets the
+// float64 key path: its active-tile count (every slot), its float32 depth bits
+// (entries that emit keys, and every visible entry of a view whose mask may
+// grow later), its tile rectangle (only in the views that keep rectangles for
+// a later recount or mass estimate, rect_slot >= 0) and, in a selecting view,
+// its score.  The blend record of an entry is formed later, entry by entry
+// (k_entry_record), once the entries are known.
 __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views,
                                                     const int32_t *__restrict__ groups,
                                                     const uint16_t *__restrict__ row_prefix,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
-                                                    uint64_t *__restrict__ rect, Record *__restrict__ rec,
-                                                    double *__restrict__ score, const double *__restrict__ exp_tab) {
+                                                    uint64_t *__restrict__ rect, double *__restrict__ score,
+                                                    const double *__restrict__ exp_tab) {
     __shared__ double s_exp[kExtentSteps + 1];
     for (int k = threadIdx.x; k <= kExtentSteps; k += blockDim.x) s_exp[k] = exp_tab[k];
     __syncthreads();
@@ -182,123 +275,55 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int v_begin = groups[blockIdx.y], v_end = groups[blockIdx.y + 1];
-    const a3fr_view &v0 = views[v_begin].v;
     const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
-    const double *Rw = v0.R;
-    const double p0 = fma(Rw[0], mx, fma(Rw[1], my, fma(Rw[2], mz, v0.t[0])));
-    const double p1 = fma(Rw[3], mx, fma(Rw[4], my, fma(Rw[5], mz, v0.t[1])));
-    const double p2 = fma(Rw[6], mx, fma(Rw[7], my, fma(Rw[8], mz, v0.t[2])));
-    Cov3 S, V;
-    const bool front = p2 > kZNear &&
-                       gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i], sc.quat_dev[3 * n + i],
-                                     sc.scale_dev[i], sc.scale_dev[n + i], sc.scale_dev[2 * n + i], S);
-    if (front) view_cov(Rw, S, V);
-    const double xz = p0 / p2, yz = p1 / p2;
-    // footprint bound Q(o): a pixel takes the Gaussian only where
-    // o exp(-q/2) >= 1/255; the smallest step k/8 with exp(k/16) >= (1.001 x 255) o
-    // (a lower bound search over the increasing table), else kExtentQ
+    Cov3 S;
+    const bool cov_ok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i],
+                                      sc.quat_dev[3 * n + i], sc.scale_dev[i], sc.scale_dev[n + i],
+                                      sc.scale_dev[2 * n + i], S);
+    EyeProj E;
+    eye_project(views[v_begin].v, mx, my, mz, cov_ok, S, E);
     const float op = sc.opacity_dev[i];
-    double qe = kExtentQ;
-    {
-        const double t = (1.001 * 255.0) * (double)op;
-        int lo = 1, cnt_k = kExtentSteps;
-        while (cnt_k > 0) {
-            const int half = cnt_k >> 1;
-            if (s_exp[lo + half] < t) {
-                lo += half + 1;
-                cnt_k -= half + 1;
-            } else {
-                cnt_k = half;
-            }
-        }
-        if (lo <= kExtentSteps) qe = (double)lo / 8.0;
-    }
+    const double qe = footprint_q(op, s_exp);
     for (int vi = v_begin; vi < v_end; ++vi) {
         const DevView &dv = views[vi];
-        const a3fr_view &v = dv.v;
         const int64_t slot = (int64_t)vi * n + i;
+        LayerProj L;
+        layer_project(dv, E, qe, L);
         uint32_t cnt = 0;
-        bool visible = false;
-        if (front) {
-            const double limx = dv.limx, limy = dv.limy;  // (1.3 (W/2)) / fx, computed on the host
-            const double txc = fmin(fmax(xz, -limx), limx);
-            const double tyc = fmin(fmax(yz, -limy), limy);
-            const double j00 = v.fx / p2, j02 = -(j00 * txc);
-            const double j11 = v.fy / p2, j12 = -(j11 * tyc);
-            const double B00 = fma(j00, V.s00, j02 * V.s02), B01 = fma(j00, V.s01, j02 * V.s12),
-                         B02 = fma(j00, V.s02, j02 * V.s22);
-            const double B11 = fma(j11, V.s11, j12 * V.s12), B12 = fma(j11, V.s12, j12 * V.s22);
-            const double a = fma(B00, j00, B02 * j02) + kDilate;
-            const double b = fma(B01, j11, B02 * j12);
-            const double c = fma(B11, j11, B12 * j12) + kDilate;
-            const double det = fma(a, c, -(b * b));
-            if (det > 0.0) {
-                const double u = fma(v.fx, xz, v.cx), w = fma(v.fy, yz, v.cy);
-                const double ex = sqrt(qe * a), ey = sqrt(qe * c);
-                const double lox = u - ex, hix = u + ex, loy = w - ey, hiy = w + ey;
-                if (hix >= 0.5 && lox <= (double)v.width - 0.5 && hiy >= 0.5 && loy <= (double)v.height - 0.5) {
-                    double fx0 = ceil((lox - ((double)kTile - 0.5)) / (double)kTile);
-                    double fx1 = floor((hix - 0.5) / (double)kTile);
-                    double fy0 = ceil((loy - ((double)kTile - 0.5)) / (double)kTile);
-                    double fy1 = floor((hiy - 0.5) / (double)kTile);
-                    fx0 = fmax(fx0, 0.0); fx1 = fmin(fx1, (double)(dv.tiles_x - 1));
-                    fy0 = fmax(fy0, 0.0); fy1 = fmin(fy1, (double)(dv.tiles_y - 1));
-                    if (fx0 <= fx1 && fy0 <= fy1) {
-                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-                        visible = true;
-                        if (v.mask == A3FR_MASK_ALL) {
-                            cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-                        } else {
-                            // only the part of the rectangle that can hold active tiles
-                            const int cx0 = max(x0, dv.ax0), cx1 = min(x1, dv.ax1);
-                            const int cy0 = max(y0, dv.ay0), cy1 = min(y1, dv.ay1);
-                            const uint16_t *pre = row_prefix + dv.mask_off;
-                            if (cx0 <= cx1)
-                                for (int ty = cy0; ty <= cy1; ++ty) {
-                                    const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
-                                    cnt += (uint32_t)(rp[cx1 + 1] - rp[cx0]);
-                                }
-                        }
+        if (L.visible) {
+            if (dv.v.mask == A3FR_MASK_ALL) {
+                cnt = (uint32_t)((L.x1 - L.x0 + 1) * (L.y1 - L.y0 + 1));
+            } else {
+                // only the part of the rectangle that can hold active tiles
+                const int cx0 = max(L.x0, dv.ax0), cx1 = min(L.x1, dv.ax1);
+                const int cy0 = max(L.y0, dv.ay0), cy1 = min(L.y1, dv.ay1);
+                const uint16_t *pre = row_prefix + dv.mask_off;
+                if (cx0 <= cx1)
+                    for (int ty = cy0; ty <= cy1; ++ty) {
+                        const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
+                        cnt += (uint32_t)(rp[cx1 + 1] - rp[cx0]);
                     }
-                    // Only entries that emit keys are read downstream, except in a
-                    // view whose mask may grow later (remask): there every visible
-                    // entry keeps its rectangle and record for the recount.  In the
-                    // masked layers most visible Gaussians touch no active tile, so
-                    // this drops most of their stores.
-                    if (visible && (cnt != 0 || dv.remask)) {
-                        const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-                        depth[slot] = __float_as_uint((float)p2);
-                        rect[slot] = (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) |
-                                     ((uint64_t)(uint16_t)y0 << 32) | ((uint64_t)(uint16_t)y1 << 48);
-                        if (v.select) score[slot] = ((double)op * 3.141592653589793) * sqrt(det);
-                        // inverse covariance in LDL^T form, float64 then rounded once
-                        const double kLog2e = 1.4426950408889634;
-                        const double inv_c = 1.0 / c, inv_det = 1.0 / det;
-                        Record R;
-                        R.u = u; R.v = w;
-                        R.a2 = (float)(-0.5 * kLog2e * (c * inv_det));
-                        R.k = (float)(-(b * inv_c));
-                        R.c2 = (float)(-0.5 * kLog2e * inv_c);
-                        R.o = op;
-                        R.r = R.g = R.b = 0.0f;
-                        R.pad = 0.0f;
-                        rec[slot] = R;
-                    }
-                }
+            }
+            // the depth key of entries that emit keys (and of every visible
+            // entry of a view whose mask may grow); in the masked layers most
+            // visible Gaussians touch no active tile
+            if (cnt != 0 || dv.remask) {
+                depth[slot] = __float_as_uint((float)E.p2);
+                if (dv.v.select) score[(int64_t)dv.sel_slot * n + i] = ((double)op * 3.141592653589793) * sqrt(L.det);
             }
         }
         counts[slot] = cnt;
-        if (dv.remask && !visible) rect[slot] = kEmptyRect;
+        if (dv.rect_slot >= 0) rect[(int64_t)dv.rect_slot * n + i] = L.visible ? pack_rect(L) : kEmptyRect;
     }
 }
 
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       Record *rec, double *score, const double *exp_tab, hipStream_t s) {
+                       double *score, const double *exp_tab, hipStream_t s) {
     if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
-                       views, groups, row_prefix, counts, depth, rect, rec, score, exp_tab);
+                       views, groups, row_prefix, counts, depth, rect, score, exp_tab);
 }
 
 // View-dependent colour (degree <= 3 real SH, float32) of Gaussian i seen
@@ -339,46 +364,72 @@ __device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_vie
     rr.b = fmaxf(col[2], 0.0f);
 }
 
-// Colour of every entry that emits keys.
-// Grid-stride over the entries: the grid is capped, so that it does not
-// dispatch blocks for the slots past the device entry count (the grid is
-// sized on the host by the slot count m, the entries are known on the device).
-__global__ void __launch_bounds__(256) k_entry_colour(a3fr_scene sc, const DevView *__restrict__ views,
+// The blend record of every entry (Sec. 3.5: formed once and reused by every
+// tile and round that draws it): entry j is (view, Gaussian) slot ent[j]; its
+// key path is evaluated again with the same float64 operations as in
+// k_preprocess (so the rectangle and depth equal the ones its keys were
+// counted with), then the record -- centre in float64, inverse covariance in
+// LDL^T form for exp2, opacity, the view-dependent colour and the depth bits
+// -- and the rectangle are written at j, contiguously, and map[slot] = j.
+// Grid-stride over the entries (the device count, bounded by cap, the records'
+// capacity; a larger count raises bit 2 of err, when given, and leaves the
+// rest unwritten).
+__global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const DevView *__restrict__ views,
                                                       const uint32_t *__restrict__ ent, const uint32_t *n_ent,
-                                                      Record *__restrict__ rec) {
-    const int64_t E = *n_ent, n = sc.n;
+                                                      int64_t cap, const double *__restrict__ exp_tab,
+                                                      Record *__restrict__ rec, uint64_t *__restrict__ rect_e,
+                                                      uint32_t *__restrict__ map, uint32_t *err) {
+    __shared__ double s_exp[kExtentSteps + 1];
+    for (int k = threadIdx.x; k <= kExtentSteps; k += blockDim.x) s_exp[k] = exp_tab[k];
+    __syncthreads();
+    int64_t E = *n_ent;
+    if (E > cap) {
+        if (err && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4u);  // err NULL: the caller checks
+        E = cap;
+    }
+    const int64_t n = sc.n;
+    const double kLog2e = 1.4426950408889634;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = ent[j];
-        const int v = (int)(e / n);
-        colour_into(sc, views[v].v, e - (int64_t)v * n, rec[e]);
+        const uint32_t slot = ent[j];
+        const int v = (int)(slot / (uint64_t)n);
+        const int64_t i = (int64_t)slot - (int64_t)v * n;
+        const DevView &dv = views[v];
+        const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
+        Cov3 S;
+        const bool cov_ok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i],
+                                          sc.quat_dev[3 * n + i], sc.scale_dev[i], sc.scale_dev[n + i],
+                                          sc.scale_dev[2 * n + i], S);
+        EyeProj E3;
+        eye_project(dv.v, mx, my, mz, cov_ok, S, E3);
+        const float op = sc.opacity_dev[i];
+        LayerProj L;
+        layer_project(dv, E3, footprint_q(op, s_exp), L);
+        // an entry is visible in its view (it was counted so); the inverse
+        // covariance in LDL^T form, float64 then rounded once
+        const double inv_c = 1.0 / L.c, inv_det = 1.0 / L.det;
+        Record R;
+        R.u = L.u; R.v = L.w;
+        R.a2 = (float)(-0.5 * kLog2e * (L.c * inv_det));
+        R.k = (float)(-(L.b * inv_c));
+        R.c2 = (float)(-0.5 * kLog2e * inv_c);
+        R.o = op;
+        colour_into(sc, dv.v, i, R);
+        R.dbits = __float_as_uint((float)E3.p2);
+        rec[j] = R;
+        rect_e[j] = pack_rect(L);
+        map[slot] = (uint32_t)j;
     }
 }
 
-// Colour of every visible slot of the views whose mask changes after the
-// projection (their entries are coloured once, before the rounds that draw them).
-__global__ void __launch_bounds__(256) k_colour_remask(a3fr_scene sc, const DevView *__restrict__ views, int64_t n,
-                                                       const uint64_t *__restrict__ rect, Record *__restrict__ rec) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const DevView &dv = views[blockIdx.y];
-    if (i >= n || !dv.remask) return;
-    const int64_t slot = (int64_t)blockIdx.y * n + i;
-    if (rect[slot] == kEmptyRect) return;
-    colour_into(sc, dv.v, i, rec[slot]);
-}
-
-void launch_colour_remask(const a3fr_scene &sc, const DevView *views, int nv, int64_t n, const uint64_t *rect,
-                          Record *rec, hipStream_t s) {
-    if (n == 0 || nv == 0) return;
-    hipLaunchKernelGGL(k_colour_remask, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0, s, sc, views, n,
-                       rect, rec);
-}
-
-void launch_entry_colour(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, Record *rec, hipStream_t s, int max_blocks) {
-    if (m == 0) return;
-    int64_t blocks = (m + 255) / 256;
-    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
-    hipLaunchKernelGGL(k_entry_colour, dim3((unsigned)blocks), dim3(256), 0, s, sc, views, ent, n_ent, rec);
+void launch_entry_record(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
+                         int64_t m, int64_t cap, const double *exp_tab, Record *rec, uint64_t *rect_e, uint32_t *map,
+                         uint32_t *err, hipStream_t s) {
+    const int64_t work = m < cap ? m : cap;
+    if (work <= 0) return;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_entry_record, dim3((unsigned)blocks), dim3(256), 0, s, sc, views, ent, n_ent, cap, exp_tab,
+                       rec, rect_e, map, err);
 }
 
 }  // namespace a3fr

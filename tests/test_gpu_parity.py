@@ -70,15 +70,20 @@ def compare_stage_outputs(ctx, ref, views, n):
     counts = _u(ctx.inspect("counts", torch.int32), np.uint32).reshape(nv, n)
     vis = ref["vis"].astype(bool)
     np.testing.assert_array_equal(counts, ref["count"].astype(np.uint32) * vis)
-    # depth and rectangle are stored for the entries that emit keys (in a view
-    # with every tile active, every visible entry)
+    # the depth key is stored for every slot with keys; the rectangle (with the
+    # blend record) for every entry: a slot with keys that, in a selecting view,
+    # the periphery subset kept
     emits = vis & (ref["count"] > 0)
     depth = _u(ctx.inspect("depth", torch.int32), np.uint32).reshape(nv, n)
     np.testing.assert_array_equal(depth[emits], ref["depth_bits"][emits])
+    sel = np.array([vw.select for vw in views], dtype=bool)[:, None]
+    entries = emits & (~sel | (ref["keep"] != 0))
     rect = _u(ctx.inspect("rect", torch.int64), np.uint64).reshape(nv, n)
     r = ref["rect"].astype(np.uint64)
     want = r[..., 0] | (r[..., 1] << np.uint64(16)) | (r[..., 2] << np.uint64(32)) | (r[..., 3] << np.uint64(48))
-    np.testing.assert_array_equal(rect[emits], want[emits])
+    np.testing.assert_array_equal(rect[entries], want[entries])
+    # slots without an entry carry the empty rectangle (x0 = 1 > x1 = 0)
+    assert np.all(rect[~entries] == np.uint64(0x0000000100000001))
     act = ctx.inspect("active", torch.uint8).cpu().numpy()
     np.testing.assert_array_equal(act, ref["active"])
     if any(v.select for v in views):
