@@ -127,7 +127,7 @@ def main():
                     help="restrict the timed loops (for profiling runs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the graph, upsampler, fallback and gaze-trace legs")
-    ap.add_argument("--trace-window", type=int, default=16, help="frames per graph launch in the gaze-trace leg")
+    ap.add_argument("--trace-window", type=int, default=64, help="frames per graph launch in the gaze-trace leg")
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed steps of the differentiable-render training loop (0: skip)")
     ap.add_argument("--gazes", type=int, default=16, help="seeded gazes per workload in the workloads leg")
@@ -750,7 +750,7 @@ def trace_leg(pkg, synth, torch, args, n=3_000_000, n_frames=64):
     for cams, gz in flat:
         ctx.render_foveated(ds, cams, gz, fov, out[:len(cams)])
         keys = max(keys, ctx.get_counts()["n_keys"])
-    ctx.graph_capture(ds, flat[0][0], flat[0][1], fov, out, min(int(keys * 1.2) + 4096, (1 << 30) - 1))
+    ctx.graph_capture(ds, flat[0][0], flat[0][1], fov, out, min(int(keys * 1.2) + 4096, (1 << 32) - 1))
     for cams, gz in flat:
         ctx.graph_launch(cams, gz)
     ctx.sync()

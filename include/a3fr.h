@@ -188,8 +188,10 @@ a3fr_status a3fr_preprocess(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_v
  * Gaussian index), a stable LSD radix sort by tile id, then each tile's
  * [start, end) run.  Global tile id = the view's tile offset (views in order)
  * + row x tiles_x + column.
- * SYNCHRONISES once (reads the key count).  *n_keys_out (host, may be NULL)
- * receives the key count.  A3FR_ECAPACITY if the count reaches 2^30. */
+ * SYNCHRONISES once (reads the entry and key counts; the entries' blend
+ * records are formed meanwhile).  *n_keys_out (host, may be NULL) receives the
+ * key count.  A3FR_ECAPACITY if the count reaches 2^32 (keys are addressed by
+ * 32-bit positions; the sort's look-back counts are 64-bit). */
 a3fr_status a3fr_bin_sort(a3fr_ctx *ctx, int64_t *n_keys_out);
 
 /* Front-to-back blend of every active tile (Sec. 2.3, rasterization stage):
@@ -496,10 +498,15 @@ a3fr_status a3fr_autotune_blend(a3fr_ctx *ctx, int32_t reps, double *ms_out, int
  * selection, fallback, key emission and sort, blend, upsampler, composite,
  * with the context's options at this moment) into a HIP graph, for frames of
  * the same layout (image sizes, eyes, fovea parameters) and poses and gazes
- * given at launch.  No host read-back happens inside the graph: key buffers
- * hold max_keys keys and the key count stays on the device; a frame with more
- * keys is cut at max_keys and reported by a3fr_sync as A3FR_ECAPACITY.  One
- * eager warm-up frame (also written to out_dev) sizes the workspace first.
+ * given at launch (n_eyes = 2 x frames for a batch of stereo frames, as in
+ * a3fr_render_batch).  No host read-back happens inside the graph: key buffers
+ * hold max_keys keys (1 <= max_keys < 2^32) and the key count stays on the
+ * device; a frame with more keys is cut at max_keys and reported by a3fr_sync
+ * as A3FR_ECAPACITY.  An exact frame first counts this layout's keys K0 and
+ * entries E0 (A3FR_ECAPACITY if K0 > max_keys); the entries and their blend
+ * records get a capacity of E0 x max_keys / K0 (+1024), also reported as
+ * A3FR_ECAPACITY when exceeded.  A warm-up frame with those capacities then
+ * sizes the workspace (both frames are also written to out_dev).
  * scene and out_dev must stay valid at the same addresses while the graph is
  * replayed.  If the context is bound to the null stream it is rebound to an
  * internal non-blocking stream (stream capture needs one).  While a graph is

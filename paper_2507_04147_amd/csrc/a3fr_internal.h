@@ -71,10 +71,6 @@ constexpr int32_t kRoundFrozen = 2;
 // rectangle of a (view, Gaussian) slot that is not visible (x0 > x1): x0 = 1, x1 = 0, y0 = 1, y1 = 0
 constexpr uint64_t kEmptyRect = 0x0000000100000001ull;
 
-// Lookback status word of the onesweep sort: [31:30] flag, [29:0] count.
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1;
 
 // ---- upsampler ----
 // flat float32 parameter vector: W1 [32][3][3][3], b1 [32], W2 [32][32][3][3],

@@ -895,7 +895,8 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
         }
         c->n_ent_pass = (int64_t)E;
         if (n_keys_out) *n_keys_out = (int64_t)K;
-        if (K >= (uint64_t(1) << 30)) return fail(c, A3FR_ECAPACITY, "key count reached 2^30: " + std::to_string(K));
+        if (K >= (uint64_t(1) << 32))
+            return fail(c, A3FR_ECAPACITY, "key count reached 2^32: " + std::to_string(K));
     }
     TRY(ensure(c, c->rect_s, sizeof(uint64_t) * (size_t)E));
     TRY(ensure(c, c->esort, sizeof(uint32_t) * (size_t)E));
@@ -1677,7 +1678,7 @@ a3fr_status a3fr_graph_destroy(a3fr_ctx *c) {
 a3fr_status a3fr_graph_capture(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_camera *cams, const a3fr_gaze *gaze,
                                int32_t n_eyes, const a3fr_fovea *f, float *out, int64_t max_keys) {
     if (!c) return A3FR_EINVAL;
-    if (max_keys < 1 || max_keys >= (int64_t(1) << 30)) return fail(c, A3FR_EINVAL, "max_keys must be in [1, 2^30)");
+    if (max_keys < 1 || max_keys >= (int64_t(1) << 32)) return fail(c, A3FR_EINVAL, "max_keys must be in [1, 2^32)");
     if (c->profiling) return fail(c, A3FR_ENOTREADY, "turn profiling off before capturing a graph");
     if (!cams || !gaze || !f || !out || n_eyes < 1 || n_eyes > kMaxEyes)
         return fail(c, A3FR_EINVAL, "graph_capture: bad arguments");

@@ -64,9 +64,10 @@ __device__ __forceinline__ void hist_add(uint32_t (*h)[kRadix], int npass, uint3
     }
 }
 
-// The kernel also clears the look-back status words of the partitions the
-// passes will use (those of n keys, not of the n_max the workspace is sized
-// for): pass p's words start at status + p x parts_max x kRadix.
+// The kernel also clears the look-back status words (64-bit) of the
+// partitions the passes will use (those of n keys, not of the n_max the
+// workspace is sized for): pass p's words start at status + p x parts_max x
+// kRadix.
 __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
                                                             int npass, uint32_t *__restrict__ hist, int items,
                                                             int64_t parts_max) {
@@ -74,10 +75,11 @@ __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__re
     for (int j = threadIdx.x; j < kHistWaves * kMaxPasses * kRadix; j += blockDim.x) (&h[0][0][0])[j] = 0;
     const int64_t n = *n_dev;
     {
-        // status = hist + npass x kRadix + 8: 16-byte aligned with the workspace, and so is each pass's part
+        // status = hist + npass x kRadix + 8 (u32 words): 16-byte aligned with the workspace, and so is each
+        // pass's part; kRadix 64-bit words per partition = kRadix / 2 uint4
         uint4 *status = reinterpret_cast<uint4 *>(hist + (int64_t)npass * kRadix + 8);
         const int64_t parts = (n + (int64_t)kSortThreads * items - 1) / ((int64_t)kSortThreads * items);
-        const int64_t per = parts * (kRadix / 4), stride = parts_max * (kRadix / 4);
+        const int64_t per = parts * (kRadix / 2), stride = parts_max * (kRadix / 2);
         const uint4 z = {0u, 0u, 0u, 0u};
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npass * per;
              j += (int64_t)gridDim.x * blockDim.x) {
@@ -113,10 +115,13 @@ __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__re
     }
 }
 
-__device__ __forceinline__ uint32_t ld_status(const uint32_t *p) {
+// Look-back status word of a (partition, digit): [63:62] flag (1 aggregate,
+// 2 inclusive prefix), [61:0] count; 64-bit so that counts up to 2^32 - 1 keys fit.
+constexpr uint64_t kSt64Agg = 1ull << 62, kSt64Inc = 2ull << 62, kSt64Val = (1ull << 62) - 1;
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_status(uint32_t *p, uint32_t v) {
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -131,7 +136,7 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
                                                            const uint32_t *__restrict__ vin,
                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                            const uint32_t *n_dev, int shift,
-                                                           const uint32_t *__restrict__ ghist, uint32_t *status,
+                                                           const uint32_t *__restrict__ ghist, uint64_t *status,
                                                            uint32_t *counter, uint32_t *err) {
     constexpr int kSortPart = kSortThreads * kSortItems;
     __shared__ uint32_t s_part;
@@ -229,7 +234,7 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
             uint32_t c[kSortWaves];
 #pragma unroll
             for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
-            st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kFlagInc : kFlagAgg) | tot);
+            st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kSt64Inc : kSt64Agg) | (uint64_t)tot);
             uint32_t run = 0;
 #pragma unroll
             for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
@@ -265,7 +270,7 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
         }
         if (tid < kRadix) {
             const int d = tid;
-            uint32_t excl = 0;
+            uint64_t excl = 0;
             if (part > 0) {
                 // look back over a window of kWin predecessors at a time: the
                 // window's loads are independent, so one round trip to the
@@ -275,26 +280,26 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
                 uint32_t spins = 0;
                 bool found = false;
                 while (!found && p >= 0) {
-                    uint32_t st[kWin];
+                    uint64_t st[kWin];
 #pragma unroll
                     for (int q = 0; q < kWin; ++q)
-                        st[q] = (p - q >= 0) ? ld_status(&status[(p - q) * kRadix + d]) : kFlagInc;
+                        st[q] = (p - q >= 0) ? ld_status(&status[(p - q) * kRadix + d]) : kSt64Inc;
                     int used = 0;
 #pragma unroll
                     for (int q = 0; q < kWin; ++q) {
                         if (found || used < q) continue;  // stopped earlier in this window
-                        const uint32_t flag = st[q] >> 30;
+                        const uint32_t flag = (uint32_t)(st[q] >> 62);
                         if (flag == 0) continue;           // not published yet: reload from here
-                        excl += st[q] & kValMask;
+                        excl += st[q] & kSt64Val;
                         used = q + 1;
                         if (flag == 2) found = true;
                     }
                     p -= used;
                     if (!found && used == 0 && ++spins > (1u << 24)) { atomicOr(err, 1u); break; }
                 }
-                st_status(&status[(int64_t)part * kRadix + d], kFlagInc | (excl + tot));
+                st_status(&status[(int64_t)part * kRadix + d], kSt64Inc | (excl + tot));
             }
-            s_gbase[d] = s_gexcl[d] + excl;
+            s_gbase[d] = s_gexcl[d] + (uint32_t)excl;
         }
         __syncthreads();
         const int64_t rem = K - base;
@@ -311,10 +316,10 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
     }
 }
 
-// ws: one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256]
+// ws (u32 words): one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256 (u64)]
 // cleared by one fill, then the digit histograms of all passes.
 int64_t sort_workspace_words(int64_t n_max, int npass, int items) {
-    return sort_zero_words(npass) + (int64_t)npass * sort_partitions(n_max, items) * kRadix;
+    return sort_zero_words(npass) + 2 * (int64_t)npass * sort_partitions(n_max, items) * kRadix;
 }
 
 int64_t sort_zero_words(int npass) { return (int64_t)npass * kRadix + 8; }
@@ -334,7 +339,8 @@ void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint
                       int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
     const int nparts = sort_partitions(n_max, items);
     if (nparts == 0) return;
-    uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix, *status = ctr + 8;
+    uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix;
+    uint64_t *status = reinterpret_cast<uint64_t *>(ctr + 8);  // 8-byte aligned: npass x 1 KiB + 32 B in
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;

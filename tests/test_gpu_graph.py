@@ -200,3 +200,49 @@ def test_batched_frames_vs_oracle(pkg, variant):
     ctx.sync()
     compare_images(views, ref, rgb, T, last, ref["active"])
     ctx.close()
+
+
+def test_gaze_trace_64_frames_one_launch(pkg):
+    """The batched gaze trace as one launch: 64 stereo frames of the 3M-Gaussian
+    scene at 1832 x 1920 (128 eyes, 384 layer views: more than 2^30 (view,
+    Gaussian) slots and more than 2^30 keys, whose sort needs the 64-bit
+    look-back counts) in one a3fr_render_batch and in one captured graph.  Every
+    frame equals the frame rendered alone (the path the single-frame parity
+    tests check against the oracle), and the batch's keys are the sum of the
+    frames' keys."""
+    W, H = 1832, 1920
+    scene, _ = synth.foveated_stereo(n=3_000_000, seed=3)
+    ds = pkg.DeviceScene.from_host(scene)
+    n = scene.n
+    del scene
+    trace = synth.gaze_trace(seed=31, n_frames=64, width=W, height=H)
+    fov = pkg.fovea_struct(0.15 * W, 0.35 * W)
+    cb = pkg.Context()
+    out = torch.empty((64, 2, 3, H, W), device="cuda")
+    cb.render_batch(ds, trace, fov, out)
+    cb.sync()
+    K = cb.get_counts()["n_keys"]
+    print(f"64 frames: {384 * n} slots, {K} keys", flush=True)
+    assert 384 * n > (1 << 30) and K > (1 << 30)
+    cs = pkg.Context()
+    one = torch.empty((2, 3, H, W), device="cuda")
+    k_sum = 0
+    for f, (cams, gz) in enumerate(trace):
+        cs.render_foveated(ds, cams, gz, fov, one)
+        cs.sync()
+        k_sum += cs.get_counts()["n_keys"]
+        assert torch.equal(out[f], one), f
+    assert k_sum == K
+    cs.close()
+    # the same window from a captured graph (no host read-back), replayed twice
+    ref = out.clone()
+    cams = [c for fr in trace for c in fr[0]]
+    gzs = [g for fr in trace for g in fr[1]]
+    cb.graph_capture(ds, cams, gzs, fov, out.view(128, 3, H, W), int(K * 1.05))
+    for _ in range(2):
+        out.fill_(float("nan"))
+        cb.graph_launch(cams, gzs)
+        cb.sync()
+        assert torch.equal(out, ref)
+    cb.graph_destroy()
+    cb.close()
