@@ -338,7 +338,8 @@ def main():
         if "incremental" in legs:
             extra["incremental"] = incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options)
         if "amr" in legs:
-            extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed)
+            extra["amr"] = amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed,
+                                   layered=dict(ms_per_frame=ms_f, periphery_psnr_db=min(psnr) if psnr else None))
         if "pipeline" in legs:
             extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
         if "net_training" in legs:
@@ -638,22 +639,34 @@ def pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options, n_trials=6, t
     return res
 
 
-def amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed):
+def amr_leg(pkg, torch, ctx, ds, cams, gaze, rad, out_r, args, timed, layered=None):
     """AMR levels (Sec. 3.4) as the alternative foveation mode: one
-    full-resolution view per eye, 2 x 2 blocks rendered at 4, 3, 2, 1
-    positions within r_f, (r_f + r_m)/2, r_m and beyond; frame time and
-    periphery PSNR against the full-resolution render."""
+    full-resolution view per eye, 2 x 2 blocks rendered at 4..1 positions by
+    eccentricity (within r_f, (r_f + r_m)/2, r_m and beyond), by the tile's
+    Gaussian count (the densest quarter, half, three quarters of a view's tiles
+    at levels 4, 3, 2) or the smaller of the two; unrendered positions
+    inherited or interpolated.  Frame time and periphery PSNR against the
+    full-resolution render, beside the layered frame's (layered: its ms and
+    PSNR) for the equal-quality comparison."""
     W, H = cams[0].width, cams[0].height
     radii = (rad[0], 0.5 * (rad[0] + rad[1]), rad[1])
-    amr = pkg.amr_struct(*radii)
     out = torch.empty((2, 3, H, W), device="cuda")
-    step = lambda: ctx.render_amr(ds, cams, gaze, amr, out)
-    for _ in range(args.warmup):
-        step()
-    ms = timed(step, args.steps)
-    psnr = _psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r)
-    log(f"AMR frame {ms:.3f} ms, periphery PSNR {min(psnr):.2f} dB")
-    return dict(ms_per_frame=ms, radii=list(radii), periphery_psnr_db=min(psnr))
+    configs = [("eccentricity/inherit", 0, 0), ("eccentricity/interpolate", 0, 1), ("count/interpolate", 1, 1),
+               ("min/interpolate", 2, 1)]
+    res = dict(radii=list(radii), count_fractions=[0.25, 0.5, 0.75], layered=layered, modes={})
+    for name, mode, fill in configs:
+        amr = pkg.amr_struct(*radii, mode=mode, fill=fill)
+        step = lambda: ctx.render_amr(ds, cams, gaze, amr, out)
+        for _ in range(args.warmup):
+            step()
+        ms = timed(step, args.steps)
+        psnr = min(_psnr_outside_fovea(ctx, W, H, gaze, rad, out, out_r))
+        res["modes"][name] = dict(ms_per_frame=ms, periphery_psnr_db=psnr)
+        log(f"AMR {name}: frame {ms:.3f} ms, periphery PSNR {psnr:.2f} dB")
+    # the first configuration keeps the flat fields of the leg
+    res.update(ms_per_frame=res["modes"]["eccentricity/inherit"]["ms_per_frame"],
+               periphery_psnr_db=res["modes"]["eccentricity/inherit"]["periphery_psnr_db"])
+    return res
 
 
 def incremental_leg(pkg, synth, torch, ds, cams, fov, rad, method_options, n_trials=8):

@@ -282,18 +282,37 @@ a3fr_status a3fr_get_counts(a3fr_ctx *ctx, a3fr_counts *out);
 
 /* ---- AMR levels -------------------------------------------------------------- */
 
-/* Adaptive resolution by 2 x 2 pixel blocks (Sec. 3.4; Sec. 3.5: tiles
- * labelled with levels 1 to 4 by eccentricity): every tile of the
- * full-resolution view is split into 2 x 2 blocks; a tile of level L renders
- * the first L positions of each block (top-left, top-right, bottom-left,
- * bottom-right) with all Gaussians, and the other positions inherit the
- * rendered pixel above them, else the top-left one.  The level of a tile is 4
- * if its pixel-centre rectangle lies within r_level[0] of the gaze, 3 within
- * r_level[1], 2 within r_level[2], else 1 (0 <= r_level[0] <= r_level[1] <=
- * r_level[2], full-resolution pixels; the same distance test as
- * A3FR_MASK_DISC).  A level-4 tile equals a3fr_render_full's pixels. */
+/* Adaptive resolution by 2 x 2 pixel blocks (Sec. 3.4 and Fig. 8; Sec. 3.5:
+ * tiles labelled with levels 1 to 4): every tile of the full-resolution view
+ * is split into 2 x 2 blocks; a tile of level L renders the first L positions
+ * of each block (top-left, top-right, bottom-left, bottom-right) with all
+ * Gaussians; a level-4 tile equals a3fr_render_full's pixels.
+ *
+ * Levels (level_mode):
+ *   0  eccentricity: 4 if the tile's pixel-centre rectangle lies within
+ *      r_level[0] of the gaze, 3 within r_level[1], 2 within r_level[2], else 1
+ *      (0 <= r_level[0] <= r_level[1] <= r_level[2], full-resolution pixels;
+ *      the distance test of A3FR_MASK_DISC);
+ *   1  Gaussian count: the view's T tiles ranked by the number of keys that
+ *      land in them (descending, ties to the lower tile index y * tiles_x + x);
+ *      the first ceil(count_frac[0] T) have level 4, the first
+ *      ceil(count_frac[1] T) at least 3, the first ceil(count_frac[2] T) at
+ *      least 2 (0 <= count_frac[0] <= count_frac[1] <= count_frac[2] <= 1):
+ *      tiles with few Gaussians are smooth and take fewer samples (Sec. 3.6);
+ *   2  the smaller of the two.
+ * Unrendered positions (fill):
+ *   0  inherit the rendered pixel above them, else the top-left one;
+ *   1  interpolate the blocks' top-left samples (rendered at every level)
+ *      bilinearly at the pixel's position on that half-resolution grid, the
+ *      last block clamped: 0.5f * (a + b) between two samples (odd x or odd
+ *      y), 0.25f * ((a + b) + (c + d)) among four (a top-left, b top-right, c
+ *      bottom-left, d bottom-right neighbour sample), in float.
+ * Fields a mode does not use are ignored; other values are A3FR_EINVAL. */
 typedef struct {
     double r_level[3];
+    int32_t level_mode;
+    int32_t fill;
+    double count_frac[3];
 } a3fr_amr;
 
 /* One full-resolution view per eye (as a3fr_render_full) rendered with AMR
@@ -590,9 +609,10 @@ typedef enum {
     /* full-resolution fallback, after an a3fr_render_foveated with a3fr_set_fallback */
     A3FR_BUF_FB_ENERGY = 19,  /* float32 [2][n_tiles]: dropped, kept opacity mass per pixel (periphery views' tiles) */
     A3FR_BUF_FB_FLAGS = 20,   /* uint8 [n_tiles]: 1 = periphery tile taken from the full-resolution layer */
-    A3FR_BUF_SEL_STATE = 21   /* uint32 [n_selecting_views][8]: periphery select of each selecting view:
+    A3FR_BUF_SEL_STATE = 21,  /* uint32 [n_selecting_views][8]: periphery select of each selecting view:
                                  visible count, kept count k, rank left in the chosen bucket, mode (0 select,
                                  1 keep all, 2 keep none), level-1 and level-2 buckets, candidates, 0 */
+    A3FR_BUF_AMR_LEVELS = 22  /* uint8 [n_tiles]: level 1..4 of every tile, after a3fr_render_amr */
 } a3fr_buffer;
 
 /* Device-to-device copy of an intermediate into dst_dev (at most max_bytes);

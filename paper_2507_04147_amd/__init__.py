@@ -25,7 +25,7 @@ TILE = 16
 
 BUF = dict(counts=0, depth=1, rect=2, offsets=3, keys=4, vals=5, sorted_keys=6, sorted_vals=7, ranges=8,
            active=9, keep=10, records=11, depth_order=12, net_x0=13, net_a1=14, net_a2=15, net_g3=16, net_g2=17,
-           net_g1=18, fb_energy=19, fb_flags=20, sel_state=21)
+           net_g1=18, fb_energy=19, fb_flags=20, sel_state=21, amr_levels=22)
 NET_PARAMS = 24016
 BLEND_VARIANTS = 15
 
@@ -92,12 +92,21 @@ class Fovea_(C.Structure):
 
 
 class Amr_(C.Structure):
-    _fields_ = [("r_level", C.c_double * 3)]
+    _fields_ = [("r_level", C.c_double * 3), ("level_mode", C.c_int32), ("fill", C.c_int32),
+                ("count_frac", C.c_double * 3)]
 
 
-def amr_struct(r4, r3, r2) -> Amr_:
+AMR_ECCENTRICITY, AMR_COUNT, AMR_MIN = 0, 1, 2
+AMR_INHERIT, AMR_INTERPOLATE = 0, 1
+
+
+def amr_struct(r4=0.0, r3=0.0, r2=0.0, mode=AMR_ECCENTRICITY, fill=AMR_INHERIT, fracs=(0.25, 0.5, 0.75)) -> Amr_:
+    """a3fr_amr: eccentricity radii (r4 <= r3 <= r2, pixels), level mode,
+    fill of the unrendered positions, count fractions (f4 <= f3 <= f2)."""
     a = Amr_()
     a.r_level[0], a.r_level[1], a.r_level[2] = float(r4), float(r3), float(r2)
+    a.level_mode, a.fill = int(mode), int(fill)
+    a.count_frac[0], a.count_frac[1], a.count_frac[2] = (float(f) for f in fracs)
     return a
 
 
@@ -385,7 +394,8 @@ class Context:
                                               C.byref(fovea), _dp(out)))
 
     def render_amr(self, scene: DeviceScene, cams, gazes, amr: Amr_, out):
-        """Full-resolution views with AMR levels 4..1 by distance from the gaze."""
+        """Full-resolution views with AMR levels 4..1 (eccentricity, Gaussian
+        count or the smaller of the two; amr_struct)."""
         self.generation += 1
         self._scene = scene
         arr = (Camera_ * len(cams))(*[camera_struct(c) for c in cams])

@@ -220,9 +220,16 @@ constexpr int kBlendVariants = A3FR_BLEND_VARIANTS;
 constexpr int kBlendDefault = 1;      // batch 64, 4 x 1 pixels per lane, grid
 constexpr int kBlendWsWords = 68;
 BlendVariant blend_variant(int k);
-// AMR levels of every tile of full views (gaze in the views): r4 >= distance: 4 positions of each 2 x 2 block, ...
+// AMR of full views (gaze in the views): tile levels (eccentricity radii r, count fractions f, mode 0
+// eccentricity / 1 count / 2 the smaller), then the level-L blend of the first L positions of each 2 x 2 block,
+// the others inherited or interpolated
+struct AmrLevels {
+    double r[3], f[3];
+    int mode, interp;
+};
 void launch_blend_amr(const DevView *views, int nv, int64_t ntiles, const uint32_t *ranges, const uint32_t *vals,
-                      const Record *rec, int64_t n, double r4, double r3, double r2, float *rgb, hipStream_t s);
+                      const Record *rec, int64_t n, const AmrLevels &a, uint64_t *thr /* [nv][3] */,
+                      uint8_t *lv /* [ntiles] */, float *rgb, int64_t max_pixels /* largest view */, hipStream_t s);
 void launch_blend(const BlendArgs &a, int variant, hipStream_t s);
 void launch_blend_order(const uint8_t *active, const uint32_t *ranges, int64_t ntiles, uint32_t *ws, uint32_t *order,
                         hipStream_t s);

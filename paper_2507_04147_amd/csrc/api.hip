@@ -127,6 +127,7 @@ struct a3fr_ctx {
     struct FbPair { int pv, fv; double r_mid; };
     std::vector<FbPair> fb_plan;           // set by a3fr_render_foveated for its a3fr_preprocess
     bool fb_last = false;                  // the last preprocess ran the fallback steps
+    bool amr_last = false;                 // the last frame was a3fr_render_amr (tile levels in amr_lv)
     // incremental foveal rounds (a3fr_incremental_*)
     bool inc_mode = false;                 // layouts made now: remask fovea and mid layers, apply inc_flags
     std::vector<int32_t> inc_flags;        // round flags per view of the next layout
@@ -171,6 +172,7 @@ struct a3fr_ctx {
     a3fr_fovea g_fovea{};
     int n_cus = 256;
     DevBuf blend_ws, blend_order, tune_img;
+    DevBuf amr_thr, amr_lv;    // AMR count thresholds [views][3], tile levels [tiles]
     int sh_degree = 0;
     int64_t K = 0;
 };
@@ -385,7 +387,7 @@ void a3fr_destroy(a3fr_ctx *c) {
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
                       &c->net_g1c, &c->net_sse, &c->fb_energy, &c->fb_flags, &c->fb_diff, &c->fb_part, &c->inc_periph, &c->inc_done, &c->fb_count, &c->blend_ws,
-                      &c->blend_order, &c->tune_img,
+                      &c->blend_order, &c->tune_img, &c->amr_thr, &c->amr_lv,
                       &c->sort_status, &c->ranges, &c->layers, &c->sse_part,
                       &c->sse_cnt, &c->keys_e, &c->vals_e, &c->pair_count, &c->cum, &c->chunk_start};
     for (DevBuf *b : bufs)
@@ -732,6 +734,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
                       keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream, true); }
     c->fb_last = false;
+    c->amr_last = false;
     if (do_fb) {
         // periphery error estimate; flagged tiles join the full-resolution layer's mask; recount it
         StageTimer t_(c, A3FR_STAGE_FALLBACK);
@@ -1102,9 +1105,14 @@ a3fr_status a3fr_render_amr(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_cam
     if (!c) return A3FR_EINVAL;
     if (!cams || !gaze || !amr || !out || n_eyes < 1 || n_eyes > kMaxEyes)
         return fail(c, A3FR_EINVAL, "render_amr: bad arguments");
-    const double *r = amr->r_level;
-    if (!(r[0] >= 0.0) || !(r[1] >= r[0]) || !(r[2] >= r[1]) || !is_fin(r[2]))
+    const double *r = amr->r_level, *f = amr->count_frac;
+    if (amr->level_mode < 0 || amr->level_mode > 2) return fail(c, A3FR_EINVAL, "render_amr: level_mode must be 0, 1 or 2");
+    if (amr->fill < 0 || amr->fill > 1) return fail(c, A3FR_EINVAL, "render_amr: fill must be 0 or 1");
+    if (amr->level_mode != 1 && (!(r[0] >= 0.0) || !(r[1] >= r[0]) || !(r[2] >= r[1]) || !is_fin(r[2])))
         return fail(c, A3FR_EINVAL, "render_amr: radii must satisfy 0 <= r_level[0] <= r_level[1] <= r_level[2]");
+    if (amr->level_mode != 0 && (!(f[0] >= 0.0) || !(f[1] >= f[0]) || !(f[2] >= f[1]) || !(f[2] <= 1.0)))
+        return fail(c, A3FR_EINVAL,
+                    "render_amr: fractions must satisfy 0 <= count_frac[0] <= count_frac[1] <= count_frac[2] <= 1");
     std::vector<a3fr_view> v(n_eyes);
     for (int e = 0; e < n_eyes; ++e) {
         view_from_camera(cams[e], e, v[e]);
@@ -1115,9 +1123,22 @@ a3fr_status a3fr_render_amr(a3fr_ctx *c, const a3fr_scene *scene, const a3fr_cam
     const a3fr_status st = a3fr_preprocess(c, scene, v.data(), n_eyes, 1, 1);
     TRY(st);
     TRY(a3fr_bin_sort(c, nullptr));
+    TRY(ensure(c, c->amr_thr, sizeof(uint64_t) * 3 * (size_t)c->nv));
+    TRY(ensure(c, c->amr_lv, (size_t)c->ntiles));
+    int64_t max_pixels = 0;
+    for (int e = 0; e < n_eyes; ++e) max_pixels = std::max(max_pixels, (int64_t)cams[e].width * cams[e].height);
+    AmrLevels a{};
+    const bool ecc = amr->level_mode != 1;  // radii unused by the count levels
+    for (int q = 0; q < 3; ++q) {
+        a.r[q] = ecc ? r[q] : 0.0;
+        a.f[q] = f[q];
+    }
+    a.mode = amr->level_mode;
+    a.interp = amr->fill;
     StageTimer t_(c, A3FR_STAGE_BLEND);
     launch_blend_amr(P<DevView>(c->views), c->nv, c->ntiles, P<uint32_t>(c->ranges), sorted_vals(c), P<Record>(c->rec),
-                     0, r[0], r[1], r[2], out, c->stream);
+                     0, a, P<uint64_t>(c->amr_thr), P<uint8_t>(c->amr_lv), out, max_pixels, c->stream);
+    c->amr_last = true;
     return check_launch(c, "render_amr");
 }
 
@@ -1922,6 +1943,9 @@ a3fr_status a3fr_inspect(a3fr_ctx *c, a3fr_buffer which, void *dst, int64_t max_
         case A3FR_BUF_FB_FLAGS:
             if (!c->fb_last) return fail(c, A3FR_ENOTREADY, "no fallback in the last frame");
             src = c->fb_flags.p; bytes = c->ntiles; break;
+        case A3FR_BUF_AMR_LEVELS:
+            if (!c->amr_last) return fail(c, A3FR_ENOTREADY, "the last frame was not an AMR frame");
+            src = c->amr_lv.p; bytes = c->ntiles; break;
         case A3FR_BUF_SEL_STATE:
             src = P<uint32_t>(c->sel) + select_hist_words(c->nsel); bytes = 32 * (int64_t)c->nsel; break;
         default: return fail(c, A3FR_EINVAL, "unknown buffer");

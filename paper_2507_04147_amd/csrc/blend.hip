@@ -233,10 +233,103 @@ __device__ __forceinline__ int amr_level(const a3fr_view &v, int tx, int ty, dou
     return d2 <= r4 * r4 ? 4 : d2 <= r3 * r3 ? 3 : d2 <= r2 * r2 ? 2 : 1;
 }
 
+// ---- AMR levels by Gaussian count ------------------------------------------
+// A tile's count key orders the tiles of a view by (number of Gaussians
+// descending, tile index ascending): (count << 32) | ~local tile index.
+__device__ __forceinline__ uint64_t amr_count_key(const uint32_t *ranges, int64_t gt, int64_t t) {
+    const uint32_t c = ranges[2 * gt + 1] - ranges[2 * gt];
+    return ((uint64_t)c << 32) | (uint64_t)(0xffffffffu - (uint32_t)t);
+}
+
+// Number of a view's T tiles that reach the level of fraction f: ceil(f T).
+__device__ __forceinline__ int64_t amr_count_k(double f, int64_t T) {
+    const int64_t k = (int64_t)ceil(f * (double)T);
+    return k < T ? k : T;
+}
+
+// One block per view: for each fraction f of (f4, f3, f2), the k-th largest
+// count key with k = ceil(f T) (T tiles of the view), by an MSD radix select
+// over the 64-bit keys (8-bit digits, a block histogram per digit); a tile
+// reaches that level iff its key is at least the threshold (k = 0: none does;
+// the threshold is not written).
+__global__ void __launch_bounds__(1024) k_amr_thresholds(const DevView *__restrict__ views,
+                                                         const uint32_t *__restrict__ ranges, double f4, double f3,
+                                                         double f2, uint64_t *__restrict__ thr) {
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ uint32_t s_krem;
+    const DevView &dv = views[blockIdx.x];
+    const int64_t T = (int64_t)dv.tiles_x * dv.tiles_y;
+    const double fr[3] = {f4, f3, f2};
+    for (int q = 0; q < 3; ++q) {
+        const int64_t k = amr_count_k(fr[q], T);
+        if (k <= 0) continue;  // uniform over the block
+        if (threadIdx.x == 0) {
+            s_prefix = 0ull;
+            s_krem = (uint32_t)k;
+        }
+        __syncthreads();
+        for (int d = 7; d >= 0; --d) {
+            for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0u;
+            __syncthreads();
+            const uint64_t prefix = s_prefix;
+            for (int64_t t = threadIdx.x; t < T; t += blockDim.x) {
+                const uint64_t key = amr_count_key(ranges, dv.tile_off + t, t);
+                if (d == 7 || (key >> (8 * (d + 1))) == prefix) atomicAdd(&hist[(key >> (8 * d)) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t above = 0;
+                const uint32_t kr = s_krem;
+                for (int b = 255; b >= 0; --b) {
+                    if (above + hist[b] >= kr) {
+                        s_prefix = (prefix << 8) | (uint64_t)b;
+                        s_krem = kr - above;
+                        break;
+                    }
+                    above += hist[b];
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) thr[3 * blockIdx.x + q] = s_prefix;
+        __syncthreads();
+    }
+}
+
+// Level of every tile: eccentricity (mode 0), Gaussian count (1) or the
+// smaller of the two (2).
+__global__ void __launch_bounds__(256) k_amr_levels(const DevView *__restrict__ views, int nv, int64_t ntiles,
+                                                    const uint32_t *__restrict__ ranges, double r4, double r3,
+                                                    double r2, double f4, double f3, double f2, int mode,
+                                                    const uint64_t *__restrict__ thr,
+                                                    uint8_t *__restrict__ lv) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gt >= ntiles) return;
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    const DevView &dv = views[lo];
+    const int64_t lt = gt - dv.tile_off;
+    const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
+    const int ecc = amr_level(dv.v, tx, ty, r4, r3, r2);
+    int cnt = 1;
+    if (mode != 0) {
+        const uint64_t key = amr_count_key(ranges, gt, lt);
+        const int64_t T = (int64_t)dv.tiles_x * dv.tiles_y;
+        const double fr[3] = {f4, f3, f2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cnt += amr_count_k(fr[q], T) > 0 && key >= thr[3 * lo + q];
+    }
+    lv[gt] = (uint8_t)(mode == 0 ? ecc : mode == 1 ? cnt : min(ecc, cnt));
+}
+
 template <int NP>
 __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, int ty, uint32_t start, uint32_t end,
                                          const uint32_t *__restrict__ vals, const Record *__restrict__ rec, int64_t n,
-                                         float *__restrict__ rgb) {
+                                         float *__restrict__ rgb, bool interp) {
     constexpr int BATCH = 64;
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
     __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
@@ -314,7 +407,8 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
         }
         __syncthreads();
     }
-    // rendered positions, then the inherited ones
+    // rendered positions, then the inherited ones (with interpolation, only the
+    // rendered ones: k_amr_interp fills the others from the top-left samples)
     const int64_t HW = (int64_t)W * H;
     float *img = rgb + 3 * dv.img_off;
     float vr[4], vg[4], vb[4];
@@ -328,7 +422,7 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int x = x0 + bx + (k & 1), y = y0 + by + (k >> 1);
-        if (x < W && y < H) {
+        if (x < W && y < H && (k < NP || !interp)) {
             const int64_t pix = (int64_t)y * W + x;
             img[pix] = vr[k];
             img[HW + pix] = vg[k];
@@ -340,7 +434,8 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
 __global__ void __launch_bounds__(64) k_blend_amr(const DevView *__restrict__ views, int nv,
                                                   const uint32_t *__restrict__ ranges,
                                                   const uint32_t *__restrict__ vals, const Record *__restrict__ rec,
-                                                  int64_t n, double r4, double r3, double r2, float *__restrict__ rgb) {
+                                                  int64_t n, const uint8_t *__restrict__ lv, int interp,
+                                                  float *__restrict__ rgb) {
     const int64_t gt = blockIdx.x;
     int lo = 0, hi = nv - 1;
     while (lo < hi) {
@@ -351,19 +446,62 @@ __global__ void __launch_bounds__(64) k_blend_amr(const DevView *__restrict__ vi
     const int64_t lt = gt - dv.tile_off;
     const int tx = (int)(lt % dv.tiles_x), ty = (int)(lt / dv.tiles_x);
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
-    switch (amr_level(dv.v, tx, ty, r4, r3, r2)) {  // wave-uniform
-        case 4: amr_tile<4>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
-        case 3: amr_tile<3>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
-        case 2: amr_tile<2>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
-        default: amr_tile<1>(dv, lo, tx, ty, start, end, vals, rec, n, rgb); break;
+    const bool ip = interp != 0;
+    switch (lv[gt]) {  // wave-uniform
+        case 4: amr_tile<4>(dv, lo, tx, ty, start, end, vals, rec, n, rgb, ip); break;
+        case 3: amr_tile<3>(dv, lo, tx, ty, start, end, vals, rec, n, rgb, ip); break;
+        case 2: amr_tile<2>(dv, lo, tx, ty, start, end, vals, rec, n, rgb, ip); break;
+        default: amr_tile<1>(dv, lo, tx, ty, start, end, vals, rec, n, rgb, ip); break;
+    }
+}
+
+// Interpolation of the unrendered positions of view blockIdx.y: the bilinear
+// interpolation of the 2 x 2 blocks' top-left samples (rendered at every level)
+// at the pixel's position on that half-resolution grid, clamped at the last
+// block: 0.5 (a + b) between two samples, 0.25 ((a + b) + (c + d)) among four.
+__global__ void __launch_bounds__(256) k_amr_interp(const DevView *__restrict__ views, const uint8_t *__restrict__ lv,
+                                                    float *__restrict__ rgb) {
+    const DevView &dv = views[blockIdx.y];
+    const int W = dv.v.width, H = dv.v.height;
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= (int64_t)W * H) return;
+    const int x = (int)(pix % W), y = (int)(pix / W);
+    const int k = (x & 1) + 2 * (y & 1);
+    if (k < (int)lv[dv.tile_off + (int64_t)(y / kTile) * dv.tiles_x + x / kTile]) return;  // rendered
+    const int bx = x >> 1, by = y >> 1, BX = (W + 1) >> 1, BY = (H + 1) >> 1;
+    const int x0 = 2 * bx, y0 = 2 * by, x1 = 2 * min(bx + 1, BX - 1), y1 = 2 * min(by + 1, BY - 1);
+    const int64_t HW = (int64_t)W * H;
+    float *img = rgb + 3 * dv.img_off;
+    for (int ch = 0; ch < 3; ++ch) {
+        const float *c = img + ch * HW;
+        const float a = c[(int64_t)y0 * W + x0];
+        float v;
+        if ((x & 1) && (y & 1)) {
+            const float b = c[(int64_t)y0 * W + x1], cc = c[(int64_t)y1 * W + x0], d = c[(int64_t)y1 * W + x1];
+            v = 0.25f * ((a + b) + (cc + d));
+        } else if (x & 1) {
+            v = 0.5f * (a + c[(int64_t)y0 * W + x1]);
+        } else {
+            v = 0.5f * (a + c[(int64_t)y1 * W + x0]);
+        }
+        img[ch * HW + pix] = v;
     }
 }
 
 void launch_blend_amr(const DevView *views, int nv, int64_t ntiles, const uint32_t *ranges, const uint32_t *vals,
-                      const Record *rec, int64_t n, double r4, double r3, double r2, float *rgb, hipStream_t s) {
+                      const Record *rec, int64_t n, const AmrLevels &a, uint64_t *thr, uint8_t *lv, float *rgb,
+                      int64_t max_pixels, hipStream_t s) {
     if (ntiles == 0) return;
-    hipLaunchKernelGGL(k_blend_amr, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, ranges, vals, rec, n, r4, r3,
-                       r2, rgb);
+    if (a.mode != 0)
+        hipLaunchKernelGGL(k_amr_thresholds, dim3((unsigned)nv), dim3(1024), 0, s, views, ranges, a.f[0], a.f[1],
+                           a.f[2], thr);
+    hipLaunchKernelGGL(k_amr_levels, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, views, nv, ntiles,
+                       ranges, a.r[0], a.r[1], a.r[2], a.f[0], a.f[1], a.f[2], a.mode, thr, lv);
+    hipLaunchKernelGGL(k_blend_amr, dim3((unsigned)ntiles), dim3(64), 0, s, views, nv, ranges, vals, rec, n, lv,
+                       a.interp, rgb);
+    if (a.interp && max_pixels > 0)
+        hipLaunchKernelGGL(k_amr_interp, dim3((unsigned)((max_pixels + 255) / 256), (unsigned)nv), dim3(256), 0, s,
+                           views, lv, rgb);
 }
 
 // Quadrant schedule: a block of four waves per tile, wave w owning the 8 x 8
