@@ -191,7 +191,7 @@ a3fr_status a3fr_preprocess(a3fr_ctx *ctx, const a3fr_scene *scene, const a3fr_v
  * SYNCHRONISES once (reads the entry and key counts; the entries' blend
  * records are formed meanwhile).  *n_keys_out (host, may be NULL) receives the
  * key count.  A3FR_ECAPACITY if the count reaches 2^32 (keys are addressed by
- * 32-bit positions; the sort's look-back counts are 64-bit). */
+ * 32-bit positions). */
 a3fr_status a3fr_bin_sort(a3fr_ctx *ctx, int64_t *n_keys_out);
 
 /* Front-to-back blend of every active tile (Sec. 2.3, rasterization stage):
@@ -546,12 +546,13 @@ typedef enum {
     A3FR_STAGE_SELECT = 2,     /* periphery radix select */
     A3FR_STAGE_SCAN = 3,       /* compaction of visible entries; key offsets in depth order */
     A3FR_STAGE_EMIT = 4,       /* key emission */
-    A3FR_STAGE_SORT_HIST = 5,  /* digit histograms of the tile-id sort */
-    A3FR_STAGE_SORT_PASS = 6,  /* one onesweep pass of the tile-id sort (one launch per 8-bit digit) */
+    A3FR_STAGE_SORT_HIST = 5,  /* per-partition digit counts and their scan, one launch per pass of the
+                                  tile-id sort */
+    A3FR_STAGE_SORT_PASS = 6,  /* the scatter of one pass of the tile-id sort (one launch per 8-bit digit) */
     A3FR_STAGE_RANGES = 7,     /* tile ranges */
     A3FR_STAGE_BLEND = 8,      /* front-to-back blend */
     A3FR_STAGE_COMPOSITE = 9,  /* foveated composite */
-    A3FR_STAGE_DEPTH_SORT = 10,/* radix sort of the visible entries by depth (histograms + 4 passes) */
+    A3FR_STAGE_DEPTH_SORT = 10,/* radix sort of the visible entries by depth (histograms + 4 onesweep passes) */
     A3FR_STAGE_ACTIVATE = 11,  /* device activation */
     A3FR_STAGE_BLEND_BWD = 12, /* reverse blend (including the clear of its accumulators) */
     A3FR_STAGE_PREPROCESS_BWD = 13, /* reverse projection, colour and activation */
@@ -565,7 +566,7 @@ typedef struct {
     int64_t launches[A3FR_STAGE_COUNT]; /* timed intervals per stage */
     double ms[A3FR_STAGE_COUNT];        /* summed event time per stage */
     int64_t sort_keys;                  /* keys sorted by tile id, summed over the timed bin_sorts */
-    int64_t sort_passes;                /* onesweep passes of the tile-id sorts, summed */
+    int64_t sort_passes;                /* scatter passes of the tile-id sorts, summed */
     int64_t blend_pairs;                /* evaluated (pixel, Gaussian) pairs of the timed blends */
 } a3fr_profile;
 

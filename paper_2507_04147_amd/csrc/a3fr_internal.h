@@ -174,20 +174,27 @@ void launch_vals_to_index(const uint32_t *vals, int64_t K, const uint32_t *rent,
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t cnt, uint32_t *out, hipStream_t s);
 void launch_scatter_dense_u64(const uint64_t *src, const uint32_t *ent, int64_t cnt, uint64_t *out, hipStream_t s);
 void launch_scatter_dense_rec(const Record *src, const uint32_t *ent, int64_t cnt, Record *out, hipStream_t s);
-// keys per thread of the onesweep passes: 16 (8192-key partitions) for the
+// keys per thread of the radix passes: 16 (8192-key partitions) for the
 // tile-id sort, 4 (2048-key partitions) for the entry depth sort
 constexpr int kSortItemsLarge = 16;
 constexpr int kSortItemsSmall = 4;
-int sort_partitions(int64_t n, int items);
-int64_t sort_workspace_words(int64_t n_max, int npass, int items);
-// leading words of the workspace (digit counts, pass counters) that must be zero
-// before launch_sort_prepare; the histogram kernel clears the status words itself
-int64_t sort_zero_words(int npass);
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
-                         uint32_t *ws, hipStream_t s,
-                         bool zeroed = false /* the first sort_zero_words(npass) words already zero */);
-void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
+// entry depth sort (onesweep): workspace of a sort of at most n_max keys in
+// npass passes (u32 words); its leading words must be zero before
+// launch_onesweep_prepare (which clears them unless zeroed)
+int64_t onesweep_workspace_words(int64_t n_max, int npass);
+int64_t onesweep_zero_words(int npass);
+void launch_onesweep_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
+                             hipStream_t s, bool zeroed = false);
+void launch_onesweep_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                          int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s);
+// tile-id sort (count, scan, scatter): workspace for at most n_max keys (u32
+// words); its first sort_zero_words(n_max) words must be zero before the first
+// pass (every pass leaves them zero).  Pass p sorts *n_dev keys by digit p.
+int64_t sort_workspace_words(int64_t n_max);
+int64_t sort_zero_words(int64_t n_max);
+void launch_sort_count(const uint32_t *ki, const uint32_t *n_dev, int64_t n_max, int p, uint32_t *ws, hipStream_t s);
+void launch_sort_scatter(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                         int64_t n_max, int p, const uint32_t *ws, hipStream_t s);
 void launch_ranges(const uint32_t *tiles, int64_t K, const uint32_t *K_dev, int64_t ntiles, uint32_t *ranges,
                    hipStream_t s);
 // forward blend: variants (LDS batch depth x lane pixel block x schedule), all bit-identical

@@ -483,7 +483,7 @@ a3fr_status a3fr_sync(a3fr_ctx *c) {
             HIPCHECK(c, hipStreamSynchronize(c->stream));
             return fail(c, A3FR_ECAPACITY, "key or entry count exceeded the graph's capacity (frame incomplete)");
         }
-        if (flag & 1u) return fail(c, A3FR_EDEVICE, "radix sort look-back gave up waiting (internal error)");
+        if (flag & 1u) return fail(c, A3FR_EDEVICE, "a scan's look-back gave up waiting (internal error)");
     }
     return A3FR_OK;
 }
@@ -630,7 +630,7 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dval_a, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dval_b, sizeof(uint32_t) * m));
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words(m, 4, kSortItemsSmall)));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)onesweep_workspace_words(m, 4)));
 
     // ---- one upload through pinned staging:
     // [views | row views | row ys | selecting views | groups | exp(k/16) table of the footprint bound]
@@ -727,7 +727,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
             add(c->fb_diff.p, 2 * dwords);
         }
         add(c->block_sums.p, 2 * scan_workspace_words(m));
-        add(c->sort_status.p, sort_zero_words(4));
+        add(c->sort_status.p, onesweep_zero_words(4));
         launch_zero_segs(z, c->stream);
     }
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
@@ -832,13 +832,13 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     }
     {   // stable sort of the entries by depth (4 passes: even, ends in the "a" buffers)
         StageTimer t_(c, A3FR_STAGE_DEPTH_SORT);
-        launch_sort_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, kSortItemsSmall, P<uint32_t>(c->sort_status),
-                            c->stream, zeroed);
+        launch_onesweep_prepare(P<uint32_t>(c->dkey_a), sc_n_ent(c->scalars), m, 4, P<uint32_t>(c->sort_status),
+                                c->stream, zeroed);
         uint32_t *ki = P<uint32_t>(c->dkey_a), *ko = P<uint32_t>(c->dkey_b);
         uint32_t *vi = P<uint32_t>(c->dval_a), *vo = P<uint32_t>(c->dval_b);
         for (int p = 0; p < 4; ++p) {
-            launch_sort_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, kSortItemsSmall, p, P<uint32_t>(c->sort_status),
-                             sc_err(c->scalars), c->stream);
+            launch_onesweep_pass(ki, vi, ko, vo, sc_n_ent(c->scalars), m, 4, p, P<uint32_t>(c->sort_status),
+                                 sc_err(c->scalars), c->stream);
             std::swap(ki, ko);
             std::swap(vi, vo);
         }
@@ -913,7 +913,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < c->ntiles) ++tile_bits;
     const int npass = (tile_bits + 7) / 8;
-    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K, npass, kSortItemsLarge)));
+    TRY(ensure(c, c->sort_status, sizeof(uint32_t) * (size_t)sort_workspace_words((int64_t)K)));
     TRY(ensure(c, c->ranges, sizeof(uint32_t) * 2 * c->ntiles));
     const DevView *dv = P<DevView>(c->views);
     if (cap_mode)
@@ -934,7 +934,7 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
                     P<uint16_t>(c->row_list), P<uint32_t>(c->cum), P<uint32_t>(c->chunk_start),
                     P<uint32_t>(c->keys_a), P<uint32_t>(c->vals_a), (int64_t)K,
                     cap_mode ? sc_n_keys(c->scalars) : nullptr, P<uint32_t>(c->sort_status),
-                    (int)sort_zero_words(npass), c->stream);
+                    (int)sort_zero_words((int64_t)K), c->stream);
     }
     if (c->keep_emission && !cap_mode) {
         TRY(ensure(c, c->keys_e, sizeof(uint32_t) * K));
@@ -946,16 +946,17 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
     uint32_t *vi = P<uint32_t>(c->vals_a), *vo = P<uint32_t>(c->vals_b);
     bool in_b = false;
     if (K > 1) {
-        {
-            StageTimer t_(c, A3FR_STAGE_SORT_HIST);
-            // the digit counts and pass counters were cleared by the emission's first kernel
-            launch_sort_prepare(ki, sc_n_keys(c->scalars), (int64_t)K, npass, kSortItemsLarge, P<uint32_t>(c->sort_status),
-                                c->stream, true);
-        }
+        // the tickets and group sums were cleared by the emission's first kernel
         for (int p = 0; p < npass; ++p) {
-            StageTimer t_(c, A3FR_STAGE_SORT_PASS);
-            launch_sort_pass(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, npass, kSortItemsLarge, p,
-                             P<uint32_t>(c->sort_status), sc_err(c->scalars), c->stream);
+            {
+                StageTimer t_(c, A3FR_STAGE_SORT_HIST);
+                launch_sort_count(ki, sc_n_keys(c->scalars), (int64_t)K, p, P<uint32_t>(c->sort_status), c->stream);
+            }
+            {
+                StageTimer t_(c, A3FR_STAGE_SORT_PASS);
+                launch_sort_scatter(ki, vi, ko, vo, sc_n_keys(c->scalars), (int64_t)K, p, P<uint32_t>(c->sort_status),
+                                    c->stream);
+            }
             std::swap(ki, ko);
             std::swap(vi, vo);
             in_b = !in_b;

@@ -697,7 +697,7 @@ constexpr int kEmitBlock = 512;
 // at j; and its slot, record index and rectangle (rect_e[r]) are copied to
 // esort[j], rsort[j] and rect_s[j], so the emission reads them next to the
 // offsets instead of through the indices.  Block 0 also clears
-// zero[0, zero_words) (the key sort's digit counts and pass counters).
+// zero[0, zero_words) (the key sort's tickets and group sums).
 __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ ent,

@@ -11,32 +11,57 @@
 //   2. the keys, emitted entry by entry in that depth order, are sorted by
 //      tile id alone; stability keeps each tile's keys in (depth, index) order.
 //
-// Both use the same onesweep LSD kernel for gfx950 (8-bit digits):
-//  * one coalesced pass builds the digit histograms of every pass;
-//  * one kernel per digit: a block takes the next partition id from an atomic
-//    counter (so it only waits on partitions that have already started), loads
-//    its keys wave-striped (lane-consecutive, coalesced), ranks them stably
-//    inside each wave with 8 ballots (lanes sharing a digit) and a popcount of
-//    the lower lanes, publishes its per-digit counts, resolves its global
-//    digit offsets by decoupled look-back over the preceding partitions, and
-//    scatters through LDS so that consecutive threads write consecutive
-//    addresses of each digit run.
-// The element count is read from device memory, so a launch may be sized by
-// an upper bound; blocks past the last partition exit at once.
+// Both are LSD radix sorts with 8-bit digits whose blocks rank their keys
+// stably inside each wave with 8 ballots (lanes sharing a digit) and a
+// popcount of the lower lanes, and scatter them through LDS so that
+// consecutive threads write consecutive addresses of each digit run.  They
+// differ in how a partition learns where its digits start, chosen by size:
+//  * the entry sort (a few hundred 2048-key partitions): onesweep, one kernel
+//    per digit after one histogram pass; a block takes the next partition id
+//    from an atomic counter, publishes its digit counts and resolves its
+//    offsets by decoupled look-back over the preceding partitions;
+//  * the tile-id sort (a thousand and more 8192-key partitions): there the
+//    look-back's chain of inclusive prefixes -- a device-coherent round trip
+//    per window of predecessors, with every resident block waiting on it --
+//    costs more than a second read of the keys, so each pass is reduce, then
+//    scan, then scatter: a count kernel writes every partition's digit counts,
+//    a scan kernel sums them by groups of partitions and its last block turns
+//    the group sums into the start of every (group, digit), and the scatter
+//    kernel adds the counts of the earlier partitions of its group
+//    (independent loads, issued while its keys load).  No block waits for
+//    another.  (Summing the groups with device-scope atomics in the count
+//    kernel instead is several times slower than the scan kernel.)
+// The key count is read from device memory, so every launch may be sized by
+// an upper bound.
+#include <algorithm>
+
 #include "a3fr_internal.h"
 
 namespace a3fr {
 
 constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;      // 8
-// keys per thread (kSortItemsLarge / kSortItemsSmall): the entry depth sort's
-// few hundred thousand keys in 8192-key partitions would leave most compute
-// units idle with one long partition each, so it runs 2048-key partitions
 constexpr int kRadix = 256;
 constexpr int kDigitWaves = kRadix / kWave;           // waves holding one digit per lane
 constexpr int kMaxPasses = 4;                         // 32-bit keys
+constexpr int kGroup = 32;                            // partitions per scan group (tile-id sort)
+constexpr int kScanBatch = 16;                        // independent loads per round trip in the scan
 
-int sort_partitions(int64_t n, int items) {
+static int sort_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// ==========================================================================
+// entry depth sort: onesweep
+// ==========================================================================
+static int onesweep_partitions(int64_t n, int items) {
     const int64_t part = (int64_t)kSortThreads * items;
     return (int)((n + part - 1) / part);
 }
@@ -318,16 +343,17 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
 
 // ws (u32 words): one workspace [hist npass x 256 | counters 8 | status npass x partitions x 256 (u64)]
 // cleared by one fill, then the digit histograms of all passes.
-int64_t sort_workspace_words(int64_t n_max, int npass, int items) {
-    return sort_zero_words(npass) + 2 * (int64_t)npass * sort_partitions(n_max, items) * kRadix;
+int64_t onesweep_workspace_words(int64_t n_max, int npass) {
+    return onesweep_zero_words(npass) + 2 * (int64_t)npass * onesweep_partitions(n_max, kSortItemsSmall) * kRadix;
 }
 
-int64_t sort_zero_words(int npass) { return (int64_t)npass * kRadix + 8; }
+int64_t onesweep_zero_words(int npass) { return (int64_t)npass * kRadix + 8; }
 
-void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, int items,
-                         uint32_t *ws, hipStream_t s, bool zeroed) {
-    const int nparts = sort_partitions(n_max, items);
-    if (!zeroed) launch_fill_u32(ws, 0u, sort_zero_words(npass), s);
+void launch_onesweep_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_max, int npass, uint32_t *ws,
+                             hipStream_t s, bool zeroed) {
+    constexpr int items = kSortItemsSmall;
+    const int nparts = onesweep_partitions(n_max, items);
+    if (!zeroed) launch_fill_u32(ws, 0u, onesweep_zero_words(npass), s);
     if (nparts == 0) return;
     int hblocks = (int)((n_max + kHistThreads * 16 - 1) / (kHistThreads * 16));
     if (hblocks > 512) hblocks = 512;
@@ -335,30 +361,298 @@ void launch_sort_prepare(const uint32_t *keys, const uint32_t *n_dev, int64_t n_
                        (int64_t)nparts);
 }
 
-void launch_sort_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
-                      int64_t n_max, int npass, int items, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
-    const int nparts = sort_partitions(n_max, items);
+void launch_onesweep_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                          int64_t n_max, int npass, int p, uint32_t *ws, uint32_t *err, hipStream_t s) {
+    constexpr int items = kSortItemsSmall;
+    const int nparts = onesweep_partitions(n_max, items);
     if (nparts == 0) return;
     uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix;
     uint64_t *status = reinterpret_cast<uint64_t *>(ctr + 8);  // 8-byte aligned: npass x 1 KiB + 32 B in
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
-    // persistent blocks: LDS per block ~74 KB (16 items) or ~26 KB (4 items)
-    const int resident = cus * (items == kSortItemsSmall ? 4 : 2);
+    // persistent blocks: LDS per block ~26 KB
+    const int resident = sort_cus() * 4;
     const int grid = nparts < resident ? nparts : resident;
-    if (items == kSortItemsSmall)
-        hipLaunchKernelGGL(k_onesweep<kSortItemsSmall>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
-                           n_dev, 8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p,
-                           err);
-    else
-        hipLaunchKernelGGL(k_onesweep<kSortItemsLarge>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo,
-                           n_dev, 8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p,
-                           err);
+    hipLaunchKernelGGL(k_onesweep<items>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev,
+                       8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
+}
+
+
+// ==========================================================================
+// tile-id sort: count (with the scan in its last block), scatter
+// ==========================================================================
+static int64_t tile_sort_parts(int64_t n) { return (n + kSortThreads * kSortItemsLarge - 1) / (kSortThreads * kSortItemsLarge); }
+static int64_t tile_sort_groups(int64_t parts) { return (parts + kGroup - 1) / kGroup; }
+
+// workspace (u32 words): [tickets 8 | cnt parts x 256 | gsum groups x 256 | base groups x 256];
+// the tickets start at zero and every pass leaves them so
+int64_t sort_zero_words(int64_t /*n_max*/) { return 8; }
+int64_t sort_workspace_words(int64_t n_max) {
+    const int64_t parts = tile_sort_parts(n_max);
+    return 8 + (parts + 2 * tile_sort_groups(parts)) * kRadix;
+}
+
+// ---- count -------------------------------------------------------------------
+// Neighbouring keys often share a digit (tile ids of one Gaussian's rectangle,
+// depths of one depth range), and LDS atomics of a wave on one address
+// serialise: when every valid key of a wave's step has the same digit, one lane
+// adds the count.
+template <int I>
+__global__ void __launch_bounds__(kSortThreads) k_sort_count(const uint32_t *__restrict__ keys,
+                                                             const uint32_t *n_dev, int shift,
+                                                             uint32_t *__restrict__ cnt) {
+    constexpr int kPart = kSortThreads * I;
+    static_assert(I % 4 == 0, "four keys per load");
+    __shared__ uint32_t h[kSortWaves][kRadix];
+    const int64_t K = *n_dev;
+    const int64_t P = (K + kPart - 1) / kPart;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t part = blockIdx.x; part < P; part += gridDim.x) {
+        __syncthreads();  // the previous partition's totals are read
+        for (int j = threadIdx.x; j < kSortWaves * kRadix; j += kSortThreads) (&h[0][0])[j] = 0;
+        __syncthreads();
+        const int64_t base = part * kPart;
+#pragma unroll
+        for (int it = 0; it < I / 4; ++it) {
+            const int64_t j = base + ((int64_t)it * kSortThreads + threadIdx.x) * 4;
+            uint4 k4 = {0u, 0u, 0u, 0u};
+            if (j + 3 < K) {
+                k4 = *reinterpret_cast<const uint4 *>(keys + j);
+            } else {
+                if (j < K) k4.x = keys[j];
+                if (j + 1 < K) k4.y = keys[j + 1];
+                if (j + 2 < K) k4.z = keys[j + 2];
+            }
+            const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool valid = j + q < K;
+                const uint64_t vm = __ballot(valid);
+                if (vm == 0) continue;  // wave-uniform
+                const uint32_t d = (kk[q] >> shift) & 255u;
+                const int first = __ffsll((unsigned long long)vm) - 1;
+                const uint32_t d0 = __shfl(d, first, 64);
+                const uint64_t same = __ballot(valid && d == d0);
+                if (same == vm) {
+                    if (lane == first) atomicAdd(&h[w][d0], (uint32_t)__popcll(vm));
+                } else if (valid) {
+                    atomicAdd(&h[w][d], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) c += h[q][d];
+            cnt[part * kRadix + d] = c;
+        }
+    }
+}
+
+// ---- scan --------------------------------------------------------------------
+// Block g (256 threads, one per digit) of a grid of at least one block per
+// group; every block takes a ticket, the last one writes
+// base[g][d] = sum over digits d' < d of the totals + sum over groups g' < g of gsum[g'][d].
+// The group sums pass between blocks through device-coherent stores and loads.
+__global__ void __launch_bounds__(256) k_sort_scan(const uint32_t *__restrict__ cnt, const uint32_t *n_dev,
+                                                   int part_keys, uint32_t *gsum, uint32_t *__restrict__ base,
+                                                   uint32_t *ticket) {
+    const int64_t K = *n_dev;
+    const int64_t P = (K + part_keys - 1) / part_keys;
+    const int64_t G = (P + kGroup - 1) / kGroup;
+    const int d = threadIdx.x;
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        uint32_t c[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) c[q] = cnt[min(g * kGroup + q, P - 1) * kRadix + d];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) s += (g * kGroup + q < P) ? c[q] : 0u;
+        __hip_atomic_store(&gsum[g * kRadix + d], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    __shared__ uint32_t s_last;
+    __syncthreads();
+    if (d == 0)
+        s_last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last || G == 0) return;
+    __threadfence();
+    // totals of every digit, kScanBatch independent loads per round trip
+    uint32_t tot = 0;
+    for (int64_t q0 = 0; q0 < G; q0 += kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (int q = 0; q < kScanBatch; ++q)
+            v[q] = __hip_atomic_load(&gsum[min(q0 + q, G - 1) * kRadix + d], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int q = 0; q < kScanBatch; ++q) tot += (q0 + q < G) ? v[q] : 0u;
+    }
+    // exclusive scan over the digits
+    __shared__ uint32_t s_ws[kDigitWaves];
+    const int lane = d & 63, w = d >> 6;
+    uint32_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_ws[w] = inc;
+    __syncthreads();
+    uint32_t run = inc - tot;
+    for (int q = 0; q < w; ++q) run += s_ws[q];
+    for (int64_t q0 = 0; q0 < G; q0 += kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (int q = 0; q < kScanBatch; ++q)
+            v[q] = __hip_atomic_load(&gsum[min(q0 + q, G - 1) * kRadix + d], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int q = 0; q < kScanBatch; ++q)
+            if (q0 + q < G) {
+                base[(q0 + q) * kRadix + d] = run;
+                run += v[q];
+            }
+    }
+    if (d == 0) *ticket = 0u;  // every block has taken its ticket: ready for the next use
+}
+
+// ---- scatter -----------------------------------------------------------------
+// at least 4 waves per SIMD (<= 128 VGPRs): two 8-wave blocks per compute unit
+template <int I>
+__global__ void __launch_bounds__(kSortThreads, 4) k_sort_scatter(const uint32_t *__restrict__ kin,
+                                                                  const uint32_t *__restrict__ vin,
+                                                                  uint32_t *__restrict__ kout,
+                                                                  uint32_t *__restrict__ vout, const uint32_t *n_dev,
+                                                                  int shift, const uint32_t *__restrict__ cnt,
+                                                                  const uint32_t *__restrict__ base) {
+    constexpr int kPart = kSortThreads * I;
+    __shared__ uint32_t s_wh[kSortWaves][kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_wsum[kDigitWaves];
+    __shared__ uint32_t s_k[kPart];
+    __shared__ uint32_t s_v[kPart];
+    const uint32_t K = *n_dev;
+    const int P = (int)(((int64_t)K + kPart - 1) / kPart);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int part = blockIdx.x; part < P; part += gridDim.x) {
+        __syncthreads();  // the previous partition is done with the LDS
+        for (int j = tid; j < kSortWaves * kRadix; j += kSortThreads) (&s_wh[0][0])[j] = 0;
+        // positions in 32 bits: b0 + l for a local index l < rem = K - b0 (no overflow near 2^32 keys)
+        const uint32_t b0 = (uint32_t)part * kPart, rem = K - b0;
+        // global start of this partition's digits: its group's start plus the
+        // earlier partitions of the group (independent of the keys)
+        if (tid < kRadix) {
+            const int p0 = part / kGroup * kGroup;
+            uint32_t c[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) c[q] = cnt[(int64_t)min(p0 + q, part) * kRadix + tid];
+            uint32_t o = base[(int64_t)(part / kGroup) * kRadix + tid];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) o += (p0 + q < part) ? c[q] : 0u;
+            s_gbase[tid] = o;
+        }
+        const uint32_t l0 = (uint32_t)(w * (I * kWave) + lane);  // local index of item 0; item it adds it x 64
+        uint32_t key[I], rk[I], val[I];
+#pragma unroll
+        for (int it = 0; it < I; ++it) key[it] = l0 + it * kWave < rem ? kin[b0 + l0 + it * kWave] : 0u;
+        __syncthreads();
+        // stable rank inside each wave: lanes with the same digit, then the
+        // wave's running count of that digit
+#pragma unroll
+        for (int it = 0; it < I; ++it) {
+            const bool valid = l0 + it * kWave < rem;
+            const uint32_t d = (key[it] >> shift) & 255u;
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            const uint32_t below = (uint32_t)__popcll(m & lt_mask);
+            uint32_t prior = 0;
+            if (valid) prior = s_wh[w][d];
+            rk[it] = prior + below;
+            if (valid && below == 0) s_wh[w][d] = prior + (uint32_t)__popcll(m);
+        }
+        // the values are loaded now: their round trip overlaps the digit
+        // bookkeeping, and they are not live during the ranking
+#pragma unroll
+        for (int it = 0; it < I; ++it) val[it] = l0 + it * kWave < rem ? vin[b0 + l0 + it * kWave] : 0u;
+        __syncthreads();
+        // threads 0..255 = digits: per-wave exclusive offsets, block-local digit starts
+        if (tid < kRadix) {
+            const int d = tid;
+            uint32_t c[kSortWaves], tot = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
+            uint32_t inc = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            if (lane == 63) s_wsum[w] = inc;
+            s_lstart[d] = inc - tot;
+        }
+        __syncthreads();
+        if (tid < kRadix) {
+            uint32_t pre = 0;
+#pragma unroll
+            for (int q = 0; q < kDigitWaves; ++q) if (q < w) pre += s_wsum[q];
+            s_lstart[tid] += pre;
+            s_gbase[tid] -= s_lstart[tid];  // global position = s_gbase[d] + local position (mod 2^32)
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < I; ++it) {
+            if (l0 + it * kWave < rem) {
+                const uint32_t dg = (key[it] >> shift) & 255u;
+                const uint32_t lp = s_lstart[dg] + s_wh[w][dg] + rk[it];
+                s_k[lp] = key[it];
+                s_v[lp] = val[it];
+            }
+        }
+        __syncthreads();
+        const int nvalid = rem < (uint32_t)kPart ? (int)rem : kPart;
+        for (int j = tid; j < nvalid; j += kSortThreads) {
+            const uint32_t kk = s_k[j];
+            const uint32_t g = s_gbase[(kk >> shift) & 255u] + (uint32_t)j;
+            if (g < K) {
+                kout[g] = kk;
+                vout[g] = s_v[j];
+            }
+        }
+    }
+}
+
+void launch_sort_count(const uint32_t *ki, const uint32_t *n_dev, int64_t n_max, int p, uint32_t *ws, hipStream_t s) {
+    const int64_t parts = tile_sort_parts(n_max);
+    if (parts == 0) return;
+    const int64_t groups = tile_sort_groups(parts);
+    uint32_t *cnt = ws + 8, *gsum = cnt + parts * kRadix, *base = gsum + groups * kRadix;
+    const int grid = (int)std::min<int64_t>(parts, 16 * sort_cus());
+    hipLaunchKernelGGL(k_sort_count<kSortItemsLarge>, dim3(grid), dim3(kSortThreads), 0, s, ki, n_dev, 8 * p, cnt);
+    const int sgrid = (int)std::min<int64_t>(groups, 4096);
+    hipLaunchKernelGGL(k_sort_scan, dim3(sgrid), dim3(kRadix), 0, s, cnt, n_dev, kSortThreads * kSortItemsLarge, gsum,
+                       base, ws + p);
+}
+
+void launch_sort_scatter(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, uint32_t *vo, const uint32_t *n_dev,
+                         int64_t n_max, int p, const uint32_t *ws, hipStream_t s) {
+    const int64_t parts = tile_sort_parts(n_max);
+    if (parts == 0) return;
+    const int64_t groups = tile_sort_groups(parts);
+    const uint32_t *cnt = ws + 8, *base = cnt + (parts + groups) * kRadix;
+    const int grid = (int)std::min<int64_t>(parts, 16 * sort_cus());
+    hipLaunchKernelGGL(k_sort_scatter<kSortItemsLarge>, dim3(grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev,
+                       8 * p, cnt, base);
 }
 
 // ------------------------------------------------------------------------
