@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "stereo frames/s @1M Gaussians, foveated vs full-res on GPU, periphery PSNR≥30dB"
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 FP32_VECTOR_PEAK_TF = 157.3   # MI355X FP32 vector (packed) peak
-SORT_BYTES_PER_KEY_PASS = 16  # tile-id sort: read key (4) + value (4), write key (4) + value (4)
+SORT_BYTES_PER_KEY_PASS = 16  # tile-id sort scatter: read key (4) + value (4), write key (4) + value (4)
 BLEND_FLOPS_PER_PAIR = 18
 # HBM traffic per dispatch from the hardware counters: rocprofv3 --pmc
 # FETCH_SIZE, then WRITE_SIZE (KiB per dispatch) of the profiled benchmark
@@ -49,38 +49,48 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="b9a74ea12a52acdfd3a21cf45e81263eff19c40749a36e2b51301f4a95819574",
-                  kib={"32,4x1,grid": (5986.2, 21750.0), "64,4x1,grid": (7002.2, 21750.0),
-                       "128,4x1,grid": (10132.4, 21750.0), "32,2x2,grid": (5991.6, 21750.0),
-                       "64,2x2,grid": (6995.4, 21750.0), "128,2x2,grid": (10133.3, 21750.0),
-                       "32,4x1,queue": (5533.1, 21831.2), "64,4x1,queue": (6518.6, 21866.3),
-                       "128,4x1,queue": (9377.5, 21884.2), "32,2x2,queue": (5517.7, 21755.1),
-                       "64,2x2,queue": (6469.1, 21811.4), "128,2x2,queue": (9382.8, 21968.6),
-                       "64,8x8q,grid": (10377.3, 21750.0), "128,8x8q,grid": (18923.1, 21750.0),
-                       "256,8x8q,grid": (35774.1, 21750.0)}),
+                  sha256="a2d61a91ad4fef5b0f1662ae2e118e836388d67974e48691cb785e1a1ffb460e",
+                  kib={"32,4x1,grid": (5909.6, 21750.0),
+                       "32,4x1,queue": (5473.7, 21873.8),
+                       "32,2x2,grid": (5909.2, 21750.0),
+                       "32,2x2,queue": (5414.6, 21630.0),
+                       "64,4x1,grid": (6907.2, 21750.0),
+                       "64,4x1,queue": (6390.5, 21797.6),
+                       "64,2x2,grid": (6910.0, 21750.0),
+                       "64,2x2,queue": (6331.6, 21699.4),
+                       "128,4x1,grid": (9960.5, 21750.0),
+                       "128,4x1,queue": (9215.9, 21896.9),
+                       "128,2x2,grid": (9961.5, 21750.0),
+                       "128,2x2,queue": (9229.0, 21855.2),
+                       "64,8x8q,grid": (10182.7, 21750.0),
+                       "128,8x8q,grid": (18047.5, 21750.0),
+                       "256,8x8q,grid": (32717.9, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="e25e4eb0efedef2841c5fc8d1b9f4e92e64b1be01373667307f388b9fe7fa370",
-                       kib={"k_preprocess": (43145.0, 162834.9)}),
+                       sha256="e36cdf2b292155e69603c7d44e316b864543986f0acccded73573d137f859577",
+                       kib={"k_preprocess": (43205.2, 84981.3)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="e25e4eb0efedef2841c5fc8d1b9f4e92e64b1be01373667307f388b9fe7fa370",
-                   kib={"k_entry_colour": (49271.2, 13557.5)}),
-    "sort_pass": dict(source="csrc/sort.hip",  # the two tile-id passes of the key sort
-                      sha256="7d7634a17e8b9014540af3f74c77957c4493eddf386d1e488f377f9c9c9da7fe",
-                      kib={"k_onesweep": (39684.9, 78171.9)}),
+                   sha256="e36cdf2b292155e69603c7d44e316b864543986f0acccded73573d137f859577",
+                   kib={"k_entry_record": (155623.6, 33778.9)}),
+    "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
+                      sha256="6eda886ea81a26b72659dcccd6ad1bd920764a0207e494910c07eb8981b6a4e2",
+                      kib={"k_sort_scatter": (40104.2, 81889.4)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
-# views): the float32 mean, scale and quaternion of every Gaussian (40 B) once
-# per eye and the opacity of the visible ones (4 B); a 4-byte key count per
-# (view, Gaussian) slot; per slot that emits keys its depth (4), rectangle (8)
-# and 48-byte record, plus an 8-byte score in the periphery (selecting) view.
-PREPROCESS_READ_PER_GAUSSIAN = 40
-PREPROCESS_READ_PER_VISIBLE = 4
+# views): the float32 mean, scale, quaternion and opacity of every Gaussian
+# (44 B) once per frame; a 4-byte key count per (view, Gaussian) slot; the
+# 4-byte depth key of every slot that emits keys, an 8-byte score in the
+# periphery (selecting) views, and an 8-byte rectangle for every slot of the
+# views that keep them (with the fallback: each eye's fovea, recounted, and
+# periphery, whose mass map reads them).
+PREPROCESS_READ_PER_GAUSSIAN = 44
 PREPROCESS_WRITE_PER_SLOT = 4
-PREPROCESS_WRITE_PER_EMITTING = 4 + 8 + 48
+PREPROCESS_WRITE_PER_EMITTING = 4
 PREPROCESS_WRITE_PER_SCORE = 8
-# view-dependent colour, per entry that emits keys: its index (4), mean (12),
-# SH coefficients (4 x 3 x 16 at degree 3) read, colour (12) written
-COLOUR_BYTES_PER_ENTRY = 4 + 12 + 192 + 12
+PREPROCESS_WRITE_PER_RECT_SLOT = 8
+# record pass, per entry (a kept slot that emits keys): its slot index (4), the
+# Gaussian's geometry (44) and SH coefficients (4 x 3 x 16 at degree 3) read;
+# its 48-byte blend record, 8-byte rectangle and 4-byte slot-to-entry map written
+RECORD_BYTES_PER_ENTRY = 4 + 44 + 48 + 8 + 4
 # key emission (chunk starts + emission): per entry its key offset (4), index
 # (4) and rectangle (8) read; per key its tile id and Gaussian index written
 EMIT_BYTES_PER_ENTRY = 4 + 4 + 8
@@ -171,9 +181,12 @@ def main():
     nets = {w: load_net(pkg, torch, w) for w in ("inside", "outside")}
     theta, use_net = nets["inside"]["theta"], nets["inside"]["use"]
 
+    fallback = pkg.FALLBACK_NET if use_net else pkg.FALLBACK_BILINEAR
+    fallback_on = math.isfinite(fallback[0])
+
     def method_options(c):
         c.set_upsampler(theta if use_net else None)
-        c.set_fallback(*(pkg.FALLBACK_NET if use_net else pkg.FALLBACK_BILINEAR))
+        c.set_fallback(*fallback)
 
     method_options(ctx)
     out_f = torch.empty((2, 3, H, W), device="cuda")
@@ -296,11 +309,12 @@ def main():
             stages[name].update(bound="hbm", achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS,
                                 bytes_per_launch=bytes_per_frame * args.steps / v["launches"])
 
-        hbm_stage("preprocess", 2 * PREPROCESS_READ_PER_GAUSSIAN * scene.n + PREPROCESS_READ_PER_VISIBLE * n_periph +
-                  PREPROCESS_WRITE_PER_SLOT * cnt.numel() + PREPROCESS_WRITE_PER_EMITTING * sum(nz) +
-                  PREPROCESS_WRITE_PER_SCORE * n_periph)
+        rect_views = 2 * len(cams) if fallback_on else 0  # each eye's fovea and periphery views
+        hbm_stage("preprocess", PREPROCESS_READ_PER_GAUSSIAN * scene.n + PREPROCESS_WRITE_PER_SLOT * cnt.numel() +
+                  PREPROCESS_WRITE_PER_EMITTING * sum(nz) + PREPROCESS_WRITE_PER_SCORE * n_periph +
+                  PREPROCESS_WRITE_PER_RECT_SLOT * rect_views * scene.n)
         sh_bytes = 4 * int(np.prod(scene.sh.shape[:-1]))  # [coef][channel][n]
-        hbm_stage("colour", n_ent * (COLOUR_BYTES_PER_ENTRY - 192 + sh_bytes))
+        hbm_stage("colour", n_ent * (RECORD_BYTES_PER_ENTRY + sh_bytes))
         hbm_stage("emit", EMIT_BYTES_PER_ENTRY * n_ent + EMIT_BYTES_PER_KEY * K)
         if st["net"]["launches"]:
             flop = net_frame_flop(np, W, H, gaze, rad[1])
@@ -312,7 +326,7 @@ def main():
         d = stages[dom]
         variant = tuned["variant"] if tuned else 1  # the library's default variant when not tuned
         key = {"blend": ",".join(str(x) for x in pkg.blend_variant_desc(variant)),
-               "preprocess": "k_preprocess", "colour": "k_entry_colour", "sort_pass": "k_onesweep"}[dom]
+               "preprocess": "k_preprocess", "colour": "k_entry_record", "sort_pass": "k_sort_scatter"}[dom]
         traffic = pmc_traffic(dom, key)
         if d["bound"] == "hbm":
             roofline = dict(kernel=dom, bound="hbm", achieved=d["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",

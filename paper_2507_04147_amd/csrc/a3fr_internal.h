@@ -116,10 +116,10 @@ void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const i
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
                        uint8_t *done /* [tiles] nullable: incremental rounds */, hipStream_t s);
 // counts [nv][n] every slot; depth [nv][n] of entries; rect [n_rect_views][n] (views with rect_slot >= 0);
-// score [nsel][n] (selecting views, by sel_slot)
+// score [nsel][n] (selecting views, by sel_slot); cum: the masked views' summed-area tables (launch_mask_cum)
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
-                       const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       double *score, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
+                       const uint32_t *cum, uint32_t *counts, uint32_t *depth, uint64_t *rect, double *score,
+                       const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
 // records and rectangles of the entries ent[0 .. min(*n_ent, cap)), at the entry's index; map[slot] = index;
 // a count above cap raises bit 2 of err
 void launch_entry_record(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,

@@ -679,7 +679,7 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
                       P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), nullptr, c->stream);
       if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
-    launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint16_t>(c->row_prefix), P<uint32_t>(c->counts),
+    launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint32_t>(c->cum), P<uint32_t>(c->counts),
                       P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), c->d_exp_tab, c->stream); }
     // the fallback pairs (periphery view, its eye's full-resolution view); their
     // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of

@@ -264,7 +264,7 @@ __device__ __forceinline__ uint64_t pack_rect(const LayerProj &L) {
 // (k_entry_record), once the entries are known.
 __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views,
                                                     const int32_t *__restrict__ groups,
-                                                    const uint16_t *__restrict__ row_prefix,
+                                                    const uint32_t *__restrict__ cum,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
                                                     uint64_t *__restrict__ rect, double *__restrict__ score,
                                                     const double *__restrict__ exp_tab) {
@@ -294,15 +294,16 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
             if (dv.v.mask == A3FR_MASK_ALL) {
                 cnt = (uint32_t)((L.x1 - L.x0 + 1) * (L.y1 - L.y0 + 1));
             } else {
-                // only the part of the rectangle that can hold active tiles
+                // active tiles in the rectangle from the view's summed-area
+                // table (cum[ty][tx]: active tiles in rows < ty, columns < tx),
+                // over the part of the rectangle that can hold active tiles
                 const int cx0 = max(L.x0, dv.ax0), cx1 = min(L.x1, dv.ax1);
                 const int cy0 = max(L.y0, dv.ay0), cy1 = min(L.y1, dv.ay1);
-                const uint16_t *pre = row_prefix + dv.mask_off;
-                if (cx0 <= cx1)
-                    for (int ty = cy0; ty <= cy1; ++ty) {
-                        const uint16_t *rp = pre + (int64_t)ty * (dv.tiles_x + 1);
-                        cnt += (uint32_t)(rp[cx1 + 1] - rp[cx0]);
-                    }
+                if (cx0 <= cx1 && cy0 <= cy1) {
+                    const uint32_t *C = cum + dv.cum_off;
+                    const int64_t st = dv.tiles_x + 1, r0 = (int64_t)cy0 * st, r1 = (int64_t)(cy1 + 1) * st;
+                    cnt = (C[r1 + cx1 + 1] - C[r0 + cx1 + 1]) - (C[r1 + cx0] - C[r0 + cx0]);
+                }
             }
             // the depth key of entries that emit keys (and of every visible
             // entry of a view whose mask may grow); in the masked layers most
@@ -318,12 +319,12 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
 }
 
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
-                       const uint16_t *row_prefix, uint32_t *counts, uint32_t *depth, uint64_t *rect,
-                       double *score, const double *exp_tab, hipStream_t s) {
+                       const uint32_t *cum, uint32_t *counts, uint32_t *depth, uint64_t *rect, double *score,
+                       const double *exp_tab, hipStream_t s) {
     if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
-                       views, groups, row_prefix, counts, depth, rect, score, exp_tab);
+                       views, groups, cum, counts, depth, rect, score, exp_tab);
 }
 
 // View-dependent colour (degree <= 3 real SH, float32) of Gaussian i seen
