@@ -40,6 +40,14 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 48, "record layout");
 
+// One Gaussian's geometry packed for the record pass's gathers (written by the
+// projection, which reads the structure-of-arrays scene coalesced):
+// a = (mean x, y, z, opacity), b = (scale x, y, z, quat w), c = (quat x, y, z, 0).
+struct alignas(16) GeomPack {
+    float4 a, b, c;
+};
+static_assert(sizeof(GeomPack) == 48, "packed geometry layout");
+
 // Device copy of the per-frame view table, plus derived tile-grid data.
 struct DevView {
     a3fr_view v;
@@ -119,12 +127,13 @@ void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const i
 // score [nsel][n] (selecting views, by sel_slot); cum: the masked views' summed-area tables (launch_mask_cum)
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint32_t *cum, uint32_t *counts, uint32_t *depth, uint64_t *rect, double *score,
-                       const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
+                       GeomPack *pack /* [n] */, const double *exp_tab /* [kExtentSteps + 1] */, hipStream_t s);
 // records and rectangles of the entries ent[0 .. min(*n_ent, cap)), at the entry's index; map[slot] = index;
 // a count above cap raises bit 2 of err
-void launch_entry_record(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, int64_t cap, const double *exp_tab, Record *rec, uint64_t *rect_e, uint32_t *map,
-                         uint32_t *err, hipStream_t s);
+void launch_entry_record(const a3fr_scene &sc, const GeomPack *pack /* this frame's projection */,
+                         const DevView *views, const uint32_t *ent, const uint32_t *n_ent, int64_t m, int64_t cap,
+                         const double *exp_tab, Record *rec, uint64_t *rect_e, uint32_t *map, uint32_t *err,
+                         hipStream_t s);
 void launch_select(const DevView *views, int nv, const int32_t *sel_views, int nsel, int64_t n,
                    const uint32_t *counts, const double *score, int keep_num, int keep_den,
                    uint32_t *sel_ws /* select_workspace_words(nsel, n) words */, uint8_t *keep, hipStream_t s,
@@ -135,14 +144,14 @@ int64_t select_workspace_words(int nsel, int64_t n);
 // clears it, so the key offsets must follow that compaction
 int64_t scan_workspace_words(int64_t m);
 // entries (slots with keys, kept; every visible slot of a keep_visible view) in slot order:
-// ent[j] = slot, dkey[j] = depth bits, dval[j] = j
+// ent[j] = slot, dkey[j] = depth bits, dval[j] = j, ecnt[j] = the slot's key count (ecnt nullable)
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const uint64_t *rect, const DevView *views,
                             int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
-                            uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err, hipStream_t s,
-                            bool zeroed = false /* ws already zero */);
-// key offsets of the entries in depth order: order[k] = entry index, its count counts[ent[order[k]]]
-void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *order, const uint32_t *n_ent,
-                        int64_t m, uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+                            uint32_t *ecnt, uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err,
+                            hipStream_t s, bool zeroed = false /* ws already zero */);
+// key offsets of the entries in depth order: order[k] = entry index, its count ecnt[order[k]]
+void launch_key_offsets(const uint32_t *ecnt, const uint32_t *order, const uint32_t *n_ent, int64_t m,
+                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
                         hipStream_t s);
 // number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
 int64_t emit_chunks(int64_t K);

@@ -108,6 +108,8 @@ struct a3fr_ctx {
     DevBuf rec, rect_e, rect_s, esort, rsort;
     DevBuf offsets, block_sums, scalars;
     DevBuf ent_a, ent_b, dkey_a, dkey_b, dval_a, dval_b;  // entries (records' / a round's), depth sort
+    DevBuf ecnt;               // key count of each entry, in entry order
+    DevBuf gpack;              // packed geometry of every Gaussian, written by the projection
     DevBuf keys_a, keys_b, vals_a, vals_b;
     DevBuf sort_status, ranges;
     DevBuf grad_acc;           // reverse blend sums, [records][12] float
@@ -382,7 +384,7 @@ void a3fr_destroy(a3fr_ctx *c) {
     DevBuf *bufs[] = {&c->views, &c->row_view, &c->row_y, &c->row_prefix, &c->row_list, &c->active,
                       &c->counts, &c->depth, &c->rect, &c->rect_s, &c->rec, &c->score, &c->keep, &c->sel_views,
                       &c->sel, &c->map, &c->rect_e, &c->esort, &c->rsort, &c->dval_a, &c->dval_b,
-                      &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->dkey_a,
+                      &c->offsets, &c->block_sums, &c->scalars, &c->ent_a, &c->ent_b, &c->ecnt, &c->gpack, &c->dkey_a,
                       &c->dkey_b, &c->keys_a, &c->keys_b,
                       &c->vals_a, &c->vals_b, &c->grad_acc, &c->net_pk, &c->net_x0, &c->net_x0c, &c->net_a1,
                       &c->net_a1c, &c->net_a2, &c->net_a2c, &c->net_g3, &c->net_g3c, &c->net_g2, &c->net_g2c,
@@ -625,6 +627,8 @@ static a3fr_status preprocess_layout(a3fr_ctx *c, int64_t n, const a3fr_view *vi
         launch_fill_u32(P<uint32_t>(c->scalars), 0u, 16, c->stream);
     }
     TRY(ensure(c, c->ent_a, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->ecnt, sizeof(uint32_t) * m));
+    TRY(ensure(c, c->gpack, sizeof(GeomPack) * (size_t)n));
     if (c->inc_mode) TRY(ensure(c, c->ent_b, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_a, sizeof(uint32_t) * m));
     TRY(ensure(c, c->dkey_b, sizeof(uint32_t) * m));
@@ -680,7 +684,8 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
       if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
     { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
     launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint32_t>(c->cum), P<uint32_t>(c->counts),
-                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), c->d_exp_tab, c->stream); }
+                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), P<GeomPack>(c->gpack),
+                      c->d_exp_tab, c->stream); }
     // the fallback pairs (periphery view, its eye's full-resolution view); their
     // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of
     // up to kFbMax per launch
@@ -763,9 +768,9 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
 // the error word) and the slot -> record map.
 static void launch_records(a3fr_ctx *c, const a3fr_scene &scene, int64_t cap) {
     StageTimer t_(c, A3FR_STAGE_COLOUR);
-    launch_entry_record(scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
-                        (int64_t)c->nv * c->n, cap, c->d_exp_tab, P<Record>(c->rec), P<uint64_t>(c->rect_e),
-                        P<uint32_t>(c->map), sc_err(c->scalars), c->stream);
+    launch_entry_record(scene, P<GeomPack>(c->gpack), P<DevView>(c->views), P<uint32_t>(c->ent_a),
+                        sc_n_ent(c->scalars), (int64_t)c->nv * c->n, cap, c->d_exp_tab, P<Record>(c->rec),
+                        P<uint64_t>(c->rect_e), P<uint32_t>(c->map), sc_err(c->scalars), c->stream);
 }
 
 // Sizes the record arrays for cap records.
@@ -802,7 +807,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
             StageTimer t_(c, A3FR_STAGE_SCAN);
             launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect), dv, nv, n,
                                    P<uint32_t>(c->depth), P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_b),
-                                   P<uint32_t>(c->dval_b), P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
+                                   P<uint32_t>(c->dval_b), nullptr, P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
                                    sc_n_ent(c->scalars), sc_err(c->scalars), c->stream, zeroed);
         }
         uint32_t E = 0;
@@ -823,7 +828,8 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
         // (keep_visible views count as such only in the visible pass)
         launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), visible_pass ? nullptr : P<uint64_t>(c->rect),
                                dv, nv, n, P<uint32_t>(c->depth), P<uint32_t>(ent), P<uint32_t>(c->dkey_a),
-                               P<uint32_t>(c->dval_a), P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
+                               P<uint32_t>(c->dval_a), P<uint32_t>(c->ecnt), P<uint64_t>(c->block_sums),
+                               sc_ent_total(c->scalars),
                                sc_n_ent(c->scalars), sc_err(c->scalars), c->stream, zeroed);
     }
     if (scene) {
@@ -845,7 +851,7 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     }
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
-        launch_key_offsets(P<uint32_t>(c->counts), P<uint32_t>(ent), P<uint32_t>(c->dval_a), sc_n_ent(c->scalars), m,
+        launch_key_offsets(P<uint32_t>(c->ecnt), P<uint32_t>(c->dval_a), sc_n_ent(c->scalars), m,
                            P<uint32_t>(c->offsets), P<uint64_t>(c->block_sums), sc_key_total(c->scalars),
                            sc_n_keys(c->scalars), sc_err(c->scalars), c->stream);
     }
@@ -882,9 +888,9 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
         const int64_t cap0 = recs ? record_capacity(c) : 0;
         if (cap0 > 0) {
             StageTimer t_(c, A3FR_STAGE_COLOUR);
-            launch_entry_record(c->rec_scene, P<DevView>(c->views), P<uint32_t>(c->ent_a), sc_n_ent(c->scalars),
-                                (int64_t)c->nv * c->n, cap0, c->d_exp_tab, P<Record>(c->rec), P<uint64_t>(c->rect_e),
-                                P<uint32_t>(c->map), nullptr, c->stream);
+            launch_entry_record(c->rec_scene, P<GeomPack>(c->gpack), P<DevView>(c->views), P<uint32_t>(c->ent_a),
+                                sc_n_ent(c->scalars), (int64_t)c->nv * c->n, cap0, c->d_exp_tab, P<Record>(c->rec),
+                                P<uint64_t>(c->rect_e), P<uint32_t>(c->map), nullptr, c->stream);
         }
         HIPCHECK(c, hipEventSynchronize(ready));
         E = c->h_total[0];

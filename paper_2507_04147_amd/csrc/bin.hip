@@ -376,14 +376,15 @@ struct EntryFlags {
     int64_t n;
 };
 
-// Key count of the j-th entry in depth order (order: entry indices sorted by depth).
+// Key count of the j-th entry in depth order (order: entry indices sorted by
+// depth; ecnt: the entries' key counts in entry order, written by the
+// compaction, so that the gather reads a compact array rather than the slots).
 struct SortedCounts {
-    const uint32_t *counts;
-    const uint32_t *ent;
+    const uint32_t *ecnt;
     const uint32_t *order;
     const uint32_t *n_ent;
     __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
-        return j < (int64_t)*n_ent ? counts[ent[order[j]]] : 0u;
+        return j < (int64_t)*n_ent ? ecnt[order[j]] : 0u;
     }
 };
 
@@ -486,7 +487,8 @@ __device__ uint64_t chained_prefix(uint64_t *status, int64_t part, uint64_t tot,
 __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
                                                         const uint32_t *__restrict__ depth, uint32_t *__restrict__ ent,
                                                         uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
-                                                        uint64_t *total, uint32_t *total32, uint32_t *err) {
+                                                        uint32_t *__restrict__ ecnt, uint64_t *total,
+                                                        uint32_t *total32, uint32_t *err) {
     __shared__ uint32_t s_part;
     __shared__ uint64_t s_w[kCompactBlock / 64];
     __shared__ uint64_t s_excl;
@@ -521,23 +523,24 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
         for (int r = 0; r < kScanItems; ++r)
             if (kv[r] == 0) cv[r] = 0;
     }
+    // every visible slot of a keep_visible view is an entry, keys or not (bit r of vbits)
+    uint32_t vbits = 0u;
     if (f.rect && (per_elem || vis0 || vis1)) {
-        // every visible slot of a keep_visible view is an entry (flag as a count of 1 when it has none)
-        uint32_t vv[kScanItems];
+        bool vv[kScanItems];
 #pragma unroll
         for (int r = 0; r < kScanItems; ++r) {
             const int64_t e = wbase + r * 64 + lane;
-            vv[r] = 0u;
+            vv[r] = false;
             if (e < m && cv[r] == 0) {
                 const int64_t v = per_elem ? e / f.n : (e < b1 ? v0 : v0 + 1);
                 const DevView &dv = f.views[v];
                 if (dv.keep_visible && dv.rect_slot >= 0 &&
                     f.rect[(int64_t)dv.rect_slot * f.n + (e - v * f.n)] != kEmptyRect)
-                    vv[r] = 1u;
+                    vv[r] = true;
             }
         }
 #pragma unroll
-        for (int r = 0; r < kScanItems; ++r) cv[r] |= vv[r];
+        for (int r = 0; r < kScanItems; ++r) vbits |= (uint32_t)vv[r] << r;
     }
     uint64_t masks[kScanItems];
     uint32_t dv[kScanItems];
@@ -545,9 +548,10 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const int64_t e = wbase + r * 64 + lane;
-        masks[r] = __ballot(cv[r] != 0);
+        const bool flag = cv[r] != 0 || ((vbits >> r) & 1u);
+        masks[r] = __ballot(flag);
         cnt += (uint32_t)__popcll(masks[r]);
-        dv[r] = cv[r] != 0 ? depth[e] : 0u;
+        dv[r] = flag ? depth[e] : 0u;
     }
     if (lane == 0) s_w[w] = cnt;
     __syncthreads();
@@ -575,6 +579,7 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
             ent[pos] = (uint32_t)(wbase + r * 64 + lane);
             dkey[pos] = dv[r];
             dval[pos] = (uint32_t)pos;
+            if (ecnt) ecnt[pos] = cv[r];
         }
         run += (uint64_t)__popcll(mk);
     }
@@ -640,8 +645,8 @@ int64_t scan_workspace_words(int64_t m) { return 2 + compact_parts(m) + (m + kSc
 
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const uint64_t *rect, const DevView *views,
                             int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
-                            uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err, hipStream_t s,
-                            bool zeroed) {
+                            uint32_t *ecnt, uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err,
+                            hipStream_t s, bool zeroed) {
     const int64_t m = (int64_t)nv * n;
     const int64_t nb = compact_parts(m);
     // both scans' tickets and status words
@@ -656,14 +661,14 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const u
     }
     EntryFlags f{counts, keep, rect, views, n};
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kCompactBlock), 0, s, f, m, nb, ws, depth, ent, dkey, dval,
-                       total, n_ent, err);
+                       ecnt, total, n_ent, err);
 }
 
-void launch_key_offsets(const uint32_t *counts, const uint32_t *ent, const uint32_t *order, const uint32_t *n_ent,
-                        int64_t m, uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
+void launch_key_offsets(const uint32_t *ecnt, const uint32_t *order, const uint32_t *n_ent, int64_t m,
+                        uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
                         hipStream_t s) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
-    SortedCounts f{counts, ent, order, n_ent};
+    SortedCounts f{ecnt, order, n_ent};
     hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, ws, total,
                        total32, offsets, err);
 }

@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
                                                     const uint32_t *__restrict__ cum,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
                                                     uint64_t *__restrict__ rect, double *__restrict__ score,
+                                                    GeomPack *__restrict__ pack,
                                                     const double *__restrict__ exp_tab) {
     __shared__ double s_exp[kExtentSteps + 1];
     for (int k = threadIdx.x; k <= kExtentSteps; k += blockDim.x) s_exp[k] = exp_tab[k];
@@ -275,14 +276,22 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int v_begin = groups[blockIdx.y], v_end = groups[blockIdx.y + 1];
-    const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
+    const float fx = sc.mean_dev[i], fy = sc.mean_dev[n + i], fz = sc.mean_dev[2 * n + i];
+    const float qw = sc.quat_dev[i], qx = sc.quat_dev[n + i], qy = sc.quat_dev[2 * n + i], qz = sc.quat_dev[3 * n + i];
+    const float sx = sc.scale_dev[i], sy = sc.scale_dev[n + i], sz = sc.scale_dev[2 * n + i];
+    const float op = sc.opacity_dev[i];
+    if (blockIdx.y == 0) {  // the first eye's threads pack the geometry for the record pass
+        GeomPack g;
+        g.a = make_float4(fx, fy, fz, op);
+        g.b = make_float4(sx, sy, sz, qw);
+        g.c = make_float4(qx, qy, qz, 0.0f);
+        pack[i] = g;
+    }
+    const double mx = fx, my = fy, mz = fz;
     Cov3 S;
-    const bool cov_ok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i],
-                                      sc.quat_dev[3 * n + i], sc.scale_dev[i], sc.scale_dev[n + i],
-                                      sc.scale_dev[2 * n + i], S);
+    const bool cov_ok = gaussian_cov3(qw, qx, qy, qz, sx, sy, sz, S);
     EyeProj E;
     eye_project(views[v_begin].v, mx, my, mz, cov_ok, S, E);
-    const float op = sc.opacity_dev[i];
     const double qe = footprint_q(op, s_exp);
     for (int vi = v_begin; vi < v_end; ++vi) {
         const DevView &dv = views[vi];
@@ -320,19 +329,18 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
 
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
                        const uint32_t *cum, uint32_t *counts, uint32_t *depth, uint64_t *rect, double *score,
-                       const double *exp_tab, hipStream_t s) {
+                       GeomPack *pack, const double *exp_tab, hipStream_t s) {
     if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
-                       views, groups, cum, counts, depth, rect, score, exp_tab);
+                       views, groups, cum, counts, depth, rect, score, pack, exp_tab);
 }
 
-// View-dependent colour (degree <= 3 real SH, float32) of Gaussian i seen
-// from its view's eye centre, clamped at zero, written into its record.
-__device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_view &vw, int64_t i, Record &rr) {
-    const int64_t n = sc.n;
-    const float dx = sc.mean_dev[i] - (float)vw.campos[0], dy = sc.mean_dev[n + i] - (float)vw.campos[1],
-                dz = sc.mean_dev[2 * n + i] - (float)vw.campos[2];
+// View-dependent colour (degree <= 3 real SH, float32) of Gaussian i (mean
+// m) seen from its view's eye centre, clamped at zero, written into its record.
+__device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_view &vw, int64_t i, const float4 &m,
+                                            Record &rr) {
+    const float dx = m.x - (float)vw.campos[0], dy = m.y - (float)vw.campos[1], dz = m.z - (float)vw.campos[2];
     const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
     float Y[16];
     sh_basis(dx * inv, dy * inv, dz * inv, Y);
@@ -375,7 +383,8 @@ __device__ __forceinline__ void colour_into(const a3fr_scene &sc, const a3fr_vie
 // Grid-stride over the entries (the device count, bounded by cap, the records'
 // capacity; a larger count raises bit 2 of err, when given, and leaves the
 // rest unwritten).
-__global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const DevView *__restrict__ views,
+__global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const GeomPack *__restrict__ pack,
+                                                      const DevView *__restrict__ views,
                                                       const uint32_t *__restrict__ ent, const uint32_t *n_ent,
                                                       int64_t cap, const double *__restrict__ exp_tab,
                                                       Record *__restrict__ rec, uint64_t *__restrict__ rect_e,
@@ -395,14 +404,13 @@ __global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const DevVi
         const int v = (int)(slot / (uint64_t)n);
         const int64_t i = (int64_t)slot - (int64_t)v * n;
         const DevView &dv = views[v];
-        const double mx = sc.mean_dev[i], my = sc.mean_dev[n + i], mz = sc.mean_dev[2 * n + i];
+        const GeomPack g = pack[i];
+        const double mx = g.a.x, my = g.a.y, mz = g.a.z;
         Cov3 S;
-        const bool cov_ok = gaussian_cov3(sc.quat_dev[i], sc.quat_dev[n + i], sc.quat_dev[2 * n + i],
-                                          sc.quat_dev[3 * n + i], sc.scale_dev[i], sc.scale_dev[n + i],
-                                          sc.scale_dev[2 * n + i], S);
+        const bool cov_ok = gaussian_cov3(g.b.w, g.c.x, g.c.y, g.c.z, g.b.x, g.b.y, g.b.z, S);
         EyeProj E3;
         eye_project(dv.v, mx, my, mz, cov_ok, S, E3);
-        const float op = sc.opacity_dev[i];
+        const float op = g.a.w;
         LayerProj L;
         layer_project(dv, E3, footprint_q(op, s_exp), L);
         // an entry is visible in its view (it was counted so); the inverse
@@ -414,7 +422,7 @@ __global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const DevVi
         R.k = (float)(-(L.b * inv_c));
         R.c2 = (float)(-0.5 * kLog2e * inv_c);
         R.o = op;
-        colour_into(sc, dv.v, i, R);
+        colour_into(sc, dv.v, i, g.a, R);
         R.dbits = __float_as_uint((float)E3.p2);
         rec[j] = R;
         rect_e[j] = pack_rect(L);
@@ -422,15 +430,15 @@ __global__ void __launch_bounds__(256) k_entry_record(a3fr_scene sc, const DevVi
     }
 }
 
-void launch_entry_record(const a3fr_scene &sc, const DevView *views, const uint32_t *ent, const uint32_t *n_ent,
-                         int64_t m, int64_t cap, const double *exp_tab, Record *rec, uint64_t *rect_e, uint32_t *map,
-                         uint32_t *err, hipStream_t s) {
+void launch_entry_record(const a3fr_scene &sc, const GeomPack *pack, const DevView *views, const uint32_t *ent,
+                         const uint32_t *n_ent, int64_t m, int64_t cap, const double *exp_tab, Record *rec,
+                         uint64_t *rect_e, uint32_t *map, uint32_t *err, hipStream_t s) {
     const int64_t work = m < cap ? m : cap;
     if (work <= 0) return;
     int64_t blocks = (work + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_entry_record, dim3((unsigned)blocks), dim3(256), 0, s, sc, views, ent, n_ent, cap, exp_tab,
-                       rec, rect_e, map, err);
+    hipLaunchKernelGGL(k_entry_record, dim3((unsigned)blocks), dim3(256), 0, s, sc, pack, views, ent, n_ent, cap,
+                       exp_tab, rec, rect_e, map, err);
 }
 
 }  // namespace a3fr

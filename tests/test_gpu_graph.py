@@ -205,8 +205,8 @@ def test_batched_frames_vs_oracle(pkg, variant):
 def test_gaze_trace_64_frames_one_launch(pkg):
     """The batched gaze trace as one launch: 64 stereo frames of the 3M-Gaussian
     scene at 1832 x 1920 (128 eyes, 384 layer views: more than 2^30 (view,
-    Gaussian) slots and more than 2^30 keys, whose sort needs the 64-bit
-    look-back counts) in one a3fr_render_batch and in one captured graph.  Every
+    Gaussian) slots and more than 2^30 keys, addressed by 32-bit positions up
+    to 2^32 - 1) in one a3fr_render_batch and in one captured graph.  Every
     frame equals the frame rendered alone (the path the single-frame parity
     tests check against the oracle), and the batch's keys are the sum of the
     frames' keys."""

@@ -201,6 +201,48 @@ def test_foveated_stereo_layers_parity(pkg, ctx, size, gaze, n):
     compare_images(views, ref, rgb, T, last, ref["active"])
 
 
+RECORD_DTYPE = np.dtype([("u", "<f8"), ("v", "<f8"), ("a2", "<f4"), ("k", "<f4"), ("c2", "<f4"), ("o", "<f4"),
+                         ("r", "<f4"), ("g", "<f4"), ("b", "<f4"), ("dbits", "<u4")])
+LOG2E = 1.4426950408889634
+
+
+def test_entry_records_vs_oracle(pkg, ctx):
+    """The blend record of every entry (row 2's float32 record, formed once
+    per visible entry): its centre (the key path's float64 u, v) and depth bits
+    bit-exact against the oracle's projection; its inverse covariance in LDL^T
+    form (t = dx + k dy; log2 of the Gaussian = a2 t^2 + c2 dy^2, from the
+    oracle's float64 covariance (xx, xy, yy) and determinant: a2 = -log2(e)/2
+    yy/det, k = -xy/yy, c2 = -log2(e)/2 / yy, rounded once to float32)
+    bit-exact; opacity exact; the float32 SH colour within 1e-5 of the
+    oracle's float64 colour seen from the view's eye centre."""
+    W, H = 232, 240
+    scene, cams = synth.foveated_stereo(n=60_000, width=W, height=H, seed=7)
+    gz = [(0.45 * W, 0.5 * H), (0.45 * W + 4.0, 0.5 * H)]
+    views = oracle.foveated_views(cams, gz, (0.15 * W, 0.35 * W))
+    ref = oracle.render(scene, views, blend=False)
+    gpu_render(pkg, ctx, scene, views)
+    nv, n = len(views), scene.n
+    rec = ctx.inspect("records", torch.int32).cpu().numpy().view(RECORD_DTYPE).reshape(nv, n)
+    kept = np.array([ref["keep"][v] if views[v].select else np.ones(n, np.uint8) for v in range(nv)]).astype(bool)
+    ent = ref["vis"].astype(bool) & (ref["count"] > 0) & kept
+    assert ent.sum() > 1000
+    mu, cov, det = ref["mu"][ent], ref["cov"][ent], ref["det"][ent]
+    r = rec[ent]
+    np.testing.assert_array_equal(r["u"], mu[:, 0])
+    np.testing.assert_array_equal(r["v"], mu[:, 1])
+    np.testing.assert_array_equal(r["dbits"], ref["depth_bits"][ent].astype(np.uint32))
+    inv_c, inv_det = 1.0 / cov[:, 2], 1.0 / det
+    np.testing.assert_array_equal(r["a2"], ((-0.5 * LOG2E) * (cov[:, 2] * inv_det)).astype(np.float32))
+    np.testing.assert_array_equal(r["k"], (-(cov[:, 1] * inv_c)).astype(np.float32))
+    np.testing.assert_array_equal(r["c2"], ((-0.5 * LOG2E) * inv_c).astype(np.float32))
+    vi, gi = np.nonzero(ent)
+    np.testing.assert_array_equal(r["o"], scene.opacity[gi])
+    col = oracle.core.colour(scene, [views[v].campos for v in range(nv)])  # [view][n][3]
+    want = col[vi, gi]
+    got = np.stack([r["r"], r["g"], r["b"]], axis=1).astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-5
+
+
 def test_full_render_and_composite_parity(pkg, ctx):
     """render_full (FRR) and render_foveated (layers + composite) against the
     oracle's, on the same small stereo scene."""
