@@ -820,6 +820,35 @@ __device__ __forceinline__ float wave_sum(float x) {
     return x;
 }
 
+// Wave sums of eight values at once.  At offset 32 a lane keeps the half of
+// its values selected by lane bit 5 and receives the same half from its
+// partner (4 shuffles), at 16 the half of those by bit 4 (2), at 8 by bit 3
+// (1); after three plain steps (4, 2, 1) lane l holds the sum over the wave of
+// value l >> 3.
+__device__ __forceinline__ float wave_multi_sum8(const float (&v)[8], int lane) {
+    const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+    float h4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b5 ? v[4 + i] : v[i], give = b5 ? v[i] : v[4 + i];
+        h4[i] = keep + __shfl_xor(give, 32, 64);
+    }
+    float h2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b4 ? h4[2 + i] : h4[i], give = b4 ? h4[i] : h4[2 + i];
+        h2[i] = keep + __shfl_xor(give, 16, 64);
+    }
+    float x;
+    {
+        const float keep = b3 ? h2[1] : h2[0], give = b3 ? h2[0] : h2[1];
+        x = keep + __shfl_xor(give, 8, 64);
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
 __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ views, int nv,
                                                   const uint8_t *__restrict__ active,
                                                   const uint32_t *__restrict__ ranges,
@@ -940,14 +969,16 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
                 }
             }
             if (__ballot(hit) != 0ull) {
-                g_t2 = wave_sum(g_t2); g_t = wave_sum(g_t); g_tdy = wave_sum(g_tdy);
-                g_dy2 = wave_sum(g_dy2); g_dy = wave_sum(g_dy); g_o = wave_sum(g_o);
-                g_r = wave_sum(g_r); g_g = wave_sum(g_g); g_b = wave_sum(g_b);
-                if (lane < 9) {
-                    const float val = lane == 0 ? g_t2 : lane == 1 ? g_t : lane == 2 ? g_tdy : lane == 3 ? g_dy2 :
-                                      lane == 4 ? g_dy : lane == 5 ? g_o : lane == 6 ? g_r : lane == 7 ? g_g : g_b;
-                    atomicAdd(&A[(int64_t)s_i[jj] * 12 + lane], val);
-                }
+                // sums 0..7 in one butterfly: each exchange step halves the
+                // values a lane carries (4 + 2 + 1 shuffles), three more steps
+                // finish the sum; lane 8 v then holds sum v over the wave.  Sum 8
+                // (blue) by a plain butterfly, held by every lane.
+                float v[8] = {g_t2, g_t, g_tdy, g_dy2, g_dy, g_o, g_r, g_g};
+                const float sb = wave_sum(g_b);
+                const float vb = wave_multi_sum8(v, lane);
+                const bool first = (lane & 7) == 0;
+                if (first || lane == 1)
+                    atomicAdd(&A[(int64_t)s_i[jj] * 12 + (first ? (lane >> 3) : 8)], first ? vb : sb);
             }
         }
         __syncthreads();
