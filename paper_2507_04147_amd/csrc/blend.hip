@@ -43,6 +43,15 @@ __device__ __forceinline__ bool tile_reach(const Record &r, float mu, float mv) 
     return box_reach(r.a2, r.k, r.c2, r.o, mu, mv, 0.0f, 0.0f, (float)kTile);
 }
 
+// The exponent at which a Gaussian of opacity o reaches the alpha threshold:
+// o 2^e >= 1/255 exactly when e >= -log2(255 o) (o = 0: +inf, never).  Every
+// blend (the forward variants, the AMR blend and the reverse blend) takes
+// this same float32 decision on the exponent, so that exp2 is evaluated only
+// for the entries some pixel of the wave takes; its rounding differs from
+// that of o 2^e by far less than the float32 error bound within which the
+// oracle flags a decision as ambiguous.
+__device__ __forceinline__ float take_exponent(float o) { return -__builtin_amdgcn_logf(255.0f * o); }
+
 // Blend one tile.  BATCH: records staged in LDS per step; ROWS: pixel rows per
 // lane (1: four horizontally adjacent pixels, 2: a 2 x 2 block).  Every
 // pixel evaluates exactly the same float32 expressions over the same list in
@@ -58,7 +67,7 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                                            float *__restrict__ Tout, uint32_t *__restrict__ lastout, uint32_t &npairs) {
     constexpr int COLS = 4 / ROWS;
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
-    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH], s_e[BATCH];
     __shared__ uint32_t s_j[BATCH];
     // view of this tile: views are ordered by tile offset
     int lo = 0, hi = nv - 1;
@@ -79,9 +88,9 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) fyr[r] = (float)(py0 + r) + 0.5f;
     float fxq[4];
-    // per pixel the alpha a Gaussian needs to be blended: 1/255 while the
-    // pixel is live, +inf once it has stopped or when it lies outside the
-    // image (one compare per pair then also carries the live test)
+    // per pixel 0 while it is live, +inf once it has stopped or when it lies
+    // outside the image: added to an entry's take exponent, one compare per
+    // pair then also carries the live test
     float thr[4];
     float T[4], Cr[4], Cg[4], Cb[4];
     uint32_t last[4];
@@ -89,12 +98,21 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
     for (int q = 0; q < 4; ++q) {
         const int cx = px0 + q % COLS, cy = py0 + q / COLS;
         fxq[q] = (float)cx + 0.5f;
-        thr[q] = (x0 + cx < W) && (y0 + cy < H) ? kAlphaMin : INFINITY;
+        thr[q] = (x0 + cx < W) && (y0 + cy < H) ? 0.0f : INFINITY;
         T[q] = 1.0f; Cr[q] = Cg[q] = Cb[q] = 0.0f; last[q] = 0;
     }
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
     const Record *R = rec + (int64_t)lo * n;
     const double dx0 = (double)x0, dy0 = (double)y0;
+    // software pipeline: the records of the next batch are gathered while the
+    // current one is blended (rn: this lane's slots of the batch at b0)
+    constexpr int PARTS = (BATCH + 63) / 64;
+    Record rn[PARTS];
+#pragma unroll
+    for (int part = 0; part < PARTS; ++part) {
+        const int slot = part * 64 + lane;
+        if (slot < BATCH && start + slot < end) rn[part] = R[vals[start + slot]];
+    }
 
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
         if (__ballot(fminf(fminf(thr[0], thr[1]), fminf(thr[2], thr[3])) < INFINITY) == 0ull) break;
@@ -103,14 +121,14 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
         // last-blended index.
         uint32_t cnt = 0;
 #pragma unroll
-        for (int part = 0; part < (BATCH + 63) / 64; ++part) {
+        for (int part = 0; part < PARTS; ++part) {
             const int slot = part * 64 + lane;
             const uint32_t j = b0 + slot;
             bool keep = false;
             Record r;
             float mu = 0.0f, mv = 0.0f;
             if (slot < BATCH && j < end) {
-                r = R[vals[j]];
+                r = rn[part];
                 mu = (float)(r.u - dx0);
                 mv = (float)(r.v - dy0);
                 keep = tile_reach(r, mu, mv);
@@ -122,11 +140,18 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 s_v[at] = mv;
                 s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
                 s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
+                s_e[at] = take_exponent(r.o);
                 s_j[at] = (uint32_t)slot;
             }
             cnt += (uint32_t)__popcll(km);
         }
         __syncthreads();
+#pragma unroll
+        for (int part = 0; part < PARTS; ++part) {
+            const int slot = part * 64 + lane;
+            const uint32_t j = b0 + BATCH + slot;
+            if (slot < BATCH && j < end) rn[part] = R[vals[j]];
+        }
         // COUNT: a dropped entry is still a pair of every live pixel (nothing
         // changes between kept entries, so the live pixels are those at the next one)
         int prev = -1;
@@ -148,7 +173,8 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 kdy[r] = kk * dy;
                 cdy[r] = c2 * dy * dy;
             }
-            float al[4];
+            const float et = s_e[jj];
+            float ex[4];
             bool take[4];
             bool any = false;
 #pragma unroll
@@ -156,9 +182,8 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
                 const int rr = q / COLS;
                 if (COUNT) npairs += thr[q] < INFINITY ? 1u : 0u;
                 const float t = (fxq[q] - mu) + kdy[rr];
-                const float e = fmaf(a2, t * t, cdy[rr]);
-                al[q] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                take[q] = al[q] >= thr[q];
+                ex[q] = fmaf(a2, t * t, cdy[rr]);
+                take[q] = ex[q] >= et + thr[q];
                 any = any || take[q];
             }
             // most evaluated pairs fall outside the footprint (alpha < 1/255): skip when the whole wave does
@@ -166,10 +191,11 @@ __device__ __forceinline__ void blend_tile(int64_t gt, const DevView *__restrict
             // branch-free: a pixel that does not blend adds fma(0, c, C) = C (colours >= 0)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float Tn = T[q] * (1.0f - al[q]);
+                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(ex[q]));
+                const float Tn = T[q] * (1.0f - al);
                 const bool stop = take[q] && Tn < kTMin;
                 const bool blend = take[q] && !stop;
-                const float wgt = blend ? al[q] * T[q] : 0.0f;
+                const float wgt = blend ? al * T[q] : 0.0f;
                 Cr[q] = fmaf(wgt, cr, Cr[q]);
                 Cg[q] = fmaf(wgt, cg, Cg[q]);
                 Cb[q] = fmaf(wgt, cb, Cb[q]);
@@ -332,19 +358,19 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
                                          float *__restrict__ rgb, bool interp) {
     constexpr int BATCH = 64;
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
-    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH], s_e[BATCH];
     const int W = dv.v.width, H = dv.v.height;
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int lane = threadIdx.x;
     const int bx = 2 * (lane & 7), by = 2 * (lane >> 3);  // the lane's 2 x 2 block in the tile
     float fx[NP], fy[NP], T[NP], Cr[NP], Cg[NP], Cb[NP];
-    float thr[NP];  // 1/255 while the pixel is live, +inf once stopped or outside the image
+    float thr[NP];  // 0 while the pixel is live, +inf once stopped or outside the image
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int cx = bx + (k & 1), cy = by + (k >> 1);
         fx[k] = (float)cx + 0.5f;
         fy[k] = (float)cy + 0.5f;
-        thr[k] = (x0 + cx < W) && (y0 + cy < H) ? kAlphaMin : INFINITY;
+        thr[k] = (x0 + cx < W) && (y0 + cy < H) ? 0.0f : INFINITY;
         T[k] = 1.0f; Cr[k] = Cg[k] = Cb[k] = 0.0f;
     }
     const Record *R = rec + lo * n;
@@ -371,12 +397,14 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
             s_v[at] = mv;
             s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
             s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
+            s_e[at] = take_exponent(r.o);
         }
         __syncthreads();
         const uint32_t cnt = (uint32_t)__popcll(km);
         for (uint32_t jj = 0; jj < cnt; ++jj) {
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
-            float al[NP];
+            const float et = s_e[jj];
+            float ex[NP];
             bool take[NP];
             bool any = false;
 #pragma unroll
@@ -385,19 +413,19 @@ __device__ __forceinline__ void amr_tile(const DevView &dv, int64_t lo, int tx, 
                 const float kdy = kk * dy;
                 const float cdy = c2 * dy * dy;
                 const float t = (fx[k] - mu) + kdy;
-                const float e = fmaf(a2, t * t, cdy);
-                al[k] = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-                take[k] = al[k] >= thr[k];
+                ex[k] = fmaf(a2, t * t, cdy);
+                take[k] = ex[k] >= et + thr[k];
                 any = any || take[k];
             }
             if (__ballot(any) == 0ull) continue;
             const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const float Tn = T[k] * (1.0f - al[k]);
+                const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(ex[k]));
+                const float Tn = T[k] * (1.0f - al);
                 const bool stop = take[k] && Tn < kTMin;
                 const bool blend = take[k] && !stop;
-                const float wgt = blend ? al[k] * T[k] : 0.0f;
+                const float wgt = blend ? al * T[k] : 0.0f;
                 Cr[k] = fmaf(wgt, cr, Cr[k]);
                 Cg[k] = fmaf(wgt, cg, Cg[k]);
                 Cb[k] = fmaf(wgt, cb, Cb[k]);
@@ -523,7 +551,7 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
     const int64_t gt = tr.base[blockIdx.y] + blockIdx.x;
     if (!active[gt]) return;  // block-uniform
     __shared__ float s_u[BATCH], s_v[BATCH], s_a[BATCH], s_k[BATCH], s_c[BATCH], s_o[BATCH];
-    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH];
+    __shared__ float s_r[BATCH], s_g[BATCH], s_b[BATCH], s_e[BATCH];
     __shared__ uint16_t s_list[4][BATCH];
     __shared__ uint32_t s_live[4];
     int lo = 0, hi = nv - 1;
@@ -540,9 +568,9 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
     const int qx = (w & 1) * 8, qy = (w >> 1) * 8;
     const int px = qx + (lane & 7), py = qy + (lane >> 3);
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-    // the alpha a Gaussian needs to be blended: 1/255 while the pixel is live,
-    // +inf once it has stopped or when it lies outside the image
-    float thr = (x0 + px < W) && (y0 + py < H) ? kAlphaMin : INFINITY;
+    // 0 while the pixel is live, +inf once it has stopped or when it lies
+    // outside the image (added to an entry's take exponent)
+    float thr = (x0 + px < W) && (y0 + py < H) ? 0.0f : INFINITY;
     float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
     uint32_t last = 0, npairs = 0;
     const uint32_t start = ranges[2 * gt], end = ranges[2 * gt + 1];
@@ -561,6 +589,7 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
                 s_v[slot] = (float)(r.v - dy0);
                 s_a[slot] = r.a2; s_k[slot] = r.k; s_c[slot] = r.c2; s_o[slot] = r.o;
                 s_r[slot] = r.r; s_g[slot] = r.g; s_b[slot] = r.b;
+                s_e[slot] = take_exponent(r.o);
             }
         }
         __syncthreads();
@@ -594,9 +623,9 @@ __global__ void __launch_bounds__(256) k_blend_quad(const DevView *__restrict__ 
             const float cdy = c2 * dy * dy;
             const float t = (fx - mu) + kdy;
             const float e = fmaf(a2, t * t, cdy);
-            const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
-            const bool take = al >= thr;
+            const bool take = e >= s_e[jj] + thr;
             if (__ballot(take) == 0ull) continue;
+            const float al = fminf(kAlphaMax, o * __builtin_amdgcn_exp2f(e));
             const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
             const float Tn = T * (1.0f - al);
             const bool stop = take && Tn < kTMin;
@@ -896,7 +925,7 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
     const Record *R = rec + (int64_t)lo * n;
     float *A = acc + (int64_t)lo * n * 12;
     __shared__ float s_u[kBatch], s_v[kBatch], s_a[kBatch], s_k[kBatch], s_c[kBatch], s_o[kBatch];
-    __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch];
+    __shared__ float s_r[kBatch], s_g[kBatch], s_b[kBatch], s_e[kBatch];
     __shared__ uint32_t s_i[kBatch], s_p[kBatch];
     const double dx0 = (double)x0, dy0 = (double)y0;
     const float kLn2 = 0.6931471805599453f;
@@ -923,6 +952,7 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
             s_v[at] = mv;
             s_a[at] = r.a2; s_k[at] = r.k; s_c[at] = r.c2; s_o[at] = r.o;
             s_r[at] = r.r; s_g[at] = r.g; s_b[at] = r.b;
+            s_e[at] = take_exponent(r.o);
             s_i[at] = idx;
             s_p[at] = bstart + (uint32_t)lane;
         }
@@ -930,7 +960,7 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
         for (int jj = __popcll(km) - 1; jj >= 0; --jj) {
             const uint32_t pos = s_p[jj];
             const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
-            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj];
+            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj], et = s_e[jj];
             const float dy = fy - mv;
             const float kdy = kk * dy;
             const float cdy = c2 * dy * dy;
@@ -943,7 +973,7 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
                 const float ex = __builtin_amdgcn_exp2f(e);
                 const float araw = o * ex;
                 const float al = fminf(kAlphaMax, araw);
-                if (pos < last[q] && al >= kAlphaMin) {
+                if (pos < last[q] && e >= et) {  // blended in the forward (the same decision)
                     hit = true;
                     const float oma = 1.0f - al;
                     const float Tb = T[q] / oma;
