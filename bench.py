@@ -510,8 +510,10 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
     first at the image centre): for each periphery option (bilinear, with the
     error estimate, the workload's network, both) the frame time, the periphery
     PSNR against the full-resolution render (minimum over the eyes) and the
-    fallback tiles; the full-resolution frame time of the pose."""
+    fallback tiles; the full-resolution frame time of the pose; for a workload
+    whose network the method uses, the network stage alone (profiled frame)."""
     import statistics as stats
+    import numpy as np
     res = {}
     for w, head in (("inside", synth.HEAD_INSIDE), ("outside", synth.HEAD_OUTSIDE)):
         _, cams = synth.foveated_stereo(n=1, head=head)
@@ -535,6 +537,25 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
                 ms = timed(step, max(3, args.steps // 4))
                 rows[name].append((ms, min(_psnr_outside_fovea(c, W, H, gz, rad, out, ref)),
                                    c.get_counts()["n_fallback_tiles"]))
+        net_stage = None
+        if nets[w]["use"]:
+            # the network's stage alone (a profiled frame keeps one stream) at the centre gaze
+            gz = [gazes[0], gazes[0]]
+            set_frame_options(pkg, c, nets[w]["theta"], True, None)
+            c.render_foveated(ds, cams, gz, fov, out)
+            n_prof = max(3, args.steps // 4)
+            c.set_profiling(True, count_pairs=False)
+            for _ in range(n_prof):
+                c.render_foveated(ds, cams, gz, fov, out)
+            c.sync()
+            st = c.get_profile()["stages"]["net"]
+            c.set_profiling(False)
+            flop = net_frame_flop(np, W, H, gz, rad[1])
+            ms = st["ms"] / n_prof
+            tf = flop / (ms / 1000.0) / 1e12
+            net_stage = dict(ms_per_frame=ms, launches_per_frame=st["launches"] / n_prof, flop_per_frame=flop,
+                             bound="mfma", achieved_TFLOPs=tf, frac=tf / BF16_MFMA_PEAK_TF)
+            log(f"workload {w}: network stage {ms * 1000:.1f} us per stereo frame, {tf:.0f} TFLOP/s")
         c.close()
         ntiles = 2 * ((W // 4 + 15) // 16) * ((H // 4 + 15) // 16)
         summ = {}
@@ -547,7 +568,7 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
                    key=lambda n_: 1.0 / summ[n_]["ms_median"], default=None)
         res[w] = dict(head=list(head), gazes=len(gazes), full_res_ms=ms_frr, options=summ,
                       network=dict(used_by_method=nets[w]["use"], held_out_psnr_db=nets[w]["held_out_psnr_db"],
-                                   pairs=nets[w]["pairs"], epochs=nets[w]["epochs"]),
+                                   pairs=nets[w]["pairs"], epochs=nets[w]["epochs"], stage=net_stage),
                       fastest_option_at_30db=best,
                       speedup_vs_full_res=(ms_frr / summ[best]["ms_median"]) if best else None)
         log(f"workload {w}: FRR {ms_frr:.3f} ms; " + "; ".join(

@@ -110,6 +110,18 @@ struct NetConvArgs {
     int gv_stride;
     double rm;
 };
+// inference forward of all three layers in one launch (float32 parameters,
+// input and output, optional frame mode as in NetConvArgs)
+struct NetFusedArgs {
+    const float *img_in;             // float32 planar [B][3][h][w], batch stride img_bstride (0: 3 h w)
+    const float *theta;              // float32 parameters (rounded to bf16 in the kernel)
+    float *img_out;                  // float32 planar [B][3][4h][4w], batch stride out_bstride (0: 3 (4h)(4w))
+    int64_t img_bstride, out_bstride;
+    int B, h, w;
+    const DevView *gv;               // frame mode as in NetConvArgs (nullable)
+    int gv_stride;
+    double rm;
+};
 struct NetWgradArgs {
     const uint16_t *g;        // channel-major zero-bordered bf16 gradient, NOUT channels
     const uint16_t *in;       // channel-major zero-bordered bf16 layer input, KIN channels
@@ -263,6 +275,7 @@ void launch_preprocess_bwd(const a3fr_params &p, const DevView *views, int nv, c
 void launch_net_prep(const float *theta, const NetPacked &pk, const float *x, int64_t x_bstride, int B, int h, int w,
                      uint16_t *nhwc, uint16_t *chw, hipStream_t s);
 void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a, hipStream_t s);
+void launch_net_fused(const NetFusedArgs &a, hipStream_t s);
 void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s);
 void launch_net_mse(const float *out, const float *target, int B, int h, int w, uint16_t *g_nhwc, uint16_t *g_chw,
                     double *sse, float *loss, hipStream_t s);

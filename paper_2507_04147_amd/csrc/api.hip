@@ -1197,14 +1197,27 @@ a3fr_status a3fr_composite(a3fr_ctx *c, int32_t W, int32_t H, a3fr_gaze g, const
 
 static NetPacked net_packed(a3fr_ctx *c);
 static a3fr_status net_check_geom(a3fr_ctx *c, int B, int h, int w);
-constexpr int kNetFrameRows = 2;  // image rows per block of the frame's convolutions
+
+// Inference forward of the upsampler: one fused launch runs all three layers
+// tile by tile with the weights and activations in LDS (gv: frame mode, see
+// NetConvArgs).
+static void net_infer(a3fr_ctx *c, const float *theta, const float *in, int64_t in_stride, int B, int h, int w,
+                      float *out, int64_t out_stride, const DevView *gv, double rm) {
+    NetFusedArgs a{};
+    a.img_in = in; a.img_bstride = in_stride;
+    a.theta = theta;
+    a.img_out = out; a.out_bstride = out_stride;
+    a.B = B; a.h = h; a.w = w;
+    a.gv = gv; a.gv_stride = 3; a.rm = rm;
+    launch_net_fused(a, c->stream);
+}
 
 // The upsampler on the periphery layers of a foveated frame, all eyes in one
-// batch (frame mode of the convolutions): layer images of eye e sit at a
-// constant distance from eye 0's (every eye has the same layer sizes);
-// waves whose receptive field lies within r_mid are skipped and only pixels
-// outside r_mid are written to out, where the composite leaves them (whole:
-// every pixel is computed and written, for a periphery whose gaze comes later).
+// batch (frame mode): layer images of eye e sit at a constant distance from
+// eye 0's (every eye has the same layer sizes); tiles and units whose
+// receptive field lies within r_mid are skipped and only pixels outside r_mid
+// are written to out, where the composite leaves them (whole: every pixel is
+// computed and written, for a periphery whose gaze comes later).
 static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n_eyes, double r_mid, const float *L,
                                      float *out, bool whole = false) {
     const int W = cams[0].width, H = cams[0].height;
@@ -1214,29 +1227,9 @@ static a3fr_status net_frame_forward(a3fr_ctx *c, const a3fr_camera *cams, int n
     const int h = H / 4, w = W / 4;
     TRY(net_check_geom(c, n_eyes, h, w));
     const int64_t in_stride = n_eyes > 1 ? 3 * (c->hviews[5].img_off - c->hviews[2].img_off) : 3 * (int64_t)h * w;
-    const int64_t px = (int64_t)n_eyes * h * w;
-    TRY(ensure(c, c->net_pk, sizeof(uint16_t) * kNetPackedElems));
-    TRY(ensure(c, c->net_x0, sizeof(uint16_t) * 8 * px));
-    TRY(ensure(c, c->net_a1, sizeof(uint16_t) * 32 * px));
-    TRY(ensure(c, c->net_a2, sizeof(uint16_t) * 32 * px));
     c->net_trained_fwd = false;
-    const float *theta = c->net_theta;
-    const NetPacked pk = net_packed(c);
-    const float *in = L + 3 * c->hviews[2].img_off;
-    launch_net_prep(theta, pk, in, in_stride, n_eyes, h, w, P<uint16_t>(c->net_x0), nullptr, c->stream);
-    NetConvArgs a{};
-    a.B = n_eyes; a.h = h; a.w = w;
-    a.rows = kNetFrameRows;
-    if (!whole) {  // skip what lies within r_mid, write only outside it
-        a.gv = P<DevView>(c->views); a.gv_stride = 3; a.rm = r_mid;
-    }
-    a.in = P<uint16_t>(c->net_x0); a.wpk = pk.f1; a.bias = theta + kNetB1; a.out = P<uint16_t>(c->net_a1);
-    launch_net_conv(1, false, a, c->stream);
-    a.in = P<uint16_t>(c->net_a1); a.wpk = pk.f2; a.bias = theta + kNetB2; a.out = P<uint16_t>(c->net_a2);
-    launch_net_conv(2, false, a, c->stream);
-    a.in = P<uint16_t>(c->net_a2); a.wpk = pk.f3; a.bias = theta + kNetB3; a.out = nullptr;
-    a.img_in = in; a.img_bstride = in_stride; a.img_out = out; a.out_bstride = 3 * (int64_t)W * H;
-    launch_net_conv(3, false, a, c->stream);
+    net_infer(c, c->net_theta, L + 3 * c->hviews[2].img_off, in_stride, n_eyes, h, w, out, 3 * (int64_t)W * H,
+              whole ? nullptr : P<DevView>(c->views), r_mid);
     return check_launch(c, "upsampler");
 }
 
@@ -1594,11 +1587,16 @@ a3fr_status a3fr_net_forward(a3fr_ctx *c, const float *theta, const float *in, i
     const int64_t px = (int64_t)B * h * w;
     const int WS = net_chw_stride(w);
     const int64_t plane = (int64_t)(h + 2) * WS;
+    const bool train = for_training != 0;
+    if (!train) {  // inference: one fused launch, no activations in memory
+        c->net_trained_fwd = false;
+        net_infer(c, theta, in, 0, B, h, w, out, 0, nullptr, 0.0);
+        return check_launch(c, "net_forward");
+    }
     TRY(ensure(c, c->net_pk, sizeof(uint16_t) * kNetPackedElems));
     TRY(ensure(c, c->net_x0, sizeof(uint16_t) * 8 * px));
     TRY(ensure(c, c->net_a1, sizeof(uint16_t) * 32 * px));
     TRY(ensure(c, c->net_a2, sizeof(uint16_t) * 32 * px));
-    const bool train = for_training != 0;
     if (train) {
         DevBuf *chw[] = {&c->net_x0c, &c->net_a1c, &c->net_a2c, &c->net_g3c, &c->net_g2c, &c->net_g1c};
         const int chans[] = {8, 32, 32, 48, 32, 32};

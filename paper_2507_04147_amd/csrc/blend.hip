@@ -1084,9 +1084,11 @@ __device__ __forceinline__ void composite_px(int x, int y, int W, int H, double 
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         const float *p = src + ch * HWl;
-        const float top = (1.0f - wx) * p[(int64_t)ya * Wl + xa] + wx * p[(int64_t)ya * Wl + xb];
-        const float bot = (1.0f - wx) * p[(int64_t)yb * Wl + xa] + wx * p[(int64_t)yb * Wl + xb];
-        out[ch * HW + pix] = (1.0f - wy) * top + wy * bot;
+        // vertical interpolation in columns xa and xb, then horizontal (the upsampler's
+        // residual takes the same steps, so a network with zero weights gives these bits)
+        const float va = (1.0f - wy) * p[(int64_t)ya * Wl + xa] + wy * p[(int64_t)yb * Wl + xa];
+        const float vb = (1.0f - wy) * p[(int64_t)ya * Wl + xb] + wy * p[(int64_t)yb * Wl + xb];
+        out[ch * HW + pix] = (1.0f - wx) * va + wx * vb;
     }
 }
 

@@ -201,11 +201,12 @@ __device__ __forceinline__ void conv_epilogue(const NetConvArgs &a, const floatx
 // pixels x 48 channels are staged, then lane l produces output column
 // X = 4 xs + l (pixel x = xs + l/4, j = l%4) of the four output rows and three
 // colour channels: out(c, 4y+i, X) = y3[x][c*16 + 4i + j] + b3 + bilinear,
-// so every store writes 64 consecutive floats.
+// so every store writes 64 consecutive floats.  Pixels x >= xend are not
+// written (xend <= w).
 constexpr int kShufStride = 49;  // floats per staged pixel (48 channels + 1: bank spread)
 
 __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const floatx4 *acc, float *st, int b, int y,
-                                                 int xs, int li, int g, int lane, double gx, double gy) {
+                                                 int xs, int li, int g, int lane, double gx, double gy, int xend) {
     const int h = a.h, w = a.w;
 #pragma unroll
     for (int nb = 0; nb < 3; ++nb)
@@ -215,7 +216,7 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int x = xs + (lane >> 2), j = lane & 3;
-    if (x < w) {
+    if (x < xend) {
         const int H4 = 4 * h, W4 = 4 * w;
         const int X = 4 * x + j;
         float sx = ((float)X + 0.5f) * 0.25f - 0.5f;
@@ -224,17 +225,6 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
         const int xa = (int)fx0, xb = xa + 1 < w ? xa + 1 : w - 1;
         const float wx = sx - fx0;
         const float *px = st + (lane >> 2) * kShufStride;
-        // the four output rows 4y + i sample input rows y - 1, y, y + 1 (clamped):
-        // their horizontal interpolations, once per row and channel
-        const int rows[3] = {y > 0 ? y - 1 : 0, y, y + 1 < h ? y + 1 : h - 1};
-        float hz[3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)c * h * w;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                hz[c][k] = (1.0f - wx) * src[(int64_t)rows[k] * w + xa] + wx * src[(int64_t)rows[k] * w + xb];
-        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int Y = 4 * y + i;
@@ -247,16 +237,15 @@ __device__ __forceinline__ void shuffle_epilogue(const NetConvArgs &a, const flo
             const float fy0 = floorf(sy);
             const int ya = (int)fy0, yb = ya + 1 < h ? ya + 1 : h - 1;
             const float wy = sy - fy0;
-            // ya and yb are among the three rows (equal rows hold equal values)
-            const int ka = ya == rows[0] ? 0 : (ya == rows[1] ? 1 : 2);
-            const int kb = yb == rows[0] ? 0 : (yb == rows[1] ? 1 : 2);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                // bilinear residual: vertical interpolation in columns xa and xb, then horizontal
+                const float *src = a.img_in + (int64_t)b * a.img_bstride + (int64_t)c * h * w;
+                const float va = (1.0f - wy) * src[(int64_t)ya * w + xa] + wy * src[(int64_t)yb * w + xa];
+                const float vb = (1.0f - wy) * src[(int64_t)ya * w + xb] + wy * src[(int64_t)yb * w + xb];
                 float *dst = a.img_out + (int64_t)b * a.out_bstride + (int64_t)c * H4 * W4;
-                const float top = ka == 0 ? hz[c][0] : (ka == 1 ? hz[c][1] : hz[c][2]);
-                const float bot = kb == 0 ? hz[c][0] : (kb == 1 ? hz[c][1] : hz[c][2]);
                 const int ch = c * 16 + 4 * i + j;
-                dst[(int64_t)Y * W4 + X] = (px[ch] + a.bias[ch]) + ((1.0f - wy) * top + wy * bot);
+                dst[(int64_t)Y * W4 + X] = (px[ch] + a.bias[ch]) + ((1.0f - wx) * va + wx * vb);
             }
         }
     }
@@ -352,12 +341,450 @@ __global__ void __launch_bounds__(256) k_net_conv(NetConvArgs a) {
             for (int rr = 0; rr < 2; ++rr) {
                 if (rr == 1 && !has1) break;
                 if (EPI == kEpiShuffle)
-                    shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy);
+                    shuffle_epilogue(a, acc[rr], shuf + wave * 16 * kShufStride, b, y + rr, xs, li, g, lane, gx, gy,
+                                     w);
                 else
                     conv_epilogue<KIN, NOUT, EPI>(a, acc[rr], stage + wave * 16 * kStageStride<NOUT>, b, y + rr, xs, li, g,
                                                   lane, WS);
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused inference forward: conv1 -> conv2 -> conv3 (+ shuffle and bilinear
+// residual) in one launch.  Resident blocks (one per compute unit) stage the
+// three layers' weights once and then take output tiles of kFxTX x kFxTY
+// pixels in turn, keeping everything a tile needs in LDS: its input with a
+// 3-pixel halo (bf16 for the products, float32 for the residual), conv1's
+// activations with a 2-pixel halo (L1) and conv2's with a 1-pixel halo (L2).
+// Only the float32 input is read from memory (each tile's, prefetched into
+// registers while the previous tile computes) and only the final image is
+// written.
+//
+// The products are the transposes of the layer-by-layer kernels' (A = the
+// weights, M = 16 output channels; B = the pixels, N = 16 pixels of a row),
+// with the same K entries in the same lanes and the same order of steps, so
+// every sum is the same and both paths give the same bits.  Lane (li, g) of
+// D then holds channels nb * 16 + 4g .. + 3 of pixel li: a hidden layer
+// stores them as one 8-byte word, and in the last layer they are the four
+// output pixels X = 4x .. 4x + 3 of output row 4y + g for colour nb (the
+// pixel shuffle), stored as one float4.
+// ---------------------------------------------------------------------------
+constexpr int kFxTX = 60;                  // output pixels per tile row (4 chunks of 16 cover the 64 of L1)
+constexpr int kFxTY = 8;                   // output rows per tile
+constexpr int kFxCols = 66;                // stored columns of every layer region
+constexpr int kFxThreads = 512;
+constexpr int kFxWaves = kFxThreads / 64;  // wave w computes chunk w % 4 of rows (w / 4) * (rows / 2) ...
+constexpr int kFxL0Rows = kFxTY + 6, kFxL1Rows = kFxTY + 4, kFxL2Rows = kFxTY + 2;
+constexpr int kFxR1 = kFxL1Rows / 2, kFxR2 = kFxL2Rows / 2, kFxR3 = kFxTY / 2;  // rows per wave and layer
+constexpr int kFxIn = kFxL0Rows * kFxCols;                                     // input pixels per tile
+constexpr int kFxInPer = (kFxIn + kFxThreads - 1) / kFxThreads;                // ... per thread
+constexpr int kFxMaskWords = 64;           // frame mode: tiles the block-wide list can rank (x 64)
+constexpr int kFxRow = kFxCols * 64;       // bytes per row of a 32-channel region
+// LDS byte offsets.  32-channel regions (L1, L2) hold 64 bytes per pixel, the
+// 16-byte piece j of column c at slot j ^ ((c >> 2) & 3), and the conv2 and
+// conv3 weights 64 bytes per row [tap][co], piece j of row r at slot
+// j ^ ((r >> 2) & 3): the 16 consecutive pixels (rows) that 16 lanes read
+// with ds_read_b128 cover the 64 banks once.  L0 (8 channels, 16 B per
+// pixel) shares its space with L2, which conv2 writes once conv1 is done.
+// W1 holds 12 taps (9 .. 11 zero: the unused K entries of conv1's last step).
+// F: the tile's float32 input, 16 bytes per pixel (3 channels and a zero).
+constexpr int kFxL1 = 0;
+constexpr int kFxL2 = kFxL1 + kFxL1Rows * kFxRow;
+constexpr int kFxL0 = kFxL2;
+constexpr int kFxW1 = kFxL2 + kFxL2Rows * kFxRow;
+constexpr int kFxW2 = kFxW1 + 12 * 32 * 16;
+constexpr int kFxW3 = kFxW2 + 9 * 32 * 64;
+constexpr int kFxBias = kFxW3 + 9 * 48 * 64;
+constexpr int kFxF32 = kFxBias + (32 + 32 + 48) * 4;
+constexpr int kFxMask = kFxF32 + kFxIn * 16;
+constexpr int kFxRank = kFxMask + kFxMaskWords * 8;
+constexpr int kFxBytes = kFxRank + (kFxMaskWords + 1) * 4;
+static_assert(kFxIn * 16 <= kFxL2Rows * kFxRow, "L0 must fit in L2's space");
+static_assert(kFxWaves == 8 && kFxL1Rows % 2 == 0 && kFxL2Rows % 2 == 0 && kFxTY % 2 == 0, "two row groups of 4 chunks");
+static_assert(kFxBytes <= 160 * 1024, "LDS of one compute unit");
+static_assert((kFxR1 + 2) * kFxRow < 65536 && 12 * 32 * 16 < 65536 && 9 * 48 * 64 < 65536, "immediate LDS offsets");
+
+// byte offset of piece j of pixel (row, col) in a 32-channel region
+__device__ __forceinline__ int fx_px(int row, int col, int j) {
+    return row * kFxRow + col * 64 + ((j ^ ((col >> 2) & 3)) << 4);
+}
+// byte offset of piece j of weight row r
+__device__ __forceinline__ int fx_wr(int r, int j) { return r * 64 + ((j ^ ((r >> 2) & 3)) << 4); }
+
+__device__ __forceinline__ uint4 lds16(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+#ifndef FX_STEP_FENCE
+#define FX_STEP_FENCE
+#endif
+// One wave's products of a hidden or last layer: NR rows x 16 pixels x NB x
+// 16 channels.  Row i reads the source from row r0 + i + dy, column
+// c0 + li + dx.  abase[dx]: the lane's byte address of (r0, c0 + li + dx, g)
+// in the source region; wbase: of its piece g of weight row li.  FIRST: the
+// source is L0 (16 B per pixel; step s holds tap 4 s + g, so abase[s] is the
+// lane's address for step s and wbase its row of tap g) and there are three
+// steps; else nine steps of one tap (32 channels, 8 per lane group).  The
+// fragments of the next step are loaded before the products of this one.
+template <int NR, int NB, bool FIRST>
+__device__ __forceinline__ void fx_conv(const uint8_t *const (&abase)[3], const uint8_t *wbase, bool last_ok,
+                                        floatx4 (&acc)[NR][NB]) {
+    constexpr int NS = FIRST ? 3 : 9;
+    constexpr int NOUT = NB * 16;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        uint4 a[NR], wv[NB];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (FIRST) {
+                a[i] = lds16(abase[s] + i * kFxCols * 16);
+                if (s == 2 && !last_ok) a[i] = uint4{0u, 0u, 0u, 0u};  // K >= 72 (the weights are zero too)
+            } else {
+                a[i] = lds16(abase[s % 3] + (i + s / 3) * kFxRow);
+            }
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            wv[nb] = FIRST ? lds16(wbase + (4 * s * 32 + nb * 16) * 16) : lds16(wbase + (s * NOUT + nb * 16) * 64);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) acc[i][nb] = mfma16(as_bf16x8(wv[nb]), as_bf16x8(a[i]), acc[i][nb]);
+        FX_STEP_FENCE
+    }
+}
+
+// Epilogue of a hidden layer: ReLU(acc + bias) rounded to bf16, channels
+// nb * 16 + 4g .. + 3 of the lane's pixel as one 8-byte store; zero for a
+// pixel outside the image (the next layer's zero padding).  dst[nb]: the
+// lane's address of its pixel in row r0, channels nb * 16 + 4g; rowin: bit i
+// set when row r0 + i lies in the image; in: the lane's column does.
+template <int NR>
+__device__ __forceinline__ void fx_hidden_store(uint8_t *const (&dst)[2], const floatx4 (&acc)[NR][2],
+                                                const float (&bias)[2][4], uint32_t rowin, bool in) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const bool on = in && ((rowin >> i) & 1u);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            uint2 v;
+            v.x = bf16_bits(fmaxf(acc[i][nb][0] + bias[nb][0], 0.0f)) |
+                  ((uint32_t)bf16_bits(fmaxf(acc[i][nb][1] + bias[nb][1], 0.0f)) << 16);
+            v.y = bf16_bits(fmaxf(acc[i][nb][2] + bias[nb][2], 0.0f)) |
+                  ((uint32_t)bf16_bits(fmaxf(acc[i][nb][3] + bias[nb][3], 0.0f)) << 16);
+            if (!on) v = uint2{0u, 0u};
+            *reinterpret_cast<uint2 *>(dst[nb] + i * kFxRow) = v;
+        }
+    }
+}
+
+struct FxTile {
+    int b, x0, y0;
+};
+
+__device__ __forceinline__ FxTile fx_tile(int64_t t, int tiles_x, int tiles_y) {
+    FxTile r;
+    r.x0 = (int)(t % tiles_x) * kFxTX;
+    const int64_t rest = t / tiles_x;
+    r.y0 = (int)(rest % tiles_y) * kFxTY;
+    r.b = (int)(rest / tiles_y);
+    return r;
+}
+
+// frame mode: true when the composite takes none of the tile's pixels from the periphery
+__device__ __forceinline__ bool fx_tile_inside(const NetFusedArgs &a, const FxTile &t) {
+    if (!a.gv) return false;
+    const DevView &v = a.gv[(int64_t)t.b * a.gv_stride];
+    return inside_mid(t.x0, min(t.x0 + kFxTX, a.w) - 1, t.y0, min(t.y0 + kFxTY, a.h) - 1, v.v.gx, v.v.gy, a.rm);
+}
+
+// Global loads of a tile's float32 input (3 channels of the thread's pixels;
+// zero outside the image) into registers.
+__device__ __forceinline__ void fx_fetch(const NetFusedArgs &a, const FxTile &t, int tid, float (&v)[kFxInPer][3]) {
+    const float *src = a.img_in + (int64_t)t.b * a.img_bstride;
+    const int64_t plane = (int64_t)a.h * a.w;
+#pragma unroll
+    for (int k = 0; k < kFxInPer; ++k) {
+        const int q = tid + k * kFxThreads;
+        const int r = q / kFxCols, c = q - r * kFxCols;
+        const int y = t.y0 - 3 + r, x = t.x0 - 3 + c;
+        v[k][0] = v[k][1] = v[k][2] = 0.0f;
+        if (q < kFxIn && y >= 0 && y < a.h && x >= 0 && x < a.w) {
+            const int64_t o = (int64_t)y * a.w + x;
+            v[k][0] = src[o];
+            v[k][1] = src[plane + o];
+            v[k][2] = src[2 * plane + o];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
+    __shared__ __attribute__((aligned(16))) uint8_t sm[kFxBytes];
+    const int h = fa.h, w = fa.w;
+    const int tiles_x = (w + kFxTX - 1) / kFxTX, tiles_y = (h + kFxTY - 1) / kFxTY;
+    const int64_t ntiles = (int64_t)fa.B * tiles_x * tiles_y;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int cb = 16 * (wave & 3), grp = wave >> 2;  // this wave's chunk and row group
+    uint64_t *mask = reinterpret_cast<uint64_t *>(sm + kFxMask);
+    uint32_t *rank = reinterpret_cast<uint32_t *>(sm + kFxRank);
+
+    // ---- the tiles this block takes: every G-th of the list, G = gridDim.x.  In
+    // frame mode with at most 64 x kFxMaskWords tiles the list holds only the
+    // tiles with periphery pixels (ranked once per block), so that blocks get
+    // equal shares; otherwise it is every tile (inside ones are then skipped).
+    const bool ranked = fa.gv && ntiles <= 64 * kFxMaskWords;
+    int64_t nlist = ntiles;
+    if (ranked) {
+        for (int t0 = 0; t0 < ntiles; t0 += kFxThreads) {
+            const int t = t0 + tid;
+            const bool real = t < ntiles && !fx_tile_inside(fa, fx_tile(t, tiles_x, tiles_y));
+            const uint64_t bal = __ballot(real);
+            if (lane == 0) mask[(t0 >> 6) + wave] = bal;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            const int nw = (int)((ntiles + 63) >> 6);
+            for (int k = 0; k < nw; ++k) {
+                rank[k] = acc;
+                acc += (uint32_t)__popcll(mask[k]);
+            }
+            rank[nw] = acc;
+        }
+        __syncthreads();
+        nlist = rank[(ntiles + 63) >> 6];
+    }
+    // list entry -> tile index
+    auto tile_of = [&](int64_t e) -> int64_t {
+        if (!ranked) return e;
+        int k = 0;
+        while (rank[k + 1] <= (uint32_t)e) ++k;
+        uint64_t m = mask[k];
+        for (uint32_t n = (uint32_t)e - rank[k]; n > 0; --n) m &= m - 1;  // drop the lower set bits
+        return (int64_t)k * 64 + __builtin_ctzll(m);
+    };
+    if ((int64_t)blockIdx.x >= nlist) return;  // block-uniform
+
+    // ---- weights (rounded to bf16 here, as net_pack_item does) and biases, once per block
+    {
+        const float *th = fa.theta;
+        // conv1 [co][c][tap] -> W1 rows [tap][co] of 8 channels (3 real); taps 9 .. 11 zero
+        for (int rw = tid; rw < 12 * 32; rw += kFxThreads) {
+            const int tap = rw / 32, co = rw % 32;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (tap < 9) {
+                v.x = bf16_bits(th[kNetW1 + (co * 3 + 0) * 9 + tap]) |
+                      ((uint32_t)bf16_bits(th[kNetW1 + (co * 3 + 1) * 9 + tap]) << 16);
+                v.y = bf16_bits(th[kNetW1 + (co * 3 + 2) * 9 + tap]);
+            }
+            *reinterpret_cast<uint4 *>(sm + kFxW1 + rw * 16) = v;
+        }
+        // conv2 [co][ci][tap], conv3 [co][ci][tap] -> rows [tap][co] of 32 channels: every
+        // load issued first (read in order), then rounded and scattered
+        constexpr int N2 = 32 * 32 * 9 / kFxThreads, N3 = 48 * 32 * 9 / kFxThreads;
+        static_assert(N2 * kFxThreads == 32 * 32 * 9 && N3 * kFxThreads == 48 * 32 * 9, "whole rounds");
+        float v2[N2], v3[N3];
+#pragma unroll
+        for (int m = 0; m < N2; ++m) v2[m] = th[kNetW2 + tid + m * kFxThreads];
+#pragma unroll
+        for (int m = 0; m < N3; ++m) v3[m] = th[kNetW3 + tid + m * kFxThreads];
+#pragma unroll
+        for (int m = 0; m < N2; ++m) {
+            const int k = tid + m * kFxThreads, tap = k % 9, ci = (k / 9) % 32, co = k / 288;
+            *reinterpret_cast<uint16_t *>(sm + kFxW2 + fx_wr(tap * 32 + co, ci >> 3) + (ci & 7) * 2) = bf16_bits(v2[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < N3; ++m) {
+            const int k = tid + m * kFxThreads, tap = k % 9, ci = (k / 9) % 32, co = k / 288;
+            *reinterpret_cast<uint16_t *>(sm + kFxW3 + fx_wr(tap * 48 + co, ci >> 3) + (ci & 7) * 2) = bf16_bits(v3[m]);
+        }
+    }
+    float *sb = reinterpret_cast<float *>(sm + kFxBias);
+    if (tid < 112) sb[tid] = fa.theta[tid < 32 ? kNetB1 + tid : (tid < 64 ? kNetB2 + tid - 32 : kNetB3 + tid - 64)];
+    float4 *F = reinterpret_cast<float4 *>(sm + kFxF32);
+
+    // ---- per-lane addresses, the same for every tile
+    const int r1 = grp * kFxR1, r2 = grp * kFxR2, r3 = grp * kFxR3;
+    const uint8_t *a1[3], *a2[3], *a3[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int tap = min(4 * s + g, 8);  // taps 9 .. 11: any valid pixel (its products are zeroed)
+        a1[s] = sm + kFxL0 + ((r1 + tap / 3) * kFxCols + cb + li + tap % 3) * 16;
+        a2[s] = sm + kFxL1 + fx_px(r2, cb + li + s, g);
+        a3[s] = sm + kFxL2 + fx_px(r3, cb + li + s, g);
+    }
+    const bool ok1 = g == 0;  // the lane's K entries of conv1's last step are real (tap 8)
+    const uint8_t *w1 = sm + kFxW1 + (g * 32 + li) * 16;
+    const uint8_t *w2 = sm + kFxW2 + fx_wr(li, g), *w3 = sm + kFxW3 + fx_wr(li, g);
+    uint8_t *d1[2], *d2[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int j = 2 * nb + (g >> 1), sub = (g & 1) * 8;
+        d1[nb] = sm + kFxL1 + fx_px(r1, cb + li, j) + sub;
+        d2[nb] = sm + kFxL2 + fx_px(r2, cb + li, j) + sub;
+    }
+    float bias1[2][4], bias2[2][4];
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bias1[nb][r] = sb[nb * 16 + 4 * g + r];
+            bias2[nb][r] = sb[32 + nb * 16 + 4 * g + r];
+        }
+    const int64_t oplane = (int64_t)(4 * h) * (4 * w);
+    const bool vec_out = (reinterpret_cast<uintptr_t>(fa.img_out) & 15) == 0 && (fa.out_bstride & 3) == 0;
+
+    float pre[kFxInPer][3];
+    FxTile cur = fx_tile(tile_of(blockIdx.x), tiles_x, tiles_y);
+    fx_fetch(fa, cur, tid, pre);
+    for (int64_t e = blockIdx.x; e < nlist; e += gridDim.x) {
+        const FxTile t = cur;
+        const bool skip_tile = !ranked && fx_tile_inside(fa, t);  // block-uniform
+        double gx = 0.0, gy = 0.0;
+        if (fa.gv) {
+            gx = fa.gv[(int64_t)t.b * fa.gv_stride].v.gx;
+            gy = fa.gv[(int64_t)t.b * fa.gv_stride].v.gy;
+        }
+        const int x0 = t.x0, y0 = t.y0;
+        const int xend = min(x0 + kFxTX, w);
+        // ---- the tile's input: bf16 NHWC8 (L0) and float32 planar (F)
+#pragma unroll
+        for (int k = 0; k < kFxInPer; ++k) {
+            const int q = tid + k * kFxThreads;
+            if (q < kFxIn) {
+                uint4 pk;
+                pk.x = bf16_bits(pre[k][0]) | ((uint32_t)bf16_bits(pre[k][1]) << 16);
+                pk.y = bf16_bits(pre[k][2]);
+                pk.z = pk.w = 0u;
+                *reinterpret_cast<uint4 *>(sm + kFxL0 + q * 16) = pk;
+                F[q] = float4{pre[k][0], pre[k][1], pre[k][2], 0.0f};
+            }
+        }
+        __syncthreads();
+        // the next tile's input is fetched while this one computes
+        if (e + gridDim.x < nlist) {
+            cur = fx_tile(tile_of(e + gridDim.x), tiles_x, tiles_y);
+            fx_fetch(fa, cur, tid, pre);
+        }
+        // ---- conv1: L1 rows r1 .. r1 + kFxR1 - 1 (image (y0 - 2, x0 - 2) at L1 (0, 0)); L0 row R + 1 + dy
+        if (!skip_tile) {
+            const int ya = y0 - 2 + r1, xa = x0 - 2 + cb;
+            if (!(fa.gv && inside_mid(max(xa - 2, 0), min(xa + 17, w - 1), max(ya - 2, 0), min(ya + kFxR1 + 1, h - 1),
+                                      gx, gy, fa.rm))) {  // wave-uniform
+                floatx4 acc[kFxR1][2];
+                fx_conv<kFxR1, 2, true>(a1, w1, ok1, acc);
+                uint32_t rowin = 0;
+#pragma unroll
+                for (int i = 0; i < kFxR1; ++i) rowin |= (ya + i >= 0 && ya + i < h) ? 1u << i : 0u;
+                const int x = xa + li;
+                fx_hidden_store<kFxR1>(d1, acc, bias1, rowin, x >= 0 && x < w);
+            }
+        }
+        __syncthreads();
+        // ---- conv2: L2 rows r2 .. (image (y0 - 1, x0 - 1) at L2 (0, 0)); L1 row R + 1 + dy
+        if (!skip_tile) {
+            const int ya = y0 - 1 + r2, xa = x0 - 1 + cb;
+            if (!(fa.gv && inside_mid(max(xa - 1, 0), min(xa + 16, w - 1), max(ya - 1, 0), min(ya + kFxR2, h - 1), gx,
+                                      gy, fa.rm))) {
+                floatx4 acc[kFxR2][2];
+                fx_conv<kFxR2, 2, false>(a2, w2, true, acc);
+                uint32_t rowin = 0;
+#pragma unroll
+                for (int i = 0; i < kFxR2; ++i) rowin |= (ya + i >= 0 && ya + i < h) ? 1u << i : 0u;
+                const int x = xa + li;
+                fx_hidden_store<kFxR2>(d2, acc, bias2, rowin, x >= 0 && x < w);
+            }
+        }
+        __syncthreads();
+        // ---- conv3 + pixel shuffle + bilinear residual: output rows y0 + r3 ..; L2 row R + 1 + dy
+        if (!skip_tile) {
+            const int yb0 = y0 + r3, xs = x0 + cb;
+            if (yb0 < h && xs < xend &&
+                !(fa.gv && inside_mid(xs, min(xs + 15, w - 1), yb0, min(yb0 + kFxR3 - 1, h - 1), gx, gy, fa.rm))) {
+                floatx4 acc[kFxR3][3];
+                fx_conv<kFxR3, 3, false>(a3, w3, true, acc);
+                // lane: pixel x, output columns X = 4x + r, output rows 4y + g
+                const int x = xs + li;
+                if (x < xend) {
+                    const int fx0 = x0 - 3, fy0 = y0 - 3;
+                    // the residual's taps (as shuffle_epilogue): columns xa_r, xb_r are among
+                    // xl = max(x - 1, 0), x, xr = min(x + 1, w - 1): r >= 2 and x = 0 take (x, xr),
+                    // else (xl, x); weights wx_r as computed there
+                    float wx[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float sx = ((float)(4 * x + r) + 0.5f) * 0.25f - 0.5f;
+                        sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
+                        wx[r] = sx - floorf(sx);
+                    }
+                    const int cl = max(x - 1, 0) - fx0, cm = x - fx0, cr = min(x + 1, w - 1) - fx0;
+                    const bool left = x >= 1;
+                    double dx2[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (fa.gv)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const double dx = ((double)(4 * x + r) + 0.5) - gx;
+                            dx2[r] = dx * dx;
+                        }
+                    float *ob = fa.img_out + (int64_t)t.b * fa.out_bstride + (int64_t)4 * x;
+#pragma unroll
+                    for (int i = 0; i < kFxR3; ++i) {
+                        const int y = yb0 + i;
+                        if (y >= h) break;  // wave-uniform
+                        const int Y = 4 * y + g;
+                        float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
+                        sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
+                        const float f0 = floorf(sy);
+                        const int ya_ = (int)f0, yb_ = ya_ + 1 < h ? ya_ + 1 : h - 1;
+                        const float wy = sy - f0;
+                        bool keep[4] = {true, true, true, true};
+                        if (fa.gv) {
+                            const double dy = ((double)Y + 0.5) - gy, dy2 = dy * dy, rm2 = fa.rm * fa.rm;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) keep[r] = dx2[r] + dy2 > rm2;
+                        }
+                        const bool all = keep[0] && keep[1] && keep[2] && keep[3];
+                        // vertical interpolation in the three columns
+                        const float4 *fa_ = F + (ya_ - fy0) * kFxCols, *fb_ = F + (yb_ - fy0) * kFxCols;
+                        const float4 ta[3] = {fa_[cl], fa_[cm], fa_[cr]}, tb[3] = {fb_[cl], fb_[cm], fb_[cr]};
+                        float v[3][3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            v[k][0] = (1.0f - wy) * ta[k].x + wy * tb[k].x;
+                            v[k][1] = (1.0f - wy) * ta[k].y + wy * tb[k].y;
+                            v[k][2] = (1.0f - wy) * ta[k].z + wy * tb[k].z;
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float vlo_a = left ? v[0][c] : v[1][c], vlo_b = left ? v[1][c] : v[2][c];
+                            float o[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const float va = r < 2 ? vlo_a : v[1][c], vb = r < 2 ? vlo_b : v[2][c];
+                                const int ch = c * 16 + 4 * g + r;
+                                o[r] = (acc[i][c][r] + sb[64 + ch]) + ((1.0f - wx[r]) * va + wx[r] * vb);
+                            }
+                            float *dst = ob + c * oplane + (int64_t)Y * (4 * w);
+                            if (vec_out && all) {
+                                *reinterpret_cast<float4 *>(dst) = float4{o[0], o[1], o[2], o[3]};
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    if (keep[r]) dst[r] = o[r];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // L0 / F are rewritten by the next tile
     }
 }
 
@@ -563,6 +990,18 @@ void launch_net_conv(int layer, bool dgrad, const NetConvArgs &a_in, hipStream_t
         if (layer == 3) hipLaunchKernelGGL((k_net_conv<48, 32, kEpiMask, false>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_net_conv<32, 32, kEpiMask, false>), grid, dim3(256), 0, s, a);
     }
+}
+
+constexpr int64_t kNetFusedBlocks = 256;
+
+void launch_net_fused(const NetFusedArgs &a_in, hipStream_t s) {
+    NetFusedArgs a = a_in;
+    if (a.img_bstride == 0) a.img_bstride = 3 * (int64_t)a.h * a.w;
+    if (a.out_bstride == 0) a.out_bstride = 3 * (int64_t)(4 * a.h) * (4 * a.w);
+    const int64_t tiles = (int64_t)a.B * ((a.h + kFxTY - 1) / kFxTY) * ((a.w + kFxTX - 1) / kFxTX);
+    // resident blocks, one per compute unit (the tile's LDS fills most of one)
+    hipLaunchKernelGGL(k_net_fused, dim3((unsigned)std::min<int64_t>(tiles, kNetFusedBlocks)), dim3(kFxThreads), 0, s,
+                       a);
 }
 
 void launch_net_wgrad(int layer, const NetWgradArgs &a, int slabs, hipStream_t s) {

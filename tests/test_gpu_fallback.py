@@ -145,10 +145,11 @@ def test_fallback_off_and_zero_network_leave_frame_unchanged(pkg):
 @pytest.mark.parametrize("gaze", ["centre", "off_centre"])
 def test_upsampler_in_frame_matches_stage_calls(pkg, gaze):
     """render_foveated with the network equals: the layers through the stage
-    calls, the periphery layer through a3fr_net_forward, a3fr_composite.  In
-    the frame the network runs on both eyes in one batch, skips what lies
-    within r_mid of each eye's own gaze and writes the periphery in place, so
-    distinct gazes near the image border are checked too."""
+    calls, the periphery layer through a3fr_net_forward (its layer-by-layer
+    training forward), a3fr_composite.  In the frame the fused network runs on
+    both eyes in one batch, skips the tiles and units that lie within r_mid of
+    each eye's own gaze and writes the periphery in place, so distinct gazes
+    near the image border are checked too."""
     W, H = 464, 480
     gz = [(0.3 * W, 0.7 * H), (0.9 * W, 0.08 * H)] if gaze == "off_centre" else None
     scene, cams, gz, rad = _frame(100_000, W, H, seed=8, gz=gz)
@@ -171,7 +172,7 @@ def test_upsampler_in_frame_matches_stage_calls(pkg, gaze):
         img = [L[3 * offs[3 * e + k]: 3 * offs[3 * e + k + 1]] for k in range(3)]
         per = img[2].view(1, 3, H // 4, W // 4)
         pf = torch.empty((1, 3, H, W), device="cuda")
-        ctx.net_forward(theta, per, pf, False)
+        ctx.net_forward(theta, per, pf, True)
         ctx.composite(W, H, gz[e], fov, img[0], img[1], img[2], pf[0], ref[e])
     ctx.sync()
     assert torch.equal(out, ref)
