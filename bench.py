@@ -143,7 +143,7 @@ def main():
     ap.add_argument("--gazes", type=int, default=16, help="seeded gazes per workload in the workloads leg")
     ap.add_argument("--legs", default="all",
                     help="comma-separated extra legs to run (parts, workloads, incremental, amr, pipeline, "
-                         "net_training, trace, training) or 'all'")
+                         "upsampler, net_training, trace, training) or 'all'")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -339,7 +339,7 @@ def main():
             ", ".join(f"{k}={v['ms_per_frame']:.3f}ms" for k, v in stages.items()))
 
     legs = set(args.legs.split(",")) if args.legs != "all" else {"parts", "workloads", "incremental", "amr", "pipeline",
-                                                                "net_training", "trace", "training"}
+                                                                "upsampler", "net_training", "trace", "training"}
     training = train_leg(pkg, synth, torch, np, args.train_steps) if args.train_steps > 0 and "training" in legs \
         else None
     extra = {}
@@ -356,6 +356,8 @@ def main():
                                    layered=dict(ms_per_frame=ms_f, periphery_psnr_db=min(psnr) if psnr else None))
         if "pipeline" in legs:
             extra["concurrent_pipeline"] = pipeline_leg(pkg, synth, torch, ds, cams, fov, method_options)
+        if "upsampler" in legs:
+            extra["upsampler_inference"] = upsampler_leg(pkg, synth, torch, np, ds, rad, fov, args, nets)
         if "net_training" in legs:
             extra["upsampler_training"] = net_train_leg(pkg, synth, torch, np, ctx, ds)
         if "trace" in legs:
@@ -510,10 +512,8 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
     first at the image centre): for each periphery option (bilinear, with the
     error estimate, the workload's network, both) the frame time, the periphery
     PSNR against the full-resolution render (minimum over the eyes) and the
-    fallback tiles; the full-resolution frame time of the pose; for a workload
-    whose network the method uses, the network stage alone (profiled frame)."""
+    fallback tiles; the full-resolution frame time of the pose."""
     import statistics as stats
-    import numpy as np
     res = {}
     for w, head in (("inside", synth.HEAD_INSIDE), ("outside", synth.HEAD_OUTSIDE)):
         _, cams = synth.foveated_stereo(n=1, head=head)
@@ -537,25 +537,6 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
                 ms = timed(step, max(3, args.steps // 4))
                 rows[name].append((ms, min(_psnr_outside_fovea(c, W, H, gz, rad, out, ref)),
                                    c.get_counts()["n_fallback_tiles"]))
-        net_stage = None
-        if nets[w]["use"]:
-            # the network's stage alone (a profiled frame keeps one stream) at the centre gaze
-            gz = [gazes[0], gazes[0]]
-            set_frame_options(pkg, c, nets[w]["theta"], True, None)
-            c.render_foveated(ds, cams, gz, fov, out)
-            n_prof = max(3, args.steps // 4)
-            c.set_profiling(True, count_pairs=False)
-            for _ in range(n_prof):
-                c.render_foveated(ds, cams, gz, fov, out)
-            c.sync()
-            st = c.get_profile()["stages"]["net"]
-            c.set_profiling(False)
-            flop = net_frame_flop(np, W, H, gz, rad[1])
-            ms = st["ms"] / n_prof
-            tf = flop / (ms / 1000.0) / 1e12
-            net_stage = dict(ms_per_frame=ms, launches_per_frame=st["launches"] / n_prof, flop_per_frame=flop,
-                             bound="mfma", achieved_TFLOPs=tf, frac=tf / BF16_MFMA_PEAK_TF)
-            log(f"workload {w}: network stage {ms * 1000:.1f} us per stereo frame, {tf:.0f} TFLOP/s")
         c.close()
         ntiles = 2 * ((W // 4 + 15) // 16) * ((H // 4 + 15) // 16)
         summ = {}
@@ -568,12 +549,63 @@ def workloads_leg(pkg, synth, torch, ds, rad, fov, args, timed, nets):
                    key=lambda n_: 1.0 / summ[n_]["ms_median"], default=None)
         res[w] = dict(head=list(head), gazes=len(gazes), full_res_ms=ms_frr, options=summ,
                       network=dict(used_by_method=nets[w]["use"], held_out_psnr_db=nets[w]["held_out_psnr_db"],
-                                   pairs=nets[w]["pairs"], epochs=nets[w]["epochs"], stage=net_stage),
+                                   pairs=nets[w]["pairs"], epochs=nets[w]["epochs"]),
                       fastest_option_at_30db=best,
                       speedup_vs_full_res=(ms_frr / summ[best]["ms_median"]) if best else None)
         log(f"workload {w}: FRR {ms_frr:.3f} ms; " + "; ".join(
             f"{n_} {v['ms_median']:.3f} ms, PSNR min {v['psnr_min_db']:.2f} dB, fallback "
             f"{v['fallback_tile_fraction_mean']:.3f}" for n_, v in summ.items()))
+    return res
+
+
+def upsampler_leg(pkg, synth, torch, np, ds, rad, fov, args, nets):
+    """The upsampler's inference forward (one fused launch): on the stereo
+    periphery layer as a whole (a3fr_net_forward, 2 x 3 x H/4 x W/4 -> 4x) and
+    as the foveated frame runs it (the camera-outside workload, whose network
+    the method uses, centre gaze: tiles and units within r_mid skipped, only the
+    periphery written), timed alone: the frame's network stage from a profiled
+    frame (one stream).  FLOPs count the multiply-adds the method must spend
+    (every pixel, resp. net_frame_flop)."""
+    _, cams = synth.foveated_stereo(n=1, head=synth.HEAD_OUTSIDE)
+    W, H = cams[0].width, cams[0].height
+    theta = nets["outside"]["theta"]
+    c = pkg.Context()
+    x = torch.rand((2, 3, H // 4, W // 4), device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    y = torch.empty((2, 3, H, W), device="cuda")
+    n = max(5, args.steps)
+    for _ in range(3):
+        c.net_forward(theta, x, y, False)
+    c.sync()
+    t = time.perf_counter()
+    for _ in range(n):
+        c.net_forward(theta, x, y, False)
+    c.sync()
+    ms_whole = (time.perf_counter() - t) * 1000.0 / n
+    flop_whole = NET_FLOP_PER_INPUT_PIXEL * 2 * (H // 4) * (W // 4)
+    gz = [(cams[0].cx, cams[0].cy)] * 2
+    out = torch.empty((2, 3, H, W), device="cuda")
+    set_frame_options(pkg, c, theta, True, None)
+    c.render_foveated(ds, cams, gz, fov, out)
+    c.set_profiling(True, count_pairs=False)
+    for _ in range(n):
+        c.render_foveated(ds, cams, gz, fov, out)
+    c.sync()
+    st = c.get_profile()["stages"]["net"]
+    c.set_profiling(False)
+    c.close()
+    ms_frame = st["ms"] / n
+    flop_frame = net_frame_flop(np, W, H, gz, rad[1])
+
+    def rate(flop, ms):
+        tf = flop / (ms / 1000.0) / 1e12
+        return dict(bound="mfma", achieved_TFLOPs=tf, peak_TFLOPs=BF16_MFMA_PEAK_TF, frac=tf / BF16_MFMA_PEAK_TF)
+
+    res = dict(kernel="k_net_fused",
+               whole_layer=dict(us_per_forward=ms_whole * 1000.0, flop=flop_whole, **rate(flop_whole, ms_whole)),
+               frame_stage=dict(us_per_frame=ms_frame * 1000.0, launches_per_frame=st["launches"] / n,
+                                flop=flop_frame, **rate(flop_frame, ms_frame)))
+    log(f"upsampler: whole layer {ms_whole * 1000:.1f} us ({res['whole_layer']['achieved_TFLOPs']:.0f} TFLOP/s); "
+        f"frame stage {ms_frame * 1000:.1f} us ({res['frame_stage']['achieved_TFLOPs']:.0f} TFLOP/s)")
     return res
 
 

@@ -522,6 +522,111 @@ __device__ __forceinline__ void fx_fetch(const NetFusedArgs &a, const FxTile &t,
     }
 }
 
+// The last layer's epilogue for the wave's kFxR3 output rows: lane (li, g)
+// holds channels c * 16 + 4g + r of pixel x = xs + li, i.e. output pixels
+// (4x + r, 4y + g) of colour c (the pixel shuffle); it adds the bias and the
+// bilinear residual (as shuffle_epilogue: vertical interpolation in columns
+// xa_r and xb_r, then horizontal; those columns are among xl = max(x - 1, 0),
+// x, xr = min(x + 1, w - 1): r >= 2 and x = 0 take (x, xr), else (xl, x)) and
+// stores the four as one float4.  FAST: every row lies in the image and every
+// output pixel outside r_mid (no checks but the tile's right edge).
+template <bool FAST, int NR>
+__device__ __forceinline__ void fx_last_epilogue(const NetFusedArgs &fa, const floatx4 (&acc)[NR][3],
+                                                 const float4 *F, const float *b3, int b, int x0, int y0, int yb0,
+                                                 int xs, int xend, int li, int g, int64_t oplane, bool vec_out,
+                                                 double gx, double gy) {
+    const int h = fa.h, w = fa.w;
+    const int x = xs + li;
+    if (!FAST && x >= xend) return;
+    const int fx0 = x0 - 3, fy0 = y0 - 3;
+    float wx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float sx = ((float)(4 * x + r) + 0.5f) * 0.25f - 0.5f;
+        sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
+        wx[r] = sx - floorf(sx);
+    }
+    const int cl = max(x - 1, 0) - fx0, cm = x - fx0, cr = min(x + 1, w - 1) - fx0;
+    const bool left = x >= 1;
+    double dx2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!FAST && fa.gv)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double dx = ((double)(4 * x + r) + 0.5) - gx;
+            dx2[r] = dx * dx;
+        }
+    float *ob = fa.img_out + (int64_t)b * fa.out_bstride + (int64_t)4 * x;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int y = yb0 + i;
+        if (!FAST && y >= h) break;  // wave-uniform
+        const int Y = 4 * y + g;
+        float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
+        sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
+        const float f0 = floorf(sy);
+        const int ya_ = (int)f0, yb_ = ya_ + 1 < h ? ya_ + 1 : h - 1;
+        const float wy = sy - f0;
+        bool keep[4] = {true, true, true, true};
+        if (!FAST && fa.gv) {
+            const double dy = ((double)Y + 0.5) - gy, dy2 = dy * dy, rm2 = fa.rm * fa.rm;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) keep[r] = dx2[r] + dy2 > rm2;
+        }
+        const bool all = keep[0] && keep[1] && keep[2] && keep[3];
+        // vertical interpolation in the three columns
+        const float4 *fa_ = F + (ya_ - fy0) * kFxCols, *fb_ = F + (yb_ - fy0) * kFxCols;
+        const float4 ta[3] = {fa_[cl], fa_[cm], fa_[cr]}, tb[3] = {fb_[cl], fb_[cm], fb_[cr]};
+        float v[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[k][0] = (1.0f - wy) * ta[k].x + wy * tb[k].x;
+            v[k][1] = (1.0f - wy) * ta[k].y + wy * tb[k].y;
+            v[k][2] = (1.0f - wy) * ta[k].z + wy * tb[k].z;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float vlo_a = left ? v[0][c] : v[1][c], vlo_b = left ? v[1][c] : v[2][c];
+            float o[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float va = r < 2 ? vlo_a : v[1][c], vb = r < 2 ? vlo_b : v[2][c];
+                const int ch = c * 16 + 4 * g + r;
+                o[r] = (acc[i][c][r] + b3[ch]) + ((1.0f - wx[r]) * va + wx[r] * vb);
+            }
+            float *dst = ob + c * oplane + (int64_t)Y * (4 * w);
+            if (FAST) {
+                *reinterpret_cast<float4 *>(dst) = float4{o[0], o[1], o[2], o[3]};
+            } else if (vec_out && all) {
+                *reinterpret_cast<float4 *>(dst) = float4{o[0], o[1], o[2], o[3]};
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (keep[r]) dst[r] = o[r];
+            }
+        }
+    }
+}
+
+// frame mode: true when every output pixel of the whole tile at (x0, y0) lies
+// outside r_mid (its rectangle's nearest point to the gaze does, with a
+// relative margin that keeps rounding on the safe side); always true otherwise
+__device__ __forceinline__ bool fx_tile_outside(const NetFusedArgs &a, int x0, int y0, double gx, double gy) {
+    if (!a.gv) return true;
+    const double xa = 4.0 * x0, xb = 4.0 * (x0 + kFxTX), ya = 4.0 * y0, yb = 4.0 * (y0 + kFxTY);
+    const double dx = gx < xa ? xa - gx : (gx > xb ? gx - xb : 0.0);
+    const double dy = gy < ya ? ya - gy : (gy > yb ? gy - yb : 0.0);
+    return dx * dx + dy * dy > a.rm * a.rm * (1.0 + 1e-12);
+}
+
+// Block barrier that orders LDS only: the output stores and the next tile's
+// input loads stay in flight across it (a plain __syncthreads would wait for
+// them, serialising each tile's stores with the next tile's products).
+__device__ __forceinline__ void fx_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
     __shared__ __attribute__((aligned(16))) uint8_t sm[kFxBytes];
     const int h = fa.h, w = fa.w;
@@ -531,6 +636,9 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, g = lane >> 4;
     const int cb = 16 * (wave & 3), grp = wave >> 2;  // this wave's chunk and row group
+    // the last layer's chunks end at the tile's edge: 0, 16, 32, 44 (pixels 44 .. 47 are
+    // computed by two waves, with the same operands, and stored twice with the same bits)
+    const int cb3 = min(cb, kFxTX - 16);
     uint64_t *mask = reinterpret_cast<uint64_t *>(sm + kFxMask);
     uint32_t *rank = reinterpret_cast<uint32_t *>(sm + kFxRank);
 
@@ -547,7 +655,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
             const uint64_t bal = __ballot(real);
             if (lane == 0) mask[(t0 >> 6) + wave] = bal;
         }
-        __syncthreads();
+        fx_sync();
         if (tid == 0) {
             uint32_t acc = 0;
             const int nw = (int)((ntiles + 63) >> 6);
@@ -557,7 +665,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
             }
             rank[nw] = acc;
         }
-        __syncthreads();
+        fx_sync();
         nlist = rank[(ntiles + 63) >> 6];
     }
     // list entry -> tile index
@@ -617,7 +725,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
         const int tap = min(4 * s + g, 8);  // taps 9 .. 11: any valid pixel (its products are zeroed)
         a1[s] = sm + kFxL0 + ((r1 + tap / 3) * kFxCols + cb + li + tap % 3) * 16;
         a2[s] = sm + kFxL1 + fx_px(r2, cb + li + s, g);
-        a3[s] = sm + kFxL2 + fx_px(r3, cb + li + s, g);
+        a3[s] = sm + kFxL2 + fx_px(r3, cb3 + li + s, g);
     }
     const bool ok1 = g == 0;  // the lane's K entries of conv1's last step are real (tap 8)
     const uint8_t *w1 = sm + kFxW1 + (g * 32 + li) * 16;
@@ -630,7 +738,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
         d2[nb] = sm + kFxL2 + fx_px(r2, cb + li, j) + sub;
     }
     float bias1[2][4], bias2[2][4];
-    __syncthreads();
+    fx_sync();
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
@@ -667,7 +775,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
                 F[q] = float4{pre[k][0], pre[k][1], pre[k][2], 0.0f};
             }
         }
-        __syncthreads();
+        fx_sync();
         // the next tile's input is fetched while this one computes
         if (e + gridDim.x < nlist) {
             cur = fx_tile(tile_of(e + gridDim.x), tiles_x, tiles_y);
@@ -687,7 +795,7 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
                 fx_hidden_store<kFxR1>(d1, acc, bias1, rowin, x >= 0 && x < w);
             }
         }
-        __syncthreads();
+        fx_sync();
         // ---- conv2: L2 rows r2 .. (image (y0 - 1, x0 - 1) at L2 (0, 0)); L1 row R + 1 + dy
         if (!skip_tile) {
             const int ya = y0 - 1 + r2, xa = x0 - 1 + cb;
@@ -702,89 +810,24 @@ __global__ void __launch_bounds__(kFxThreads) k_net_fused(NetFusedArgs fa) {
                 fx_hidden_store<kFxR2>(d2, acc, bias2, rowin, x >= 0 && x < w);
             }
         }
-        __syncthreads();
+        fx_sync();
         // ---- conv3 + pixel shuffle + bilinear residual: output rows y0 + r3 ..; L2 row R + 1 + dy
         if (!skip_tile) {
-            const int yb0 = y0 + r3, xs = x0 + cb;
+            const int yb0 = y0 + r3, xs = x0 + cb3;
             if (yb0 < h && xs < xend &&
                 !(fa.gv && inside_mid(xs, min(xs + 15, w - 1), yb0, min(yb0 + kFxR3 - 1, h - 1), gx, gy, fa.rm))) {
                 floatx4 acc[kFxR3][3];
                 fx_conv<kFxR3, 3, false>(a3, w3, true, acc);
-                // lane: pixel x, output columns X = 4x + r, output rows 4y + g
-                const int x = xs + li;
-                if (x < xend) {
-                    const int fx0 = x0 - 3, fy0 = y0 - 3;
-                    // the residual's taps (as shuffle_epilogue): columns xa_r, xb_r are among
-                    // xl = max(x - 1, 0), x, xr = min(x + 1, w - 1): r >= 2 and x = 0 take (x, xr),
-                    // else (xl, x); weights wx_r as computed there
-                    float wx[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float sx = ((float)(4 * x + r) + 0.5f) * 0.25f - 0.5f;
-                        sx = fminf(fmaxf(sx, 0.0f), (float)(w - 1));
-                        wx[r] = sx - floorf(sx);
-                    }
-                    const int cl = max(x - 1, 0) - fx0, cm = x - fx0, cr = min(x + 1, w - 1) - fx0;
-                    const bool left = x >= 1;
-                    double dx2[4] = {0.0, 0.0, 0.0, 0.0};
-                    if (fa.gv)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const double dx = ((double)(4 * x + r) + 0.5) - gx;
-                            dx2[r] = dx * dx;
-                        }
-                    float *ob = fa.img_out + (int64_t)t.b * fa.out_bstride + (int64_t)4 * x;
-#pragma unroll
-                    for (int i = 0; i < kFxR3; ++i) {
-                        const int y = yb0 + i;
-                        if (y >= h) break;  // wave-uniform
-                        const int Y = 4 * y + g;
-                        float sy = ((float)Y + 0.5f) * 0.25f - 0.5f;
-                        sy = fminf(fmaxf(sy, 0.0f), (float)(h - 1));
-                        const float f0 = floorf(sy);
-                        const int ya_ = (int)f0, yb_ = ya_ + 1 < h ? ya_ + 1 : h - 1;
-                        const float wy = sy - f0;
-                        bool keep[4] = {true, true, true, true};
-                        if (fa.gv) {
-                            const double dy = ((double)Y + 0.5) - gy, dy2 = dy * dy, rm2 = fa.rm * fa.rm;
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) keep[r] = dx2[r] + dy2 > rm2;
-                        }
-                        const bool all = keep[0] && keep[1] && keep[2] && keep[3];
-                        // vertical interpolation in the three columns
-                        const float4 *fa_ = F + (ya_ - fy0) * kFxCols, *fb_ = F + (yb_ - fy0) * kFxCols;
-                        const float4 ta[3] = {fa_[cl], fa_[cm], fa_[cr]}, tb[3] = {fb_[cl], fb_[cm], fb_[cr]};
-                        float v[3][3];
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            v[k][0] = (1.0f - wy) * ta[k].x + wy * tb[k].x;
-                            v[k][1] = (1.0f - wy) * ta[k].y + wy * tb[k].y;
-                            v[k][2] = (1.0f - wy) * ta[k].z + wy * tb[k].z;
-                        }
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const float vlo_a = left ? v[0][c] : v[1][c], vlo_b = left ? v[1][c] : v[2][c];
-                            float o[4];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const float va = r < 2 ? vlo_a : v[1][c], vb = r < 2 ? vlo_b : v[2][c];
-                                const int ch = c * 16 + 4 * g + r;
-                                o[r] = (acc[i][c][r] + sb[64 + ch]) + ((1.0f - wx[r]) * va + wx[r] * vb);
-                            }
-                            float *dst = ob + c * oplane + (int64_t)Y * (4 * w);
-                            if (vec_out && all) {
-                                *reinterpret_cast<float4 *>(dst) = float4{o[0], o[1], o[2], o[3]};
-                            } else {
-#pragma unroll
-                                for (int r = 0; r < 4; ++r)
-                                    if (keep[r]) dst[r] = o[r];
-                            }
-                        }
-                    }
-                }
+                // whole tiles whose every output pixel the composite takes: no checks per row or pixel
+                if (vec_out && x0 + kFxTX <= w && y0 + kFxTY <= h && fx_tile_outside(fa, x0, y0, gx, gy))
+                    fx_last_epilogue<true, kFxR3>(fa, acc, F, sb + 64, t.b, x0, y0, yb0, xs, xend, li, g, oplane, true,
+                                                  gx, gy);
+                else
+                    fx_last_epilogue<false, kFxR3>(fa, acc, F, sb + 64, t.b, x0, y0, yb0, xs, xend, li, g, oplane,
+                                                   vec_out, gx, gy);
             }
         }
-        __syncthreads();  // L0 / F are rewritten by the next tile
+        fx_sync();  // L0 / F are rewritten by the next tile
     }
 }
 
