@@ -842,14 +842,13 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         rb[k] = y1[k] + 1;
         base[k] = 0;
     }
+    // row ty: largest y in [y0, y1] with (keys of the entry in rows < y) <= r; bra keeps
+    // that count for row ra (0 for y0), so the row's count needs no second load, and the
+    // prefix of row y0 (base) is loaded with the first bisection step's
+    uint32_t bra[kEmitPer];
 #pragma unroll
-    for (int k = 0; k < kEmitPer; ++k)
-        if (search[k]) {
-            const int64_t st = TX[k] + 1;
-            base[k] = cm[k][(int64_t)y0[k] * st + x1[k] + 1] - cm[k][(int64_t)y0[k] * st + x0[k]];
-        }
-    // row ty: largest y in [y0, y1] with (keys of the entry in rows < y) <= r
-    bool more = true;
+    for (int k = 0; k < kEmitPer; ++k) bra[k] = 0;
+    bool more = true, first = true;
     while (more) {
         more = false;
 #pragma unroll
@@ -857,11 +856,18 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
             if (search[k] && rb[k] - ra[k] > 1) {
                 const int64_t st = TX[k] + 1;
                 const int mid = (ra[k] + rb[k]) >> 1;
-                const uint32_t before = cm[k][(int64_t)mid * st + x1[k] + 1] - cm[k][(int64_t)mid * st + x0[k]] -
-                                        base[k];
-                if (before <= r[k]) ra[k] = mid; else rb[k] = mid;
+                const uint32_t cmid = cm[k][(int64_t)mid * st + x1[k] + 1] - cm[k][(int64_t)mid * st + x0[k]];
+                if (first) base[k] = cm[k][(int64_t)y0[k] * st + x1[k] + 1] - cm[k][(int64_t)y0[k] * st + x0[k]];
+                const uint32_t before = cmid - base[k];
+                if (before <= r[k]) {
+                    ra[k] = mid;
+                    bra[k] = before;
+                } else {
+                    rb[k] = mid;
+                }
                 more |= rb[k] - ra[k] > 1;
             }
+        first = false;
     }
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k)
@@ -870,8 +876,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
             const int t = lo[k];
             const EmitView &ev = s_view[s_v[t]];
             ty[k] = ra[k];
-            const uint32_t before = cm[k][(int64_t)ty[k] * st + x1[k] + 1] - cm[k][(int64_t)ty[k] * st + x0[k]] -
-                                    base[k];
+            const uint32_t before = bra[k];
             const uint16_t *rp = row_prefix + ev.mask_off + (int64_t)ty[k] * st;
             const uint16_t *rl = row_list + ev.mask_off + (int64_t)ty[k] * st;
             tx[k] = rl[rp[x0[k]] + (r[k] - before)];
