@@ -49,31 +49,31 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="a2d61a91ad4fef5b0f1662ae2e118e836388d67974e48691cb785e1a1ffb460e",
-                  kib={"32,4x1,grid": (5909.6, 21750.0),
-                       "32,4x1,queue": (5473.7, 21873.8),
-                       "32,2x2,grid": (5909.2, 21750.0),
-                       "32,2x2,queue": (5414.6, 21630.0),
-                       "64,4x1,grid": (6907.2, 21750.0),
-                       "64,4x1,queue": (6390.5, 21797.6),
-                       "64,2x2,grid": (6910.0, 21750.0),
-                       "64,2x2,queue": (6331.6, 21699.4),
-                       "128,4x1,grid": (9960.5, 21750.0),
-                       "128,4x1,queue": (9215.9, 21896.9),
-                       "128,2x2,grid": (9961.5, 21750.0),
-                       "128,2x2,queue": (9229.0, 21855.2),
-                       "64,8x8q,grid": (10182.7, 21750.0),
-                       "128,8x8q,grid": (18047.5, 21750.0),
-                       "256,8x8q,grid": (32717.9, 21750.0)}),
+                  sha256="ce162a8a40d3dd42d9b6630738ac7d48bc67dec55cc73c107d2f72dbddd0d743",
+                  kib={"32,4x1,grid": (7395.2, 21750.0),
+                       "32,4x1,queue": (6893.1, 23962.8),
+                       "32,2x2,grid": (7389.3, 21750.0),
+                       "32,2x2,queue": (6827.3, 21879.3),
+                       "64,4x1,grid": (10533.2, 21750.0),
+                       "64,4x1,queue": (9874.8, 24573.6),
+                       "64,2x2,grid": (10518.8, 21750.0),
+                       "64,2x2,queue": (9751.1, 22031.9),
+                       "128,4x1,grid": (18969.0, 21750.0),
+                       "128,4x1,queue": (18689.7, 25039.9),
+                       "128,2x2,grid": (18934.0, 21750.0),
+                       "128,2x2,queue": (18283.3, 22377.6),
+                       "64,8x8q,grid": (10183.2, 21750.0),
+                       "128,8x8q,grid": (18049.2, 21750.0),
+                       "256,8x8q,grid": (32726.4, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="e36cdf2b292155e69603c7d44e316b864543986f0acccded73573d137f859577",
-                       kib={"k_preprocess": (43205.2, 84981.3)}),
+                       sha256="c4bcc955a3e42c9363057081922ca4f0dc8de609c9b2b8742253110764f488a7",
+                       kib={"k_preprocess": (43207.0, 131859.6)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="e36cdf2b292155e69603c7d44e316b864543986f0acccded73573d137f859577",
-                   kib={"k_entry_record": (155623.6, 33778.9)}),
+                   sha256="c4bcc955a3e42c9363057081922ca4f0dc8de609c9b2b8742253110764f488a7",
+                   kib={"k_entry_record": (85771.4, 33776.6)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
                       sha256="6eda886ea81a26b72659dcccd6ad1bd920764a0207e494910c07eb8981b6a4e2",
-                      kib={"k_sort_scatter": (40104.2, 81889.4)}),
+                      kib={"k_sort_scatter": (40104.1, 81888.7)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale, quaternion and opacity of every Gaussian
