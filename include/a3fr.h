@@ -430,7 +430,9 @@ a3fr_status a3fr_preprocess_backward(a3fr_ctx *ctx, const a3fr_params *params, c
  *   out = pixel_shuffle_x4(conv3(relu(conv2(relu(conv1(x)))))) + bilinear_x4(x),
  * 3x3 convolutions (zero padding 1, bias) of 3->32, 32->32 and 32->48
  * channels; channel c*16 + 4i + j of conv3 goes to output pixel
- * (c, 4y+i, 4x+j); bilinear with align_corners = false, clamp to edge.
+ * (c, 4y+i, 4x+j); bilinear with align_corners = false, clamp to edge,
+ * interpolated vertically and then horizontally (as the composite's
+ * bilinear, so that a zero network gives the bilinear frame bit for bit).
  * bfloat16 operands (input, weights, post-ReLU activations) on the matrix
  * cores with float32 accumulation; the last layer, the shuffle and the
  * residual are float32.
@@ -440,8 +442,10 @@ a3fr_status a3fr_preprocess_backward(a3fr_ctx *ctx, const a3fr_params *params, c
 #define A3FR_NET_PARAMS 24016
 
 /* in_dev: float32 [B][3][h][w]; out_dev: float32 [B][3][4h][4w].
- * for_training = 1 keeps the activations (and their channel-major copies) in
- * the context for a3fr_net_backward. */
+ * for_training = 0: one fused launch (the activations stay on chip; the
+ * weights are rounded to bf16 in the kernel).  for_training = 1: the three
+ * layers one launch each, keeping the activations (and their channel-major
+ * copies) in the context for a3fr_net_backward.  Both give the same bits. */
 a3fr_status a3fr_net_forward(a3fr_ctx *ctx, const float *theta_dev, const float *in_dev, int32_t batch, int32_t h,
                              int32_t w, float *out_dev, int32_t for_training);
 
