@@ -66,11 +66,11 @@ PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH K
                        "128,8x8q,grid": (18049.2, 21750.0),
                        "256,8x8q,grid": (32726.4, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="c4bcc955a3e42c9363057081922ca4f0dc8de609c9b2b8742253110764f488a7",
-                       kib={"k_preprocess": (43207.0, 131859.6)}),
+                       sha256="af2272d3583a0ee17823ad39331b870d924180520b9047cfb65d45c3a91758ff",
+                       kib={"k_preprocess": (21721.4, 101022.2)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="c4bcc955a3e42c9363057081922ca4f0dc8de609c9b2b8742253110764f488a7",
-                   kib={"k_entry_record": (85771.4, 33776.6)}),
+                   sha256="af2272d3583a0ee17823ad39331b870d924180520b9047cfb65d45c3a91758ff",
+                   kib={"k_entry_record": (85803.4, 33774.8)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
                       sha256="6eda886ea81a26b72659dcccd6ad1bd920764a0207e494910c07eb8981b6a4e2",
                       kib={"k_sort_scatter": (40104.1, 81888.7)}),

@@ -260,9 +260,10 @@ __device__ __forceinline__ uint64_t pack_rect(const LayerProj &L) {
 // (entries that emit keys, and every visible entry of a view whose mask may
 // grow later), its tile rectangle (only in the views that keep rectangles for
 // a later recount or mass estimate, rect_slot >= 0) and, in a selecting view,
-// its score.  The blend record of an entry is formed later, entry by entry
-// (k_entry_record), once the entries are known.
-__global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views,
+// its score; a Gaussian visible in a view of the group also gets its packed
+// geometry (48 B) written for the record pass.  The blend record of an entry
+// is formed later, entry by entry (k_entry_record), once the entries are known.
+__global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView *__restrict__ views, int ngroups,
                                                     const int32_t *__restrict__ groups,
                                                     const uint32_t *__restrict__ cum,
                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ depth,
@@ -273,26 +274,27 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
     for (int k = threadIdx.x; k <= kExtentSteps; k += blockDim.x) s_exp[k] = exp_tab[k];
     __syncthreads();
     const int64_t n = sc.n;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // block b: chunk of 256 Gaussians and eye group, numbered so that the groups of
+    // one chunk are 8 blocks apart (blocks go to the 8 XCDs in turn): they run on
+    // one XCD at about the same time, and the chunk's geometry comes from HBM once
+    const int xl = (int)(blockIdx.x & 7u);
+    const int64_t rest = blockIdx.x >> 3;
+    const int grp = (int)(rest % ngroups);
+    const int64_t chunk = (rest / ngroups) * 8 + xl;
+    const int64_t i = chunk * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int v_begin = groups[blockIdx.y], v_end = groups[blockIdx.y + 1];
+    const int v_begin = groups[grp], v_end = groups[grp + 1];
     const float fx = sc.mean_dev[i], fy = sc.mean_dev[n + i], fz = sc.mean_dev[2 * n + i];
     const float qw = sc.quat_dev[i], qx = sc.quat_dev[n + i], qy = sc.quat_dev[2 * n + i], qz = sc.quat_dev[3 * n + i];
     const float sx = sc.scale_dev[i], sy = sc.scale_dev[n + i], sz = sc.scale_dev[2 * n + i];
     const float op = sc.opacity_dev[i];
-    if (blockIdx.y == 0) {  // the first eye's threads pack the geometry for the record pass
-        GeomPack g;
-        g.a = make_float4(fx, fy, fz, op);
-        g.b = make_float4(sx, sy, sz, qw);
-        g.c = make_float4(qx, qy, qz, 0.0f);
-        pack[i] = g;
-    }
     const double mx = fx, my = fy, mz = fz;
     Cov3 S;
     const bool cov_ok = gaussian_cov3(qw, qx, qy, qz, sx, sy, sz, S);
     EyeProj E;
     eye_project(views[v_begin].v, mx, my, mz, cov_ok, S, E);
     const double qe = footprint_q(op, s_exp);
+    bool seen = false;  // visible in a view of this group
     for (int vi = v_begin; vi < v_end; ++vi) {
         const DevView &dv = views[vi];
         const int64_t slot = (int64_t)vi * n + i;
@@ -324,6 +326,15 @@ __global__ void __launch_bounds__(256) k_preprocess(a3fr_scene sc, const DevView
         }
         counts[slot] = cnt;
         if (dv.rect_slot >= 0) rect[(int64_t)dv.rect_slot * n + i] = L.visible ? pack_rect(L) : kEmptyRect;
+        seen = seen || L.visible;
+    }
+    if (seen) {  // the record pass reads the packed geometry of visible Gaussians only (each group
+                 // seeing one writes the same values)
+        GeomPack g;
+        g.a = make_float4(fx, fy, fz, op);
+        g.b = make_float4(sx, sy, sz, qw);
+        g.c = make_float4(qx, qy, qz, 0.0f);
+        pack[i] = g;
     }
 }
 
@@ -332,8 +343,10 @@ void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, 
                        GeomPack *pack, const double *exp_tab, hipStream_t s) {
     if (sc.n == 0 || ngroups == 0) return;
     const int blk = 256;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((sc.n + blk - 1) / blk), (unsigned)ngroups), dim3(blk), 0, s, sc,
-                       views, groups, cum, counts, depth, rect, score, pack, exp_tab);
+    const int64_t chunks = (sc.n + blk - 1) / blk;
+    const int64_t grid = (chunks + 7) / 8 * 8 * ngroups;  // see k_preprocess for the numbering
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(blk), 0, s, sc, views, ngroups, groups, cum, counts,
+                       depth, rect, score, pack, exp_tab);
 }
 
 // View-dependent colour (degree <= 3 real SH, float32) of Gaussian i (mean
