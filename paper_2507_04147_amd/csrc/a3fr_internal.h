@@ -157,6 +157,7 @@ int64_t select_workspace_words(int nsel, int64_t n);
 int64_t scan_workspace_words(int64_t m);
 // entries (slots with keys, kept; every visible slot of a keep_visible view) in slot order:
 // ent[j] = slot, dkey[j] = depth bits, dval[j] = j, ecnt[j] = the slot's key count (ecnt nullable)
+// keep: a byte per slot, or NULL when no view selects; rect NULL: keep_visible views count as others
 void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const uint64_t *rect, const DevView *views,
                             int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
                             uint32_t *ecnt, uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err,

@@ -805,8 +805,9 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
         // every visible entry of the fovea and mid layers gets its record now, for the later rounds
         {
             StageTimer t_(c, A3FR_STAGE_SCAN);
-            launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), P<uint64_t>(c->rect), dv, nv, n,
-                                   P<uint32_t>(c->depth), P<uint32_t>(c->ent_a), P<uint32_t>(c->dkey_b),
+            launch_compact_entries(P<uint32_t>(c->counts), c->nsel ? P<uint8_t>(c->keep) : nullptr,
+                                   P<uint64_t>(c->rect), dv, nv, n, P<uint32_t>(c->depth), P<uint32_t>(c->ent_a),
+                                   P<uint32_t>(c->dkey_b),
                                    P<uint32_t>(c->dval_b), nullptr, P<uint64_t>(c->block_sums), sc_ent_total(c->scalars),
                                    sc_n_ent(c->scalars), sc_err(c->scalars), c->stream, zeroed);
         }
@@ -826,7 +827,8 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
         // (keep_visible views count as such only in the visible pass)
-        launch_compact_entries(P<uint32_t>(c->counts), P<uint8_t>(c->keep), visible_pass ? nullptr : P<uint64_t>(c->rect),
+        launch_compact_entries(P<uint32_t>(c->counts), c->nsel ? P<uint8_t>(c->keep) : nullptr,
+                               visible_pass ? nullptr : P<uint64_t>(c->rect),
                                dv, nv, n, P<uint32_t>(c->depth), P<uint32_t>(ent), P<uint32_t>(c->dkey_a),
                                P<uint32_t>(c->dval_a), P<uint32_t>(c->ecnt), P<uint64_t>(c->block_sums),
                                sc_ent_total(c->scalars),

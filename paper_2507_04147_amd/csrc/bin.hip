@@ -360,10 +360,13 @@ int64_t select_workspace_words(int nsel, int64_t n) {
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block (key offsets)
-// the compaction's partitions are larger (16 waves of 1024 entries): fewer
-// partitions, so the look-back finds an inclusive prefix within fewer windows
-constexpr int kCompactBlock = 1024;
-constexpr int kCompactTile = kScanItems * kCompactBlock;
+// the compaction's partitions: 12 waves of 1024 slots (two blocks per CU at
+// its register count, so that a stereo frame of a million Gaussians, 6M slots,
+// is in flight at once; fewer, larger partitions take fewer tickets, which
+// are serialised on one device-coherent counter)
+constexpr int kCompactItems = 16;
+constexpr int kCompactBlock = 768;
+constexpr int kCompactTile = kCompactItems * kCompactBlock;
 
 // Slot e = view * n + index is an entry iff it has keys (a count) and, in a
 // selecting view, is kept; in a view with keep_visible, iff its rectangle
@@ -376,16 +379,14 @@ struct EntryFlags {
     int64_t n;
 };
 
-// Key count of the j-th entry in depth order (order: entry indices sorted by
-// depth; ecnt: the entries' key counts in entry order, written by the
-// compaction, so that the gather reads a compact array rather than the slots).
+// Key counts of the entries in depth order: the j-th is ecnt[order[j]]
+// (order: entry indices sorted by depth; ecnt: the entries' key counts in
+// entry order, written by the compaction, so that the gather reads a compact
+// array rather than the slots).
 struct SortedCounts {
     const uint32_t *ecnt;
     const uint32_t *order;
     const uint32_t *n_ent;
-    __device__ __forceinline__ uint32_t operator()(int64_t j, int64_t) const {
-        return j < (int64_t)*n_ent ? ecnt[order[j]] : 0u;
-    }
 };
 
 // wave-level inclusive scan of a 64-bit value (wave64 via shuffles)
@@ -399,35 +400,19 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
     return x;
 }
 
-// block-wide exclusive scan of one 64-bit value per thread (256 threads)
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t *total) {
-    __shared__ uint64_t wsum[kScanBlock / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = wave_incl_scan(x);
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint64_t wpre = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < kScanBlock / 64; ++k) {
-        if (k < w) wpre += wsum[k];
-        tot += wsum[k];
-    }
-    __syncthreads();
-    *total = tot;
-    return wpre + inc - x;
-}
-
-// Single-pass scans with decoupled look-back.  Each block takes its
-// partition (kScanTile consecutive items) from a ticket counter, so a
-// partition's predecessors are already held by running blocks; it publishes
-// its total (flag AGG), then wave 0 walks back over the predecessors' words,
-// 64 at a time, adding totals until it meets an inclusive prefix (flag INC),
-// and publishes its own inclusive prefix.  Status words are 64-bit: flag in
-// the top two bits, value in the low 62, zeroed before the launch.
-// Workspace (uint64): [0] compaction ticket, [1] offsets ticket, then the
-// compaction partitions' words, then the offsets partitions' words.
-constexpr uint64_t kStAgg = 1ull << 62, kStInc = 2ull << 62, kStVal = (1ull << 62) - 1;
-constexpr uint32_t kLookbackSpins = 1u << 22;  // bound on a wait (never expected: a report, not a hang)
+// Single-pass scans.  Each block takes its partition (consecutive items)
+// from a ticket counter, so a partition's predecessors are already held by
+// running blocks (or done); it publishes its total in a status word (flag AGG)
+// as soon as its items are counted, and its exclusive prefix is the sum of its
+// predecessors' totals, all read at once (total_prefix).  No block waits on
+// another's prefix, so there is no chain of device-coherent round trips; the
+// cost is a read of every predecessor's word, a few KB per block.  Status
+// words are 64-bit: flag in the top two bits, value in the low 62, zeroed
+// before the launch.  Workspace (uint64): [0] compaction ticket, [1] offsets
+// ticket, then the compaction partitions' words, then the offsets
+// partitions' words.
+constexpr uint64_t kStAgg = 1ull << 62, kStVal = (1ull << 62) - 1;
+constexpr uint32_t kPrefixSpins = 1u << 22;  // bound on a wait (never expected: a report, not a hang)
 
 __device__ __forceinline__ uint64_t ld_st64(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -441,49 +426,92 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Called by all 64 lanes of wave 0 of the block: the exclusive prefix of
-// partition part, whose own total is tot; publishes part's inclusive prefix.
-__device__ uint64_t chained_prefix(uint64_t *status, int64_t part, uint64_t tot, uint32_t *err) {
+// Called by all 64 lanes of one wave of the block: the sum of the totals of
+// partitions 0 .. part-1, after publishing part's own total.  The words are
+// device-coherent loads, a long round trip each, so they are issued in
+// batches before any is waited for (each lane reads every 64th word,
+// kPrefixWindows windows of 64 per round trip).
+constexpr int kPrefixWindows = 8;
+__device__ uint64_t total_prefix(uint64_t *status, int64_t part, uint64_t tot, uint32_t *err) {
     const int lane = threadIdx.x & 63;
-    if (part == 0) {
-        if (lane == 0) st_st64(&status[0], kStInc | tot);
-        return 0;
-    }
     if (lane == 0) st_st64(&status[part], kStAgg | tot);
-    uint64_t excl = 0;
+    uint64_t sum = 0;
     uint32_t spins = 0;
-    for (int64_t top = part - 1;; top -= 64) {
-        const int64_t q = top - lane;
-        uint64_t st = q >= 0 ? ld_st64(&status[q]) : kStInc;  // below partition 0: nothing to add
-        while (__ballot((st >> 62) == 0) != 0) {
-            if (++spins > kLookbackSpins) {
-                if (lane == 0) atomicOr(err, 1u);
-                st = (st >> 62) == 0 ? kStInc : st;
-                break;
+    for (int64_t q0 = 0; q0 < part; q0 += kPrefixWindows * 64) {
+        uint64_t st[kPrefixWindows];
+#pragma unroll
+        for (int u = 0; u < kPrefixWindows; ++u) {
+            const int64_t q = q0 + u * 64 + lane;
+            st[u] = q < part ? ld_st64(&status[q]) : kStAgg;  // past part: adds 0
+        }
+#pragma unroll
+        for (int u = 0; u < kPrefixWindows; ++u) {
+            const int64_t q = q0 + u * 64 + lane;
+            while (__ballot((st[u] >> 62) == 0) != 0) {
+                if (++spins > kPrefixSpins) {
+                    if (lane == 0) atomicOr(err, 1u);
+                    st[u] = (st[u] >> 62) == 0 ? kStAgg : st[u];
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                if ((st[u] >> 62) == 0) st[u] = ld_st64(&status[q]);
             }
-            __builtin_amdgcn_s_sleep(1);
-            if ((st >> 62) == 0) st = ld_st64(&status[q]);
+            sum += st[u] & kStVal;
         }
-        const uint64_t inc = __ballot((st >> 62) == 2);
-        if (inc) {
-            const int first = __ffsll((unsigned long long)inc) - 1;  // nearest inclusive prefix
-            excl += wave_sum64(lane <= first ? (st & kStVal) : 0ull);
-            break;
-        }
-        excl += wave_sum64(st & kStVal);
     }
-    if (lane == 0) st_st64(&status[part], kStInc | (excl + tot));
-    return excl;
+    return wave_sum64(sum);
+}
+
+// Barrier of the block that orders its LDS accesses only: global loads in
+// flight stay in flight across it (a plain __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Loads of slots e0 + 64 r, r < kCompactItems, issued back to back and waited
+// for once (a load under a branch is waited for before the branch's other side
+// writes its register, so there is none): the counts and, where keep is given
+// (it then holds a byte for every slot), the keep bytes; the depths.  kClamp:
+// indices past the last slot read the last slot (the caller drops them).
+template <bool kClamp>
+__device__ __forceinline__ void compact_loads(const EntryFlags &f, int64_t e0, int64_t m, uint32_t (&cv)[kCompactItems],
+                                              uint8_t (&kv)[kCompactItems]) {
+#pragma unroll
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t e = e0 + r * 64;
+        cv[r] = f.counts[kClamp && e >= m ? m - 1 : e];
+    }
+    if (f.keep) {
+#pragma unroll
+        for (int r = 0; r < kCompactItems; ++r) {
+            const int64_t e = e0 + r * 64;
+            kv[r] = f.keep[kClamp && e >= m ? m - 1 : e];
+        }
+    }
+}
+template <bool kClamp>
+__device__ __forceinline__ void depth_loads(const uint32_t *__restrict__ depth, int64_t e0, int64_t m,
+                                            uint32_t (&dv)[kCompactItems]) {
+#pragma unroll
+    for (int r = 0; r < kCompactItems; ++r) {
+        const int64_t e = e0 + r * 64;
+        dv[r] = depth[kClamp && e >= m ? m - 1 : e];
+    }
 }
 
 // Compaction: slot e with flag 1 becomes entry j (its exclusive prefix):
 // ent[j] = e, with its depth bits as sort key dkey[j] and j itself as sort
 // value dval[j].  Each wave takes 1024 consecutive slots in 16 rounds of 64
 // (coalesced), packing the flagged ones with a ballot per round; the waves of
-// a block are combined in LDS and the blocks by the look-back.  All loads of a
-// kind are issued before any is used (counts, then the keep bytes or
-// rectangles where a view needs them, then the depths of the flagged slots), so
-// a wave waits for a few round trips, not one per round.
+// a block are combined in LDS and the blocks by the prefix of totals.  The
+// loads are few round trips: the views' flags, the counts and the keep bytes
+// together; the depths (read for every slot and dropped where there is no
+// entry: the entries are spread over most cache lines of the array anyway)
+// issued before the prefix and in flight while it is formed; only the
+// rectangles of keep_visible views wait for the counts.  keep: NULL when no
+// view selects.
 __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t m, int64_t nb, uint64_t *ws,
                                                         const uint32_t *__restrict__ depth, uint32_t *__restrict__ ent,
                                                         uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
@@ -496,70 +524,72 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
     if (threadIdx.x == 0) s_part = atomicAdd(reinterpret_cast<uint32_t *>(&ws[0]), 1u);
     __syncthreads();
     const int64_t part = s_part;
-    const int64_t wbase = part * kCompactTile + (int64_t)w * 64 * kScanItems;
+    const int64_t wbase = part * kCompactTile + (int64_t)w * 64 * kCompactItems;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // views of the block's entries: at most two when n >= kCompactTile
+    const bool full = wbase + 64 * kCompactItems <= m;  // wave-uniform: no slot past the last
+    // views of the block's slots: at most two when n >= kCompactTile
     const bool per_elem = f.n < kCompactTile;
     const int64_t v0 = (part * kCompactTile) / f.n, b1 = (v0 + 1) * f.n;
-    const bool sel0 = f.views[v0].v.select != 0, sel1 = b1 < m && f.views[v0 + 1].v.select != 0;
+    const int64_t v1 = b1 < m ? v0 + 1 : v0;
+    uint32_t cv[kCompactItems];
+    uint8_t kv[kCompactItems];
+    if (full)
+        compact_loads<false>(f, wbase + lane, m, cv, kv);
+    else
+        compact_loads<true>(f, wbase + lane, m, cv, kv);
+    const int32_t s0 = f.views[v0].v.select, s1 = f.views[v1].v.select;
+    const int32_t k0 = f.views[v0].keep_visible, k1 = f.views[v1].keep_visible;
+    const bool sel0 = f.keep && s0 != 0, sel1 = f.keep && b1 < m && s1 != 0;
     // keep_visible views count as such only when the rectangles are given
-    const bool vis0 = f.rect && f.views[v0].keep_visible != 0, vis1 = f.rect && b1 < m && f.views[v0 + 1].keep_visible != 0;
-    uint32_t cv[kScanItems];
+    const bool vis0 = f.rect && k0 != 0, vis1 = f.rect && b1 < m && k1 != 0;
+    if (per_elem) {
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t e = wbase + r * 64 + lane;
-        cv[r] = e < m ? f.counts[e] : 0u;
-    }
-    if (per_elem || sel0 || sel1) {
-        uint8_t kv[kScanItems];
-#pragma unroll
-        for (int r = 0; r < kScanItems; ++r) {
+        for (int r = 0; r < kCompactItems; ++r) {
             const int64_t e = wbase + r * 64 + lane;
-            bool sel = false;
-            if (cv[r] != 0) sel = per_elem ? f.views[e / f.n].v.select != 0 : (e < b1 ? sel0 : sel1);
-            kv[r] = sel ? f.keep[e] : (uint8_t)1;
+            if (e >= m) cv[r] = 0;
+            else if (cv[r] != 0 && f.keep && f.views[e / f.n].v.select != 0 && kv[r] == 0) cv[r] = 0;
         }
+    } else {
 #pragma unroll
-        for (int r = 0; r < kScanItems; ++r)
-            if (kv[r] == 0) cv[r] = 0;
+        for (int r = 0; r < kCompactItems; ++r) {
+            const int64_t e = wbase + r * 64 + lane;
+            if (e >= m || ((e < b1 ? sel0 : sel1) && kv[r] == 0)) cv[r] = 0;
+        }
     }
     // every visible slot of a keep_visible view is an entry, keys or not (bit r of vbits)
     uint32_t vbits = 0u;
     if (f.rect && (per_elem || vis0 || vis1)) {
-        bool vv[kScanItems];
+        bool vv[kCompactItems];
 #pragma unroll
-        for (int r = 0; r < kScanItems; ++r) {
+        for (int r = 0; r < kCompactItems; ++r) {
             const int64_t e = wbase + r * 64 + lane;
             vv[r] = false;
             if (e < m && cv[r] == 0) {
                 const int64_t v = per_elem ? e / f.n : (e < b1 ? v0 : v0 + 1);
-                const DevView &dv = f.views[v];
-                if (dv.keep_visible && dv.rect_slot >= 0 &&
-                    f.rect[(int64_t)dv.rect_slot * f.n + (e - v * f.n)] != kEmptyRect)
+                const DevView &dvw = f.views[v];
+                if (dvw.keep_visible && dvw.rect_slot >= 0 &&
+                    f.rect[(int64_t)dvw.rect_slot * f.n + (e - v * f.n)] != kEmptyRect)
                     vv[r] = true;
             }
         }
 #pragma unroll
-        for (int r = 0; r < kScanItems; ++r) vbits |= (uint32_t)vv[r] << r;
+        for (int r = 0; r < kCompactItems; ++r) vbits |= (uint32_t)vv[r] << r;
     }
-    uint64_t masks[kScanItems];
-    uint32_t dv[kScanItems];
     uint32_t cnt = 0;
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t e = wbase + r * 64 + lane;
-        const bool flag = cv[r] != 0 || ((vbits >> r) & 1u);
-        masks[r] = __ballot(flag);
-        cnt += (uint32_t)__popcll(masks[r]);
-        dv[r] = flag ? depth[e] : 0u;
-    }
+    for (int r = 0; r < kCompactItems; ++r) cnt += (uint32_t)__popcll(__ballot(cv[r] != 0 || ((vbits >> r) & 1u)));
     if (lane == 0) s_w[w] = cnt;
-    __syncthreads();
+    uint32_t dv[kCompactItems];
+    if (full)
+        depth_loads<false>(depth, wbase + lane, m, dv);
+    else
+        depth_loads<true>(depth, wbase + lane, m, dv);
+    lds_barrier();  // the depths stay in flight while the prefix is formed
     if (w == 0) {
         uint64_t tot = 0;
 #pragma unroll
         for (int q = 0; q < kCompactBlock / 64; ++q) tot += s_w[q];
-        const uint64_t excl = chained_prefix(ws + 2, part, tot, err);
+        const uint64_t excl = total_prefix(ws + 2, part, tot, err);
         if (lane == 0) {
             s_excl = excl;
             if (part == nb - 1) {
@@ -568,13 +598,14 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     uint64_t run = s_excl;
     for (int q = 0; q < w; ++q) run += s_w[q];
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-        const uint64_t mk = masks[r];
-        if ((mk >> lane) & 1ull) {
+    for (int r = 0; r < kCompactItems; ++r) {
+        const bool flag = cv[r] != 0 || ((vbits >> r) & 1u);
+        const uint64_t mk = __ballot(flag);
+        if (flag) {
             const uint64_t pos = run + (uint64_t)__popcll(mk & lt);
             ent[pos] = (uint32_t)(wbase + r * 64 + lane);
             dkey[pos] = dv[r];
@@ -587,13 +618,17 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
 
 // Offsets of the keys of the entries in depth order; offsets[E] = K.  The
 // grid is sized for the largest entry count; blocks past the partitions of
-// the device count leave without a ticket.
+// the device count leave without a ticket.  Each wave takes 1024 consecutive
+// entries in 16 rounds of 64 (coalesced loads of the order, gathers of the
+// counts, coalesced stores), with a wave scan per round; the waves of a block
+// are combined in LDS and the blocks by the prefix of totals.
 __host__ __device__ inline int64_t compact_parts(int64_t m) { return (m + kCompactTile - 1) / kCompactTile; }
 
 __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t m, uint64_t *ws,
                                                         uint64_t *total, uint32_t *total32, uint32_t *offsets,
                                                         uint32_t *err) {
     __shared__ uint32_t s_part;
+    __shared__ uint64_t s_w[kScanBlock / 64];
     __shared__ uint64_t s_excl;
     const int64_t E = *f.n_ent;
     const int64_t nparts = (E + kScanTile - 1) / kScanTile;
@@ -608,20 +643,35 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
     if ((int64_t)blockIdx.x >= nparts) return;  // block-uniform
     if (threadIdx.x == 0) s_part = atomicAdd(reinterpret_cast<uint32_t *>(&ws[1]), 1u);
     __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t part = s_part;
-    const int64_t base = part * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t wbase = part * kScanTile + (int64_t)w * 64 * kScanItems;
+    // unconditional loads at clamped indices (issued back to back), then the
+    // counts past E dropped
+    const int64_t lastE = E - 1;
     uint32_t c[kScanItems];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t j = wbase + r * 64 + lane;
+        c[r] = f.order[j < E ? j : lastE];
+    }
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) c[r] = f.ecnt[c[r]];
     uint64_t acc = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        c[j] = f(base + j, 0);
-        acc += c[j];
+    for (int r = 0; r < kScanItems; ++r) {
+        if (wbase + r * 64 + lane >= E) c[r] = 0;
+        acc += c[r];
     }
-    uint64_t tot;
-    const uint64_t pre = block_excl_scan(acc, &tot);
-    if (threadIdx.x < 64) {
-        const uint64_t excl = chained_prefix(ws + 2 + compact_parts(m), part, tot, err);
-        if (threadIdx.x == 0) {
+    acc = wave_sum64(acc);
+    if (lane == 0) s_w[w] = acc;
+    __syncthreads();
+    if (w == 0) {
+        uint64_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < kScanBlock / 64; ++q) tot += s_w[q];
+        const uint64_t excl = total_prefix(ws + 2 + compact_parts(m), part, tot, err);
+        if (lane == 0) {
             s_excl = excl;
             if (part == nparts - 1) {
                 const uint64_t K = excl + tot;
@@ -632,12 +682,14 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
         }
     }
     __syncthreads();
-    uint64_t run = s_excl + pre;
+    uint64_t run = s_excl;
+    for (int q = 0; q < w; ++q) run += s_w[q];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t e = base + j;
-        if (e < E) offsets[e] = (uint32_t)run;
-        run += c[j];
+    for (int r = 0; r < kScanItems; ++r) {
+        const int64_t e = wbase + r * 64 + lane;
+        const uint64_t inc = wave_incl_scan((uint64_t)c[r]);
+        if (e < E) offsets[e] = (uint32_t)(run + inc - c[r]);
+        run += __shfl(inc, 63, 64);
     }
 }
 
