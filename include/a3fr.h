@@ -146,7 +146,9 @@ a3fr_status a3fr_set_debug(a3fr_ctx *ctx, int32_t keep_emission_order);
 a3fr_status a3fr_sync(a3fr_ctx *ctx);
 /* How the host thread waits inside the library (a3fr_sync and the key-count
  * read of a3fr_bin_sort): blocking = 0 polls (the lowest wake-up latency, the
- * default); 1 sleeps on blocking-sync events, leaving the CPU to other threads
+ * default; the counts are then written by the kernel that forms them straight
+ * into host-coherent memory and polled there, with no copy or event in the
+ * stream); 1 sleeps on blocking-sync events, leaving the CPU to other threads
  * (the gaze tracker of Algorithm 1, which runs on the CPU beside the renderer,
  * Sec. 3.1).  A3FR_EINVAL for other values. */
 a3fr_status a3fr_set_host_wait(a3fr_ctx *ctx, int32_t blocking);

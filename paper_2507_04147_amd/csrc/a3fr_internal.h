@@ -162,10 +162,11 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const u
                             int nv, int64_t n, const uint32_t *depth, uint32_t *ent, uint32_t *dkey, uint32_t *dval,
                             uint32_t *ecnt, uint64_t *ws, uint64_t *total, uint32_t *n_ent, uint32_t *err,
                             hipStream_t s, bool zeroed = false /* ws already zero */);
-// key offsets of the entries in depth order: order[k] = entry index, its count ecnt[order[k]]
+// key offsets of the entries in depth order: order[k] = entry index, its count ecnt[order[k]];
+// sig (nullable, host-coherent): E, K and then seq are written there for the host
 void launch_key_offsets(const uint32_t *ecnt, const uint32_t *order, const uint32_t *n_ent, int64_t m,
                         uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
-                        hipStream_t s);
+                        uint64_t *sig, uint64_t seq, hipStream_t s);
 // number of key chunks (blocks) of the emission for K keys; chunk_start needs one word per chunk
 int64_t emit_chunks(int64_t K);
 // The entries of one emission, in depth order: entry order[k] of this pass has slot ent[order[k]]

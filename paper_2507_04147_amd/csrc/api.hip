@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -87,6 +88,15 @@ struct a3fr_ctx {
     hipEvent_t upload_done = nullptr;
     uint64_t *h_total = nullptr;
     hipEvent_t total_ready = nullptr;  // the key total has reached h_total
+    // host-coherent words the key-offsets kernel writes the entry and key
+    // totals and a sequence number into ([0] E, [1] K, [2] seq), so that the
+    // host reads them without a copy or an event in the stream (h_sig: host
+    // address, d_sig: device address; NULL when unavailable); sig_seq: the
+    // number of the last frame that asked for them, sig_pending: this frame's
+    // totals come that way
+    uint64_t *h_sig = nullptr, *d_sig = nullptr;
+    uint64_t sig_seq = 0;
+    bool sig_pending = false;
     // a3fr_set_host_wait(1): host waits sleep on blocking-sync events instead of polling
     bool block_wait = false;
     hipEvent_t total_ready_block = nullptr, sync_block = nullptr;
@@ -360,6 +370,18 @@ a3fr_status a3fr_create(a3fr_ctx **out, void *hip_stream) {
         delete c;
         return A3FR_ENOMEM;
     }
+    {   // optional: without it the totals are read back by a copy
+        void *hs = nullptr, *ds = nullptr;
+        if (hipHostMalloc(&hs, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
+            hipHostGetDevicePointer(&ds, hs, 0) == hipSuccess) {
+            c->h_sig = static_cast<uint64_t *>(hs);
+            c->d_sig = static_cast<uint64_t *>(ds);
+            std::memset(hs, 0, 64);
+        } else {
+            if (hs) (void)hipHostFree(hs);
+            (void)hipGetLastError();
+        }
+    }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
@@ -396,6 +418,7 @@ void a3fr_destroy(a3fr_ctx *c) {
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->h_total) (void)hipHostFree(c->h_total);
+    if (c->h_sig) (void)hipHostFree(c->h_sig);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     if (c->total_ready) (void)hipEventDestroy(c->total_ready);
     if (c->total_ready_block) (void)hipEventDestroy(c->total_ready_block);
@@ -853,12 +876,44 @@ static a3fr_status entry_stages(a3fr_ctx *c, const a3fr_scene *scene, bool zeroe
     }
     {
         StageTimer t_(c, A3FR_STAGE_SCAN);
+        // outside graph mode (no host read-back there) and blocking host waits
+        // (they sleep on an event), the totals go straight to the host
+        c->sig_pending = c->d_sig && c->capacity <= 0 && !c->block_wait;
+        if (c->sig_pending) ++c->sig_seq;
         launch_key_offsets(P<uint32_t>(c->ecnt), P<uint32_t>(c->dval_a), sc_n_ent(c->scalars), m,
                            P<uint32_t>(c->offsets), P<uint64_t>(c->block_sums), sc_key_total(c->scalars),
-                           sc_n_keys(c->scalars), sc_err(c->scalars), c->stream);
+                           sc_n_keys(c->scalars), sc_err(c->scalars), c->sig_pending ? c->d_sig : nullptr,
+                           c->sig_seq, c->stream);
     }
     TRY(check_launch(c, "preprocess"));
     c->preprocessed = true;
+    return A3FR_OK;
+}
+
+// Waits (polling) until the key-offsets kernel of this frame has written the
+// totals and their sequence number to host-coherent memory.  The stream is
+// queried every few thousand polls: when it has completed (or failed) the
+// words are there (or never will be), so the wait always ends.
+static a3fr_status wait_sig(a3fr_ctx *c, uint64_t *E, uint64_t *K) {
+    volatile uint64_t *h = c->h_sig;
+    for (uint32_t it = 1;; ++it) {
+        if (h[2] == c->sig_seq) break;
+        if ((it & 4095u) == 0) {
+            const hipError_t q = hipStreamQuery(c->stream);
+            if (q == hipSuccess) {
+                if (h[2] == c->sig_seq) break;
+                return fail(c, A3FR_EDEVICE, "the key totals did not reach the host");
+            }
+            if (q != hipErrorNotReady) {
+                (void)hipGetLastError();
+                return fail(c, A3FR_EDEVICE, std::string("waiting for the key totals: ") + hipGetErrorString(q));
+            }
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *E = h[0];
+    *K = h[1];
     return A3FR_OK;
 }
 
@@ -880,13 +935,19 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
         }
         if (n_keys_out) *n_keys_out = -1;
     } else {
-        // the entry and key totals (scalars [0], [1]) in one read-back; the
-        // records are formed meanwhile into the arrays as they are (formed again
-        // after the wait if they turn out too small)
-        HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_ent_total(c->scalars), 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                                   c->stream));
+        // the entry and key totals: written to host-coherent memory by the
+        // key-offsets kernel (sig_pending), else read back by a copy (scalars
+        // [0], [1]) and an event; the records are formed meanwhile into the
+        // arrays as they are (formed again after the wait if they turn out too
+        // small)
+        const bool sig = c->sig_pending;
+        c->sig_pending = false;
         hipEvent_t ready = c->block_wait ? c->total_ready_block : c->total_ready;
-        HIPCHECK(c, hipEventRecord(ready, c->stream));
+        if (!sig) {
+            HIPCHECK(c, hipMemcpyAsync(c->h_total, sc_ent_total(c->scalars), 2 * sizeof(uint64_t),
+                                       hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipEventRecord(ready, c->stream));
+        }
         const int64_t cap0 = recs ? record_capacity(c) : 0;
         if (cap0 > 0) {
             StageTimer t_(c, A3FR_STAGE_COLOUR);
@@ -894,9 +955,13 @@ a3fr_status a3fr_bin_sort(a3fr_ctx *c, int64_t *n_keys_out) {
                                 sc_n_ent(c->scalars), (int64_t)c->nv * c->n, cap0, c->d_exp_tab, P<Record>(c->rec),
                                 P<uint64_t>(c->rect_e), P<uint32_t>(c->map), nullptr, c->stream);
         }
-        HIPCHECK(c, hipEventSynchronize(ready));
-        E = c->h_total[0];
-        K = c->h_total[1];
+        if (sig) {
+            TRY(wait_sig(c, &E, &K));
+        } else {
+            HIPCHECK(c, hipEventSynchronize(ready));
+            E = c->h_total[0];
+            K = c->h_total[1];
+        }
         if (recs) {
             if ((int64_t)E > cap0) {
                 TRY(ensure_records(c, (int64_t)E));

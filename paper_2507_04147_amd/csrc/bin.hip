@@ -624,9 +624,18 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(EntryFlags f, int64_t
 // are combined in LDS and the blocks by the prefix of totals.
 __host__ __device__ inline int64_t compact_parts(int64_t m) { return (m + kCompactTile - 1) / kCompactTile; }
 
+// Totals for the host (sig != NULL, host-coherent memory): E, K, then the
+// sequence number seq, released after them at system scope.
+__device__ __forceinline__ void totals_to_host(uint64_t *sig, uint64_t seq, uint64_t E, uint64_t K) {
+    if (!sig) return;
+    __hip_atomic_store(&sig[0], E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&sig[1], K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&sig[2], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t m, uint64_t *ws,
                                                         uint64_t *total, uint32_t *total32, uint32_t *offsets,
-                                                        uint32_t *err) {
+                                                        uint32_t *err, uint64_t *sig, uint64_t seq) {
     __shared__ uint32_t s_part;
     __shared__ uint64_t s_w[kScanBlock / 64];
     __shared__ uint64_t s_excl;
@@ -637,6 +646,7 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
             offsets[0] = 0;
             *total = 0;
             *total32 = 0;
+            totals_to_host(sig, seq, 0, 0);
         }
         return;
     }
@@ -678,6 +688,7 @@ __global__ void __launch_bounds__(kScanBlock) k_offsets(SortedCounts f, int64_t 
                 offsets[E] = (uint32_t)K;
                 *total = K;
                 *total32 = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+                totals_to_host(sig, seq, (uint64_t)E, K);
             }
         }
     }
@@ -718,11 +729,11 @@ void launch_compact_entries(const uint32_t *counts, const uint8_t *keep, const u
 
 void launch_key_offsets(const uint32_t *ecnt, const uint32_t *order, const uint32_t *n_ent, int64_t m,
                         uint32_t *offsets, uint64_t *ws, uint64_t *total, uint32_t *total32, uint32_t *err,
-                        hipStream_t s) {
+                        uint64_t *sig, uint64_t seq, hipStream_t s) {
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
     SortedCounts f{ecnt, order, n_ent};
     hipLaunchKernelGGL(k_offsets, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanBlock), 0, s, f, m, ws, total,
-                       total32, offsets, err);
+                       total32, offsets, err, sig, seq);
 }
 
 // ------------------------------------------------------------------------
