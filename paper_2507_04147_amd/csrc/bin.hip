@@ -124,7 +124,7 @@ __device__ __forceinline__ void sel_count(uint32_t *lh, uint32_t d, bool valid) 
     if (valid && d != d0) atomicAdd(&lh[d], 1u);
 }
 
-constexpr int kSelUnroll = 4;
+constexpr int kSelUnroll = 8;
 // Level histograms; a level-1 block first takes the level-0 decision (block
 // 0 of the view stores it in the state for the later kernels).
 __global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, const uint32_t *__restrict__ counts,
@@ -153,23 +153,22 @@ __global__ void __launch_bounds__(256) k_sel_hist(const int32_t *sel_views, cons
     __syncthreads();
     const int64_t base = (int64_t)sel_views[slot] * n, sbase = (int64_t)slot * n;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // block-uniform trip count (the ballots need whole waves); loads first
+    // block-uniform trip count (the ballots need whole waves); the step's
+    // loads are unconditional (indices past n read the last Gaussian and are
+    // dropped), so that they issue together and are waited for once
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += kSelUnroll * stride) {
         uint32_t cv[kSelUnroll];
         uint64_t bits[kSelUnroll];
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
-            const int64_t i = i0 + u * stride + threadIdx.x;
-            cv[u] = i < n ? counts[base + i] : 0u;
+            const int64_t i = i0 + u * stride + threadIdx.x, ic = i < n ? i : n - 1;
+            cv[u] = counts[base + ic];
+            bits[u] = (uint64_t)__double_as_longlong(score[sbase + ic]);
         }
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
             const int64_t i = i0 + u * stride + threadIdx.x;
-            bits[u] = cv[u] != 0 ? (uint64_t)__double_as_longlong(score[sbase + i]) : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            const bool valid = cv[u] != 0 && (level == 0 || sel_level(bits[u], 0) == b0);
+            const bool valid = i < n && cv[u] != 0 && (level == 0 || sel_level(bits[u], 0) == b0);
             sel_count(lh, sel_level(bits[u], level), valid);
         }
     }
@@ -203,26 +202,23 @@ __global__ void __launch_bounds__(256) k_sel_gather(const int32_t *sel_views, co
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // block-uniform trip count; each step's loads issued before any is used
+    // block-uniform trip count; each step's loads are unconditional (indices
+    // past n read the last Gaussian and are dropped), issued together
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += kSelUnroll * stride) {
         uint32_t cv[kSelUnroll];
         uint64_t bits[kSelUnroll];
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
-            const int64_t i = i0 + u * stride + threadIdx.x;
-            cv[u] = i < n ? counts[base + i] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            const int64_t i = i0 + u * stride + threadIdx.x;
-            bits[u] = cv[u] != 0 && mode == 0 ? (uint64_t)__double_as_longlong(score[sbase + i]) : 0ull;
+            const int64_t i = i0 + u * stride + threadIdx.x, ic = i < n ? i : n - 1;
+            cv[u] = counts[base + ic];
+            bits[u] = (uint64_t)__double_as_longlong(score[sbase + ic]);
         }
 #pragma unroll
         for (int u = 0; u < kSelUnroll; ++u) {
             const int64_t i = i0 + u * stride + threadIdx.x;
             uint8_t kp = 0;
             bool cand = false;
-            if (cv[u] != 0) {
+            if (i < n && cv[u] != 0) {
                 if (mode == 1) {
                     kp = 1;
                 } else if (mode == 0) {

@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(256) k_drop_energy(const DevView *__restrict__
 // partial each ([pair][block][cells], cells = b.max_cells apart), and
 // k_drop_reduce sums the partials; device-scope atomics on a few hundred
 // addresses from every XCD would serialise.
+constexpr int kDropUnroll = 8;
 __global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restrict__ views, FbBatch b, int64_t n,
                                                          const uint32_t *__restrict__ counts,
                                                          const uint8_t *__restrict__ keep,
@@ -76,10 +77,28 @@ __global__ void __launch_bounds__(256) k_drop_energy_lds(const DevView *__restri
     __syncthreads();
     const uint64_t *rv = rect + (int64_t)dv.rect_slot * n;
     const double *sv = score + (int64_t)dv.sel_slot * n;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t slot = (int64_t)pv * n + i;
-        if (counts[slot] == 0) continue;
-        drop_share(sh, plane, S, rv[i], sv[i], keep[slot] != 0);
+    const uint32_t *cv = counts + (int64_t)pv * n;
+    const uint8_t *kv = keep + (int64_t)pv * n;
+    // kDropUnroll Gaussians per step, their loads unconditional (indices past
+    // n read the last Gaussian and are dropped) and issued together, so a
+    // thread waits for one round trip per step rather than two per Gaussian
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += kDropUnroll * stride) {
+        uint32_t c[kDropUnroll];
+        uint64_t r[kDropUnroll];
+        double sc[kDropUnroll];
+        uint8_t kp[kDropUnroll];
+#pragma unroll
+        for (int u = 0; u < kDropUnroll; ++u) {
+            const int64_t i = i0 + u * stride, ic = i < n ? i : n - 1;
+            c[u] = cv[ic];
+            r[u] = rv[ic];
+            sc[u] = sv[ic];
+            kp[u] = kv[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < kDropUnroll; ++u)
+            if (i0 + u * stride < n && c[u] != 0) drop_share(sh, plane, S, r[u], sc[u], kp[u] != 0);
     }
     __syncthreads();
     double *out = partials + ((int64_t)k * gridDim.x + blockIdx.x) * b.max_cells;

@@ -662,18 +662,23 @@ void launch_sort_scatter(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, u
 // binary searches (lower bounds of t and t + 1); an empty tile gets (0, 0).
 // Threads of a wave search neighbouring tiles, so the upper levels of the
 // searches hit the same cache lines.
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v) {
-    uint32_t lo = 0, len = n;
-    while (len > 0) {
+
+// Lower bounds of v0 and v1 in the sorted a[0, n), n >= 1, found together so
+// that their two chains of dependent loads overlap.  Branch-free halving: the
+// lower bound stays in [b, b + len] (everything before b is below the value),
+// and the steps depend only on n, the same for every lane.
+__device__ __forceinline__ void lower_bounds2_u32(const uint32_t *__restrict__ a, uint32_t n, uint32_t v0,
+                                                  uint32_t v1, uint32_t &r0, uint32_t &r1) {
+    uint32_t b0 = 0, b1 = 0, len = n;
+    while (len > 1) {
         const uint32_t half = len >> 1;
-        if (a[lo + half] < v) {
-            lo += half + 1;
-            len -= half + 1;
-        } else {
-            len = half;
-        }
+        const uint32_t x0 = a[b0 + half - 1], x1 = a[b1 + half - 1];
+        b0 += x0 < v0 ? half : 0u;
+        b1 += x1 < v1 ? half : 0u;
+        len -= half;
     }
-    return lo;
+    r0 = b0 + (a[b0] < v0 ? 1u : 0u);
+    r1 = b1 + (a[b1] < v1 ? 1u : 0u);
 }
 
 __global__ void __launch_bounds__(256) k_ranges(const uint32_t *__restrict__ tiles, int64_t K, const uint32_t *K_dev,
@@ -682,8 +687,8 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t *__restrict__ til
     if (t >= ntiles) return;
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode
     const uint32_t n = (uint32_t)K;
-    const uint32_t s0 = lower_bound_u32(tiles, n, (uint32_t)t);
-    const uint32_t s1 = lower_bound_u32(tiles, n, (uint32_t)t + 1u);
+    uint32_t s0 = 0, s1 = 0;
+    if (n > 0) lower_bounds2_u32(tiles, n, (uint32_t)t, (uint32_t)t + 1u, s0, s1);
     ranges[2 * t] = s0 == s1 ? 0u : s0;
     ranges[2 * t + 1] = s0 == s1 ? 0u : s1;
 }
