@@ -132,9 +132,18 @@ struct NetWgradArgs {
 __host__ __device__ int net_chw_stride(int w);
 
 // ---- kernels' host launchers (all enqueue on `s`) ----
+// up to kFillSegs device ranges of 32-bit words to clear in one launch
+constexpr int kFillSegs = 8;
+struct FillSegs {
+    uint32_t *p[kFillSegs];
+    int64_t n[kFillSegs];  // words; only the first count are used
+    int count;
+};
+// zero: ranges the same launch clears (count 0: none), so that a frame's
+// accumulators need no launch of their own
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
-                       uint8_t *done /* [tiles] nullable: incremental rounds */, hipStream_t s);
+                       uint8_t *done /* [tiles] nullable: incremental rounds */, const FillSegs &zero, hipStream_t s);
 // counts [nv][n] every slot; depth [nv][n] of entries; rect [n_rect_views][n] (views with rect_slot >= 0);
 // score [nsel][n] (selecting views, by sel_slot); cum: the masked views' summed-area tables (launch_mask_cum)
 void launch_preprocess(const a3fr_scene &sc, const DevView *views, int ngroups, const int32_t *groups,
@@ -330,12 +339,6 @@ void launch_region_sse_sum(const double *partial, const unsigned long long *cnt,
                            int64_t *count3, hipStream_t s);
 void launch_fp64_probe(const double *x, const double *y, double *sq, double *dv, int64_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-constexpr int kFillSegs = 8;
-struct FillSegs {
-    uint32_t *p[kFillSegs];
-    int64_t n[kFillSegs];  // words; only the first count are used
-    int count;
-};
 void launch_zero_segs(const FillSegs &f, hipStream_t s);
 
 }  // namespace a3fr

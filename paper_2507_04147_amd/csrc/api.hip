@@ -699,16 +699,6 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
     c->blend_bwd_done = false;
     c->sh_degree = scene->sh_degree;
 
-    // ---- kernels
-    const DevView *dv = P<DevView>(c->views);
-    { StageTimer t_(c, A3FR_STAGE_MASKS);
-    launch_tile_masks(dv, nv, c->rows_total, d_row_view, d_row_y,
-                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), nullptr, c->stream);
-      if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
-    { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
-    launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint32_t>(c->cum), P<uint32_t>(c->counts),
-                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), P<GeomPack>(c->gpack),
-                      c->d_exp_tab, c->stream); }
     // the fallback pairs (periphery view, its eye's full-resolution view); their
     // difference planes [2][tiles_y + 1][tiles_x + 1] (doubles) go in batches of
     // up to kFbMax per launch
@@ -736,13 +726,14 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         TRY(ensure(c, c->fb_part, sizeof(double) * (size_t)drop_energy_parts() * (size_t)max_part));
         TRY(ensure(c, c->fb_count, 16));
     }
-    {   // one launch clears what the later stages accumulate into: the select
-        // histograms, the fallback's counters and planes, the scans' tickets and
-        // status words, the depth sort's digit counts and pass counters (its
-        // histogram kernel clears the status words of the partitions in use)
-        StageTimer t_(c, A3FR_STAGE_MASKS);
+    // what the later stages accumulate into, cleared by the tile-mask launch:
+    // the select histograms, the fallback's counters and planes, the scans'
+    // tickets and status words, the depth sort's digit counts and pass
+    // counters (its histogram kernel clears the status words of the
+    // partitions in use)
+    FillSegs z{};
+    {
         const int64_t m = (int64_t)nv * n;
-        FillSegs z{};
         const auto add = [&z](void *p, int64_t words) {
             z.p[z.count] = reinterpret_cast<uint32_t *>(p);
             z.n[z.count] = words;
@@ -756,8 +747,19 @@ static a3fr_status preprocess_kernels(a3fr_ctx *c, const a3fr_scene *scene, int3
         }
         add(c->block_sums.p, 2 * scan_workspace_words(m));
         add(c->sort_status.p, onesweep_zero_words(4));
-        launch_zero_segs(z, c->stream);
     }
+
+    // ---- kernels
+    const DevView *dv = P<DevView>(c->views);
+    { StageTimer t_(c, A3FR_STAGE_MASKS);
+    launch_tile_masks(dv, nv, c->rows_total, d_row_view, d_row_y,
+                      P<uint16_t>(c->row_prefix), P<uint16_t>(c->row_list), P<uint8_t>(c->active), nullptr, z,
+                      c->stream);
+      if (c->cum_entries) launch_mask_cum(dv, nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream); }
+    { StageTimer t_(c, A3FR_STAGE_PREPROCESS);
+    launch_preprocess(*scene, dv, (int)c->hgroups.size() - 1, d_groups, P<uint32_t>(c->cum), P<uint32_t>(c->counts),
+                      P<uint32_t>(c->depth), P<uint64_t>(c->rect), P<double>(c->score), P<GeomPack>(c->gpack),
+                      c->d_exp_tab, c->stream); }
     if (c->nsel) { StageTimer t_(c, A3FR_STAGE_SELECT);
         launch_select(dv, nv, d_sel_views, c->nsel, n, P<uint32_t>(c->counts), P<double>(c->score),
                       keep_num, keep_den, P<uint32_t>(c->sel), P<uint8_t>(c->keep), c->stream, true); }
@@ -1445,7 +1447,8 @@ static a3fr_status inc_round(a3fr_ctx *c, const a3fr_gaze *gaze, double radius, 
     {
         StageTimer t_(c, A3FR_STAGE_MASKS);
         launch_tile_masks(dv, c->nv, c->rows_total, c->d_row_view, c->d_row_y, P<uint16_t>(c->row_prefix),
-                          P<uint16_t>(c->row_list), P<uint8_t>(c->active), P<uint8_t>(c->inc_done), c->stream);
+                          P<uint16_t>(c->row_list), P<uint8_t>(c->active), P<uint8_t>(c->inc_done), FillSegs{},
+                          c->stream);
         if (c->cum_entries)
             launch_mask_cum(dv, c->nv, c->max_tiles_x, P<uint16_t>(c->row_prefix), P<uint32_t>(c->cum), c->stream);
         // fovea and mid layers of every eye, up to kFbMax views per launch

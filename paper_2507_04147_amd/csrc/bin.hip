@@ -775,13 +775,24 @@ __global__ void __launch_bounds__(256) k_chunk_starts(const uint32_t *n_ent, con
         for (int i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0u;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)*n_ent || j >= cap) return;  // entries past the capacity emit no key (k_clamp_keys)
-    const uint32_t e = order[j];
-    const uint32_t slot = ent[e];
-    const uint32_t r = map ? map[slot] : e;
-    rect_s[j] = rect_e[r];
-    esort[j] = slot;
-    rsort[j] = r;
     const uint64_t lo = offsets[j], hi = offsets[j + 1];
+    const uint32_t e = order[j];
+    if (map) {  // records of an earlier pass: found through the slot
+        const uint32_t slot = ent[e];
+        const uint32_t r = map[slot];
+        rect_s[j] = rect_e[r];
+        esort[j] = slot;
+        rsort[j] = r;
+    } else {    // the record is the entry: its rectangle loads beside the slot
+        // (read as two words, so that the compiler does not merge this load
+        // with the other branch's behind a common wait for the slot)
+        const uint2 rw = reinterpret_cast<const uint2 *>(rect_e)[e];
+        const uint32_t slot = ent[e];
+        const uint64_t rc = ((uint64_t)rw.y << 32) | rw.x;
+        rect_s[j] = rc;
+        esort[j] = slot;
+        rsort[j] = e;
+    }
     for (uint64_t c = (lo + kEmitChunk - 1) / kEmitChunk; c * kEmitChunk < hi && (int64_t)c < nchunks; ++c)
         chunk_start[c] = (uint32_t)j;
 }

@@ -46,9 +46,21 @@ __device__ __forceinline__ bool tile_active(const a3fr_view &v, int tx, int ty) 
 // columns of the row's active tiles in order (row_list), built with ballots.
 // Incremental rounds: a frozen view has no active tile; a view excluding done
 // tiles drops the tiles an earlier round rendered and marks its new ones done.
+// The ranges of zero are cleared first, spread over every thread of the grid.
 __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_t rows_total, const int32_t *row_view,
                                                     const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list,
-                                                    uint8_t *active, uint8_t *done) {
+                                                    uint8_t *active, uint8_t *done, FillSegs zero) {
+    if (zero.count > 0) {
+        int64_t total = 0;
+        for (int k = 0; k < zero.count; ++k) total += zero.n[k];
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
+             j += (int64_t)gridDim.x * blockDim.x) {
+            int64_t q = j;
+            int k = 0;
+            while (q >= zero.n[k]) q -= zero.n[k++];
+            zero.p[k][q] = 0u;
+        }
+    }
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= rows_total) return;
@@ -88,11 +100,14 @@ __global__ void __launch_bounds__(256) k_tile_masks(const DevView *views, int64_
 
 void launch_tile_masks(const DevView *views, int nv, int64_t rows_total, const int32_t *row_view,
                        const int32_t *row_y, uint16_t *row_prefix, uint16_t *row_list, uint8_t *active,
-                       uint8_t *done, hipStream_t s) {
+                       uint8_t *done, const FillSegs &zero, hipStream_t s) {
     (void)nv;
-    if (rows_total == 0) return;
+    if (rows_total == 0) {
+        if (zero.count > 0) launch_zero_segs(zero, s);
+        return;
+    }
     hipLaunchKernelGGL(k_tile_masks, dim3((unsigned)((rows_total + 3) / 4)), dim3(256), 0, s, views, rows_total,
-                       row_view, row_y, row_prefix, row_list, active, done);
+                       row_view, row_y, row_prefix, row_list, active, done, zero);
 }
 
 // ------------------------------------------------------------------------

@@ -44,7 +44,8 @@ def _stream(n=6):
 @pytest.mark.parametrize("speculative", [True, False])
 def test_render_loop_follows_the_exits(speculative):
     exits, sig, final = _stream()
-    times = [3.0, 6.0, 9.0, 12.0, 15.0, 18.0]
+    # exits 30 ms apart: far slower than a call, and than a scheduling hiccup of the test process
+    times = [30.0, 60.0, 90.0, 120.0, 150.0, 180.0]
     ctx = FakeCtx()
     r = pipeline.run(ctx, None, None, Fovea(), exits, final, sig, times, speculative=speculative)
     kinds = [e[0] for e in r["events"]]
