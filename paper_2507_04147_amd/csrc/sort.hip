@@ -45,7 +45,7 @@ constexpr int kRadix = 256;
 constexpr int kDigitWaves = kRadix / kWave;           // waves holding one digit per lane
 constexpr int kMaxPasses = 4;                         // 32-bit keys
 constexpr int kGroup = 32;                            // partitions per scan group (tile-id sort)
-constexpr int kScanBatch = 16;                        // independent loads per round trip in the scan
+constexpr int kScanBatch = 64;                        // independent loads per round trip in the scan
 
 static int sort_cus() {
     static int cus = 0;
@@ -477,10 +477,12 @@ __global__ void __launch_bounds__(256) k_sort_scan(const uint32_t *__restrict__ 
     __syncthreads();
     if (!s_last || G == 0) return;
     __threadfence();
-    // totals of every digit, kScanBatch independent loads per round trip
+    // totals of every digit, kScanBatch independent loads per round trip; the
+    // last batch stays in v for the second pass (with G <= kScanBatch, the
+    // usual case, the group sums are read once)
     uint32_t tot = 0;
+    uint32_t v[kScanBatch];
     for (int64_t q0 = 0; q0 < G; q0 += kScanBatch) {
-        uint32_t v[kScanBatch];
 #pragma unroll
         for (int q = 0; q < kScanBatch; ++q)
             v[q] = __hip_atomic_load(&gsum[min(q0 + q, G - 1) * kRadix + d], __ATOMIC_RELAXED,
@@ -502,11 +504,12 @@ __global__ void __launch_bounds__(256) k_sort_scan(const uint32_t *__restrict__ 
     uint32_t run = inc - tot;
     for (int q = 0; q < w; ++q) run += s_ws[q];
     for (int64_t q0 = 0; q0 < G; q0 += kScanBatch) {
-        uint32_t v[kScanBatch];
+        if (G > kScanBatch) {  // block-uniform: more than one batch, reloaded in order
 #pragma unroll
-        for (int q = 0; q < kScanBatch; ++q)
-            v[q] = __hip_atomic_load(&gsum[min(q0 + q, G - 1) * kRadix + d], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < kScanBatch; ++q)
+                v[q] = __hip_atomic_load(&gsum[min(q0 + q, G - 1) * kRadix + d], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        }
 #pragma unroll
         for (int q = 0; q < kScanBatch; ++q)
             if (q0 + q < G) {
