@@ -754,6 +754,7 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 // (depth order) whose key range holds key c * kEmitChunk.
 constexpr int kEmitChunk = 1024;
 constexpr int kEmitBlock = 512;
+static_assert(kEmitChunk == 2 * kEmitBlock, "k_emit stages a chunk's entries two per thread");
 
 // Thread per entry j (depth order: entry order[j] of this pass, slot
 // ent[order[j]], record r = map[slot] when the records belong to an earlier
@@ -842,29 +843,51 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     if (K_dev && (int64_t)*K_dev < K) K = *K_dev;  // capacity mode: the device count, clamped
     if (q0 >= K) return;                           // block-uniform
     const int64_t E = *n_ent;
+    if (E == 0) return;  // no entry, no key (block-uniform)
     const int64_t j0 = chunk_start[blockIdx.x];
     const int64_t qend = q0 + kEmitChunk < K ? q0 + kEmitChunk : K;
     // s_off[t] = offsets[j0 + t] (offsets[E], the key total, past the last entry):
-    // s_off[0] <= q0 and s_off[kEmitChunk] > q0 + kEmitChunk - 1
-    for (int t = tid; t <= kEmitChunk; t += kEmitBlock) {
-        const int64_t jj = j0 + t;
-        s_off[t] = offsets[jj < E ? jj : E];
-    }
+    // s_off[0] <= q0 and s_off[kEmitChunk] > q0 + kEmitChunk - 1.  A thread's
+    // loads are issued together, the views' fields with them (every field
+    // loaded, then selected: no load waits on another); kEmitChunk = 2 kEmitBlock.
+    const int64_t ja = j0 + tid, jb = j0 + tid + kEmitBlock, jc = j0 + kEmitChunk;
+    const uint32_t oa = offsets[ja < E ? ja : E], ob = offsets[jb < E ? jb : E];
+    const uint32_t oc = offsets[jc < E ? jc : E];
     for (int v = tid; v < nv; v += kEmitBlock) {
         const DevView &dv = views[v];
-        const bool all = dv.v.mask == A3FR_MASK_ALL;
-        s_view[v] = EmitView{(uint32_t)dv.tile_off, dv.tiles_x, all ? -1 : (int32_t)dv.cum_off,
-                             all ? -1 : (int32_t)dv.mask_off};
+        const int32_t mask = dv.v.mask, coff = (int32_t)dv.cum_off, moff = (int32_t)dv.mask_off;
+        const uint32_t toff = (uint32_t)dv.tile_off;
+        const int32_t tx = dv.tiles_x;
+        const bool all = mask == A3FR_MASK_ALL;
+        s_view[v] = EmitView{toff, tx, all ? -1 : coff, all ? -1 : moff};
     }
+    s_off[tid] = oa;
+    s_off[tid + kEmitBlock] = ob;
+    if (tid == 0) s_off[kEmitChunk] = oc;
     __syncthreads();
     // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E);
     // their record index (the keys' value), view and rectangle
+    // (loaded unconditionally at clamped indices, both of a thread's entries
+    // together)
     const uint32_t nn = (uint32_t)n;
-    for (int t = tid; t < kEmitChunk; t += kEmitBlock) {
-        if ((int64_t)s_off[t] < qend) {
-            s_rect[t] = rect_s[j0 + t];
-            s_v[t] = esort[j0 + t] / nn;
-            s_i[t] = rsort[j0 + t];
+    {
+        uint64_t rc[2];
+        uint32_t es[2], rs[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t jj = j0 + tid + u * kEmitBlock, jc = jj < E ? jj : E - 1;
+            rc[u] = rect_s[jc];
+            es[u] = esort[jc];
+            rs[u] = rsort[jc];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = tid + u * kEmitBlock;
+            if ((int64_t)s_off[t] < qend) {
+                s_rect[t] = rc[u];
+                s_v[t] = es[u] / nn;
+                s_i[t] = rs[u];
+            }
         }
     }
     __syncthreads();
