@@ -50,30 +50,30 @@ PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
                   sha256="ce162a8a40d3dd42d9b6630738ac7d48bc67dec55cc73c107d2f72dbddd0d743",
-                  kib={"32,4x1,grid": (7395.2, 21750.0),
-                       "32,4x1,queue": (6893.1, 23962.8),
-                       "32,2x2,grid": (7389.3, 21750.0),
-                       "32,2x2,queue": (6827.3, 21879.3),
-                       "64,4x1,grid": (10533.2, 21750.0),
-                       "64,4x1,queue": (9874.8, 24573.6),
-                       "64,2x2,grid": (10518.8, 21750.0),
-                       "64,2x2,queue": (9751.1, 22031.9),
-                       "128,4x1,grid": (18969.0, 21750.0),
-                       "128,4x1,queue": (18689.7, 25039.9),
-                       "128,2x2,grid": (18934.0, 21750.0),
-                       "128,2x2,queue": (18283.3, 22377.6),
-                       "64,8x8q,grid": (10183.2, 21750.0),
-                       "128,8x8q,grid": (18049.2, 21750.0),
-                       "256,8x8q,grid": (32726.4, 21750.0)}),
+                  kib={"32,4x1,grid": (7393.7, 21750.0),
+                       "32,4x1,queue": (6907.9, 24085.7),
+                       "32,2x2,grid": (7388.8, 21750.0),
+                       "32,2x2,queue": (6858.6, 22016.6),
+                       "64,4x1,grid": (10532.1, 21750.0),
+                       "64,4x1,queue": (9887.5, 24559.0),
+                       "64,2x2,grid": (10534.4, 21750.0),
+                       "64,2x2,queue": (9717.2, 22108.0),
+                       "128,4x1,grid": (18961.7, 21750.0),
+                       "128,4x1,queue": (18657.9, 25517.5),
+                       "128,2x2,grid": (18949.8, 21750.0),
+                       "128,2x2,queue": (18493.8, 22446.3),
+                       "64,8x8q,grid": (10183.3, 21750.0),
+                       "128,8x8q,grid": (18048.5, 21750.0),
+                       "256,8x8q,grid": (32729.2, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
-                       sha256="af2272d3583a0ee17823ad39331b870d924180520b9047cfb65d45c3a91758ff",
-                       kib={"k_preprocess": (21721.4, 101022.2)}),
+                       sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
+                       kib={"k_preprocess": (21722.3, 100988.7)}),
     "colour": dict(source="csrc/preprocess.hip",
-                   sha256="af2272d3583a0ee17823ad39331b870d924180520b9047cfb65d45c3a91758ff",
-                   kib={"k_entry_record": (85803.4, 33774.8)}),
+                   sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
+                   kib={"k_entry_record": (85770.2, 33774.5)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
-                      sha256="6eda886ea81a26b72659dcccd6ad1bd920764a0207e494910c07eb8981b6a4e2",
-                      kib={"k_sort_scatter": (40104.1, 81888.7)}),
+                      sha256="c3ba030832d91fb9190ad1c086e47acaf6004bae6e05637ccbbd060804168df7",
+                      kib={"k_sort_scatter": (40104.4, 81888.5)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale, quaternion and opacity of every Gaussian

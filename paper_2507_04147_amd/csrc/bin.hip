@@ -867,15 +867,17 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     __syncthreads();
     // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E);
     // their record index (the keys' value), view and rectangle
-    // (loaded unconditionally at clamped indices, both of a thread's entries
-    // together)
+    // (loaded unconditionally, both of a thread's entries together; a slot
+    // whose entry holds no key of the chunk reads entry j0, the chunk's first,
+    // so that it costs no memory traffic)
     const uint32_t nn = (uint32_t)n;
     {
         uint64_t rc[2];
         uint32_t es[2], rs[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int64_t jj = j0 + tid + u * kEmitBlock, jc = jj < E ? jj : E - 1;
+            const int t = tid + u * kEmitBlock;
+            const int64_t jc = (int64_t)s_off[t] < qend ? j0 + t : j0;
             rc[u] = rect_s[jc];
             es[u] = esort[jc];
             rs[u] = rsort[jc];
