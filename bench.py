@@ -49,31 +49,31 @@ PMC_FETCH_FACTOR = 524288.0 / 262166.6
 PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
-                  sha256="ce162a8a40d3dd42d9b6630738ac7d48bc67dec55cc73c107d2f72dbddd0d743",
-                  kib={"32,4x1,grid": (7393.7, 21750.0),
-                       "32,4x1,queue": (6907.9, 24085.7),
-                       "32,2x2,grid": (7388.8, 21750.0),
-                       "32,2x2,queue": (6858.6, 22016.6),
-                       "64,4x1,grid": (10532.1, 21750.0),
-                       "64,4x1,queue": (9887.5, 24559.0),
-                       "64,2x2,grid": (10534.4, 21750.0),
-                       "64,2x2,queue": (9717.2, 22108.0),
-                       "128,4x1,grid": (18961.7, 21750.0),
-                       "128,4x1,queue": (18657.9, 25517.5),
-                       "128,2x2,grid": (18949.8, 21750.0),
-                       "128,2x2,queue": (18493.8, 22446.3),
-                       "64,8x8q,grid": (10183.3, 21750.0),
-                       "128,8x8q,grid": (18048.5, 21750.0),
-                       "256,8x8q,grid": (32729.2, 21750.0)}),
+                  sha256="56f821fff9a95f00860d8993a5417dd80d0363ec35df19f2aad1ddd6a39f7747",
+                  kib={"32,4x1,grid": (7397.5, 21750.0),
+                       "32,4x1,queue": (6903.1, 23723.0),
+                       "32,2x2,grid": (7386.6, 21750.0),
+                       "32,2x2,queue": (6846.8, 21881.1),
+                       "64,4x1,grid": (10528.4, 21750.0),
+                       "64,4x1,queue": (9897.2, 24472.3),
+                       "64,2x2,grid": (10522.1, 21750.0),
+                       "64,2x2,queue": (9693.1, 22105.2),
+                       "128,4x1,grid": (18966.7, 21750.0),
+                       "128,4x1,queue": (18518.7, 25256.5),
+                       "128,2x2,grid": (18947.7, 21750.0),
+                       "128,2x2,queue": (18338.1, 22448.3),
+                       "64,8x8q,grid": (10183.4, 21750.0),
+                       "128,8x8q,grid": (18055.9, 21750.0),
+                       "256,8x8q,grid": (32730.9, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
                        sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
-                       kib={"k_preprocess": (21722.3, 100988.7)}),
+                       kib={"k_preprocess": (21721.7, 100986.8)}),
     "colour": dict(source="csrc/preprocess.hip",
                    sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
-                   kib={"k_entry_record": (85770.2, 33774.5)}),
+                   kib={"k_entry_record": (85782.3, 33774.4)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
                       sha256="c3ba030832d91fb9190ad1c086e47acaf6004bae6e05637ccbbd060804168df7",
-                      kib={"k_sort_scatter": (40104.4, 81888.5)}),
+                      kib={"k_sort_scatter": (40103.4, 81889.9)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale, quaternion and opacity of every Gaussian

@@ -832,7 +832,8 @@ BlendVariant blend_variant(int k) {
 // back: each pixel starts at its last blended Gaussian with its final
 // transmittance T and S = T (bg . D), D = dL/dC, and for each blended
 // Gaussian j (alpha >= 1/255, position < last) going towards the front
-//   T_j   = T_{j+1} / (1 - alpha_j)           (transmittance in front of j)
+//   T_j   = T_{j+1} / (1 - alpha_j)           (transmittance in front of j;
+//           times the hardware reciprocal, 1 ulp, instead of a divide)
 //   dL/dalpha_j = T_j (c_j . D) - S / (1 - alpha_j),   S += (c_j . D) alpha_j T_j,
 //   dL/dc_j    += alpha_j T_j D.
 // Through alpha = o 2^e (when not clamped at 0.99): dL/do += dL/dalpha 2^e and
@@ -877,6 +878,36 @@ __device__ __forceinline__ float wave_multi_sum8(const float (&v)[8], int lane) 
     for (int off = 4; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
 }
+
+// Wave sums of V values at once (V = 32 or 64), the same halving as above run
+// to the end: at each exchange step a lane keeps the half of its values
+// selected by one lane bit and receives that half from its partner, so after
+// log2 V steps (V - 1 shuffles) lane l holds the sum over the wave of value
+// l >> (6 - log2 V); with V = 32 a last plain step at offset 1 completes it.
+template <int V>
+__device__ __forceinline__ float wave_multi_sum(const float (&v)[V], int lane) {
+    static_assert(V == 32 || V == 64, "32 or 64 values");
+    float c[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) c[i] = v[i];
+#pragma unroll
+    for (int off = 32, n = V; n > 1; off >>= 1, n >>= 1) {
+        const bool b = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) {
+            const float keep = b ? c[n / 2 + i] : c[i], give = b ? c[i] : c[n / 2 + i];
+            c[i] = keep + __shfl_xor(give, off, 64);
+        }
+    }
+    float x = c[0];
+    if (V == 32) x += __shfl_xor(x, 1, 64);
+    return x;
+}
+
+// entries of the list whose nine sums are reduced together (9 x 7 = 63 of
+// the 64 lanes: one shuffle tree per seven entries instead of one per entry)
+constexpr int kBwdGroup = 7;
+constexpr int kBwdVals = 64;
 
 __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ views, int nv,
                                                   const uint8_t *__restrict__ active,
@@ -957,58 +988,68 @@ __global__ void __launch_bounds__(64) k_blend_bwd(const DevView *__restrict__ vi
             s_p[at] = bstart + (uint32_t)lane;
         }
         __syncthreads();
-        for (int jj = __popcll(km) - 1; jj >= 0; --jj) {
-            const uint32_t pos = s_p[jj];
-            const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
-            const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj], et = s_e[jj];
-            const float dy = fy - mv;
-            const float kdy = kk * dy;
-            const float cdy = c2 * dy * dy;
-            float g_t2 = 0.f, g_t = 0.f, g_tdy = 0.f, g_dy2 = 0.f, g_dy = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f, g_b = 0.f;
-            bool hit = false;
+        for (int jb = __popcll(km) - 1; jb >= 0; jb -= kBwdGroup) {  // groups of entries, back to front
+            float vsum[kBwdVals];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float t = (fxq[q] - mu) + kdy;
-                const float e = fmaf(a2, t * t, cdy);
-                const float ex = __builtin_amdgcn_exp2f(e);
-                const float araw = o * ex;
-                const float al = fminf(kAlphaMax, araw);
-                if (pos < last[q] && e >= et) {  // blended in the forward (the same decision)
-                    hit = true;
-                    const float oma = 1.0f - al;
-                    const float Tb = T[q] / oma;
-                    const float cD = cr * D0[q] + cg * D1[q] + cb * D2[q];
-                    const float w = al * Tb;
-                    g_r = fmaf(w, D0[q], g_r);
-                    g_g = fmaf(w, D1[q], g_g);
-                    g_b = fmaf(w, D2[q], g_b);
-                    const float dal = Tb * cD - S[q] / oma;
-                    S[q] = fmaf(cD, w, S[q]);
-                    T[q] = Tb;
-                    if (araw < kAlphaMax) {
-                        const float g = dal * al * kLn2;
-                        const float gt = g * t;
-                        g_t2 = fmaf(gt, t, g_t2);
-                        g_t += gt;
-                        g_tdy = fmaf(gt, dy, g_tdy);
-                        const float gdy = g * dy;
-                        g_dy2 = fmaf(gdy, dy, g_dy2);
-                        g_dy += gdy;
-                        g_o = fmaf(dal, ex, g_o);
+            for (int i = 0; i < kBwdVals; ++i) vsum[i] = 0.0f;
+            uint32_t hitm = 0;
+#pragma unroll
+            for (int u = 0; u < kBwdGroup; ++u) {
+                const int jj = jb - u;
+                if (jj < 0) break;  // wave-uniform
+                const uint32_t pos = s_p[jj];
+                const float mu = s_u[jj], mv = s_v[jj], a2 = s_a[jj], kk = s_k[jj], c2 = s_c[jj], o = s_o[jj];
+                const float cr = s_r[jj], cg = s_g[jj], cb = s_b[jj], et = s_e[jj];
+                const float dy = fy - mv;
+                const float kdy = kk * dy;
+                const float cdy = c2 * dy * dy;
+                float g_t2 = 0.f, g_t = 0.f, g_tdy = 0.f, g_dy2 = 0.f, g_dy = 0.f, g_o = 0.f, g_r = 0.f, g_g = 0.f,
+                      g_b = 0.f;
+                bool hit = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float t = (fxq[q] - mu) + kdy;
+                    const float e = fmaf(a2, t * t, cdy);
+                    const float ex = __builtin_amdgcn_exp2f(e);
+                    const float araw = o * ex;
+                    const float al = fminf(kAlphaMax, araw);
+                    if (pos < last[q] && e >= et) {  // blended in the forward (the same decision)
+                        hit = true;
+                        const float oma = 1.0f - al;
+                        const float inv = __builtin_amdgcn_rcpf(oma);  // 1 ulp; 1 - alpha in [0.01, 1]
+                        const float Tb = T[q] * inv;
+                        const float cD = cr * D0[q] + cg * D1[q] + cb * D2[q];
+                        const float w = al * Tb;
+                        g_r = fmaf(w, D0[q], g_r);
+                        g_g = fmaf(w, D1[q], g_g);
+                        g_b = fmaf(w, D2[q], g_b);
+                        const float dal = Tb * cD - S[q] * inv;
+                        S[q] = fmaf(cD, w, S[q]);
+                        T[q] = Tb;
+                        if (araw < kAlphaMax) {
+                            const float g = dal * al * kLn2;
+                            const float gt = g * t;
+                            g_t2 = fmaf(gt, t, g_t2);
+                            g_t += gt;
+                            g_tdy = fmaf(gt, dy, g_tdy);
+                            const float gdy = g * dy;
+                            g_dy2 = fmaf(gdy, dy, g_dy2);
+                            g_dy += gdy;
+                            g_o = fmaf(dal, ex, g_o);
+                        }
                     }
                 }
+                if (__ballot(hit) != 0ull) hitm |= 1u << u;
+                vsum[9 * u + 0] = g_t2; vsum[9 * u + 1] = g_t; vsum[9 * u + 2] = g_tdy;
+                vsum[9 * u + 3] = g_dy2; vsum[9 * u + 4] = g_dy; vsum[9 * u + 5] = g_o;
+                vsum[9 * u + 6] = g_r; vsum[9 * u + 7] = g_g; vsum[9 * u + 8] = g_b;
             }
-            if (__ballot(hit) != 0ull) {
-                // sums 0..7 in one butterfly: each exchange step halves the
-                // values a lane carries (4 + 2 + 1 shuffles), three more steps
-                // finish the sum; lane 8 v then holds sum v over the wave.  Sum 8
-                // (blue) by a plain butterfly, held by every lane.
-                float v[8] = {g_t2, g_t, g_tdy, g_dy2, g_dy, g_o, g_r, g_g};
-                const float sb = wave_sum(g_b);
-                const float vb = wave_multi_sum8(v, lane);
-                const bool first = (lane & 7) == 0;
-                if (first || lane == 1)
-                    atomicAdd(&A[(int64_t)s_i[jj] * 12 + (first ? (lane >> 3) : 8)], first ? vb : sb);
+            if (hitm != 0u) {  // wave-uniform
+                // lane l: sum l % 9 of the group's entry l / 9
+                const float sum = wave_multi_sum<kBwdVals>(vsum, lane);
+                const int u = lane / 9, k = lane - 9 * (lane / 9);
+                if (u < kBwdGroup && ((hitm >> u) & 1u))
+                    atomicAdd(&A[(int64_t)s_i[jb - u] * 12 + k], sum);
             }
         }
         __syncthreads();
