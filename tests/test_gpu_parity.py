@@ -11,6 +11,8 @@ its near-threshold decisions causes (oracle amb_tol).
 """
 import math
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -352,6 +354,33 @@ def test_deterministic_across_runs(pkg, ctx):
     _, _, rgb1, T1, l1 = gpu_render(pkg, ctx, scene, views, debug=False)
     _, _, rgb2, T2, l2 = gpu_render(pkg, ctx, scene, views, debug=False)
     assert torch.equal(rgb1, rgb2) and torch.equal(T1, T2) and torch.equal(l1, l2)
+
+
+@pytest.mark.parametrize("blocking", [False, True])
+def test_key_totals_of_the_last_preprocess(pkg, blocking):
+    """The entry and key totals reach the host from the key-offsets kernel
+    (polling a host-coherent word with a sequence number) or, with blocking
+    waits, by a copy: either way a3fr_bin_sort sizes its arrays by the latest
+    a3fr_preprocess, also after a preprocess whose totals it never read."""
+    scene, cam = synth.single_view(n=20000)
+    big = [oracle.full_view(cam)]
+    small = [oracle.full_view(dataclasses.replace(cam, width=96, height=80, cx=48.0, cy=40.0))]
+    c = pkg.Context()
+    c.set_host_wait(blocking)
+    ds = pkg.DeviceScene.from_host(scene)
+    c.preprocess(ds, small)
+    K_small = c.bin_sort()
+    c.preprocess(ds, big)
+    K_big = c.bin_sort()
+    c.preprocess(ds, small)  # totals never read
+    c.preprocess(ds, big)
+    assert c.bin_sort() == K_big
+    c.preprocess(ds, big)
+    c.preprocess(ds, small)
+    assert c.bin_sort() == K_small
+    ref = oracle.render(scene, small, blend=False)
+    assert K_small == ref["keys"].size
+    c.close()
 
 
 def test_invalid_arguments_enqueue_nothing(pkg, ctx):
