@@ -16,7 +16,7 @@
 // popcount of the lower lanes, and scatter them through LDS so that
 // consecutive threads write consecutive addresses of each digit run.  They
 // differ in how a partition learns where its digits start, chosen by size:
-//  * the entry sort (a few hundred 2048-key partitions): onesweep, one kernel
+//  * the entry sort (a hundred or more 4096-key partitions): onesweep, one kernel
 //    per digit after one histogram pass; a block takes the next partition id
 //    from an atomic counter, publishes its digit counts and resolves its
 //    offsets by decoupled look-back over the preceding partitions;
@@ -41,6 +41,8 @@ namespace a3fr {
 
 constexpr int kSortThreads = 512;
 constexpr int kSortWaves = kSortThreads / kWave;      // 8
+constexpr int kOsThreads = 1024;                      // the entry sort's blocks (16 waves: 4096-key partitions)
+constexpr int kOsWaves = kOsThreads / kWave;
 constexpr int kRadix = 256;
 constexpr int kDigitWaves = kRadix / kWave;           // waves holding one digit per lane
 constexpr int kMaxPasses = 4;                         // 32-bit keys
@@ -62,7 +64,7 @@ static int sort_cus() {
 // entry depth sort: onesweep
 // ==========================================================================
 static int onesweep_partitions(int64_t n, int items) {
-    const int64_t part = (int64_t)kSortThreads * items;
+    const int64_t part = (int64_t)kOsThreads * items;
     return (int)((n + part - 1) / part);
 }
 
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(kHistThreads) k_sort_hist(const uint32_t *__re
         // status = hist + npass x kRadix + 8 (u32 words): 16-byte aligned with the workspace, and so is each
         // pass's part; kRadix 64-bit words per partition = kRadix / 2 uint4
         uint4 *status = reinterpret_cast<uint4 *>(hist + (int64_t)npass * kRadix + 8);
-        const int64_t parts = (n + (int64_t)kSortThreads * items - 1) / ((int64_t)kSortThreads * items);
+        const int64_t parts = (n + (int64_t)kOsThreads * items - 1) / ((int64_t)kOsThreads * items);
         const int64_t per = parts * (kRadix / 2), stride = parts_max * (kRadix / 2);
         const uint4 z = {0u, 0u, 0u, 0u};
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < npass * per;
@@ -157,15 +159,15 @@ __device__ __forceinline__ void st_status(uint64_t *p, uint64_t v) {
 // predecessors always publish; the bound turns a logic error into a report
 // instead of a hang).
 template <int kSortItems>
-__global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__restrict__ kin,
+__global__ void __launch_bounds__(kOsThreads) k_onesweep(const uint32_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                            const uint32_t *n_dev, int shift,
                                                            const uint32_t *__restrict__ ghist, uint64_t *status,
                                                            uint32_t *counter, uint32_t *err) {
-    constexpr int kSortPart = kSortThreads * kSortItems;
+    constexpr int kSortPart = kOsThreads * kSortItems;
     __shared__ uint32_t s_part;
-    __shared__ uint32_t s_wh[kSortWaves][kRadix];
+    __shared__ uint32_t s_wh[kOsWaves][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_gexcl[kRadix];
@@ -212,7 +214,7 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
     for (;;) {
         __syncthreads();  // previous partition done with the LDS
         if (tid == 0) s_part = atomicAdd(counter, 1u);
-        for (int j = tid; j < kSortWaves * kRadix; j += kSortThreads) (&s_wh[0][0])[j] = 0;
+        for (int j = tid; j < kOsWaves * kRadix; j += kOsThreads) (&s_wh[0][0])[j] = 0;
         __syncthreads();
         const uint32_t part = s_part;
         if ((int)part >= nparts) break;
@@ -256,13 +258,13 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
         uint32_t tot = 0;
         if (tid < kRadix) {
             const int d = tid;
-            uint32_t c[kSortWaves];
+            uint32_t c[kOsWaves];
 #pragma unroll
-            for (int q = 0; q < kSortWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
+            for (int q = 0; q < kOsWaves; ++q) { c[q] = s_wh[q][d]; tot += c[q]; }
             st_status(&status[(int64_t)part * kRadix + d], (part == 0 ? kSt64Inc : kSt64Agg) | (uint64_t)tot);
             uint32_t run = 0;
 #pragma unroll
-            for (int q = 0; q < kSortWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
+            for (int q = 0; q < kOsWaves; ++q) { s_wh[q][d] = run; run += c[q]; }
             // block-local exclusive scan over digits (waves 0..3)
             uint32_t inc = tot;
 #pragma unroll
@@ -329,7 +331,7 @@ __global__ void __launch_bounds__(kSortThreads, 4) k_onesweep(const uint32_t *__
         __syncthreads();
         const int64_t rem = K - base;
         const int nvalid = rem < kSortPart ? (int)rem : kSortPart;
-        for (int j = tid; j < nvalid; j += kSortThreads) {
+        for (int j = tid; j < nvalid; j += kOsThreads) {
             const uint32_t kk = s_k[j];
             const uint32_t dg = (kk >> shift) & 255u;
             const uint32_t g = s_gbase[dg] + ((uint32_t)j - s_lstart[dg]);
@@ -368,10 +370,10 @@ void launch_onesweep_pass(const uint32_t *ki, const uint32_t *vi, uint32_t *ko, 
     if (nparts == 0) return;
     uint32_t *hist = ws, *ctr = ws + (int64_t)npass * kRadix;
     uint64_t *status = reinterpret_cast<uint64_t *>(ctr + 8);  // 8-byte aligned: npass x 1 KiB + 32 B in
-    // persistent blocks: LDS per block ~26 KB
-    const int resident = sort_cus() * 4;
+    // persistent blocks: LDS per block ~52 KB
+    const int resident = sort_cus();  // one 16-wave block per compute unit at its register count
     const int grid = nparts < resident ? nparts : resident;
-    hipLaunchKernelGGL(k_onesweep<items>, dim3((unsigned)grid), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n_dev,
+    hipLaunchKernelGGL(k_onesweep<items>, dim3((unsigned)grid), dim3(kOsThreads), 0, s, ki, vi, ko, vo, n_dev,
                        8 * p, hist + (int64_t)p * kRadix, status + (int64_t)p * nparts * kRadix, ctr + p, err);
 }
 
