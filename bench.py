@@ -50,30 +50,30 @@ PMC_WRITE_FACTOR = 1.0
 PMC_TRAFFIC = {  # stage -> source under the package, its sha256, {key: (FETCH KiB, WRITE KiB) per dispatch}
     "blend": dict(source="csrc/blend.hip",
                   sha256="56f821fff9a95f00860d8993a5417dd80d0363ec35df19f2aad1ddd6a39f7747",
-                  kib={"32,4x1,grid": (7397.5, 21750.0),
-                       "32,4x1,queue": (6903.1, 23723.0),
-                       "32,2x2,grid": (7386.6, 21750.0),
-                       "32,2x2,queue": (6846.8, 21881.1),
-                       "64,4x1,grid": (10528.4, 21750.0),
-                       "64,4x1,queue": (9897.2, 24472.3),
-                       "64,2x2,grid": (10522.1, 21750.0),
-                       "64,2x2,queue": (9693.1, 22105.2),
-                       "128,4x1,grid": (18966.7, 21750.0),
-                       "128,4x1,queue": (18518.7, 25256.5),
-                       "128,2x2,grid": (18947.7, 21750.0),
-                       "128,2x2,queue": (18338.1, 22448.3),
+                  kib={"32,4x1,grid": (7391.3, 21750.0),
+                       "32,4x1,queue": (6907.5, 23917.3),
+                       "32,2x2,grid": (7394.2, 21750.0),
+                       "32,2x2,queue": (6863.3, 21967.7),
+                       "64,4x1,grid": (10525.8, 21750.0),
+                       "64,4x1,queue": (9891.7, 24541.2),
+                       "64,2x2,grid": (10541.1, 21750.0),
+                       "64,2x2,queue": (9785.6, 22118.5),
+                       "128,4x1,grid": (18967.4, 21750.0),
+                       "128,4x1,queue": (18750.9, 25320.5),
+                       "128,2x2,grid": (18933.1, 21750.0),
+                       "128,2x2,queue": (18566.8, 22442.3),
                        "64,8x8q,grid": (10183.4, 21750.0),
-                       "128,8x8q,grid": (18055.9, 21750.0),
-                       "256,8x8q,grid": (32730.9, 21750.0)}),
+                       "128,8x8q,grid": (18054.5, 21750.0),
+                       "256,8x8q,grid": (32726.9, 21750.0)}),
     "preprocess": dict(source="csrc/preprocess.hip",
                        sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
-                       kib={"k_preprocess": (21721.7, 100986.8)}),
+                       kib={"k_preprocess": (21722.5, 100987.8)}),
     "colour": dict(source="csrc/preprocess.hip",
                    sha256="044dc8100cd9684f7154eb5e94863f28896b7b63b5a8875195212cefd947bc8a",
-                   kib={"k_entry_record": (85782.3, 33774.4)}),
+                   kib={"k_entry_record": (85767.5, 33774.9)}),
     "sort_pass": dict(source="csrc/sort.hip",  # the scatter of each tile-id pass
-                      sha256="c3ba030832d91fb9190ad1c086e47acaf6004bae6e05637ccbbd060804168df7",
-                      kib={"k_sort_scatter": (40103.4, 81889.9)}),
+                      sha256="166153c8db95ae1265c358d997265e86b9ad0b13047e449c838020c17afb1a0a",
+                      kib={"k_sort_scatter": (40104.4, 81888.8)}),
 }
 # projection, one launch for both eyes (each with its fovea, mid and periphery
 # views): the float32 mean, scale, quaternion and opacity of every Gaussian

@@ -354,8 +354,8 @@ int64_t select_workspace_words(int nsel, int64_t n) {
 // scans: compaction of the visible entries, then key offsets in depth order
 // ------------------------------------------------------------------------
 constexpr int kScanItems = 16;
-constexpr int kScanBlock = 256;
-constexpr int kScanTile = kScanItems * kScanBlock;  // 4096 entries per block (key offsets)
+constexpr int kScanBlock = 128;
+constexpr int kScanTile = kScanItems * kScanBlock;  // 2048 entries per block (key offsets)
 // the compaction's partitions: 12 waves of 1024 slots (two blocks per CU at
 // its register count, so that a stereo frame of a million Gaussians, 6M slots,
 // is in flight at once; fewer, larger partitions take fewer tickets, which
