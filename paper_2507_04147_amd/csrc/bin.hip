@@ -765,7 +765,6 @@ __device__ __forceinline__ void unpack_rect(uint64_t r, int &x0, int &x1, int &y
 // (depth order) whose key range holds key c * kEmitChunk.
 constexpr int kEmitChunk = 1024;
 constexpr int kEmitBlock = 512;
-static_assert(kEmitChunk == 2 * kEmitBlock, "k_emit stages a chunk's entries two per thread");
 
 // Thread per entry j (depth order: entry order[j] of this pass, slot
 // ent[order[j]], record r = map[slot] when the records belong to an earlier
@@ -860,9 +859,14 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     // s_off[t] = offsets[j0 + t] (offsets[E], the key total, past the last entry):
     // s_off[0] <= q0 and s_off[kEmitChunk] > q0 + kEmitChunk - 1.  A thread's
     // loads are issued together, the views' fields with them (every field
-    // loaded, then selected: no load waits on another); kEmitChunk = 2 kEmitBlock.
-    const int64_t ja = j0 + tid, jb = j0 + tid + kEmitBlock, jc = j0 + kEmitChunk;
-    const uint32_t oa = offsets[ja < E ? ja : E], ob = offsets[jb < E ? jb : E];
+    // loaded, then selected: no load waits on another).
+    uint32_t oo[kEmitPer];
+#pragma unroll
+    for (int u = 0; u < kEmitPer; ++u) {
+        const int64_t ja = j0 + tid + u * kEmitBlock;
+        oo[u] = offsets[ja < E ? ja : E];
+    }
+    const int64_t jc = j0 + kEmitChunk;
     const uint32_t oc = offsets[jc < E ? jc : E];
     for (int v = tid; v < nv; v += kEmitBlock) {
         const DevView &dv = views[v];
@@ -872,8 +876,8 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
         const bool all = mask == A3FR_MASK_ALL;
         s_view[v] = EmitView{toff, tx, all ? -1 : coff, all ? -1 : moff};
     }
-    s_off[tid] = oa;
-    s_off[tid + kEmitBlock] = ob;
+#pragma unroll
+    for (int u = 0; u < kEmitPer; ++u) s_off[tid + u * kEmitBlock] = oo[u];
     if (tid == 0) s_off[kEmitChunk] = oc;
     __syncthreads();
     // the entries with keys in [q0, qend): t < kEmitChunk with s_off[t] < qend (then j0 + t < E);
@@ -883,10 +887,10 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
     // so that it costs no memory traffic)
     const uint32_t nn = (uint32_t)n;
     {
-        uint64_t rc[2];
-        uint32_t es[2], rs[2];
+        uint64_t rc[kEmitPer];
+        uint32_t es[kEmitPer], rs[kEmitPer];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < kEmitPer; ++u) {
             const int t = tid + u * kEmitBlock;
             const int64_t jc = (int64_t)s_off[t] < qend ? j0 + t : j0;
             rc[u] = rect_s[jc];
@@ -894,7 +898,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_emit(const DevView *__restrict__
             rs[u] = rsort[jc];
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < kEmitPer; ++u) {
             const int t = tid + u * kEmitBlock;
             if ((int64_t)s_off[t] < qend) {
                 s_rect[t] = rc[u];
